@@ -1,0 +1,213 @@
+/*
+ * fic.h -- fractal image encoding on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libfic.so. It implements the encoder of Miar Naimi & Salarian,
+ * "A Fast Fractal Image Compression Algorithm Using Predefined Values for
+ * Contrast Scaling".
+ *
+ * Terms (Section 2 of the paper):
+ *   range   a B x B block of the image; ranges tile the image.
+ *   domain  a 2B x 2B block whose top-left corner lies on a grid of step L;
+ *           it is decimated to B x B by taking 2x2 means.
+ *   iso     one of 8 isometries applied to the decimated domain:
+ *             t=0 identity            t=1 rotate 90 degrees clockwise
+ *             t=2 rotate 180 degrees  t=3 rotate 270 degrees clockwise
+ *             t=4..7 the left-right mirror of t=0..3.
+ *           On a B x B block with row i and column c, t=1 places in[B-1-c][i]
+ *           at (i, c), t=2 places in[B-1-i][B-1-c], and t=3 places
+ *           in[c][B-1-i]. Mirrored forms read column B-1-c of the rotation.
+ *   s, o    the contrast and offset of the affine map. s = k/10 with integer
+ *           k in 0..10. The offset is that of eq. (3), o = mean(R) - s*mean(D).
+ *   E       the distance of eq. (1), E = sum_i (s*d_i + o - r_i)^2.
+ *
+ * The search is exhaustive and exact. For every range the library returns
+ * the candidate (domain, iso, contrast) with the smallest E. Exact integers
+ * decide it, and ties go to the smallest (E, domain, iso, contrast index).
+ * e_num = 1600 * n * E is an integer (n = B*B) and is reported exactly.
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless marked [host].
+ *   - The caller owns every buffer. The library never frees, keeps or
+ *     aliases caller memory after a call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
+ *     Outputs are valid once that stream has synchronised, unless the entry
+ *     point says it synchronises itself.
+ *   - Each call returns FIC_OK (0) or a negative fic_status. Arguments are
+ *     validated on the host before any device work is queued; on an error
+ *     nothing is queued. fic_last_error() then gives a message.
+ *   - The library keeps internal device workspace per (device, stream). Calls
+ *     on different streams may run concurrently; calls sharing one stream are
+ *     ordered by it.
+ */
+#ifndef FIC_H
+#define FIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fic_status {
+    FIC_OK = 0,
+    FIC_EINVAL = -1,    /* bad argument (shape, range, null pointer, ...) */
+    FIC_ECAPACITY = -2, /* an output buffer is too small (see fic_encode_image) */
+    FIC_EDEVICE = -3,   /* a HIP runtime error; the message carries its text */
+    FIC_ENOMEM = -4     /* device workspace could not be allocated */
+};
+
+/* Largest image side the library accepts. */
+#define FIC_MAX_SIDE 16384
+/* Largest number of contrast values in one set. */
+#define FIC_MAX_S 11
+
+/* Best transform of one range block (24 bytes). */
+typedef struct {
+    int64_t e_num;  /* exact 1600 * n * E, E being eq. (1) at the optimum          */
+    int32_t dom;    /* domain index on the level's unfiltered grid:                 */
+                    /*   dom = (y / L) * gx + x / L, gx = (W - 2B) / L + 1          */
+    uint8_t iso;    /* isometry t, 0..7                                             */
+    uint8_t s_idx;  /* position of the chosen k in the contrast set                 */
+    uint8_t k;      /* contrast numerator: s = k / 10                               */
+    uint8_t flags;  /* reserved, 0                                                  */
+    int16_t q_o;    /* offset of eq. (3) rounded half up to an integer              */
+    int16_t pad_;
+    float E;        /* e_num / (1600 n) in FP32 (for reporting; e_num is exact)     */
+} fic_match;
+
+/* One leaf of the quadtree (32 bytes). */
+typedef struct {
+    int64_t e_num;  /* exact 1600 * n * E                                           */
+    int32_t dom;    /* domain index on the level's unfiltered grid                  */
+    int16_t y, x;   /* range top-left corner (pixels)                               */
+    int16_t dy, dx; /* domain top-left corner (pixels)                              */
+    int16_t q_o;    /* quantised offset                                             */
+    uint8_t log2B;  /* range side B = 1 << log2B                                    */
+    uint8_t iso;    /* isometry 0..7                                                */
+    uint8_t k;      /* s = k / 10                                                   */
+    uint8_t s_idx;  /* position of k in the level's contrast set                    */
+    uint8_t level;  /* 0-based quadtree level                                       */
+    uint8_t pad_[5];
+} fic_code;
+
+/* Per-level counters written by fic_encode_image (24 bytes). */
+typedef struct {
+    int64_t matches;  /* active ranges * pool domains * 8 isometries                */
+    int32_t pool;     /* domains searched at this level                             */
+    int32_t passed;   /* domains above the entropy threshold (= grid size if off)   */
+    int32_t active;   /* ranges matched at this level                               */
+    int32_t accepted; /* ranges whose transform was kept at this level              */
+} fic_level_stats;
+
+/* Encoder parameters (Sections 2 and 3). */
+typedef struct {
+    int32_t n_levels;       /* 1..4; level l has range side B0 >> l (>= 2)                */
+    int32_t B0;             /* first-level range side, in {2, 4, 8, 16}                   */
+    int32_t L[4];           /* domain step per level, >= 1                                */
+    int32_t n_s[4];         /* contrast values per level, 1..FIC_MAX_S                    */
+    int8_t s_k[4][12];      /* strictly increasing k in 0..10 per level (s = k/10)        */
+    float rms_thresh;       /* keep a transform iff sqrt(E / n) <= rms_thresh;            */
+                            /* the last level always keeps it                             */
+    int32_t entropy_mode;   /* 0: no filter. 1: keep domains whose 8-bin (p >> 5)          */
+                            /* histogram entropy in bits exceeds entropy_bits             */
+    float entropy_bits;     /* threshold of mode 1 (strict >)                             */
+    int32_t min_pool;       /* if fewer domains pass, use the min_pool highest-entropy    */
+                            /* domains instead (ties to the lower index); >= 1            */
+} fic_params;
+
+/*
+ * Exhaustive matching at one level (Section 2; entropy filter of Section 3).
+ *
+ * img        uint8 image, H rows of W pixels, row stride `pitch` bytes.
+ * B, L       range side (2, 4, 8 or 16) and domain step (>= 1). H and W must
+ *            be multiples of B and at least 2B.
+ * s_k, n_s   [host] 1..FIC_MAX_S strictly increasing contrast numerators k,
+ *            each in 0..10 (s = k/10). The paper searches a sampled [0, 1]
+ *            (Section 2) or a predefined per-step set (Section 3.1).
+ * entropy_mode, entropy_bits, min_pool
+ *            the domain-pool filter, as in fic_params. With entropy_mode = 0
+ *            the pool is the whole grid.
+ * range_yx   n_ranges pairs (y, x) of range top-left corners (multiples of B,
+ *            inside the image), or NULL for the whole range grid in raster
+ *            order (then n_ranges must equal (H/B)*(W/B)).
+ * out        n_ranges fic_match records, in the order of range_yx.
+ * pool_out   optional (may be NULL): receives the ascending domain indices
+ *            searched; it must hold one int32 per grid domain.
+ * pool_count optional (may be NULL): one device int32 receiving the pool size.
+ *
+ * Errors: FIC_EINVAL for bad shapes or arguments (range corners are checked
+ * on the device; an out-of-image corner yields dom = -1 in its record).
+ */
+int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
+                     int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
+                     float entropy_bits, int32_t min_pool, const int32_t* range_yx,
+                     int32_t n_ranges, fic_match* out, int32_t* pool_out, int32_t* pool_count,
+                     void* stream);
+
+/*
+ * Quadtree encoder (Section 2; the three cases at the end of Section 3.1).
+ * Level 0 matches every B0 x B0 range. A range whose best transform has
+ * RMS error above p->rms_thresh is split into its four quadrants (top-left,
+ * top-right, bottom-left, bottom-right) for the next level. The last level
+ * keeps everything.
+ *
+ * codes      capacity fic_code records. Codes are written level by level. Within a level
+ *            they follow the active list: raster order at level 0, and below it
+ *            the four children of each split range in the order of their parents.
+ * n_codes    one device int32. It receives the number of codes the image
+ *            needs, even when that exceeds `capacity`; records past capacity
+ *            are dropped. After synchronising, n_codes > capacity means the
+ *            buffer was too small.
+ * stats      optional (may be NULL): p->n_levels fic_level_stats records.
+ *
+ * Errors: FIC_EINVAL (shapes, parameters); FIC_ECAPACITY when capacity is
+ * below (H/B0)*(W/B0), the fewest codes any image needs.
+ */
+int fic_encode_image(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
+                     const fic_params* p, fic_code* codes, int32_t capacity, int32_t* n_codes,
+                     fic_level_stats* stats, void* stream);
+
+/*
+ * Decoder for the reconstructions of Section 4 (the paper does not describe
+ * one). Starts from a uniform grey 128 image and applies the code's map
+ * `iters` times. Each iteration rebuilds every leaf from the previous image:
+ * value = (k/10) * T_iso(2x2 mean of the domain) + q_o, rounded half up and
+ * clamped to 0..255, in exact integer arithmetic.
+ *
+ * codes, n_codes  leaves that tile the H x W image exactly.
+ * out             uint8 image, row stride out_pitch (>= W).
+ * Synchronises `stream` before returning. Codes that do not tile the image,
+ * or that point outside it, give FIC_EINVAL.
+ */
+int fic_decode(const fic_code* codes, int32_t n_codes, int32_t H, int32_t W, int32_t iters,
+               uint8_t* out, int32_t out_pitch, void* stream);
+
+/*
+ * Sum of squared differences between two uint8 images (for PSNR).
+ * sse: one device uint64.
+ */
+int fic_sse(const uint8_t* a, int32_t pitch_a, const uint8_t* b, int32_t pitch_b, int32_t H,
+            int32_t W, uint64_t* sse, void* stream);
+
+/*
+ * Predefined contrast values estimated from low-entropy ranges (abstract;
+ * Section 3.1). Runs the plain method (k = 0..10, no domain filter) through
+ * the quadtree of p (n_levels, B0, L, rms_thresh). At each level it takes the
+ * kept ranges whose 8-bin entropy is <= p->entropy_bits, and returns the mean
+ * of their best k rounded half up. A level without such a range gets -1.
+ * k_out: [host] p->n_levels int8. Synchronises `stream`.
+ */
+int fic_calibrate_s(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
+                    const fic_params* p, int8_t* k_out, void* stream);
+
+/* Message for the last non-zero return on this thread. */
+const char* fic_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int fic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIC_H */

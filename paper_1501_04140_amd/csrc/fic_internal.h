@@ -1,0 +1,47 @@
+// Shared declarations of the libfic kernels and host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fic.h"
+
+namespace fic {
+
+constexpr int kBlock = 256;    // threads per workgroup (4 wavefronts of 64)
+constexpr int kItems = 8;      // items per thread in the compaction kernels
+constexpr int kSelBits = 12;   // radix-select digit width
+constexpr int kSelBins = 1 << kSelBits;
+constexpr int kEntFrac = 32;   // fixed-point fraction bits of the entropy table
+constexpr int kMaxWindow = 1024;  // largest histogram window (32 x 32 domain)
+
+// Device-resident control block of one workspace.
+struct Ctrl {
+    int32_t act_count[5];  // active ranges per quadtree level (index = level)
+    int32_t pool_count;    // domains in the current level's pool
+    int32_t pass_count;    // domains above the entropy threshold
+    int32_t n_codes;       // codes emitted so far (may exceed capacity)
+    int32_t code_base;     // first code slot of the current level
+    int32_t err;
+    int32_t sel_rank;      // rank still to find inside the current key prefix
+    uint32_t ticket;       // last-workgroup ticket of the radix select
+    uint64_t sel_prefix;   // key bits fixed so far by the radix select
+    uint32_t ghist[kSelBins];
+};
+
+// Contrast set of a level: s = k / 10.
+struct KSet {
+    int n;            // number of values
+    int consecutive;  // 1 iff k = k0, k0+1, ..., k1
+    int k0, k1;
+    int k[12];
+};
+
+// Best candidate of one range over one chunk of the pool.
+struct Partial {
+    int64_t F;    // k^2 A' - 80 k B'  (= 1600 n E minus the range constant 1600 C)
+    int64_t key;  // (domain << 8) | (iso << 4) | contrast index
+};
+
+}  // namespace fic

@@ -1,0 +1,242 @@
+"""Python binding of libfic (include/fic.h): argument marshalling only.
+
+Every step of the encoder runs in the library's HIP kernels. PyTorch only
+provides device memory and the current stream. The binding refuses to run
+when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfic.so")
+
+FIC_OK, FIC_EINVAL, FIC_ECAPACITY, FIC_EDEVICE, FIC_ENOMEM = 0, -1, -2, -3, -4
+MAX_S = 11
+PLAIN_K = tuple(range(11))                   # s = 0, 0.1, ..., 1.0 (Section 2)
+PAPER_K = ((1,), (2, 4), (3, 8), (5, 9))     # predefined s per step (Section 3.1)
+LEVELS = (16, 8, 4, 2)                       # range sides of the four steps (Section 2)
+
+MATCH_DTYPE = np.dtype([("e_num", "<i8"), ("dom", "<i4"), ("iso", "u1"), ("s_idx", "u1"),
+                        ("k", "u1"), ("flags", "u1"), ("q_o", "<i2"), ("pad_", "<i2"),
+                        ("E", "<f4")])
+CODE_DTYPE = np.dtype([("e_num", "<i8"), ("dom", "<i4"), ("y", "<i2"), ("x", "<i2"),
+                       ("dy", "<i2"), ("dx", "<i2"), ("q_o", "<i2"), ("log2B", "u1"),
+                       ("iso", "u1"), ("k", "u1"), ("s_idx", "u1"), ("level", "u1"),
+                       ("pad_", "u1", (5,))])
+STATS_DTYPE = np.dtype([("matches", "<i8"), ("pool", "<i4"), ("passed", "<i4"),
+                        ("active", "<i4"), ("accepted", "<i4")])
+assert MATCH_DTYPE.itemsize == 24 and CODE_DTYPE.itemsize == 32 and STATS_DTYPE.itemsize == 24
+
+
+class FicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfic error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("B0", ctypes.c_int32), ("L", ctypes.c_int32 * 4),
+                ("n_s", ctypes.c_int32 * 4), ("s_k", (ctypes.c_int8 * 12) * 4),
+                ("rms_thresh", ctypes.c_float), ("entropy_mode", ctypes.c_int32),
+                ("entropy_bits", ctypes.c_float), ("min_pool", ctypes.c_int32)]
+
+
+@dataclass
+class EncoderParams:
+    """Quadtree encoder settings (fic_params)."""
+    levels: tuple = LEVELS
+    steps: tuple | None = None                 # default: L = B/2 (1 at B = 2)
+    s_sets: tuple = PAPER_K
+    rms: float = 8.0
+    entropy_mode: int = 1
+    entropy_bits: float = 2.5
+    min_pool: int = 256
+    extra: dict = field(default_factory=dict)
+
+    def to_c(self) -> Params:
+        p = Params()
+        n = len(self.levels)
+        p.n_levels = n
+        p.B0 = int(self.levels[0])
+        steps = self.steps or tuple(max(int(B) // 2, 1) for B in self.levels)
+        for l in range(n):
+            p.L[l] = int(steps[l])
+            ks = tuple(int(k) for k in self.s_sets[l])
+            p.n_s[l] = len(ks)
+            for i, k in enumerate(ks):
+                p.s_k[l][i] = k
+        p.rms_thresh = float(self.rms)
+        p.entropy_mode = int(self.entropy_mode)
+        p.entropy_bits = float(self.entropy_bits)
+        p.min_pool = int(self.min_pool)
+        return p
+
+
+_lib = None
+
+
+def load():
+    """Load libfic.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FicError(FIC_EDEVICE, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    lib.fic_encode_level.argtypes = [vp, i32, i32, i32, i32, i32, vp, i32, i32, f32, i32, vp, i32,
+                                     vp, vp, vp, vp]
+    lib.fic_encode_image.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, i32, vp, vp, vp]
+    lib.fic_decode.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp]
+    lib.fic_sse.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
+    lib.fic_calibrate_s.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, vp]
+    lib.fic_last_error.restype = ctypes.c_char_p
+    for name in ("fic_encode_level", "fic_encode_image", "fic_decode", "fic_sse",
+                 "fic_calibrate_s", "fic_version"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != FIC_OK:
+        raise FicError(rc, load().fic_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_u8_image(img):
+    import torch
+    if not isinstance(img, torch.Tensor) or img.dtype != torch.uint8 or img.dim() != 2:
+        raise TypeError("image must be a 2-D torch.uint8 tensor")
+    if not img.is_cuda:
+        raise TypeError("image must be on the GPU")
+    if img.stride(1) != 1:
+        raise ValueError("image rows must be contiguous")
+    return img
+
+
+def encode_level(img, B: int, L: int, s_k=PLAIN_K, entropy_mode: int = 0,
+                 entropy_bits: float = 2.5, min_pool: int = 256, ranges=None,
+                 return_pool: bool = False, stream=None):
+    """fic_encode_level. Returns a uint8 tensor [n_ranges, 24] of fic_match records
+    (and, with return_pool, the pool index tensor and a 1-element pool-count tensor)."""
+    import torch
+    img = _dev_u8_image(img)
+    H, W = img.shape
+    lib = load()
+    ks = (ctypes.c_int8 * max(1, len(s_k)))(*[int(k) for k in s_k])
+    if ranges is not None:
+        ranges = ranges.to(device=img.device, dtype=torch.int32).contiguous().reshape(-1, 2)
+        n = ranges.shape[0]
+    else:
+        n = (H // B) * (W // B) if B > 0 else 0
+    out = torch.empty((max(n, 1), 24), dtype=torch.uint8, device=img.device)
+    gx = (W - 2 * B) // L + 1 if L > 0 else 1
+    gy = (H - 2 * B) // L + 1 if L > 0 else 1
+    pool = torch.empty(max(gx * gy, 1), dtype=torch.int32, device=img.device) if return_pool else None
+    pcount = torch.zeros(1, dtype=torch.int32, device=img.device) if return_pool else None
+    rc = lib.fic_encode_level(img.data_ptr(), H, W, img.stride(0), B, L, ks, len(s_k),
+                              entropy_mode, entropy_bits, min_pool,
+                              ranges.data_ptr() if ranges is not None else None, n,
+                              out.data_ptr(), pool.data_ptr() if pool is not None else None,
+                              pcount.data_ptr() if pcount is not None else None, _stream(stream))
+    _check(rc)
+    out = out[:n]
+    return (out, pool, pcount) if return_pool else out
+
+
+def code_capacity(H: int, W: int, levels=LEVELS) -> int:
+    """Most codes a quadtree with these levels can emit."""
+    return (H // levels[-1]) * (W // levels[-1])
+
+
+def encode_image(img, params: EncoderParams | None = None, capacity: int | None = None,
+                 stream=None):
+    """fic_encode_image. Returns (codes uint8 [capacity, 32], n_codes int32 [1],
+    stats uint8 [n_levels, 24]) as device tensors."""
+    import torch
+    img = _dev_u8_image(img)
+    params = params or EncoderParams()
+    H, W = img.shape
+    cap = code_capacity(H, W, params.levels) if capacity is None else capacity
+    codes = torch.empty((max(cap, 1), 32), dtype=torch.uint8, device=img.device)
+    ncodes = torch.zeros(1, dtype=torch.int32, device=img.device)
+    stats = torch.zeros((len(params.levels), 24), dtype=torch.uint8, device=img.device)
+    p = params.to_c()
+    rc = load().fic_encode_image(img.data_ptr(), H, W, img.stride(0), ctypes.byref(p),
+                                 codes.data_ptr(), cap, ncodes.data_ptr(), stats.data_ptr(),
+                                 _stream(stream))
+    _check(rc)
+    return codes, ncodes, stats
+
+
+def decode(codes, n_codes: int, H: int, W: int, iters: int = 64, stream=None):
+    """fic_decode (synchronous). Returns a uint8 [H, W] device tensor."""
+    import torch
+    out = torch.empty((H, W), dtype=torch.uint8, device=codes.device)
+    rc = load().fic_decode(codes.data_ptr(), int(n_codes), H, W, iters, out.data_ptr(), W,
+                           _stream(stream))
+    _check(rc)
+    return out
+
+
+def sse(a, b, stream=None):
+    """fic_sse: sum of squared differences of two uint8 images, as an int64 device tensor."""
+    import torch
+    a, b = _dev_u8_image(a), _dev_u8_image(b)
+    if a.shape != b.shape:
+        raise ValueError("shape mismatch")
+    out = torch.zeros(1, dtype=torch.int64, device=a.device)
+    rc = load().fic_sse(a.data_ptr(), a.stride(0), b.data_ptr(), b.stride(0), a.shape[0],
+                        a.shape[1], out.data_ptr(), _stream(stream))
+    _check(rc)
+    return out
+
+
+def psnr(a, b) -> float:
+    """10 log10(255^2 / MSE) with the SSE from the GPU."""
+    import math
+    s = int(sse(a, b).item())
+    return float("inf") if s == 0 else 10.0 * math.log10(255.0 ** 2 * a.numel() / s)
+
+
+def calibrate_s(img, params: EncoderParams | None = None, stream=None):
+    """fic_calibrate_s: per-level mean best k of kept low-entropy ranges (-1 = none)."""
+    img = _dev_u8_image(img)
+    params = params or EncoderParams()
+    p = params.to_c()
+    out = (ctypes.c_int8 * 4)()
+    rc = load().fic_calibrate_s(img.data_ptr(), img.shape[0], img.shape[1], img.stride(0),
+                                ctypes.byref(p), out, _stream(stream))
+    _check(rc)
+    return [int(out[i]) for i in range(len(params.levels))]
+
+
+def calibrated_sets(ks, fallback=PAPER_K):
+    """Per-level 1-element contrast sets from calibrate_s output (fallback where -1)."""
+    return tuple((k,) if k >= 0 else tuple(fallback[l]) for l, k in enumerate(ks))
+
+
+# ------------------------------------------------------------------ host views
+def matches_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().reshape(-1).view(MATCH_DTYPE)
+
+
+def codes_numpy(codes, n_codes) -> np.ndarray:
+    n = int(n_codes.item()) if hasattr(n_codes, "item") else int(n_codes)
+    n = min(n, codes.shape[0])
+    return codes[:n].cpu().numpy().reshape(-1).view(CODE_DTYPE)
+
+
+def stats_numpy(stats) -> np.ndarray:
+    return stats.cpu().numpy().reshape(-1).view(STATS_DTYPE)

@@ -1,0 +1,141 @@
+"""C-ABI library: it loads, exports every declared symbol, and rejects bad
+arguments on the host before any device call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1501_04140_amd import fic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fic.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fic_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return fic.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert {"fic_encode_level", "fic_encode_image", "fic_decode", "fic_last_error"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.fic_version() == 100
+
+
+def test_struct_layouts_match_header():
+    assert fic.MATCH_DTYPE.itemsize == 24
+    assert fic.CODE_DTYPE.itemsize == 32
+    assert fic.STATS_DTYPE.itemsize == 24
+    assert ctypes.sizeof(fic.Params) == 4 + 4 + 16 + 16 + 48 + 4 + 4 + 4 + 4
+
+
+def _level(lib, **kw):
+    a = dict(img=1, H=64, W=64, pitch=64, B=8, L=4, s_k=(0, 1, 2), n_s=None, mode=0, bits=2.5,
+             min_pool=1, ranges=None, n_ranges=None, out=1)
+    a.update(kw)
+    ks = (ctypes.c_int8 * 16)(*a["s_k"])
+    n_s = len(a["s_k"]) if a["n_s"] is None else a["n_s"]
+    n_r = (a["H"] // max(a["B"], 1)) * (a["W"] // max(a["B"], 1)) if a["n_ranges"] is None else a["n_ranges"]
+    rc = lib.fic_encode_level(a["img"], a["H"], a["W"], a["pitch"], a["B"], a["L"], ks, n_s,
+                              a["mode"], a["bits"], a["min_pool"], a["ranges"], n_r, a["out"],
+                              None, None, None)
+    return rc, lib.fic_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(img=None), "image pointer"),
+    (dict(B=3), "range side"),
+    (dict(B=32), "range side"),
+    (dict(H=60), "multiple"),
+    (dict(H=8, W=8), "smaller than a domain"),
+    (dict(pitch=32), "pitch"),
+    (dict(L=0), "step"),
+    (dict(s_k=(2, 1)), "increasing"),
+    (dict(s_k=(0, 11)), "not in 0..10"),
+    (dict(s_k=tuple(range(11)) + (0,), n_s=12), "size"),
+    (dict(n_s=0), "size"),
+    (dict(mode=2), "entropy_mode"),
+    (dict(min_pool=0), "min_pool"),
+    (dict(n_ranges=5), "n_ranges"),
+    (dict(out=None), "out is NULL"),
+    (dict(H=32768, W=64), "above"),
+])
+def test_encode_level_rejects(lib, kw, frag):
+    rc, msg = _level(lib, **kw)
+    assert rc == fic.FIC_EINVAL and frag in msg
+
+
+def _params(**kw):
+    p = fic.EncoderParams(**{k: v for k, v in kw.items() if k in fic.EncoderParams.__dataclass_fields__})
+    c = p.to_c()
+    for k, v in kw.items():
+        if k not in fic.EncoderParams.__dataclass_fields__:
+            setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw,code,frag", [
+    (dict(n_levels=0), fic.FIC_EINVAL, "n_levels"),
+    (dict(n_levels=5), fic.FIC_EINVAL, "n_levels"),
+    (dict(B0=12), fic.FIC_EINVAL, "B0"),
+    (dict(B0=4), fic.FIC_EINVAL, "last level"),
+    (dict(rms=-1.0), fic.FIC_EINVAL, "rms_thresh"),
+    (dict(rms=float("inf")), fic.FIC_EINVAL, "rms_thresh"),
+    (dict(entropy_mode=3), fic.FIC_EINVAL, "entropy_mode"),
+    (dict(min_pool=0), fic.FIC_EINVAL, "min_pool"),
+    (dict(s_sets=((1,), (2, 2), (3,), (5,))), fic.FIC_EINVAL, "increasing"),
+])
+def test_encode_image_rejects(lib, kw, code, frag):
+    c = _params(**kw)
+    n = ctypes.c_int32(0)
+    rc = lib.fic_encode_image(1, 64, 64, 64, ctypes.byref(c), 1, 4096, 1, None, None)
+    assert rc == code and frag in lib.fic_last_error().decode()
+
+
+def test_encode_image_capacity_lower_bound(lib):
+    c = _params()
+    rc = lib.fic_encode_image(1, 64, 64, 64, ctypes.byref(c), 1, 15, 1, None, None)
+    assert rc == fic.FIC_ECAPACITY and "capacity" in lib.fic_last_error().decode()
+
+
+def test_decode_and_sse_reject(lib):
+    assert lib.fic_decode(1, 4, 16, 16, 4, None, 16, None) == fic.FIC_EINVAL
+    assert lib.fic_decode(1, 0, 16, 16, 4, 1, 16, None) == fic.FIC_EINVAL
+    assert lib.fic_decode(1, 4, 16, 16, -1, 1, 16, None) == fic.FIC_EINVAL
+    assert lib.fic_decode(1, 4, 16, 16, 4, 1, 8, None) == fic.FIC_EINVAL
+    assert lib.fic_sse(None, 4, 1, 4, 4, 4, 1, None) == fic.FIC_EINVAL
+    assert lib.fic_sse(1, 2, 1, 4, 4, 4, 1, None) == fic.FIC_EINVAL
+
+
+def test_calibrate_rejects(lib):
+    c = _params(n_levels=0)
+    out = (ctypes.c_int8 * 4)()
+    assert lib.fic_calibrate_s(1, 64, 64, 64, ctypes.byref(c), out, None) == fic.FIC_EINVAL
+    c = _params()
+    assert lib.fic_calibrate_s(1, 64, 64, 64, ctypes.byref(c), None, None) == fic.FIC_EINVAL
+
+
+def test_params_marshalling():
+    c = fic.EncoderParams(s_sets=fic.PAPER_K).to_c()
+    assert (c.n_levels, c.B0) == (4, 16)
+    assert list(c.L) == [8, 4, 2, 1]
+    assert list(c.n_s) == [1, 2, 2, 2]
+    assert [list(c.s_k[l])[:c.n_s[l]] for l in range(4)] == [[1], [2, 4], [3, 8], [5, 9]]
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        fic.encode_level(torch.zeros((16, 16), dtype=torch.uint8), 4, 2)
+    with pytest.raises(TypeError):
+        fic.encode_level(np.zeros((16, 16), np.uint8), 4, 2)

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by
+element. Every integer field must match exactly; e_num (1600 n E) times n must
+equal the oracle's exact (40 n)^2 E."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_04140_amd import fic, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fic.load()
+    return torch.device("cuda:0")
+
+
+def gpu_level(dev, img, B, L, ks, entropy=0, bits=2.5, min_pool=256, ranges=None):
+    x = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
+    r = None if ranges is None else torch.from_numpy(np.asarray(ranges, np.int32)).to(dev)
+    out, pool, pc = fic.encode_level(x, B, L, ks, entropy, bits, min_pool, ranges=r, return_pool=True)
+    torch.cuda.synchronize()
+    return fic.matches_numpy(out), pool.cpu().numpy()[:int(pc.item())]
+
+
+def assert_level_equal(got, ref, B):
+    n = B * B
+    assert len(got) == len(ref)
+    assert np.array_equal(got["dom"], ref["dom"])
+    assert np.array_equal(got["iso"].astype(np.int32), ref["iso"])
+    assert np.array_equal(got["s_idx"].astype(np.int32), ref["s_idx"])
+    assert np.array_equal(got["k"].astype(np.int32), ref["k"])
+    assert np.array_equal(got["q_o"].astype(np.int32), ref["q_o"])
+    assert np.array_equal(got["e_num"] * n, ref["e_lit"])
+    E_ref = ref["e_lit"] / (40.0 * n) ** 2
+    assert np.allclose(got["E"], E_ref, rtol=1e-6, atol=1e-6)
+
+
+def check_level(dev, img, B, L, ks, entropy=0, min_pool=256, ranges=None, bits=2.5):
+    say(f"[level] shape={img.shape} B={B} L={L} ks={ks} entropy={entropy} min_pool={min_pool}")
+    got, gpool = gpu_level(dev, img, B, L, ks, entropy, bits, min_pool, ranges)
+    if entropy:
+        pool, _ = oracle.entropy_pool(img, B, L, bits, min_pool)
+        assert np.array_equal(gpool, pool)
+    else:
+        gy, gx = oracle.domain_grid(*img.shape, B, L)
+        pool = None
+        assert len(gpool) == gy * gx
+    ref = oracle.match_level(img, B, L, ks, pool, ranges)
+    assert_level_equal(got, ref, B)
+    return got
+
+
+# ------------------------------------------------------------------ single level
+def test_single_level_workload_full(dev):
+    """128x128 gradients + blobs + noise, 8x8 ranges, step 4 (841 domains), s = 0..1."""
+    img = synth.single_level_image(0)
+    check_level(dev, img, 8, 4, oracle.PLAIN_K)
+
+
+@pytest.mark.parametrize("B,L,ks", [
+    (2, 1, oracle.PLAIN_K), (2, 3, (5, 9)), (4, 2, oracle.PLAIN_K), (4, 5, (2, 4)),
+    (8, 3, (3, 8)), (8, 8, (0,)), (16, 8, (1,)), (16, 5, oracle.PLAIN_K),
+    (4, 1, (10,)), (8, 2, (1, 5, 9)), (2, 2, (3, 4, 5, 6)),
+])
+def test_level_shapes_and_sets(dev, B, L, ks):
+    img = synth.power_law(64, 96, beta=2.0, seed=B * 100 + L, n_rect=2)
+    check_level(dev, img, B, L, ks)
+
+
+@pytest.mark.parametrize("kind", ["constant", "replicated", "noise", "two_tone"])
+def test_level_adversarial(dev, kind):
+    rng = np.random.default_rng(5)
+    if kind == "constant":
+        img = np.full((48, 48), 131, np.uint8)
+    elif kind == "replicated":
+        img = np.kron(rng.integers(0, 256, size=(24, 24)), np.ones((2, 2))).astype(np.uint8)
+    elif kind == "noise":
+        img = rng.integers(0, 256, size=(48, 48)).astype(np.uint8)
+    else:
+        img = (rng.integers(0, 2, size=(48, 48)) * 255).astype(np.uint8)
+    for B, L in ((2, 1), (4, 2), (8, 4)):
+        check_level(dev, img, B, L, oracle.PLAIN_K)
+        check_level(dev, img, B, L, (2, 4))
+
+
+def test_isometric_copies(dev):
+    rng = np.random.default_rng(0)
+    for t in range(8):
+        img = rng.integers(0, 256, size=(48, 48)).astype(np.int64)
+        m = rng.integers(0, 26, size=(4, 4))
+        img[24:32, 24:32] = np.kron(10 * m, np.ones((2, 2), dtype=np.int64))
+        rot = [m, np.rot90(m, -1), np.rot90(m, 2), np.rot90(m, 1)][t % 4]
+        rot = np.fliplr(rot) if t >= 4 else rot
+        img[4:8, 8:12] = 10 * rot + 3
+        img = img.astype(np.uint8)
+        got = check_level(dev, img, 4, 4, oracle.PLAIN_K, ranges=np.array([[4, 8], [0, 0]]))
+        assert got["e_num"][0] == 0 and got["iso"][0] == t and got["k"][0] == 10
+
+
+def test_range_subset_and_invalid_corner(dev):
+    img = synth.power_law(64, beta=1.8, seed=2)
+    ranges = np.array([[8, 16], [0, 0], [56, 56], [3, 4], [64, 0], [24, 8]], np.int32)
+    say("[level] invalid corners")
+    got, _ = gpu_level(dev, img, 8, 4, oracle.PLAIN_K, ranges=ranges)
+    assert got["dom"][3] == -1 and got["dom"][4] == -1
+    ok = [0, 1, 2, 5]
+    ref = oracle.match_level(img, 8, 4, oracle.PLAIN_K, None, ranges[ok])
+    assert_level_equal(got[ok], ref, 8)
+
+
+# ------------------------------------------------------------------ entropy filter (Section 3)
+@pytest.mark.parametrize("B,L,min_pool", [(2, 1, 256), (4, 2, 256), (8, 4, 64), (16, 8, 32),
+                                          (4, 2, 5000), (2, 1, 10 ** 6)])
+def test_entropy_pool_floor_and_pass(dev, B, L, min_pool):
+    img = synth.power_law(96, beta=2.0, seed=1, n_rect=3)
+    check_level(dev, img, B, L, (2, 4), entropy=1, min_pool=min_pool)
+
+
+def test_entropy_pool_many_pass(dev):
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, size=(64, 64)).astype(np.uint8)   # near-uniform bins: high entropy
+    img[:32, :32] = 100
+    for B, L in ((2, 1), (4, 2), (8, 4)):
+        check_level(dev, img, B, L, (3, 8), entropy=1, min_pool=16)
+
+
+def test_entropy_threshold_variants(dev):
+    img = synth.power_law(64, beta=1.5, seed=4)
+    for bits in (0.0, 1.0, 1.75, 2.0):
+        check_level(dev, img, 4, 2, (1,), entropy=1, min_pool=8, bits=bits)
+
+
+# ------------------------------------------------------------------ quadtree
+def gpu_image(dev, img, params):
+    x = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
+    codes, n, stats = fic.encode_image(x, params)
+    torch.cuda.synchronize()
+    return codes, n, fic.codes_numpy(codes, n), fic.stats_numpy(stats)
+
+
+def assert_codes_equal(got, ref):
+    assert len(got) == len(ref)
+    for f in ("level", "y", "x", "dom", "dy", "dx", "iso", "s_idx", "k", "q_o"):
+        assert np.array_equal(got[f].astype(np.int64), ref[f].astype(np.int64)), f
+    assert np.array_equal(1 << got["log2B"].astype(np.int64), ref["B"])
+    n = (1 << got["log2B"].astype(np.int64)) ** 2
+    assert np.array_equal(got["e_num"] * n, ref["e_lit"])
+
+
+@pytest.mark.parametrize("size,seed,min_pool,sets", [
+    (64, 0, 64, "paper"), (96, 1, 128, "paper"), (128, 2, 256, "paper"), (64, 3, 16, "plain"),
+])
+def test_quadtree_matches_oracle(dev, size, seed, min_pool, sets):
+    img = synth.power_law(size, beta=2.0, seed=seed, n_rect=3)
+    ks = oracle.PAPER_K if sets == "paper" else (oracle.PLAIN_K,) * 4
+    say(f"[quadtree] size={size} seed={seed} min_pool={min_pool} sets={sets}")
+    codes, n, got, st = gpu_image(dev, img, fic.EncoderParams(s_sets=ks, min_pool=min_pool))
+    ref, rst = oracle.encode_image(img, s_sets=ks, min_pool=min_pool)
+    assert_codes_equal(got, ref)
+    for l, s in enumerate(rst):
+        assert (st["pool"][l], st["active"][l], st["accepted"][l], st["matches"][l]) == (
+            s["pool"], s["active"], s["accepted"], s["matches"])
+        assert st["passed"][l] == s["passed"]
+    rec = fic.decode(codes, int(n.item()), size, size, iters=24)
+    assert np.array_equal(rec.cpu().numpy(), oracle.decode(ref, size, size, iters=24))
+
+
+def test_quadtree_unfiltered_plain(dev):
+    img = synth.gradients_blobs(64, seed=7)
+    params = fic.EncoderParams(s_sets=(oracle.PLAIN_K,) * 4, entropy_mode=0)
+    say("[quadtree] unfiltered plain 64")
+    _, _, got, _ = gpu_image(dev, img, params)
+    ref, _ = oracle.encode_image(img, s_sets=(oracle.PLAIN_K,) * 4, entropy=False)
+    assert_codes_equal(got, ref)
+
+
+def test_quadtree_capacity_overflow_reports_required(dev):
+    img = synth.power_law(64, beta=2.0, seed=0, n_rect=3)
+    x = torch.from_numpy(img).to(dev)
+    params = fic.EncoderParams(min_pool=64)
+    say("[quadtree] capacity overflow")
+    full, nfull, _ = fic.encode_image(x, params)
+    small, nsmall, _ = fic.encode_image(x, params, capacity=16)
+    torch.cuda.synchronize()
+    need = int(nfull.item())
+    assert int(nsmall.item()) == need and need > 16
+    assert np.array_equal(small.cpu().numpy()[:16], full.cpu().numpy()[:16])
+
+
+def test_quadtree_full_size_paper_preset(dev):
+    """512x512 1/f^2 + rectangles with the predefined s of Section 3.1, whole image."""
+    img = synth.quadtree_image(0)
+    say("[quadtree] 512 paper preset")
+    codes, n, got, st = gpu_image(dev, img, fic.EncoderParams(s_sets=oracle.PAPER_K))
+    ref, _ = oracle.encode_image(img, s_sets=oracle.PAPER_K)
+    assert_codes_equal(got, ref)
+    rec = fic.decode(codes, int(n.item()), 512, 512, iters=8)
+    assert np.array_equal(rec.cpu().numpy(), oracle.decode(ref, 512, 512, iters=8))
+
+
+def test_calibration_matches_oracle(dev):
+    img = synth.power_law(64, beta=2.0, seed=0, n_rect=3)
+    say("[calibrate] 64")
+    x = torch.from_numpy(img).to(dev)
+    ks = fic.calibrate_s(x, fic.EncoderParams())
+    ref = oracle.calibrate_s(img, fallback=((-1,),) * 4)
+    assert ks == [r[0] for r in ref]
+
+
+def test_sse_psnr(dev):
+    rng = np.random.default_rng(0)
+    a = rng.integers(0, 256, size=(37, 53)).astype(np.uint8)
+    b = rng.integers(0, 256, size=(37, 53)).astype(np.uint8)
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    assert int(fic.sse(ta, tb).item()) == int(((a.astype(np.int64) - b) ** 2).sum())
+    assert fic.psnr(ta, tb) == pytest.approx(oracle.psnr(a, b), rel=1e-12)
+
+
+def test_decode_rejects_bad_codes(dev):
+    img = synth.power_law(32, beta=2.0, seed=0)
+    x = torch.from_numpy(img).to(dev)
+    codes, n, _ = fic.encode_image(x, fic.EncoderParams(min_pool=8))
+    torch.cuda.synchronize()
+    k = int(n.item())
+    with pytest.raises(fic.FicError):
+        fic.decode(codes, k - 1, 32, 32, iters=2)          # a hole
+    bad = codes.clone()
+    bad[0, 16:18] = torch.tensor([30, 0], dtype=torch.uint8)  # dy = 30: domain leaves the image
+    with pytest.raises(fic.FicError):
+        fic.decode(bad, k, 32, 32, iters=2)
+
+
+# ------------------------------------------------------------------ large sizes, sampled
+def test_precision_workload_sampled(dev):
+    """1024x1024 1/f^1.8, 8x8 ranges, step 2 (505^2 domains), s = 0..1: the whole
+    image on the GPU, a deterministic sample of ranges through the oracle."""
+    img = synth.precision_image(0)
+    say("[level] 1024 precision workload")
+    got, _ = gpu_level(dev, img, 8, 2, oracle.PLAIN_K)
+    idx = np.arange(0, 16384, 1031)[:12]
+    ranges = oracle.full_ranges(1024, 1024, 8)[idx]
+    ref = oracle.match_level(img, 8, 2, oracle.PLAIN_K, None, ranges)
+    assert_level_equal(got[idx], ref, 8)
