@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the fractal encoder's matching path on one MI355X.
+
+Default workload: the paper's method (Section 3) on a 512x512 1/f^2 image with
+three hard-edged rectangles. That is the entropy-filtered pool at L = B/2, the
+16 -> 8 -> 4 -> 2 quadtree splitting at RMS error > 8, and per-level
+predefined contrast values estimated from low-entropy ranges. One step is one
+whole quadtree encode of the resident image.
+
+Prints one JSON line: matches/s (range x pool domain x isometry, summed over
+levels), encode ms, PSNR of the decoded image against the plain exhaustive
+encoder, the matcher's roofline and the CPU oracle's rate on the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_ALU_TOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 ops (32-bit multiply-add per lane per clock)
+PEAK_INT8_TOPS = 5000.0
+PEAK_HBM_GBS = 8000.0
+
+
+def match_ops(n: int, n_s: int) -> int:
+    """Algorithmic integer ops of one match (range x domain x isometry): the
+    correlation sum r*d' (n multiply-adds), B' = n P - sumR sumD' (2 ops) and,
+    per contrast value, k^2 A' - 80 k B' (3 ops)."""
+    return 2 * n + 2 + 3 * n_s
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="quadtree512",
+                    choices=["quadtree512", "single128", "precision1024"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-psnr", action="store_true")
+    ap.add_argument("--preset", default="calibrated", choices=["calibrated", "paper"])
+    return ap.parse_args()
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def roofline_from_profile(prof, per_label_ops):
+    """Dominant kernel over the timed region: algorithmic ops per launch / mean launch time."""
+    best = None
+    for label, (launches, total_ms) in prof.items():
+        if best is None or total_ms > best[2]:
+            best = (label, launches, total_ms)
+    label, launches, total_ms = best
+    ops = per_label_ops.get(label)
+    out = {"kernel": label, "launches": launches, "avg_us": total_ms / launches * 1e3}
+    if ops is None:
+        return out
+    avg_s = total_ms / launches / 1e3
+    achieved = ops / avg_s / 1e12
+    out.update({"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TOPS, "unit": "TOP/s",
+                "frac": achieved / PEAK_ALU_TOPS, "traffic": None,
+                "ops_per_launch": ops})
+    return out
+
+
+def run_quadtree(args, torch):
+    import numpy as np
+
+    from paper_1501_04140_amd import fic, synth
+
+    img = synth.quadtree_image(0)
+    H, W = img.shape
+    x = torch.from_numpy(img).cuda()
+    if args.preset == "calibrated":
+        ks = fic.calibrate_s(x, fic.EncoderParams())
+        s_sets = fic.calibrated_sets(ks)
+    else:
+        s_sets = fic.PAPER_K
+    params = fic.EncoderParams(s_sets=s_sets)
+    out = fic.encode_image(x, params)
+    torch.cuda.synchronize()
+    st = fic.stats_numpy(out[2])
+    matches = int(st["matches"].sum())
+
+    ms, wall_ms = time_steps(lambda: fic.encode_image(x, params, out=out), args.steps,
+                             args.warmup, torch)
+    # same steps again with HIP events around every matcher launch
+    fic.profile_begin()
+    for _ in range(args.steps):
+        fic.encode_image(x, params, out=out)
+    torch.cuda.synchronize()
+    prof = fic.profile_end()
+    per_label = {}
+    for lv, B in enumerate(params.levels):
+        n = B * B
+        per_label[f"match_b{B}"] = int(st["matches"][lv]) * match_ops(n, len(s_sets[lv]))
+    match_prof = {k: v for k, v in prof.items() if k.startswith("match")}
+    roof = roofline_from_profile(match_prof, per_label)
+
+    res = {
+        "metric": "matches/s (range×domain×isometry) + 512² encode ms; PSNR Δ vs exhaustive",
+        "value": matches / (ms / 1e3),
+        "unit": "matches/s",
+        "encode_ms": ms,
+        "encode_ms_wall": wall_ms,
+        "matches_per_step": matches,
+        "s_candidates_per_match": [len(s) for s in s_sets],
+        "config": {
+            "workload": "quadtree512: paper's method, 512x512 1/f^2 + 3 rectangles (seed 0)",
+            "levels": list(params.levels), "L": [max(B // 2, 1) for B in params.levels],
+            "s_k": [list(s) for s in s_sets], "s_preset": args.preset,
+            "entropy_bits": 2.5, "min_pool": 256, "rms_split": 8.0,
+            "pool": [int(v) for v in st["pool"]], "active": [int(v) for v in st["active"]],
+            "accepted": [int(v) for v in st["accepted"]],
+        },
+        "roofline": roof,
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(
+            prof.items(), key=lambda kv: -kv[1][1])},
+    }
+    if not args.no_psnr:
+        codes, n, _ = out
+        rec = fic.decode(codes, int(n.item()), H, W, iters=64)
+        p_method = fic.psnr(rec, x)
+        plain = fic.EncoderParams(s_sets=(fic.PLAIN_K,) * 4, entropy_mode=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c2, n2, s2 = fic.encode_image(x, plain)
+        torch.cuda.synchronize()
+        ex_ms = (time.perf_counter() - t0) * 1e3
+        rec2 = fic.decode(c2, int(n2.item()), H, W, iters=64)
+        p_ex = fic.psnr(rec2, x)
+        ex_matches = int(fic.stats_numpy(s2)["matches"].sum())
+        res["psnr_db"] = p_method
+        res["psnr_exhaustive_db"] = p_ex
+        res["psnr_delta_db"] = p_method - p_ex
+        res["exhaustive"] = {"encode_ms": ex_ms, "matches": ex_matches,
+                             "codes": int(n2.item()), "codes_method": int(n.item())}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        _, ost = oracle.encode_image(img, s_sets=s_sets)
+        dt = time.perf_counter() - t0
+        om = sum(s["matches"] for s in ost)
+        res["cpu_baseline"] = {"value": om / dt, "unit": "matches/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "seconds": dt,
+                               "sample": "the whole 512x512 encode once, same image and s values"}
+    return res
+
+
+def run_level(args, torch, which):
+    from paper_1501_04140_amd import fic, synth
+
+    if which == "single128":
+        img, B, L = synth.single_level_image(0), 8, 4
+        desc = "single128: 128x128 gradients+blobs+noise, 8x8 ranges, L=4, s=0..1 (11 values)"
+    else:
+        img, B, L = synth.precision_image(0), 8, 2
+        desc = "precision1024: 1024x1024 1/f^1.8, 8x8 ranges, L=2, s=0..1 (11 values)"
+    H, W = img.shape
+    x = torch.from_numpy(img).cuda()
+    ks = fic.PLAIN_K
+    n_r = (H // B) * (W // B)
+    gy, gx = (H - 2 * B) // L + 1, (W - 2 * B) // L + 1
+    matches = n_r * gy * gx * 8
+    ms, wall_ms = time_steps(lambda: fic.encode_level(x, B, L, ks), args.steps, args.warmup, torch)
+    fic.profile_begin()
+    for _ in range(args.steps):
+        fic.encode_level(x, B, L, ks)
+    torch.cuda.synchronize()
+    prof = fic.profile_end()
+    roof = roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")},
+                                 {f"match_b{B}": matches * match_ops(B * B, 1)})
+    res = {
+        "metric": "matches/s (range×domain×isometry)",
+        "value": matches / (ms / 1e3), "unit": "matches/s", "encode_ms": ms,
+        "encode_ms_wall": wall_ms, "matches_per_step": matches,
+        "config": {"workload": desc}, "roofline": roof,
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        import numpy as np
+
+        import oracle
+        oracle.build(force=False)
+        ranges = oracle.full_ranges(H, W, B)
+        if which == "precision1024":
+            ranges = ranges[::512]
+        t0 = time.perf_counter()
+        oracle.match_level(img, B, L, ks, None, ranges)
+        dt = time.perf_counter() - t0
+        om = len(ranges) * gy * gx * 8
+        res["cpu_baseline"] = {"value": om / dt, "unit": "matches/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "seconds": dt,
+                               "sample": f"{len(ranges)} of {n_r} ranges, every domain"}
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark measures one GPU; the encoder's multi-GPU "
+                                   "sharding is a design only, so --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    from paper_1501_04140_amd import fic
+    fic.load()
+    if args.workload == "quadtree512":
+        res = run_quadtree(args, torch)
+    else:
+        res = run_level(args, torch, args.workload)
+    line = {
+        "metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["encode_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8 dot4 -> i32, i64 exact", "data": "synthetic",
+    }
+    line.update(res)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

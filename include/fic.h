@@ -200,6 +200,27 @@ int fic_sse(const uint8_t* a, int32_t pitch_a, const uint8_t* b, int32_t pitch_b
 int fic_calibrate_s(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
                     const fic_params* p, int8_t* k_out, void* stream);
 
+/* Device time of one kernel label, from HIP events (40 bytes). */
+typedef struct {
+    char name[24];     /* kernel label, e.g. "match_b2" or "pool_score"             */
+    int32_t launches;  /* launches recorded                                          */
+    int32_t pad_;
+    double total_ms;   /* summed time between the events around each launch          */
+} fic_kernel_time;
+
+/*
+ * Profiling hooks (measurement only; the encoder never needs them).
+ * fic_profile_begin clears earlier records and starts recording. Every later
+ * launch of a library kernel, on any stream, is then bracketed by two HIP
+ * events on its stream.
+ * fic_profile_end stops recording and waits for the recorded events. It sums
+ * the intervals per kernel label into out[0 .. max-1], longest total first,
+ * and writes the number of labels to *n_out (out and n_out may be NULL).
+ * Process-wide; not meant to run while another thread encodes.
+ */
+int fic_profile_begin(void);
+int fic_profile_end(fic_kernel_time* out, int32_t max, int32_t* n_out);
+
 /* Message for the last non-zero return on this thread. */
 const char* fic_last_error(void);
 

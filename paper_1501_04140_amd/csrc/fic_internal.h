@@ -20,13 +20,15 @@ constexpr int kMaxWindow = 1024;  // largest histogram window (32 x 32 domain)
 struct Ctrl {
     int32_t act_count[5];  // active ranges per quadtree level (index = level)
     int32_t pool_count;    // domains in the current level's pool
-    int32_t pass_count;    // domains above the entropy threshold
+    int32_t pass_count;    // running count of the entropy score kernel (reset by it)
+    int32_t passed;        // domains above the entropy threshold at this level
     int32_t n_codes;       // codes emitted so far (may exceed capacity)
     int32_t code_base;     // first code slot of the current level
     int32_t err;
     int32_t sel_rank;      // rank still to find inside the current key prefix
-    uint32_t ticket;       // last-workgroup ticket of the radix select
-    uint64_t sel_prefix;   // key bits fixed so far by the radix select
+    uint32_t ticket;       // last-workgroup ticket (each kernel resets it)
+    uint64_t sel_prefix;   // unused, kept for layout
+    uint64_t cut_bound;    // floor mode: upper bound on the min_pool-th smallest key
     uint32_t ghist[kSelBins];
 };
 

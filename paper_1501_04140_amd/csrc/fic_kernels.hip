@@ -12,6 +12,9 @@
 // with A' = n sum d'^2 - (sum d')^2, B' = n <r, d'> - sum r sum d',
 // C = n sum r^2 - (sum r)^2 and d' = 4 d, the integer 2x2 sum. This is eq. (1)
 // with o from eq. (3) expanded in the moments of R and D.
+#include <limits>
+#include <type_traits>
+
 #include "fic_internal.h"
 
 namespace fic {
@@ -40,42 +43,50 @@ __device__ inline int64_t floordiv64(int64_t a, int64_t b) {  // b > 0
     return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
-// ---------------------------------------------------------------- control block
-__global__ void k_level_init(Ctrl* ctrl, int lv, int act_count_init, int pool_identity_count,
-                             int min_pool_rank) {
-    int tid = threadIdx.x;
-    for (int i = tid; i < kSelBins; i += blockDim.x) ctrl->ghist[i] = 0u;
-    if (tid == 0) {
-        if (act_count_init >= 0) ctrl->act_count[lv] = act_count_init;
-        ctrl->pass_count = pool_identity_count >= 0 ? pool_identity_count : 0;
-        ctrl->pool_count = pool_identity_count >= 0 ? pool_identity_count : 0;
-        ctrl->sel_prefix = 0ull;
-        ctrl->sel_rank = min_pool_rank;
-        ctrl->ticket = 0u;
-    }
+// ---------------------------------------------------------------- coherent loads
+// Reads of values that other workgroups of the same launch published with
+// atomics, after a ticket showed they are complete.
+template <typename T>
+__device__ inline T ld_agent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_ctrl_reset(Ctrl* ctrl) {
+// True in the workgroup that finishes last (self-resetting ticket).
+__device__ inline bool last_workgroup(uint32_t* ticket) {
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 0; i < 5; ++i) ctrl->act_count[i] = 0;
-        ctrl->n_codes = 0;
-        ctrl->code_base = 0;
-        ctrl->err = 0;
+        s_last = atomicAdd(ticket, 1u) == gridDim.x * gridDim.y - 1;
+        if (s_last) *ticket = 0u;
     }
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last;
 }
 
 // ---------------------------------------------------------------- active range lists
-// Packed corner: (y << 16) | x.
-__global__ void k_act_full(int32_t* act, int gy, int gx, int B) {
+// Packed corner: (y << 16) | x. Block 0 also sets the level's active count
+// and, when asked, clears the code counter of a new quadtree.
+__global__ void k_act_full(int32_t* act, int gy, int gx, int B, Ctrl* ctrl, int lv, int reset) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) {
+        ctrl->act_count[lv] = gy * gx;
+        if (reset) {
+            ctrl->n_codes = 0;
+            ctrl->code_base = 0;
+        }
+    }
     if (q >= gy * gx) return;
     int ry = q / gx, rx = q - ry * gx;
     act[q] = ((ry * B) << 16) | (rx * B);
 }
 
 // Caller-supplied corners; an invalid corner is stored as -1.
-__global__ void k_act_from_yx(int32_t* act, const int32_t* yx, int n, int H, int W, int B) {
+__global__ void k_act_from_yx(int32_t* act, const int32_t* yx, int n, int H, int W, int B,
+                              Ctrl* ctrl) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) ctrl->act_count[0] = n;
     if (q >= n) return;
     int y = yx[2 * q], x = yx[2 * q + 1];
     bool ok = y >= 0 && x >= 0 && y + B <= H && x + B <= W && (y % B) == 0 && (x % B) == 0;
@@ -86,25 +97,57 @@ __global__ void k_act_from_yx(int32_t* act, const int32_t* yx, int n, int H, int
 // key[j] = sum_b T[c_b] over the 8-bin (p >> 5) histogram of the 2B x 2B
 // domain j, where T[c] = round(c log2 c * 2^32). Entropy in bits is
 // log2 Nw - key / (Nw 2^32), so the domain passes iff key < M.
-__global__ void k_pool_score(const uint8_t* __restrict__ img, int pitch, int side, int L, int gx,
-                             int total, const int64_t* __restrict__ T, int64_t M,
-                             int64_t* __restrict__ key, Ctrl* ctrl) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int pass = 0;
-    if (j < total) {
-        int y = (j / gx) * L, x = (j % gx) * L;
-        int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int i = 0; i < side; ++i) {
-            const uint8_t* row = img + (int64_t)(y + i) * pitch + x;
-            for (int u = 0; u < side; ++u) {
-                int b = row[u] >> 5;
+// TPD lanes of one wavefront share a domain; each lane counts 16 pixels into
+// eight 8-bit counters packed in a 64-bit word. ctrl->pass_count accumulates
+// the domains that pass (k_floor_select clears it after the pool is built).
+template <int SIDE>
+struct ScoreShape {
+    static constexpr int NPIX = SIDE * SIDE;
+    static constexpr int PER = 16;  // pixels per lane
+    static constexpr int TPD = NPIX / PER;
+};
+
+template <int SIDE>
+__global__ __launch_bounds__(kBlock) void k_pool_score(const uint8_t* __restrict__ img, int pitch,
+                                                       int L, int gx, int total,
+                                                       const int64_t* __restrict__ T, int64_t M,
+                                                       int64_t* __restrict__ key, Ctrl* ctrl) {
+    using S = ScoreShape<SIDE>;
+    constexpr int TPD = S::TPD, PER = S::PER;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = g / TPD, sub = g % TPD;
+    const bool ok = j < total;
+    uint64_t acc = 0;
+    if (ok) {
+        const int y = (j / gx) * L, x = (j % gx) * L;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) c[q] += (b == q);
-            }
+        for (int q = 0; q < PER; ++q) {
+            const int m = sub * PER + q;
+            const int i = m / SIDE, c = m % SIDE;
+            const uint32_t b = img[(int64_t)(y + i) * pitch + x + c] >> 5;
+            acc += 1ull << (8 * b);
         }
+    }
+    // widen to 16-bit counters (4 bins per word) and add over the domain's lanes
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        lo |= ((acc >> (8 * b)) & 0xffull) << (16 * b);
+        hi |= ((acc >> (8 * (b + 4))) & 0xffull) << (16 * b);
+    }
+#pragma unroll
+    for (int m = 1; m < TPD; m <<= 1) {
+        lo += __shfl_xor(lo, m, 64);
+        hi += __shfl_xor(hi, m, 64);
+    }
+    int pass = 0;
+    if (ok && sub == 0) {
         int64_t s = 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s += T[c[q]];
+        for (int b = 0; b < 4; ++b) {
+            s += T[(lo >> (16 * b)) & 0xffff];
+            s += T[(hi >> (16 * b)) & 0xffff];
+        }
         key[j] = s;
         pass = s < M;
     }
@@ -113,64 +156,67 @@ __global__ void k_pool_score(const uint8_t* __restrict__ img, int pitch, int sid
 }
 
 // Pool mode for a level: 0 = threshold passers, 1 = floor (lowest keys), 2 = all.
-__device__ inline int pool_mode(const Ctrl* ctrl, int total, int min_pool) {
+__device__ inline int pool_mode(int passed, int total, int min_pool) {
     if (total <= min_pool) return 2;
-    return ctrl->pass_count >= min_pool ? 0 : 1;
+    return passed >= min_pool ? 0 : 1;
 }
 
-// One 12-bit digit of a radix select for the min_pool-th smallest key
-// (keys < 2^48). The last workgroup to finish picks the digit.
-__global__ void k_select_pass(const int64_t* __restrict__ key, int total, int min_pool, int shift,
-                              Ctrl* ctrl) {
-    if (pool_mode(ctrl, total, min_pool) != 1) return;
+// Floor, step 1. Workgroup b takes keys [b*chunk, (b+1)*chunk) and finds the
+// bucket of key >> shift (shift puts every key below 2^(shift+12)) holding its
+// own r-th smallest key. The chunk alone has r keys not above that bucket's
+// largest key, so the global r-th smallest key is not above it either.
+__global__ __launch_bounds__(kBlock) void k_floor_bound(const int64_t* __restrict__ key, int total,
+                                                        int min_pool, int r, int shift, int chunk,
+                                                        Ctrl* ctrl) {
+    if (pool_mode(ctrl->pass_count, total, min_pool) != 1) return;
+    const int lo = blockIdx.x * chunk, hi = min(total, lo + chunk);
+    if (hi - lo < r) return;
     __shared__ uint32_t h[kSelBins];
-    __shared__ int s_last;
-    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) h[i] = 0u;
-    __syncthreads();
-    const uint64_t prefix = ctrl->sel_prefix;
-    const int hs = shift + kSelBits;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        uint64_t u = (uint64_t)key[i];
-        if ((u >> hs) == (prefix >> hs)) atomicAdd(&h[(u >> shift) & (kSelBins - 1)], 1u);
+    __shared__ uint32_t part[kBlock];
+    __shared__ int s_t;
+    __shared__ uint32_t s_cum;
+    for (int i = threadIdx.x; i < kSelBins; i += kBlock) h[i] = 0u;
+    if (threadIdx.x == 0) {
+        s_t = 0;
+        s_cum = 0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x)
-        if (h[i]) atomicAdd(&ctrl->ghist[i], h[i]);
-    __threadfence();
+    for (int i = lo + threadIdx.x; i < hi; i += kBlock)
+        atomicAdd(&h[min((uint64_t)key[i] >> shift, (uint64_t)(kSelBins - 1))], 1u);
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&ctrl->ticket, 1u) == gridDim.x - 1);
+    constexpr int per = kSelBins / kBlock;
+    uint32_t mine = 0;
+    for (int b = 0; b < per; ++b) mine += h[threadIdx.x * per + b];
+    part[threadIdx.x] = mine;
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    // last workgroup: find the digit holding rank sel_rank (1-based)
-    __shared__ uint32_t part[256];
-    const int per = kSelBins / 256;
-    uint32_t sum = 0;
-    if (threadIdx.x < 256)
-        for (int b = 0; b < per; ++b) sum += atomicAdd(&ctrl->ghist[threadIdx.x * per + b], 0u);
-    if (threadIdx.x < 256) part[threadIdx.x] = sum;
+    for (int d = 1; d < kBlock; d <<= 1) {
+        uint32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const uint32_t incl = part[threadIdx.x], excl = incl - mine;
+    if (excl < (uint32_t)r && (uint32_t)r <= incl) {
+        s_t = threadIdx.x;
+        s_cum = excl;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t rank = (uint32_t)ctrl->sel_rank, cum = 0;
-        int t = 0;
-        while (t < 255 && cum + part[t] < rank) cum += part[t++];
-        int b = t * per;
-        for (;; ++b) {
-            uint32_t hb = atomicAdd(&ctrl->ghist[b], 0u);
-            if (cum + hb >= rank || b == t * per + per - 1) break;
-            cum += hb;
+        uint32_t cum = s_cum;
+        int b = s_t * per;
+        for (; b < s_t * per + per - 1; ++b) {
+            if (cum + h[b] >= (uint32_t)r) break;
+            cum += h[b];
         }
-        ctrl->sel_prefix = prefix | ((uint64_t)b << shift);
-        ctrl->sel_rank = (int)(rank - cum);
-        ctrl->ticket = 0u;
+        const unsigned long long bound = (((unsigned long long)b + 1) << shift) - 1;
+        atomicMin(reinterpret_cast<unsigned long long*>(&ctrl->cut_bound), bound);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) ctrl->ghist[i] = 0u;
 }
 
 // ---------------------------------------------------------------- order-preserving compaction
-// Two flags per item (f0, f1). Used for the pool (f0 = below the cut, f1 = tied
-// at the cut) and for the quadtree (f0 = kept, f1 = split).
+// Two flags per item (f0, f1). Pool: f0 = domain kept (threshold mode), a
+// floor candidate (key <= bound) or any domain (all mode). Quadtree: f0 =
+// range kept, f1 = range split.
 struct CompactArgs {
     int kind;  // 0 pool, 1 quadtree
     int total;
@@ -181,33 +227,28 @@ struct CompactArgs {
     const uint8_t* decision;   // quadtree: 1 kept, 0 split, 2 invalid
 };
 
+constexpr int kPoolItems = 32;  // domains per thread in the pool compaction
+constexpr int kQuadItems = 4;   // ranges per thread in the quadtree step
+
 __device__ inline void item_flags(const CompactArgs& a, const Ctrl* ctrl, int mode, int i, int& f0,
                                   int& f1) {
     f0 = 0;
     f1 = 0;
     if (a.kind == 0) {
         if (i >= a.total) return;
-        int64_t k = a.key[i];
+        const int64_t k = a.key[i];
         if (mode == 2) f0 = 1;
         else if (mode == 0) f0 = k < a.M;
-        else {
-            int64_t cut = (int64_t)ctrl->sel_prefix;
-            f0 = k < cut;
-            f1 = k == cut;
-        }
+        else f0 = (uint64_t)k <= ctrl->cut_bound;
     } else {
         if (i >= *a.act_count) return;
-        uint8_t d = a.decision[i];
+        const uint8_t d = a.decision[i];
         f0 = d == 1;
         f1 = d == 0;
     }
 }
 
-__device__ inline int compact_mode(const CompactArgs& a, const Ctrl* ctrl) {
-    return a.kind == 0 ? pool_mode(ctrl, a.total, a.min_pool) : 0;
-}
-
-// Inclusive scan over a 256-thread block of two counters; returns exclusive values.
+// Exclusive scan over a 256-thread block of two counters; also returns totals.
 __device__ inline void block_scan2(int v0, int v1, int& e0, int& e1, int& t0, int& t1) {
     __shared__ int w0[kBlock / 64], w1[kBlock / 64];
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -241,26 +282,9 @@ __device__ inline void block_scan2(int v0, int v1, int& e0, int& e1, int& t0, in
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_count(CompactArgs a, const Ctrl* ctrl,
-                                                          int2* blk) {
-    int mode = compact_mode(a, ctrl);
-    int base = blockIdx.x * kBlock * kItems + threadIdx.x * kItems;
-    int c0 = 0, c1 = 0;
-    for (int u = 0; u < kItems; ++u) {
-        int f0, f1;
-        item_flags(a, ctrl, mode, base + u, f0, f1);
-        c0 += f0;
-        c1 += f1;
-    }
-    int e0, e1, t0, t1;
-    block_scan2(c0, c1, e0, e1, t0, t1);
-    if (threadIdx.x == 0) blk[blockIdx.x] = make_int2(t0, t1);
-}
-
-// Single workgroup: exclusive scan of the per-block counts, then the totals.
-__global__ __launch_bounds__(kBlock) void k_compact_scan(CompactArgs a, Ctrl* ctrl, int2* blk,
-                                                         int nblk, int lv, fic_level_stats* stats,
-                                                         int codes_capacity) {
+// The last workgroup turns per-workgroup counts blk[0..nblk) into exclusive
+// offsets and returns the totals.
+__device__ inline void scan_block_counts(int2* blk, int nblk, int& tot0, int& tot1) {
     __shared__ int carry0, carry1;
     if (threadIdx.x == 0) {
         carry0 = 0;
@@ -268,8 +292,9 @@ __global__ __launch_bounds__(kBlock) void k_compact_scan(CompactArgs a, Ctrl* ct
     }
     __syncthreads();
     for (int base = 0; base < nblk; base += kBlock) {
-        int i = base + threadIdx.x;
-        int2 v = i < nblk ? blk[i] : make_int2(0, 0);
+        const int i = base + threadIdx.x;
+        int2 v = make_int2(0, 0);
+        if (i < nblk) v = make_int2(ld_agent(&blk[i].x), ld_agent(&blk[i].y));
         int e0, e1, t0, t1;
         block_scan2(v.x, v.y, e0, e1, t0, t1);
         if (i < nblk) blk[i] = make_int2(carry0 + e0, carry1 + e1);
@@ -280,163 +305,301 @@ __global__ __launch_bounds__(kBlock) void k_compact_scan(CompactArgs a, Ctrl* ct
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    if (a.kind == 0) {
-        int mode = pool_mode(ctrl, a.total, a.min_pool);
-        ctrl->pool_count = mode == 1 ? carry0 + min(carry1, ctrl->sel_rank) : carry0;
-    } else {
-        int act = *a.act_count;
-        int pool = ctrl->pool_count;
-        ctrl->code_base = ctrl->n_codes;
-        ctrl->n_codes += carry0;
-        ctrl->act_count[lv + 1] = 4 * carry1;
-        if (stats) {
-            fic_level_stats s;
-            s.matches = (int64_t)act * pool * 8;
-            s.pool = pool;
-            s.passed = ctrl->pass_count;
-            s.active = act;
-            s.accepted = carry0;
-            stats[lv] = s;
-        }
-    }
-    (void)codes_capacity;
+    tot0 = carry0;
+    tot1 = carry1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_scatter(
-    CompactArgs a, const Ctrl* ctrl, const int2* blk, int32_t* pool_out,
-    // quadtree outputs
-    const fic_code* tmp_codes, fic_code* codes, int capacity, const int32_t* act,
-    int32_t* act_next, int half) {
-    int mode = compact_mode(a, ctrl);
-    int base = blockIdx.x * kBlock * kItems + threadIdx.x * kItems;
-    int f0[kItems], f1[kItems];
+__device__ inline void publish_count(int2* blk, int t0, int t1) {
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&blk[blockIdx.x].x, t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&blk[blockIdx.x].y, t1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Pool compaction, pass 1: per-workgroup counts; the last workgroup scans them
+// and sets pool_count (the pool, or the floor candidates).
+__global__ __launch_bounds__(kBlock) void k_pool_count(CompactArgs a, Ctrl* ctrl, int2* blk) {
+    const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
+    const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
+    int c0 = 0;
+    for (int u = 0; u < kPoolItems; ++u) {
+        int f0, f1;
+        item_flags(a, ctrl, mode, base + u, f0, f1);
+        c0 += f0;
+    }
+    int e0, e1, t0, t1;
+    block_scan2(c0, 0, e0, e1, t0, t1);
+    publish_count(blk, t0, t1);
+    if (!last_workgroup(&ctrl->ticket)) return;
+    int tot0, tot1;
+    scan_block_counts(blk, gridDim.x, tot0, tot1);
+    if (threadIdx.x == 0) ctrl->pool_count = tot0;
+}
+
+// Pool compaction, pass 2: kept domains in ascending index order.
+__global__ __launch_bounds__(kBlock) void k_pool_scatter(CompactArgs a, const Ctrl* ctrl,
+                                                         const int2* blk, int32_t* pool_out) {
+    const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
+    const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
+    uint32_t bits = 0;
+    int c0 = 0;
+    for (int u = 0; u < kPoolItems; ++u) {
+        int f0, f1;
+        item_flags(a, ctrl, mode, base + u, f0, f1);
+        bits |= (uint32_t)f0 << u;
+        c0 += f0;
+    }
+    int e0, e1, t0, t1;
+    block_scan2(c0, 0, e0, e1, t0, t1);
+    int r0 = blk[blockIdx.x].x + e0;
+    for (int u = 0; u < kPoolItems; ++u)
+        if ((bits >> u) & 1u) pool_out[r0++] = base + u;
+}
+
+// Floor, step 3 (one workgroup): exact radix select of the r-th smallest key
+// among the candidates, then in-place compaction to the keys below it plus the
+// first ties in index order. Always launched: it also publishes the number of
+// domains that passed the threshold and clears the per-level counters.
+__global__ __launch_bounds__(1024) void k_floor_select(const int64_t* __restrict__ key, int total,
+                                                       int min_pool, int r,
+                                                       int32_t* __restrict__ pool, Ctrl* ctrl) {
+    __shared__ uint32_t h[kSelBins];
+    __shared__ uint32_t part[1024];
+    __shared__ uint64_t s_prefix;
+    __shared__ uint32_t s_rank, s_cum;
+    __shared__ int s_t, s_w0[16], s_w1[16], s_c0, s_c1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int passed = ctrl->pass_count;
+    const int mode = pool_mode(passed, total, min_pool);
+    if (mode == 1) {
+        const int C = ctrl->pool_count;
+        if (tid == 0) {
+            s_prefix = 0;
+            s_rank = (uint32_t)r;
+        }
+        for (int shift = 48 - kSelBits; shift >= 0; shift -= kSelBits) {
+            for (int i = tid; i < kSelBins; i += nt) h[i] = 0u;
+            __syncthreads();
+            const uint64_t prefix = s_prefix;
+            const int hs = shift + kSelBits;
+            for (int i = tid; i < C; i += nt) {
+                const uint64_t u = (uint64_t)key[pool[i]];
+                if ((u >> hs) == (prefix >> hs)) atomicAdd(&h[(u >> shift) & (kSelBins - 1)], 1u);
+            }
+            __syncthreads();
+            constexpr int per = kSelBins / 1024;
+            uint32_t mine = 0;
+            for (int b = 0; b < per; ++b) mine += h[tid * per + b];
+            part[tid] = mine;
+            if (tid == 0) {
+                s_t = 0;
+                s_cum = 0;
+            }
+            __syncthreads();
+            for (int d = 1; d < nt; d <<= 1) {
+                uint32_t v = tid >= d ? part[tid - d] : 0u;
+                __syncthreads();
+                part[tid] += v;
+                __syncthreads();
+            }
+            const uint32_t rank = s_rank;
+            const uint32_t incl = part[tid], excl = incl - mine;
+            if (excl < rank && rank <= incl) {
+                s_t = tid;
+                s_cum = excl;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t cum = s_cum;
+                int b = s_t * per;
+                for (; b < s_t * per + per - 1; ++b) {
+                    if (cum + h[b] >= rank) break;
+                    cum += h[b];
+                }
+                s_prefix = prefix | ((uint64_t)b << shift);
+                s_rank = rank - cum;
+            }
+            __syncthreads();
+        }
+        const uint64_t cut = s_prefix;
+        const int take = (int)s_rank;  // ties at the cut to keep
+        if (tid == 0) {
+            s_c0 = 0;
+            s_c1 = 0;
+        }
+        __syncthreads();
+        for (int base = 0; base < C; base += nt) {
+            const int i = base + tid;
+            int j = 0, less = 0, tie = 0;
+            if (i < C) {
+                j = pool[i];
+                const uint64_t u = (uint64_t)key[j];
+                less = u < cut;
+                tie = u == cut;
+            }
+            // block-wide exclusive scan of (less, tie)
+            int a0 = less, a1 = tie;
+            const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                int x0 = __shfl_up(a0, d, 64), x1 = __shfl_up(a1, d, 64);
+                if (lane >= d) {
+                    a0 += x0;
+                    a1 += x1;
+                }
+            }
+            if (lane == 63) {
+                s_w0[wid] = a0;
+                s_w1[wid] = a1;
+            }
+            __syncthreads();
+            int b0 = s_c0, b1 = s_c1, t0 = 0, t1 = 0;
+            for (int w = 0; w < nt / 64; ++w) {
+                if (w < wid) {
+                    b0 += s_w0[w];
+                    b1 += s_w1[w];
+                }
+                t0 += s_w0[w];
+                t1 += s_w1[w];
+            }
+            const int lr = b0 + a0 - less, tr = b1 + a1 - tie;
+            __syncthreads();
+            if (i < C && (less || (tie && tr < take))) pool[lr + min(tr, take)] = j;
+            if (tid == 0) {
+                s_c0 += t0;
+                s_c1 += t1;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) ctrl->pool_count = r;
+    }
+    if (tid == 0) {
+        ctrl->passed = passed;
+        ctrl->pass_count = 0;
+        ctrl->cut_bound = ~0ull;
+    }
+}
+
+// Quadtree compaction: kept leaves to the code list (after code_base), the
+// four children of each split range to the next active list, in order.
+__global__ __launch_bounds__(kBlock) void k_quad_scatter(CompactArgs a, const Ctrl* ctrl,
+                                                         const int2* blk, const fic_code* tmp_codes,
+                                                         fic_code* codes, int capacity,
+                                                         const int32_t* act, int32_t* act_next,
+                                                         int half) {
+    const int base = blockIdx.x * kBlock * kQuadItems + threadIdx.x * kQuadItems;
+    int f0[kQuadItems], f1[kQuadItems];
     int c0 = 0, c1 = 0;
-    for (int u = 0; u < kItems; ++u) {
-        item_flags(a, ctrl, mode, base + u, f0[u], f1[u]);
+#pragma unroll
+    for (int u = 0; u < kQuadItems; ++u) {
+        item_flags(a, ctrl, 0, base + u, f0[u], f1[u]);
         c0 += f0[u];
         c1 += f1[u];
     }
     int e0, e1, t0, t1;
     block_scan2(c0, c1, e0, e1, t0, t1);
-    int2 off = blk[blockIdx.x];
+    const int2 off = blk[blockIdx.x];
     int r0 = off.x + e0, r1 = off.y + e1;
-    if (a.kind == 0) {
-        int take = mode == 1 ? ctrl->sel_rank : 0;
-        for (int u = 0; u < kItems; ++u) {
-            int keep = f0[u] || (f1[u] && r1 < take);
-            if (keep) pool_out[r0 + min(r1, take)] = base + u;
-            r0 += f0[u];
-            r1 += f1[u];
+    const int cb = ctrl->code_base;
+#pragma unroll
+    for (int u = 0; u < kQuadItems; ++u) {
+        const int i = base + u;
+        if (f0[u]) {
+            const int pos = cb + r0;
+            if (pos < capacity) codes[pos] = tmp_codes[i];
+            ++r0;
         }
-    } else {
-        int cb = ctrl->code_base;
-        for (int u = 0; u < kItems; ++u) {
-            int i = base + u;
-            if (f0[u]) {
-                int pos = cb + r0;
-                if (pos < capacity) codes[pos] = tmp_codes[i];
-            }
-            if (f1[u]) {
-                int yx = act[i];
-                int y = yx >> 16, x = yx & 0xffff;
-                int32_t* dst = act_next + 4 * r1;
-                dst[0] = (y << 16) | x;
-                dst[1] = (y << 16) | (x + half);
-                dst[2] = ((y + half) << 16) | x;
-                dst[3] = ((y + half) << 16) | (x + half);
-            }
-            r0 += f0[u];
-            r1 += f1[u];
+        if (f1[u]) {
+            const int yx = act[i];
+            const int y = yx >> 16, x = yx & 0xffff;
+            int32_t* dst = act_next + 4 * r1;
+            dst[0] = (y << 16) | x;
+            dst[1] = (y << 16) | (x + half);
+            dst[2] = ((y + half) << 16) | x;
+            dst[3] = ((y + half) << 16) | (x + half);
+            ++r1;
         }
     }
 }
 
-// ---------------------------------------------------------------- pool and range preparation
+// ---------------------------------------------------------------- pool preparation
 // Per pool entry p: the decimated domain d' (2x2 sums) as packed high and low
-// bytes, S = sum d', A' = n sum d'^2 - S^2 and the grid index j.
+// bytes, S = sum d', A' = n sum d'^2 - S^2 and the grid index j. TPD lanes
+// share a domain, 16 decimated values each. identity_total >= 0 means the
+// pool is the whole grid (no filter); block 0 then publishes its size.
+template <int B>
+struct PrepShape {
+    static constexpr int n = B * B;
+    static constexpr int PER = n < 16 ? n : 16;
+    static constexpr int TPD = n / PER;
+};
+
 template <int B>
 __global__ __launch_bounds__(kBlock) void k_pool_prep(const uint8_t* __restrict__ img, int pitch,
                                                       int L, int gx, const int32_t* __restrict__ pool,
-                                                      const Ctrl* ctrl, uint32_t* __restrict__ HL,
+                                                      int identity_total, Ctrl* ctrl,
+                                                      uint32_t* __restrict__ HL,
                                                       uint32_t* __restrict__ Sd,
                                                       int64_t* __restrict__ Ad,
                                                       int32_t* __restrict__ Jd) {
-    constexpr int n = B * B, NW = n / 4;
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= ctrl->pool_count) return;
-    int j = pool ? pool[p] : p;
-    int y = (j / gx) * L, x = (j % gx) * L;
+    using S = PrepShape<B>;
+    constexpr int n = B * B, NW = n / 4, PER = S::PER, TPD = S::TPD;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (identity_total >= 0 && g == 0) {
+        ctrl->pool_count = identity_total;
+        ctrl->passed = identity_total;
+    }
+    const int count = identity_total >= 0 ? identity_total : ctrl->pool_count;
+    const int p = g / TPD, sub = g % TPD;
+    const bool ok = p < count;
     uint32_t s = 0;
     uint64_t q = 0;
-    uint32_t* hl = HL + (int64_t)p * 2 * NW;
-    for (int w = 0; w < NW; ++w) {
-        uint32_t hw = 0, lw = 0;
-        for (int b = 0; b < 4; ++b) {
-            int m = 4 * w + b, i = m / B, c = m % B;
-            const uint8_t* px = img + (int64_t)(y + 2 * i) * pitch + x + 2 * c;
-            uint32_t d = (uint32_t)px[0] + px[1] + px[pitch] + px[pitch + 1];
-            s += d;
-            q += (uint64_t)d * d;
-            hw |= (d >> 8) << (8 * b);
-            lw |= (d & 255u) << (8 * b);
-        }
-        hl[w] = hw;
-        hl[NW + w] = lw;
-    }
-    Sd[p] = s;
-    Ad[p] = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
-    Jd[p] = j;
-}
-
-// Row q*8+t holds the range block R of active range q rearranged so that
-// <row, d'> = <R, T_t(d')>: row[m] = R[iso_src(inverse(t), m)].
-template <int B>
-__global__ __launch_bounds__(kBlock) void k_range_prep(const uint8_t* __restrict__ img, int pitch,
-                                                       const int32_t* __restrict__ act,
-                                                       const int32_t* act_count,
-                                                       uint32_t* __restrict__ Arow,
-                                                       int32_t* __restrict__ SR,
-                                                       int64_t* __restrict__ CR) {
-    constexpr int n = B * B, NW = n / 4;
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= 8 * *act_count) return;
-    int q = row >> 3, t = row & 7;
-    int yx = act[q];
-    uint32_t* dst = Arow + (int64_t)row * NW;
-    if (yx < 0) {
-        for (int w = 0; w < NW; ++w) dst[w] = 0u;
-        if (t == 0) {
-            SR[q] = 0;
-            CR[q] = 0;
-        }
-        return;
-    }
-    int y = yx >> 16, x = yx & 0xffff;
-    int u = iso_inverse(t);
-    for (int w = 0; w < NW; ++w) {
-        uint32_t v = 0;
-        for (int b = 0; b < 4; ++b) {
-            int src = iso_src(B, u, (4 * w + b) / B, (4 * w + b) % B);
-            v |= (uint32_t)img[(int64_t)(y + src / B) * pitch + x + src % B] << (8 * b);
-        }
-        dst[w] = v;
-    }
-    if (t == 0) {
-        int s = 0;
-        int64_t s2 = 0;
-        for (int i = 0; i < B; ++i)
-            for (int c = 0; c < B; ++c) {
-                int v = img[(int64_t)(y + i) * pitch + x + c];
-                s += v;
-                s2 += v * v;
+    int j = 0;
+    if (ok) {
+        j = identity_total >= 0 ? p : pool[p];
+        const int y = (j / gx) * L, x = (j % gx) * L;
+        uint32_t* hl = HL + (int64_t)p * 2 * NW;
+#pragma unroll
+        for (int w = 0; w < PER / 4; ++w) {
+            uint32_t hw = 0, lw = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int m = sub * PER + 4 * w + b, i = m / B, c = m % B;
+                const uint8_t* px = img + (int64_t)(y + 2 * i) * pitch + x + 2 * c;
+                const uint32_t d = (uint32_t)px[0] + px[1] + px[pitch] + px[pitch + 1];
+                s += d;
+                q += (uint64_t)d * d;
+                hw |= (d >> 8) << (8 * b);
+                lw |= (d & 255u) << (8 * b);
             }
-        SR[q] = s;
-        CR[q] = (int64_t)n * s2 - (int64_t)s * s;
+            hl[sub * (PER / 4) + w] = hw;
+            hl[NW + sub * (PER / 4) + w] = lw;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < TPD; m <<= 1) {
+        s += __shfl_xor(s, m, 64);
+        q += __shfl_xor(q, m, 64);
+    }
+    if (ok && sub == 0) {
+        Sd[p] = s;
+        Ad[p] = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
+        Jd[p] = j;
     }
 }
 
 // ---------------------------------------------------------------- the matcher
+// Candidate key: (domain << 27) | (iso << 24) | (contrast index << 20) | sum d'.
+// Ordering keys orders (domain, iso, contrast index); the low 20 bits carry the
+// domain sum (< 2^18), a function of the domain, for the offset of eq. (3).
+__device__ inline int64_t make_key(int64_t j, int t, int s, uint32_t S) {
+    return (j << 27) | ((int64_t)t << 24) | ((int64_t)s << 20) | (int64_t)S;
+}
+
+__device__ inline bool pair_less(int64_t fa, int64_t ka, int64_t fb, int64_t kb) {
+    return fa < fb || (fa == fb && ka < kb);
+}
+
 // Best contrast for one (row, domain) element. F = k^2 A' - 8Q k B' is
 // 16 Q^2 n E(k) minus the row constant 16 Q^2 C. For a consecutive set
 // k0..k1 the minimiser is the smallest k with (2k+1) A' >= 8Q B' (F is a
@@ -468,61 +631,138 @@ __device__ inline void best_contrast(int64_t Bp, int64_t Ap, const KSet& ks, int
     }
 }
 
-__device__ inline bool pair_less(int64_t fa, int64_t ka, int64_t fb, int64_t kb) {
-    return fa < fb || (fa == fb && ka < kb);
-}
-
 template <int B>
 struct MatchTile {
     static constexpr int n = B * B;
     static constexpr int NW = n / 4;
-    // domains per LDS tile: about 24-36 KiB of LDS
+    // domains per LDS tile: 8-34 KiB of LDS
     static constexpr int TN = B == 16 ? 64 : (B == 8 ? 128 : 256);
+    // target domains per pool chunk (one workgroup's share of the pool)
+    static constexpr int CG = B == 16 ? 16 : (B == 8 ? 32 : (B == 4 ? 128 : 256));
+    // exact integer widths (bounds by Cauchy-Schwarz: |B'| <= sqrt(A' C))
+    using BpT = typename std::conditional<(B <= 8), int32_t, int64_t>::type;   // B'
+    using GT = typename std::conditional<(B <= 4), int32_t, int64_t>::type;    // k A' - 80 B'
 };
 
+// Contrast-set modes of the matcher.
+enum { kModeSmall = 0, kModeGrid = 1, kModeList = 2 };
+constexpr int kSmallMax = 2;
+
+// Number of pool chunks actually used: about one LDS tile each, at most the
+// chunks the grid was launched with.
+__device__ inline int active_chunks(int P, int TN, int n_chunks) {
+    return max(1, min(n_chunks, (P + TN - 1) / TN));
+}
+
 // grid: x = row blocks of 256 rows (32 ranges x 8 isometries), y = pool chunks.
-template <int B>
-__global__ __launch_bounds__(kBlock) void k_match(const uint32_t* __restrict__ Arow,
-                                                  const int32_t* __restrict__ SR,
+// The workgroup stages its 32 range blocks in LDS; thread (range q, iso t)
+// keeps row[m] = R[iso_src(inverse(t), m)] in registers as packed bytes, so
+// that <row, d'> = <R, T_t(d')>.
+//  kModeSmall: at most kSmallMax contrast values. For each value k > 0 the
+//    thread keeps the smallest G = k A' - 80 B' (F = k G), in 32-bit integers
+//    for B <= 4; k = 0 gives F = 0 everywhere, so its best is the first domain.
+//  kModeGrid: consecutive k0..k1, closed-form minimiser, exact in int64.
+//  kModeList: any set, every value evaluated in int64.
+template <int B, int MODE>
+__global__ __launch_bounds__(kBlock) void k_match(const uint8_t* __restrict__ img, int pitch,
+                                                  const int32_t* __restrict__ act,
                                                   const int32_t* act_count,
                                                   const uint32_t* __restrict__ HL,
                                                   const uint32_t* __restrict__ Sd,
                                                   const int64_t* __restrict__ Ad,
                                                   const int32_t* __restrict__ Jd, const Ctrl* ctrl,
-                                                  KSet ks, int n_chunks, Partial* __restrict__ part) {
-    using T = MatchTile<B>;
-    constexpr int n = T::n, NW = T::NW, TN = T::TN;
+                                                  KSet ks, int n_chunks, Partial* __restrict__ part,
+                                                  int32_t* __restrict__ SRout,
+                                                  int64_t* __restrict__ CRout) {
+    using Tl = MatchTile<B>;
+    using BpT = typename Tl::BpT;
+    using GT = typename Tl::GT;
+    constexpr int n = Tl::n, NW = Tl::NW, TN = Tl::TN, RPB = kBlock / 8;
+    constexpr int NKA = MODE == kModeSmall ? kSmallMax : 1;
     __shared__ uint32_t sHL[TN * 2 * NW];
     __shared__ uint32_t sS[TN];
-    __shared__ int64_t sA[TN];
-    __shared__ int32_t sJ[TN];
+    __shared__ int64_t sA[MODE == kModeSmall ? 1 : TN];
+    __shared__ GT sKA[NKA][TN];
+    __shared__ uint8_t sR[RPB * n];
 
-    const int nrows = 8 * *act_count;
-    const int row0 = blockIdx.x * kBlock;
-    if (row0 >= nrows) return;
-    const int row = row0 + threadIdx.x;
-    const bool valid = row < nrows;
-    const int t = row & 7;
-
-    uint32_t r[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) r[w] = valid ? Arow[(int64_t)row * NW + w] : 0u;
-    const int64_t sr = valid ? SR[row >> 3] : 0;
-
+    const int nact = *act_count;
+    const int q0 = blockIdx.x * RPB;
+    if (q0 >= nact) return;
     const int P = ctrl->pool_count;
     const int c = blockIdx.y;
-    const int lo = (int)((int64_t)P * c / n_chunks);
-    const int hi = (int)((int64_t)P * (c + 1) / n_chunks);
+    if (c >= active_chunks(P, Tl::CG, n_chunks)) return;
+    const int nca = active_chunks(P, Tl::CG, n_chunks);
 
-    int64_t bestF = INT64_MAX, bestK = INT64_MAX;
+    for (int e = threadIdx.x; e < RPB * n; e += kBlock) {
+        const int lq = e / n, m = e % n, q = q0 + lq;
+        uint8_t v = 0;
+        if (q < nact) {
+            const int yx = act[q];
+            if (yx >= 0) v = img[(int64_t)((yx >> 16) + m / B) * pitch + (yx & 0xffff) + m % B];
+        }
+        sR[e] = v;
+    }
+    __syncthreads();
+    const int lq = threadIdx.x >> 3, t = threadIdx.x & 7, q = q0 + lq;
+    const bool valid = q < nact;
+    const uint8_t* rr = sR + lq * n;
+    uint32_t r[NW];
+    {
+        // T_u is affine in (i, c): source index = a0 + a1 i + a2 c
+        const int u = iso_inverse(t);
+        const int a0 = iso_src(B, u, 0, 0);
+        const int a1 = iso_src(B, u, 1, 0) - a0, a2 = iso_src(B, u, 0, 1) - a0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int m = 4 * w + b;
+                v |= (uint32_t)rr[a0 + a1 * (m / B) + a2 * (m % B)] << (8 * b);
+            }
+            r[w] = v;
+        }
+    }
+    // sum r and sum r^2 (the same for every isometry)
+    uint32_t srum = 0, sq = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        srum = __builtin_amdgcn_udot4(r[w], 0x01010101u, srum, false);
+        sq = __builtin_amdgcn_udot4(r[w], r[w], sq, false);
+    }
+    if (valid && t == 0 && c == 0) {
+        SRout[q] = (int32_t)srum;
+        CRout[q] = (int64_t)n * sq - (int64_t)srum * srum;
+    }
+    const BpT sr = (BpT)srum;
+    const int lo = (int)((int64_t)P * c / nca);
+    const int hi = (int)((int64_t)P * (c + 1) / nca);
+
+    // kModeSmall state
+    GT bestG[kSmallMax];
+    int bestPs[kSmallMax];
+#pragma unroll
+    for (int u = 0; u < kSmallMax; ++u) {
+        bestG[u] = std::numeric_limits<GT>::max();
+        bestPs[u] = lo;  // k = 0: every domain ties, the first one wins
+    }
+    // other modes
+    int64_t bestF = INT64_MAX;
+    int bestP = -1, bestS = 0;
+
     for (int base = lo; base < hi; base += TN) {
         const int cnt = min(TN, hi - base);
         __syncthreads();
         for (int i = threadIdx.x; i < cnt * 2 * NW; i += kBlock) sHL[i] = HL[(int64_t)base * 2 * NW + i];
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
             sS[i] = Sd[base + i];
-            sA[i] = Ad[base + i];
-            sJ[i] = Jd[base + i];
+            const int64_t a = Ad[base + i];
+            if (MODE == kModeSmall) {
+#pragma unroll
+                for (int u = 0; u < kSmallMax; ++u) sKA[u][i] = (GT)(u < ks.n ? ks.k[u] : 0) * (GT)a;
+            } else {
+                sA[i] = a;
+            }
         }
         __syncthreads();
         for (int d = 0; d < cnt; ++d) {
@@ -533,41 +773,85 @@ __global__ __launch_bounds__(kBlock) void k_match(const uint32_t* __restrict__ A
                 ph = __builtin_amdgcn_udot4(r[w], hl[w], ph, false);
                 pl = __builtin_amdgcn_udot4(r[w], hl[NW + w], pl, false);
             }
-            const int64_t Pv = ((int64_t)ph << 8) + pl;
-            const int64_t Bp = Pv * n - sr * (int64_t)sS[d];
-            int64_t F;
-            int s;
-            best_contrast(Bp, sA[d], ks, F, s);
-            if (F < bestF) {
-                bestF = F;
-                bestK = ((int64_t)sJ[d] << 8) | (t << 4) | s;
+            const BpT Pv = (BpT)((ph << 8) + pl);
+            const BpT Bp = Pv * (BpT)n - sr * (BpT)sS[d];
+            if (MODE == kModeSmall) {
+                const GT b80 = (GT)80 * (GT)Bp;
+#pragma unroll
+                for (int u = 0; u < kSmallMax; ++u) {
+                    if (u < ks.n && ks.k[u] != 0) {
+                        const GT g = sKA[u][d] - b80;
+                        if (g < bestG[u]) {
+                            bestG[u] = g;
+                            bestPs[u] = base + d;
+                        }
+                    }
+                }
+            } else {
+                int64_t F;
+                int sidx;
+                if (MODE == kModeGrid) {
+                    KSet kg = ks;
+                    kg.consecutive = 1;
+                    best_contrast((int64_t)Bp, sA[d], kg, F, sidx);
+                } else {
+                    KSet kl = ks;
+                    kl.consecutive = 0;
+                    best_contrast((int64_t)Bp, sA[d], kl, F, sidx);
+                }
+                if (F < bestF) {
+                    bestF = F;
+                    bestP = base + d;
+                    bestS = sidx;
+                }
             }
+        }
+    }
+    int64_t outF = INT64_MAX, outK = INT64_MAX;
+    if (lo < hi) {
+        if (MODE == kModeSmall) {
+#pragma unroll
+            for (int u = 0; u < kSmallMax; ++u) {
+                if (u >= ks.n) continue;
+                const int k = ks.k[u];
+                if (k != 0 && bestG[u] == std::numeric_limits<GT>::max()) continue;
+                const int64_t F = k == 0 ? 0 : (int64_t)k * (int64_t)bestG[u];
+                const int p = bestPs[u];
+                const int64_t K = make_key(Jd[p], t, u, Sd[p]);
+                if (pair_less(F, K, outF, outK)) {
+                    outF = F;
+                    outK = K;
+                }
+            }
+        } else if (bestP >= 0) {
+            outF = bestF;
+            outK = make_key(Jd[bestP], t, bestS, Sd[bestP]);
         }
     }
     // reduce the 8 isometry rows of each range (8 consecutive lanes)
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1) {
-        int64_t of = __shfl_xor(bestF, m, 64);
-        int64_t ok = __shfl_xor(bestK, m, 64);
-        if (pair_less(of, ok, bestF, bestK)) {
-            bestF = of;
-            bestK = ok;
+        const int64_t of = __shfl_xor(outF, m, 64);
+        const int64_t ok = __shfl_xor(outK, m, 64);
+        if (pair_less(of, ok, outF, outK)) {
+            outF = of;
+            outK = ok;
         }
     }
     if (valid && t == 0) {
         Partial pr;
-        pr.F = bestF;
-        pr.key = bestK;
-        part[(int64_t)(row >> 3) * n_chunks + c] = pr;
+        pr.F = outF;
+        pr.key = outK;
+        part[(int64_t)q * n_chunks + c] = pr;
     }
 }
 
 // ---------------------------------------------------------------- per-range result
-__device__ inline bool finish_range(const uint8_t* img, int pitch, int yx, int B, int L, int gx,
-                                    const Partial* pr, int n_chunks, int64_t CRq, int32_t SRq,
-                                    const KSet& ks, fic_match& m, int& dy, int& dx) {
+__device__ inline bool finish_range(int yx, int B, int L, int gx, const Partial* pr, int nca,
+                                    int64_t CRq, int32_t SRq, const KSet& ks, fic_match& m,
+                                    int& dy, int& dx) {
     int64_t F = INT64_MAX, K = INT64_MAX;
-    for (int c = 0; c < n_chunks; ++c)
+    for (int c = 0; c < nca; ++c)
         if (pair_less(pr[c].F, pr[c].key, F, K)) {
             F = pr[c].F;
             K = pr[c].key;
@@ -586,15 +870,11 @@ __device__ inline bool finish_range(const uint8_t* img, int pitch, int yx, int B
         return false;
     }
     const int n = B * B;
-    const int j = (int)(K >> 8), t = (int)((K >> 4) & 15), s = (int)(K & 15);
+    const int j = (int)(K >> 27), t = (int)((K >> 24) & 7), s = (int)((K >> 20) & 15);
+    const int64_t sd = K & 0xfffff;
     const int k = ks.consecutive ? ks.k0 + s : ks.k[s];
     dy = (j / gx) * L;
     dx = (j % gx) * L;
-    int64_t sd = 0;
-    for (int i = 0; i < 2 * B; ++i) {
-        const uint8_t* row = img + (int64_t)(dy + i) * pitch + dx;
-        for (int u = 0; u < 2 * B; ++u) sd += row[u];
-    }
     m.e_num = F + 1600 * CRq;
     m.dom = j;
     m.iso = (uint8_t)t;
@@ -606,56 +886,88 @@ __device__ inline bool finish_range(const uint8_t* img, int pitch, int yx, int B
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_level(const uint8_t* __restrict__ img, int pitch,
-                                                         int B, int L, int gx,
+__global__ __launch_bounds__(kBlock) void k_reduce_level(int B, int L, int gx,
                                                          const int32_t* __restrict__ act,
                                                          const int32_t* act_count,
                                                          const Partial* __restrict__ part,
-                                                         int n_chunks, const int64_t* __restrict__ CR,
+                                                         int n_chunks, int CG, const Ctrl* ctrl,
+                                                         const int64_t* __restrict__ CR,
                                                          const int32_t* __restrict__ SR, KSet ks,
                                                          fic_match* __restrict__ out) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= *act_count) return;
     fic_match m;
     int dy, dx;
-    finish_range(img, pitch, act[q], B, L, gx, part + (int64_t)q * n_chunks, n_chunks, CR[q], SR[q],
-                 ks, m, dy, dx);
+    const int nca = active_chunks(ctrl->pool_count, CG, n_chunks);
+    finish_range(act[q], B, L, gx, part + (int64_t)q * n_chunks, nca, CR[q], SR[q], ks, m, dy, dx);
     out[q] = m;
 }
 
-// Quadtree step: the leaf record and the keep/split decision of each active range.
+// Quadtree step: the leaf record and the keep/split decision of each active
+// range, kQuadItems consecutive ranges per thread. Per-workgroup counts of
+// kept and split ranges go to blk; the last workgroup scans them, advances the
+// code counter and sets the next level's active count (4 children per split).
 __global__ __launch_bounds__(kBlock) void k_reduce_quad(
-    const uint8_t* __restrict__ img, int pitch, int B, int L, int gx, int lv, int last,
-    int64_t thr, const int32_t* __restrict__ act, const int32_t* act_count,
-    const Partial* __restrict__ part, int n_chunks, const int64_t* __restrict__ CR,
-    const int32_t* __restrict__ SR, KSet ks, fic_code* __restrict__ tmp, uint8_t* __restrict__ dec) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= *act_count) return;
-    fic_match m;
-    int dy, dx;
-    const int yx = act[q];
-    bool ok = finish_range(img, pitch, yx, B, L, gx, part + (int64_t)q * n_chunks, n_chunks, CR[q],
-                           SR[q], ks, m, dy, dx);
-    if (!ok) {
-        dec[q] = 2;
-        return;
+    int B, int L, int gx, int lv, int last, int64_t thr, const int32_t* __restrict__ act,
+    Ctrl* ctrl, const Partial* __restrict__ part, int n_chunks, int CG,
+    const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, KSet ks,
+    fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk, fic_level_stats* stats) {
+    const int base = blockIdx.x * kBlock * kQuadItems + threadIdx.x * kQuadItems;
+    const int nact = ctrl->act_count[lv];
+    const int nca = active_chunks(ctrl->pool_count, CG, n_chunks);
+    int kept = 0, split = 0;
+    for (int u = 0; u < kQuadItems; ++u) {
+        const int q = base + u;
+        if (q >= nact) break;
+        fic_match m;
+        int dy, dx;
+        const int yx = act[q];
+        const bool ok = finish_range(yx, B, L, gx, part + (int64_t)q * n_chunks, nca, CR[q], SR[q],
+                                     ks, m, dy, dx);
+        uint8_t d = 2;
+        if (ok) {
+            fic_code c;
+            c.e_num = m.e_num;
+            c.dom = m.dom;
+            c.y = (int16_t)(yx >> 16);
+            c.x = (int16_t)(yx & 0xffff);
+            c.dy = (int16_t)dy;
+            c.dx = (int16_t)dx;
+            c.q_o = m.q_o;
+            c.log2B = (uint8_t)(31 - __clz(B));
+            c.iso = m.iso;
+            c.k = m.k;
+            c.s_idx = m.s_idx;
+            c.level = (uint8_t)lv;
+            for (int i = 0; i < 5; ++i) c.pad_[i] = 0;
+            tmp[q] = c;
+            d = (last || m.e_num <= thr) ? 1 : 0;
+        }
+        dec[q] = d;
+        kept += d == 1;
+        split += d == 0;
     }
-    fic_code c;
-    c.e_num = m.e_num;
-    c.dom = m.dom;
-    c.y = (int16_t)(yx >> 16);
-    c.x = (int16_t)(yx & 0xffff);
-    c.dy = (int16_t)dy;
-    c.dx = (int16_t)dx;
-    c.q_o = m.q_o;
-    c.log2B = (uint8_t)(31 - __clz(B));
-    c.iso = m.iso;
-    c.k = m.k;
-    c.s_idx = m.s_idx;
-    c.level = (uint8_t)lv;
-    for (int i = 0; i < 5; ++i) c.pad_[i] = 0;
-    tmp[q] = c;
-    dec[q] = (last || m.e_num <= thr) ? 1 : 0;
+    int e0, e1, t0, t1;
+    block_scan2(kept, split, e0, e1, t0, t1);
+    publish_count(blk, t0, t1);
+    if (!last_workgroup(&ctrl->ticket)) return;
+    int tot0, tot1;
+    scan_block_counts(blk, gridDim.x, tot0, tot1);
+    if (threadIdx.x == 0) {
+        const int pool = ctrl->pool_count;
+        ctrl->code_base = ctrl->n_codes;
+        ctrl->n_codes += tot0;
+        ctrl->act_count[lv + 1] = 4 * tot1;
+        if (stats) {
+            fic_level_stats st;
+            st.matches = (int64_t)nact * pool * 8;
+            st.pool = pool;
+            st.passed = ctrl->passed;
+            st.active = nact;
+            st.accepted = tot0;
+            stats[lv] = st;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- decoder
@@ -758,12 +1070,13 @@ __global__ void k_calib_accum(const uint8_t* __restrict__ img, int pitch,
 }
 
 // ---------------------------------------------------------------- launch helpers
-int match_tile_domains(int B) {
+// Domains per pool chunk of the matcher (see active_chunks).
+int match_chunk_domains(int B) {
     switch (B) {
-        case 2: return MatchTile<2>::TN;
-        case 4: return MatchTile<4>::TN;
-        case 8: return MatchTile<8>::TN;
-        default: return MatchTile<16>::TN;
+        case 2: return MatchTile<2>::CG;
+        case 4: return MatchTile<4>::CG;
+        case 8: return MatchTile<8>::CG;
+        default: return MatchTile<16>::CG;
     }
 }
 

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -66,10 +67,13 @@ struct Workspace {
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
-std::vector<int64_t> entropy_table() {
-    std::vector<int64_t> t(kMaxWindow + 1, 0);
-    for (int c = 2; c <= kMaxWindow; ++c)
-        t[c] = llround((double)c * std::log2((double)c) * std::ldexp(1.0, kEntFrac));
+const std::vector<int64_t>& entropy_table() {
+    static const std::vector<int64_t> t = [] {
+        std::vector<int64_t> v(kMaxWindow + 1, 0);
+        for (int c = 2; c <= kMaxWindow; ++c)
+            v[c] = llround((double)c * std::log2((double)c) * std::ldexp(1.0, kEntFrac));
+        return v;
+    }();
     return t;
 }
 
@@ -101,9 +105,14 @@ int get_ws(hipStream_t s, Workspace** out) {
         delete ws;
         return fail(FIC_ENOMEM, "hipMalloc of the entropy table failed");
     }
-    std::vector<int64_t> t = entropy_table();
+    const std::vector<int64_t>& t = entropy_table();
     HIP_TRY(hipMemcpyAsync(ws->T, t.data(), sizeof(int64_t) * t.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ws->ctrl, 0, sizeof(Ctrl), s));
+    {
+        static Ctrl init;  // zero counters, empty histogram, no floor bound yet
+        std::memset(&init, 0, sizeof init);
+        init.cut_bound = ~0ull;
+        HIP_TRY(hipMemcpyAsync(ws->ctrl, &init, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     g_ws[{dev, s}] = ws;
     *out = ws;
@@ -132,6 +141,62 @@ int ensure(Workspace& ws, Buf& b, size_t bytes) {
 template <typename T>
 T* P(Buf& b) {
     return reinterpret_cast<T*>(b.p);
+}
+
+// ---------------------------------------------------------------- profiling
+// While on, each launch of a library kernel is bracketed by two HIP events on
+// its stream; fic_profile_end sums the intervals per kernel label.
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> spare;
+} g_prof;
+
+hipEvent_t prof_event() {
+    if (!g_prof.spare.empty()) {
+        hipEvent_t e = g_prof.spare.back();
+        g_prof.spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+class ProfScope {
+  public:
+    ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!g_prof.on) return;
+        a_ = prof_event();
+        b_ = prof_event();
+        if (a_ && b_) (void)hipEventRecord(a_, s_);
+    }
+    ~ProfScope() {
+        if (!a_ || !b_) return;
+        (void)hipEventRecord(b_, s_);
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        g_prof.recs.push_back({name_, a_, b_});
+    }
+
+  private:
+    const char* name_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+const char* match_label(int B) {
+    switch (B) {
+        case 2: return "match_b2";
+        case 4: return "match_b4";
+        case 8: return "match_b8";
+        default: return "match_b16";
+    }
 }
 
 // ---------------------------------------------------------------- validation
@@ -193,7 +258,7 @@ void grow(Sizes& s, const Level& v) {
     s.arow = std::max(s.arow, (size_t)v.max_act * 8 * n);
     s.rng = std::max(s.rng, (size_t)v.max_act);
     s.part = std::max(s.part, (size_t)v.max_act * v.nc * sizeof(Partial));
-    size_t nblk = (size_t)std::max(cdiv(v.total, kBlock * kItems), cdiv(v.max_act, kBlock * kItems));
+    size_t nblk = (size_t)std::max(cdiv(v.total, kBlock * kPoolItems), cdiv(v.max_act, kBlock * kQuadItems));
     s.blk = std::max(s.blk, nblk * sizeof(int2));
     s.act = std::max(s.act, (size_t)v.max_act);
 }
@@ -223,46 +288,100 @@ void launch_level_kernels(Workspace& ws, const Level& v, const uint8_t* img, int
                           bool filtered, const int32_t* act) {
     hipStream_t st = ws.stream;
     const int32_t* act_count = ws.ctrl->act_count + v.lv;
-    k_pool_prep<B><<<cdiv(v.total, kBlock), kBlock, 0, st>>>(
-        img, pitch, v.L, v.gx, filtered ? P<int32_t>(ws.pool) : nullptr, ws.ctrl, P<uint32_t>(ws.hl),
-        P<uint32_t>(ws.sd), P<int64_t>(ws.ad), P<int32_t>(ws.jd));
-    k_range_prep<B><<<cdiv((int64_t)8 * v.max_act, kBlock), kBlock, 0, st>>>(
-        img, pitch, act, act_count, P<uint32_t>(ws.arow), P<int32_t>(ws.sr), P<int64_t>(ws.cr));
-    dim3 grid(cdiv((int64_t)8 * v.max_act, kBlock), v.nc);
-    k_match<B><<<grid, kBlock, 0, st>>>(P<uint32_t>(ws.arow), P<int32_t>(ws.sr), act_count,
-                                        P<uint32_t>(ws.hl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad),
-                                        P<int32_t>(ws.jd), ws.ctrl, v.ks, v.nc, P<Partial>(ws.part));
+    {
+        ProfScope ps("pool_prep", st);
+        k_pool_prep<B><<<cdiv((int64_t)v.total * PrepShape<B>::TPD, kBlock), kBlock, 0, st>>>(
+            img, pitch, v.L, v.gx, P<int32_t>(ws.pool), filtered ? -1 : v.total, ws.ctrl,
+            P<uint32_t>(ws.hl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad), P<int32_t>(ws.jd));
+    }
+    ProfScope ps(match_label(B), st);
+    dim3 grid(cdiv(v.max_act, kBlock / 8), v.nc);
+    const int mode = v.ks.n <= kSmallMax ? kModeSmall : (v.ks.consecutive ? kModeGrid : kModeList);
+#define FIC_MATCH_ARGS                                                                          \
+    img, pitch, act, act_count, P<uint32_t>(ws.hl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad),      \
+        P<int32_t>(ws.jd), ws.ctrl, v.ks, v.nc, P<Partial>(ws.part), P<int32_t>(ws.sr),          \
+        P<int64_t>(ws.cr)
+    if (mode == kModeSmall)
+        k_match<B, kModeSmall><<<grid, kBlock, 0, st>>>(FIC_MATCH_ARGS);
+    else if (mode == kModeGrid)
+        k_match<B, kModeGrid><<<grid, kBlock, 0, st>>>(FIC_MATCH_ARGS);
+    else
+        k_match<B, kModeList><<<grid, kBlock, 0, st>>>(FIC_MATCH_ARGS);
+#undef FIC_MATCH_ARGS
+}
+
+// Radix-select digits (shift, width) covering the bits of keys below maxkey.
+std::vector<std::pair<int, int>> select_digits(int64_t maxkey) {
+    int bits = 1;
+    while (bits < 63 && ((int64_t)1 << bits) <= maxkey) ++bits;
+    std::vector<std::pair<int, int>> d;
+    for (int hi = bits; hi > 0; hi -= kSelBits) {
+        int w = std::min(kSelBits, hi);
+        d.push_back({hi - w, w});
+    }
+    return d;
 }
 
 // Pool of one level (entropy filter of Section 3, or the whole grid), then the
-// pool moments, range rows and the matcher. act_init >= 0 sets the level's
-// active count; -1 keeps the count a previous level wrote.
+// pool moments and the matcher. The level's active list and count must
+// already be on the device.
 int run_level(Workspace& ws, const Level& v, const uint8_t* img, int pitch, int entropy_mode,
-              float entropy_bits, int min_pool, int act_init, const int32_t* act) {
+              float entropy_bits, int min_pool, const int32_t* act) {
     hipStream_t st = ws.stream;
     const bool filtered = entropy_mode == 1;
-    k_level_init<<<1, kBlock, 0, st>>>(ws.ctrl, v.lv, act_init, filtered ? -1 : v.total,
-                                       std::min(min_pool, v.total));
     if (filtered) {
         const int side = 2 * v.B;
         const int64_t M = entropy_cut(side * side, (double)entropy_bits);
-        k_pool_score<<<cdiv(v.total, kBlock), kBlock, 0, st>>>(img, pitch, side, v.L, v.gx, v.total,
-                                                              ws.T, M, P<int64_t>(ws.key), ws.ctrl);
-        const int nsel = std::max(1, std::min(cdiv(v.total, kBlock * 16), 512));
-        for (int shift = 48 - kSelBits; shift >= 0; shift -= kSelBits)
-            k_select_pass<<<nsel, kBlock, 0, st>>>(P<int64_t>(ws.key), v.total, min_pool, shift,
-                                                   ws.ctrl);
-        CompactArgs a{};
-        a.kind = 0;
-        a.total = v.total;
-        a.min_pool = min_pool;
-        a.M = M;
-        a.key = P<int64_t>(ws.key);
-        const int nblk = cdiv(v.total, kBlock * kItems);
-        k_compact_count<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk));
-        k_compact_scan<<<1, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk), nblk, v.lv, nullptr, 0);
-        k_compact_scatter<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk), P<int32_t>(ws.pool),
-                                                   nullptr, nullptr, 0, nullptr, nullptr, 0);
+        {
+            ProfScope ps("pool_score", st);
+            switch (side) {
+                case 4:
+                    k_pool_score<4><<<cdiv((int64_t)v.total * ScoreShape<4>::TPD, kBlock), kBlock, 0, st>>>(
+                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
+                    break;
+                case 8:
+                    k_pool_score<8><<<cdiv((int64_t)v.total * ScoreShape<8>::TPD, kBlock), kBlock, 0, st>>>(
+                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
+                    break;
+                case 16:
+                    k_pool_score<16><<<cdiv((int64_t)v.total * ScoreShape<16>::TPD, kBlock), kBlock, 0, st>>>(
+                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
+                    break;
+                default:
+                    k_pool_score<32><<<cdiv((int64_t)v.total * ScoreShape<32>::TPD, kBlock), kBlock, 0, st>>>(
+                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
+                    break;
+            }
+        }
+        const int rank = std::min(min_pool, v.total);
+        {
+            // floor: an upper bound on the rank-th smallest key
+            ProfScope ps("pool_select", st);
+            const int64_t maxkey = entropy_table()[side * side] + 1;
+            int shift = 0;
+            while ((maxkey >> shift) >= kSelBins) ++shift;
+            const int chunk = std::max(8192, cdiv(v.total, 64));
+            k_floor_bound<<<cdiv(v.total, chunk), kBlock, 0, st>>>(P<int64_t>(ws.key), v.total,
+                                                                   min_pool, rank, shift, chunk,
+                                                                   ws.ctrl);
+        }
+        {
+            ProfScope ps("pool_compact", st);
+            CompactArgs a{};
+            a.kind = 0;
+            a.total = v.total;
+            a.min_pool = min_pool;
+            a.M = M;
+            a.key = P<int64_t>(ws.key);
+            const int nblk = cdiv(v.total, kBlock * kPoolItems);
+            k_pool_count<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk));
+            k_pool_scatter<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk), P<int32_t>(ws.pool));
+        }
+        {
+            ProfScope ps("pool_select", st);
+            k_floor_select<<<1, 1024, 0, st>>>(P<int64_t>(ws.key), v.total, min_pool, rank,
+                                               P<int32_t>(ws.pool), ws.ctrl);
+        }
     }
     switch (v.B) {
         case 2: launch_level_kernels<2>(ws, v, img, pitch, filtered, act); break;
@@ -319,15 +438,14 @@ int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch
     }
     int rc = ensure_sizes(ws, sz);
     if (rc) return rc;
-    k_ctrl_reset<<<1, 64, 0, st>>>(ws.ctrl);
     k_act_full<<<cdiv(lv[0].max_act, kBlock), kBlock, 0, st>>>(P<int32_t>(ws.act0), H / p->B0,
-                                                             W / p->B0, p->B0);
+                                                             W / p->B0, p->B0, ws.ctrl, 0, 1);
     Buf* cur = &ws.act0;
     Buf* nxt = &ws.act1;
     for (int l = 0; l < p->n_levels; ++l) {
         const Level& v = lv[l];
         rc = run_level(ws, v, img, pitch, p->entropy_mode, p->entropy_bits, p->min_pool,
-                       l == 0 ? v.max_act : -1, P<int32_t>(*cur));
+                       P<int32_t>(*cur));
         if (rc) return rc;
         const int n = v.B * v.B;
         const bool last = l == p->n_levels - 1;
@@ -335,21 +453,24 @@ int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch
         double thr_d = std::floor(1600.0 * (double)p->rms_thresh * (double)p->rms_thresh *
                                   (double)n * (double)n);
         int64_t thr = thr_d >= 9.0e18 ? INT64_MAX : (int64_t)thr_d;
-        const int32_t* act_count = ws.ctrl->act_count + l;
-        k_reduce_quad<<<cdiv(v.max_act, kBlock), kBlock, 0, st>>>(
-            img, pitch, v.B, v.L, v.gx, l, last ? 1 : 0, thr, P<int32_t>(*cur), act_count,
-            P<Partial>(ws.part), v.nc, P<int64_t>(ws.cr), P<int32_t>(ws.sr), v.ks,
-            P<fic_code>(ws.tmpc), P<uint8_t>(ws.dec));
-        CompactArgs a{};
-        a.kind = 1;
-        a.act_count = act_count;
-        a.decision = P<uint8_t>(ws.dec);
-        const int nblk = cdiv(v.max_act, kBlock * kItems);
-        k_compact_count<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk));
-        k_compact_scan<<<1, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk), nblk, l, stats, capacity);
-        k_compact_scatter<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk), nullptr,
-                                                   P<fic_code>(ws.tmpc), codes, capacity,
-                                                   P<int32_t>(*cur), P<int32_t>(*nxt), v.B / 2);
+        const int nblk = cdiv(v.max_act, kBlock * kQuadItems);
+        {
+            ProfScope ps("reduce_quad", st);
+            k_reduce_quad<<<nblk, kBlock, 0, st>>>(
+                v.B, v.L, v.gx, l, last ? 1 : 0, thr, P<int32_t>(*cur), ws.ctrl, P<Partial>(ws.part),
+                v.nc, match_chunk_domains(v.B), P<int64_t>(ws.cr), P<int32_t>(ws.sr), v.ks,
+                P<fic_code>(ws.tmpc), P<uint8_t>(ws.dec), P<int2>(ws.blk), stats);
+        }
+        {
+            ProfScope ps("quad_compact", st);
+            CompactArgs a{};
+            a.kind = 1;
+            a.act_count = ws.ctrl->act_count + l;
+            a.decision = P<uint8_t>(ws.dec);
+            k_quad_scatter<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk),
+                                                    P<fic_code>(ws.tmpc), codes, capacity,
+                                                    P<int32_t>(*cur), P<int32_t>(*nxt), v.B / 2);
+        }
         LAUNCH_CHECK();
         std::swap(cur, nxt);
     }
@@ -392,14 +513,18 @@ FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t p
     hipStream_t st = ws->stream;
     int32_t* act = P<int32_t>(ws->act0);
     if (range_yx)
-        k_act_from_yx<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(act, range_yx, n_ranges, H, W, B);
+        k_act_from_yx<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(act, range_yx, n_ranges, H, W, B,
+                                                                 ws->ctrl);
     else
-        k_act_full<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(act, H / B, W / B, B);
-    if ((rc = run_level(*ws, v, img, pitch, entropy_mode, entropy_bits, min_pool, n_ranges, act)))
+        k_act_full<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(act, H / B, W / B, B, ws->ctrl, 0, 0);
+    if ((rc = run_level(*ws, v, img, pitch, entropy_mode, entropy_bits, min_pool, act)))
         return rc;
+    {
+    ProfScope ps("reduce_level", st);
     k_reduce_level<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(
-        img, pitch, B, L, v.gx, act, ws->ctrl->act_count, P<Partial>(ws->part), v.nc,
-        P<int64_t>(ws->cr), P<int32_t>(ws->sr), ks, out);
+        B, L, v.gx, act, ws->ctrl->act_count, P<Partial>(ws->part), v.nc, match_chunk_domains(B),
+        ws->ctrl, P<int64_t>(ws->cr), P<int32_t>(ws->sr), ks, out);
+    }
     LAUNCH_CHECK();
     if (pool_count)
         HIP_TRY(hipMemcpyAsync(pool_count, &ws->ctrl->pool_count, sizeof(int32_t),
@@ -466,6 +591,7 @@ FIC_API int fic_decode(const fic_code* codes, int32_t n_codes, int32_t H, int32_
     for (int it = 0; it < iters; ++it) {
         const bool lastit = it == iters - 1;
         uint8_t* dst = lastit ? out : b;
+        ProfScope ps("decode_iter", st);
         k_decode_iter<<<cdiv(npx, kBlock), kBlock, 0, st>>>(codes, P<int32_t>(ws->map), a, W, dst,
                                                            lastit ? out_pitch : W, H, W);
         std::swap(a, b);
@@ -532,5 +658,64 @@ FIC_API int fic_calibrate_s(const uint8_t* img, int32_t H, int32_t W, int32_t pi
         unsigned long long tot = acc[2 * l], cnt = acc[2 * l + 1];
         k_out[l] = cnt ? (int8_t)((2 * tot + cnt) / (2 * cnt)) : (int8_t)-1;
     }
+    return FIC_OK;
+}
+
+FIC_API int fic_profile_begin(void) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& r : g_prof.recs) {
+        g_prof.spare.push_back(r.a);
+        g_prof.spare.push_back(r.b);
+    }
+    g_prof.recs.clear();
+    g_prof.on = true;
+    return FIC_OK;
+}
+
+FIC_API int fic_profile_end(fic_kernel_time* out, int32_t max, int32_t* n_out) {
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        g_prof.on = false;
+        recs.swap(g_prof.recs);
+    }
+    std::vector<fic_kernel_time> agg;
+    int rc = FIC_OK;
+    for (auto& r : recs) {
+        if (rc == FIC_OK) {
+            hipError_t e = hipEventSynchronize(r.b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+            if (e != hipSuccess) {
+                rc = fail(FIC_EDEVICE, "profiling event: %s", hipGetErrorString(e));
+            } else {
+                fic_kernel_time* t = nullptr;
+                for (auto& x : agg)
+                    if (std::strncmp(x.name, r.name, sizeof x.name) == 0) t = &x;
+                if (!t) {
+                    fic_kernel_time z;
+                    std::memset(&z, 0, sizeof z);
+                    std::strncpy(z.name, r.name, sizeof z.name - 1);
+                    agg.push_back(z);
+                    t = &agg.back();
+                }
+                t->launches += 1;
+                t->total_ms += ms;
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        for (auto& r : recs) {
+            g_prof.spare.push_back(r.a);
+            g_prof.spare.push_back(r.b);
+        }
+    }
+    if (rc) return rc;
+    std::sort(agg.begin(), agg.end(),
+              [](const fic_kernel_time& x, const fic_kernel_time& y) { return x.total_ms > y.total_ms; });
+    if (n_out) *n_out = (int32_t)agg.size();
+    if (out)
+        for (int i = 0; i < (int)agg.size() && i < max; ++i) out[i] = agg[i];
     return FIC_OK;
 }

@@ -30,7 +30,10 @@ CODE_DTYPE = np.dtype([("e_num", "<i8"), ("dom", "<i4"), ("y", "<i2"), ("x", "<i
                        ("pad_", "u1", (5,))])
 STATS_DTYPE = np.dtype([("matches", "<i8"), ("pool", "<i4"), ("passed", "<i4"),
                         ("active", "<i4"), ("accepted", "<i4")])
+KTIME_DTYPE = np.dtype([("name", "S24"), ("launches", "<i4"), ("pad_", "<i4"),
+                        ("total_ms", "<f8")])
 assert MATCH_DTYPE.itemsize == 24 and CODE_DTYPE.itemsize == 32 and STATS_DTYPE.itemsize == 24
+assert KTIME_DTYPE.itemsize == 40
 
 
 class FicError(RuntimeError):
@@ -95,9 +98,10 @@ def load():
     lib.fic_decode.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp]
     lib.fic_sse.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
     lib.fic_calibrate_s.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, vp]
+    lib.fic_profile_end.argtypes = [vp, i32, vp]
     lib.fic_last_error.restype = ctypes.c_char_p
     for name in ("fic_encode_level", "fic_encode_image", "fic_decode", "fic_sse",
-                 "fic_calibrate_s", "fic_version"):
+                 "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -161,17 +165,22 @@ def code_capacity(H: int, W: int, levels=LEVELS) -> int:
 
 
 def encode_image(img, params: EncoderParams | None = None, capacity: int | None = None,
-                 stream=None):
+                 stream=None, out=None):
     """fic_encode_image. Returns (codes uint8 [capacity, 32], n_codes int32 [1],
-    stats uint8 [n_levels, 24]) as device tensors."""
+    stats uint8 [n_levels, 24]) as device tensors. ``out`` may pass that triple
+    back in to reuse its buffers."""
     import torch
     img = _dev_u8_image(img)
     params = params or EncoderParams()
     H, W = img.shape
-    cap = code_capacity(H, W, params.levels) if capacity is None else capacity
-    codes = torch.empty((max(cap, 1), 32), dtype=torch.uint8, device=img.device)
-    ncodes = torch.zeros(1, dtype=torch.int32, device=img.device)
-    stats = torch.zeros((len(params.levels), 24), dtype=torch.uint8, device=img.device)
+    if out is not None:
+        codes, ncodes, stats = out
+        cap = codes.shape[0]
+    else:
+        cap = code_capacity(H, W, params.levels) if capacity is None else capacity
+        codes = torch.empty((max(cap, 1), 32), dtype=torch.uint8, device=img.device)
+        ncodes = torch.zeros(1, dtype=torch.int32, device=img.device)
+        stats = torch.zeros((len(params.levels), 24), dtype=torch.uint8, device=img.device)
     p = params.to_c()
     rc = load().fic_encode_image(img.data_ptr(), H, W, img.stride(0), ctypes.byref(p),
                                  codes.data_ptr(), cap, ncodes.data_ptr(), stats.data_ptr(),
@@ -225,6 +234,20 @@ def calibrate_s(img, params: EncoderParams | None = None, stream=None):
 def calibrated_sets(ks, fallback=PAPER_K):
     """Per-level 1-element contrast sets from calibrate_s output (fallback where -1)."""
     return tuple((k,) if k >= 0 else tuple(fallback[l]) for l, k in enumerate(ks))
+
+
+def profile_begin():
+    """Start bracketing every library kernel launch with HIP events."""
+    _check(load().fic_profile_begin())
+
+
+def profile_end(max_labels: int = 64) -> dict:
+    """Stop profiling; returns {label: (launches, total_ms)} from the HIP events."""
+    buf = np.zeros(max_labels, dtype=KTIME_DTYPE)
+    n = ctypes.c_int32(0)
+    _check(load().fic_profile_end(buf.ctypes.data, max_labels, ctypes.byref(n)))
+    return {r["name"].decode(): (int(r["launches"]), float(r["total_ms"]))
+            for r in buf[:min(n.value, max_labels)]}
 
 
 # ------------------------------------------------------------------ host views
