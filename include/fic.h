@@ -144,6 +144,29 @@ int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, in
                      int32_t n_ranges, fic_match* out, int32_t* pool_out, int32_t* pool_count,
                      void* stream);
 
+/* Matcher implementations for fic_encode_level_ex. */
+enum fic_match_variant {
+    FIC_MATCH_AUTO = 0,     /* the library's choice (what fic_encode_level uses)          */
+    FIC_MATCH_VALU = 1,     /* dot4 correlation, exact 32/64-bit integer epilogue        */
+    FIC_MATCH_MFMA_I8 = 2,  /* int8 MFMA correlation (hi/lo split of the 2x2 sums),      */
+                            /* FP32 screen with a proven margin, exact int64 rescoring   */
+    FIC_MATCH_FP32 = 3      /* FP32 FMA correlation and FP32 E, no exact rescoring: a    */
+                            /* comparator whose result may differ from the exact search  */
+};
+
+/*
+ * fic_encode_level with an explicit matcher. FIC_MATCH_MFMA_I8 and
+ * FIC_MATCH_FP32 need B = 8 and a contrast set 0, 1, ..., k1 with k1 >= 2
+ * (FIC_EINVAL otherwise). VALU, MFMA_I8 and AUTO return the exact result.
+ * FP32 returns its own FP32 argmin with its FP32 E in `E` and, in e_num, the
+ * exact 1600 n E of the candidate it chose.
+ */
+int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
+                        int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
+                        float entropy_bits, int32_t min_pool, const int32_t* range_yx,
+                        int32_t n_ranges, fic_match* out, int32_t* pool_out, int32_t* pool_count,
+                        int32_t variant, void* stream);
+
 /*
  * Quadtree encoder (Section 2; the three cases at the end of Section 3.1).
  * Level 0 matches every B0 x B0 range. A range whose best transform has

@@ -1080,4 +1080,517 @@ int match_chunk_domains(int B) {
     }
 }
 
+
+// ================================================================ int8 MFMA matcher (B = 8)
+// The correlation of every range row with every pool domain as an integer
+// GEMM on the matrix cores: rows are r' = r - 128 (int8), columns split the
+// 2x2 sums as d' = 128 h + l with h in 0..7 and l in 0..127 (both int8), so
+//   X = sum r' d' = 128 sum r' h + sum r' l
+// is exact in int32 after two v_mfma_i32_16x16x64_i8 (K = 64 = n). Then
+//   B' = n P - sumR sumD' = 64 X - sumR' S,   sumR' = sumR - 128 n,
+// also exact in int32. An FP32 screen (below) discards elements that cannot
+// beat the row's best; the rest are decided exactly in int64, keeping the
+// result identical to the exhaustive definition.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kM8Waves = 4;                            // wavefronts per workgroup
+constexpr int kM8RowTiles = 2;                         // 16-row MFMA tiles per wavefront
+constexpr int kM8Rows = kM8Waves * 16 * kM8RowTiles;   // 128 rows = 16 ranges x 8 isometries
+constexpr int kM8ColTiles = 4;                         // 16-column tiles per LDS stage
+constexpr int kM8Cols = 16 * kM8ColTiles;              // 64 pool domains per LDS stage
+constexpr int kM8Chunk = 1024;                         // target pool domains per chunk
+
+// Rows r' = r - 128 of the 8 inverse-isometry arrangements of each range:
+// Ar[(8q + t) * 64 + m] = R[iso_src(8, inverse(t), m)] - 128. Thread per row.
+__global__ __launch_bounds__(kBlock) void k_range_prep_i8(const uint8_t* __restrict__ img, int pitch,
+                                                          const int32_t* __restrict__ act,
+                                                          const int32_t* act_count,
+                                                          int8_t* __restrict__ Ar,
+                                                          int32_t* __restrict__ SR,
+                                                          int32_t* __restrict__ SRp,
+                                                          int64_t* __restrict__ CR) {
+    constexpr int B = 8, n = 64;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= 8 * *act_count) return;
+    const int q = row >> 3, t = row & 7;
+    const int yx = act[q];
+    uint32_t* dst = reinterpret_cast<uint32_t*>(Ar + (int64_t)row * n);
+    if (yx < 0) {
+        for (int w = 0; w < n / 4; ++w) dst[w] = 0x80808080u;  // r = 0 -> r' = -128
+        if (t == 0) {
+            SR[q] = 0;
+            SRp[q] = -128 * n;
+            CR[q] = 0;
+        }
+        return;
+    }
+    const uint8_t* r = img + (int64_t)(yx >> 16) * pitch + (yx & 0xffff);
+    const int u = iso_inverse(t);
+    const int a0 = iso_src(B, u, 0, 0);
+    const int a1 = iso_src(B, u, 1, 0) - a0, a2 = iso_src(B, u, 0, 1) - a0;
+#pragma unroll
+    for (int w = 0; w < n / 4; ++w) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int m = 4 * w + b;
+            const int src = a0 + a1 * (m / B) + a2 * (m % B);
+            v |= (uint32_t)(uint8_t)((int)r[(src / B) * pitch + src % B] - 128) << (8 * b);
+        }
+        dst[w] = v;
+    }
+    if (t == 0) {
+        int s = 0;
+        int64_t s2 = 0;
+        for (int i = 0; i < B; ++i)
+            for (int c = 0; c < B; ++c) {
+                const int v = r[i * pitch + c];
+                s += v;
+                s2 += v * v;
+            }
+        SR[q] = s;
+        SRp[q] = s - 128 * n;
+        CR[q] = (int64_t)n * s2 - (int64_t)s * s;
+    }
+}
+
+// Columns for the int8 matcher: h and l rows of each pool domain, and
+// G = 40 / A' (0 for a constant domain) and A' in FP32 for the screen. Four
+// lanes share a domain, 16 decimated values each.
+__global__ __launch_bounds__(kBlock) void k_pool_prep_i8(const uint8_t* __restrict__ img, int pitch,
+                                                         int L, int gx, const int32_t* __restrict__ pool,
+                                                         int identity_total, Ctrl* ctrl,
+                                                         int8_t* __restrict__ Dh, int8_t* __restrict__ Dl,
+                                                         uint32_t* __restrict__ Sd, int64_t* __restrict__ Ad,
+                                                         int32_t* __restrict__ Jd, float* __restrict__ Gd,
+                                                         float* __restrict__ Af) {
+    constexpr int B = 8, n = 64, TPD = 4, PER = 16;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (identity_total >= 0 && g == 0) {
+        ctrl->pool_count = identity_total;
+        ctrl->passed = identity_total;
+    }
+    const int count = identity_total >= 0 ? identity_total : ctrl->pool_count;
+    const int p = g / TPD, sub = g % TPD;
+    const bool ok = p < count;
+    uint32_t s = 0;
+    uint64_t q = 0;
+    int j = 0;
+    if (ok) {
+        j = identity_total >= 0 ? p : pool[p];
+        const int y = (j / gx) * L, x = (j % gx) * L;
+        uint32_t* hd = reinterpret_cast<uint32_t*>(Dh + (int64_t)p * n + sub * PER);
+        uint32_t* ld = reinterpret_cast<uint32_t*>(Dl + (int64_t)p * n + sub * PER);
+#pragma unroll
+        for (int w = 0; w < PER / 4; ++w) {
+            uint32_t hw = 0, lw = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int m = sub * PER + 4 * w + b, i = m / B, c = m % B;
+                const uint8_t* px = img + (int64_t)(y + 2 * i) * pitch + x + 2 * c;
+                const uint32_t d = (uint32_t)px[0] + px[1] + px[pitch] + px[pitch + 1];
+                s += d;
+                q += (uint64_t)d * d;
+                hw |= (d >> 7) << (8 * b);
+                lw |= (d & 127u) << (8 * b);
+            }
+            hd[w] = hw;
+            ld[w] = lw;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < TPD; m <<= 1) {
+        s += __shfl_xor(s, m, 64);
+        q += __shfl_xor(q, m, 64);
+    }
+    if (ok && sub == 0) {
+        const int64_t A = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
+        Sd[p] = s;
+        Ad[p] = A;
+        Jd[p] = j;
+        Gd[p] = A > 0 ? 40.0f / (float)A : 0.0f;
+        Af[p] = (float)A;
+    }
+}
+
+// Smallest k in [0, k1] with (2k+1) A' >= 80 B' (the exact minimiser of F).
+__device__ inline int grid_k(int64_t Bp, int64_t Ap, int k1) {
+    if (Ap <= 0 || Bp <= 0) return 0;
+    int k = (int)fminf(fmaxf(rintf((float)Bp * (40.0f / (float)Ap)), 0.0f), (float)k1);
+    const int64_t b80 = 80 * Bp;
+    while (k > 0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
+    while (k < k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
+    return k;
+}
+
+__device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
+    const int64_t of = __shfl_xor(F, mask, 64);
+    const int64_t ok = __shfl_xor(K, mask, 64);
+    if (pair_less(of, ok, F, K)) {
+        F = of;
+        K = ok;
+    }
+}
+
+// grid: x = workgroups of 256 rows, y = pool chunks. The contrast set is
+// k = 0..k1. Each wavefront keeps 32 rows; each lane holds 4 rows x 1 column
+// of every 16x16 output tile. Per element the screen evaluates
+//   F~ = k~ (k~ A' - 80 B'),  k~ = clamp(rint(40 B' / A'), 0, k1)
+// in FP32 from the exact integer B'. For n = 64, |F~ - F(k~)| <= 2.4e5 (five
+// roundings of values below 2^40) and F(k~) - F(k*) <= 6e3 (k~ can only be off
+// by one next to a half-integer), so F* >= F~ - 2.5e5. The row threshold is
+// F~(best) + kM8ScreenMargin >= F_best + 7.5e5, and an element with F~ at or
+// above it has F* > F_best: it cannot win or tie and is skipped. The others are
+// decided exactly in int64 (the FP32 k corrected by one step). The 16 lanes of
+// a row share their thresholds every kM8Share stages.
+constexpr float kM8ScreenMargin = 1.0e6f;
+constexpr int kM8Share = 4;
+
+__global__ __launch_bounds__(kM8Waves * 64) void k_match_mfma8(
+    const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int32_t* act_count,
+    const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
+    const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Af,
+    const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
+    Partial* __restrict__ part) {
+    __shared__ v4i sH[kM8Cols * 4];  // column c, K-group g at [c * 4 + g]
+    __shared__ v4i sL[kM8Cols * 4];
+    __shared__ float sG[kM8Cols], sAf[kM8Cols];
+    __shared__ int32_t sS[kM8Cols];
+    __shared__ int64_t sA[kM8Cols];
+
+    const int nrows = 8 * *act_count;
+    const int row_blk = blockIdx.x * kM8Rows;
+    if (row_blk >= nrows) return;
+    const int P = ctrl->pool_count;
+    const int nca = active_chunks(P, kM8Chunk, n_chunks);
+    const int c = blockIdx.y;
+    if (c >= nca) return;
+    const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int wrow0 = row_blk + wave * 16 * kM8RowTiles;
+    const float kmax = (float)k1;
+
+    v4i a[kM8RowTiles];
+    int nsrp[kM8RowTiles];  // -sum r' of the lane's output range, per row tile
+    int64_t bestF[kM8RowTiles][4];
+    int bestPK[kM8RowTiles][4];
+    float thr[kM8RowTiles][4];
+#pragma unroll
+    for (int rt = 0; rt < kM8RowTiles; ++rt) {
+        const int arow = wrow0 + 16 * rt + c16;
+        const v4i z = {0, 0, 0, 0};
+        a[rt] = arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 16 * g) : z;
+        const int orow = wrow0 + 16 * rt + 4 * g;
+        nsrp[rt] = orow < nrows ? -SRp[orow >> 3] : 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            bestF[rt][e] = 0;          // k = 0 gives F = 0 for every domain;
+            bestPK[rt][e] = lo * 16;   // its smallest key is the chunk's first domain
+            thr[rt][e] = kM8ScreenMargin;
+        }
+    }
+
+    int stage = 0;
+    for (int base = lo; base < hi; base += kM8Cols, ++stage) {
+        const int cnt = min(kM8Cols, hi - base);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 2 * kM8Cols * 4; idx += kM8Waves * 64) {
+            // 256 16-byte chunks of h, then 256 of l
+            const int e = idx & (kM8Cols * 4 - 1), col = e >> 2, gg = e & 3;
+            const bool is_h = idx < kM8Cols * 4;
+            v4i v = {0, 0, 0, 0};
+            if (col < cnt)
+                v = *reinterpret_cast<const v4i*>((is_h ? Dh : Dl) + (int64_t)(base + col) * 64 +
+                                                   16 * gg);
+            if (is_h) sH[e] = v;
+            else sL[e] = v;
+        }
+        if (threadIdx.x < kM8Cols) {
+            const int col = threadIdx.x;
+            const bool ok = col < cnt;
+            // a padded column gets g = 0 and A'f = 1e30: F~ = 0 * ... = huge, never a candidate
+            sG[col] = ok ? Gd[base + col] : 0.0f;
+            sAf[col] = ok ? Af[base + col] : 1.0e30f;
+            sS[col] = ok ? (int32_t)Sd[base + col] : 0;
+            sA[col] = ok ? Ad[base + col] : 0;
+        }
+        __syncthreads();
+        v4i bh[kM8ColTiles], bl[kM8ColTiles];
+#pragma unroll
+        for (int ct = 0; ct < kM8ColTiles; ++ct) {
+            bh[ct] = sH[(16 * ct + c16) * 4 + g];
+            bl[ct] = sL[(16 * ct + c16) * 4 + g];
+        }
+        v4i acc[kM8RowTiles][kM8ColTiles];
+        const v4i z = {0, 0, 0, 0};
+#pragma unroll
+        for (int rt = 0; rt < kM8RowTiles; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < kM8ColTiles; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bh[ct], z, 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < kM8RowTiles; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < kM8ColTiles; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bl[ct], acc[rt][ct] << 7,
+                                                                    0, 0, 0);
+#pragma unroll
+        for (int ct = 0; ct < kM8ColTiles; ++ct) {
+            const int col = 16 * ct + c16;
+            const float gj = sG[col], aj = sAf[col];
+            const int sj = sS[col];
+#pragma unroll
+            for (int rt = 0; rt < kM8RowTiles; ++rt) {
+                const int toff = __mul24(nsrp[rt], sj);  // -sum r' * S (24-bit operands)
+                int bi[4];
+                float kk[4], ft[4];
+                bool cand[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    bi[e] = (acc[rt][ct][e] << 6) + toff;  // B' = 64 X - sum r' S, exact
+                    const float bf = (float)bi[e];
+                    kk[e] = __builtin_amdgcn_fmed3f(rintf(bf * gj), 0.0f, kmax);
+                    ft[e] = kk[e] * fmaf(kk[e], aj, -80.0f * bf);
+                    cand[e] = ft[e] < thr[rt][e];
+                }
+                if (__any(cand[0] | cand[1] | cand[2] | cand[3])) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (cand[e]) {
+                            // exact: the FP32 k is within one of the minimiser
+                            const int64_t Bp = bi[e];
+                            const int64_t Ap = sA[col];
+                            const int64_t b80 = 80 * Bp;
+                            int k = (int)kk[e];
+                            if (Ap <= 0) k = 0;
+                            else if (k > 0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
+                            else if (k < k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
+                            const int64_t F = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
+                            if (F < bestF[rt][e]) {
+                                bestF[rt][e] = F;
+                                bestPK[rt][e] = (base + col) * 16 + k;
+                                thr[rt][e] = fminf(thr[rt][e], ft[e] + kM8ScreenMargin);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if ((stage % kM8Share) == kM8Share - 1) {
+            // the 16 lanes of a row (same g) share the smallest threshold
+#pragma unroll
+            for (int rt = 0; rt < kM8RowTiles; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float t = thr[rt][e];
+                    t = fminf(t, __shfl_xor(t, 1, 64));
+                    t = fminf(t, __shfl_xor(t, 2, 64));
+                    t = fminf(t, __shfl_xor(t, 4, 64));
+                    t = fminf(t, __shfl_xor(t, 8, 64));
+                    thr[rt][e] = t;
+                }
+        }
+    }
+    // per range: 4 rows per lane, 16 lanes per row, 2 lane groups per range
+#pragma unroll
+    for (int rt = 0; rt < kM8RowTiles; ++rt) {
+        const int orow = wrow0 + 16 * rt + 4 * g;
+        int64_t F = INT64_MAX, K = INT64_MAX;
+        if (lo < hi && orow < nrows) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = bestPK[rt][e] >> 4, k = bestPK[rt][e] & 15;
+                const int64_t key = make_key(Jd[p], (orow + e) & 7, k, Sd[p]);
+                if (pair_less(bestF[rt][e], key, F, K)) {
+                    F = bestF[rt][e];
+                    K = key;
+                }
+            }
+        }
+        lex_min_shfl(F, K, 1);
+        lex_min_shfl(F, K, 2);
+        lex_min_shfl(F, K, 4);
+        lex_min_shfl(F, K, 8);
+        lex_min_shfl(F, K, 16);
+        if (c16 == 0 && (g & 1) == 0 && orow < nrows) {
+            Partial pr;
+            pr.F = F;
+            pr.key = K;
+            part[(int64_t)(orow >> 3) * n_chunks + c] = pr;
+        }
+    }
+}
+
+// ================================================================ FP32-FMA comparator (B = 8)
+// The same search with the correlation in FP32 FMAs (exact: every partial sum
+// is an integer below 2^24) and E decided in FP32, with no exact rescoring:
+// it shows what plain single precision gets right and wrong.
+__device__ inline int64_t ordered_float(float f) {
+    const int32_t b = __float_as_int(f);
+    return (int64_t)(b >= 0 ? b : (b ^ 0x7fffffff));
+}
+
+__device__ inline float float_from_ordered(int64_t o) {
+    const int32_t b = (int32_t)o;
+    return __int_as_float(b >= 0 ? b : (b ^ 0x7fffffff));
+}
+
+constexpr int kF32Tile = 64;  // domains per LDS stage
+
+__global__ __launch_bounds__(kBlock) void k_match_fp32(const uint8_t* __restrict__ img, int pitch,
+                                                       const int32_t* __restrict__ act,
+                                                       const int32_t* act_count,
+                                                       const uint8_t* __restrict__ DDimg, int L,
+                                                       int gx, const int32_t* __restrict__ Jd,
+                                                       const Ctrl* ctrl, int k1, int n_chunks,
+                                                       Partial* __restrict__ part) {
+    constexpr int B = 8, n = 64, RPB = kBlock / 8;
+    __shared__ float sD[kF32Tile * n];
+    __shared__ float sS[kF32Tile], sA[kF32Tile];
+    __shared__ uint8_t sR[RPB * n];
+    const int nact = *act_count;
+    const int q0 = blockIdx.x * RPB;
+    if (q0 >= nact) return;
+    const int P = ctrl->pool_count;
+    const int nca = active_chunks(P, 256, n_chunks);
+    const int c = blockIdx.y;
+    if (c >= nca) return;
+    const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
+    for (int e = threadIdx.x; e < RPB * n; e += kBlock) {
+        const int lq = e / n, m = e % n, q = q0 + lq;
+        uint8_t v = 0;
+        if (q < nact) {
+            const int yx = act[q];
+            if (yx >= 0) v = img[(int64_t)((yx >> 16) + m / B) * pitch + (yx & 0xffff) + m % B];
+        }
+        sR[e] = v;
+    }
+    __syncthreads();
+    const int lq = threadIdx.x >> 3, t = threadIdx.x & 7, q = q0 + lq;
+    const uint8_t* rr = sR + lq * n;
+    float r[n];
+    float sr = 0.0f;
+    {
+        const int u = iso_inverse(t);
+        const int a0 = iso_src(B, u, 0, 0);
+        const int a1 = iso_src(B, u, 1, 0) - a0, a2 = iso_src(B, u, 0, 1) - a0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) {
+            r[m] = (float)rr[a0 + a1 * (m / B) + a2 * (m % B)];
+            sr += r[m];
+        }
+    }
+    float bestF = INFINITY;
+    int bestP = lo, bestK = 0;
+    for (int base = lo; base < hi; base += kF32Tile) {
+        const int cnt = min(kF32Tile, hi - base);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * n; e += kBlock) {
+            const int d = e / n, m = e % n;
+            const int j = Jd[base + d];
+            const int y = (j / gx) * L, x = (j % gx) * L;
+            const uint8_t* px = DDimg + (int64_t)(y + 2 * (m / B)) * pitch + x + 2 * (m % B);
+            sD[e] = (float)((int)px[0] + px[1] + px[pitch] + px[pitch + 1]);
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < cnt; d += kBlock) {
+            float s = 0.0f, s2 = 0.0f;
+            for (int m = 0; m < n; ++m) {
+                const float v = sD[d * n + m];
+                s += v;
+                s2 = fmaf(v, v, s2);
+            }
+            sS[d] = s;
+            sA[d] = fmaf((float)n, s2, -s * s);
+        }
+        __syncthreads();
+        for (int d = 0; d < cnt; ++d) {
+            float p = 0.0f;
+#pragma unroll
+            for (int m = 0; m < n; ++m) p = fmaf(r[m], sD[d * n + m], p);
+            const float Bp = fmaf((float)n, p, -sr * sS[d]);
+            const float Ap = sA[d];
+            float kf = Ap > 0.0f ? fminf(fmaxf(rintf(40.0f * Bp / Ap), 0.0f), (float)k1) : 0.0f;
+            const float F = kf * fmaf(kf, Ap, -80.0f * Bp);
+            if (F < bestF) {
+                bestF = F;
+                bestP = base + d;
+                bestK = (int)kf;
+            }
+        }
+    }
+    int64_t outF = INT64_MAX, outK = INT64_MAX;
+    if (lo < hi) {
+        outF = ordered_float(bestF);
+        outK = make_key(Jd[bestP], t, bestK, 0);
+    }
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) lex_min_shfl(outF, outK, m);
+    if (q < nact && t == 0) {
+        Partial pr;
+        pr.F = outF;
+        pr.key = outK;
+        part[(int64_t)q * n_chunks + c] = pr;
+    }
+}
+
+// Result of the FP32 comparator: its own argmin and FP32 E, plus the exact
+// e_num of the candidate it chose (recomputed in integers for reporting).
+__global__ __launch_bounds__(kBlock) void k_reduce_fp32(const uint8_t* __restrict__ img, int pitch,
+                                                        int L, int gx, const int32_t* __restrict__ act,
+                                                        const int32_t* act_count,
+                                                        const Partial* __restrict__ part,
+                                                        int n_chunks, const Ctrl* ctrl,
+                                                        fic_match* __restrict__ out) {
+    constexpr int B = 8, n = 64;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= *act_count) return;
+    const int nca = active_chunks(ctrl->pool_count, 256, n_chunks);
+    int64_t F = INT64_MAX, K = INT64_MAX;
+    for (int c = 0; c < nca; ++c)
+        if (pair_less(part[(int64_t)q * n_chunks + c].F, part[(int64_t)q * n_chunks + c].key, F, K)) {
+            F = part[(int64_t)q * n_chunks + c].F;
+            K = part[(int64_t)q * n_chunks + c].key;
+        }
+    fic_match m;
+    m.flags = 0;
+    m.pad_ = 0;
+    const int yx = act[q];
+    if (yx < 0 || K == INT64_MAX) {
+        m.e_num = -1;
+        m.dom = -1;
+        m.iso = m.s_idx = m.k = 0;
+        m.q_o = 0;
+        m.E = -1.0f;
+        out[q] = m;
+        return;
+    }
+    const int j = (int)(K >> 27), t = (int)((K >> 24) & 7), k = (int)((K >> 20) & 15);
+    const int dy = (j / gx) * L, dx = (j % gx) * L;
+    const uint8_t* R = img + (int64_t)(yx >> 16) * pitch + (yx & 0xffff);
+    int64_t sr = 0, sr2 = 0, sd = 0, sd2 = 0, pr = 0;
+    for (int i = 0; i < B; ++i)
+        for (int cc = 0; cc < B; ++cc) {
+            const int src = iso_src(B, t, i, cc);
+            const uint8_t* px = img + (int64_t)(dy + 2 * (src / B)) * pitch + dx + 2 * (src % B);
+            const int64_t d = (int64_t)px[0] + px[1] + px[pitch] + px[pitch + 1];
+            const int64_t r = R[i * pitch + cc];
+            sr += r;
+            sr2 += r * r;
+            sd += d;
+            sd2 += d * d;
+            pr += r * d;
+        }
+    const int64_t Ap = n * sd2 - sd * sd, Bp = n * pr - sr * sd, C = n * sr2 - sr * sr;
+    m.e_num = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp + 1600 * C;
+    m.dom = j;
+    m.iso = (uint8_t)t;
+    m.s_idx = (uint8_t)k;
+    m.k = (uint8_t)k;
+    m.q_o = (int16_t)floordiv64(2 * (40 * sr - k * sd) + 40 * n, 80 * (int64_t)n);
+    m.E = (float_from_ordered(F) + 1600.0f * (float)C) / (1600.0f * (float)n);
+    out[q] = m;
+}
+
 }  // namespace fic

@@ -62,6 +62,7 @@ struct Workspace {
     int64_t* T = nullptr;  // entropy table, kMaxWindow + 1 entries
     Buf key, pool, hl, sd, ad, jd, arow, sr, cr, part, blk, act0, act1, tmpc, dec, codes, map,
         imgA, imgB, acc, mr;
+    Buf ar, srp, dh, dl, wd, cw;  // int8 MFMA matcher (B = 8)
 };
 
 std::mutex g_mu;
@@ -220,15 +221,28 @@ int check_kset(const int8_t* k, int n, KSet* ks) {
 bool valid_B(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
 
 // ---------------------------------------------------------------- one level
+// Matcher selected for a level (fic_encode_level_ex's variant).
+enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3 };
+
 struct Level {
     int lv, B, L, gy, gx, total;  // domain grid
     int max_act;                  // worst-case active ranges
     int nc;                       // pool chunks of the matcher
+    int var;                      // kVarValu, kVarMfma or kVarFp32
     KSet ks;
 };
 
-Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks) {
+// The int8 MFMA matcher serves B = 8 with a contrast grid 0..k1 (k1 >= 2).
+bool mfma_eligible(int B, const KSet& ks) {
+    return B == 8 && ks.consecutive && ks.k0 == 0 && ks.n >= 3;
+}
+
+// Pool domains per chunk of the level's matcher (its partials per range).
+int chunk_domains(const Level& v);
+
+Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks, int variant = 0) {
     Level v;
+    v.var = variant != 0 ? variant : (mfma_eligible(B, ks) ? kVarMfma : kVarValu);
     v.lv = lv;
     v.B = B;
     v.L = L;
@@ -245,8 +259,15 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
     return v;
 }
 
+int chunk_domains(const Level& v) {
+    if (v.var == kVarMfma) return kM8Chunk;
+    if (v.var == kVarFp32) return 256;
+    return match_chunk_domains(v.B);
+}
+
 struct Sizes {
     size_t key = 0, pool = 0, hl = 0, dom = 0, arow = 0, rng = 0, part = 0, blk = 0, act = 0;
+    size_t ar = 0, dcol = 0;  // int8 MFMA matcher
 };
 
 void grow(Sizes& s, const Level& v) {
@@ -261,6 +282,10 @@ void grow(Sizes& s, const Level& v) {
     size_t nblk = (size_t)std::max(cdiv(v.total, kBlock * kPoolItems), cdiv(v.max_act, kBlock * kQuadItems));
     s.blk = std::max(s.blk, nblk * sizeof(int2));
     s.act = std::max(s.act, (size_t)v.max_act);
+    if (v.var == kVarMfma) {
+        s.ar = std::max(s.ar, (size_t)v.max_act * 8 * 64);
+        s.dcol = std::max(s.dcol, (size_t)v.total);
+    }
 }
 
 int ensure_sizes(Workspace& ws, const Sizes& s) {
@@ -280,7 +305,40 @@ int ensure_sizes(Workspace& ws, const Sizes& s) {
     if ((rc = ensure(ws, ws.act1, s.act * 4))) return rc;
     if ((rc = ensure(ws, ws.tmpc, s.act * sizeof(fic_code)))) return rc;
     if ((rc = ensure(ws, ws.dec, s.act))) return rc;
+    if (s.ar) {
+        if ((rc = ensure(ws, ws.ar, s.ar))) return rc;
+        if ((rc = ensure(ws, ws.srp, s.rng * 4))) return rc;
+        if ((rc = ensure(ws, ws.dh, s.dcol * 64))) return rc;
+        if ((rc = ensure(ws, ws.dl, s.dcol * 64))) return rc;
+        if ((rc = ensure(ws, ws.wd, s.dcol * 4))) return rc;
+        if ((rc = ensure(ws, ws.cw, s.dcol * 4))) return rc;
+    }
     return FIC_OK;
+}
+
+void launch_mfma8(Workspace& ws, const Level& v, const uint8_t* img, int pitch, bool filtered,
+                  const int32_t* act) {
+    hipStream_t st = ws.stream;
+    const int32_t* act_count = ws.ctrl->act_count + v.lv;
+    {
+        ProfScope ps("pool_prep", st);
+        k_pool_prep_i8<<<cdiv((int64_t)v.total * 4, kBlock), kBlock, 0, st>>>(
+            img, pitch, v.L, v.gx, P<int32_t>(ws.pool), filtered ? -1 : v.total, ws.ctrl,
+            P<int8_t>(ws.dh), P<int8_t>(ws.dl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad),
+            P<int32_t>(ws.jd), P<float>(ws.wd), P<float>(ws.cw));
+    }
+    {
+        ProfScope ps("range_prep", st);
+        k_range_prep_i8<<<cdiv((int64_t)8 * v.max_act, kBlock), kBlock, 0, st>>>(
+            img, pitch, act, act_count, P<int8_t>(ws.ar), P<int32_t>(ws.sr), P<int32_t>(ws.srp),
+            P<int64_t>(ws.cr));
+    }
+    ProfScope ps("match_b8_mfma", st);
+    dim3 grid(cdiv((int64_t)8 * v.max_act, kM8Rows), v.nc);
+    k_match_mfma8<<<grid, kM8Waves * 64, 0, st>>>(
+        P<int8_t>(ws.ar), P<int32_t>(ws.srp), act_count, P<int8_t>(ws.dh), P<int8_t>(ws.dl),
+        P<uint32_t>(ws.sd), P<int64_t>(ws.ad), P<float>(ws.wd), P<float>(ws.cw), P<int32_t>(ws.jd),
+        ws.ctrl, v.ks.k1, v.nc, P<Partial>(ws.part));
 }
 
 template <int B>
@@ -288,11 +346,23 @@ void launch_level_kernels(Workspace& ws, const Level& v, const uint8_t* img, int
                           bool filtered, const int32_t* act) {
     hipStream_t st = ws.stream;
     const int32_t* act_count = ws.ctrl->act_count + v.lv;
+    if (B == 8 && v.var == kVarMfma) {
+        launch_mfma8(ws, v, img, pitch, filtered, act);
+        return;
+    }
     {
         ProfScope ps("pool_prep", st);
         k_pool_prep<B><<<cdiv((int64_t)v.total * PrepShape<B>::TPD, kBlock), kBlock, 0, st>>>(
             img, pitch, v.L, v.gx, P<int32_t>(ws.pool), filtered ? -1 : v.total, ws.ctrl,
             P<uint32_t>(ws.hl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad), P<int32_t>(ws.jd));
+    }
+    if (B == 8 && v.var == kVarFp32) {
+        ProfScope ps("match_b8_fp32", st);
+        dim3 g32(cdiv(v.max_act, kBlock / 8), v.nc);
+        k_match_fp32<<<g32, kBlock, 0, st>>>(img, pitch, act, act_count, img, v.L, v.gx,
+                                             P<int32_t>(ws.jd), ws.ctrl, v.ks.k1, v.nc,
+                                             P<Partial>(ws.part));
+        return;
     }
     ProfScope ps(match_label(B), st);
     dim3 grid(cdiv(v.max_act, kBlock / 8), v.nc);
@@ -458,7 +528,7 @@ int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch
             ProfScope ps("reduce_quad", st);
             k_reduce_quad<<<nblk, kBlock, 0, st>>>(
                 v.B, v.L, v.gx, l, last ? 1 : 0, thr, P<int32_t>(*cur), ws.ctrl, P<Partial>(ws.part),
-                v.nc, match_chunk_domains(v.B), P<int64_t>(ws.cr), P<int32_t>(ws.sr), v.ks,
+                v.nc, chunk_domains(v), P<int64_t>(ws.cr), P<int32_t>(ws.sr), v.ks,
                 P<fic_code>(ws.tmpc), P<uint8_t>(ws.dec), P<int2>(ws.blk), stats);
         }
         {
@@ -486,11 +556,11 @@ FIC_API int fic_version(void) { return 100; }
 
 FIC_API const char* fic_last_error(void) { return g_err.c_str(); }
 
-FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
-                             int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
-                             float entropy_bits, int32_t min_pool, const int32_t* range_yx,
-                             int32_t n_ranges, fic_match* out, int32_t* pool_out,
-                             int32_t* pool_count, void* stream) {
+FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
+                                int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
+                                float entropy_bits, int32_t min_pool, const int32_t* range_yx,
+                                int32_t n_ranges, fic_match* out, int32_t* pool_out,
+                                int32_t* pool_count, int32_t variant, void* stream) {
     int rc = check_image(img, H, W, pitch, B);
     if (rc) return rc;
     if (L < 1) return fail(FIC_EINVAL, "domain step L=%d < 1", L);
@@ -503,10 +573,18 @@ FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t p
     if (!range_yx && n_ranges != (H / B) * (W / B))
         return fail(FIC_EINVAL, "range_yx is NULL but n_ranges %d != %d", n_ranges, (H / B) * (W / B));
     if (n_ranges > 0 && !out) return fail(FIC_EINVAL, "out is NULL");
+    if (variant < FIC_MATCH_AUTO || variant > FIC_MATCH_FP32)
+        return fail(FIC_EINVAL, "matcher variant %d unknown", variant);
+    if ((variant == FIC_MATCH_MFMA_I8 || variant == FIC_MATCH_FP32) && !mfma_eligible(B, ks))
+        return fail(FIC_EINVAL, "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2)",
+                    variant);
     if (n_ranges == 0) return FIC_OK;
     Workspace* ws;
     if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
-    Level v = make_level(0, H, W, B, L, n_ranges, ks);
+    const int var = variant == FIC_MATCH_VALU ? kVarValu
+                    : variant == FIC_MATCH_MFMA_I8 ? kVarMfma
+                    : variant == FIC_MATCH_FP32 ? kVarFp32 : 0;
+    Level v = make_level(0, H, W, B, L, n_ranges, ks, var);
     Sizes sz;
     grow(sz, v);
     if ((rc = ensure_sizes(*ws, sz))) return rc;
@@ -520,10 +598,15 @@ FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t p
     if ((rc = run_level(*ws, v, img, pitch, entropy_mode, entropy_bits, min_pool, act)))
         return rc;
     {
-    ProfScope ps("reduce_level", st);
-    k_reduce_level<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(
-        B, L, v.gx, act, ws->ctrl->act_count, P<Partial>(ws->part), v.nc, match_chunk_domains(B),
-        ws->ctrl, P<int64_t>(ws->cr), P<int32_t>(ws->sr), ks, out);
+        ProfScope ps("reduce_level", st);
+        if (v.var == kVarFp32)
+            k_reduce_fp32<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(
+                img, pitch, L, v.gx, act, ws->ctrl->act_count, P<Partial>(ws->part), v.nc, ws->ctrl,
+                out);
+        else
+            k_reduce_level<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(
+                B, L, v.gx, act, ws->ctrl->act_count, P<Partial>(ws->part), v.nc, chunk_domains(v),
+                ws->ctrl, P<int64_t>(ws->cr), P<int32_t>(ws->sr), ks, out);
     }
     LAUNCH_CHECK();
     if (pool_count)
@@ -538,6 +621,16 @@ FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t p
                                    hipMemcpyDeviceToDevice, st));
     }
     return FIC_OK;
+}
+
+FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
+                             int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
+                             float entropy_bits, int32_t min_pool, const int32_t* range_yx,
+                             int32_t n_ranges, fic_match* out, int32_t* pool_out,
+                             int32_t* pool_count, void* stream) {
+    return fic_encode_level_ex(img, H, W, pitch, B, L, s_k, n_s, entropy_mode, entropy_bits,
+                               min_pool, range_yx, n_ranges, out, pool_out, pool_count,
+                               FIC_MATCH_AUTO, stream);
 }
 
 FIC_API int fic_encode_image(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,

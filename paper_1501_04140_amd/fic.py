@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfic.so")
 
 FIC_OK, FIC_EINVAL, FIC_ECAPACITY, FIC_EDEVICE, FIC_ENOMEM = 0, -1, -2, -3, -4
+MATCH_AUTO, MATCH_VALU, MATCH_MFMA_I8, MATCH_FP32 = 0, 1, 2, 3
 MAX_S = 11
 PLAIN_K = tuple(range(11))                   # s = 0, 0.1, ..., 1.0 (Section 2)
 PAPER_K = ((1,), (2, 4), (3, 8), (5, 9))     # predefined s per step (Section 3.1)
@@ -94,13 +95,15 @@ def load():
     vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
     lib.fic_encode_level.argtypes = [vp, i32, i32, i32, i32, i32, vp, i32, i32, f32, i32, vp, i32,
                                      vp, vp, vp, vp]
+    lib.fic_encode_level_ex.argtypes = [vp, i32, i32, i32, i32, i32, vp, i32, i32, f32, i32, vp,
+                                        i32, vp, vp, vp, i32, vp]
     lib.fic_encode_image.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, i32, vp, vp, vp]
     lib.fic_decode.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp]
     lib.fic_sse.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
     lib.fic_calibrate_s.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, vp]
     lib.fic_profile_end.argtypes = [vp, i32, vp]
     lib.fic_last_error.restype = ctypes.c_char_p
-    for name in ("fic_encode_level", "fic_encode_image", "fic_decode", "fic_sse",
+    for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_image", "fic_decode", "fic_sse",
                  "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -131,8 +134,8 @@ def _dev_u8_image(img):
 
 def encode_level(img, B: int, L: int, s_k=PLAIN_K, entropy_mode: int = 0,
                  entropy_bits: float = 2.5, min_pool: int = 256, ranges=None,
-                 return_pool: bool = False, stream=None):
-    """fic_encode_level. Returns a uint8 tensor [n_ranges, 24] of fic_match records
+                 return_pool: bool = False, stream=None, variant: int = MATCH_AUTO):
+    """fic_encode_level_ex. Returns a uint8 tensor [n_ranges, 24] of fic_match records
     (and, with return_pool, the pool index tensor and a 1-element pool-count tensor)."""
     import torch
     img = _dev_u8_image(img)
@@ -149,11 +152,12 @@ def encode_level(img, B: int, L: int, s_k=PLAIN_K, entropy_mode: int = 0,
     gy = (H - 2 * B) // L + 1 if L > 0 else 1
     pool = torch.empty(max(gx * gy, 1), dtype=torch.int32, device=img.device) if return_pool else None
     pcount = torch.zeros(1, dtype=torch.int32, device=img.device) if return_pool else None
-    rc = lib.fic_encode_level(img.data_ptr(), H, W, img.stride(0), B, L, ks, len(s_k),
-                              entropy_mode, entropy_bits, min_pool,
-                              ranges.data_ptr() if ranges is not None else None, n,
-                              out.data_ptr(), pool.data_ptr() if pool is not None else None,
-                              pcount.data_ptr() if pcount is not None else None, _stream(stream))
+    rc = lib.fic_encode_level_ex(img.data_ptr(), H, W, img.stride(0), B, L, ks, len(s_k),
+                                 entropy_mode, entropy_bits, min_pool,
+                                 ranges.data_ptr() if ranges is not None else None, n,
+                                 out.data_ptr(), pool.data_ptr() if pool is not None else None,
+                                 pcount.data_ptr() if pcount is not None else None, variant,
+                                 _stream(stream))
     _check(rc)
     out = out[:n]
     return (out, pool, pcount) if return_pool else out

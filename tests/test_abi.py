@@ -108,6 +108,18 @@ def test_encode_image_capacity_lower_bound(lib):
     assert rc == fic.FIC_ECAPACITY and "capacity" in lib.fic_last_error().decode()
 
 
+def test_encode_level_ex_rejects_variants(lib):
+    ks = (ctypes.c_int8 * 16)(*range(11))
+    def call(B, n_s, variant):
+        return lib.fic_encode_level_ex(1, 64, 64, 64, B, 4, ks, n_s, 0, 2.5, 1, None,
+                                       (64 // B) ** 2, 1, None, None, variant, None)
+    assert call(8, 11, 4) == fic.FIC_EINVAL and "variant" in lib.fic_last_error().decode()
+    assert call(8, 11, -1) == fic.FIC_EINVAL
+    assert call(4, 11, fic.MATCH_MFMA_I8) == fic.FIC_EINVAL and "B = 8" in lib.fic_last_error().decode()
+    assert call(8, 2, fic.MATCH_MFMA_I8) == fic.FIC_EINVAL
+    assert call(16, 11, fic.MATCH_FP32) == fic.FIC_EINVAL
+
+
 def test_decode_and_sse_reject(lib):
     assert lib.fic_decode(1, 4, 16, 16, 4, None, 16, None) == fic.FIC_EINVAL
     assert lib.fic_decode(1, 0, 16, 16, 4, 1, 16, None) == fic.FIC_EINVAL

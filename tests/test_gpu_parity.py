@@ -23,10 +23,12 @@ def dev():
     return torch.device("cuda:0")
 
 
-def gpu_level(dev, img, B, L, ks, entropy=0, bits=2.5, min_pool=256, ranges=None):
+def gpu_level(dev, img, B, L, ks, entropy=0, bits=2.5, min_pool=256, ranges=None,
+              variant=fic.MATCH_AUTO):
     x = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
     r = None if ranges is None else torch.from_numpy(np.asarray(ranges, np.int32)).to(dev)
-    out, pool, pc = fic.encode_level(x, B, L, ks, entropy, bits, min_pool, ranges=r, return_pool=True)
+    out, pool, pc = fic.encode_level(x, B, L, ks, entropy, bits, min_pool, ranges=r, return_pool=True,
+                                     variant=variant)
     torch.cuda.synchronize()
     return fic.matches_numpy(out), pool.cpu().numpy()[:int(pc.item())]
 
@@ -44,9 +46,11 @@ def assert_level_equal(got, ref, B):
     assert np.allclose(got["E"], E_ref, rtol=1e-6, atol=1e-6)
 
 
-def check_level(dev, img, B, L, ks, entropy=0, min_pool=256, ranges=None, bits=2.5):
-    say(f"[level] shape={img.shape} B={B} L={L} ks={ks} entropy={entropy} min_pool={min_pool}")
-    got, gpool = gpu_level(dev, img, B, L, ks, entropy, bits, min_pool, ranges)
+def check_level(dev, img, B, L, ks, entropy=0, min_pool=256, ranges=None, bits=2.5,
+                variant=fic.MATCH_AUTO):
+    say(f"[level] shape={img.shape} B={B} L={L} ks={ks} entropy={entropy} min_pool={min_pool} "
+        f"variant={variant}")
+    got, gpool = gpu_level(dev, img, B, L, ks, entropy, bits, min_pool, ranges, variant)
     if entropy:
         pool, _ = oracle.entropy_pool(img, B, L, bits, min_pool)
         assert np.array_equal(gpool, pool)
@@ -250,3 +254,87 @@ def test_precision_workload_sampled(dev):
     ranges = oracle.full_ranges(1024, 1024, 8)[idx]
     ref = oracle.match_level(img, 8, 2, oracle.PLAIN_K, None, ranges)
     assert_level_equal(got[idx], ref, 8)
+
+
+# ------------------------------------------------------------------ precision form (B = 8)
+@pytest.mark.parametrize("variant", [fic.MATCH_VALU, fic.MATCH_MFMA_I8])
+def test_single_level_workload_variants(dev, variant):
+    img = synth.single_level_image(0)
+    check_level(dev, img, 8, 4, oracle.PLAIN_K, variant=variant)
+
+
+@pytest.mark.parametrize("kind", ["constant", "replicated", "noise", "two_tone", "blobs", "copy"])
+@pytest.mark.parametrize("ks", [oracle.PLAIN_K, (0, 1, 2), (0, 1, 2, 3, 4, 5)])
+def test_mfma_exact_on_adversarial(dev, kind, ks):
+    rng = np.random.default_rng(11)
+    if kind == "constant":
+        img = np.full((72, 88), 201, np.uint8)
+    elif kind == "replicated":
+        img = np.kron(rng.integers(0, 256, size=(36, 44)), np.ones((2, 2))).astype(np.uint8)
+    elif kind == "noise":
+        img = rng.integers(0, 256, size=(72, 88)).astype(np.uint8)
+    elif kind == "two_tone":
+        img = (rng.integers(0, 2, size=(72, 88)) * 255).astype(np.uint8)
+    elif kind == "blobs":
+        img = synth.gradients_blobs(88, seed=3)[:72]
+    else:
+        img = rng.integers(0, 256, size=(72, 88)).astype(np.int64)
+        m = rng.integers(0, 26, size=(8, 8))
+        img[40:56, 56:72] = np.kron(10 * m, np.ones((2, 2), dtype=np.int64))
+        img[0:8, 8:16] = 10 * np.fliplr(np.rot90(m, -1)) + 5
+        img = img.astype(np.uint8)
+    for L in (1, 3):
+        check_level(dev, img, 8, L, ks, variant=fic.MATCH_MFMA_I8)
+
+
+def test_mfma_ragged_ranges_and_pool(dev):
+    img = synth.power_law(120, 136, beta=1.8, seed=9)
+    rng = np.random.default_rng(2)
+    corners = oracle.full_ranges(120, 136, 8)
+    sub = corners[np.sort(rng.choice(len(corners), 37, replace=False))]
+    check_level(dev, img, 8, 5, oracle.PLAIN_K, ranges=sub, variant=fic.MATCH_MFMA_I8)
+    check_level(dev, img, 8, 2, oracle.PLAIN_K, entropy=1, min_pool=300, variant=fic.MATCH_MFMA_I8)
+
+
+def test_mfma_in_quadtree_unfiltered(dev):
+    img = synth.power_law(96, beta=2.0, seed=5, n_rect=2)
+    say("[quadtree] plain grid, MFMA level")
+    _, _, got, _ = gpu_image(dev, img, fic.EncoderParams(s_sets=(oracle.PLAIN_K,) * 4,
+                                                         entropy_mode=0))
+    ref, _ = oracle.encode_image(img, s_sets=(oracle.PLAIN_K,) * 4, entropy=False)
+    assert_codes_equal(got, ref)
+
+
+def test_precision_workload_mfma_sampled(dev):
+    """1024x1024 1/f^1.8, 8x8 ranges, step 2: int8 MFMA over the whole image,
+    a deterministic sample of ranges through the oracle."""
+    img = synth.precision_image(0)
+    say("[level] 1024 precision workload, MFMA")
+    got, _ = gpu_level(dev, img, 8, 2, oracle.PLAIN_K, variant=fic.MATCH_MFMA_I8)
+    valu, _ = gpu_level(dev, img, 8, 2, oracle.PLAIN_K, variant=fic.MATCH_VALU)
+    for f in ("e_num", "dom", "iso", "k", "q_o"):
+        assert np.array_equal(got[f], valu[f]), f
+    idx = np.arange(0, 16384, 1301)[:12]
+    ranges = oracle.full_ranges(1024, 1024, 8)[idx]
+    ref = oracle.match_level(img, 8, 2, oracle.PLAIN_K, None, ranges)
+    assert_level_equal(got[idx], ref, 8)
+
+
+def test_fp32_comparator_error_is_reported(dev):
+    """The FP32 comparator: its e_num is the exact value of the candidate it picked,
+    never below the exact optimum; its FP32 E is close to that exact value."""
+    img = synth.single_level_image(0)
+    say("[level] FP32 comparator")
+    f32, _ = gpu_level(dev, img, 8, 4, oracle.PLAIN_K, variant=fic.MATCH_FP32)
+    ref = oracle.match_level(img, 8, 4, oracle.PLAIN_K)
+    n = 64
+    exact_pick = f32["e_num"] * n
+    assert np.all(exact_pick >= ref["e_lit"])
+    E_exact = ref["e_lit"] / (40.0 * n) ** 2
+    E_pick = f32["e_num"] / (1600.0 * n)
+    same = (f32["dom"] == ref["dom"]) & (f32["iso"] == ref["iso"]) & (f32["k"] == ref["k"])
+    rel = np.abs(f32["E"] - E_pick) / np.maximum(E_pick, 1.0)
+    say(f"[fp32] argmin agrees on {same.mean():.4f} of ranges; max rel E error "
+        f"{rel.max():.3e}; max E excess {np.max(E_pick - E_exact):.3e}")
+    assert same.mean() > 0.9
+    assert np.all(E_pick - E_exact <= 1e-3 * np.maximum(E_exact, 1.0) + 1.0)
