@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="quadtree512",
-                    choices=["quadtree512", "single128", "precision1024"])
+                    choices=["quadtree512", "single128", "precision1024", "batch64"])
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines autotune cache for batch64 (default: none, always tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
     ap.add_argument("--preset", default="calibrated", choices=["calibrated", "paper"])
@@ -168,6 +170,70 @@ def run_quadtree(args, torch):
     return res
 
 
+def run_batch(args, torch):
+    import numpy as np
+
+    from paper_1501_04140_amd import fic, synth
+
+    imgs = synth.batch_images(64)
+    xs = [torch.from_numpy(im).cuda() for im in imgs]
+    params = fic.EncoderParams(s_sets=fic.PAPER_K)
+    b = fic.Batch(xs, params)
+    tune_ms = b.autotune(reps=2, cache_path=args.tune_cache)
+    b.run()
+    torch.cuda.synchronize()
+    st = np.stack([fic.stats_numpy(b.stats[i]) for i in range(len(xs))])
+    matches_lv = st["matches"].sum(0)
+    matches = int(matches_lv.sum())
+    ms, wall_ms = time_steps(lambda: b.run(), args.steps, args.warmup, torch)
+    # the graph's kernels queued one by one, with HIP events around each launch
+    fic.profile_begin()
+    for _ in range(args.steps):
+        b.run_eager()
+    torch.cuda.synchronize()
+    prof = fic.profile_end()
+    per_label = {f"match_b{B}": int(matches_lv[lv]) * match_ops(B * B, len(params.s_sets[lv]))
+                 for lv, B in enumerate(params.levels)}
+    roof = roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")}, per_label)
+    eager_ms = sum(v[1] for v in prof.values()) / args.steps
+    sides = [int(im.shape[0]) for im in imgs]
+    res = {
+        "metric": "matches/s (range×domain×isometry), 64-image batch",
+        "value": matches / (ms / 1e3), "unit": "matches/s", "encode_ms": ms,
+        "encode_ms_wall": wall_ms, "images_per_s": len(xs) / (ms / 1e3),
+        "matches_per_step": matches, "autotune_ms": tune_ms,
+        "config": {"workload": "batch64: 64 1/f^beta images, beta~U[1.5,2.5], sides from "
+                               "{256,384,512,768,1024,2048} (seeded), paper's method, one hipGraph",
+                   "sides": {str(v): sides.count(v) for v in sorted(set(sides))},
+                   "pixels": int(sum(v * v for v in sides)), "chunks": b.chunks(),
+                   "s_k": [list(s) for s in params.s_sets],
+                   "matches_per_level": [int(v) for v in matches_lv]},
+        "roofline": roof,
+        "kernel_ms_per_step_eager": {k: v[1] / args.steps for k, v in sorted(
+            prof.items(), key=lambda kv: -kv[1][1])},
+        "eager_kernel_sum_ms": eager_ms,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        order = np.argsort(sides, kind="stable")
+        om, dt, done = 0, 0.0, []
+        for i in order:
+            if dt > 10.0:
+                break
+            t0 = time.perf_counter()
+            _, ost = oracle.encode_image(imgs[i], s_sets=params.s_sets)
+            dt += time.perf_counter() - t0
+            om += sum(s["matches"] for s in ost)
+            done.append(sides[i])
+        res["cpu_baseline"] = {"value": om / dt, "unit": "matches/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "seconds": dt,
+                               "sample": f"whole encodes of {len(done)} of the 64 images "
+                                         f"(smallest first, sides {done})"}
+    b.close()
+    return res
+
+
 def run_level(args, torch, which):
     from paper_1501_04140_amd import fic, synth
 
@@ -230,6 +296,8 @@ def main():
     fic.load()
     if args.workload == "quadtree512":
         res = run_quadtree(args, torch)
+    elif args.workload == "batch64":
+        res = run_batch(args, torch)
     else:
         res = run_level(args, torch, args.workload)
     line = {

@@ -244,6 +244,57 @@ typedef struct {
 int fic_profile_begin(void);
 int fic_profile_end(fic_kernel_time* out, int32_t max, int32_t* n_out);
 
+/*
+ * Batched quadtree encoder. It encodes n images of possibly different sizes
+ * with the same parameters. Every level of every image runs in shared kernel
+ * launches, which are captured once into a hipGraph; fic_batch_run replays
+ * that graph.
+ *
+ * imgs, H, W, pitch  [host] arrays of n: device image pointers and their
+ *                    shapes, as in fic_encode_image. The images must stay
+ *                    valid and at the same addresses while the batch exists.
+ * codes, code_offset codes is a device buffer. code_offset is a [host] array
+ *                    of n+1 entries: image i writes its codes to
+ *                    codes[code_offset[i] .. code_offset[i+1]). Each range
+ *                    must hold at least (H/B0)*(W/B0) codes (FIC_ECAPACITY).
+ * n_codes            device int32[n]: codes needed per image, as in
+ *                    fic_encode_image.
+ * stats              optional device fic_level_stats[n * p->n_levels].
+ * The batch owns one workspace per image and a private stream for capture.
+ * Replays on one batch must not overlap. Only the device memory is per call.
+ */
+typedef struct fic_batch fic_batch;
+int fic_batch_create(int32_t n, const uint8_t* const* imgs, const int32_t* H, const int32_t* W,
+                     const int32_t* pitch, const fic_params* p, fic_code* codes,
+                     const int64_t* code_offset, int32_t* n_codes, fic_level_stats* stats,
+                     fic_batch** out);
+/* Replay the captured encode on `stream` (asynchronous). */
+int fic_batch_run(fic_batch* b, void* stream);
+/*
+ * The same kernels with the same launch shapes, queued one by one on
+ * `stream` instead of through the graph (asynchronous). Used to time each
+ * kernel between fic_profile_begin and fic_profile_end.
+ */
+int fic_batch_run_eager(fic_batch* b, void* stream);
+/*
+ * Tile shape of the batch: pool domains per matcher chunk for each level
+ * ([host] p->n_levels values, 0 = the library default). Set it directly, or
+ * let fic_batch_autotune choose it.
+ */
+int fic_batch_set_chunks(fic_batch* b, const int32_t* chunks);
+int fic_batch_get_chunks(const fic_batch* b, int32_t* chunks);
+/*
+ * Autotuner: coordinate descent over each level's chunk size, timing `reps`
+ * graph replays on `stream` per candidate, then keeping the fastest.
+ * The choice is cached in cache_path (JSON lines; may be NULL), keyed by GPU
+ * architecture, HIP runtime version, image sizes and parameters. A cached
+ * entry is applied without tuning. *best_ms (may be NULL) receives the mean
+ * replay time. Synchronises `stream`.
+ */
+int fic_batch_autotune(fic_batch* b, void* stream, int32_t reps, const char* cache_path,
+                       float* best_ms);
+int fic_batch_destroy(fic_batch* b);
+
 /* Message for the last non-zero return on this thread. */
 const char* fic_last_error(void);
 

@@ -46,4 +46,46 @@ struct Partial {
     int64_t key;  // (domain << 8) | (iso << 4) | contrast index
 };
 
+// Arguments of the quadtree kernels for one image at one level. Kernels read
+// tab[blockIdx.z]: a table of one for a single image, one entry per image for
+// a batch.
+struct Lvl {
+    const uint8_t* img;
+    int32_t pitch, H, W;
+    int32_t B, L, gx, gy, total;  // domain grid
+    int32_t max_act;              // worst-case active ranges
+    int32_t lv, last;             // quadtree level; 1 on the last level
+    int32_t nc, cg;               // matcher: pool chunks launched, domains per chunk
+    int32_t min_pool, rank;       // entropy floor: pool size wanted, min(min_pool, total)
+    int32_t sel_shift, bound_chunk;
+    int32_t capacity;
+    int32_t var;                  // matcher: 1 dot4 VALU, 2 int8 MFMA, 3 FP32 comparator
+    int64_t M;                    // entropy cut (keep iff key < M)
+    int64_t thr;                  // keep iff 1600 n E <= thr
+    Ctrl* ctrl;
+    int64_t* key;
+    int32_t* pool;
+    uint32_t* hl;
+    uint32_t* sd;
+    int64_t* ad;
+    int32_t* jd;
+    Partial* part;
+    int32_t* sr;
+    int64_t* cr;
+    int32_t* act;
+    int32_t* act_next;
+    fic_code* tmpc;
+    uint8_t* dec;
+    int2* blk;
+    fic_code* codes;
+    fic_level_stats* stats;
+    int8_t* ar;  // int8 MFMA matcher (B = 8)
+    int32_t* srp;
+    int8_t* dh;
+    int8_t* dl;
+    float* gd;
+    float* af;
+    KSet ks;
+};
+
 }  // namespace fic

@@ -51,13 +51,14 @@ __device__ inline T ld_agent(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// True in the workgroup that finishes last (self-resetting ticket).
-__device__ inline bool last_workgroup(uint32_t* ticket) {
+// True in the last of `nblocks` participating workgroups to get here
+// (self-resetting ticket).
+__device__ inline bool last_workgroup(uint32_t* ticket, int nblocks) {
     __shared__ int s_last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        s_last = atomicAdd(ticket, 1u) == gridDim.x * gridDim.y - 1;
+        s_last = atomicAdd(ticket, 1u) == (uint32_t)nblocks - 1;
         if (s_last) *ticket = 0u;
     }
     __syncthreads();
@@ -68,7 +69,7 @@ __device__ inline bool last_workgroup(uint32_t* ticket) {
 // ---------------------------------------------------------------- active range lists
 // Packed corner: (y << 16) | x. Block 0 also sets the level's active count
 // and, when asked, clears the code counter of a new quadtree.
-__global__ void k_act_full(int32_t* act, int gy, int gx, int B, Ctrl* ctrl, int lv, int reset) {
+__device__ inline void k_act_full_body(int32_t* act, int gy, int gx, int B, Ctrl* ctrl, int lv, int reset) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) {
         ctrl->act_count[lv] = gy * gx;
@@ -83,7 +84,7 @@ __global__ void k_act_full(int32_t* act, int gy, int gx, int B, Ctrl* ctrl, int 
 }
 
 // Caller-supplied corners; an invalid corner is stored as -1.
-__global__ void k_act_from_yx(int32_t* act, const int32_t* yx, int n, int H, int W, int B,
+__device__ inline void k_act_from_yx_body(int32_t* act, const int32_t* yx, int n, int H, int W, int B,
                               Ctrl* ctrl) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) ctrl->act_count[0] = n;
@@ -108,7 +109,7 @@ struct ScoreShape {
 };
 
 template <int SIDE>
-__global__ __launch_bounds__(kBlock) void k_pool_score(const uint8_t* __restrict__ img, int pitch,
+__device__ inline void k_pool_score_body(const uint8_t* __restrict__ img, int pitch,
                                                        int L, int gx, int total,
                                                        const int64_t* __restrict__ T, int64_t M,
                                                        int64_t* __restrict__ key, Ctrl* ctrl) {
@@ -165,7 +166,7 @@ __device__ inline int pool_mode(int passed, int total, int min_pool) {
 // bucket of key >> shift (shift puts every key below 2^(shift+12)) holding its
 // own r-th smallest key. The chunk alone has r keys not above that bucket's
 // largest key, so the global r-th smallest key is not above it either.
-__global__ __launch_bounds__(kBlock) void k_floor_bound(const int64_t* __restrict__ key, int total,
+__device__ inline void k_floor_bound_body(const int64_t* __restrict__ key, int total,
                                                         int min_pool, int r, int shift, int chunk,
                                                         Ctrl* ctrl) {
     if (pool_mode(ctrl->pass_count, total, min_pool) != 1) return;
@@ -318,7 +319,7 @@ __device__ inline void publish_count(int2* blk, int t0, int t1) {
 
 // Pool compaction, pass 1: per-workgroup counts; the last workgroup scans them
 // and sets pool_count (the pool, or the floor candidates).
-__global__ __launch_bounds__(kBlock) void k_pool_count(CompactArgs a, Ctrl* ctrl, int2* blk) {
+__device__ inline void k_pool_count_body(CompactArgs a, Ctrl* ctrl, int2* blk, int nblk) {
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
     const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
     int c0 = 0;
@@ -330,14 +331,14 @@ __global__ __launch_bounds__(kBlock) void k_pool_count(CompactArgs a, Ctrl* ctrl
     int e0, e1, t0, t1;
     block_scan2(c0, 0, e0, e1, t0, t1);
     publish_count(blk, t0, t1);
-    if (!last_workgroup(&ctrl->ticket)) return;
+    if (!last_workgroup(&ctrl->ticket, nblk)) return;
     int tot0, tot1;
-    scan_block_counts(blk, gridDim.x, tot0, tot1);
+    scan_block_counts(blk, nblk, tot0, tot1);
     if (threadIdx.x == 0) ctrl->pool_count = tot0;
 }
 
 // Pool compaction, pass 2: kept domains in ascending index order.
-__global__ __launch_bounds__(kBlock) void k_pool_scatter(CompactArgs a, const Ctrl* ctrl,
+__device__ inline void k_pool_scatter_body(CompactArgs a, const Ctrl* ctrl,
                                                          const int2* blk, int32_t* pool_out) {
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
     const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_pool_scatter(CompactArgs a, const Ct
 // among the candidates, then in-place compaction to the keys below it plus the
 // first ties in index order. Always launched: it also publishes the number of
 // domains that passed the threshold and clears the per-level counters.
-__global__ __launch_bounds__(1024) void k_floor_select(const int64_t* __restrict__ key, int total,
+__device__ inline void k_floor_select_body(const int64_t* __restrict__ key, int total,
                                                        int min_pool, int r,
                                                        int32_t* __restrict__ pool, Ctrl* ctrl) {
     __shared__ uint32_t h[kSelBins];
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(1024) void k_floor_select(const int64_t* __restrict
 
 // Quadtree compaction: kept leaves to the code list (after code_base), the
 // four children of each split range to the next active list, in order.
-__global__ __launch_bounds__(kBlock) void k_quad_scatter(CompactArgs a, const Ctrl* ctrl,
+__device__ inline void k_quad_scatter_body(CompactArgs a, const Ctrl* ctrl,
                                                          const int2* blk, const fic_code* tmp_codes,
                                                          fic_code* codes, int capacity,
                                                          const int32_t* act, int32_t* act_next,
@@ -535,7 +536,7 @@ struct PrepShape {
 };
 
 template <int B>
-__global__ __launch_bounds__(kBlock) void k_pool_prep(const uint8_t* __restrict__ img, int pitch,
+__device__ inline void k_pool_prep_body(const uint8_t* __restrict__ img, int pitch,
                                                       int L, int gx, const int32_t* __restrict__ pool,
                                                       int identity_total, Ctrl* ctrl,
                                                       uint32_t* __restrict__ HL,
@@ -664,7 +665,7 @@ __device__ inline int active_chunks(int P, int TN, int n_chunks) {
 //  kModeGrid: consecutive k0..k1, closed-form minimiser, exact in int64.
 //  kModeList: any set, every value evaluated in int64.
 template <int B, int MODE>
-__global__ __launch_bounds__(kBlock) void k_match(const uint8_t* __restrict__ img, int pitch,
+__device__ inline void k_match_body(const uint8_t* __restrict__ img, int pitch,
                                                   const int32_t* __restrict__ act,
                                                   const int32_t* act_count,
                                                   const uint32_t* __restrict__ HL,
@@ -673,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_match(const uint8_t* __restrict__ im
                                                   const int32_t* __restrict__ Jd, const Ctrl* ctrl,
                                                   KSet ks, int n_chunks, Partial* __restrict__ part,
                                                   int32_t* __restrict__ SRout,
-                                                  int64_t* __restrict__ CRout) {
+                                                  int64_t* __restrict__ CRout, int cg) {
     using Tl = MatchTile<B>;
     using BpT = typename Tl::BpT;
     using GT = typename Tl::GT;
@@ -690,8 +691,8 @@ __global__ __launch_bounds__(kBlock) void k_match(const uint8_t* __restrict__ im
     if (q0 >= nact) return;
     const int P = ctrl->pool_count;
     const int c = blockIdx.y;
-    if (c >= active_chunks(P, Tl::CG, n_chunks)) return;
-    const int nca = active_chunks(P, Tl::CG, n_chunks);
+    if (c >= active_chunks(P, cg, n_chunks)) return;
+    const int nca = active_chunks(P, cg, n_chunks);
 
     for (int e = threadIdx.x; e < RPB * n; e += kBlock) {
         const int lq = e / n, m = e % n, q = q0 + lq;
@@ -886,7 +887,7 @@ __device__ inline bool finish_range(int yx, int B, int L, int gx, const Partial*
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_level(int B, int L, int gx,
+__device__ inline void k_reduce_level_body(int B, int L, int gx,
                                                          const int32_t* __restrict__ act,
                                                          const int32_t* act_count,
                                                          const Partial* __restrict__ part,
@@ -907,11 +908,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_level(int B, int L, int gx,
 // range, kQuadItems consecutive ranges per thread. Per-workgroup counts of
 // kept and split ranges go to blk; the last workgroup scans them, advances the
 // code counter and sets the next level's active count (4 children per split).
-__global__ __launch_bounds__(kBlock) void k_reduce_quad(
+__device__ inline void k_reduce_quad_body(
     int B, int L, int gx, int lv, int last, int64_t thr, const int32_t* __restrict__ act,
     Ctrl* ctrl, const Partial* __restrict__ part, int n_chunks, int CG,
     const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, KSet ks,
-    fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk, fic_level_stats* stats) {
+    fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk, fic_level_stats* stats,
+    int nblk) {
     const int base = blockIdx.x * kBlock * kQuadItems + threadIdx.x * kQuadItems;
     const int nact = ctrl->act_count[lv];
     const int nca = active_chunks(ctrl->pool_count, CG, n_chunks);
@@ -950,9 +952,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_quad(
     int e0, e1, t0, t1;
     block_scan2(kept, split, e0, e1, t0, t1);
     publish_count(blk, t0, t1);
-    if (!last_workgroup(&ctrl->ticket)) return;
+    if (!last_workgroup(&ctrl->ticket, nblk)) return;
     int tot0, tot1;
-    scan_block_counts(blk, gridDim.x, tot0, tot1);
+    scan_block_counts(blk, nblk, tot0, tot1);
     if (threadIdx.x == 0) {
         const int pool = ctrl->pool_count;
         ctrl->code_base = ctrl->n_codes;
@@ -1069,16 +1071,6 @@ __global__ void k_calib_accum(const uint8_t* __restrict__ img, int pitch,
     }
 }
 
-// ---------------------------------------------------------------- launch helpers
-// Domains per pool chunk of the matcher (see active_chunks).
-int match_chunk_domains(int B) {
-    switch (B) {
-        case 2: return MatchTile<2>::CG;
-        case 4: return MatchTile<4>::CG;
-        case 8: return MatchTile<8>::CG;
-        default: return MatchTile<16>::CG;
-    }
-}
 
 
 // ================================================================ int8 MFMA matcher (B = 8)
@@ -1102,7 +1094,7 @@ constexpr int kM8Chunk = 1024;                         // target pool domains pe
 
 // Rows r' = r - 128 of the 8 inverse-isometry arrangements of each range:
 // Ar[(8q + t) * 64 + m] = R[iso_src(8, inverse(t), m)] - 128. Thread per row.
-__global__ __launch_bounds__(kBlock) void k_range_prep_i8(const uint8_t* __restrict__ img, int pitch,
+__device__ inline void k_range_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
                                                           const int32_t* __restrict__ act,
                                                           const int32_t* act_count,
                                                           int8_t* __restrict__ Ar,
@@ -1157,7 +1149,7 @@ __global__ __launch_bounds__(kBlock) void k_range_prep_i8(const uint8_t* __restr
 // Columns for the int8 matcher: h and l rows of each pool domain, and
 // G = 40 / A' (0 for a constant domain) and A' in FP32 for the screen. Four
 // lanes share a domain, 16 decimated values each.
-__global__ __launch_bounds__(kBlock) void k_pool_prep_i8(const uint8_t* __restrict__ img, int pitch,
+__device__ inline void k_pool_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
                                                          int L, int gx, const int32_t* __restrict__ pool,
                                                          int identity_total, Ctrl* ctrl,
                                                          int8_t* __restrict__ Dh, int8_t* __restrict__ Dl,
@@ -1246,12 +1238,12 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
 constexpr float kM8ScreenMargin = 1.0e6f;
 constexpr int kM8Share = 4;
 
-__global__ __launch_bounds__(kM8Waves * 64) void k_match_mfma8(
+__device__ inline void k_match_mfma8_body(
     const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int32_t* act_count,
     const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
     const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Af,
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
-    Partial* __restrict__ part) {
+    Partial* __restrict__ part, int cg) {
     __shared__ v4i sH[kM8Cols * 4];  // column c, K-group g at [c * 4 + g]
     __shared__ v4i sL[kM8Cols * 4];
     __shared__ float sG[kM8Cols], sAf[kM8Cols];
@@ -1262,7 +1254,7 @@ __global__ __launch_bounds__(kM8Waves * 64) void k_match_mfma8(
     const int row_blk = blockIdx.x * kM8Rows;
     if (row_blk >= nrows) return;
     const int P = ctrl->pool_count;
-    const int nca = active_chunks(P, kM8Chunk, n_chunks);
+    const int nca = active_chunks(P, cg, n_chunks);
     const int c = blockIdx.y;
     if (c >= nca) return;
     const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
@@ -1438,13 +1430,13 @@ __device__ inline float float_from_ordered(int64_t o) {
 
 constexpr int kF32Tile = 64;  // domains per LDS stage
 
-__global__ __launch_bounds__(kBlock) void k_match_fp32(const uint8_t* __restrict__ img, int pitch,
+__device__ inline void k_match_fp32_body(const uint8_t* __restrict__ img, int pitch,
                                                        const int32_t* __restrict__ act,
                                                        const int32_t* act_count,
                                                        const uint8_t* __restrict__ DDimg, int L,
                                                        int gx, const int32_t* __restrict__ Jd,
                                                        const Ctrl* ctrl, int k1, int n_chunks,
-                                                       Partial* __restrict__ part) {
+                                                       Partial* __restrict__ part, int cg) {
     constexpr int B = 8, n = 64, RPB = kBlock / 8;
     __shared__ float sD[kF32Tile * n];
     __shared__ float sS[kF32Tile], sA[kF32Tile];
@@ -1453,7 +1445,7 @@ __global__ __launch_bounds__(kBlock) void k_match_fp32(const uint8_t* __restrict
     const int q0 = blockIdx.x * RPB;
     if (q0 >= nact) return;
     const int P = ctrl->pool_count;
-    const int nca = active_chunks(P, 256, n_chunks);
+    const int nca = active_chunks(P, cg, n_chunks);
     const int c = blockIdx.y;
     if (c >= nca) return;
     const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
@@ -1537,16 +1529,16 @@ __global__ __launch_bounds__(kBlock) void k_match_fp32(const uint8_t* __restrict
 
 // Result of the FP32 comparator: its own argmin and FP32 E, plus the exact
 // e_num of the candidate it chose (recomputed in integers for reporting).
-__global__ __launch_bounds__(kBlock) void k_reduce_fp32(const uint8_t* __restrict__ img, int pitch,
+__device__ inline void k_reduce_fp32_body(const uint8_t* __restrict__ img, int pitch,
                                                         int L, int gx, const int32_t* __restrict__ act,
                                                         const int32_t* act_count,
                                                         const Partial* __restrict__ part,
-                                                        int n_chunks, const Ctrl* ctrl,
+                                                        int n_chunks, int cg, const Ctrl* ctrl,
                                                         fic_match* __restrict__ out) {
     constexpr int B = 8, n = 64;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= *act_count) return;
-    const int nca = active_chunks(ctrl->pool_count, 256, n_chunks);
+    const int nca = active_chunks(ctrl->pool_count, cg, n_chunks);
     int64_t F = INT64_MAX, K = INT64_MAX;
     for (int c = 0; c < nca; ++c)
         if (pair_less(part[(int64_t)q * n_chunks + c].F, part[(int64_t)q * n_chunks + c].key, F, K)) {
@@ -1592,5 +1584,148 @@ __global__ __launch_bounds__(kBlock) void k_reduce_fp32(const uint8_t* __restric
     m.E = (float_from_ordered(F) + 1600.0f * (float)C) / (1600.0f * (float)n);
     out[q] = m;
 }
+
+
+// ================================================================ table-driven launches
+// Every quadtree kernel reads its image's arguments from tab[blockIdx.z] (a
+// batch) or, when tab is NULL, from the by-value a0 (one image). Workgroups
+// beyond an image's own grid return at once.
+#define FIC_LV const Lvl& a = tab ? tab[blockIdx.z] : a0
+
+// Default matcher chunk (domains per pool chunk) for a level.
+int match_chunk_domains(int B) {
+    switch (B) {
+        case 2: return MatchTile<2>::CG;
+        case 4: return MatchTile<4>::CG;
+        case 8: return MatchTile<8>::CG;
+        default: return MatchTile<16>::CG;
+    }
+}
+
+__global__ void kt_act_full(Lvl a0, const Lvl* __restrict__ tab, int reset) {
+    FIC_LV;
+    k_act_full_body(a.act, a.H / a.B, a.W / a.B, a.B, a.ctrl, a.lv, reset);
+}
+
+__global__ void kt_act_from_yx(Lvl a0, const Lvl* __restrict__ tab, const int32_t* yx, int n) {
+    FIC_LV;
+    k_act_from_yx_body(a.act, yx, n, a.H, a.W, a.B, a.ctrl);
+}
+
+template <int SIDE>
+__global__ __launch_bounds__(kBlock) void kt_pool_score(Lvl a0, const Lvl* __restrict__ tab,
+                                                        const int64_t* __restrict__ T) {
+    FIC_LV;
+    if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * ScoreShape<SIDE>::TPD) return;
+    k_pool_score_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, T, a.M, a.key, a.ctrl);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_floor_bound(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    k_floor_bound_body(a.key, a.total, a.min_pool, a.rank, a.sel_shift, a.bound_chunk, a.ctrl);
+}
+
+__device__ inline CompactArgs pool_args(const Lvl& a) {
+    CompactArgs c{};
+    c.kind = 0;
+    c.total = a.total;
+    c.min_pool = a.min_pool;
+    c.M = a.M;
+    c.key = a.key;
+    return c;
+}
+
+__global__ __launch_bounds__(kBlock) void kt_pool_count(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
+    if ((int)blockIdx.x >= nblk) return;
+    k_pool_count_body(pool_args(a), a.ctrl, a.blk, nblk);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_pool_scatter(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
+    if ((int)blockIdx.x >= nblk) return;
+    k_pool_scatter_body(pool_args(a), a.ctrl, a.blk, a.pool);
+}
+
+__global__ __launch_bounds__(1024) void kt_floor_select(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.ctrl);
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void kt_pool_prep(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
+    FIC_LV;
+    if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * PrepShape<B>::TPD) return;
+    k_pool_prep_body<B>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.ctrl, a.hl,
+                        a.sd, a.ad, a.jd);
+}
+
+template <int B, int MODE>
+__global__ __launch_bounds__(kBlock) void kt_match(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    k_match_body<B, MODE>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.hl, a.sd, a.ad, a.jd,
+                          a.ctrl, a.ks, a.nc, a.part, a.sr, a.cr, a.cg);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_pool_prep_i8(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
+    FIC_LV;
+    if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * 4) return;
+    k_pool_prep_i8_body(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.ctrl, a.dh,
+                        a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_range_prep_i8(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    k_range_prep_i8_body(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
+}
+
+__global__ __launch_bounds__(kM8Waves * 64) void kt_match_mfma8(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    k_match_mfma8_body(a.ar, a.srp, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
+                       a.jd, a.ctrl, a.ks.k1, a.nc, a.part, a.cg);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_match_fp32(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    k_match_fp32_body(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.img, a.L, a.gx, a.jd,
+                      a.ctrl, a.ks.k1, a.nc, a.part, a.cg);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_reduce_level(Lvl a0, const Lvl* __restrict__ tab,
+                                                          fic_match* __restrict__ out) {
+    FIC_LV;
+    k_reduce_level_body(a.B, a.L, a.gx, a.act, a.ctrl->act_count + a.lv, a.part, a.nc, a.cg,
+                        a.ctrl, a.cr, a.sr, a.ks, out);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_reduce_fp32(Lvl a0, const Lvl* __restrict__ tab,
+                                                         fic_match* __restrict__ out) {
+    FIC_LV;
+    k_reduce_fp32_body(a.img, a.pitch, a.L, a.gx, a.act, a.ctrl->act_count + a.lv, a.part, a.nc,
+                       a.cg, a.ctrl, out);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_reduce_quad(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    const int nblk = (a.max_act + kBlock * kQuadItems - 1) / (kBlock * kQuadItems);
+    if ((int)blockIdx.x >= nblk) return;
+    k_reduce_quad_body(a.B, a.L, a.gx, a.lv, a.last, a.thr, a.act, a.ctrl, a.part, a.nc, a.cg, a.cr,
+                       a.sr, a.ks, a.tmpc, a.dec, a.blk, a.stats, nblk);
+}
+
+__global__ __launch_bounds__(kBlock) void kt_quad_scatter(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    const int nblk = (a.max_act + kBlock * kQuadItems - 1) / (kBlock * kQuadItems);
+    if ((int)blockIdx.x >= nblk) return;
+    CompactArgs c{};
+    c.kind = 1;
+    c.act_count = a.ctrl->act_count + a.lv;
+    c.decision = a.dec;
+    k_quad_scatter_body(c, a.ctrl, a.blk, a.tmpc, a.codes, a.capacity, a.act, a.act_next, a.B / 2);
+}
+
+#undef FIC_LV
 
 }  // namespace fic

@@ -63,6 +63,7 @@ struct Workspace {
     Buf key, pool, hl, sd, ad, jd, arow, sr, cr, part, blk, act0, act1, tmpc, dec, codes, map,
         imgA, imgB, acc, mr;
     Buf ar, srp, dh, dl, wd, cw;  // int8 MFMA matcher (B = 8)
+
 };
 
 std::mutex g_mu;
@@ -85,15 +86,8 @@ int64_t entropy_cut(int nw, double theta) {
     return llround(v);
 }
 
-int get_ws(hipStream_t s, Workspace** out) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_ws.find({dev, s});
-    if (it != g_ws.end()) {
-        *out = it->second;
-        return FIC_OK;
-    }
+// A new workspace bound to stream s: control block and entropy table.
+int new_ws(int dev, hipStream_t s, Workspace** out) {
     Workspace* ws = new Workspace();
     ws->device = dev;
     ws->stream = s;
@@ -107,17 +101,42 @@ int get_ws(hipStream_t s, Workspace** out) {
         return fail(FIC_ENOMEM, "hipMalloc of the entropy table failed");
     }
     const std::vector<int64_t>& t = entropy_table();
-    HIP_TRY(hipMemcpyAsync(ws->T, t.data(), sizeof(int64_t) * t.size(), hipMemcpyHostToDevice, s));
-    {
-        static Ctrl init;  // zero counters, empty histogram, no floor bound yet
-        std::memset(&init, 0, sizeof init);
-        init.cut_bound = ~0ull;
-        HIP_TRY(hipMemcpyAsync(ws->ctrl, &init, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpy(ws->T, t.data(), sizeof(int64_t) * t.size(), hipMemcpyHostToDevice));
+    Ctrl init;  // zero counters, empty histogram, no floor bound yet
+    std::memset(&init, 0, sizeof init);
+    init.cut_bound = ~0ull;
+    HIP_TRY(hipMemcpy(ws->ctrl, &init, sizeof(Ctrl), hipMemcpyHostToDevice));
+    *out = ws;
+    return FIC_OK;
+}
+
+int get_ws(hipStream_t s, Workspace** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find({dev, s});
+    if (it != g_ws.end()) {
+        *out = it->second;
+        return FIC_OK;
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    Workspace* ws;
+    int rc = new_ws(dev, s, &ws);
+    if (rc) return rc;
     g_ws[{dev, s}] = ws;
     *out = ws;
     return FIC_OK;
+}
+
+void free_ws(Workspace* ws) {
+    Buf* bufs[] = {&ws->key, &ws->pool, &ws->hl, &ws->sd, &ws->ad, &ws->jd, &ws->arow, &ws->sr,
+                   &ws->cr, &ws->part, &ws->blk, &ws->act0, &ws->act1, &ws->tmpc, &ws->dec,
+                   &ws->codes, &ws->map, &ws->imgA, &ws->imgB, &ws->acc, &ws->mr, &ws->ar,
+                   &ws->srp, &ws->dh, &ws->dl, &ws->wd, &ws->cw};
+    for (Buf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    (void)hipFree(ws->ctrl);
+    (void)hipFree(ws->T);
+    delete ws;
 }
 
 int ensure(Workspace& ws, Buf& b, size_t bytes) {
@@ -174,6 +193,8 @@ class ProfScope {
     ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (!g_prof.on) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
         a_ = prof_event();
         b_ = prof_event();
         if (a_ && b_) (void)hipEventRecord(a_, s_);
@@ -224,23 +245,29 @@ bool valid_B(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
 // Matcher selected for a level (fic_encode_level_ex's variant).
 enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3 };
 
-struct Level {
-    int lv, B, L, gy, gx, total;  // domain grid
-    int max_act;                  // worst-case active ranges
-    int nc;                       // pool chunks of the matcher
-    int var;                      // kVarValu, kVarMfma or kVarFp32
-    KSet ks;
-};
-
 // The int8 MFMA matcher serves B = 8 with a contrast grid 0..k1 (k1 >= 2).
 bool mfma_eligible(int B, const KSet& ks) {
     return B == 8 && ks.consecutive && ks.k0 == 0 && ks.n >= 3;
 }
 
-// Pool domains per chunk of the level's matcher (its partials per range).
-int chunk_domains(const Level& v);
+// Host plan of one level of one image.
+struct Level {
+    int lv, B, L, gy, gx, total;  // domain grid
+    int max_act;                  // worst-case active ranges
+    int nc;                       // pool chunks of the matcher
+    int cg;                       // domains per pool chunk
+    int var;                      // kVarValu, kVarMfma or kVarFp32
+    KSet ks;
+};
 
-Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks, int variant = 0) {
+int default_cg(int B, int var) {
+    if (var == kVarMfma) return kM8Chunk;
+    if (var == kVarFp32) return 256;
+    return match_chunk_domains(B);
+}
+
+Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks, int variant = 0,
+                 int cg = 0) {
     Level v;
     v.var = variant != 0 ? variant : (mfma_eligible(B, ks) ? kVarMfma : kVarValu);
     v.lv = lv;
@@ -251,22 +278,20 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
     v.total = v.gy * v.gx;
     v.max_act = max_act;
     v.ks = ks;
-    int row_blocks = cdiv((int64_t)8 * max_act, kBlock);
+    v.cg = cg > 0 ? cg : default_cg(B, v.var);
+    // enough workgroups to fill the chip when the pool is large, at most one
+    // chunk per cg domains and 64 chunks
+    const int rows_per_block = v.var == kVarMfma ? kM8Rows : kBlock;
+    const int row_blocks = cdiv((int64_t)8 * max_act, rows_per_block);
     int nc = cdiv(2048, row_blocks);
     nc = std::max(1, std::min(nc, 64));
-    nc = std::min(nc, std::max(1, cdiv(v.total, 64)));
+    nc = std::min(nc, std::max(1, cdiv(v.total, v.cg)));
     v.nc = nc;
     return v;
 }
 
-int chunk_domains(const Level& v) {
-    if (v.var == kVarMfma) return kM8Chunk;
-    if (v.var == kVarFp32) return 256;
-    return match_chunk_domains(v.B);
-}
-
 struct Sizes {
-    size_t key = 0, pool = 0, hl = 0, dom = 0, arow = 0, rng = 0, part = 0, blk = 0, act = 0;
+    size_t key = 0, pool = 0, hl = 0, dom = 0, rng = 0, part = 0, blk = 0, act = 0;
     size_t ar = 0, dcol = 0;  // int8 MFMA matcher
 };
 
@@ -276,7 +301,6 @@ void grow(Sizes& s, const Level& v) {
     s.pool = std::max(s.pool, (size_t)v.total * 4);
     s.hl = std::max(s.hl, (size_t)v.total * (n / 2) * 4);
     s.dom = std::max(s.dom, (size_t)v.total);
-    s.arow = std::max(s.arow, (size_t)v.max_act * 8 * n);
     s.rng = std::max(s.rng, (size_t)v.max_act);
     s.part = std::max(s.part, (size_t)v.max_act * v.nc * sizeof(Partial));
     size_t nblk = (size_t)std::max(cdiv(v.total, kBlock * kPoolItems), cdiv(v.max_act, kBlock * kQuadItems));
@@ -296,7 +320,6 @@ int ensure_sizes(Workspace& ws, const Sizes& s) {
     if ((rc = ensure(ws, ws.sd, s.dom * 4))) return rc;
     if ((rc = ensure(ws, ws.ad, s.dom * 8))) return rc;
     if ((rc = ensure(ws, ws.jd, s.dom * 4))) return rc;
-    if ((rc = ensure(ws, ws.arow, s.arow))) return rc;
     if ((rc = ensure(ws, ws.sr, s.rng * 4))) return rc;
     if ((rc = ensure(ws, ws.cr, s.rng * 8))) return rc;
     if ((rc = ensure(ws, ws.part, s.part))) return rc;
@@ -316,148 +339,177 @@ int ensure_sizes(Workspace& ws, const Sizes& s) {
     return FIC_OK;
 }
 
-void launch_mfma8(Workspace& ws, const Level& v, const uint8_t* img, int pitch, bool filtered,
-                  const int32_t* act) {
-    hipStream_t st = ws.stream;
-    const int32_t* act_count = ws.ctrl->act_count + v.lv;
+// Kernel arguments of one image at one level.
+Lvl make_lvl(Workspace& ws, const Level& v, const uint8_t* img, int H, int W, int pitch,
+             int entropy_mode, float entropy_bits, int min_pool, int32_t* act, int32_t* act_next,
+             int last, int64_t thr, fic_code* codes, int capacity, fic_level_stats* stats) {
+    Lvl a;
+    std::memset(&a, 0, sizeof a);
+    a.img = img;
+    a.pitch = pitch;
+    a.H = H;
+    a.W = W;
+    a.B = v.B;
+    a.L = v.L;
+    a.gx = v.gx;
+    a.gy = v.gy;
+    a.total = v.total;
+    a.max_act = v.max_act;
+    a.lv = v.lv;
+    a.last = last;
+    a.nc = v.nc;
+    a.cg = v.cg;
+    a.var = v.var;
+    a.min_pool = min_pool;
+    a.rank = std::min(min_pool, v.total);
+    const int side = 2 * v.B;
+    a.M = entropy_mode == 1 ? entropy_cut(side * side, (double)entropy_bits) : 0;
     {
-        ProfScope ps("pool_prep", st);
-        k_pool_prep_i8<<<cdiv((int64_t)v.total * 4, kBlock), kBlock, 0, st>>>(
-            img, pitch, v.L, v.gx, P<int32_t>(ws.pool), filtered ? -1 : v.total, ws.ctrl,
-            P<int8_t>(ws.dh), P<int8_t>(ws.dl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad),
-            P<int32_t>(ws.jd), P<float>(ws.wd), P<float>(ws.cw));
+        const int64_t maxkey = entropy_table()[side * side] + 1;
+        int shift = 0;
+        while ((maxkey >> shift) >= kSelBins) ++shift;
+        a.sel_shift = shift;
+        a.bound_chunk = std::max(8192, cdiv(v.total, 64));
     }
-    {
-        ProfScope ps("range_prep", st);
-        k_range_prep_i8<<<cdiv((int64_t)8 * v.max_act, kBlock), kBlock, 0, st>>>(
-            img, pitch, act, act_count, P<int8_t>(ws.ar), P<int32_t>(ws.sr), P<int32_t>(ws.srp),
-            P<int64_t>(ws.cr));
-    }
-    ProfScope ps("match_b8_mfma", st);
-    dim3 grid(cdiv((int64_t)8 * v.max_act, kM8Rows), v.nc);
-    k_match_mfma8<<<grid, kM8Waves * 64, 0, st>>>(
-        P<int8_t>(ws.ar), P<int32_t>(ws.srp), act_count, P<int8_t>(ws.dh), P<int8_t>(ws.dl),
-        P<uint32_t>(ws.sd), P<int64_t>(ws.ad), P<float>(ws.wd), P<float>(ws.cw), P<int32_t>(ws.jd),
-        ws.ctrl, v.ks.k1, v.nc, P<Partial>(ws.part));
+    a.thr = thr;
+    a.capacity = capacity;
+    a.ctrl = ws.ctrl;
+    a.key = P<int64_t>(ws.key);
+    a.pool = P<int32_t>(ws.pool);
+    a.hl = P<uint32_t>(ws.hl);
+    a.sd = P<uint32_t>(ws.sd);
+    a.ad = P<int64_t>(ws.ad);
+    a.jd = P<int32_t>(ws.jd);
+    a.part = P<Partial>(ws.part);
+    a.sr = P<int32_t>(ws.sr);
+    a.cr = P<int64_t>(ws.cr);
+    a.act = act;
+    a.act_next = act_next;
+    a.tmpc = P<fic_code>(ws.tmpc);
+    a.dec = P<uint8_t>(ws.dec);
+    a.blk = P<int2>(ws.blk);
+    a.codes = codes;
+    a.stats = stats;
+    a.ar = P<int8_t>(ws.ar);
+    a.srp = P<int32_t>(ws.srp);
+    a.dh = P<int8_t>(ws.dh);
+    a.dl = P<int8_t>(ws.dl);
+    a.gd = P<float>(ws.wd);
+    a.af = P<float>(ws.cw);
+    a.ks = v.ks;
+    return a;
+}
+
+// keep iff E <= T^2 n  <=>  1600 n E <= 1600 T^2 n^2
+int64_t keep_threshold(float rms, int B) {
+    const double n = (double)B * B;
+    const double thr = std::floor(1600.0 * (double)rms * (double)rms * n * n);
+    return thr >= 9.0e18 ? INT64_MAX : (int64_t)thr;
+}
+
+template <typename F>
+int max_over(const std::vector<Lvl>& h, F f) {
+    int m = 1;
+    for (const Lvl& a : h) m = std::max(m, f(a));
+    return m;
+}
+
+template <int SIDE>
+void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
+    const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });
+    kt_pool_score<SIDE><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt, T);
 }
 
 template <int B>
-void launch_level_kernels(Workspace& ws, const Level& v, const uint8_t* img, int pitch,
-                          bool filtered, const int32_t* act) {
-    hipStream_t st = ws.stream;
-    const int32_t* act_count = ws.ctrl->act_count + v.lv;
-    if (B == 8 && v.var == kVarMfma) {
-        launch_mfma8(ws, v, img, pitch, filtered, act);
+void launch_prep_match(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, hipStream_t st) {
+    const int n = (int)h.size();
+    const Lvl& a0 = h[0];
+    const int max_act = max_over(h, [](const Lvl& a) { return a.max_act; });
+    const int max_nc = max_over(h, [](const Lvl& a) { return a.nc; });
+    if (B == 8 && a0.var == kVarMfma) {
+        {
+            ProfScope ps("pool_prep", st);
+            const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * 4, kBlock); });
+            kt_pool_prep_i8<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
+        }
+        {
+            ProfScope ps("range_prep", st);
+            kt_range_prep_i8<<<dim3(cdiv((int64_t)8 * max_act, kBlock), 1, n), kBlock, 0, st>>>(h[0], dt);
+        }
+        ProfScope ps("match_b8_mfma", st);
+        kt_match_mfma8<<<dim3(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n), kM8Waves * 64, 0, st>>>(h[0], dt);
         return;
     }
     {
         ProfScope ps("pool_prep", st);
-        k_pool_prep<B><<<cdiv((int64_t)v.total * PrepShape<B>::TPD, kBlock), kBlock, 0, st>>>(
-            img, pitch, v.L, v.gx, P<int32_t>(ws.pool), filtered ? -1 : v.total, ws.ctrl,
-            P<uint32_t>(ws.hl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad), P<int32_t>(ws.jd));
+        const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * PrepShape<B>::TPD, kBlock); });
+        kt_pool_prep<B><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
     }
-    if (B == 8 && v.var == kVarFp32) {
+    const dim3 grid(cdiv(max_act, kBlock / 8), max_nc, n);
+    if (B == 8 && a0.var == kVarFp32) {
         ProfScope ps("match_b8_fp32", st);
-        dim3 g32(cdiv(v.max_act, kBlock / 8), v.nc);
-        k_match_fp32<<<g32, kBlock, 0, st>>>(img, pitch, act, act_count, img, v.L, v.gx,
-                                             P<int32_t>(ws.jd), ws.ctrl, v.ks.k1, v.nc,
-                                             P<Partial>(ws.part));
+        kt_match_fp32<<<grid, kBlock, 0, st>>>(h[0], dt);
         return;
     }
     ProfScope ps(match_label(B), st);
-    dim3 grid(cdiv(v.max_act, kBlock / 8), v.nc);
-    const int mode = v.ks.n <= kSmallMax ? kModeSmall : (v.ks.consecutive ? kModeGrid : kModeList);
-#define FIC_MATCH_ARGS                                                                          \
-    img, pitch, act, act_count, P<uint32_t>(ws.hl), P<uint32_t>(ws.sd), P<int64_t>(ws.ad),      \
-        P<int32_t>(ws.jd), ws.ctrl, v.ks, v.nc, P<Partial>(ws.part), P<int32_t>(ws.sr),          \
-        P<int64_t>(ws.cr)
-    if (mode == kModeSmall)
-        k_match<B, kModeSmall><<<grid, kBlock, 0, st>>>(FIC_MATCH_ARGS);
-    else if (mode == kModeGrid)
-        k_match<B, kModeGrid><<<grid, kBlock, 0, st>>>(FIC_MATCH_ARGS);
-    else
-        k_match<B, kModeList><<<grid, kBlock, 0, st>>>(FIC_MATCH_ARGS);
-#undef FIC_MATCH_ARGS
+    const KSet& ks = a0.ks;
+    if (ks.n <= kSmallMax) kt_match<B, kModeSmall><<<grid, kBlock, 0, st>>>(h[0], dt);
+    else if (ks.consecutive) kt_match<B, kModeGrid><<<grid, kBlock, 0, st>>>(h[0], dt);
+    else kt_match<B, kModeList><<<grid, kBlock, 0, st>>>(h[0], dt);
 }
 
-// Radix-select digits (shift, width) covering the bits of keys below maxkey.
-std::vector<std::pair<int, int>> select_digits(int64_t maxkey) {
-    int bits = 1;
-    while (bits < 63 && ((int64_t)1 << bits) <= maxkey) ++bits;
-    std::vector<std::pair<int, int>> d;
-    for (int hi = bits; hi > 0; hi -= kSelBits) {
-        int w = std::min(kSelBits, hi);
-        d.push_back({hi - w, w});
-    }
-    return d;
-}
-
-// Pool of one level (entropy filter of Section 3, or the whole grid), then the
-// pool moments and the matcher. The level's active list and count must
-// already be on the device.
-int run_level(Workspace& ws, const Level& v, const uint8_t* img, int pitch, int entropy_mode,
-              float entropy_bits, int min_pool, const int32_t* act) {
-    hipStream_t st = ws.stream;
-    const bool filtered = entropy_mode == 1;
+// Pool of one level (entropy filter of Section 3, or the whole grid), pool
+// moments and the matcher, for h.size() images whose arguments are at dt.
+int launch_level(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
+                 hipStream_t st) {
+    const int n = (int)h.size();
+    const int B = h[0].B;
     if (filtered) {
-        const int side = 2 * v.B;
-        const int64_t M = entropy_cut(side * side, (double)entropy_bits);
         {
             ProfScope ps("pool_score", st);
-            switch (side) {
-                case 4:
-                    k_pool_score<4><<<cdiv((int64_t)v.total * ScoreShape<4>::TPD, kBlock), kBlock, 0, st>>>(
-                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
-                    break;
-                case 8:
-                    k_pool_score<8><<<cdiv((int64_t)v.total * ScoreShape<8>::TPD, kBlock), kBlock, 0, st>>>(
-                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
-                    break;
-                case 16:
-                    k_pool_score<16><<<cdiv((int64_t)v.total * ScoreShape<16>::TPD, kBlock), kBlock, 0, st>>>(
-                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
-                    break;
-                default:
-                    k_pool_score<32><<<cdiv((int64_t)v.total * ScoreShape<32>::TPD, kBlock), kBlock, 0, st>>>(
-                        img, pitch, v.L, v.gx, v.total, ws.T, M, P<int64_t>(ws.key), ws.ctrl);
-                    break;
+            switch (2 * B) {
+                case 4: launch_score<4>(dt, h, T, st); break;
+                case 8: launch_score<8>(dt, h, T, st); break;
+                case 16: launch_score<16>(dt, h, T, st); break;
+                default: launch_score<32>(dt, h, T, st); break;
             }
         }
-        const int rank = std::min(min_pool, v.total);
         {
-            // floor: an upper bound on the rank-th smallest key
             ProfScope ps("pool_select", st);
-            const int64_t maxkey = entropy_table()[side * side] + 1;
-            int shift = 0;
-            while ((maxkey >> shift) >= kSelBins) ++shift;
-            const int chunk = std::max(8192, cdiv(v.total, 64));
-            k_floor_bound<<<cdiv(v.total, chunk), kBlock, 0, st>>>(P<int64_t>(ws.key), v.total,
-                                                                   min_pool, rank, shift, chunk,
-                                                                   ws.ctrl);
+            const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, a.bound_chunk); });
+            kt_floor_bound<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
         {
             ProfScope ps("pool_compact", st);
-            CompactArgs a{};
-            a.kind = 0;
-            a.total = v.total;
-            a.min_pool = min_pool;
-            a.M = M;
-            a.key = P<int64_t>(ws.key);
-            const int nblk = cdiv(v.total, kBlock * kPoolItems);
-            k_pool_count<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk));
-            k_pool_scatter<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk), P<int32_t>(ws.pool));
+            const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
+            kt_pool_count<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+            kt_pool_scatter<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
         {
             ProfScope ps("pool_select", st);
-            k_floor_select<<<1, 1024, 0, st>>>(P<int64_t>(ws.key), v.total, min_pool, rank,
-                                               P<int32_t>(ws.pool), ws.ctrl);
+            kt_floor_select<<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt);
         }
     }
-    switch (v.B) {
-        case 2: launch_level_kernels<2>(ws, v, img, pitch, filtered, act); break;
-        case 4: launch_level_kernels<4>(ws, v, img, pitch, filtered, act); break;
-        case 8: launch_level_kernels<8>(ws, v, img, pitch, filtered, act); break;
-        default: launch_level_kernels<16>(ws, v, img, pitch, filtered, act); break;
+    switch (B) {
+        case 2: launch_prep_match<2>(dt, h, filtered, st); break;
+        case 4: launch_prep_match<4>(dt, h, filtered, st); break;
+        case 8: launch_prep_match<8>(dt, h, filtered, st); break;
+        default: launch_prep_match<16>(dt, h, filtered, st); break;
+    }
+    LAUNCH_CHECK();
+    return FIC_OK;
+}
+
+// Keep/split decisions and compaction for a quadtree level.
+int launch_quad(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
+    const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.max_act, kBlock * kQuadItems); });
+    {
+        ProfScope ps("reduce_quad", st);
+        kt_reduce_quad<<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
+    }
+    {
+        ProfScope ps("quad_compact", st);
+        kt_quad_scatter<<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
     }
     LAUNCH_CHECK();
     return FIC_OK;
@@ -473,7 +525,7 @@ int check_image(const uint8_t* img, int H, int W, int pitch, int B) {
     return FIC_OK;
 }
 
-int check_params(const fic_params* p, int H, int W, std::vector<KSet>& ks) {
+int check_params(const fic_params* p, std::vector<KSet>& ks) {
     if (!p) return fail(FIC_EINVAL, "params pointer is NULL");
     if (p->n_levels < 1 || p->n_levels > 4) return fail(FIC_EINVAL, "n_levels %d not in 1..4", p->n_levels);
     if (!valid_B(p->B0)) return fail(FIC_EINVAL, "B0 %d not in {2,4,8,16}", p->B0);
@@ -489,62 +541,65 @@ int check_params(const fic_params* p, int H, int W, std::vector<KSet>& ks) {
         int rc = check_kset(p->s_k[l], p->n_s[l], &ks[l]);
         if (rc) return rc;
     }
-    (void)H;
-    (void)W;
     return FIC_OK;
 }
 
-// Quadtree encode into `codes` (device), counters in the control block.
+// Per-level plans of one image's quadtree.
+std::vector<Level> quad_levels(int H, int W, const fic_params* p, const std::vector<KSet>& ks,
+                               const int* cg = nullptr) {
+    std::vector<Level> lv;
+    for (int l = 0; l < p->n_levels; ++l) {
+        const int B = p->B0 >> l;
+        lv.push_back(make_level(l, H, W, B, p->L[l], (H / B) * (W / B), ks[l], 0, cg ? cg[l] : 0));
+    }
+    return lv;
+}
+
+// Argument tables of one image's quadtree (one entry per level).
+std::vector<Lvl> quad_tables(Workspace& ws, const std::vector<Level>& lv, const uint8_t* img,
+                             int H, int W, int pitch, const fic_params* p, fic_code* codes,
+                             int capacity, fic_level_stats* stats) {
+    std::vector<Lvl> t;
+    for (size_t l = 0; l < lv.size(); ++l) {
+        const Level& v = lv[l];
+        int32_t* cur = P<int32_t>((l % 2) ? ws.act1 : ws.act0);
+        int32_t* nxt = P<int32_t>((l % 2) ? ws.act0 : ws.act1);
+        const int last = l + 1 == lv.size();
+        t.push_back(make_lvl(ws, v, img, H, W, pitch, p->entropy_mode, p->entropy_bits, p->min_pool,
+                             cur, nxt, last, keep_threshold(p->rms_thresh, v.B), codes, capacity,
+                             stats));
+    }
+    return t;
+}
+
+// Queue the whole quadtree of one image (tables at dt, host copies t).
+int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, const int64_t* T,
+                    bool filtered, hipStream_t st) {
+    const int nl = (int)t.size() / n_images;
+    std::vector<Lvl> h0(t.begin(), t.begin() + n_images);
+    const int gx = max_over(h0, [](const Lvl& a) { return cdiv((a.H / a.B) * (a.W / a.B), kBlock); });
+    kt_act_full<<<dim3(gx, 1, n_images), kBlock, 0, st>>>(t[0], dt, 1);
+    for (int l = 0; l < nl; ++l) {
+        std::vector<Lvl> h(t.begin() + l * n_images, t.begin() + (l + 1) * n_images);
+        const Lvl* dl = dt ? dt + l * n_images : nullptr;
+        int rc = launch_level(dl, h, T, filtered, st);
+        if (rc) return rc;
+        if ((rc = launch_quad(dl, h, st))) return rc;
+    }
+    return FIC_OK;
+}
+
+// Quadtree encode of one image into `codes` (device); counters in ws.ctrl.
 int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch,
                       const fic_params* p, const std::vector<KSet>& ks, fic_code* codes,
                       int capacity, fic_level_stats* stats) {
-    hipStream_t st = ws.stream;
-    std::vector<Level> lv;
+    std::vector<Level> lv = quad_levels(H, W, p, ks);
     Sizes sz;
-    for (int l = 0; l < p->n_levels; ++l) {
-        int B = p->B0 >> l;
-        lv.push_back(make_level(l, H, W, B, p->L[l], (H / B) * (W / B), ks[l]));
-        grow(sz, lv.back());
-    }
+    for (const Level& v : lv) grow(sz, v);
     int rc = ensure_sizes(ws, sz);
     if (rc) return rc;
-    k_act_full<<<cdiv(lv[0].max_act, kBlock), kBlock, 0, st>>>(P<int32_t>(ws.act0), H / p->B0,
-                                                             W / p->B0, p->B0, ws.ctrl, 0, 1);
-    Buf* cur = &ws.act0;
-    Buf* nxt = &ws.act1;
-    for (int l = 0; l < p->n_levels; ++l) {
-        const Level& v = lv[l];
-        rc = run_level(ws, v, img, pitch, p->entropy_mode, p->entropy_bits, p->min_pool,
-                       P<int32_t>(*cur));
-        if (rc) return rc;
-        const int n = v.B * v.B;
-        const bool last = l == p->n_levels - 1;
-        // keep iff E <= T^2 n  <=>  1600 n E <= 1600 T^2 n^2
-        double thr_d = std::floor(1600.0 * (double)p->rms_thresh * (double)p->rms_thresh *
-                                  (double)n * (double)n);
-        int64_t thr = thr_d >= 9.0e18 ? INT64_MAX : (int64_t)thr_d;
-        const int nblk = cdiv(v.max_act, kBlock * kQuadItems);
-        {
-            ProfScope ps("reduce_quad", st);
-            k_reduce_quad<<<nblk, kBlock, 0, st>>>(
-                v.B, v.L, v.gx, l, last ? 1 : 0, thr, P<int32_t>(*cur), ws.ctrl, P<Partial>(ws.part),
-                v.nc, chunk_domains(v), P<int64_t>(ws.cr), P<int32_t>(ws.sr), v.ks,
-                P<fic_code>(ws.tmpc), P<uint8_t>(ws.dec), P<int2>(ws.blk), stats);
-        }
-        {
-            ProfScope ps("quad_compact", st);
-            CompactArgs a{};
-            a.kind = 1;
-            a.act_count = ws.ctrl->act_count + l;
-            a.decision = P<uint8_t>(ws.dec);
-            k_quad_scatter<<<nblk, kBlock, 0, st>>>(a, ws.ctrl, P<int2>(ws.blk),
-                                                    P<fic_code>(ws.tmpc), codes, capacity,
-                                                    P<int32_t>(*cur), P<int32_t>(*nxt), v.B / 2);
-        }
-        LAUNCH_CHECK();
-        std::swap(cur, nxt);
-    }
-    return FIC_OK;
+    std::vector<Lvl> t = quad_tables(ws, lv, img, H, W, pitch, p, codes, capacity, stats);
+    return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode == 1, ws.stream);
 }
 
 }  // namespace
@@ -590,23 +645,21 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     if ((rc = ensure_sizes(*ws, sz))) return rc;
     hipStream_t st = ws->stream;
     int32_t* act = P<int32_t>(ws->act0);
+    std::vector<Lvl> t{make_lvl(*ws, v, img, H, W, pitch, entropy_mode, entropy_bits, min_pool, act,
+                                P<int32_t>(ws->act1), 1, 0, nullptr, 0, nullptr)};
+    const Lvl* dt = nullptr;  // one image: arguments by value
+    const std::vector<Lvl>& h = t;
     if (range_yx)
-        k_act_from_yx<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(act, range_yx, n_ranges, H, W, B,
-                                                                 ws->ctrl);
+        kt_act_from_yx<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, range_yx, n_ranges);
     else
-        k_act_full<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(act, H / B, W / B, B, ws->ctrl, 0, 0);
-    if ((rc = run_level(*ws, v, img, pitch, entropy_mode, entropy_bits, min_pool, act)))
-        return rc;
+        kt_act_full<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, 0);
+    if ((rc = launch_level(dt, t, ws->T, entropy_mode == 1, st))) return rc;
     {
         ProfScope ps("reduce_level", st);
         if (v.var == kVarFp32)
-            k_reduce_fp32<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(
-                img, pitch, L, v.gx, act, ws->ctrl->act_count, P<Partial>(ws->part), v.nc, ws->ctrl,
-                out);
+            kt_reduce_fp32<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, out);
         else
-            k_reduce_level<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(
-                B, L, v.gx, act, ws->ctrl->act_count, P<Partial>(ws->part), v.nc, chunk_domains(v),
-                ws->ctrl, P<int64_t>(ws->cr), P<int32_t>(ws->sr), ks, out);
+            kt_reduce_level<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, out);
     }
     LAUNCH_CHECK();
     if (pool_count)
@@ -637,7 +690,7 @@ FIC_API int fic_encode_image(const uint8_t* img, int32_t H, int32_t W, int32_t p
                              const fic_params* p, fic_code* codes, int32_t capacity,
                              int32_t* n_codes, fic_level_stats* stats, void* stream) {
     std::vector<KSet> ks;
-    int rc = check_params(p, H, W, ks);
+    int rc = check_params(p, ks);
     if (rc) return rc;
     if ((rc = check_image(img, H, W, pitch, p->B0))) return rc;
     if (!codes || !n_codes) return fail(FIC_EINVAL, "codes or n_codes is NULL");
@@ -719,7 +772,7 @@ FIC_API int fic_calibrate_s(const uint8_t* img, int32_t H, int32_t W, int32_t pi
         for (int k = 0; k <= 10; ++k) q.s_k[l][k] = (int8_t)k;
     }
     std::vector<KSet> ks;
-    int rc = check_params(&q, H, W, ks);
+    int rc = check_params(&q, ks);
     if (rc) return rc;
     if (!std::isfinite(p->entropy_bits)) return fail(FIC_EINVAL, "entropy_bits not finite");
     if ((rc = check_image(img, H, W, pitch, q.B0))) return rc;
@@ -810,5 +863,331 @@ FIC_API int fic_profile_end(fic_kernel_time* out, int32_t max, int32_t* n_out) {
     if (n_out) *n_out = (int32_t)agg.size();
     if (out)
         for (int i = 0; i < (int)agg.size() && i < max; ++i) out[i] = agg[i];
+    return FIC_OK;
+}
+
+// ================================================================ batched quadtree
+// n images, each with its own workspace; every level of every image runs in
+// the same launches (image = blockIdx.z), captured once into a hipGraph.
+namespace fic {
+namespace {
+
+__global__ void kt_copy_counts(const Lvl* __restrict__ tab, int n, int32_t* __restrict__ n_codes) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) n_codes[i] = tab[i].ctrl->n_codes;
+}
+
+struct BatchImage {
+    const uint8_t* img;
+    int H, W, pitch;
+    int64_t code_off;
+    int capacity;
+    Workspace* ws;
+};
+
+}  // namespace
+}  // namespace fic
+
+struct fic_batch {
+    int device = 0;
+    hipStream_t st = nullptr;
+    fic_params p;
+    std::vector<fic::KSet> ks;
+    std::vector<fic::BatchImage> im;
+    fic_code* codes = nullptr;
+    int32_t* n_codes = nullptr;
+    fic_level_stats* stats = nullptr;
+    std::vector<int> cg;  // per level; 0 = default
+    std::vector<fic::Lvl> htab;  // host copy of the [level][image] argument table
+    void* dtab = nullptr;
+    size_t dtab_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t matches_hint = 0;
+};
+
+namespace fic {
+namespace {
+
+void batch_drop_graph(fic_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Every kernel of the batch, in order, on stream st.
+int batch_launch(fic_batch* b, hipStream_t st) {
+    const Lvl* dt = static_cast<const Lvl*>(b->dtab);
+    const int n = (int)b->im.size();
+    int rc = launch_quadtree(dt, b->htab, n, b->im[0].ws->T, b->p.entropy_mode == 1, st);
+    if (rc) return rc;
+    kt_copy_counts<<<cdiv(n, kBlock), kBlock, 0, st>>>(dt, n, b->n_codes);
+    LAUNCH_CHECK();
+    return FIC_OK;
+}
+
+// (Re)build the argument table and the captured graph of a batch.
+int batch_build(fic_batch* b) {
+    // a replay may still run on a caller stream while buffers are regrown
+    HIP_TRY(hipDeviceSynchronize());
+    batch_drop_graph(b);
+    const int n = (int)b->im.size(), nl = b->p.n_levels;
+    std::vector<Lvl> tab((size_t)nl * n);
+    for (int i = 0; i < n; ++i) {
+        BatchImage& m = b->im[i];
+        std::vector<Level> lv = quad_levels(m.H, m.W, &b->p, b->ks, b->cg.data());
+        Sizes sz;
+        for (const Level& v : lv) grow(sz, v);
+        int rc = ensure_sizes(*m.ws, sz);
+        if (rc) return rc;
+        std::vector<Lvl> t = quad_tables(*m.ws, lv, m.img, m.H, m.W, m.pitch, &b->p,
+                                         b->codes + m.code_off, m.capacity,
+                                         b->stats ? b->stats + (size_t)i * nl : nullptr);
+        for (int l = 0; l < nl; ++l) tab[(size_t)l * n + i] = t[l];
+    }
+    const size_t bytes = sizeof(Lvl) * tab.size();
+    if (b->dtab_bytes < bytes) {
+        if (b->dtab) (void)hipFree(b->dtab);
+        b->dtab = nullptr;
+        b->dtab_bytes = 0;
+        if (hipMalloc(&b->dtab, bytes) != hipSuccess) return fail(FIC_ENOMEM, "hipMalloc(%zu) failed", bytes);
+        b->dtab_bytes = bytes;
+    }
+    HIP_TRY(hipMemcpy(b->dtab, tab.data(), bytes, hipMemcpyHostToDevice));
+    b->htab = tab;
+    HIP_TRY(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    int rc = batch_launch(b, b->st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->st, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(FIC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return FIC_OK;
+}
+
+int batch_time(fic_batch* b, hipStream_t s, int reps, float* ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipGraphLaunch(b->exec, s));  // warm-up
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(b->exec, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / reps;
+    return FIC_OK;
+}
+
+// Chunk size level l actually uses (a 0 entry means the library default).
+int batch_chunk(const fic_batch* b, int l) {
+    if (b->cg[l] > 0) return b->cg[l];
+    const int B = b->p.B0 >> l;
+    return default_cg(B, mfma_eligible(B, b->ks[l]) ? kVarMfma : kVarValu);
+}
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Cache key: GPU architecture, HIP runtime version, the batch's image sizes and parameters.
+std::string batch_key(const fic_batch* b) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
+    int rt = 0;
+    (void)hipRuntimeGetVersion(&rt);
+    uint64_t h = 1469598103934665603ull;
+    for (const BatchImage& m : b->im) {
+        h = fnv1a(h, &m.H, sizeof m.H);
+        h = fnv1a(h, &m.W, sizeof m.W);
+    }
+    h = fnv1a(h, &b->p, sizeof b->p);
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|hip%d|n%zu|%016llx", arch.c_str(), rt, b->im.size(),
+                  (unsigned long long)h);
+    return buf;
+}
+
+}  // namespace
+}  // namespace fic
+
+FIC_API int fic_batch_create(int32_t n, const uint8_t* const* imgs, const int32_t* H,
+                             const int32_t* W, const int32_t* pitch, const fic_params* p,
+                             fic_code* codes, const int64_t* code_offset, int32_t* n_codes,
+                             fic_level_stats* stats, fic_batch** out) {
+    if (!out) return fail(FIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 65535) return fail(FIC_EINVAL, "batch size %d not in 1..65535", n);
+    if (!imgs || !H || !W || !pitch || !code_offset) return fail(FIC_EINVAL, "NULL host array");
+    if (!codes || !n_codes) return fail(FIC_EINVAL, "codes or n_codes is NULL");
+    std::vector<KSet> ks;
+    int rc = check_params(p, ks);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        if ((rc = check_image(imgs[i], H[i], W[i], pitch[i], p->B0)))
+            return fail(rc, "image %d: %s", i, g_err.c_str());
+        const int64_t cap = code_offset[i + 1] - code_offset[i];
+        const int64_t lower = (int64_t)(H[i] / p->B0) * (W[i] / p->B0);
+        if (code_offset[i] < 0 || cap < lower)
+            return fail(FIC_ECAPACITY, "image %d: code capacity %lld below %lld", i, (long long)cap,
+                        (long long)lower);
+        if (cap > INT32_MAX) return fail(FIC_EINVAL, "image %d: code capacity too large", i);
+    }
+    fic_batch* b = new fic_batch();
+    b->p = *p;
+    b->ks = ks;
+    b->codes = codes;
+    b->n_codes = n_codes;
+    b->stats = stats;
+    b->cg.assign(p->n_levels, 0);
+    auto bail = [&](int code) {
+        fic_batch_destroy(b);
+        return code;
+    };
+    if (hipGetDevice(&b->device) != hipSuccess) return bail(fail(FIC_EDEVICE, "hipGetDevice failed"));
+    if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(FIC_EDEVICE, "hipStreamCreateWithFlags failed"));
+    for (int i = 0; i < n; ++i) {
+        BatchImage m;
+        m.img = imgs[i];
+        m.H = H[i];
+        m.W = W[i];
+        m.pitch = pitch[i];
+        m.code_off = code_offset[i];
+        m.capacity = (int)(code_offset[i + 1] - code_offset[i]);
+        m.ws = nullptr;
+        if ((rc = new_ws(b->device, b->st, &m.ws))) return bail(rc);
+        b->im.push_back(m);
+    }
+    if ((rc = batch_build(b))) return bail(rc);
+    *out = b;
+    return FIC_OK;
+}
+
+FIC_API int fic_batch_run(fic_batch* b, void* stream) {
+    if (!b || !b->exec) return fail(FIC_EINVAL, "batch is NULL or not built");
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return FIC_OK;
+}
+
+FIC_API int fic_batch_run_eager(fic_batch* b, void* stream) {
+    if (!b || !b->exec) return fail(FIC_EINVAL, "batch is NULL or not built");
+    return batch_launch(b, (hipStream_t)stream);
+}
+
+FIC_API int fic_batch_set_chunks(fic_batch* b, const int32_t* cg) {
+    if (!b) return fail(FIC_EINVAL, "batch is NULL");
+    for (int l = 0; l < b->p.n_levels; ++l) {
+        const int v = cg ? cg[l] : 0;
+        if (v < 0 || v > (1 << 20)) return fail(FIC_EINVAL, "chunk %d not in 0..2^20", v);
+        b->cg[l] = v;
+    }
+    return batch_build(b);
+}
+
+FIC_API int fic_batch_get_chunks(const fic_batch* b, int32_t* cg) {
+    if (!b || !cg) return fail(FIC_EINVAL, "NULL argument");
+    for (int l = 0; l < b->p.n_levels; ++l) cg[l] = fic::batch_chunk(b, l);
+    return FIC_OK;
+}
+
+FIC_API int fic_batch_autotune(fic_batch* b, void* stream, int32_t reps, const char* cache_path,
+                               float* best_ms) {
+    if (!b) return fail(FIC_EINVAL, "batch is NULL");
+    if (reps < 1) return fail(FIC_EINVAL, "reps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = batch_key(b);
+    const int nl = b->p.n_levels;
+    // cached choice?
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            std::vector<int> found;
+            while (std::fgets(line, sizeof line, f)) {
+                std::string ln(line);
+                if (ln.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+                size_t q = ln.find("\"chunks\": [");
+                if (q == std::string::npos) continue;
+                found.clear();
+                const char* c = ln.c_str() + q + 11;
+                for (int l = 0; l < nl; ++l) {
+                    char* end = nullptr;
+                    long v = std::strtol(c, &end, 10);
+                    if (end == c) break;
+                    found.push_back((int)v);
+                    c = end;
+                    while (*c == ',' || *c == ' ') ++c;
+                }
+            }
+            std::fclose(f);
+            if ((int)found.size() == nl) {
+                int rc = fic_batch_set_chunks(b, found.data());
+                if (rc) return rc;
+                if (best_ms) {
+                    float ms;
+                    if ((rc = batch_time(b, s, reps, &ms))) return rc;
+                    *best_ms = ms;
+                }
+                return FIC_OK;
+            }
+        }
+    }
+    // coordinate descent over the matcher chunk of each level
+    static const int cand[] = {32, 64, 128, 256, 512, 1024, 2048, 4096};
+    float best;
+    int rc = batch_time(b, s, reps, &best);
+    if (rc) return rc;
+    for (int l = 0; l < nl; ++l) b->cg[l] = batch_chunk(b, l);
+    for (int l = 0; l < nl; ++l) {
+        const int keep = b->cg[l];
+        int best_cg = keep;
+        for (int c : cand) {
+            b->cg[l] = c;
+            if ((rc = batch_build(b))) return rc;
+            float ms;
+            if ((rc = batch_time(b, s, reps, &ms))) return rc;
+            if (ms < best) {
+                best = ms;
+                best_cg = c;
+            }
+        }
+        b->cg[l] = best_cg;
+    }
+    if ((rc = batch_build(b))) return rc;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "{\"key\": \"%s\", \"chunks\": [", key.c_str());
+            for (int l = 0; l < nl; ++l) std::fprintf(f, "%s%d", l ? ", " : "", b->cg[l]);
+            std::fprintf(f, "], \"ms\": %.4f}\n", best);
+            std::fclose(f);
+        }
+    }
+    return FIC_OK;
+}
+
+FIC_API int fic_batch_destroy(fic_batch* b) {
+    if (!b) return FIC_OK;
+    (void)hipDeviceSynchronize();
+    fic::batch_drop_graph(b);
+    for (fic::BatchImage& m : b->im)
+        if (m.ws) fic::free_ws(m.ws);
+    if (b->dtab) (void)hipFree(b->dtab);
+    if (b->st) (void)hipStreamDestroy(b->st);
+    delete b;
     return FIC_OK;
 }

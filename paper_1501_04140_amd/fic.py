@@ -102,9 +102,19 @@ def load():
     lib.fic_sse.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
     lib.fic_calibrate_s.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, vp]
     lib.fic_profile_end.argtypes = [vp, i32, vp]
+    lib.fic_batch_create.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(Params), vp, vp, vp, vp,
+                                     ctypes.POINTER(vp)]
+    lib.fic_batch_run.argtypes = [vp, vp]
+    lib.fic_batch_run_eager.argtypes = [vp, vp]
+    lib.fic_batch_set_chunks.argtypes = [vp, vp]
+    lib.fic_batch_get_chunks.argtypes = [vp, vp]
+    lib.fic_batch_autotune.argtypes = [vp, vp, i32, ctypes.c_char_p, ctypes.POINTER(f32)]
+    lib.fic_batch_destroy.argtypes = [vp]
     lib.fic_last_error.restype = ctypes.c_char_p
     for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_image", "fic_decode", "fic_sse",
-                 "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end"):
+                 "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end",
+                 "fic_batch_create", "fic_batch_run", "fic_batch_run_eager", "fic_batch_set_chunks", "fic_batch_get_chunks",
+                 "fic_batch_autotune", "fic_batch_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -191,6 +201,77 @@ def encode_image(img, params: EncoderParams | None = None, capacity: int | None 
                                  _stream(stream))
     _check(rc)
     return codes, ncodes, stats
+
+
+class Batch:
+    """fic_batch_*: n images (any sizes the encoder accepts) encoded by one
+    captured hipGraph. The images must stay alive and in place; ``codes`` holds
+    every image's codes back to back (``offsets[i]`` .. ``offsets[i+1]``)."""
+
+    def __init__(self, images, params: EncoderParams | None = None):
+        import torch
+        self.images = [_dev_u8_image(im) for im in images]
+        if not self.images:
+            raise ValueError("empty batch")
+        self.params = params or EncoderParams()
+        n = len(self.images)
+        dev = self.images[0].device
+        caps = [max(code_capacity(im.shape[0], im.shape[1], self.params.levels), 1) for im in self.images]
+        self.offsets = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
+        self.codes = torch.empty((int(self.offsets[-1]), 32), dtype=torch.uint8, device=dev)
+        self.n_codes = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.stats = torch.zeros((n, len(self.params.levels), 24), dtype=torch.uint8, device=dev)
+        ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in self.images])
+        H = (ctypes.c_int32 * n)(*[im.shape[0] for im in self.images])
+        W = (ctypes.c_int32 * n)(*[im.shape[1] for im in self.images])
+        pitch = (ctypes.c_int32 * n)(*[im.stride(0) for im in self.images])
+        off = (ctypes.c_int64 * (n + 1))(*[int(v) for v in self.offsets])
+        self._p = self.params.to_c()
+        self._h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(load().fic_batch_create(n, ptrs, H, W, pitch, ctypes.byref(self._p),
+                                       self.codes.data_ptr(), off, self.n_codes.data_ptr(),
+                                       self.stats.data_ptr(), ctypes.byref(self._h)))
+
+    def run(self, stream=None):
+        _check(load().fic_batch_run(self._h, _stream(stream)))
+        return self.codes, self.n_codes, self.stats
+
+    def run_eager(self, stream=None):
+        """Same kernels, launched one by one (for per-kernel timing)."""
+        _check(load().fic_batch_run_eager(self._h, _stream(stream)))
+        return self.codes, self.n_codes, self.stats
+
+    def chunks(self) -> list:
+        out = (ctypes.c_int32 * len(self.params.levels))()
+        _check(load().fic_batch_get_chunks(self._h, out))
+        return list(out)
+
+    def set_chunks(self, chunks):
+        arr = (ctypes.c_int32 * len(self.params.levels))(*[int(c) for c in chunks])
+        _check(load().fic_batch_set_chunks(self._h, arr))
+
+    def autotune(self, reps: int = 3, cache_path: str | None = None, stream=None) -> float:
+        ms = ctypes.c_float(0.0)
+        path = cache_path.encode() if cache_path else None
+        _check(load().fic_batch_autotune(self._h, _stream(stream), reps, path, ctypes.byref(ms)))
+        return ms.value
+
+    def image_codes(self, i: int):
+        """Codes of image i (device uint8 [n, 32]); call after run() has finished."""
+        n = int(self.n_codes[i].item())
+        return self.codes[int(self.offsets[i]):int(self.offsets[i]) + n]
+
+    def close(self):
+        if self._h:
+            load().fic_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def decode(codes, n_codes: int, H: int, W: int, iters: int = 64, stream=None):

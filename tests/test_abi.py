@@ -151,3 +151,40 @@ def test_binding_refuses_cpu_tensors():
         fic.encode_level(torch.zeros((16, 16), dtype=torch.uint8), 4, 2)
     with pytest.raises(TypeError):
         fic.encode_level(np.zeros((16, 16), np.uint8), 4, 2)
+
+
+def _batch(lib, n=1, H=(64,), W=(64,), pitch=None, off=None, params=None, codes=1, ncodes=1, out=True):
+    pitch = W if pitch is None else pitch
+    c = params or _params()
+    imgs = (ctypes.c_void_p * max(n, 1))(*([1] * max(n, 1)))
+    Ha = (ctypes.c_int32 * max(n, 1))(*H)
+    Wa = (ctypes.c_int32 * max(n, 1))(*W)
+    Pa = (ctypes.c_int32 * max(n, 1))(*pitch)
+    off = off or [0] + list(np.cumsum([(h // 2) * (w // 2) for h, w in zip(H, W)]))
+    Oa = (ctypes.c_int64 * (len(off)))(*[int(v) for v in off])
+    h = ctypes.c_void_p()
+    rc = lib.fic_batch_create(n, imgs, Ha, Wa, Pa, ctypes.byref(c), codes, Oa, ncodes, None,
+                              ctypes.byref(h) if out else None)
+    return rc, lib.fic_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code,frag", [
+    (dict(n=0), fic.FIC_EINVAL, "batch size"),
+    (dict(out=False), fic.FIC_EINVAL, "out is NULL"),
+    (dict(codes=None), fic.FIC_EINVAL, "codes"),
+    (dict(H=(60,)), fic.FIC_EINVAL, "image 0"),
+    (dict(n=2, H=(64, 64), W=(64, 40)), fic.FIC_EINVAL, "image 1"),
+    (dict(n=2, H=(64, 64), W=(64, 64), off=[0, 1024, 1030]), fic.FIC_ECAPACITY, "image 1"),
+    (dict(params=_params(n_levels=0)), fic.FIC_EINVAL, "n_levels"),
+])
+def test_batch_create_rejects(lib, kw, code, frag):
+    rc, msg = _batch(lib, **kw)
+    assert rc == code and frag in msg
+
+
+def test_batch_calls_reject_null(lib):
+    assert lib.fic_batch_run(None, None) == fic.FIC_EINVAL
+    assert lib.fic_batch_set_chunks(None, None) == fic.FIC_EINVAL
+    assert lib.fic_batch_get_chunks(None, None) == fic.FIC_EINVAL
+    assert lib.fic_batch_autotune(None, None, 1, None, None) == fic.FIC_EINVAL
+    assert lib.fic_batch_destroy(None) == fic.FIC_OK
