@@ -30,6 +30,10 @@ __all__ = [
     "BATCH_SIDES",
     "learned_train_image",
     "learned_eval_image",
+    "MLP_SHAPES",
+    "mlp_init",
+    "unit_rows_f16",
+    "grad_like",
 ]
 
 BATCH_SIDES = (256, 384, 512, 768, 1024, 2048)
@@ -125,3 +129,43 @@ def learned_train_image(i: int, n: int = 512) -> np.ndarray:
 def learned_eval_image(i: int, n: int = 2048) -> np.ndarray:
     """Evaluation image i (seed 2000 + i), beta ~ U[1.5, 2.5]."""
     return _beta_image(2000 + i, n)
+
+
+# Parameter layout of the proposal network (64 -> 256 -> 256 -> 64): W of shape
+# (out, in) then b, layer by layer, concatenated.
+MLP_SHAPES = ((256, 64), (256,), (256, 256), (256,), (64, 256), (64,))
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Initial parameters (float32): He-uniform weights U(-sqrt(6/fan_in), +), zero biases,
+    rounded to the nearest float16 so that every consumer starts from the same values."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            bound = np.sqrt(6.0 / shape[1])
+            parts.append(rng.uniform(-bound, bound, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float16).astype(np.float32)
+
+
+def unit_rows_f16(n: int, seed: int = 0, dim: int = 64, n_dup: int = 0) -> np.ndarray:
+    """n random unit rows rounded to float16; the last n_dup rows repeat earlier rows
+    (exact ties)."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, dim))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    x = x.astype(np.float16)
+    if n_dup:
+        src = rng.integers(0, max(n - n_dup, 1), size=n_dup)
+        x[n - n_dup:] = x[src]
+    return x
+
+
+def grad_like(n: int, seed: int = 0, scale: float = 1e-2) -> np.ndarray:
+    """Synthetic float32 gradient: normal values with a spread of magnitudes and some zeros."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(n) * scale * np.exp(rng.uniform(-4, 2, size=n))
+    g[rng.random(n) < 0.05] = 0.0
+    return g.astype(np.float32)
