@@ -69,7 +69,7 @@ typedef struct {
     uint8_t iso;    /* isometry t, 0..7                                             */
     uint8_t s_idx;  /* position of the chosen k in the contrast set                 */
     uint8_t k;      /* contrast numerator: s = k / 10                               */
-    uint8_t flags;  /* reserved, 0                                                  */
+    uint8_t flags;  /* FIC_FLAG_FALLBACK (learned encoder only), else 0             */
     int16_t q_o;    /* offset of eq. (3) rounded half up to an integer              */
     int16_t pad_;
     float E;        /* e_num / (1600 n) in FP32 (for reporting; e_num is exact)     */
@@ -294,6 +294,91 @@ int fic_batch_get_chunks(const fic_batch* b, int32_t* chunks);
 int fic_batch_autotune(fic_batch* b, void* stream, int32_t reps, const char* cache_path,
                        float* best_ms);
 int fic_batch_destroy(fic_batch* b);
+
+/*
+ * Learned domain proposal: an extension of the exhaustive search of Section 2
+ * for 8 x 8 ranges. A network f (64 -> 256 -> 256 -> 64, ReLU after the first
+ * two layers, fp16 weights, fp32 accumulation) embeds a block vector x (the
+ * block's 64 values -- range pixels, or a domain's 2x2 sums -- mean removed
+ * and scaled to unit norm, zero for a constant block) as
+ *     g(x) = S / |S|,  S = sum over the 8 isometries T_t of f(T_t x),
+ * which is invariant under the isometries. The k domains whose embeddings
+ * have the largest dot product with a range's are its proposals. They are
+ * matched exactly (eq. (1) with the offset of eq. (3), all isometries and
+ * contrast values, ties as in the exhaustive matcher). A range whose best
+ * proposal fails the RMS test of Section 2 (E > rms^2 n) is matched against
+ * every domain instead.
+ *
+ * Parameters, flat fp32, FIC_MLP_PARAMS values: W1 [256][64], b1 [256],
+ * W2 [256][256], b2 [256], W3 [64][256], b3 [64], each W stored (out, in).
+ * A fic_mlp owns device copies of them, the Adam moments and scratch space.
+ * Calls on one fic_mlp must not overlap. Its entry points run on the device
+ * that was current at fic_mlp_create.
+ */
+#define FIC_MLP_PARAMS 98880
+#define FIC_FLAG_FALLBACK 1 /* fic_match.flags: the exhaustive search decided */
+typedef struct fic_mlp fic_mlp;
+/* init: [host] FIC_MLP_PARAMS finite values. tau > 0: similarity scale of the
+ * training loss. Synchronous. */
+int fic_mlp_create(const float* init, float tau, fic_mlp** out);
+int fic_mlp_destroy(fic_mlp* m);
+/* Current parameters into [host] out (FIC_MLP_PARAMS floats). Synchronises the device. */
+int fic_mlp_get_params(const fic_mlp* m, float* out);
+/*
+ * Embeddings of n blocks into out (device, fp16 bit patterns, [n][64]).
+ * kind 0: 8 x 8 ranges; list = device int32 [n][2] corners (y, x), or NULL
+ *         for the whole range grid in raster order (n = (H/8)(W/8)).
+ * kind 1: 16 x 16 domains on the step-L grid; list = device int32 [n] domain
+ *         indices, or NULL for every domain (n = grid size).
+ * H, W multiples of 8 and >= 16. A corner or index outside the image gives
+ * the embedding of a constant block.
+ */
+int fic_mlp_embed(fic_mlp* m, const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t kind,
+                  int32_t L, const int32_t* list, int32_t n, uint16_t* out, void* stream);
+/*
+ * Training loss and gradient. For the n_ranges ranges at range_yx (device
+ * int32 [n][2], or NULL for the whole grid) and every domain of the step-L
+ * grid: the mean over ranges of the softmax cross-entropy of the similarities
+ * g(r) . g(d_j) / tau against labels (device int32 [n], a domain index;
+ * a label outside the grid contributes nothing). loss_out: device float
+ * (may be NULL). grad_out: device float [FIC_MLP_PARAMS] (may be NULL; the
+ * gradient is also kept for fic_mlp_adam).
+ */
+int fic_mlp_loss_grad(fic_mlp* m, const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
+                      int32_t L, const int32_t* range_yx, const int32_t* labels, int32_t n_ranges,
+                      float* loss_out, float* grad_out, void* stream);
+/* One Adam step (bias-corrected) with grad (device float [FIC_MLP_PARAMS]) or,
+ * when grad is NULL, the last gradient fic_mlp_loss_grad computed. */
+int fic_mlp_adam(fic_mlp* m, const float* grad, float lr, float beta1, float beta2, float eps,
+                 void* stream);
+/* fic_mlp_loss_grad then fic_mlp_adam(lr, 0.9, 0.999, 1e-8). */
+int fic_mlp_train_step(fic_mlp* m, const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
+                       int32_t L, const int32_t* range_yx, const int32_t* labels,
+                       int32_t n_ranges, float lr, float* loss_out, void* stream);
+/*
+ * For each of nq query rows (device fp16 [nq][64], 16-byte aligned), the k
+ * (1..32) key rows (device fp16 [nk][64]) with the largest dot products,
+ * best first, ties to the lower key index: idx device int32 [nq][k], score
+ * device float [nq][k] (may be NULL). Dot products accumulate in fp32.
+ * m provides scratch space only.
+ */
+int fic_topk_similar(const uint16_t* q, int32_t nq, const uint16_t* keys, int32_t nk, int32_t k,
+                     int32_t* idx, float* score, fic_mlp* m, void* stream);
+/*
+ * Learned-proposal encode of the full 8 x 8 range grid (raster order) with
+ * domains on the step-L grid, contrast values s_k / 10 ([host] n_s values)
+ * and topk proposals (1..32) per range. out: device fic_match [(H/8)(W/8)];
+ * ranges decided by the exhaustive fallback carry FIC_FLAG_FALLBACK.
+ * proposals_out: device int32 [(H/8)(W/8)][topk] or NULL; n_fallback: device
+ * int32 or NULL.
+ */
+int fic_encode_level_learned(fic_mlp* m, const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
+                             int32_t L, const int8_t* s_k, int32_t n_s, int32_t topk,
+                             float rms_thresh, fic_match* out, int32_t* proposals_out,
+                             int32_t* n_fallback, void* stream);
+/* Codes (level 0) of a full range grid's matches, for fic_decode. */
+int fic_level_codes(const fic_match* m, int32_t H, int32_t W, int32_t B, int32_t L, fic_code* codes,
+                    void* stream);
 
 /* Message for the last non-zero return on this thread. */
 const char* fic_last_error(void);

@@ -18,6 +18,7 @@
 
 #include "fic_internal.h"
 #include "fic_kernels.hip"
+#include "fic_mlp_kernels.hip"
 
 #define FIC_API extern "C" __attribute__((visibility("default")))
 
@@ -1191,3 +1192,5 @@ FIC_API int fic_batch_destroy(fic_batch* b) {
     delete b;
     return FIC_OK;
 }
+
+#include "fic_learned_api.hip"

@@ -1,0 +1,689 @@
+// Device kernels of the learned domain proposal (an extension of the
+// exhaustive search of Section 2): a 64-256-256-64 network embeds 8 x 8 range
+// blocks and 2x2-summed domain blocks, the k most similar domains of each
+// range are rescored exactly with the moment form of eq. (1), and ranges whose
+// best proposal fails the RMS test fall back to the exhaustive matcher.
+//
+// Matrix products run on the fp16 MFMA (v_mfma_f32_16x16x32_f16, fp32
+// accumulation). Operand layout of that instruction on a 64-wide wave:
+//   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + e], e = 0..7
+//   B (32 x 16): lane l holds B[8 (l / 16) + e][l % 16]
+//   C (16 x 16): lane l holds C[4 (l / 16) + e][l % 16], e = 0..3
+// Every product here is C = A * B^T with both operands stored K-contiguous
+// ("NT"), so each lane's fragment is one 16-byte load.
+#include "fic_internal.h"
+
+namespace fic {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Parameter layout (fp32 master copy): W1 [256][64], b1, W2 [256][256], b2,
+// W3 [64][256], b3 -- each W stored (out, in).
+constexpr int kMlpIn = 64, kMlpHid = 256, kMlpOut = 64;
+constexpr int kOffW1 = 0, kOffB1 = 16384, kOffW2 = 16640, kOffB2 = 82176, kOffW3 = 82432,
+              kOffB3 = 98816, kMlpParams = 98880;
+// fp16 copies: W1, W2, W3 as above, then their transposes W1t [64][256],
+// W2t [256][256], W3t [256][64] (the operands of the backward products).
+constexpr int kH16W1 = 0, kH16W2 = 16384, kH16W3 = 81920, kH16W1t = 98304, kH16W2t = 114688,
+              kH16W3t = 180224, kH16Total = 196608;
+
+__device__ inline f4 mfma16(h8 a, h8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline int wave_sum_i32(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline float wave_sum_f32(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline float wave_max_f32(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int o) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor(lo, o, 64);
+    hi = __shfl_xor(hi, o, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// LDS writes by some lanes of a wave, then reads of them by other lanes.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------- block vectors
+// One wave per block; lane e holds element e (row e / 8, column e % 8). The
+// block's 64 values (range pixels, or the 2x2 sums of a domain) are centred
+// and scaled to unit norm -- exactly up to the final division: 64 v - sum v
+// and its squared norm are integers -- and written as the 8 rows T_t x,
+// t = 0..7 (row 8 q + t). A constant or out-of-image block gives zero rows.
+__global__ __launch_bounds__(256) void k_block_rows(const uint8_t* __restrict__ img, int pitch,
+                                                    int H, int W, int kind, int L, int gx,
+                                                    int total, const int32_t* __restrict__ list,
+                                                    int n, _Float16* __restrict__ X) {
+    const int q = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= n) return;
+    int y, x;
+    bool ok;
+    if (kind == 0) {
+        const int rgx = W / 8;
+        if (list) {
+            y = list[2 * q];
+            x = list[2 * q + 1];
+        } else {
+            y = (q / rgx) * 8;
+            x = (q % rgx) * 8;
+        }
+        ok = y >= 0 && x >= 0 && y + 8 <= H && x + 8 <= W;
+    } else {
+        const int j = list ? list[q] : q;
+        ok = j >= 0 && j < total;
+        y = ok ? (j / gx) * L : 0;
+        x = ok ? (j % gx) * L : 0;
+        ok = ok && y + 16 <= H && x + 16 <= W;
+    }
+    const int i = lane >> 3, c = lane & 7;
+    int v = 0;
+    if (ok) {
+        if (kind == 0) {
+            v = img[(int64_t)(y + i) * pitch + x + c];
+        } else {
+            const uint8_t* p = img + (int64_t)(y + 2 * i) * pitch + x + 2 * c;
+            v = p[0] + p[1] + p[pitch] + p[pitch + 1];
+        }
+    }
+    const int s = wave_sum_i32(v);
+    const int cen = 64 * v - s;
+    const int64_t nn = wave_sum_i64((int64_t)cen * cen);
+    const float xv = nn > 0 ? (float)cen / sqrtf((float)nn) : 0.0f;
+    _Float16* out = X + (int64_t)q * 8 * 64 + lane;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) out[t * 64] = (_Float16)__shfl(xv, iso_src(8, t, i, c), 64);
+}
+
+// ---------------------------------------------------------------- matrix product
+enum { kEpiRelu16 = 0, kEpiF32 = 1, kEpiMask16 = 2, kEpiPart32 = 3 };
+
+// C[m][n] = alpha * sum_k A[m][k] B[n][k] over k in this split's chunk, then
+//   kEpiRelu16: C16 = max(C + bias[n], 0)          (forward hidden layers)
+//   kEpiF32:    C32 = C + bias[n] (bias may be NULL)
+//   kEpiMask16: C16 = C if mask[m][n] > 0 else 0   (ReLU derivative)
+//   kEpiPart32: C32[split][m][n] = C               (split-K partial sums)
+// Workgroup tile 64 x 64 (2 x 2 waves of 32 x 32). Rows and columns past M, N
+// read the last valid row and are not stored. The K range of every split must
+// be a multiple of 32, and lda, ldb multiples of 8.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(const _Float16* __restrict__ A, int lda,
+                                                 const _Float16* __restrict__ B, int ldb, int M,
+                                                 int N, int kchunk, int ktot, float alpha,
+                                                 const float* __restrict__ bias,
+                                                 const _Float16* __restrict__ mask, int ldm,
+                                                 void* __restrict__ C, int ldc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(ktot, kb + kchunk);
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    const _Float16* a0 = A + (int64_t)min(m0 + r, M - 1) * lda + kq;
+    const _Float16* a1 = A + (int64_t)min(m0 + 16 + r, M - 1) * lda + kq;
+    const _Float16* b0 = B + (int64_t)min(n0 + r, N - 1) * ldb + kq;
+    const _Float16* b1 = B + (int64_t)min(n0 + 16 + r, N - 1) * ldb + kq;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k = kb; k < ke; k += 32) {
+        const h8 fa0 = *reinterpret_cast<const h8*>(a0 + k);
+        const h8 fa1 = *reinterpret_cast<const h8*>(a1 + k);
+        const h8 fb0 = *reinterpret_cast<const h8*>(b0 + k);
+        const h8 fb1 = *reinterpret_cast<const h8*>(b1 + k);
+        acc[0][0] = mfma16(fa0, fb0, acc[0][0]);
+        acc[0][1] = mfma16(fa0, fb1, acc[0][1]);
+        acc[1][0] = mfma16(fa1, fb0, acc[1][0]);
+        acc[1][1] = mfma16(fa1, fb1, acc[1][1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + 16 * j + (lane & 15);
+            if (col >= N) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + 16 * i + 4 * (lane >> 4) + e;
+                if (row >= M) continue;
+                const float v = alpha * acc[i][j][e];
+                const int64_t at = (int64_t)row * ldc + col;
+                if (EPI == kEpiRelu16) {
+                    static_cast<_Float16*>(C)[at] = (_Float16)fmaxf(v + bias[col], 0.0f);
+                } else if (EPI == kEpiF32) {
+                    static_cast<float*>(C)[at] = v + (bias ? bias[col] : 0.0f);
+                } else if (EPI == kEpiMask16) {
+                    const bool on = (float)mask[(int64_t)row * ldm + col] > 0.0f;
+                    static_cast<_Float16*>(C)[at] = (_Float16)(on ? v : 0.0f);
+                } else {
+                    static_cast<float*>(C)[(int64_t)blockIdx.z * M * ldc + at] = v;
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------- embedding
+// S_q = sum_t Y[8 q + t]; G_q = S_q / |S_q| (0 if S_q = 0). One wave per block.
+__global__ __launch_bounds__(256) void k_iso_norm(const float* __restrict__ Y, int n,
+                                                  float* __restrict__ G32, float* __restrict__ nrm,
+                                                  _Float16* __restrict__ G16) {
+    const int q = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= n) return;
+    const float* y = Y + (int64_t)q * 8 * 64 + lane;
+    float s = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s += y[t * 64];
+    const float nn = sqrtf(wave_sum_f32(s * s));
+    const float g = nn > 0.0f ? s / nn : 0.0f;
+    if (G32) G32[(int64_t)q * 64 + lane] = g;
+    if (nrm && lane == 0) nrm[q] = nn;
+    G16[(int64_t)q * 64 + lane] = (_Float16)g;
+}
+
+// ---------------------------------------------------------------- loss
+// One workgroup per range: z = Z[r][0..nd) (similarities / tau), label y.
+// loss[r] = logsumexp(z) - z_y; P[r][j] = softmax(z)_j - [j = y] (fp16), zero
+// for nd <= j < ldp. A label outside 0..nd-1 zeroes the row (no loss).
+__global__ __launch_bounds__(256) void k_softmax_ce(const float* __restrict__ Z, int ldz, int nd,
+                                                    const int32_t* __restrict__ labels,
+                                                    _Float16* __restrict__ P, int ldp,
+                                                    float* __restrict__ loss) {
+    __shared__ float red[4];
+    const int r = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const float* z = Z + (int64_t)r * ldz;
+    _Float16* p = P + (int64_t)r * ldp;
+    const int y = labels[r];
+    if (y < 0 || y >= nd) {
+        for (int j = tid; j < ldp; j += 256) p[j] = (_Float16)0.0f;
+        if (tid == 0) loss[r] = 0.0f;
+        return;
+    }
+    float m = -INFINITY;
+    for (int j = tid; j < nd; j += 256) m = fmaxf(m, z[j]);
+    m = wave_max_f32(m);
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    __syncthreads();
+    float s = 0.0f;
+    for (int j = tid; j < nd; j += 256) s += __expf(z[j] - m);
+    s = wave_sum_f32(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    s = red[0] + red[1] + red[2] + red[3];
+    const float lse = m + __logf(s);
+    for (int j = tid; j < ldp; j += 256) {
+        float v = 0.0f;
+        if (j < nd) v = __expf(z[j] - lse) - (j == y ? 1.0f : 0.0f);
+        p[j] = (_Float16)v;
+    }
+    if (tid == 0) loss[r] = lse - z[y];
+}
+
+// mean of n values (one workgroup)
+__global__ __launch_bounds__(256) void k_mean(const float* __restrict__ v, int n, float* __restrict__ out) {
+    __shared__ float red[4];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) s += v[i];
+    s = wave_sum_f32(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (red[0] + red[1] + red[2] + red[3]) / (float)max(n, 1);
+}
+
+// out[c][r] = in[r][c] for r < rows, c < cols; zero for rows <= r < rows_pad.
+__global__ __launch_bounds__(256) void k_transpose16(const _Float16* __restrict__ in, int ldi,
+                                                     int rows, int cols,
+                                                     _Float16* __restrict__ out, int ldo,
+                                                     int rows_pad) {
+    __shared__ _Float16 tile[64][65];
+    const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int r = r0 + i, c = c0 + tx;
+        tile[i][tx] = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : (_Float16)0.0f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int c = c0 + i, r = r0 + tx;
+        if (c < cols && r < rows_pad) out[(int64_t)c * ldo + r] = tile[tx][i];
+    }
+}
+
+// dS = (dG - G (G . dG)) / |S| for each block; records max |dS| (float bits).
+__global__ __launch_bounds__(256) void k_norm_bwd(const float* __restrict__ dG,
+                                                  const float* __restrict__ G,
+                                                  const float* __restrict__ nrm, int n,
+                                                  float* __restrict__ dS,
+                                                  uint32_t* __restrict__ maxbits) {
+    const int q = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= n) return;
+    const int64_t at = (int64_t)q * 64 + lane;
+    const float g = G[at], dg = dG[at], nn = nrm[q];
+    const float dot = wave_sum_f32(g * dg);
+    const float v = nn > 0.0f ? (dg - g * dot) / nn : 0.0f;
+    dS[at] = v;
+    const float mx = wave_max_f32(fabsf(v));
+    if (lane == 0) atomicMax(maxbits, __float_as_uint(mx));
+}
+
+// Power-of-two scale that brings max |dS| near 2^10 for the fp16 backward.
+__device__ inline float grad_scale(uint32_t maxbits) {
+    const float mx = __uint_as_float(maxbits);
+    if (!(mx > 0.0f) || !isfinite(mx)) return 1.0f;
+    const int e = 10 - (int)ceilf(log2f(mx));
+    return ldexpf(1.0f, max(-60, min(60, e)));
+}
+
+// dY16[8 q + t] = fp16(dS_q * scale) for every isometry t.
+__global__ __launch_bounds__(256) void k_expand_grad(const float* __restrict__ dS, int n,
+                                                     const uint32_t* __restrict__ maxbits,
+                                                     _Float16* __restrict__ dY) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)n * 8 * 64) return;
+    const int64_t q = i >> 9;
+    const int e = (int)(i & 63);
+    dY[i] = (_Float16)(dS[q * 64 + e] * grad_scale(*maxbits));
+}
+
+// out[c] = sum_r At[c][r] (one workgroup per c)
+__global__ __launch_bounds__(256) void k_row_sums(const _Float16* __restrict__ At, int ld, int len,
+                                                  float* __restrict__ out) {
+    __shared__ float red[4];
+    const _Float16* a = At + (int64_t)blockIdx.x * ld;
+    float s = 0.0f;
+    for (int r = threadIdx.x; r < len; r += 256) s += (float)a[r];
+    s = wave_sum_f32(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// grad[i] = (sum over splits of part[s][i]) * scale / grad_scale
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ part, int splits,
+                                                     int count, float scale,
+                                                     const uint32_t* __restrict__ maxbits,
+                                                     float* __restrict__ grad) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * count + i];
+    grad[i] = s * scale / grad_scale(*maxbits);
+}
+
+// bias gradients: grad[i] = sums[i] * scale / grad_scale
+__global__ void k_scale_into(const float* __restrict__ sums, int count, float scale,
+                             const uint32_t* __restrict__ maxbits, float* __restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) grad[i] = sums[i] * scale / grad_scale(*maxbits);
+}
+
+// Adam with bias correction (bc1 = 1 - beta1^t, bc2 = 1 - beta2^t); writes
+// the fp16 weight copies and their transposes.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, float* __restrict__ m,
+                                              float* __restrict__ v,
+                                              const float* __restrict__ g, float lr, float beta1,
+                                              float beta2, float eps, float bc1, float bc2,
+                                              _Float16* __restrict__ w16) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kMlpParams) return;
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[i] = wi;
+    const _Float16 h = (_Float16)wi;
+    if (i >= kOffW1 && i < kOffB1) {
+        const int o = (i - kOffW1) / kMlpIn, k = (i - kOffW1) % kMlpIn;
+        w16[kH16W1 + o * kMlpIn + k] = h;
+        w16[kH16W1t + k * kMlpHid + o] = h;
+    } else if (i >= kOffW2 && i < kOffB2) {
+        const int o = (i - kOffW2) / kMlpHid, k = (i - kOffW2) % kMlpHid;
+        w16[kH16W2 + o * kMlpHid + k] = h;
+        w16[kH16W2t + k * kMlpHid + o] = h;
+    } else if (i >= kOffW3 && i < kOffB3) {
+        const int o = (i - kOffW3) / kMlpHid, k = (i - kOffW3) % kMlpHid;
+        w16[kH16W3 + o * kMlpHid + k] = h;
+        w16[kH16W3t + k * kMlpOut + o] = h;
+    }
+}
+
+// fp16 copies (and transposes) of the master weights
+__global__ __launch_bounds__(256) void k_weights16(const float* __restrict__ w, _Float16* __restrict__ w16) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kMlpParams) return;
+    const _Float16 h = (_Float16)w[i];
+    if (i < kOffB1) {
+        const int o = i / kMlpIn, k = i % kMlpIn;
+        w16[kH16W1 + o * kMlpIn + k] = h;
+        w16[kH16W1t + k * kMlpHid + o] = h;
+    } else if (i >= kOffW2 && i < kOffB2) {
+        const int o = (i - kOffW2) / kMlpHid, k = (i - kOffW2) % kMlpHid;
+        w16[kH16W2 + o * kMlpHid + k] = h;
+        w16[kH16W2t + k * kMlpHid + o] = h;
+    } else if (i >= kOffW3 && i < kOffB3) {
+        const int o = (i - kOffW3) / kMlpHid, k = (i - kOffW3) % kMlpHid;
+        w16[kH16W3 + o * kMlpHid + k] = h;
+        w16[kH16W3t + k * kMlpOut + o] = h;
+    }
+}
+
+// ---------------------------------------------------------------- top-k similarity
+constexpr int kTopK = 32;    // largest proposal count
+constexpr int kTkRows = 32;  // ranges per wave
+constexpr int kTkCap = 64;   // candidate slots per range
+constexpr int kTkWaves = 4;
+
+// Ordered key: larger key = larger score, then lower domain index.
+__device__ inline uint64_t tk_key(float s, int d) {
+    uint32_t u = __float_as_uint(s);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)u << 32) | (uint32_t)(~(uint32_t)d);
+}
+
+__device__ inline float tk_score(uint64_t key) {
+    uint32_t u = (uint32_t)(key >> 32);
+    u = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    return __uint_as_float(u);
+}
+
+__device__ inline int tk_index(uint64_t key) { return (int)(~(uint32_t)key); }
+
+// Bitonic sort of one key per lane, descending across the wave.
+__device__ inline uint64_t wave_sort_desc(uint64_t v, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t o = shfl_xor_u64(v, j);
+            const bool take_max = ((lane & j) == 0) == ((lane & k) == 0);
+            v = take_max ? (v > o ? v : o) : (v < o ? v : o);
+        }
+    return v;
+}
+
+// Keep the 32 best of a range's slots; its threshold becomes the 32nd best
+// score (none while fewer than 32 are held).
+__device__ inline void tk_merge_row(uint64_t* buf, int* cnt, float* thr, int lane) {
+    const int c = *cnt;
+    uint64_t v = lane < c ? buf[lane] : 0ull;
+    v = wave_sort_desc(v, lane);
+    wave_lds_sync();
+    if (lane < kTopK) buf[lane] = v;
+    if (lane == kTopK - 1) *thr = c >= kTopK ? tk_score(v) : -INFINITY;
+    if (lane == 0) *cnt = min(c, kTopK);
+    wave_lds_sync();
+}
+
+// Each wave scores 32 ranges against the domains of one segment with MFMA and
+// keeps, per range, every score above the range's running threshold in LDS;
+// the slots are pruned back to the best 32 before they can overflow. Exact:
+// a domain is dropped only when 32 domains of lower index score at least as
+// high. Output: the segment's best 32 keys per range, descending (0 = none).
+__global__ __launch_bounds__(256) void k_topk_sim(const _Float16* __restrict__ GR, int nr,
+                                                  const _Float16* __restrict__ GD, int nd,
+                                                  int seg_len, uint64_t* __restrict__ out) {
+    __shared__ uint64_t sbuf[kTkWaves][kTkRows][kTkCap];
+    __shared__ int scnt[kTkWaves][kTkRows];
+    __shared__ float sthr[kTkWaves][kTkRows];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r0 = (blockIdx.x * kTkWaves + wave) * kTkRows;
+    if (r0 >= nr) return;
+    const int seg = blockIdx.y;
+    const int d_lo = seg * seg_len, d_hi = min(nd, d_lo + seg_len);
+    if (lane < kTkRows) {
+        scnt[wave][lane] = 0;
+        sthr[wave][lane] = -INFINITY;
+    }
+    wave_lds_sync();
+    const int kq = (lane >> 4) * 8;
+    h8 a[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const _Float16* pa = GR + (int64_t)min(r0 + 16 * rt + (lane & 15), nr - 1) * 64 + kq;
+        a[rt][0] = *reinterpret_cast<const h8*>(pa);
+        a[rt][1] = *reinterpret_cast<const h8*>(pa + 32);
+    }
+    float th[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) th[rt][e] = -INFINITY;
+    bool rowok[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rowok[rt][e] = r0 + 16 * rt + 4 * (lane >> 4) + e < nr;
+
+    for (int d0 = d_lo; d0 < d_hi; d0 += 16) {
+        const int dcol = d0 + (lane & 15);
+        const _Float16* pb = GD + (int64_t)min(dcol, nd - 1) * 64 + kq;
+        const h8 b0 = *reinterpret_cast<const h8*>(pb);
+        const h8 b1 = *reinterpret_cast<const h8*>(pb + 32);
+        const bool colok = dcol < d_hi;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma16(a[rt][0], b0, acc);
+            acc = mfma16(a[rt][1], b1, acc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float s = acc[e];
+                if (colok && rowok[rt][e] && s > th[rt][e]) {
+                    const int row = 16 * rt + 4 * (lane >> 4) + e;
+                    const int pos = atomicAdd(&scnt[wave][row], 1);
+                    sbuf[wave][row][pos] = tk_key(s, dcol);
+                }
+            }
+        }
+        wave_lds_sync();
+        const int c = lane < kTkRows ? scnt[wave][lane] : 0;
+        uint64_t need = __ballot(c > kTkCap - 16);
+        if (need) {
+            while (need) {
+                const int row = __ffsll((unsigned long long)need) - 1;
+                need &= need - 1;
+                tk_merge_row(sbuf[wave][row], &scnt[wave][row], &sthr[wave][row], lane);
+            }
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) th[rt][e] = sthr[wave][16 * rt + 4 * (lane >> 4) + e];
+        }
+    }
+    for (int row = 0; row < kTkRows && r0 + row < nr; ++row) {
+        const int c = scnt[wave][row];
+        uint64_t v = lane < c ? sbuf[wave][row][lane] : 0ull;
+        v = wave_sort_desc(v, lane);
+        if (lane < kTopK) out[((int64_t)seg * nr + r0 + row) * kTopK + lane] = v;
+    }
+}
+
+// Best k of the segments' lists per range (one wave per range).
+__global__ __launch_bounds__(256) void k_topk_merge(const uint64_t* __restrict__ keys, int nseg,
+                                                    int nr, int k, int32_t* __restrict__ idx,
+                                                    float* __restrict__ score) {
+    const int r = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= nr) return;
+    uint64_t v = lane < kTopK ? keys[(int64_t)r * kTopK + lane] : 0ull;
+    for (int s = 1; s < nseg; ++s) {
+        if (lane >= kTopK) v = keys[((int64_t)s * nr + r) * kTopK + lane - kTopK];
+        v = wave_sort_desc(v, lane);
+    }
+    if (lane < k) {
+        idx[(int64_t)r * k + lane] = v ? tk_index(v) : -1;
+        if (score) score[(int64_t)r * k + lane] = v ? tk_score(v) : -INFINITY;
+    }
+}
+
+// ---------------------------------------------------------------- exact rescoring
+// One workgroup per 8 x 8 range of the grid; thread = (proposal c = tid / 8,
+// isometry t = tid % 8). Evaluates the distance of eq. (1) exactly over the
+// range's proposals, isometries and contrast values (same moment form and tie
+// order as the exhaustive matcher), writes the match, and appends the range to
+// the fallback list when 1600 n E > thr.
+__global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img, int pitch,
+                                                 int W, int L, int gx, int total,
+                                                 const int32_t* __restrict__ cand, int kc,
+                                                 int nr, KSet ks, int64_t thr,
+                                                 fic_match* __restrict__ out,
+                                                 int32_t* __restrict__ fb_act,
+                                                 int32_t* __restrict__ fb_q,
+                                                 int32_t* __restrict__ fb_count) {
+    __shared__ int sr[64];
+    __shared__ int sd[kTopK][64];
+    __shared__ int64_t redF[4], redK[4];
+    const int q = blockIdx.x, tid = threadIdx.x;
+    if (q >= nr) return;
+    const int rgx = W / 8;
+    const int y = (q / rgx) * 8, x = (q % rgx) * 8;
+    if (tid < 64) sr[tid] = img[(int64_t)(y + (tid >> 3)) * pitch + x + (tid & 7)];
+    for (int e = tid; e < kTopK * 64; e += 256) {
+        const int c = e >> 6, m = e & 63;
+        const int j = c < kc ? cand[(int64_t)q * kc + c] : -1;
+        int v = 0;
+        if (j >= 0 && j < total) {
+            const uint8_t* p = img + (int64_t)((j / gx) * L + 2 * (m >> 3)) * pitch + (j % gx) * L + 2 * (m & 7);
+            v = p[0] + p[1] + p[pitch] + p[pitch + 1];
+        }
+        sd[c][m] = v;
+    }
+    __syncthreads();
+    const int c = tid >> 3, t = tid & 7;
+    const int j = c < kc ? cand[(int64_t)q * kc + c] : -1;
+    int64_t F = INT64_MAX, K = INT64_MAX;
+    int SR = 0, SR2 = 0;
+    for (int e = 0; e < 64; ++e) {
+        SR += sr[e];
+        SR2 += sr[e] * sr[e];
+    }
+    if (j >= 0 && j < total) {
+        int S = 0, Pc = 0;
+        int64_t S2 = 0;
+        for (int e = 0; e < 64; ++e) {
+            const int d = sd[c][e];
+            S += d;
+            S2 += d * d;
+            Pc += sr[e] * sd[c][iso_src(8, t, e >> 3, e & 7)];
+        }
+        const int64_t Ap = 64 * S2 - (int64_t)S * S;
+        const int64_t Bp = 64 * (int64_t)Pc - (int64_t)SR * S;
+        int s;
+        best_contrast(Bp, Ap, ks, F, s);
+        K = make_key(j, t, s, (uint32_t)S);
+    }
+    // workgroup argmin of (F, K)
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t f2 = __shfl_xor(F, o, 64), k2 = __shfl_xor(K, o, 64);
+        if (pair_less(f2, k2, F, K)) {
+            F = f2;
+            K = k2;
+        }
+    }
+    if ((tid & 63) == 0) {
+        redF[tid >> 6] = F;
+        redK[tid >> 6] = K;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    for (int w = 1; w < 4; ++w)
+        if (pair_less(redF[w], redK[w], F, K)) {
+            F = redF[w];
+            K = redK[w];
+        }
+    fic_match m;
+    m.flags = 0;
+    m.pad_ = 0;
+    if (K == INT64_MAX) {  // no proposal at all: exhaustive search decides
+        m.e_num = -1;
+        m.dom = -1;
+        m.iso = 0;
+        m.s_idx = 0;
+        m.k = 0;
+        m.q_o = 0;
+        m.E = -1.0f;
+    } else {
+        const int64_t CR = 64 * (int64_t)SR2 - (int64_t)SR * SR;
+        const int jj = (int)(K >> 27), tt = (int)((K >> 24) & 7), ss = (int)((K >> 20) & 15);
+        const int64_t sdom = K & 0xfffff;
+        const int k = ks.consecutive ? ks.k0 + ss : ks.k[ss];
+        m.e_num = F + 1600 * CR;
+        m.dom = jj;
+        m.iso = (uint8_t)tt;
+        m.s_idx = (uint8_t)ss;
+        m.k = (uint8_t)k;
+        m.q_o = (int16_t)floordiv64(2 * (40 * (int64_t)SR - k * sdom) + 40 * 64, 80 * 64);
+        m.E = (float)m.e_num / (1600.0f * 64.0f);
+    }
+    out[q] = m;
+    if (K == INT64_MAX || m.e_num > thr) {
+        const int pos = atomicAdd(fb_count, 1);
+        fb_act[pos] = (y << 16) | x;
+        fb_q[pos] = q;
+    }
+}
+
+// out[fb_q[p]] = exhaustive match p, flagged as a fallback
+__global__ void k_fallback_scatter(const fic_match* __restrict__ tmp, const int32_t* __restrict__ fb_q,
+                                   const int32_t* __restrict__ fb_count, fic_match* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *fb_count) return;
+    fic_match m = tmp[p];
+    m.flags |= FIC_FLAG_FALLBACK;
+    out[fb_q[p]] = m;
+}
+
+// Level codes of a full range grid (single-level encodes, for the decoder).
+__global__ void k_level_codes(const fic_match* __restrict__ m, int nr, int W, int B, int L, int gx,
+                              fic_code* __restrict__ codes) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nr) return;
+    const fic_match a = m[q];
+    const int rgx = W / B;
+    fic_code c;
+    c.e_num = a.e_num;
+    c.dom = a.dom;
+    c.y = (int16_t)((q / rgx) * B);
+    c.x = (int16_t)((q % rgx) * B);
+    c.dy = (int16_t)(a.dom >= 0 ? (a.dom / gx) * L : 0);
+    c.dx = (int16_t)(a.dom >= 0 ? (a.dom % gx) * L : 0);
+    c.q_o = a.q_o;
+    c.log2B = (uint8_t)(31 - __clz(B));
+    c.iso = a.iso;
+    c.k = a.k;
+    c.s_idx = a.s_idx;
+    c.level = 0;
+    for (int i = 0; i < 5; ++i) c.pad_[i] = 0;
+    codes[q] = c;
+}
+
+}  // namespace fic

@@ -110,11 +110,25 @@ def load():
     lib.fic_batch_get_chunks.argtypes = [vp, vp]
     lib.fic_batch_autotune.argtypes = [vp, vp, i32, ctypes.c_char_p, ctypes.POINTER(f32)]
     lib.fic_batch_destroy.argtypes = [vp]
+    lib.fic_mlp_create.argtypes = [vp, f32, ctypes.POINTER(vp)]
+    lib.fic_mlp_destroy.argtypes = [vp]
+    lib.fic_mlp_get_params.argtypes = [vp, vp]
+    lib.fic_mlp_embed.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, i32, vp, vp]
+    lib.fic_mlp_loss_grad.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, i32, vp, vp, vp]
+    lib.fic_mlp_adam.argtypes = [vp, vp, f32, f32, f32, f32, vp]
+    lib.fic_mlp_train_step.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, i32, f32, vp, vp]
+    lib.fic_topk_similar.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp, vp]
+    lib.fic_encode_level_learned.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, i32, f32, vp, vp,
+                                             vp, vp]
+    lib.fic_level_codes.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     lib.fic_last_error.restype = ctypes.c_char_p
     for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_image", "fic_decode", "fic_sse",
                  "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end",
                  "fic_batch_create", "fic_batch_run", "fic_batch_run_eager", "fic_batch_set_chunks", "fic_batch_get_chunks",
-                 "fic_batch_autotune", "fic_batch_destroy"):
+                 "fic_batch_autotune", "fic_batch_destroy", "fic_mlp_create", "fic_mlp_destroy",
+                 "fic_mlp_get_params", "fic_mlp_embed", "fic_mlp_loss_grad", "fic_mlp_adam",
+                 "fic_mlp_train_step", "fic_topk_similar", "fic_encode_level_learned",
+                 "fic_level_codes"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -272,6 +286,129 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+MLP_PARAMS = 98880
+FLAG_FALLBACK = 1
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Mlp:
+    """fic_mlp_*: the learned domain proposal network (64-256-256-64) with its
+    Adam state. ``init`` is a flat float32 parameter vector (see include/fic.h)."""
+
+    def __init__(self, init, tau: float = 0.1):
+        init = np.ascontiguousarray(init, dtype=np.float32)
+        if init.size != MLP_PARAMS:
+            raise ValueError(f"init must hold {MLP_PARAMS} values")
+        self.tau = tau
+        self._init = init
+        self._h = ctypes.c_void_p()
+        _check(load().fic_mlp_create(init.ctypes.data, tau, ctypes.byref(self._h)))
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(load().fic_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def embed(self, img, kind: int, L: int = 4, idx=None, stream=None):
+        """fp16 [n, 64] embeddings of ranges (kind 0; idx = [n, 2] corners) or domains
+        (kind 1; idx = [n] indices); idx None = all of them."""
+        import torch
+        img = _dev_u8_image(img)
+        H, W = img.shape
+        if idx is not None:
+            idx = idx.to(device=img.device, dtype=torch.int32).contiguous()
+            n = idx.shape[0]
+        elif kind == 0:
+            n = (H // 8) * (W // 8)
+        else:
+            n = ((H - 16) // L + 1) * ((W - 16) // L + 1)
+        out = torch.empty((max(n, 1), 64), dtype=torch.float16, device=img.device)
+        _check(load().fic_mlp_embed(self._h, img.data_ptr(), H, W, img.stride(0), kind, L, _ptr(idx),
+                                    n, out.data_ptr(), _stream(stream)))
+        return out[:n]
+
+    def loss_grad(self, img, L: int, labels, ranges=None, stream=None):
+        """(mean loss [1], gradient [MLP_PARAMS]) as float32 device tensors."""
+        import torch
+        img = _dev_u8_image(img)
+        H, W = img.shape
+        labels = labels.to(device=img.device, dtype=torch.int32).contiguous()
+        if ranges is not None:
+            ranges = ranges.to(device=img.device, dtype=torch.int32).contiguous()
+        loss = torch.zeros(1, dtype=torch.float32, device=img.device)
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=img.device)
+        _check(load().fic_mlp_loss_grad(self._h, img.data_ptr(), H, W, img.stride(0), L, _ptr(ranges),
+                                        labels.data_ptr(), labels.shape[0], loss.data_ptr(),
+                                        grad.data_ptr(), _stream(stream)))
+        return loss, grad
+
+    def adam(self, grad=None, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, stream=None):
+        _check(load().fic_mlp_adam(self._h, _ptr(grad), lr, beta1, beta2, eps, _stream(stream)))
+
+    def train_step(self, img, L: int, labels, ranges=None, lr: float = 1e-3, loss=None, stream=None):
+        import torch
+        img = _dev_u8_image(img)
+        H, W = img.shape
+        if ranges is not None:
+            ranges = ranges.to(device=img.device, dtype=torch.int32).contiguous()
+        loss = torch.zeros(1, dtype=torch.float32, device=img.device) if loss is None else loss
+        _check(load().fic_mlp_train_step(self._h, img.data_ptr(), H, W, img.stride(0), L, _ptr(ranges),
+                                         labels.data_ptr(), labels.shape[0], lr, loss.data_ptr(),
+                                         _stream(stream)))
+        return loss
+
+    def topk(self, q, keys, k: int, stream=None):
+        """(idx int32 [nq, k], score float32 [nq, k]) of fp16 [n, 64] device tensors."""
+        import torch
+        q = q.contiguous()
+        keys = keys.contiguous()
+        idx = torch.empty((max(q.shape[0], 1), k), dtype=torch.int32, device=q.device)
+        score = torch.empty((max(q.shape[0], 1), k), dtype=torch.float32, device=q.device)
+        _check(load().fic_topk_similar(q.data_ptr(), q.shape[0], keys.data_ptr(), keys.shape[0], k,
+                                       idx.data_ptr(), score.data_ptr(), self._h, _stream(stream)))
+        return idx[:q.shape[0]], score[:q.shape[0]]
+
+    def encode_level(self, img, L: int = 4, s_k=PLAIN_K, topk: int = 32, rms: float = 8.0,
+                     return_proposals: bool = False, stream=None):
+        """fic_encode_level_learned: (matches uint8 [nr, 24], n_fallback int32 [1][, proposals])."""
+        import torch
+        img = _dev_u8_image(img)
+        H, W = img.shape
+        nr = (H // 8) * (W // 8)
+        ks = (ctypes.c_int8 * max(1, len(s_k)))(*[int(k) for k in s_k])
+        out = torch.empty((max(nr, 1), 24), dtype=torch.uint8, device=img.device)
+        nfb = torch.zeros(1, dtype=torch.int32, device=img.device)
+        props = torch.empty((max(nr, 1), topk), dtype=torch.int32, device=img.device) if return_proposals else None
+        _check(load().fic_encode_level_learned(self._h, img.data_ptr(), H, W, img.stride(0), L, ks, len(s_k),
+                                               topk, rms, out.data_ptr(), _ptr(props), nfb.data_ptr(),
+                                               _stream(stream)))
+        return (out[:nr], nfb, props[:nr]) if return_proposals else (out[:nr], nfb)
+
+    def close(self):
+        if self._h:
+            load().fic_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def level_codes(matches, H: int, W: int, B: int, L: int, stream=None):
+    """fic_level_codes: uint8 [nr, 32] codes of a full range grid's matches."""
+    import torch
+    nr = (H // B) * (W // B)
+    codes = torch.empty((max(nr, 1), 32), dtype=torch.uint8, device=matches.device)
+    _check(load().fic_level_codes(matches.data_ptr(), H, W, B, L, codes.data_ptr(), _stream(stream)))
+    return codes[:nr]
 
 
 def decode(codes, n_codes: int, H: int, W: int, iters: int = 64, stream=None):

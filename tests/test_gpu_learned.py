@@ -1,0 +1,327 @@
+"""Learned domain proposal on the GPU against the fp64 oracle: embeddings,
+cross-entropy gradients, Adam, the similarity top-k, the proposal encoder
+(exact over its proposals, exhaustive fallback) and training."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as ol
+from paper_1501_04140_amd import fic, synth
+
+from test_gpu_parity import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# fp16 rounding of the block vector and of both hidden layers (unit roundoff
+# 2^-11 each), fp32 accumulation, and the fp16 output: a few 1e-3 absolute on
+# unit-norm embeddings, with margin.
+EMB_ATOL = 1e-2
+EMB_COS = 0.999
+# gradients: the same roundings plus the fp16 softmax residuals and the fp16
+# backward operands, relative in the Euclidean norm of each tensor
+GRAD_REL = 5e-2
+GRAD_COS = 0.998
+# dot products of fp16 rows in fp32: 64 exact products, rounding of the sum
+DOT_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fic.load()
+    return torch.device("cuda:0")
+
+
+def theta_with_biases(seed):
+    theta = synth.mlp_init(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    o = 0
+    for name, shape in ol.SHAPES:
+        size = int(np.prod(shape))
+        if name.startswith("b"):
+            theta[o:o + size] = rng.uniform(-0.1, 0.1, size=size).astype(np.float32)
+        o += size
+    return theta.astype(np.float32)
+
+
+def identity_theta():
+    p = {name: np.zeros(shape, np.float32) for name, shape in ol.SHAPES}
+    p["W1"][:64] = np.eye(64)
+    p["W1"][64:128] = -np.eye(64)
+    p["W2"][:] = np.eye(256)
+    p["W3"][:, :64] = np.eye(64)
+    p["W3"][:, 64:128] = -np.eye(64)
+    return np.concatenate([p[name].ravel() for name, _ in ol.SHAPES])
+
+
+def check_embeddings(got, ref, what):
+    got = got.float().cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max()
+    cos = (got * ref).sum(1) / np.maximum(np.linalg.norm(got, axis=1) * np.linalg.norm(ref, axis=1), 1e-30)
+    nz = np.linalg.norm(ref, axis=1) > 0
+    say(f"[learned] {what}: max abs err {err:.2e}, min cos {cos[nz].min():.6f}")
+    assert err <= EMB_ATOL
+    assert cos[nz].min() >= EMB_COS
+
+
+@pytest.mark.parametrize("shape,L", [((64, 64), 4), ((48, 80), 4), ((40, 40), 2)])
+def test_identity_network_embeds_orbit_sums(dev, shape, L):
+    """f(u) = u exactly in fp16: g is the normalised sum of the 8 isometric copies."""
+    img = synth.power_law(*shape, beta=2.0, seed=3)
+    x = torch.from_numpy(img).to(dev)
+    theta = identity_theta()
+    m = fic.Mlp(theta)
+    try:
+        H, W = shape
+        g_r = m.embed(x, 0)
+        g_d = m.embed(x, 1, L)
+        torch.cuda.synchronize()
+        ref_r, _ = ol.embed(theta, ol.block_vectors(ol.range_blocks(img, oracle.full_ranges(H, W, 8))))
+        ref_d, _ = ol.embed(theta, ol.block_vectors(ol.domain_blocks(img, L)))
+        got = g_r.float().cpu().numpy()
+        assert np.abs(got - ref_r).max() < 2e-3
+        assert np.abs(g_d.float().cpu().numpy() - ref_d).max() < 2e-3
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_embeddings_match_oracle(dev, seed):
+    img = synth.power_law(64, 80, beta=1.8, seed=seed, n_rect=1)
+    x = torch.from_numpy(img).to(dev)
+    theta = theta_with_biases(seed)
+    m = fic.Mlp(theta)
+    try:
+        ranges = np.array([[0, 0], [8, 72], [56, 40], [-8, 0], [60, 0]], np.int32)  # two invalid corners
+        dom = np.array([0, 5, 220, 13, 999], np.int32)  # 999 is outside the grid
+        g_all = m.embed(x, 0)
+        g_r = m.embed(x, 0, idx=torch.from_numpy(ranges))
+        g_d = m.embed(x, 1, 4, idx=torch.from_numpy(dom))
+        gd_all = m.embed(x, 1, 4)
+        torch.cuda.synchronize()
+        ref_all, _ = ol.embed(theta, ol.block_vectors(ol.range_blocks(img, oracle.full_ranges(64, 80, 8))))
+        check_embeddings(g_all, ref_all, "ranges")
+        blocks = np.zeros((5, 64))
+        blocks[:3] = ol.range_blocks(img, ranges[:3])
+        ref_r, _ = ol.embed(theta, ol.block_vectors(blocks))  # invalid corners: constant block
+        check_embeddings(g_r, ref_r, "range list")
+        dblocks = np.zeros((5, 64))
+        dblocks[:4] = ol.domain_blocks(img, 4, dom[:4])
+        ref_d, _ = ol.embed(theta, ol.block_vectors(dblocks))
+        check_embeddings(g_d, ref_d, "domain list")
+        ref_dall, _ = ol.embed(theta, ol.block_vectors(ol.domain_blocks(img, 4)))
+        check_embeddings(gd_all, ref_dall, "domains")
+    finally:
+        m.close()
+
+
+def grad_errors(got, ref):
+    out = []
+    o = 0
+    for name, shape in ol.SHAPES:
+        size = int(np.prod(shape))
+        a, b = got[o:o + size], ref[o:o + size]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        cos = (a @ b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
+        out.append((name, rel, cos))
+        o += size
+    return out
+
+
+@pytest.mark.parametrize("shape,L,subset,tau", [((48, 48), 4, False, 0.1), ((64, 80), 4, True, 0.1),
+                                                ((64, 64), 2, False, 0.05)])
+def test_loss_and_gradient_match_oracle(dev, shape, L, subset, tau):
+    H, W = shape
+    img = synth.power_law(H, W, beta=2.0, seed=11)
+    x = torch.from_numpy(img).to(dev)
+    theta = theta_with_biases(4)
+    ranges = oracle.full_ranges(H, W, 8)
+    if subset:
+        ranges = ranges[np.random.default_rng(0).choice(len(ranges), 37, replace=False)]
+    labels = oracle.match_level(img, 8, L, oracle.PLAIN_K, None, ranges)["dom"].astype(np.int32)
+    m = fic.Mlp(theta, tau=tau)
+    try:
+        say(f"[learned] loss/grad {shape} L={L} subset={subset} tau={tau}")
+        loss, grad = m.loss_grad(x, L, torch.from_numpy(labels),
+                                 ranges=torch.from_numpy(ranges) if subset else None)
+        torch.cuda.synchronize()
+        ref_loss, ref_grad = ol.loss_and_grad(theta, ol.block_vectors(ol.range_blocks(img, ranges)),
+                                              ol.block_vectors(ol.domain_blocks(img, L)), labels, tau)
+        got = grad.cpu().numpy().astype(np.float64)
+        say(f"[learned] loss gpu {loss.item():.6f} oracle {ref_loss:.6f}")
+        assert abs(loss.item() - ref_loss) <= 1e-2 * abs(ref_loss) + 1e-3
+        for name, rel, cos in grad_errors(got, ref_grad):
+            say(f"[learned]   {name}: rel {rel:.2e} cos {cos:.6f}")
+            assert rel <= GRAD_REL and cos >= GRAD_COS, name
+    finally:
+        m.close()
+
+
+def test_adam_matches_oracle(dev):
+    theta = synth.mlp_init(1)
+    g = synth.grad_like(fic.MLP_PARAMS, seed=3)
+    m = fic.Mlp(theta)
+    try:
+        gt = torch.from_numpy(g).to(dev)
+        ref = theta.astype(np.float64)
+        mm = np.zeros_like(ref)
+        vv = np.zeros_like(ref)
+        for step, lr in enumerate((1e-3, 5e-4, 2e-3), start=1):
+            m.adam(gt, lr=lr, beta1=0.8, beta2=0.99, eps=1e-6)
+            ref, mm, vv = ol.adam_step(ref, g, mm, vv, step, lr, beta1=0.8, beta2=0.99, eps=1e-6)
+        got = m.params().astype(np.float64)
+        assert np.allclose(got, ref, rtol=1e-5, atol=2e-7)
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("nq,nk,k,dup", [(100, 3000, 32, 300), (37, 20, 32, 0), (64, 1000, 1, 50),
+                                         (5, 4099, 7, 0)])
+def test_topk_matches_brute_force(dev, nq, nk, k, dup):
+    q = synth.unit_rows_f16(nq, seed=1)
+    keys = synth.unit_rows_f16(nk, seed=2, n_dup=dup)
+    # exact ties at the top: copies of query 0 at three key positions
+    for pos in (nk // 3, 0, nk - 1):
+        keys[pos] = q[0]
+    m = fic.Mlp(synth.mlp_init(0))
+    try:
+        idx, score = m.topk(torch.from_numpy(q).to(dev), torch.from_numpy(keys).to(dev), k)
+        torch.cuda.synchronize()
+    finally:
+        m.close()
+    idx = idx.cpu().numpy()
+    score = score.cpu().numpy().astype(np.float64)
+    S = q.astype(np.float64) @ keys.astype(np.float64).T
+    kk = min(k, nk)
+    for r in range(nq):
+        got = idx[r, :kk]
+        assert (idx[r, kk:] == -1).all()
+        assert len(set(got.tolist())) == kk and got.min() >= 0 and got.max() < nk
+        s = S[r, got]
+        assert np.all(np.abs(score[r, :kk] - s) <= DOT_TOL)
+        assert np.all(np.diff(score[r, :kk]) <= 0)
+        kth = np.sort(S[r])[::-1][kk - 1]
+        assert s.min() >= kth - 2 * DOT_TOL
+        must = np.nonzero(S[r] > kth + 2 * DOT_TOL)[0]
+        assert set(must.tolist()) <= set(got.tolist())
+    # the planted exact ties come first, lower index first
+    top = sorted({0, nk // 3, nk - 1})[:kk]
+    assert list(idx[0, :len(top)]) == top
+
+
+def gpu_learned(dev, img, theta, L, k, rms=8.0, s_k=oracle.PLAIN_K):
+    x = torch.from_numpy(img).to(dev)
+    m = fic.Mlp(theta)
+    try:
+        out, nfb, props = m.encode_level(x, L, s_k, k, rms, return_proposals=True)
+        torch.cuda.synchronize()
+        return fic.matches_numpy(out), int(nfb.item()), props.cpu().numpy()
+    finally:
+        m.close()
+
+
+def assert_matches_equal(got, ref, n=64):
+    for f in ("dom", "iso", "s_idx", "k", "q_o"):
+        assert np.array_equal(got[f].astype(np.int64), ref[f].astype(np.int64)), f
+    assert np.array_equal(got["e_num"].astype(np.int64) * n, ref["e_lit"])
+
+
+def test_learned_with_every_domain_proposed_is_exhaustive(dev):
+    """32 x 32 image at L = 4: 25 domains, all of them proposed."""
+    img = synth.power_law(32, beta=1.8, seed=7)
+    got, nfb, props = gpu_learned(dev, img, theta_with_biases(2), 4, 25, rms=1e6)
+    assert nfb == 0 and not (got["flags"] & fic.FLAG_FALLBACK).any()
+    assert np.array_equal(np.sort(props, axis=1), np.tile(np.arange(25), (16, 1)))
+    assert_matches_equal(got, oracle.match_level(img, 8, 4))
+
+
+def test_learned_always_falling_back_is_exhaustive(dev):
+    img = synth.power_law(64, 96, beta=2.0, seed=8)
+    got, nfb, _ = gpu_learned(dev, img, theta_with_biases(3), 4, 4, rms=0.0)
+    ref = oracle.match_level(img, 8, 4)
+    fb = (got["flags"] & fic.FLAG_FALLBACK) != 0
+    pos = ref["e_lit"] > 0
+    assert fb[pos].all() and nfb == int(fb.sum())
+    assert_matches_equal(got[pos], ref[pos])
+    assert (got["e_num"][~pos] == 0).all()  # an exact copy among the proposals
+
+
+@pytest.mark.parametrize("shape,L,k,rms,sets", [((64, 64), 4, 8, 8.0, "plain"), ((48, 80), 2, 32, 6.0, "plain"),
+                                               ((64, 64), 4, 5, 8.0, "paper")])
+def test_learned_encode_is_exact_over_its_proposals(dev, shape, L, k, rms, sets):
+    img = synth.power_law(*shape, beta=1.6, seed=9, n_rect=1)
+    theta = theta_with_biases(5)
+    s_k = oracle.PLAIN_K if sets == "plain" else oracle.PAPER_K[1]
+    got, nfb, props = gpu_learned(dev, img, theta, L, k, rms, s_k)
+    say(f"[learned] {shape} L={L} k={k}: {nfb} fallbacks of {len(got)}")
+    # the oracle decides every range from the same proposal lists
+    ref, fb, _ = ol.learned_match(img, theta, L, k, s_k=s_k, rms=rms, proposals=props)
+    assert np.array_equal((got["flags"] & fic.FLAG_FALLBACK) != 0, fb) and nfb == int(fb.sum())
+    assert_matches_equal(got, ref)
+    # and the lists are the fp64 top-k up to the embedding error
+    H, W = shape
+    GR, _ = ol.embed(theta, ol.block_vectors(ol.range_blocks(img, oracle.full_ranges(H, W, 8))))
+    GD, _ = ol.embed(theta, ol.block_vectors(ol.domain_blocks(img, L)))
+    S = GR @ GD.T
+    tol = 2 * EMB_ATOL * 8
+    for r in range(len(props)):
+        kth = np.sort(S[r])[::-1][k - 1]
+        assert S[r, props[r]].min() >= kth - tol
+        assert set(np.nonzero(S[r] > kth + tol)[0].tolist()) <= set(props[r].tolist())
+
+
+def test_level_codes_decode_like_the_oracle(dev):
+    img = synth.power_law(64, beta=2.0, seed=4)
+    x = torch.from_numpy(img).to(dev)
+    out = fic.encode_level(x, 8, 4, oracle.PLAIN_K)
+    codes = fic.level_codes(out, 64, 64, 8, 4)
+    rec = fic.decode(codes, codes.shape[0], 64, 64, iters=16)
+    ref = oracle.match_level(img, 8, 4)
+    rc = np.zeros(len(ref), dtype=oracle.CODE_DTYPE)
+    yx = oracle.full_ranges(64, 64, 8)
+    rc["y"], rc["x"], rc["B"] = yx[:, 0], yx[:, 1], 8
+    for f in ("dom", "dy", "dx", "iso", "s_idx", "k", "q_o", "e_lit"):
+        rc[f] = ref[f]
+    assert np.array_equal(rec.cpu().numpy(), oracle.decode(rc, 64, 64, iters=16))
+
+
+def test_training_lowers_the_loss(dev):
+    img = synth.learned_train_image(0, n=128)
+    x = torch.from_numpy(img).to(dev)
+    labels = oracle.match_level(img, 8, 4)["dom"].astype(np.int32)
+    lab = torch.from_numpy(labels).to(dev)
+    m = fic.Mlp(synth.mlp_init(0))
+    try:
+        losses = []
+        for it in range(40):
+            losses.append(m.train_step(x, 4, lab, lr=2e-3).item())
+        say(f"[learned] loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+        assert np.isfinite(losses).all() and losses[-1] < 0.8 * losses[0]
+    finally:
+        m.close()
+
+
+def test_eval_workload_sampled(dev):
+    """One 2048 x 2048 evaluation image, as the benchmark runs it: sampled ranges
+    are exact over their proposals; sampled fallbacks equal the exhaustive oracle."""
+    img = synth.learned_eval_image(0)
+    theta = synth.mlp_init(0)
+    say("[learned] 2048 eval image")
+    got, nfb, props = gpu_learned(dev, img, theta, 4, 32)
+    fb = (got["flags"] & fic.FLAG_FALLBACK) != 0
+    say(f"[learned] fallbacks {nfb} of {len(got)}")
+    assert nfb == int(fb.sum())
+    thr = 1600 * 64 * 64 * 64
+    assert (got["e_num"][~fb] <= thr).all()
+    rng = np.random.default_rng(0)
+    ranges = oracle.full_ranges(2048, 2048, 8)
+    pick = rng.choice(np.nonzero(~fb)[0], size=min(12, int((~fb).sum())), replace=False)
+    for q in pick:
+        ref = oracle.match_level(img, 8, 4, oracle.PLAIN_K, np.unique(props[q]), ranges[q:q + 1])
+        assert_matches_equal(got[q:q + 1], ref)
+    fbi = np.nonzero(fb)[0]
+    for q in rng.choice(fbi, size=min(3, len(fbi)), replace=False) if len(fbi) else []:
+        ref = oracle.match_level(img, 8, 4, oracle.PLAIN_K, None, ranges[q:q + 1])
+        assert_matches_equal(got[q:q + 1], ref)
