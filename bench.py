@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_ALU_TOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 ops (32-bit multiply-add per lane per clock)
-PEAK_INT8_TOPS = 5000.0
+PEAK_INT8_TOPS = 5000.0  # dense int8 MFMA
+PEAK_FP16_TFLOPS = 2500.0  # dense fp16 MFMA
 PEAK_HBM_GBS = 8000.0
 
 
@@ -41,7 +42,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="quadtree512",
-                    choices=["quadtree512", "single128", "precision1024", "batch64"])
+                    choices=["quadtree512", "single128", "precision1024", "batch64", "learned2048"])
+    ap.add_argument("--n-train", type=int, default=200, help="learned2048: training images")
+    ap.add_argument("--epochs", type=int, default=LEARNED_EPOCHS, help="learned2048: epochs")
+    ap.add_argument("--n-eval", type=int, default=16, help="learned2048: evaluation images")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines autotune cache for batch64 (default: none, always tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -67,21 +71,24 @@ def time_steps(fn, steps, warmup, torch):
 
 
 def roofline_from_profile(prof, per_label_ops):
-    """Dominant kernel over the timed region: algorithmic ops per launch / mean launch time."""
+    """Dominant kernel over the timed region: algorithmic ops per launch / mean launch time.
+
+    per_label_ops maps a profile label to its ops per launch, or to a tuple
+    (ops, bound, peak, unit) for kernels not bound by the 32-bit vector ALU."""
     best = None
     for label, (launches, total_ms) in prof.items():
         if best is None or total_ms > best[2]:
             best = (label, launches, total_ms)
     label, launches, total_ms = best
-    ops = per_label_ops.get(label)
+    spec = per_label_ops.get(label)
     out = {"kernel": label, "launches": launches, "avg_us": total_ms / launches * 1e3}
-    if ops is None:
+    if spec is None:
         return out
+    ops, bound, peak, unit = spec if isinstance(spec, tuple) else (spec, "alu", PEAK_ALU_TOPS, "TOP/s")
     avg_s = total_ms / launches / 1e3
     achieved = ops / avg_s / 1e12
-    out.update({"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TOPS, "unit": "TOP/s",
-                "frac": achieved / PEAK_ALU_TOPS, "traffic": None,
-                "ops_per_launch": ops})
+    out.update({"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None, "ops_per_launch": ops})
     return out
 
 
@@ -234,6 +241,148 @@ def run_batch(args, torch):
     return res
 
 
+LEARNED_LR = 1e-3
+LEARNED_TAU = 0.03
+LEARNED_EPOCHS = 10
+LEARNED_TOPK = 32
+
+
+def train_labels(fic, x, np, torch):
+    """Exhaustive argmin domain of every 8x8 range (GPU exhaustive matcher), keeping ranges
+    whose best contrast is above 0 (with s = 0 every domain ties, so the label says nothing)."""
+    m = fic.matches_numpy(fic.encode_level(x, 8, 4, fic.PLAIN_K))
+    H, W = x.shape
+    yy, xx = np.mgrid[0:H // 8, 0:W // 8]
+    yx = np.stack([yy.ravel() * 8, xx.ravel() * 8], 1).astype(np.int32)
+    keep = m["k"] > 0
+    return (torch.from_numpy(yx[keep]).to(x.device),
+            torch.from_numpy(m["dom"][keep].astype(np.int32)).to(x.device))
+
+
+def run_learned(args, torch):
+    import numpy as np
+
+    from paper_1501_04140_amd import fic, synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    train = [torch.from_numpy(synth.learned_train_image(i)).to(dev) for i in range(args.n_train)]
+    data = [train_labels(fic, x, np, torch) for x in train]
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    init = synth.mlp_init(0)
+    net = fic.Mlp(init, tau=LEARNED_TAU)
+    base = fic.Mlp(init, tau=LEARNED_TAU)
+    loss = torch.zeros(1, device=dev)
+    steps, hist = 0, []
+    total = args.epochs * len(train)
+    t0 = time.perf_counter()
+    for ep in range(args.epochs):
+        ls = []
+        for i in np.random.default_rng(ep).permutation(len(train)):
+            lr = LEARNED_LR * 0.5 * (1 + math.cos(math.pi * steps / total))
+            net.train_step(train[i], 4, data[i][1], ranges=data[i][0], lr=lr, loss=loss)
+            ls.append(loss.item())
+            steps += 1
+        hist.append(float(np.mean(ls)))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) / reps
+
+    def psnr_of(out, x):
+        H, W = x.shape
+        rec = fic.decode(fic.level_codes(out, H, W, 8, 4), (H // 8) * (W // 8), H, W, iters=64)
+        return fic.psnr(rec, x)
+
+    reps = max(1, args.steps // 10)
+    rows = []
+    for i in range(args.n_eval):
+        x = torch.from_numpy(synth.learned_eval_image(i)).to(dev)
+        ex, t_ex = timed(lambda: fic.encode_level(x, 8, 4, fic.PLAIN_K), reps)
+        exm = fic.matches_numpy(ex)
+        row = {"t_exhaustive": t_ex, "psnr_exhaustive": psnr_of(ex, x)}
+        for name, m, rms in (("learned", net, 8.0), ("proposals_only", net, 1e30),
+                             ("untrained", base, 8.0)):
+            (out, nfb, props), t = timed(
+                lambda: m.encode_level(x, 4, fic.PLAIN_K, LEARNED_TOPK, rms, return_proposals=True), reps)
+            row[name] = {"ms": t, "psnr": psnr_of(out, x), "fallbacks": int(nfb.item()),
+                         "recall": float((props.cpu().numpy() == exm["dom"][:, None]).any(1).mean())}
+        rows.append(row)
+        print(json.dumps({"eval_image": i, **row}), file=sys.stderr, flush=True)
+    # per-kernel times of the learned encode of one image
+    x = torch.from_numpy(synth.learned_eval_image(0)).to(dev)
+    fic.profile_begin()
+    for _ in range(reps):
+        net.encode_level(x, 4, fic.PLAIN_K, LEARNED_TOPK, 1e30)
+    torch.cuda.synchronize()
+    prof = fic.profile_end()
+    nr, nd = 65536, 259081
+    # similarity top-k: a [ranges x 64] x [64 x domains] fp16 product, 2 flops per MAC
+    roof = roofline_from_profile({"learned_topk": prof["learned_topk"]},
+                                 {"learned_topk": (2 * 64 * nr * nd, "mfma", PEAK_FP16_TFLOPS, "TFLOP/s")})
+
+    def mean(key, sub=None):
+        return float(np.mean([r[key] if sub is None else r[key][sub] for r in rows]))
+
+    res = {
+        "metric": "learned-proposal encode of a 2048² image: ms, PSNR Δ vs exhaustive GPU search",
+        "dtype": "fp16 MFMA (f32 accumulate) proposals; u8 -> i64 exact rescoring",
+        "value": nr / (mean("learned", "ms") / 1e3), "unit": "ranges/s",
+        "encode_ms": mean("learned", "ms"),
+        "exhaustive_ms": mean("t_exhaustive"),
+        "speedup_vs_exhaustive": mean("t_exhaustive") / mean("learned", "ms"),
+        "psnr_delta_db": mean("learned", "psnr") - mean("psnr_exhaustive"),
+        "fallback_frac": mean("learned", "fallbacks") / nr,
+        "recall_at_32": mean("learned", "recall"),
+        "proposals_only": {"ms": mean("proposals_only", "ms"),
+                           "speedup_vs_exhaustive": mean("t_exhaustive") / mean("proposals_only", "ms"),
+                           "psnr_delta_db": mean("proposals_only", "psnr") - mean("psnr_exhaustive")},
+        "untrained_network": {"ms": mean("untrained", "ms"),
+                              "psnr_delta_db": mean("untrained", "psnr") - mean("psnr_exhaustive"),
+                              "fallback_frac": mean("untrained", "fallbacks") / nr,
+                              "recall_at_32": mean("untrained", "recall")},
+        "training": {"images": len(train), "epochs": args.epochs, "steps": steps, "seconds": train_s,
+                     "ms_per_step": train_s / max(steps, 1) * 1e3, "loss_per_epoch": hist,
+                     "labelled_ranges": int(sum(len(d[1]) for d in data)), "label_seconds": label_s,
+                     "lr": LEARNED_LR, "tau": LEARNED_TAU},
+        "config": {"workload": "learned2048: 8x8 ranges, L=4, s=0..1 (11 values), top-32 proposals, "
+                               "RMS 8 fallback; trained on 512x512, evaluated on 2048x2048 1/f^beta "
+                               "images, beta~U[1.5,2.5]",
+                   "eval_images": args.n_eval, "psnr_exhaustive_db": mean("psnr_exhaustive")},
+        "roofline": roof,
+        "kernel_ms_per_encode_proposals_only": {k: v[1] / reps for k, v in prof.items()},
+        "per_image": rows,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import learned as ol
+        oracle.build(force=False)
+        theta = net.params()
+        img = synth.learned_eval_image(0)[:512, :512].copy()
+        ranges = oracle.full_ranges(512, 512, 8)[::16]
+        t0 = time.perf_counter()
+        ol.learned_match(img, theta, 4, LEARNED_TOPK, rms=8.0, ranges=ranges)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(ranges) / dt, "unit": "ranges/s",
+                               "cores": oracle.num_threads(), "kind": "oracle", "seconds": dt,
+                               "sample": f"{len(ranges)} ranges of a 512x512 crop of eval image 0 "
+                                         "(embeddings of all 15625 crop domains included)"}
+    net.close()
+    base.close()
+    return res
+
+
 def run_level(args, torch, which):
     from paper_1501_04140_amd import fic, synth
 
@@ -256,9 +405,15 @@ def run_level(args, torch, which):
     torch.cuda.synchronize()
     prof = fic.profile_end()
     roof = roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")},
-                                 {f"match_b{B}": matches * match_ops(B * B, 1)})
+                                 {f"match_b{B}": matches * match_ops(B * B, 1),
+                                  # int8 MFMA form: the correlation's 2n ops per match are the
+                                  # contraction; the hi/lo split issues it twice
+                                  f"match_b{B}_mfma": (matches * 2 * B * B, "mfma", PEAK_INT8_TOPS,
+                                                       "TOP/s")})
     res = {
         "metric": "matches/s (range×domain×isometry)",
+        "dtype": ("u8 -> int8 MFMA (hi/lo split), i32 accumulate, i64 exact" if which == "precision1024"
+                  else "u8 dot4 -> i32, i64 exact"),
         "value": matches / (ms / 1e3), "unit": "matches/s", "encode_ms": ms,
         "encode_ms_wall": wall_ms, "matches_per_step": matches,
         "config": {"workload": desc}, "roofline": roof,
@@ -298,13 +453,15 @@ def main():
         res = run_quadtree(args, torch)
     elif args.workload == "batch64":
         res = run_batch(args, torch)
+    elif args.workload == "learned2048":
+        res = run_learned(args, torch)
     else:
         res = run_level(args, torch, args.workload)
     line = {
         "metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"),
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": res["encode_ms"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u8 dot4 -> i32, i64 exact", "data": "synthetic",
+        "vs_baseline": None, "dtype": res.pop("dtype", "u8 dot4 -> i32, i64 exact"), "data": "synthetic",
     }
     line.update(res)
     print(json.dumps(line), flush=True)

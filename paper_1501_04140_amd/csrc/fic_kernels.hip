@@ -69,7 +69,7 @@ __device__ inline bool last_workgroup(uint32_t* ticket, int nblocks) {
 // ---------------------------------------------------------------- active range lists
 // Packed corner: (y << 16) | x. Block 0 also sets the level's active count
 // and, when asked, clears the code counter of a new quadtree.
-__device__ inline void k_act_full_body(int32_t* act, int gy, int gx, int B, Ctrl* ctrl, int lv, int reset) {
+__device__ __forceinline__ void k_act_full_body(int32_t* act, int gy, int gx, int B, Ctrl* ctrl, int lv, int reset) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) {
         ctrl->act_count[lv] = gy * gx;
@@ -84,7 +84,7 @@ __device__ inline void k_act_full_body(int32_t* act, int gy, int gx, int B, Ctrl
 }
 
 // Caller-supplied corners; an invalid corner is stored as -1.
-__device__ inline void k_act_from_yx_body(int32_t* act, const int32_t* yx, int n, int H, int W, int B,
+__device__ __forceinline__ void k_act_from_yx_body(int32_t* act, const int32_t* yx, int n, int H, int W, int B,
                               Ctrl* ctrl) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) ctrl->act_count[0] = n;
@@ -109,7 +109,7 @@ struct ScoreShape {
 };
 
 template <int SIDE>
-__device__ inline void k_pool_score_body(const uint8_t* __restrict__ img, int pitch,
+__device__ __forceinline__ void k_pool_score_body(const uint8_t* __restrict__ img, int pitch,
                                                        int L, int gx, int total,
                                                        const int64_t* __restrict__ T, int64_t M,
                                                        int64_t* __restrict__ key, Ctrl* ctrl) {
@@ -166,7 +166,7 @@ __device__ inline int pool_mode(int passed, int total, int min_pool) {
 // bucket of key >> shift (shift puts every key below 2^(shift+12)) holding its
 // own r-th smallest key. The chunk alone has r keys not above that bucket's
 // largest key, so the global r-th smallest key is not above it either.
-__device__ inline void k_floor_bound_body(const int64_t* __restrict__ key, int total,
+__device__ __forceinline__ void k_floor_bound_body(const int64_t* __restrict__ key, int total,
                                                         int min_pool, int r, int shift, int chunk,
                                                         Ctrl* ctrl) {
     if (pool_mode(ctrl->pass_count, total, min_pool) != 1) return;
@@ -319,7 +319,7 @@ __device__ inline void publish_count(int2* blk, int t0, int t1) {
 
 // Pool compaction, pass 1: per-workgroup counts; the last workgroup scans them
 // and sets pool_count (the pool, or the floor candidates).
-__device__ inline void k_pool_count_body(CompactArgs a, Ctrl* ctrl, int2* blk, int nblk) {
+__device__ __forceinline__ void k_pool_count_body(CompactArgs a, Ctrl* ctrl, int2* blk, int nblk) {
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
     const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
     int c0 = 0;
@@ -338,7 +338,7 @@ __device__ inline void k_pool_count_body(CompactArgs a, Ctrl* ctrl, int2* blk, i
 }
 
 // Pool compaction, pass 2: kept domains in ascending index order.
-__device__ inline void k_pool_scatter_body(CompactArgs a, const Ctrl* ctrl,
+__device__ __forceinline__ void k_pool_scatter_body(CompactArgs a, const Ctrl* ctrl,
                                                          const int2* blk, int32_t* pool_out) {
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
     const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
@@ -361,7 +361,7 @@ __device__ inline void k_pool_scatter_body(CompactArgs a, const Ctrl* ctrl,
 // among the candidates, then in-place compaction to the keys below it plus the
 // first ties in index order. Always launched: it also publishes the number of
 // domains that passed the threshold and clears the per-level counters.
-__device__ inline void k_floor_select_body(const int64_t* __restrict__ key, int total,
+__device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ key, int total,
                                                        int min_pool, int r,
                                                        int32_t* __restrict__ pool, Ctrl* ctrl) {
     __shared__ uint32_t h[kSelBins];
@@ -483,7 +483,7 @@ __device__ inline void k_floor_select_body(const int64_t* __restrict__ key, int 
 
 // Quadtree compaction: kept leaves to the code list (after code_base), the
 // four children of each split range to the next active list, in order.
-__device__ inline void k_quad_scatter_body(CompactArgs a, const Ctrl* ctrl,
+__device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, const Ctrl* ctrl,
                                                          const int2* blk, const fic_code* tmp_codes,
                                                          fic_code* codes, int capacity,
                                                          const int32_t* act, int32_t* act_next,
@@ -536,7 +536,7 @@ struct PrepShape {
 };
 
 template <int B>
-__device__ inline void k_pool_prep_body(const uint8_t* __restrict__ img, int pitch,
+__device__ __forceinline__ void k_pool_prep_body(const uint8_t* __restrict__ img, int pitch,
                                                       int L, int gx, const int32_t* __restrict__ pool,
                                                       int identity_total, Ctrl* ctrl,
                                                       uint32_t* __restrict__ HL,
@@ -665,7 +665,7 @@ __device__ inline int active_chunks(int P, int TN, int n_chunks) {
 //  kModeGrid: consecutive k0..k1, closed-form minimiser, exact in int64.
 //  kModeList: any set, every value evaluated in int64.
 template <int B, int MODE>
-__device__ inline void k_match_body(const uint8_t* __restrict__ img, int pitch,
+__device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, int pitch,
                                                   const int32_t* __restrict__ act,
                                                   const int32_t* act_count,
                                                   const uint32_t* __restrict__ HL,
@@ -887,7 +887,7 @@ __device__ inline bool finish_range(int yx, int B, int L, int gx, const Partial*
     return true;
 }
 
-__device__ inline void k_reduce_level_body(int B, int L, int gx,
+__device__ __forceinline__ void k_reduce_level_body(int B, int L, int gx,
                                                          const int32_t* __restrict__ act,
                                                          const int32_t* act_count,
                                                          const Partial* __restrict__ part,
@@ -908,7 +908,7 @@ __device__ inline void k_reduce_level_body(int B, int L, int gx,
 // range, kQuadItems consecutive ranges per thread. Per-workgroup counts of
 // kept and split ranges go to blk; the last workgroup scans them, advances the
 // code counter and sets the next level's active count (4 children per split).
-__device__ inline void k_reduce_quad_body(
+__device__ __forceinline__ void k_reduce_quad_body(
     int B, int L, int gx, int lv, int last, int64_t thr, const int32_t* __restrict__ act,
     Ctrl* ctrl, const Partial* __restrict__ part, int n_chunks, int CG,
     const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, KSet ks,
@@ -1094,7 +1094,7 @@ constexpr int kM8Chunk = 1024;                         // target pool domains pe
 
 // Rows r' = r - 128 of the 8 inverse-isometry arrangements of each range:
 // Ar[(8q + t) * 64 + m] = R[iso_src(8, inverse(t), m)] - 128. Thread per row.
-__device__ inline void k_range_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
+__device__ __forceinline__ void k_range_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
                                                           const int32_t* __restrict__ act,
                                                           const int32_t* act_count,
                                                           int8_t* __restrict__ Ar,
@@ -1149,7 +1149,7 @@ __device__ inline void k_range_prep_i8_body(const uint8_t* __restrict__ img, int
 // Columns for the int8 matcher: h and l rows of each pool domain, and
 // G = 40 / A' (0 for a constant domain) and A' in FP32 for the screen. Four
 // lanes share a domain, 16 decimated values each.
-__device__ inline void k_pool_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
+__device__ __forceinline__ void k_pool_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
                                                          int L, int gx, const int32_t* __restrict__ pool,
                                                          int identity_total, Ctrl* ctrl,
                                                          int8_t* __restrict__ Dh, int8_t* __restrict__ Dl,
@@ -1238,7 +1238,7 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
 constexpr float kM8ScreenMargin = 1.0e6f;
 constexpr int kM8Share = 4;
 
-__device__ inline void k_match_mfma8_body(
+__device__ __forceinline__ void k_match_mfma8_body(
     const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int32_t* act_count,
     const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
     const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Af,
@@ -1430,7 +1430,7 @@ __device__ inline float float_from_ordered(int64_t o) {
 
 constexpr int kF32Tile = 64;  // domains per LDS stage
 
-__device__ inline void k_match_fp32_body(const uint8_t* __restrict__ img, int pitch,
+__device__ __forceinline__ void k_match_fp32_body(const uint8_t* __restrict__ img, int pitch,
                                                        const int32_t* __restrict__ act,
                                                        const int32_t* act_count,
                                                        const uint8_t* __restrict__ DDimg, int L,
@@ -1529,7 +1529,7 @@ __device__ inline void k_match_fp32_body(const uint8_t* __restrict__ img, int pi
 
 // Result of the FP32 comparator: its own argmin and FP32 E, plus the exact
 // e_num of the candidate it chose (recomputed in integers for reporting).
-__device__ inline void k_reduce_fp32_body(const uint8_t* __restrict__ img, int pitch,
+__device__ __forceinline__ void k_reduce_fp32_body(const uint8_t* __restrict__ img, int pitch,
                                                         int L, int gx, const int32_t* __restrict__ act,
                                                         const int32_t* act_count,
                                                         const Partial* __restrict__ part,
@@ -1588,9 +1588,17 @@ __device__ inline void k_reduce_fp32_body(const uint8_t* __restrict__ img, int p
 
 // ================================================================ table-driven launches
 // Every quadtree kernel reads its image's arguments from tab[blockIdx.z] (a
-// batch) or, when tab is NULL, from the by-value a0 (one image). Workgroups
-// beyond an image's own grid return at once.
-#define FIC_LV const Lvl& a = tab ? tab[blockIdx.z] : a0
+// batch, TAB = true) or from the by-value a0 (one image, TAB = false). The
+// choice is a template parameter so that either source stays a uniform
+// (scalar) load. Workgroups beyond an image's own grid return at once.
+template <bool TAB>
+__device__ inline const Lvl& lvl_of(const Lvl& a0, const Lvl* __restrict__ tab) {
+    if constexpr (TAB)
+        return tab[blockIdx.z];
+    else
+        return a0;
+}
+#define FIC_LV const Lvl& a = lvl_of<TAB>(a0, tab)
 
 // Default matcher chunk (domains per pool chunk) for a level.
 int match_chunk_domains(int B) {
@@ -1602,17 +1610,19 @@ int match_chunk_domains(int B) {
     }
 }
 
+template <bool TAB>
 __global__ void kt_act_full(Lvl a0, const Lvl* __restrict__ tab, int reset) {
     FIC_LV;
     k_act_full_body(a.act, a.H / a.B, a.W / a.B, a.B, a.ctrl, a.lv, reset);
 }
 
+template <bool TAB>
 __global__ void kt_act_from_yx(Lvl a0, const Lvl* __restrict__ tab, const int32_t* yx, int n) {
     FIC_LV;
     k_act_from_yx_body(a.act, yx, n, a.H, a.W, a.B, a.ctrl);
 }
 
-template <int SIDE>
+template <int SIDE, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_score(Lvl a0, const Lvl* __restrict__ tab,
                                                         const int64_t* __restrict__ T) {
     FIC_LV;
@@ -1620,6 +1630,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_score(Lvl a0, const Lvl* __res
     k_pool_score_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, T, a.M, a.key, a.ctrl);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_floor_bound(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_floor_bound_body(a.key, a.total, a.min_pool, a.rank, a.sel_shift, a.bound_chunk, a.ctrl);
@@ -1635,6 +1646,7 @@ __device__ inline CompactArgs pool_args(const Lvl& a) {
     return c;
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_count(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
@@ -1642,6 +1654,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_count(Lvl a0, const Lvl* __res
     k_pool_count_body(pool_args(a), a.ctrl, a.blk, nblk);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_scatter(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
@@ -1649,12 +1662,13 @@ __global__ __launch_bounds__(kBlock) void kt_pool_scatter(Lvl a0, const Lvl* __r
     k_pool_scatter_body(pool_args(a), a.ctrl, a.blk, a.pool);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(1024) void kt_floor_select(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.ctrl);
 }
 
-template <int B>
+template <int B, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_prep(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * PrepShape<B>::TPD) return;
@@ -1662,13 +1676,14 @@ __global__ __launch_bounds__(kBlock) void kt_pool_prep(Lvl a0, const Lvl* __rest
                         a.sd, a.ad, a.jd);
 }
 
-template <int B, int MODE>
+template <int B, int MODE, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_match(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_match_body<B, MODE>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.hl, a.sd, a.ad, a.jd,
                           a.ctrl, a.ks, a.nc, a.part, a.sr, a.cr, a.cg);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_prep_i8(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * 4) return;
@@ -1676,23 +1691,27 @@ __global__ __launch_bounds__(kBlock) void kt_pool_prep_i8(Lvl a0, const Lvl* __r
                         a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_range_prep_i8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_range_prep_i8_body(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kM8Waves * 64) void kt_match_mfma8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_match_mfma8_body(a.ar, a.srp, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
                        a.jd, a.ctrl, a.ks.k1, a.nc, a.part, a.cg);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_match_fp32(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_match_fp32_body(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.img, a.L, a.gx, a.jd,
                       a.ctrl, a.ks.k1, a.nc, a.part, a.cg);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_reduce_level(Lvl a0, const Lvl* __restrict__ tab,
                                                           fic_match* __restrict__ out) {
     FIC_LV;
@@ -1700,6 +1719,7 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_level(Lvl a0, const Lvl* __r
                         a.ctrl, a.cr, a.sr, a.ks, out);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_reduce_fp32(Lvl a0, const Lvl* __restrict__ tab,
                                                          fic_match* __restrict__ out) {
     FIC_LV;
@@ -1707,6 +1727,7 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_fp32(Lvl a0, const Lvl* __re
                        a.cg, a.ctrl, out);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_reduce_quad(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     const int nblk = (a.max_act + kBlock * kQuadItems - 1) / (kBlock * kQuadItems);
@@ -1715,6 +1736,7 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_quad(Lvl a0, const Lvl* __re
                        a.sr, a.ks, a.tmpc, a.dec, a.blk, a.stats, nblk);
 }
 
+template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_quad_scatter(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     const int nblk = (a.max_act + kBlock * kQuadItems - 1) / (kBlock * kQuadItems);

@@ -436,7 +436,7 @@ FIC_API int fic_encode_level_learned(fic_mlp* M, const uint8_t* img, int32_t H, 
     {
         ProfScope ps("learned_fallback", st);
         fic_match* tmp = P<fic_match>(M->tmpm);
-        kt_reduce_level<<<cdiv(nr, kBlock), kBlock, 0, st>>>(lv, nullptr, tmp);
+        kt_reduce_level<false><<<cdiv(nr, kBlock), kBlock, 0, st>>>(lv, nullptr, tmp);
         k_fallback_scatter<<<cdiv(nr, kBlock), kBlock, 0, st>>>(tmp, P<int32_t>(M->fbq), fb_count, out);
         LAUNCH_CHECK();
     }

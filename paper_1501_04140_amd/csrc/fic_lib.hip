@@ -415,13 +415,13 @@ int max_over(const std::vector<Lvl>& h, F f) {
     return m;
 }
 
-template <int SIDE>
+template <int SIDE, bool TAB>
 void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
     const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });
-    kt_pool_score<SIDE><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt, T);
+    kt_pool_score<SIDE, TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt, T);
 }
 
-template <int B>
+template <int B, bool TAB>
 void launch_prep_match(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, hipStream_t st) {
     const int n = (int)h.size();
     const Lvl& a0 = h[0];
@@ -431,89 +431,102 @@ void launch_prep_match(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, 
         {
             ProfScope ps("pool_prep", st);
             const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * 4, kBlock); });
-            kt_pool_prep_i8<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
+            kt_pool_prep_i8<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
         }
         {
             ProfScope ps("range_prep", st);
-            kt_range_prep_i8<<<dim3(cdiv((int64_t)8 * max_act, kBlock), 1, n), kBlock, 0, st>>>(h[0], dt);
+            kt_range_prep_i8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kBlock), 1, n), kBlock, 0, st>>>(h[0], dt);
         }
         ProfScope ps("match_b8_mfma", st);
-        kt_match_mfma8<<<dim3(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n), kM8Waves * 64, 0, st>>>(h[0], dt);
+        kt_match_mfma8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n), kM8Waves * 64, 0, st>>>(h[0], dt);
         return;
     }
     {
         ProfScope ps("pool_prep", st);
         const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * PrepShape<B>::TPD, kBlock); });
-        kt_pool_prep<B><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
+        kt_pool_prep<B, TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
     }
     const dim3 grid(cdiv(max_act, kBlock / 8), max_nc, n);
     if (B == 8 && a0.var == kVarFp32) {
         ProfScope ps("match_b8_fp32", st);
-        kt_match_fp32<<<grid, kBlock, 0, st>>>(h[0], dt);
+        kt_match_fp32<TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
         return;
     }
     ProfScope ps(match_label(B), st);
     const KSet& ks = a0.ks;
-    if (ks.n <= kSmallMax) kt_match<B, kModeSmall><<<grid, kBlock, 0, st>>>(h[0], dt);
-    else if (ks.consecutive) kt_match<B, kModeGrid><<<grid, kBlock, 0, st>>>(h[0], dt);
-    else kt_match<B, kModeList><<<grid, kBlock, 0, st>>>(h[0], dt);
+    if (ks.n <= kSmallMax) kt_match<B, kModeSmall, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
+    else if (ks.consecutive) kt_match<B, kModeGrid, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
+    else kt_match<B, kModeList, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
 }
 
 // Pool of one level (entropy filter of Section 3, or the whole grid), pool
 // moments and the matcher, for h.size() images whose arguments are at dt.
-int launch_level(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
-                 hipStream_t st) {
+template <bool TAB>
+int launch_level_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
+                   hipStream_t st) {
     const int n = (int)h.size();
     const int B = h[0].B;
     if (filtered) {
         {
             ProfScope ps("pool_score", st);
             switch (2 * B) {
-                case 4: launch_score<4>(dt, h, T, st); break;
-                case 8: launch_score<8>(dt, h, T, st); break;
-                case 16: launch_score<16>(dt, h, T, st); break;
-                default: launch_score<32>(dt, h, T, st); break;
+                case 4: launch_score<4, TAB>(dt, h, T, st); break;
+                case 8: launch_score<8, TAB>(dt, h, T, st); break;
+                case 16: launch_score<16, TAB>(dt, h, T, st); break;
+                default: launch_score<32, TAB>(dt, h, T, st); break;
             }
         }
         {
             ProfScope ps("pool_select", st);
             const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, a.bound_chunk); });
-            kt_floor_bound<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+            kt_floor_bound<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
         {
             ProfScope ps("pool_compact", st);
             const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
-            kt_pool_count<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
-            kt_pool_scatter<<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+            kt_pool_count<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+            kt_pool_scatter<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
         {
             ProfScope ps("pool_select", st);
-            kt_floor_select<<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt);
+            kt_floor_select<TAB><<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt);
         }
     }
     switch (B) {
-        case 2: launch_prep_match<2>(dt, h, filtered, st); break;
-        case 4: launch_prep_match<4>(dt, h, filtered, st); break;
-        case 8: launch_prep_match<8>(dt, h, filtered, st); break;
-        default: launch_prep_match<16>(dt, h, filtered, st); break;
+        case 2: launch_prep_match<2, TAB>(dt, h, filtered, st); break;
+        case 4: launch_prep_match<4, TAB>(dt, h, filtered, st); break;
+        case 8: launch_prep_match<8, TAB>(dt, h, filtered, st); break;
+        default: launch_prep_match<16, TAB>(dt, h, filtered, st); break;
     }
     LAUNCH_CHECK();
     return FIC_OK;
 }
 
+// Pool, moments and matcher of one level for h.size() images (arguments at
+// dt for a batch, by value when dt is NULL).
+int launch_level(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
+                 hipStream_t st) {
+    return dt ? launch_level_t<true>(dt, h, T, filtered, st) : launch_level_t<false>(dt, h, T, filtered, st);
+}
+
 // Keep/split decisions and compaction for a quadtree level.
-int launch_quad(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
+template <bool TAB>
+int launch_quad_t(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
     const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.max_act, kBlock * kQuadItems); });
     {
         ProfScope ps("reduce_quad", st);
-        kt_reduce_quad<<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
+        kt_reduce_quad<TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
     }
     {
         ProfScope ps("quad_compact", st);
-        kt_quad_scatter<<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
+        kt_quad_scatter<TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
     }
     LAUNCH_CHECK();
     return FIC_OK;
+}
+
+int launch_quad(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
+    return dt ? launch_quad_t<true>(dt, h, st) : launch_quad_t<false>(dt, h, st);
 }
 
 int check_image(const uint8_t* img, int H, int W, int pitch, int B) {
@@ -579,7 +592,10 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
     const int nl = (int)t.size() / n_images;
     std::vector<Lvl> h0(t.begin(), t.begin() + n_images);
     const int gx = max_over(h0, [](const Lvl& a) { return cdiv((a.H / a.B) * (a.W / a.B), kBlock); });
-    kt_act_full<<<dim3(gx, 1, n_images), kBlock, 0, st>>>(t[0], dt, 1);
+    if (dt)
+        kt_act_full<true><<<dim3(gx, 1, n_images), kBlock, 0, st>>>(t[0], dt, 1);
+    else
+        kt_act_full<false><<<dim3(gx, 1, n_images), kBlock, 0, st>>>(t[0], dt, 1);
     for (int l = 0; l < nl; ++l) {
         std::vector<Lvl> h(t.begin() + l * n_images, t.begin() + (l + 1) * n_images);
         const Lvl* dl = dt ? dt + l * n_images : nullptr;
@@ -651,16 +667,16 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     const Lvl* dt = nullptr;  // one image: arguments by value
     const std::vector<Lvl>& h = t;
     if (range_yx)
-        kt_act_from_yx<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, range_yx, n_ranges);
+        kt_act_from_yx<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, range_yx, n_ranges);
     else
-        kt_act_full<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, 0);
+        kt_act_full<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, 0);
     if ((rc = launch_level(dt, t, ws->T, entropy_mode == 1, st))) return rc;
     {
         ProfScope ps("reduce_level", st);
         if (v.var == kVarFp32)
-            kt_reduce_fp32<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, out);
+            kt_reduce_fp32<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, out);
         else
-            kt_reduce_level<<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, out);
+            kt_reduce_level<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, out);
     }
     LAUNCH_CHECK();
     if (pool_count)
