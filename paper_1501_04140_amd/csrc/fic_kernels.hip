@@ -43,6 +43,11 @@ __device__ inline int64_t floordiv64(int64_t a, int64_t b) {  // b > 0
     return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
+__device__ inline int floordiv32(int a, int b) {  // b > 0
+    const int q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
 // ---------------------------------------------------------------- coherent loads
 // Reads of values that other workgroups of the same launch published with
 // atomics, after a ticket showed they are complete.
@@ -357,73 +362,111 @@ __device__ __forceinline__ void k_pool_scatter_body(CompactArgs a, const Ctrl* c
         if ((bits >> u) & 1u) pool_out[r0++] = base + u;
 }
 
-// Floor, step 3 (one workgroup): exact radix select of the r-th smallest key
-// among the candidates, then in-place compaction to the keys below it plus the
-// first ties in index order. Always launched: it also publishes the number of
-// domains that passed the threshold and clears the per-level counters.
+// Exclusive scan of one int per thread over a 1024-thread workgroup (16
+// waves); returns this thread's offset and sets the total. s_w: 16 ints of LDS.
+__device__ inline int scan1024(int v, int* s_w, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int s = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(s, d, 64);
+        if (lane >= d) s += t;
+    }
+    if (lane == 63) s_w[wid] = s;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const int x = s_w[w];
+        base += w < wid ? x : 0;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return base + s - v;
+}
+
+constexpr int kSelStage = 8192;  // floor candidates held in LDS by the select
+
+// Floor, step 3 (one workgroup of 1024): exact radix select of the r-th
+// smallest key among the C candidates (all keys <= cut_bound), then in-place
+// compaction to the keys below it plus the first ties in index order. The
+// candidates are staged in LDS when they fit; the digits start at the highest
+// bit a candidate can have, and the select stops as soon as the chosen bucket
+// is taken whole. Always launched: it also publishes the number of domains
+// that passed the threshold and clears the per-level counters.
 __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ key, int total,
                                                        int min_pool, int r,
                                                        int32_t* __restrict__ pool, Ctrl* ctrl) {
+    __shared__ uint64_t sk[kSelStage];
+    __shared__ int32_t sj[kSelStage];
     __shared__ uint32_t h[kSelBins];
-    __shared__ uint32_t part[1024];
+    __shared__ int s_w[16];
     __shared__ uint64_t s_prefix;
-    __shared__ uint32_t s_rank, s_cum;
-    __shared__ int s_t, s_w0[16], s_w1[16], s_c0, s_c1;
+    __shared__ uint32_t s_rank;
+    __shared__ int s_lo, s_done, s_c0, s_c1;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int passed = ctrl->pass_count;
     const int mode = pool_mode(passed, total, min_pool);
     if (mode == 1) {
         const int C = ctrl->pool_count;
+        const bool staged = C <= kSelStage;
+        if (staged)
+            for (int i = tid; i < C; i += nt) {
+                const int j = pool[i];
+                sj[i] = j;
+                sk[i] = (uint64_t)key[j];
+            }
+        const uint64_t ub = ctrl->cut_bound;
+        const int top = min(62, ub ? 63 - __clzll((long long)ub) : 0);
         if (tid == 0) {
             s_prefix = 0;
             s_rank = (uint32_t)r;
+            s_done = 0;
+            s_lo = 0;
         }
-        for (int shift = 48 - kSelBits; shift >= 0; shift -= kSelBits) {
+        __syncthreads();
+        for (int p = top - (kSelBits - 1);; p -= kSelBits) {
+            const int lo = max(p, 0);
+            const int hs = p + kSelBits;  // bits >= hs are already decided
+            const uint32_t dmask = (1u << (hs - lo)) - 1u;
+            const uint64_t prefix = s_prefix;
             for (int i = tid; i < kSelBins; i += nt) h[i] = 0u;
             __syncthreads();
-            const uint64_t prefix = s_prefix;
-            const int hs = shift + kSelBits;
             for (int i = tid; i < C; i += nt) {
-                const uint64_t u = (uint64_t)key[pool[i]];
-                if ((u >> hs) == (prefix >> hs)) atomicAdd(&h[(u >> shift) & (kSelBins - 1)], 1u);
+                const uint64_t u = staged ? sk[i] : (uint64_t)key[pool[i]];
+                if ((u >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(u >> lo) & dmask], 1u);
             }
             __syncthreads();
-            constexpr int per = kSelBins / 1024;
-            uint32_t mine = 0;
-            for (int b = 0; b < per; ++b) mine += h[tid * per + b];
-            part[tid] = mine;
-            if (tid == 0) {
-                s_t = 0;
-                s_cum = 0;
-            }
-            __syncthreads();
-            for (int d = 1; d < nt; d <<= 1) {
-                uint32_t v = tid >= d ? part[tid - d] : 0u;
-                __syncthreads();
-                part[tid] += v;
-                __syncthreads();
-            }
             const uint32_t rank = s_rank;
-            const uint32_t incl = part[tid], excl = incl - mine;
-            if (excl < rank && rank <= incl) {
-                s_t = tid;
-                s_cum = excl;
+            uint32_t c4[4], mine = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                c4[b] = h[tid * 4 + b];
+                mine += c4[b];
             }
-            __syncthreads();
-            if (tid == 0) {
-                uint32_t cum = s_cum;
-                int b = s_t * per;
-                for (; b < s_t * per + per - 1; ++b) {
-                    if (cum + h[b] >= rank) break;
-                    cum += h[b];
+            int tot;
+            const uint32_t excl = (uint32_t)scan1024((int)mine, s_w, tot);
+            if (excl < rank && rank <= excl + mine) {
+                uint32_t cum = excl;
+                int b = 0;
+                for (; b < 3; ++b) {
+                    if (cum + c4[b] >= rank) break;
+                    cum += c4[b];
                 }
-                s_prefix = prefix | ((uint64_t)b << shift);
+                s_prefix = prefix | ((uint64_t)(tid * 4 + b) << lo);
                 s_rank = rank - cum;
+                s_lo = lo;
+                s_done = (c4[b] == rank - cum) || lo == 0;
             }
             __syncthreads();
+            if (s_done) break;
         }
+        // keep keys whose bits >= s_lo are below the chosen prefix, and the
+        // first s_rank (in index order) of those equal to it
+        const uint64_t hmask = ~((1ull << s_lo) - 1ull);
         const uint64_t cut = s_prefix;
-        const int take = (int)s_rank;  // ties at the cut to keep
+        const int take = (int)s_rank;
         if (tid == 0) {
             s_c0 = 0;
             s_c1 = 0;
@@ -433,42 +476,19 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
             const int i = base + tid;
             int j = 0, less = 0, tie = 0;
             if (i < C) {
-                j = pool[i];
-                const uint64_t u = (uint64_t)key[j];
+                j = staged ? sj[i] : pool[i];
+                const uint64_t u = (staged ? sk[i] : (uint64_t)key[j]) & hmask;
                 less = u < cut;
                 tie = u == cut;
             }
-            // block-wide exclusive scan of (less, tie)
-            int a0 = less, a1 = tie;
-            const int lane = tid & 63, wid = tid >> 6;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                int x0 = __shfl_up(a0, d, 64), x1 = __shfl_up(a1, d, 64);
-                if (lane >= d) {
-                    a0 += x0;
-                    a1 += x1;
-                }
-            }
-            if (lane == 63) {
-                s_w0[wid] = a0;
-                s_w1[wid] = a1;
-            }
-            __syncthreads();
-            int b0 = s_c0, b1 = s_c1, t0 = 0, t1 = 0;
-            for (int w = 0; w < nt / 64; ++w) {
-                if (w < wid) {
-                    b0 += s_w0[w];
-                    b1 += s_w1[w];
-                }
-                t0 += s_w0[w];
-                t1 += s_w1[w];
-            }
-            const int lr = b0 + a0 - less, tr = b1 + a1 - tie;
-            __syncthreads();
+            int tot;
+            const int packed = scan1024(less | (tie << 16), s_w, tot);
+            const int lr = s_c0 + (packed & 0xffff), tr = s_c1 + (packed >> 16);
             if (i < C && (less || (tie && tr < take))) pool[lr + min(tr, take)] = j;
+            __syncthreads();
             if (tid == 0) {
-                s_c0 += t0;
-                s_c1 += t1;
+                s_c0 += tot & 0xffff;
+                s_c1 += tot >> 16;
             }
             __syncthreads();
         }
@@ -882,7 +902,8 @@ __device__ inline bool finish_range(int yx, int B, int L, int gx, const Partial*
     m.s_idx = (uint8_t)s;
     m.k = (uint8_t)k;
     // o = (4Q sumR - k sumD') / (4Q n), rounded half up
-    m.q_o = (int16_t)floordiv64(2 * (40 * (int64_t)SRq - k * sd) + 40 * n, 80 * (int64_t)n);
+    // |numerator| < 2^24 for n <= 256 (sum r <= 255 n, sum d' <= 1020 n, k <= 10)
+    m.q_o = (int16_t)floordiv32(2 * (40 * SRq - k * (int)sd) + 40 * n, 80 * n);
     m.E = (float)m.e_num / (1600.0f * (float)n);
     return true;
 }
