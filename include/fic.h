@@ -108,11 +108,13 @@ typedef struct {
     int8_t s_k[4][12];      /* strictly increasing k in 0..10 per level (s = k/10)        */
     float rms_thresh;       /* keep a transform iff sqrt(E / n) <= rms_thresh;            */
                             /* the last level always keeps it                             */
-    int32_t entropy_mode;   /* 0: no filter. 1: keep domains whose 8-bin (p >> 5)          */
-                            /* histogram entropy in bits exceeds entropy_bits             */
-    float entropy_bits;     /* threshold of mode 1 (strict >)                             */
-    int32_t min_pool;       /* if fewer domains pass, use the min_pool highest-entropy    */
-                            /* domains instead (ties to the lower index); >= 1            */
+    int32_t entropy_mode;   /* pool filter. 0: none. 1: keep domains whose 8-bin (p >> 5)  */
+                            /* histogram entropy in bits exceeds entropy_bits (Section 3).*/
+                            /* 2: keep domains whose pixel variance exceeds entropy_bits  */
+                            /* (a variance filter, as a comparator)                       */
+    float entropy_bits;     /* threshold of the filter (strict >): bits, or grey levels^2 */
+    int32_t min_pool;       /* if fewer domains pass, use the min_pool domains of highest */
+                            /* entropy (or variance) instead, ties to the lower index; >=1*/
 } fic_params;
 
 /*

@@ -224,6 +224,33 @@ def entropy_pool(img: np.ndarray, B: int, L: int, theta: float = 2.5, min_pool: 
     return np.sort(idx).astype(np.int32), n_pass
 
 
+def variance_pool(img: np.ndarray, B: int, L: int, vmin: float, min_pool: int = 256):
+    """Domain pool of one level by pixel variance (the classical alternative the paper
+    cites to the entropy filter): keep every 2B x 2B domain whose variance exceeds
+    ``vmin`` (strictly, the float32 value compared exactly); if fewer than ``min_pool``
+    pass, the ``min_pool`` highest-variance domains, ties to the lower index.
+    Returns (ascending index array, number that passed)."""
+    H, W = img.shape
+    gy, gx = domain_grid(H, W, B, L)
+    side = 2 * B
+    N = side * side
+    win = np.lib.stride_tricks.sliding_window_view(np.asarray(img, dtype=np.int64),
+                                                   (side, side))[::L, ::L]
+    s1 = win.sum(axis=(2, 3)).reshape(-1)
+    s2 = (win * win).sum(axis=(2, 3)).reshape(-1)
+    vp = N * s2 - s1 * s1                      # N^2 * variance, exact
+    t = Fraction(float(np.float32(vmin))) * N * N
+    keep = np.array([Fraction(int(v)) > t for v in vp], dtype=bool)
+    n_pass = int(keep.sum())
+    total = gy * gx
+    if n_pass >= min_pool:
+        return np.flatnonzero(keep).astype(np.int32), n_pass
+    if total <= min_pool:
+        return np.arange(total, dtype=np.int32), n_pass
+    idx = np.lexsort((np.arange(total), -vp))[:min_pool]
+    return np.sort(idx).astype(np.int32), n_pass
+
+
 def range_entropy_low(img: np.ndarray, y: int, x: int, B: int, theta: float = 2.5) -> bool:
     """True iff the B x B range block's 8-bin entropy is <= theta bits (a low-activity range)."""
     return not entropy_above(hist8(img[y:y + B, x:x + B]), theta)
@@ -308,13 +335,15 @@ def accept(e_lit: int, n: int, rms: float) -> bool:
 
 def encode_image(img: np.ndarray, s_sets=PAPER_K, levels=LEVEL_SIDES, steps=None,
                  rms: float = 8.0, entropy: bool = True, theta: float = 2.5,
-                 min_pool: int = 256):
+                 min_pool: int = 256, variance: float | None = None):
     """Quadtree encoder: match every active range, keep it if its RMS error is at most
     ``rms`` (always at the last level), else split it into TL, TR, BL, BR children.
 
     Returns (codes, stats). Codes are in level order; within a level they follow the
     active list, which is raster order at the first level and, below it, the four
-    children of each rejected range in the order of their parents.
+    children of each rejected range in the order of their parents. With ``variance``
+    set, the pool filter is the variance filter with that threshold instead of the
+    entropy filter.
     """
     img = np.ascontiguousarray(img, dtype=np.uint8)
     H, W = img.shape
@@ -326,7 +355,9 @@ def encode_image(img: np.ndarray, s_sets=PAPER_K, levels=LEVEL_SIDES, steps=None
     stats = []
     for lv, (B, L) in enumerate(zip(levels, steps)):
         gy, gx = domain_grid(H, W, B, L)
-        if entropy:
+        if variance is not None:
+            pool, n_pass = variance_pool(img, B, L, variance, min_pool)
+        elif entropy:
             pool, n_pass = entropy_pool(img, B, L, theta, min_pool)
         else:
             pool, n_pass = np.arange(gy * gx, dtype=np.int32), gy * gx

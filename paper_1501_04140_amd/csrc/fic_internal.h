@@ -60,7 +60,9 @@ struct Lvl {
     int32_t sel_shift, bound_chunk;
     int32_t capacity;
     int32_t var;                  // matcher: 1 dot4 VALU, 2 int8 MFMA, 3 FP32 comparator
-    int64_t M;                    // entropy cut (keep iff key < M)
+    int32_t pmode;                // pool filter: 0 none, 1 entropy, 2 variance
+    int64_t M;                    // filter cut (keep iff key < M)
+    int64_t kv;                   // variance filter: key = kv - (N sum p^2 - (sum p)^2)
     int64_t thr;                  // keep iff 1600 n E <= thr
     Ctrl* ctrl;
     int64_t* key;

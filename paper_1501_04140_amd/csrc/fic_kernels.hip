@@ -161,6 +161,46 @@ __device__ __forceinline__ void k_pool_score_body(const uint8_t* __restrict__ im
     if (threadIdx.x == 0 && cnt) atomicAdd(&ctrl->pass_count, cnt);
 }
 
+// Variance filter (an alternative to the entropy filter of Section 3): key[j]
+// = kv - V' with V' = N sum p^2 - (sum p)^2 over the N = SIDE^2 pixels of the
+// domain (N^2 times its variance, exact), so smaller keys mean higher variance
+// and the floor keeps the highest-variance domains. Passes iff key < M.
+template <int SIDE>
+__device__ __forceinline__ void k_pool_var_body(const uint8_t* __restrict__ img, int pitch, int L,
+                                                int gx, int total, int64_t kv, int64_t M,
+                                                int64_t* __restrict__ key, Ctrl* ctrl) {
+    using S = ScoreShape<SIDE>;
+    constexpr int TPD = S::TPD, PER = S::PER;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = g / TPD, sub = g % TPD;
+    const bool ok = j < total;
+    int s1 = 0, s2 = 0;
+    if (ok) {
+        const int y = (j / gx) * L, x = (j % gx) * L;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int m = sub * PER + q;
+            const int v = img[(int64_t)(y + m / SIDE) * pitch + x + m % SIDE];
+            s1 += v;
+            s2 += v * v;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < TPD; m <<= 1) {
+        s1 += __shfl_xor(s1, m, 64);
+        s2 += __shfl_xor(s2, m, 64);
+    }
+    int pass = 0;
+    if (ok && sub == 0) {
+        const int64_t vp = (int64_t)S::NPIX * s2 - (int64_t)s1 * s1;
+        const int64_t k = kv - vp;
+        key[j] = k;
+        pass = k < M;
+    }
+    int cnt = __syncthreads_count(pass);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&ctrl->pass_count, cnt);
+}
+
 // Pool mode for a level: 0 = threshold passers, 1 = floor (lowest keys), 2 = all.
 __device__ inline int pool_mode(int passed, int total, int min_pool) {
     if (total <= min_pool) return 2;
@@ -1649,6 +1689,13 @@ __global__ __launch_bounds__(kBlock) void kt_pool_score(Lvl a0, const Lvl* __res
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * ScoreShape<SIDE>::TPD) return;
     k_pool_score_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, T, a.M, a.key, a.ctrl);
+}
+
+template <int SIDE, bool TAB>
+__global__ __launch_bounds__(kBlock) void kt_pool_var(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * ScoreShape<SIDE>::TPD) return;
+    k_pool_var_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, a.kv, a.M, a.key, a.ctrl);
 }
 
 template <bool TAB>

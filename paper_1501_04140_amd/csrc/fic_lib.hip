@@ -364,9 +364,18 @@ Lvl make_lvl(Workspace& ws, const Level& v, const uint8_t* img, int H, int W, in
     a.min_pool = min_pool;
     a.rank = std::min(min_pool, v.total);
     const int side = 2 * v.B;
+    a.pmode = entropy_mode;
     a.M = entropy_mode == 1 ? entropy_cut(side * side, (double)entropy_bits) : 0;
+    if (entropy_mode == 2) {
+        // keep iff V' > t N^2, i.e. V' > floor(t N^2) (exact in double: t is a float, N^2 <= 2^20)
+        const double nn = (double)side * side * side * side;
+        a.kv = (int64_t)(side * side) * (side * side) * 16257;  // > N^2 * 127.5^2 >= V'
+        const double cut = std::floor((double)entropy_bits * nn);
+        const double m = (double)a.kv - cut;
+        a.M = m <= 0.0 ? 0 : (m > (double)a.kv + 1.0 ? a.kv + 1 : (int64_t)m);
+    }
     {
-        const int64_t maxkey = entropy_table()[side * side] + 1;
+        const int64_t maxkey = entropy_mode == 2 ? a.kv + 1 : entropy_table()[side * side] + 1;
         int shift = 0;
         while ((maxkey >> shift) >= kSelBins) ++shift;
         a.sel_shift = shift;
@@ -417,6 +426,11 @@ int max_over(const std::vector<Lvl>& h, F f) {
 
 template <int SIDE, bool TAB>
 void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
+    if (h[0].pmode == 2) {
+        const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });
+        kt_pool_var<SIDE, TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
+        return;
+    }
     const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });
     kt_pool_score<SIDE, TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt, T);
 }
@@ -546,8 +560,8 @@ int check_params(const fic_params* p, std::vector<KSet>& ks) {
     if ((p->B0 >> (p->n_levels - 1)) < 2) return fail(FIC_EINVAL, "last level range side below 2");
     if (!(p->rms_thresh >= 0.0f) || !std::isfinite(p->rms_thresh))
         return fail(FIC_EINVAL, "rms_thresh must be finite and >= 0");
-    if (p->entropy_mode != 0 && p->entropy_mode != 1) return fail(FIC_EINVAL, "entropy_mode %d not 0 or 1", p->entropy_mode);
-    if (p->entropy_mode == 1 && !std::isfinite(p->entropy_bits)) return fail(FIC_EINVAL, "entropy_bits not finite");
+    if (p->entropy_mode < 0 || p->entropy_mode > 2) return fail(FIC_EINVAL, "entropy_mode %d not 0, 1 or 2", p->entropy_mode);
+    if (p->entropy_mode != 0 && !std::isfinite(p->entropy_bits)) return fail(FIC_EINVAL, "entropy_bits not finite");
     if (p->min_pool < 1) return fail(FIC_EINVAL, "min_pool must be >= 1");
     ks.resize(p->n_levels);
     for (int l = 0; l < p->n_levels; ++l) {
@@ -616,7 +630,7 @@ int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch
     int rc = ensure_sizes(ws, sz);
     if (rc) return rc;
     std::vector<Lvl> t = quad_tables(ws, lv, img, H, W, pitch, p, codes, capacity, stats);
-    return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode == 1, ws.stream);
+    return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode != 0, ws.stream);
 }
 
 }  // namespace
@@ -638,8 +652,8 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     if (L < 1) return fail(FIC_EINVAL, "domain step L=%d < 1", L);
     KSet ks;
     if ((rc = check_kset(s_k, n_s, &ks))) return rc;
-    if (entropy_mode != 0 && entropy_mode != 1) return fail(FIC_EINVAL, "entropy_mode %d not 0 or 1", entropy_mode);
-    if (entropy_mode == 1 && !std::isfinite(entropy_bits)) return fail(FIC_EINVAL, "entropy_bits not finite");
+    if (entropy_mode < 0 || entropy_mode > 2) return fail(FIC_EINVAL, "entropy_mode %d not 0, 1 or 2", entropy_mode);
+    if (entropy_mode != 0 && !std::isfinite(entropy_bits)) return fail(FIC_EINVAL, "entropy_bits not finite");
     if (min_pool < 1) return fail(FIC_EINVAL, "min_pool must be >= 1");
     if (n_ranges < 0) return fail(FIC_EINVAL, "n_ranges < 0");
     if (!range_yx && n_ranges != (H / B) * (W / B))
@@ -670,7 +684,7 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
         kt_act_from_yx<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, range_yx, n_ranges);
     else
         kt_act_full<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, 0);
-    if ((rc = launch_level(dt, t, ws->T, entropy_mode == 1, st))) return rc;
+    if ((rc = launch_level(dt, t, ws->T, entropy_mode != 0, st))) return rc;
     {
         ProfScope ps("reduce_level", st);
         if (v.var == kVarFp32)
@@ -683,7 +697,7 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
         HIP_TRY(hipMemcpyAsync(pool_count, &ws->ctrl->pool_count, sizeof(int32_t),
                                hipMemcpyDeviceToDevice, st));
     if (pool_out) {
-        if (entropy_mode == 1)
+        if (entropy_mode != 0)
             HIP_TRY(hipMemcpyAsync(pool_out, ws->pool.p, sizeof(int32_t) * v.total,
                                    hipMemcpyDeviceToDevice, st));
         else
@@ -937,7 +951,7 @@ void batch_drop_graph(fic_batch* b) {
 int batch_launch(fic_batch* b, hipStream_t st) {
     const Lvl* dt = static_cast<const Lvl*>(b->dtab);
     const int n = (int)b->im.size();
-    int rc = launch_quadtree(dt, b->htab, n, b->im[0].ws->T, b->p.entropy_mode == 1, st);
+    int rc = launch_quadtree(dt, b->htab, n, b->im[0].ws->T, b->p.entropy_mode != 0, st);
     if (rc) return rc;
     kt_copy_counts<<<cdiv(n, kBlock), kBlock, 0, st>>>(dt, n, b->n_codes);
     LAUNCH_CHECK();

@@ -64,7 +64,8 @@ def _level(lib, **kw):
     (dict(s_k=(0, 11)), "not in 0..10"),
     (dict(s_k=tuple(range(11)) + (0,), n_s=12), "size"),
     (dict(n_s=0), "size"),
-    (dict(mode=2), "entropy_mode"),
+    (dict(mode=3), "entropy_mode"),
+    (dict(mode=-1), "entropy_mode"),
     (dict(min_pool=0), "min_pool"),
     (dict(n_ranges=5), "n_ranges"),
     (dict(out=None), "out is NULL"),

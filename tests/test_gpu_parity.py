@@ -51,7 +51,10 @@ def check_level(dev, img, B, L, ks, entropy=0, min_pool=256, ranges=None, bits=2
     say(f"[level] shape={img.shape} B={B} L={L} ks={ks} entropy={entropy} min_pool={min_pool} "
         f"variant={variant}")
     got, gpool = gpu_level(dev, img, B, L, ks, entropy, bits, min_pool, ranges, variant)
-    if entropy:
+    if entropy == 2:
+        pool, _ = oracle.variance_pool(img, B, L, bits, min_pool)
+        assert np.array_equal(gpool, pool)
+    elif entropy:
         pool, _ = oracle.entropy_pool(img, B, L, bits, min_pool)
         assert np.array_equal(gpool, pool)
     else:
@@ -143,6 +146,21 @@ def test_entropy_threshold_variants(dev):
         check_level(dev, img, 4, 2, (1,), entropy=1, min_pool=8, bits=bits)
 
 
+@pytest.mark.parametrize("B,L,vmin,min_pool", [(2, 1, 50.0, 256), (4, 2, 300.0, 64), (8, 4, 900.0, 16),
+                                               (16, 8, 1e9, 32), (4, 2, -1.0, 8), (2, 1, 0.0, 10 ** 6)])
+def test_variance_pool_levels(dev, B, L, vmin, min_pool):
+    """Variance filter (threshold and floor) against the oracle, then the matcher on that pool."""
+    img = synth.power_law(96, beta=1.8, seed=6, n_rect=2)
+    check_level(dev, img, B, L, (2, 4), entropy=2, min_pool=min_pool, bits=vmin)
+
+
+def test_variance_pool_ties(dev):
+    rng = np.random.default_rng(1)
+    img = (rng.integers(0, 4, size=(64, 64)) * 60).astype(np.uint8)  # few distinct variances
+    for B, L in ((2, 1), (4, 2)):
+        check_level(dev, img, B, L, (1,), entropy=2, min_pool=100, bits=1e9)
+
+
 # ------------------------------------------------------------------ quadtree
 def gpu_image(dev, img, params):
     x = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
@@ -176,6 +194,17 @@ def test_quadtree_matches_oracle(dev, size, seed, min_pool, sets):
         assert st["passed"][l] == s["passed"]
     rec = fic.decode(codes, int(n.item()), size, size, iters=24)
     assert np.array_equal(rec.cpu().numpy(), oracle.decode(ref, size, size, iters=24))
+
+
+def test_quadtree_variance_pool(dev):
+    img = synth.power_law(96, beta=2.0, seed=2, n_rect=3)
+    params = fic.EncoderParams(s_sets=oracle.PAPER_K, entropy_mode=2, entropy_bits=200.0, min_pool=48)
+    say("[quadtree] variance pool 96")
+    codes, n, got, st = gpu_image(dev, img, params)
+    ref, rst = oracle.encode_image(img, s_sets=oracle.PAPER_K, min_pool=48, variance=200.0)
+    assert_codes_equal(got, ref)
+    for l, s in enumerate(rst):
+        assert (st["pool"][l], st["passed"][l], st["accepted"][l]) == (s["pool"], s["passed"], s["accepted"])
 
 
 def test_quadtree_unfiltered_plain(dev):

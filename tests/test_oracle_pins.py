@@ -394,3 +394,41 @@ def test_psnr_definition(orc):
     b = a.copy()
     b[0, 0] = 4
     assert orc.psnr(a, b) == pytest.approx(10 * math.log10(255 ** 2 / (16 / 16)))
+
+
+# --------------------------------------------------------------------------- variance pool
+import oracle  # noqa: E402
+
+
+def _window_vars(img, side, step):
+    win = np.lib.stride_tricks.sliding_window_view(img.astype(np.float64), (side, side))[::step, ::step]
+    return win.reshape(win.shape[0] * win.shape[1], -1).var(axis=1)
+
+
+@pytest.mark.parametrize("B,L,vmin", [(4, 2, 150.0), (8, 4, 400.0), (2, 1, 30.5)])
+def test_variance_pool_threshold_matches_numpy_var(B, L, vmin):
+    img = synth.power_law(64, beta=1.6, seed=3)
+    pool, n_pass = oracle.variance_pool(img, B, L, vmin, min_pool=1)
+    v = _window_vars(img, 2 * B, L)
+    clear = np.abs(v - vmin) > 1e-6
+    keep = np.zeros(len(v), dtype=bool)
+    keep[pool] = True
+    assert n_pass == len(pool) and n_pass > 0
+    assert np.array_equal(keep[clear], (v > vmin)[clear])
+
+
+def test_variance_pool_floor_is_a_stable_sort():
+    rng = np.random.default_rng(0)
+    img = (rng.integers(0, 4, size=(40, 40)) * 60).astype(np.uint8)  # few distinct variances
+    pool, n_pass = oracle.variance_pool(img, 4, 2, 1e9, min_pool=37)
+    v = _window_vars(img, 8, 2)
+    order = sorted(range(len(v)), key=lambda j: (-round(v[j] * 64 * 64), j))[:37]
+    assert n_pass == 0 and list(pool) == sorted(order)
+
+
+def test_variance_pool_constant_image():
+    img = np.full((32, 32), 90, np.uint8)
+    pool, n = oracle.variance_pool(img, 4, 4, 0.0, min_pool=5)
+    assert n == 0 and list(pool) == [0, 1, 2, 3, 4]
+    pool, n = oracle.variance_pool(img, 4, 4, -1.0, min_pool=5)
+    assert n == len(pool) == 49  # (32 - 8) / 4 + 1 = 7 domains per side
