@@ -367,6 +367,7 @@ def encode_image(img: np.ndarray, s_sets=PAPER_K, levels=LEVEL_SIDES, steps=None
         last = lv == len(levels) - 1
         children = []
         n_acc = 0
+        split = np.zeros(len(active), dtype=bool)
         for q in range(len(active)):
             y, x = (int(v) for v in active[q])
             if last or accept(int(m["e_lit"][q]), n, rms):
@@ -374,11 +375,13 @@ def encode_image(img: np.ndarray, s_sets=PAPER_K, levels=LEVEL_SIDES, steps=None
                 codes.append((lv, y, x, B, m["dom"][q], m["dy"][q], m["dx"][q], m["iso"][q],
                               m["s_idx"][q], m["k"][q], m["q_o"][q], m["e_lit"][q]))
             else:
+                split[q] = True
                 h = B // 2
                 children += [(y, x), (y, x + h), (y + h, x), (y + h, x + h)]
         stats.append(dict(B=B, L=L, pool=len(pool), passed=n_pass, active=len(active),
                           accepted=n_acc, matches=len(active) * len(pool) * N_ISO,
-                          n_s=len(ks)))
+                          n_s=len(ks), pool_list=np.asarray(pool, np.int32), split=split,
+                          filtered=bool(entropy or variance is not None), grid=gy * gx))
         active = np.array(children, dtype=np.int32).reshape(-1, 2)
         if len(active) == 0:
             break
