@@ -247,6 +247,52 @@ int fic_profile_begin(void);
 int fic_profile_end(fic_kernel_time* out, int32_t max, int32_t* n_out);
 
 /*
+ * fic_encode_image with two optional outputs for the bitstream:
+ * flags  device uint32 bitmap (may be NULL): bit sum_{l'<l} active_l' + q is
+ *        set iff active range q of level l was split (levels but the last).
+ *        Size: one bit per possible range of every level but the last, i.e.
+ *        ceil(sum_l<n_levels-1 (H/B_l)(W/B_l) / 32) words; cleared here.
+ * pools  device int32 (may be NULL; used only with a pool filter): level l's
+ *        ascending pool list at offset sum_{l'<l} grid_l' (grid_l = domains
+ *        of level l's unfiltered grid), stats[l].pool entries long.
+ */
+int fic_encode_image_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, const fic_params* p,
+                        fic_code* codes, int32_t capacity, int32_t* n_codes, fic_level_stats* stats,
+                        uint32_t* flags, int32_t* pools, void* stream);
+
+/*
+ * Bitstream of a quadtree encode (the paper reports compression ratios in
+ * Section 4 without a bit allocation; this fixed-length layout is the reading
+ * used here). Bit b is bit (b mod 8) of byte b / 8.
+ *   header  magic 0xF1C5 (16), version 1 (8), H (16), W (16), B0 (5),
+ *           n_levels (3); per level: L (16), n_s (4), the k values (4 each),
+ *           listed (1); if listed (a pool filter is on, the level has leaves
+ *           and 24 + P bits(grid) + leaves bits(P) < leaves bits(grid)): pool
+ *           size P (24), then the P ascending grid indices (bits(grid) each).
+ *   flags   every level but the last: one bit per active range, active-list
+ *           order, 1 = split into TL, TR, BL, BR.
+ *   leaves  code order: domain (position in the level's pool, bits(P); the
+ *           grid index when not listed), isometry (3), contrast index
+ *           (bits(n_s)), offset q_o (9, two's complement).
+ * bits(x) = ceil(log2 x) for x >= 2, else 0.
+ *
+ * fic_stream_bound: bytes that always suffice (a multiple of 4), or -1.
+ * fic_pack_stream: codes, stats, flags and pools of one fic_encode_image_ex
+ *   call (device); out is device memory, 4-byte aligned, capacity a multiple
+ *   of 4 bytes. *n_bytes (device int64) receives the stream length; bytes
+ *   beyond capacity are not written.
+ * fic_unpack_stream: [host] reader. Fills up to capacity [host] codes (e_num
+ *   = -1: not stored), sets *n_codes to the number in the stream, and *H, *W.
+ *   FIC_EINVAL on a malformed stream, FIC_ECAPACITY if capacity is too small.
+ */
+int64_t fic_stream_bound(int32_t H, int32_t W, const fic_params* p);
+int fic_pack_stream(const fic_code* codes, int32_t n_codes, int32_t H, int32_t W, const fic_params* p,
+                    const fic_level_stats* stats, const uint32_t* flags, const int32_t* pools,
+                    uint8_t* out, int64_t capacity, int64_t* n_bytes, void* stream);
+int fic_unpack_stream(const uint8_t* data, int64_t n_bytes, fic_code* codes, int32_t capacity,
+                      int32_t* n_codes, int32_t* H, int32_t* W);
+
+/*
  * Batched quadtree encoder. It encodes n images of possibly different sizes
  * with the same parameters. Every level of every image runs in shared kernel
  * launches, which are captured once into a hipGraph; fic_batch_run replays

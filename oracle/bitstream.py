@@ -9,7 +9,8 @@ stream is bit (b mod 8) of byte b // 8 (least significant first).
            per level: L (16), n_s (4), the n_s contrast numerators k (4 each),
            listed (1); if listed: pool size P (24) and the P ascending grid
            indices of the pool (g bits each, g = bits for the grid size).
-           A level is listed iff a pool filter is on and it has active ranges.
+           A level is listed iff a pool filter is on, it has leaves, and the
+           list makes the level shorter: 24 + P g + leaves bits(P) < leaves g.
   flags    for every level but the last, one bit per active range in
            active-list order: 1 = split into TL, TR, BL, BR.
   leaves   in code order (level by level, active-list order): the domain's
@@ -31,6 +32,15 @@ VERSION = 1
 
 def bits_for(x: int) -> int:
     return 0 if x <= 1 else int(x - 1).bit_length()
+
+
+def _listed(st, H, W, B, L) -> bool:
+    if st is None or not st["filtered"] or st["active"] == 0 or st["accepted"] == 0:
+        return False
+    gy, gx = domain_grid(H, W, B, L)
+    g = bits_for(gy * gx)
+    P = len(st["pool_list"])
+    return 24 + P * g + st["accepted"] * bits_for(P) < st["accepted"] * g
 
 
 class _Writer:
@@ -78,7 +88,7 @@ def pack(codes, stats, H: int, W: int, levels, steps, s_sets) -> bytes:
         for k in s_sets[lv]:
             w.put(k, 4)
         st = stats[lv] if lv < len(stats) else None
-        listed = st is not None and st["filtered"] and st["active"] > 0
+        listed = _listed(st, H, W, B, L)
         w.put(int(listed), 1)
         if listed:
             gy, gx = domain_grid(H, W, B, L)
@@ -95,8 +105,7 @@ def pack(codes, stats, H: int, W: int, levels, steps, s_sets) -> bytes:
         st = stats[lv]
         B, L = levels[lv], steps[lv]
         gy, gx = domain_grid(H, W, B, L)
-        listed = st["filtered"] and st["active"] > 0
-        if listed:
+        if _listed(st, H, W, B, L):
             pos = int(np.searchsorted(st["pool_list"], int(c["dom"])))
             assert st["pool_list"][pos] == c["dom"]
             w.put(pos, bits_for(len(st["pool_list"])))
@@ -167,13 +176,13 @@ def stream_bits(stats, H: int, W: int, levels, steps, s_sets) -> int:
     for lv, (B, L) in enumerate(zip(levels, steps)):
         n += 16 + 4 + 4 * len(s_sets[lv]) + 1
         st = stats[lv] if lv < len(stats) else None
-        if st is not None and st["filtered"] and st["active"] > 0:
+        if _listed(st, H, W, B, L):
             gy, gx = domain_grid(H, W, B, L)
             n += 24 + len(st["pool_list"]) * bits_for(gy * gx)
     for lv, st in enumerate(stats):
         if lv < len(levels) - 1:
             n += st["active"]
         gy, gx = domain_grid(H, W, levels[lv], steps[lv])
-        P = len(st["pool_list"]) if st["filtered"] and st["active"] > 0 else gy * gx
+        P = len(st["pool_list"]) if _listed(st, H, W, levels[lv], steps[lv]) else gy * gx
         n += st["accepted"] * (bits_for(P) + 3 + bits_for(len(s_sets[lv])) + 9)
     return n

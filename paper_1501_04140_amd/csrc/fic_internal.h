@@ -87,6 +87,8 @@ struct Lvl {
     int8_t* dl;
     float* gd;
     float* af;
+    uint32_t* flags;    // optional: split flags, one bit per active range, levels in order
+    int32_t* pools_out; // optional: this level's pool list
     KSet ks;
 };
 

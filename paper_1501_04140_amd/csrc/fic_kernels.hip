@@ -974,9 +974,11 @@ __device__ __forceinline__ void k_reduce_quad_body(
     Ctrl* ctrl, const Partial* __restrict__ part, int n_chunks, int CG,
     const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, KSet ks,
     fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk, fic_level_stats* stats,
-    int nblk) {
+    int nblk, uint32_t* __restrict__ flags) {
     const int base = blockIdx.x * kBlock * kQuadItems + threadIdx.x * kQuadItems;
     const int nact = ctrl->act_count[lv];
+    int fbase = 0;  // first flag bit of this level
+    for (int l = 0; l < lv; ++l) fbase += ctrl->act_count[l];
     const int nca = active_chunks(ctrl->pool_count, CG, n_chunks);
     int kept = 0, split = 0;
     for (int u = 0; u < kQuadItems; ++u) {
@@ -1009,6 +1011,7 @@ __device__ __forceinline__ void k_reduce_quad_body(
         dec[q] = d;
         kept += d == 1;
         split += d == 0;
+        if (flags && d == 0) atomicOr(&flags[(fbase + q) >> 5], 1u << ((fbase + q) & 31));
     }
     int e0, e1, t0, t1;
     block_scan2(kept, split, e0, e1, t0, t1);
@@ -1698,6 +1701,14 @@ __global__ __launch_bounds__(kBlock) void kt_pool_var(Lvl a0, const Lvl* __restr
     k_pool_var_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, a.kv, a.M, a.key, a.ctrl);
 }
 
+// Copy of the level's final pool list (for the bitstream).
+template <bool TAB>
+__global__ __launch_bounds__(kBlock) void kt_copy_pool(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    const int n = a.ctrl->pool_count;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) a.pools_out[i] = a.pool[i];
+}
+
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_floor_bound(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
@@ -1801,7 +1812,7 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_quad(Lvl a0, const Lvl* __re
     const int nblk = (a.max_act + kBlock * kQuadItems - 1) / (kBlock * kQuadItems);
     if ((int)blockIdx.x >= nblk) return;
     k_reduce_quad_body(a.B, a.L, a.gx, a.lv, a.last, a.thr, a.act, a.ctrl, a.part, a.nc, a.cg, a.cr,
-                       a.sr, a.ks, a.tmpc, a.dec, a.blk, a.stats, nblk);
+                       a.sr, a.ks, a.tmpc, a.dec, a.blk, a.stats, nblk, a.flags);
 }
 
 template <bool TAB>

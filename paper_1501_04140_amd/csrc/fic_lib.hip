@@ -64,6 +64,7 @@ struct Workspace {
     Buf key, pool, hl, sd, ad, jd, arow, sr, cr, part, blk, act0, act1, tmpc, dec, codes, map,
         imgA, imgB, acc, mr;
     Buf ar, srp, dh, dl, wd, cw;  // int8 MFMA matcher (B = 8)
+    Buf plan;                     // bitstream section offsets
 
 };
 
@@ -132,7 +133,7 @@ void free_ws(Workspace* ws) {
     Buf* bufs[] = {&ws->key, &ws->pool, &ws->hl, &ws->sd, &ws->ad, &ws->jd, &ws->arow, &ws->sr,
                    &ws->cr, &ws->part, &ws->blk, &ws->act0, &ws->act1, &ws->tmpc, &ws->dec,
                    &ws->codes, &ws->map, &ws->imgA, &ws->imgB, &ws->acc, &ws->mr, &ws->ar,
-                   &ws->srp, &ws->dh, &ws->dl, &ws->wd, &ws->cw};
+                   &ws->srp, &ws->dh, &ws->dl, &ws->wd, &ws->cw, &ws->plan};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     (void)hipFree(ws->ctrl);
@@ -505,6 +506,10 @@ int launch_level_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, b
             ProfScope ps("pool_select", st);
             kt_floor_select<TAB><<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt);
         }
+        if (h[0].pools_out) {
+            const int gx = max_over(h, [](const Lvl& a) { return std::min(cdiv(a.total, kBlock), 1024); });
+            kt_copy_pool<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+        }
     }
     switch (B) {
         case 2: launch_prep_match<2, TAB>(dt, h, filtered, st); break;
@@ -586,8 +591,10 @@ std::vector<Level> quad_levels(int H, int W, const fic_params* p, const std::vec
 // Argument tables of one image's quadtree (one entry per level).
 std::vector<Lvl> quad_tables(Workspace& ws, const std::vector<Level>& lv, const uint8_t* img,
                              int H, int W, int pitch, const fic_params* p, fic_code* codes,
-                             int capacity, fic_level_stats* stats) {
+                             int capacity, fic_level_stats* stats, uint32_t* flags = nullptr,
+                             int32_t* pools = nullptr) {
     std::vector<Lvl> t;
+    int64_t pool_off = 0;
     for (size_t l = 0; l < lv.size(); ++l) {
         const Level& v = lv[l];
         int32_t* cur = P<int32_t>((l % 2) ? ws.act1 : ws.act0);
@@ -596,6 +603,9 @@ std::vector<Lvl> quad_tables(Workspace& ws, const std::vector<Level>& lv, const 
         t.push_back(make_lvl(ws, v, img, H, W, pitch, p->entropy_mode, p->entropy_bits, p->min_pool,
                              cur, nxt, last, keep_threshold(p->rms_thresh, v.B), codes, capacity,
                              stats));
+        t.back().flags = last ? nullptr : flags;
+        t.back().pools_out = (pools && p->entropy_mode != 0) ? pools + pool_off : nullptr;
+        pool_off += v.total;
     }
     return t;
 }
@@ -621,15 +631,31 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
 }
 
 // Quadtree encode of one image into `codes` (device); counters in ws.ctrl.
+// Words of the split-flag bitmap: one bit per possible active range of every level but the last.
+int64_t flag_words(int H, int W, const fic_params* p) {
+    int64_t bits = 0;
+    for (int l = 0; l + 1 < p->n_levels; ++l) {
+        const int B = p->B0 >> l;
+        bits += (int64_t)(H / B) * (W / B);
+    }
+    return (bits + 31) / 32;
+}
+
 int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch,
                       const fic_params* p, const std::vector<KSet>& ks, fic_code* codes,
-                      int capacity, fic_level_stats* stats) {
+                      int capacity, fic_level_stats* stats, uint32_t* flags = nullptr,
+                      int32_t* pools = nullptr) {
     std::vector<Level> lv = quad_levels(H, W, p, ks);
     Sizes sz;
     for (const Level& v : lv) grow(sz, v);
     int rc = ensure_sizes(ws, sz);
     if (rc) return rc;
-    std::vector<Lvl> t = quad_tables(ws, lv, img, H, W, pitch, p, codes, capacity, stats);
+    if (flags) {
+        const int64_t nw = flag_words(H, W, p);
+        if (nw > 0)
+            k_fill_i32<<<cdiv(nw, kBlock), kBlock, 0, ws.stream>>>(reinterpret_cast<int32_t*>(flags), (int)nw, 0);
+    }
+    std::vector<Lvl> t = quad_tables(ws, lv, img, H, W, pitch, p, codes, capacity, stats, flags, pools);
     return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode != 0, ws.stream);
 }
 
@@ -731,6 +757,27 @@ FIC_API int fic_encode_image(const uint8_t* img, int32_t H, int32_t W, int32_t p
     Workspace* ws;
     if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
     if ((rc = encode_image_impl(*ws, img, H, W, pitch, p, ks, codes, capacity, stats))) return rc;
+    HIP_TRY(hipMemcpyAsync(n_codes, &ws->ctrl->n_codes, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                           ws->stream));
+    return FIC_OK;
+}
+
+FIC_API int fic_encode_image_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
+                                const fic_params* p, fic_code* codes, int32_t capacity,
+                                int32_t* n_codes, fic_level_stats* stats, uint32_t* flags,
+                                int32_t* pools, void* stream) {
+    std::vector<KSet> ks;
+    int rc = check_params(p, ks);
+    if (rc) return rc;
+    if ((rc = check_image(img, H, W, pitch, p->B0))) return rc;
+    if (!codes || !n_codes) return fail(FIC_EINVAL, "codes or n_codes is NULL");
+    const int lower = (H / p->B0) * (W / p->B0);
+    if (capacity < lower)
+        return fail(FIC_ECAPACITY, "capacity %d below the %d codes of the first level", capacity, lower);
+    Workspace* ws;
+    if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
+    if ((rc = encode_image_impl(*ws, img, H, W, pitch, p, ks, codes, capacity, stats, flags, pools)))
+        return rc;
     HIP_TRY(hipMemcpyAsync(n_codes, &ws->ctrl->n_codes, sizeof(int32_t), hipMemcpyDeviceToDevice,
                            ws->stream));
     return FIC_OK;
@@ -1224,3 +1271,4 @@ FIC_API int fic_batch_destroy(fic_batch* b) {
 }
 
 #include "fic_learned_api.hip"
+#include "fic_stream.hip"

@@ -121,6 +121,14 @@ def load():
     lib.fic_encode_level_learned.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, i32, f32, vp, vp,
                                              vp, vp]
     lib.fic_level_codes.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    lib.fic_encode_image_ex.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, i32, vp, vp, vp,
+                                        vp, vp]
+    lib.fic_stream_bound.argtypes = [i32, i32, ctypes.POINTER(Params)]
+    lib.fic_stream_bound.restype = ctypes.c_int64
+    lib.fic_pack_stream.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, vp, vp, vp,
+                                    ctypes.c_int64, vp, vp]
+    lib.fic_unpack_stream.argtypes = [vp, ctypes.c_int64, vp, i32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.fic_last_error.restype = ctypes.c_char_p
     for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_image", "fic_decode", "fic_sse",
                  "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end",
@@ -128,7 +136,7 @@ def load():
                  "fic_batch_autotune", "fic_batch_destroy", "fic_mlp_create", "fic_mlp_destroy",
                  "fic_mlp_get_params", "fic_mlp_embed", "fic_mlp_loss_grad", "fic_mlp_adam",
                  "fic_mlp_train_step", "fic_topk_similar", "fic_encode_level_learned",
-                 "fic_level_codes"):
+                 "fic_level_codes", "fic_encode_image_ex", "fic_pack_stream", "fic_unpack_stream"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -409,6 +417,65 @@ def level_codes(matches, H: int, W: int, B: int, L: int, stream=None):
     codes = torch.empty((max(nr, 1), 32), dtype=torch.uint8, device=matches.device)
     _check(load().fic_level_codes(matches.data_ptr(), H, W, B, L, codes.data_ptr(), _stream(stream)))
     return codes[:nr]
+
+
+def stream_bound(H: int, W: int, params: EncoderParams | None = None) -> int:
+    p = (params or EncoderParams()).to_c()
+    n = load().fic_stream_bound(H, W, ctypes.byref(p))
+    if n < 0:
+        raise FicError(FIC_EINVAL, "parameters do not fit the image")
+    return int(n)
+
+
+def encode_image_stream(img, params: EncoderParams | None = None, stream=None):
+    """fic_encode_image_ex then fic_pack_stream. Returns (stream bytes as a host numpy
+    uint8 array, codes, n_codes, stats) -- the last three as in encode_image."""
+    import torch
+    img = _dev_u8_image(img)
+    params = params or EncoderParams()
+    H, W = img.shape
+    p = params.to_c()
+    cap = code_capacity(H, W, params.levels)
+    dev = img.device
+    codes = torch.empty((max(cap, 1), 32), dtype=torch.uint8, device=dev)
+    ncodes = torch.zeros(1, dtype=torch.int32, device=dev)
+    stats = torch.zeros((len(params.levels), 24), dtype=torch.uint8, device=dev)
+    nflag = sum((H // B) * (W // B) for B in params.levels[:-1])
+    flags = torch.zeros(max((nflag + 31) // 32, 1), dtype=torch.int32, device=dev)
+    steps = params.steps or tuple(max(int(B) // 2, 1) for B in params.levels)
+    ngrid = sum(((H - 2 * B) // L + 1) * ((W - 2 * B) // L + 1) for B, L in zip(params.levels, steps))
+    pools = torch.zeros(max(ngrid, 1), dtype=torch.int32, device=dev)
+    lib = load()
+    st = _stream(stream)
+    _check(lib.fic_encode_image_ex(img.data_ptr(), H, W, img.stride(0), ctypes.byref(p), codes.data_ptr(),
+                                   cap, ncodes.data_ptr(), stats.data_ptr(), flags.data_ptr(),
+                                   pools.data_ptr(), st))
+    n = int(ncodes.item())
+    bound = stream_bound(H, W, params)
+    out = torch.zeros(bound, dtype=torch.uint8, device=dev)
+    nbytes = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib.fic_pack_stream(codes.data_ptr(), min(n, cap), H, W, ctypes.byref(p), stats.data_ptr(),
+                               flags.data_ptr(), pools.data_ptr(), out.data_ptr(), bound,
+                               nbytes.data_ptr(), st))
+    nb = int(nbytes.item())
+    return out[:nb].cpu().numpy(), codes, ncodes, stats
+
+
+def unpack_stream(data):
+    """fic_unpack_stream (host): (codes numpy CODE_DTYPE, H, W); e_num is -1."""
+    buf = np.ascontiguousarray(np.frombuffer(bytes(data), dtype=np.uint8))
+    n = ctypes.c_int32(0)
+    H = ctypes.c_int32(0)
+    W = ctypes.c_int32(0)
+    lib = load()
+    rc = lib.fic_unpack_stream(buf.ctypes.data, buf.size, None, 0, ctypes.byref(n), ctypes.byref(H),
+                               ctypes.byref(W))
+    if rc not in (FIC_OK, FIC_ECAPACITY):
+        _check(rc)
+    codes = np.zeros(max(n.value, 1), dtype=CODE_DTYPE)
+    _check(lib.fic_unpack_stream(buf.ctypes.data, buf.size, codes.ctypes.data, n.value, ctypes.byref(n),
+                                 ctypes.byref(H), ctypes.byref(W)))
+    return codes[:n.value], H.value, W.value
 
 
 def decode(codes, n_codes: int, H: int, W: int, iters: int = 64, stream=None):

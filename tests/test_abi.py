@@ -189,3 +189,43 @@ def test_batch_calls_reject_null(lib):
     assert lib.fic_batch_get_chunks(None, None) == fic.FIC_EINVAL
     assert lib.fic_batch_autotune(None, None, 1, None, None) == fic.FIC_EINVAL
     assert lib.fic_batch_destroy(None) == fic.FIC_OK
+
+
+# ------------------------------------------------------------------ bitstream reader (host code)
+@pytest.mark.parametrize("size,kw", [(64, dict(min_pool=64)), (96, dict(min_pool=32, variance=150.0)),
+                                     (64, dict(entropy=False, s_sets=("plain",) * 4))])
+def test_library_reader_parses_reference_streams(size, kw):
+    """The library's host reader against streams written by the reference writer."""
+    import oracle
+    from oracle import bitstream as bs
+    from paper_1501_04140_amd import synth
+    img = synth.power_law(size, beta=2.0, seed=3, n_rect=2)
+    s_sets = kw.pop("s_sets", oracle.PAPER_K)
+    if s_sets[0] == "plain":
+        s_sets = (oracle.PLAIN_K,) * 4
+    codes, stats = oracle.encode_image(img, s_sets=s_sets, **kw)
+    data = bs.pack(codes, stats, size, size, oracle.LEVEL_SIDES, oracle.default_steps(), s_sets)
+    got, H, W = fic.unpack_stream(data)
+    assert (H, W) == (size, size) and len(got) == len(codes)
+    for f in ("level", "y", "x", "dom", "dy", "dx", "iso", "s_idx", "k", "q_o"):
+        assert np.array_equal(got[f].astype(np.int64), codes[f].astype(np.int64)), f
+    assert np.array_equal(1 << got["log2B"].astype(np.int64), codes["B"])
+    assert (got["e_num"] == -1).all()
+
+
+def test_library_reader_rejects_bad_streams(lib):
+    import oracle
+    from oracle import bitstream as bs
+    from paper_1501_04140_amd import synth
+    img = synth.power_law(64, beta=2.0, seed=0)
+    codes, stats = oracle.encode_image(img, min_pool=16)
+    data = bs.pack(codes, stats, 64, 64, oracle.LEVEL_SIDES, oracle.default_steps(), oracle.PAPER_K)
+    n = ctypes.c_int32(0)
+    buf = (ctypes.c_uint8 * len(data)).from_buffer_copy(data)
+    assert lib.fic_unpack_stream(buf, len(data) // 2, None, 0, ctypes.byref(n), None, None) == fic.FIC_EINVAL
+    bad = bytearray(data)
+    bad[0] ^= 1
+    buf2 = (ctypes.c_uint8 * len(bad)).from_buffer_copy(bytes(bad))
+    assert lib.fic_unpack_stream(buf2, len(bad), None, 0, ctypes.byref(n), None, None) == fic.FIC_EINVAL
+    assert lib.fic_unpack_stream(buf, len(data), None, 0, ctypes.byref(n), None, None) == fic.FIC_ECAPACITY
+    assert n.value == len(codes)
