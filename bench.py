@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="quadtree512",
-                    choices=["quadtree512", "single128", "precision1024", "batch64", "learned2048"])
+                    choices=["quadtree512", "single128", "precision1024", "batch64", "learned2048",
+                             "sweep512"])
     ap.add_argument("--n-train", type=int, default=200, help="learned2048: training images")
     ap.add_argument("--epochs", type=int, default=LEARNED_EPOCHS, help="learned2048: epochs")
     ap.add_argument("--n-eval", type=int, default=16, help="learned2048: evaluation images")
@@ -228,6 +229,13 @@ def run_quadtree(args, torch):
         res["psnr_db"] = p_method
         res["psnr_exhaustive_db"] = p_ex
         res["psnr_delta_db"] = p_method - p_ex
+        data, _, _, _ = fic.encode_image_stream(x, params)
+        data_ex, _, _, _ = fic.encode_image_stream(x, plain)
+        res["stream_bytes"] = int(len(data))
+        res["bpp"] = len(data) * 8 / (H * W)
+        res["compression_ratio"] = H * W / len(data)
+        res["exhaustive"].update({"stream_bytes": int(len(data_ex)), "bpp": len(data_ex) * 8 / (H * W),
+                                  "compression_ratio": H * W / len(data_ex)})
         res["exhaustive"] = {"encode_ms": ex_ms, "matches": ex_matches,
                              "codes": int(n2.item()), "codes_method": int(n.item())}
     if not args.no_cpu_baseline:
@@ -454,6 +462,59 @@ def run_learned(args, torch):
     return res
 
 
+def run_sweep(args, torch):
+    """Pool sizes 256/64/32 for the entropy-based method (filtered pool, s over the
+    11-value grid) and the proposed method (filtered pool, predefined s), against the
+    plain exhaustive encoder: encode ms, PSNR and compression ratio of the stream."""
+    from paper_1501_04140_amd import fic, synth
+
+    img = synth.quadtree_image(0)
+    H, W = img.shape
+    x = torch.from_numpy(img).cuda()
+    ks = fic.calibrate_s(x, fic.EncoderParams())
+    methods = {"entropy_based": (fic.PLAIN_K,) * 4, "proposed_calibrated": fic.calibrated_sets(ks),
+               "proposed_paper_s": fic.PAPER_K}
+
+    def measure(params, reps):
+        out = fic.encode_image(x, params)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fic.encode_image(x, params, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        codes, n, st = out
+        rec = fic.decode(codes, int(n.item()), H, W, iters=64)
+        data, _, _, _ = fic.encode_image_stream(x, params)
+        stats = fic.stats_numpy(st)
+        return {"encode_ms": e0.elapsed_time(e1) / reps, "psnr_db": fic.psnr(rec, x),
+                "stream_bytes": int(len(data)), "bpp": len(data) * 8 / (H * W),
+                "compression_ratio": H * W / len(data), "codes": int(n.item()),
+                "matches": int(stats["matches"].sum())}
+
+    reps = max(1, args.steps // 5)
+    ex = measure(fic.EncoderParams(s_sets=(fic.PLAIN_K,) * 4, entropy_mode=0), 1)
+    table = {}
+    for pool in (256, 64, 32):
+        for name, sets in methods.items():
+            r = measure(fic.EncoderParams(s_sets=sets, min_pool=pool), reps)
+            r["psnr_delta_db"] = r["psnr_db"] - ex["psnr_db"]
+            r["speedup_vs_exhaustive"] = ex["encode_ms"] / r["encode_ms"]
+            table[f"{name}@{pool}"] = r
+            print(json.dumps({"pool": pool, "method": name, **r}), file=sys.stderr, flush=True)
+    base, prop = table["entropy_based@256"], table["proposed_calibrated@256"]
+    return {
+        "metric": "pool-size sweep (256/64/32): encode ms, PSNR, compression ratio per method",
+        "value": base["encode_ms"] / prop["encode_ms"], "unit": "x (proposed vs entropy-based, pool 256)",
+        "encode_ms": prop["encode_ms"],
+        "config": {"workload": "sweep512: 512x512 1/f^2 + 3 rectangles (seed 0), quadtree 16..2, RMS 8",
+                   "s_calibrated": [list(v) for v in methods["proposed_calibrated"]]},
+        "exhaustive": ex, "table": table,
+    }
+
+
 def run_level(args, torch, which):
     from paper_1501_04140_amd import fic, synth
 
@@ -559,6 +620,8 @@ def main():
         res = run_batch(args, torch)
     elif args.workload == "learned2048":
         res = run_learned(args, torch)
+    elif args.workload == "sweep512":
+        res = run_sweep(args, torch)
     else:
         res = run_level(args, torch, args.workload)
     line = {
