@@ -229,6 +229,8 @@ def run_quadtree(args, torch):
         res["psnr_db"] = p_method
         res["psnr_exhaustive_db"] = p_ex
         res["psnr_delta_db"] = p_method - p_ex
+        res["exhaustive"] = {"encode_ms": ex_ms, "matches": ex_matches,
+                             "codes": int(n2.item()), "codes_method": int(n.item())}
         data, _, _, _ = fic.encode_image_stream(x, params)
         data_ex, _, _, _ = fic.encode_image_stream(x, plain)
         res["stream_bytes"] = int(len(data))
@@ -236,8 +238,6 @@ def run_quadtree(args, torch):
         res["compression_ratio"] = H * W / len(data)
         res["exhaustive"].update({"stream_bytes": int(len(data_ex)), "bpp": len(data_ex) * 8 / (H * W),
                                   "compression_ratio": H * W / len(data_ex)})
-        res["exhaustive"] = {"encode_ms": ex_ms, "matches": ex_matches,
-                             "codes": int(n2.item()), "codes_method": int(n.item())}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
@@ -494,6 +494,15 @@ def run_sweep(args, torch):
                 "compression_ratio": H * W / len(data), "codes": int(n.item()),
                 "matches": int(stats["matches"].sum())}
 
+    # Fig. 3: histograms of the optimal s per step over a set of 8 images (seeds 1..8, not
+    # the test image), and the 1-2 most frequent values per step
+    hist = None
+    for seed in range(1, 9):
+        hist = fic.s_histogram(torch.from_numpy(synth.quadtree_image(seed)).cuda(), fic.EncoderParams(),
+                               False, hist)
+    hist_np = hist.cpu().numpy()
+    chosen = fic.select_s(hist_np)
+    methods["proposed_histogram"] = tuple(c if c else fic.PAPER_K[l] for l, c in enumerate(chosen))
     reps = max(1, args.steps // 5)
     ex = measure(fic.EncoderParams(s_sets=(fic.PLAIN_K,) * 4, entropy_mode=0), 1)
     table = {}
@@ -510,7 +519,9 @@ def run_sweep(args, torch):
         "value": base["encode_ms"] / prop["encode_ms"], "unit": "x (proposed vs entropy-based, pool 256)",
         "encode_ms": prop["encode_ms"],
         "config": {"workload": "sweep512: 512x512 1/f^2 + 3 rectangles (seed 0), quadtree 16..2, RMS 8",
-                   "s_calibrated": [list(v) for v in methods["proposed_calibrated"]]},
+                   "s_calibrated": [list(v) for v in methods["proposed_calibrated"]],
+                   "s_histogram_set": [list(v) for v in methods["proposed_histogram"]]},
+        "s_histograms_8_images": hist_np.tolist(),
         "exhaustive": ex, "table": table,
     }
 

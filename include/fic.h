@@ -428,6 +428,25 @@ int fic_encode_level_learned(fic_mlp* m, const uint8_t* img, int32_t H, int32_t 
 int fic_level_codes(const fic_match* m, int32_t H, int32_t W, int32_t B, int32_t L, fic_code* codes,
                     void* stream);
 
+/*
+ * Distribution of the optimal contrast, for choosing predefined values per
+ * quadtree step (Section 3.1, Fig. 3). Encodes the image with the plain
+ * method (11 values, no pool filter, p's levels, steps and RMS threshold) and
+ * adds 1 to hist[l][k] (device uint64 [4][11], not cleared: calls accumulate
+ * over an image set) for every kept leaf of level l with contrast k/10 -- all
+ * of them, or with low_entropy_only only those whose range has 8-bin entropy
+ * <= p->entropy_bits. Synchronises `stream`.
+ */
+int fic_s_histogram(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, const fic_params* p,
+                    int32_t low_entropy_only, uint64_t* hist, void* stream);
+/*
+ * [host] Predefined values from such histograms ([host] uint64 [n_levels][11]):
+ * per level the most frequent k, plus the second most frequent when its count
+ * is at least second_frac of the first (ties to the smaller k); s_k [4][2]
+ * ascending, n_s[l] = 1 or 2, or 0 for an empty histogram.
+ */
+int fic_select_s(const uint64_t* hist, int32_t n_levels, float second_frac, int8_t* s_k, int32_t* n_s);
+
 /* Message for the last non-zero return on this thread. */
 const char* fic_last_error(void);
 

@@ -412,6 +412,36 @@ def calibrate_s(img: np.ndarray, levels=LEVEL_SIDES, steps=None, rms: float = 8.
 
 
 # --------------------------------------------------------------------------- decoder (Section 4)
+def s_histogram(img: np.ndarray, levels=LEVEL_SIDES, steps=None, rms: float = 8.0,
+                low_only: bool = False, theta: float = 2.5) -> np.ndarray:
+    """Counts [len(levels), 11] of the optimal contrast numerator k over the kept leaves
+    of the plain quadtree (11 values, no pool filter) -- Section 3.1's Fig. 3 -- over
+    all leaves, or only those whose range has 8-bin entropy <= theta."""
+    codes, _ = encode_image(img, s_sets=(PLAIN_K,) * len(levels), levels=levels, steps=steps,
+                            rms=rms, entropy=False)
+    hist = np.zeros((len(levels), 11), dtype=np.int64)
+    for c in codes:
+        if low_only and not range_entropy_low(img, int(c["y"]), int(c["x"]), int(c["B"]), theta):
+            continue
+        hist[int(c["level"]), int(c["k"])] += 1
+    return hist
+
+
+def select_s(hist, second_frac: float = 0.5):
+    """Per level: the most frequent k, and the second most frequent too when its count is at
+    least ``second_frac`` of the first (ties to the smaller k). Empty levels give ()."""
+    out = []
+    for h in np.asarray(hist):
+        order = sorted((k for k in range(11) if h[k] > 0), key=lambda k: (-h[k], k))
+        if not order:
+            out.append(())
+        elif len(order) > 1 and h[order[1]] >= second_frac * h[order[0]]:
+            out.append(tuple(sorted(order[:2])))
+        else:
+            out.append((order[0],))
+    return tuple(out)
+
+
 def decode(codes, H: int, W: int, iters: int = 64) -> np.ndarray:
     """Iterate the code's map from a mid-grey image, all in integers.
 

@@ -1137,6 +1137,34 @@ __global__ void k_calib_accum(const uint8_t* __restrict__ img, int pitch,
 
 
 
+// Histogram of the optimal contrast numerator k over kept leaves (all of them,
+// or only those whose B x B range has 8-bin entropy <= theta): hist[level][k].
+__global__ void k_calib_hist(const uint8_t* __restrict__ img, int pitch,
+                             const fic_code* __restrict__ codes, const Ctrl* ctrl, int capacity,
+                             const int64_t* __restrict__ T, const int64_t* __restrict__ Mr,
+                             int low_only, unsigned long long* __restrict__ hist /* [4][11] */) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = min(ctrl->n_codes, capacity);
+    if (i >= nc) return;
+    const fic_code c = codes[i];
+    if (c.k > 10 || c.level > 3) return;
+    if (low_only) {
+        const int B = 1 << c.log2B;
+        int h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < B; ++a)
+            for (int b = 0; b < B; ++b) {
+                const int v = img[(c.y + a) * pitch + c.x + b] >> 5;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) h[q] += (v == q);
+            }
+        int64_t s = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += T[h[q]];
+        if (s < Mr[c.level]) return;
+    }
+    atomicAdd(&hist[c.level * 11 + c.k], 1ull);
+}
+
 // ================================================================ int8 MFMA matcher (B = 8)
 // The correlation of every range row with every pool domain as an integer
 // GEMM on the matrix cores: rows are r' = r - 128 (int8), columns split the

@@ -885,6 +885,72 @@ FIC_API int fic_calibrate_s(const uint8_t* img, int32_t H, int32_t W, int32_t pi
     return FIC_OK;
 }
 
+FIC_API int fic_s_histogram(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, const fic_params* p,
+                            int32_t low_entropy_only, uint64_t* hist, void* stream) {
+    if (!hist) return fail(FIC_EINVAL, "hist is NULL");
+    if (!p) return fail(FIC_EINVAL, "params pointer is NULL");
+    fic_params q = *p;
+    q.entropy_mode = 0;
+    for (int l = 0; l < 4; ++l) {
+        q.n_s[l] = 11;
+        for (int k = 0; k <= 10; ++k) q.s_k[l][k] = (int8_t)k;
+    }
+    std::vector<KSet> ks;
+    int rc = check_params(&q, ks);
+    if (rc) return rc;
+    if (low_entropy_only && !std::isfinite(p->entropy_bits)) return fail(FIC_EINVAL, "entropy_bits not finite");
+    if ((rc = check_image(img, H, W, pitch, q.B0))) return rc;
+    Workspace* ws;
+    if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
+    const int Blast = q.B0 >> (q.n_levels - 1);
+    const int capacity = (H / Blast) * (W / Blast);
+    if ((rc = ensure(*ws, ws->codes, (size_t)capacity * sizeof(fic_code)))) return rc;
+    if ((rc = ensure(*ws, ws->mr, 64))) return rc;
+    if ((rc = encode_image_impl(*ws, img, H, W, pitch, &q, ks, P<fic_code>(ws->codes), capacity, nullptr)))
+        return rc;
+    hipStream_t st = ws->stream;
+    int64_t mr[4] = {0, 0, 0, 0};
+    for (int l = 0; l < q.n_levels; ++l) {
+        const int B = q.B0 >> l;
+        mr[l] = low_entropy_only ? entropy_cut(B * B, (double)p->entropy_bits) : 0;
+    }
+    HIP_TRY(hipMemcpyAsync(ws->mr.p, mr, sizeof mr, hipMemcpyHostToDevice, st));
+    k_calib_hist<<<cdiv(capacity, kBlock), kBlock, 0, st>>>(img, pitch, P<fic_code>(ws->codes), ws->ctrl,
+                                                          capacity, ws->T, P<int64_t>(ws->mr),
+                                                          low_entropy_only ? 1 : 0,
+                                                          reinterpret_cast<unsigned long long*>(hist));
+    LAUNCH_CHECK();
+    HIP_TRY(hipStreamSynchronize(st));  // the host copy of mr must outlive the upload
+    return FIC_OK;
+}
+
+FIC_API int fic_select_s(const uint64_t* hist, int32_t n_levels, float second_frac, int8_t* s_k,
+                         int32_t* n_s) {
+    if (!hist || !s_k || !n_s) return fail(FIC_EINVAL, "NULL argument");
+    if (n_levels < 1 || n_levels > 4) return fail(FIC_EINVAL, "n_levels %d not in 1..4", n_levels);
+    if (!(second_frac >= 0.0f) || !(second_frac <= 1.0f)) return fail(FIC_EINVAL, "second_frac not in [0, 1]");
+    for (int l = 0; l < n_levels; ++l) {
+        const uint64_t* h = hist + 11 * l;
+        int a = -1, b = -1;  // most and second most frequent k (ties to the smaller k)
+        for (int k = 0; k <= 10; ++k) {
+            if (h[k] == 0) continue;
+            if (a < 0 || h[k] > h[a]) {
+                b = a;
+                a = k;
+            } else if (b < 0 || h[k] > h[b]) {
+                b = k;
+            }
+        }
+        n_s[l] = 0;
+        if (a < 0) continue;
+        const bool two = b >= 0 && (double)h[b] >= (double)second_frac * (double)h[a];
+        s_k[2 * l] = (int8_t)(two ? std::min(a, b) : a);
+        s_k[2 * l + 1] = (int8_t)(two ? std::max(a, b) : 0);
+        n_s[l] = two ? 2 : 1;
+    }
+    return FIC_OK;
+}
+
 FIC_API int fic_profile_begin(void) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     for (auto& r : g_prof.recs) {

@@ -123,6 +123,8 @@ def load():
     lib.fic_level_codes.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     lib.fic_encode_image_ex.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, i32, vp, vp, vp,
                                         vp, vp]
+    lib.fic_s_histogram.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), i32, vp, vp]
+    lib.fic_select_s.argtypes = [vp, i32, f32, vp, vp]
     lib.fic_stream_bound.argtypes = [i32, i32, ctypes.POINTER(Params)]
     lib.fic_stream_bound.restype = ctypes.c_int64
     lib.fic_pack_stream.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, vp, vp, vp,
@@ -136,7 +138,8 @@ def load():
                  "fic_batch_autotune", "fic_batch_destroy", "fic_mlp_create", "fic_mlp_destroy",
                  "fic_mlp_get_params", "fic_mlp_embed", "fic_mlp_loss_grad", "fic_mlp_adam",
                  "fic_mlp_train_step", "fic_topk_similar", "fic_encode_level_learned",
-                 "fic_level_codes", "fic_encode_image_ex", "fic_pack_stream", "fic_unpack_stream"):
+                 "fic_level_codes", "fic_encode_image_ex", "fic_pack_stream", "fic_unpack_stream",
+                 "fic_s_histogram", "fic_select_s"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -417,6 +420,30 @@ def level_codes(matches, H: int, W: int, B: int, L: int, stream=None):
     codes = torch.empty((max(nr, 1), 32), dtype=torch.uint8, device=matches.device)
     _check(load().fic_level_codes(matches.data_ptr(), H, W, B, L, codes.data_ptr(), _stream(stream)))
     return codes[:nr]
+
+
+def s_histogram(img, params: EncoderParams | None = None, low_entropy_only: bool = False, hist=None,
+                stream=None):
+    """fic_s_histogram: adds the image's optimal-contrast counts to ``hist`` (device int64
+    [4, 11], created zeroed when None) and returns it."""
+    import torch
+    img = _dev_u8_image(img)
+    H, W = img.shape
+    p = (params or EncoderParams()).to_c()
+    if hist is None:
+        hist = torch.zeros((4, 11), dtype=torch.int64, device=img.device)
+    _check(load().fic_s_histogram(img.data_ptr(), H, W, img.stride(0), ctypes.byref(p),
+                                  int(low_entropy_only), hist.data_ptr(), _stream(stream)))
+    return hist
+
+
+def select_s(hist, n_levels: int = 4, second_frac: float = 0.5):
+    """fic_select_s (host): predefined contrast sets (tuples of k) from histograms."""
+    h = np.ascontiguousarray(np.asarray(hist, dtype=np.uint64).reshape(-1, 11)[:n_levels])
+    sk = np.zeros((4, 2), dtype=np.int8)
+    ns = np.zeros(4, dtype=np.int32)
+    _check(load().fic_select_s(h.ctypes.data, n_levels, second_frac, sk.ctypes.data, ns.ctypes.data))
+    return tuple(tuple(int(v) for v in sk[l, :ns[l]]) for l in range(n_levels))
 
 
 def stream_bound(H: int, W: int, params: EncoderParams | None = None) -> int:

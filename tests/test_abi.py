@@ -229,3 +229,12 @@ def test_library_reader_rejects_bad_streams(lib):
     assert lib.fic_unpack_stream(buf2, len(bad), None, 0, ctypes.byref(n), None, None) == fic.FIC_EINVAL
     assert lib.fic_unpack_stream(buf, len(data), None, 0, ctypes.byref(n), None, None) == fic.FIC_ECAPACITY
     assert n.value == len(codes)
+
+
+def test_select_s_matches_reference_rule():
+    import oracle
+    rng = np.random.default_rng(0)
+    for trial in range(50):
+        h = rng.integers(0, 5, size=(4, 11)) * rng.integers(0, 2, size=(4, 11))
+        for frac in (0.0, 0.3, 0.5, 1.0):
+            assert fic.select_s(h, 4, frac) == oracle.select_s(h, frac), (trial, frac)

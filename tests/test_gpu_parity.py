@@ -367,3 +367,18 @@ def test_fp32_comparator_error_is_reported(dev):
         f"{rel.max():.3e}; max E excess {np.max(E_pick - E_exact):.3e}")
     assert same.mean() > 0.9
     assert np.all(E_pick - E_exact <= 1e-3 * np.maximum(E_exact, 1.0) + 1.0)
+
+
+# ------------------------------------------------------------------ contrast histograms (Fig. 3)
+@pytest.mark.parametrize("low_only", [False, True])
+def test_s_histogram_matches_oracle(dev, low_only):
+    imgs = [synth.power_law(64, beta=2.0, seed=s, n_rect=2) for s in (0, 1)] + [synth.gradients_blobs(96, 2)]
+    hist = None
+    ref = np.zeros((4, 11), dtype=np.int64)
+    for im in imgs:
+        hist = fic.s_histogram(torch.from_numpy(im).to(dev), fic.EncoderParams(), low_only, hist)
+        ref += oracle.s_histogram(im, low_only=low_only)
+    torch.cuda.synchronize()
+    say(f"[s-hist] low_only={low_only}: {hist.cpu().numpy().tolist()}")
+    assert np.array_equal(hist.cpu().numpy(), ref)
+    assert fic.select_s(hist.cpu().numpy()) == oracle.select_s(ref)

@@ -432,3 +432,29 @@ def test_variance_pool_constant_image():
     assert n == 0 and list(pool) == [0, 1, 2, 3, 4]
     pool, n = oracle.variance_pool(img, 4, 4, -1.0, min_pool=5)
     assert n == len(pool) == 49  # (32 - 8) / 4 + 1 = 7 domains per side
+
+
+# --------------------------------------------------------------------------- contrast histograms
+def test_s_histogram_counts_kept_leaves():
+    img = synth.power_law(64, beta=2.0, seed=5, n_rect=2)
+    hist = oracle.s_histogram(img)
+    codes, stats = oracle.encode_image(img, s_sets=(oracle.PLAIN_K,) * 4, entropy=False)
+    assert [int(v) for v in hist.sum(axis=1)] == [s["accepted"] for s in stats] + [0] * (4 - len(stats))
+    low = oracle.s_histogram(img, low_only=True)
+    assert (low <= hist).all()
+    # the mean of the low-entropy histogram is the calibrated value
+    cal = oracle.calibrate_s(img)
+    for l in range(4):
+        if low[l].sum():
+            mean = Fraction(int((low[l] * np.arange(11)).sum()), int(low[l].sum()))
+            assert cal[l] == (math.floor(mean + Fraction(1, 2)),)
+
+
+def test_select_s_rule():
+    h = np.zeros((4, 11), dtype=np.int64)
+    h[0, 3] = 10; h[0, 7] = 5; h[0, 1] = 4          # second at exactly half
+    h[1, 9] = 10; h[1, 2] = 4                         # second below half
+    h[2, 4] = 6; h[2, 6] = 6                          # tie: smaller k first
+    assert oracle.select_s(h, 0.5) == ((3, 7), (9,), (4, 6), ())
+    assert oracle.select_s(h, 0.0)[1] == (2, 9)
+    assert oracle.select_s(h, 1.0)[0] == (3,)
