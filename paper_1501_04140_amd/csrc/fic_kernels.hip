@@ -273,7 +273,7 @@ struct CompactArgs {
     const uint8_t* decision;   // quadtree: 1 kept, 0 split, 2 invalid
 };
 
-constexpr int kPoolItems = 32;  // domains per thread in the pool compaction
+constexpr int kPoolItems = 8;   // domains per thread in the pool compaction
 constexpr int kQuadItems = 4;   // ranges per thread in the quadtree step
 
 __device__ inline void item_flags(const CompactArgs& a, const Ctrl* ctrl, int mode, int i, int& f0,
@@ -362,19 +362,37 @@ __device__ inline void publish_count(int2* blk, int t0, int t1) {
     }
 }
 
-// Pool compaction, pass 1: per-workgroup counts; the last workgroup scans them
-// and sets pool_count (the pool, or the floor candidates).
+// Pool compaction. A workgroup covers kBlock * kPoolItems consecutive
+// domains; thread t reads domains base + u * kBlock + t (u < kPoolItems), so
+// every load of a wave is contiguous, and keeps the kept flags as a bit mask.
+__device__ inline uint32_t pool_flag_bits(const CompactArgs& a, const Ctrl* ctrl, int mode, int base) {
+    const uint64_t cut = ctrl->cut_bound;
+    uint32_t bits = 0;
+#pragma unroll 8
+    for (int u = 0; u < kPoolItems; ++u) {
+        const int i = base + u * kBlock + (int)threadIdx.x;
+        int f = 0;
+        if (i < a.total) {
+            if (mode == 2) {
+                f = 1;
+            } else {
+                const int64_t k = a.key[i];
+                f = mode == 0 ? (k < a.M) : ((uint64_t)k <= cut);
+            }
+        }
+        bits |= (uint32_t)f << u;
+    }
+    return bits;
+}
+
+// Pass 1: per-workgroup counts; the last workgroup scans them and sets
+// pool_count (the pool, or the floor candidates).
 __device__ __forceinline__ void k_pool_count_body(CompactArgs a, Ctrl* ctrl, int2* blk, int nblk) {
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
-    const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
-    int c0 = 0;
-    for (int u = 0; u < kPoolItems; ++u) {
-        int f0, f1;
-        item_flags(a, ctrl, mode, base + u, f0, f1);
-        c0 += f0;
-    }
+    const int base = blockIdx.x * kBlock * kPoolItems;
+    const uint32_t bits = pool_flag_bits(a, ctrl, mode, base);
     int e0, e1, t0, t1;
-    block_scan2(c0, 0, e0, e1, t0, t1);
+    block_scan2(__popc(bits), 0, e0, e1, t0, t1);
     publish_count(blk, t0, t1);
     if (!last_workgroup(&ctrl->ticket, nblk)) return;
     int tot0, tot1;
@@ -382,24 +400,54 @@ __device__ __forceinline__ void k_pool_count_body(CompactArgs a, Ctrl* ctrl, int
     if (threadIdx.x == 0) ctrl->pool_count = tot0;
 }
 
-// Pool compaction, pass 2: kept domains in ascending index order.
+// Pass 2: kept domains in ascending index order. Items are ordered (u, wave,
+// lane); the per-(u, wave) counts come from wave ballots.
 __device__ __forceinline__ void k_pool_scatter_body(CompactArgs a, const Ctrl* ctrl,
                                                          const int2* blk, int32_t* pool_out) {
+    constexpr int NW = kBlock / 64;
+    __shared__ int s_off[kPoolItems * NW];
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
-    const int base = blockIdx.x * kBlock * kPoolItems + threadIdx.x * kPoolItems;
-    uint32_t bits = 0;
-    int c0 = 0;
+    const int base = blockIdx.x * kBlock * kPoolItems;
+    const uint32_t bits = pool_flag_bits(a, ctrl, mode, base);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll 8
     for (int u = 0; u < kPoolItems; ++u) {
-        int f0, f1;
-        item_flags(a, ctrl, mode, base + u, f0, f1);
-        bits |= (uint32_t)f0 << u;
-        c0 += f0;
+        const uint64_t m = __ballot((bits >> u) & 1u);
+        if (lane == 0) s_off[u * NW + wid] = __popcll(m);
     }
-    int e0, e1, t0, t1;
-    block_scan2(c0, 0, e0, e1, t0, t1);
-    int r0 = blk[blockIdx.x].x + e0;
-    for (int u = 0; u < kPoolItems; ++u)
-        if ((bits >> u) & 1u) pool_out[r0++] = base + u;
+    __syncthreads();
+    if (wid == 0) {  // exclusive scan of the kPoolItems * NW counts in (u, wave) order
+        constexpr int NE = kPoolItems * NW;
+        constexpr int PER = NE >= 64 ? NE / 64 : 1;
+        static_assert(NE < 64 || NE % 64 == 0, "scan layout");
+        int v[PER], sum = 0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            v[e] = lane * PER + e < NE ? s_off[lane * PER + e] : 0;
+            sum += v[e];
+        }
+        int incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += t;
+        }
+        int run = incl - sum;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            if (lane * PER + e < NE) s_off[lane * PER + e] = run;
+            run += v[e];
+        }
+    }
+    __syncthreads();
+    const int boff = blk[blockIdx.x].x;
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll 8
+    for (int u = 0; u < kPoolItems; ++u) {
+        const bool f = (bits >> u) & 1u;
+        const uint64_t m = __ballot(f);
+        if (f) pool_out[boff + s_off[u * NW + wid] + __popcll(m & below)] = base + u * kBlock + threadIdx.x;
+    }
 }
 
 // Exclusive scan of one int per thread over a 1024-thread workgroup (16
@@ -740,10 +788,14 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
     using GT = typename Tl::GT;
     constexpr int n = Tl::n, NW = Tl::NW, TN = Tl::TN, RPB = kBlock / 8;
     constexpr int NKA = MODE == kModeSmall ? kSmallMax : 1;
+    // small sets at B <= 4: per domain (S, k0 A', k1 A') in one 16-byte record
+    constexpr bool kFast = MODE == kModeSmall && B <= 4;
     __shared__ uint32_t sHL[TN * 2 * NW];
-    __shared__ uint32_t sS[TN];
+    __shared__ uint32_t sS[kFast ? 1 : TN];
     __shared__ int64_t sA[MODE == kModeSmall ? 1 : TN];
-    __shared__ GT sKA[NKA][TN];
+    __shared__ GT sKA[NKA][kFast ? 1 : TN];
+    __shared__ int4 sRec[kFast ? TN : 1];
+    __shared__ int32_t sE1[kFast && B == 2 ? TN : 1];
     __shared__ uint8_t sR[RPB * n];
 
     const int nact = *act_count;
@@ -816,16 +868,104 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
         __syncthreads();
         for (int i = threadIdx.x; i < cnt * 2 * NW; i += kBlock) sHL[i] = HL[(int64_t)base * 2 * NW + i];
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
-            sS[i] = Sd[base + i];
             const int64_t a = Ad[base + i];
-            if (MODE == kModeSmall) {
-#pragma unroll
-                for (int u = 0; u < kSmallMax; ++u) sKA[u][i] = (GT)(u < ks.n ? ks.k[u] : 0) * (GT)a;
+            if constexpr (kFast && B == 2) {
+                // B = 2: the 4 sums d' as two pairs of 16-bit values (from the high and
+                // low bytes), S, and k0 A' + 80 sum r S is formed per thread below
+                const uint32_t h = HL[(int64_t)(base + i) * 2], l = HL[(int64_t)(base + i) * 2 + 1];
+                int4 rec;
+                rec.x = (int)__builtin_amdgcn_perm(h, l, 0x05010400u);  // d0 | d1 << 16
+                rec.y = (int)__builtin_amdgcn_perm(h, l, 0x07030602u);  // d2 | d3 << 16
+                rec.z = (int)Sd[base + i];
+                rec.w = (int)((uint32_t)(ks.n > 0 ? ks.k[0] : 0) * (uint32_t)a);
+                sRec[i] = rec;
+                sE1[i] = (int)((uint32_t)(ks.n > 1 ? ks.k[1] : 0) * (uint32_t)a) - rec.w;
+            } else if constexpr (kFast) {
+                // k A' may wrap in 32 bits; G = k A' - 80 B' fits (|G| < 2^31) and is
+                // computed modulo 2^32
+                int4 rec;
+                rec.x = (int)Sd[base + i];
+                rec.y = (int)((uint32_t)(ks.n > 0 ? ks.k[0] : 0) * (uint32_t)a);
+                rec.z = (int)((uint32_t)(ks.n > 1 ? ks.k[1] : 0) * (uint32_t)a);
+                rec.w = 0;
+                sRec[i] = rec;
             } else {
-                sA[i] = a;
+                sS[i] = Sd[base + i];
+                if (MODE == kModeSmall) {
+#pragma unroll
+                    for (int u = 0; u < kSmallMax; ++u) sKA[u][i] = (GT)(u < ks.n ? ks.k[u] : 0) * (GT)a;
+                } else {
+                    sA[i] = a;
+                }
             }
         }
         __syncthreads();
+        if constexpr (kFast) {
+            // G_u = k_u A' + 80 sum r S - 80 n (256 P_hi + P_lo); every 24-bit operand is
+            // below 2^23 for B <= 4, so three 24-bit multiply-adds at full rate
+            const bool use0 = ks.n > 0 && ks.k[0] != 0, use1 = ks.n > 1 && ks.k[1] != 0;
+            const int c1 = 80 * (int)srum;
+            constexpr int kPh = 80 * n * 256, kPl = 80 * n;
+            if constexpr (B == 2) {
+                // P = r . d' with two v_dot2_u32_u16; G0 = k0 A' + 80 sum r S - 320 P,
+                // G1 = G0 + (k1 - k0) A'
+                typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+                const uint32_t rw = r[0];
+                const uint32_t r01 = (rw & 0xffu) | ((rw & 0xff00u) << 8);
+                const uint32_t r23 = ((rw >> 16) & 0xffu) | ((rw >> 8) & 0xff0000u);
+#pragma unroll 4
+                for (int d = 0; d < cnt; ++d) {
+                    const int4 rec = sRec[d];
+                    uint32_t pv = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, r01),
+                                                         __builtin_bit_cast(us2, (uint32_t)rec.x), 0u, false);
+                    pv = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, r23),
+                                                __builtin_bit_cast(us2, (uint32_t)rec.y), pv, false);
+                    const uint32_t g0u = (uint32_t)rec.w + (uint32_t)__mul24(c1, rec.z) -
+                                         (uint32_t)__mul24(kPl, (int)pv);
+                    const int dd = base + d;
+                    if (use0) {
+                        const int g = (int)g0u;
+                        const bool lt = g < bestG[0];
+                        bestG[0] = lt ? g : bestG[0];
+                        bestPs[0] = lt ? dd : bestPs[0];
+                    }
+                    if (use1) {
+                        const int g = (int)(g0u + (uint32_t)sE1[d]);
+                        const bool lt = g < bestG[1];
+                        bestG[1] = lt ? g : bestG[1];
+                        bestPs[1] = lt ? dd : bestPs[1];
+                    }
+                }
+                continue;
+            }
+#pragma unroll 4
+            for (int d = 0; d < cnt; ++d) {
+                const uint32_t* hl = sHL + d * 2 * NW;
+                uint32_t ph = 0, pl = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    ph = __builtin_amdgcn_udot4(r[w], hl[w], ph, false);
+                    pl = __builtin_amdgcn_udot4(r[w], hl[NW + w], pl, false);
+                }
+                const int4 rec = sRec[d];
+                const uint32_t cs = (uint32_t)__mul24(c1, rec.x);
+                const uint32_t pt = (uint32_t)__mul24(kPh, (int)ph) + (uint32_t)__mul24(kPl, (int)pl);
+                const int dd = base + d;
+                if (use0) {
+                    const int g = (int)((uint32_t)rec.y + cs - pt);
+                    const bool lt = g < bestG[0];
+                    bestG[0] = lt ? g : bestG[0];
+                    bestPs[0] = lt ? dd : bestPs[0];
+                }
+                if (use1) {
+                    const int g = (int)((uint32_t)rec.z + cs - pt);
+                    const bool lt = g < bestG[1];
+                    bestG[1] = lt ? g : bestG[1];
+                    bestPs[1] = lt ? dd : bestPs[1];
+                }
+            }
+            continue;
+        }
         for (int d = 0; d < cnt; ++d) {
             const uint32_t* hl = sHL + d * 2 * NW;
             uint32_t ph = 0, pl = 0;
@@ -908,15 +1048,9 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
 }
 
 // ---------------------------------------------------------------- per-range result
-__device__ inline bool finish_range(int yx, int B, int L, int gx, const Partial* pr, int nca,
-                                    int64_t CRq, int32_t SRq, const KSet& ks, fic_match& m,
-                                    int& dy, int& dx) {
-    int64_t F = INT64_MAX, K = INT64_MAX;
-    for (int c = 0; c < nca; ++c)
-        if (pair_less(pr[c].F, pr[c].key, F, K)) {
-            F = pr[c].F;
-            K = pr[c].key;
-        }
+// Fill the match of a range from its best (F, key) over all pool chunks.
+__device__ inline bool finish_best(int yx, int B, int L, int gx, int64_t F, int64_t K, int64_t CRq,
+                                   int32_t SRq, const KSet& ks, fic_match& m, int& dy, int& dx) {
     m.flags = 0;
     m.pad_ = 0;
     if (yx < 0 || K == INT64_MAX) {
@@ -941,11 +1075,22 @@ __device__ inline bool finish_range(int yx, int B, int L, int gx, const Partial*
     m.iso = (uint8_t)t;
     m.s_idx = (uint8_t)s;
     m.k = (uint8_t)k;
-    // o = (4Q sumR - k sumD') / (4Q n), rounded half up
     // |numerator| < 2^24 for n <= 256 (sum r <= 255 n, sum d' <= 1020 n, k <= 10)
     m.q_o = (int16_t)floordiv32(2 * (40 * SRq - k * (int)sd) + 40 * n, 80 * n);
     m.E = (float)m.e_num / (1600.0f * (float)n);
     return true;
+}
+
+__device__ inline bool finish_range(int yx, int B, int L, int gx, const Partial* pr, int nca,
+                                    int64_t CRq, int32_t SRq, const KSet& ks, fic_match& m,
+                                    int& dy, int& dx) {
+    int64_t F = INT64_MAX, K = INT64_MAX;
+    for (int c = 0; c < nca; ++c)
+        if (pair_less(pr[c].F, pr[c].key, F, K)) {
+            F = pr[c].F;
+            K = pr[c].key;
+        }
+    return finish_best(yx, B, L, gx, F, K, CRq, SRq, ks, m, dy, dx);
 }
 
 __device__ __forceinline__ void k_reduce_level_body(int B, int L, int gx,
@@ -980,15 +1125,44 @@ __device__ __forceinline__ void k_reduce_quad_body(
     int fbase = 0;  // first flag bit of this level
     for (int l = 0; l < lv; ++l) fbase += ctrl->act_count[l];
     const int nca = active_chunks(ctrl->pool_count, CG, n_chunks);
+    // best (F, key) of the thread's ranges over the pool chunks, loads of all
+    // ranges of a chunk in flight together
+    int64_t bF[kQuadItems], bK[kQuadItems], cr[kQuadItems];
+    int yxs[kQuadItems], srs[kQuadItems];
+#pragma unroll
+    for (int u = 0; u < kQuadItems; ++u) {
+        const int q = base + u;
+        const bool v = q < nact;
+        bF[u] = INT64_MAX;
+        bK[u] = INT64_MAX;
+        yxs[u] = v ? act[q] : -1;
+        cr[u] = v ? CR[q] : 0;
+        srs[u] = v ? SR[q] : 0;
+    }
+    for (int c = 0; c < nca; ++c) {
+        Partial pr[kQuadItems];
+#pragma unroll
+        for (int u = 0; u < kQuadItems; ++u) {
+            const int q = base + u;
+            if (q < nact) pr[u] = part[(int64_t)q * n_chunks + c];
+            else pr[u] = Partial{INT64_MAX, INT64_MAX};
+        }
+#pragma unroll
+        for (int u = 0; u < kQuadItems; ++u)
+            if (pair_less(pr[u].F, pr[u].key, bF[u], bK[u])) {
+                bF[u] = pr[u].F;
+                bK[u] = pr[u].key;
+            }
+    }
     int kept = 0, split = 0;
+#pragma unroll
     for (int u = 0; u < kQuadItems; ++u) {
         const int q = base + u;
         if (q >= nact) break;
         fic_match m;
         int dy, dx;
-        const int yx = act[q];
-        const bool ok = finish_range(yx, B, L, gx, part + (int64_t)q * n_chunks, nca, CR[q], SR[q],
-                                     ks, m, dy, dx);
+        const int yx = yxs[u];
+        const bool ok = finish_best(yx, B, L, gx, bF[u], bK[u], cr[u], srs[u], ks, m, dy, dx);
         uint8_t d = 2;
         if (ok) {
             fic_code c;
