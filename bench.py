@@ -87,10 +87,11 @@ def time_steps(fn, steps, warmup, torch, spread=None):
     return e0.elapsed_time(e1) / steps, wall / steps * 1e3
 
 
-def roofline_from_profile(prof, per_label_ops):
-    """Dominant kernel over the timed region: algorithmic ops per launch / mean launch time.
+def roofline_from_profile(prof, per_label_ops, steps=None):
+    """Dominant kernel over the timed region: algorithmic ops per step / its time per step.
+    With one launch per step (steps None) that is ops per launch / mean launch time.
 
-    per_label_ops maps a profile label to its ops per launch, or to a tuple
+    per_label_ops maps a profile label to its ops per step, or to a tuple
     (ops, bound, peak, unit) for kernels not bound by the 32-bit vector ALU."""
     best = None
     for label, (launches, total_ms) in prof.items():
@@ -98,11 +99,13 @@ def roofline_from_profile(prof, per_label_ops):
             best = (label, launches, total_ms)
     label, launches, total_ms = best
     spec = per_label_ops.get(label)
-    out = {"kernel": label, "launches": launches, "avg_us": total_ms / launches * 1e3}
+    per = steps or launches
+    out = {"kernel": label, "launches": launches, "launches_per_step": launches / per,
+           "avg_us": total_ms / launches * 1e3, "us_per_step": total_ms / per * 1e3}
     if spec is None:
         return out
     ops, bound, peak, unit = spec if isinstance(spec, tuple) else (spec, "alu", PEAK_ALU_TOPS, "TOP/s")
-    avg_s = total_ms / launches / 1e3
+    avg_s = total_ms / per / 1e3
     achieved = ops / avg_s / 1e12
     out.update({"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": None, "ops_per_launch": ops})
@@ -189,7 +192,7 @@ def run_quadtree(args, torch):
         n = B * B
         per_label[f"match_b{B}"] = int(st["matches"][lv]) * match_ops(n, len(s_sets[lv]))
     match_prof = {k: v for k, v in prof.items() if k.startswith("match")}
-    roof = with_traffic(roofline_from_profile(match_prof, per_label), "quadtree512")
+    roof = with_traffic(roofline_from_profile(match_prof, per_label, steps=args.steps), "quadtree512")
 
     res = {
         "metric": "matches/s (range×domain×isometry) + 512² encode ms; PSNR Δ vs exhaustive",
@@ -279,7 +282,7 @@ def run_batch(args, torch):
     per_label = {f"match_b{B}": int(matches_lv[lv]) * match_ops(B * B, len(params.s_sets[lv]))
                  for lv, B in enumerate(params.levels)}
     roof = with_traffic(roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")},
-                                              per_label), "batch64")
+                                              per_label, steps=args.steps), "batch64")
     eager_ms = sum(v[1] for v in prof.values()) / args.steps
     sides = [int(im.shape[0]) for im in imgs]
     res = {

@@ -611,21 +611,34 @@ std::vector<Lvl> quad_tables(Workspace& ws, const std::vector<Level>& lv, const 
 }
 
 // Queue the whole quadtree of one image (tables at dt, host copies t).
+// Images [start, start + count) of a batch table launch together; a batch sorted
+// by size launches each size class with grids sized for it.
+struct Group {
+    int start, count;
+};
+
 int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, const int64_t* T,
-                    bool filtered, hipStream_t st) {
+                    bool filtered, hipStream_t st, const std::vector<Group>* groups = nullptr) {
     const int nl = (int)t.size() / n_images;
-    std::vector<Lvl> h0(t.begin(), t.begin() + n_images);
-    const int gx = max_over(h0, [](const Lvl& a) { return cdiv((a.H / a.B) * (a.W / a.B), kBlock); });
-    if (dt)
-        kt_act_full<true><<<dim3(gx, 1, n_images), kBlock, 0, st>>>(t[0], dt, 1);
-    else
-        kt_act_full<false><<<dim3(gx, 1, n_images), kBlock, 0, st>>>(t[0], dt, 1);
+    const std::vector<Group> all{{0, n_images}};
+    const std::vector<Group>& gs = groups ? *groups : all;
+    for (const Group& g : gs) {
+        std::vector<Lvl> h0(t.begin() + g.start, t.begin() + g.start + g.count);
+        const int gx = max_over(h0, [](const Lvl& a) { return cdiv((a.H / a.B) * (a.W / a.B), kBlock); });
+        if (dt)
+            kt_act_full<true><<<dim3(gx, 1, g.count), kBlock, 0, st>>>(h0[0], dt + g.start, 1);
+        else
+            kt_act_full<false><<<dim3(gx, 1, g.count), kBlock, 0, st>>>(h0[0], dt, 1);
+    }
     for (int l = 0; l < nl; ++l) {
-        std::vector<Lvl> h(t.begin() + l * n_images, t.begin() + (l + 1) * n_images);
-        const Lvl* dl = dt ? dt + l * n_images : nullptr;
-        int rc = launch_level(dl, h, T, filtered, st);
-        if (rc) return rc;
-        if ((rc = launch_quad(dl, h, st))) return rc;
+        for (const Group& g : gs) {
+            std::vector<Lvl> h(t.begin() + l * n_images + g.start,
+                               t.begin() + l * n_images + g.start + g.count);
+            const Lvl* dl = dt ? dt + l * n_images + g.start : nullptr;
+            int rc = launch_level(dl, h, T, filtered, st);
+            if (rc) return rc;
+            if ((rc = launch_quad(dl, h, st))) return rc;
+        }
     }
     return FIC_OK;
 }
@@ -1016,9 +1029,11 @@ FIC_API int fic_profile_end(fic_kernel_time* out, int32_t max, int32_t* n_out) {
 namespace fic {
 namespace {
 
-__global__ void kt_copy_counts(const Lvl* __restrict__ tab, int n, int32_t* __restrict__ n_codes) {
+// n_codes of table entry i (an image in size order) goes to the caller's slot orig[i]
+__global__ void kt_copy_counts(const Lvl* __restrict__ tab, int n, const int32_t* __restrict__ orig,
+                               int32_t* __restrict__ n_codes) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) n_codes[i] = tab[i].ctrl->n_codes;
+    if (i < n) n_codes[orig[i]] = tab[i].ctrl->n_codes;
 }
 
 struct BatchImage {
@@ -1027,6 +1042,7 @@ struct BatchImage {
     int64_t code_off;
     int capacity;
     Workspace* ws;
+    int orig;  // index in the caller's arrays
 };
 
 }  // namespace
@@ -1043,6 +1059,8 @@ struct fic_batch {
     fic_level_stats* stats = nullptr;
     std::vector<int> cg;  // per level; 0 = default
     std::vector<fic::Lvl> htab;  // host copy of the [level][image] argument table
+    std::vector<fic::Group> groups;  // runs of images of equal size (images sorted by size)
+    int32_t* dorig = nullptr;        // device: caller index of each image
     void* dtab = nullptr;
     size_t dtab_bytes = 0;
     hipGraph_t graph = nullptr;
@@ -1064,9 +1082,9 @@ void batch_drop_graph(fic_batch* b) {
 int batch_launch(fic_batch* b, hipStream_t st) {
     const Lvl* dt = static_cast<const Lvl*>(b->dtab);
     const int n = (int)b->im.size();
-    int rc = launch_quadtree(dt, b->htab, n, b->im[0].ws->T, b->p.entropy_mode != 0, st);
+    int rc = launch_quadtree(dt, b->htab, n, b->im[0].ws->T, b->p.entropy_mode != 0, st, &b->groups);
     if (rc) return rc;
-    kt_copy_counts<<<cdiv(n, kBlock), kBlock, 0, st>>>(dt, n, b->n_codes);
+    kt_copy_counts<<<cdiv(n, kBlock), kBlock, 0, st>>>(dt, n, b->dorig, b->n_codes);
     LAUNCH_CHECK();
     return FIC_OK;
 }
@@ -1087,7 +1105,7 @@ int batch_build(fic_batch* b) {
         if (rc) return rc;
         std::vector<Lvl> t = quad_tables(*m.ws, lv, m.img, m.H, m.W, m.pitch, &b->p,
                                          b->codes + m.code_off, m.capacity,
-                                         b->stats ? b->stats + (size_t)i * nl : nullptr);
+                                         b->stats ? b->stats + (size_t)m.orig * nl : nullptr);
         for (int l = 0; l < nl; ++l) tab[(size_t)l * n + i] = t[l];
     }
     const size_t bytes = sizeof(Lvl) * tab.size();
@@ -1214,8 +1232,26 @@ FIC_API int fic_batch_create(int32_t n, const uint8_t* const* imgs, const int32_
         m.code_off = code_offset[i];
         m.capacity = (int)(code_offset[i + 1] - code_offset[i]);
         m.ws = nullptr;
+        m.orig = i;
         if ((rc = new_ws(b->device, b->st, &m.ws))) return bail(rc);
         b->im.push_back(m);
+    }
+    // largest images first; equal sizes form one launch group
+    std::stable_sort(b->im.begin(), b->im.end(), [](const BatchImage& x, const BatchImage& y) {
+        return (int64_t)x.H * x.W != (int64_t)y.H * y.W ? (int64_t)x.H * x.W > (int64_t)y.H * y.W
+                                                          : (x.H != y.H ? x.H > y.H : false);
+    });
+    for (int i = 0; i < n; ++i) {
+        if (i == 0 || b->im[i].H != b->im[i - 1].H || b->im[i].W != b->im[i - 1].W)
+            b->groups.push_back({i, 0});
+        b->groups.back().count++;
+    }
+    {
+        std::vector<int32_t> orig(n);
+        for (int i = 0; i < n; ++i) orig[i] = b->im[i].orig;
+        if (hipMalloc(&b->dorig, sizeof(int32_t) * n) != hipSuccess) return bail(fail(FIC_ENOMEM, "hipMalloc failed"));
+        if (hipMemcpy(b->dorig, orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(FIC_EDEVICE, "upload of the image order failed"));
     }
     if ((rc = batch_build(b))) return bail(rc);
     *out = b;
@@ -1331,6 +1367,7 @@ FIC_API int fic_batch_destroy(fic_batch* b) {
     for (fic::BatchImage& m : b->im)
         if (m.ws) fic::free_ws(m.ws);
     if (b->dtab) (void)hipFree(b->dtab);
+    if (b->dorig) (void)hipFree(b->dorig);
     if (b->st) (void)hipStreamDestroy(b->st);
     delete b;
     return FIC_OK;
