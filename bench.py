@@ -108,7 +108,7 @@ def roofline_from_profile(prof, per_label_ops, steps=None):
     avg_s = total_ms / per / 1e3
     achieved = ops / avg_s / 1e12
     out.update({"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "ops_per_launch": ops})
+                "frac": achieved / peak, "traffic": None, "ops_per_step": ops})
     return out
 
 

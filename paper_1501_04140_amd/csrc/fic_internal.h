@@ -64,7 +64,9 @@ struct Lvl {
     int64_t M;                    // filter cut (keep iff key < M)
     int64_t kv;                   // variance filter: key = kv - (N sum p^2 - (sum p)^2)
     int64_t thr;                  // keep iff 1600 n E <= thr
-    Ctrl* ctrl;
+    Ctrl* ctrl;                   // quadtree control: active counts, codes
+    Ctrl* pctrl;                  // this level's pool control: pool size, filter counters
+    int2* pblk;                   // pool compaction: per-workgroup counts
     int64_t* key;
     int32_t* pool;
     uint32_t* hl;

@@ -1116,7 +1116,7 @@ __device__ __forceinline__ void k_reduce_level_body(int B, int L, int gx,
 // code counter and sets the next level's active count (4 children per split).
 __device__ __forceinline__ void k_reduce_quad_body(
     int B, int L, int gx, int lv, int last, int64_t thr, const int32_t* __restrict__ act,
-    Ctrl* ctrl, const Partial* __restrict__ part, int n_chunks, int CG,
+    Ctrl* ctrl, const Ctrl* pctrl, const Partial* __restrict__ part, int n_chunks, int CG,
     const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, KSet ks,
     fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk, fic_level_stats* stats,
     int nblk, uint32_t* __restrict__ flags) {
@@ -1124,7 +1124,7 @@ __device__ __forceinline__ void k_reduce_quad_body(
     const int nact = ctrl->act_count[lv];
     int fbase = 0;  // first flag bit of this level
     for (int l = 0; l < lv; ++l) fbase += ctrl->act_count[l];
-    const int nca = active_chunks(ctrl->pool_count, CG, n_chunks);
+    const int nca = active_chunks(pctrl->pool_count, CG, n_chunks);
     // best (F, key) of the thread's ranges over the pool chunks, loads of all
     // ranges of a chunk in flight together
     int64_t bF[kQuadItems], bK[kQuadItems], cr[kQuadItems];
@@ -1194,7 +1194,7 @@ __device__ __forceinline__ void k_reduce_quad_body(
     int tot0, tot1;
     scan_block_counts(blk, nblk, tot0, tot1);
     if (threadIdx.x == 0) {
-        const int pool = ctrl->pool_count;
+        const int pool = pctrl->pool_count;
         ctrl->code_base = ctrl->n_codes;
         ctrl->n_codes += tot0;
         ctrl->act_count[lv + 1] = 4 * tot1;
@@ -1202,7 +1202,7 @@ __device__ __forceinline__ void k_reduce_quad_body(
             fic_level_stats st;
             st.matches = (int64_t)nact * pool * 8;
             st.pool = pool;
-            st.passed = ctrl->passed;
+            st.passed = pctrl->passed;
             st.active = nact;
             st.accepted = tot0;
             stats[lv] = st;
@@ -1893,28 +1893,28 @@ __global__ __launch_bounds__(kBlock) void kt_pool_score(Lvl a0, const Lvl* __res
                                                         const int64_t* __restrict__ T) {
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * ScoreShape<SIDE>::TPD) return;
-    k_pool_score_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, T, a.M, a.key, a.ctrl);
+    k_pool_score_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, T, a.M, a.key, a.pctrl);
 }
 
 template <int SIDE, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_var(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * ScoreShape<SIDE>::TPD) return;
-    k_pool_var_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, a.kv, a.M, a.key, a.ctrl);
+    k_pool_var_body<SIDE>(a.img, a.pitch, a.L, a.gx, a.total, a.kv, a.M, a.key, a.pctrl);
 }
 
 // Copy of the level's final pool list (for the bitstream).
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_copy_pool(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    const int n = a.ctrl->pool_count;
+    const int n = a.pctrl->pool_count;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) a.pools_out[i] = a.pool[i];
 }
 
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_floor_bound(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_floor_bound_body(a.key, a.total, a.min_pool, a.rank, a.sel_shift, a.bound_chunk, a.ctrl);
+    k_floor_bound_body(a.key, a.total, a.min_pool, a.rank, a.sel_shift, a.bound_chunk, a.pctrl);
 }
 
 __device__ inline CompactArgs pool_args(const Lvl& a) {
@@ -1932,7 +1932,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_count(Lvl a0, const Lvl* __res
     FIC_LV;
     const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
     if ((int)blockIdx.x >= nblk) return;
-    k_pool_count_body(pool_args(a), a.ctrl, a.blk, nblk);
+    k_pool_count_body(pool_args(a), a.pctrl, a.pblk, nblk);
 }
 
 template <bool TAB>
@@ -1940,20 +1940,20 @@ __global__ __launch_bounds__(kBlock) void kt_pool_scatter(Lvl a0, const Lvl* __r
     FIC_LV;
     const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
     if ((int)blockIdx.x >= nblk) return;
-    k_pool_scatter_body(pool_args(a), a.ctrl, a.blk, a.pool);
+    k_pool_scatter_body(pool_args(a), a.pctrl, a.pblk, a.pool);
 }
 
 template <bool TAB>
 __global__ __launch_bounds__(1024) void kt_floor_select(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.ctrl);
+    k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.pctrl);
 }
 
 template <int B, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_prep(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * PrepShape<B>::TPD) return;
-    k_pool_prep_body<B>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.ctrl, a.hl,
+    k_pool_prep_body<B>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl, a.hl,
                         a.sd, a.ad, a.jd);
 }
 
@@ -1961,14 +1961,14 @@ template <int B, int MODE, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_match(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_match_body<B, MODE>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.hl, a.sd, a.ad, a.jd,
-                          a.ctrl, a.ks, a.nc, a.part, a.sr, a.cr, a.cg);
+                          a.pctrl, a.ks, a.nc, a.part, a.sr, a.cr, a.cg);
 }
 
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_prep_i8(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * 4) return;
-    k_pool_prep_i8_body(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.ctrl, a.dh,
+    k_pool_prep_i8_body(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl, a.dh,
                         a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
 }
 
@@ -1982,14 +1982,14 @@ template <bool TAB>
 __global__ __launch_bounds__(kM8Waves * 64) void kt_match_mfma8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_match_mfma8_body(a.ar, a.srp, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
-                       a.jd, a.ctrl, a.ks.k1, a.nc, a.part, a.cg);
+                       a.jd, a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
 }
 
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_match_fp32(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     k_match_fp32_body(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.img, a.L, a.gx, a.jd,
-                      a.ctrl, a.ks.k1, a.nc, a.part, a.cg);
+                      a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
 }
 
 template <bool TAB>
@@ -1997,7 +1997,7 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_level(Lvl a0, const Lvl* __r
                                                           fic_match* __restrict__ out) {
     FIC_LV;
     k_reduce_level_body(a.B, a.L, a.gx, a.act, a.ctrl->act_count + a.lv, a.part, a.nc, a.cg,
-                        a.ctrl, a.cr, a.sr, a.ks, out);
+                        a.pctrl, a.cr, a.sr, a.ks, out);
 }
 
 template <bool TAB>
@@ -2005,7 +2005,7 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_fp32(Lvl a0, const Lvl* __re
                                                          fic_match* __restrict__ out) {
     FIC_LV;
     k_reduce_fp32_body(a.img, a.pitch, a.L, a.gx, a.act, a.ctrl->act_count + a.lv, a.part, a.nc,
-                       a.cg, a.ctrl, out);
+                       a.cg, a.pctrl, out);
 }
 
 template <bool TAB>
@@ -2013,8 +2013,8 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_quad(Lvl a0, const Lvl* __re
     FIC_LV;
     const int nblk = (a.max_act + kBlock * kQuadItems - 1) / (kBlock * kQuadItems);
     if ((int)blockIdx.x >= nblk) return;
-    k_reduce_quad_body(a.B, a.L, a.gx, a.lv, a.last, a.thr, a.act, a.ctrl, a.part, a.nc, a.cg, a.cr,
-                       a.sr, a.ks, a.tmpc, a.dec, a.blk, a.stats, nblk, a.flags);
+    k_reduce_quad_body(a.B, a.L, a.gx, a.lv, a.last, a.thr, a.act, a.ctrl, a.pctrl, a.part, a.nc,
+                       a.cg, a.cr, a.sr, a.ks, a.tmpc, a.dec, a.blk, a.stats, nblk, a.flags);
 }
 
 template <bool TAB>

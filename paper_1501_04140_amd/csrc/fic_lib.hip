@@ -56,16 +56,26 @@ struct Buf {
     size_t cap = 0;
 };
 
+// Domain-side buffers of one quadtree level: they depend only on the image,
+// so the pools of all levels are built concurrently.
+struct PoolBufs {
+    Buf key, pool, hl, sd, ad, jd, blk;
+    Buf dh, dl, wd, cw;  // int8 MFMA matcher (B = 8)
+};
+
+constexpr int kLevels = 4;
+
 struct Workspace {
     int device = 0;
     hipStream_t stream = nullptr;
-    Ctrl* ctrl = nullptr;
+    Ctrl* ctrl = nullptr;  // [1 + kLevels]: the quadtree's control, then each level's pool control
     int64_t* T = nullptr;  // entropy table, kMaxWindow + 1 entries
-    Buf key, pool, hl, sd, ad, jd, arow, sr, cr, part, blk, act0, act1, tmpc, dec, codes, map,
-        imgA, imgB, acc, mr;
-    Buf ar, srp, dh, dl, wd, cw;  // int8 MFMA matcher (B = 8)
-    Buf plan;                     // bitstream section offsets
-
+    PoolBufs pl[kLevels];
+    Buf arow, sr, cr, part, blk, act0, act1, tmpc, dec, codes, map, imgA, imgB, acc, mr;
+    Buf ar, srp;  // int8 MFMA matcher (B = 8)
+    Buf plan;     // bitstream section offsets
+    hipStream_t side[kLevels] = {};  // one per level's pool phase (default priority)
+    hipEvent_t ev_fork = nullptr, ev_pool[kLevels] = {};
 };
 
 std::mutex g_mu;
@@ -93,7 +103,7 @@ int new_ws(int dev, hipStream_t s, Workspace** out) {
     Workspace* ws = new Workspace();
     ws->device = dev;
     ws->stream = s;
-    if (hipMalloc(&ws->ctrl, sizeof(Ctrl)) != hipSuccess) {
+    if (hipMalloc(&ws->ctrl, sizeof(Ctrl) * (1 + kLevels)) != hipSuccess) {
         delete ws;
         return fail(FIC_ENOMEM, "hipMalloc of the control block failed");
     }
@@ -104,11 +114,22 @@ int new_ws(int dev, hipStream_t s, Workspace** out) {
     }
     const std::vector<int64_t>& t = entropy_table();
     HIP_TRY(hipMemcpy(ws->T, t.data(), sizeof(int64_t) * t.size(), hipMemcpyHostToDevice));
-    Ctrl init;  // zero counters, empty histogram, no floor bound yet
-    std::memset(&init, 0, sizeof init);
-    init.cut_bound = ~0ull;
-    HIP_TRY(hipMemcpy(ws->ctrl, &init, sizeof(Ctrl), hipMemcpyHostToDevice));
+    std::vector<Ctrl> init(1 + kLevels);  // zero counters, empty histograms, no floor bound yet
+    std::memset(init.data(), 0, sizeof(Ctrl) * init.size());
+    for (Ctrl& c : init) c.cut_bound = ~0ull;
+    HIP_TRY(hipMemcpy(ws->ctrl, init.data(), sizeof(Ctrl) * init.size(), hipMemcpyHostToDevice));
     *out = ws;
+    return FIC_OK;
+}
+
+// Level streams and events of a workspace that forks the pool phases (made on first use).
+int ensure_fork(Workspace& ws) {
+    if (ws.ev_fork) return FIC_OK;
+    for (int l = 0; l < kLevels; ++l) {
+        HIP_TRY(hipStreamCreateWithFlags(&ws.side[l], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ws.ev_pool[l], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming));
     return FIC_OK;
 }
 
@@ -130,12 +151,21 @@ int get_ws(hipStream_t s, Workspace** out) {
 }
 
 void free_ws(Workspace* ws) {
-    Buf* bufs[] = {&ws->key, &ws->pool, &ws->hl, &ws->sd, &ws->ad, &ws->jd, &ws->arow, &ws->sr,
-                   &ws->cr, &ws->part, &ws->blk, &ws->act0, &ws->act1, &ws->tmpc, &ws->dec,
-                   &ws->codes, &ws->map, &ws->imgA, &ws->imgB, &ws->acc, &ws->mr, &ws->ar,
-                   &ws->srp, &ws->dh, &ws->dl, &ws->wd, &ws->cw, &ws->plan};
+    Buf* bufs[] = {&ws->arow, &ws->sr, &ws->cr, &ws->part, &ws->blk, &ws->act0, &ws->act1,
+                   &ws->tmpc, &ws->dec, &ws->codes, &ws->map, &ws->imgA, &ws->imgB, &ws->acc,
+                   &ws->mr, &ws->ar, &ws->srp, &ws->plan};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
+    for (PoolBufs& pb : ws->pl) {
+        Buf* pbs[] = {&pb.key, &pb.pool, &pb.hl, &pb.sd, &pb.ad, &pb.jd, &pb.blk, &pb.dh, &pb.dl, &pb.wd, &pb.cw};
+        for (Buf* b : pbs)
+            if (b->p) (void)hipFree(b->p);
+    }
+    for (int l = 0; l < kLevels; ++l) {
+        if (ws->side[l]) (void)hipStreamDestroy(ws->side[l]);
+        if (ws->ev_pool[l]) (void)hipEventDestroy(ws->ev_pool[l]);
+    }
+    if (ws->ev_fork) (void)hipEventDestroy(ws->ev_fork);
     (void)hipFree(ws->ctrl);
     (void)hipFree(ws->T);
     delete ws;
@@ -145,7 +175,10 @@ int ensure(Workspace& ws, Buf& b, size_t bytes) {
     if (bytes == 0) bytes = 1;
     if (b.cap >= bytes) return FIC_OK;
     if (b.p) {
+        // the buffer may still be in use on the caller's stream or a level's stream
         HIP_TRY(hipStreamSynchronize(ws.stream));
+        for (hipStream_t sd : ws.side)
+            if (sd) HIP_TRY(hipStreamSynchronize(sd));
         HIP_TRY(hipFree(b.p));
         b.p = nullptr;
         b.cap = 0;
@@ -293,35 +326,47 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
 }
 
 struct Sizes {
-    size_t key = 0, pool = 0, hl = 0, dom = 0, rng = 0, part = 0, blk = 0, act = 0;
-    size_t ar = 0, dcol = 0;  // int8 MFMA matcher
+    size_t rng = 0, part = 0, blk = 0, act = 0, ar = 0;                // range side, all levels
+    size_t key[kLevels] = {}, hl[kLevels] = {}, dom[kLevels] = {};      // domain side, per level
+    size_t pblk[kLevels] = {}, dcol[kLevels] = {};
 };
 
 void grow(Sizes& s, const Level& v) {
     const int n = v.B * v.B;
-    s.key = std::max(s.key, (size_t)v.total * 8);
-    s.pool = std::max(s.pool, (size_t)v.total * 4);
-    s.hl = std::max(s.hl, (size_t)v.total * (n / 2) * 4);
-    s.dom = std::max(s.dom, (size_t)v.total);
+    const int l = v.lv;
+    s.key[l] = std::max(s.key[l], (size_t)v.total * 8);
+    s.hl[l] = std::max(s.hl[l], (size_t)v.total * (n / 2) * 4);
+    s.dom[l] = std::max(s.dom[l], (size_t)v.total);
+    s.pblk[l] = std::max(s.pblk[l], (size_t)cdiv(v.total, kBlock * kPoolItems) * sizeof(int2));
     s.rng = std::max(s.rng, (size_t)v.max_act);
     s.part = std::max(s.part, (size_t)v.max_act * v.nc * sizeof(Partial));
-    size_t nblk = (size_t)std::max(cdiv(v.total, kBlock * kPoolItems), cdiv(v.max_act, kBlock * kQuadItems));
-    s.blk = std::max(s.blk, nblk * sizeof(int2));
+    s.blk = std::max(s.blk, (size_t)cdiv(v.max_act, kBlock * kQuadItems) * sizeof(int2));
     s.act = std::max(s.act, (size_t)v.max_act);
     if (v.var == kVarMfma) {
         s.ar = std::max(s.ar, (size_t)v.max_act * 8 * 64);
-        s.dcol = std::max(s.dcol, (size_t)v.total);
+        s.dcol[l] = std::max(s.dcol[l], (size_t)v.total);
     }
 }
 
 int ensure_sizes(Workspace& ws, const Sizes& s) {
     int rc;
-    if ((rc = ensure(ws, ws.key, s.key))) return rc;
-    if ((rc = ensure(ws, ws.pool, s.pool))) return rc;
-    if ((rc = ensure(ws, ws.hl, s.hl))) return rc;
-    if ((rc = ensure(ws, ws.sd, s.dom * 4))) return rc;
-    if ((rc = ensure(ws, ws.ad, s.dom * 8))) return rc;
-    if ((rc = ensure(ws, ws.jd, s.dom * 4))) return rc;
+    for (int l = 0; l < kLevels; ++l) {
+        if (!s.dom[l]) continue;
+        PoolBufs& pb = ws.pl[l];
+        if ((rc = ensure(ws, pb.key, s.key[l]))) return rc;
+        if ((rc = ensure(ws, pb.pool, s.dom[l] * 4))) return rc;
+        if ((rc = ensure(ws, pb.hl, s.hl[l]))) return rc;
+        if ((rc = ensure(ws, pb.sd, s.dom[l] * 4))) return rc;
+        if ((rc = ensure(ws, pb.ad, s.dom[l] * 8))) return rc;
+        if ((rc = ensure(ws, pb.jd, s.dom[l] * 4))) return rc;
+        if ((rc = ensure(ws, pb.blk, s.pblk[l]))) return rc;
+        if (s.dcol[l]) {
+            if ((rc = ensure(ws, pb.dh, s.dcol[l] * 64))) return rc;
+            if ((rc = ensure(ws, pb.dl, s.dcol[l] * 64))) return rc;
+            if ((rc = ensure(ws, pb.wd, s.dcol[l] * 4))) return rc;
+            if ((rc = ensure(ws, pb.cw, s.dcol[l] * 4))) return rc;
+        }
+    }
     if ((rc = ensure(ws, ws.sr, s.rng * 4))) return rc;
     if ((rc = ensure(ws, ws.cr, s.rng * 8))) return rc;
     if ((rc = ensure(ws, ws.part, s.part))) return rc;
@@ -333,10 +378,6 @@ int ensure_sizes(Workspace& ws, const Sizes& s) {
     if (s.ar) {
         if ((rc = ensure(ws, ws.ar, s.ar))) return rc;
         if ((rc = ensure(ws, ws.srp, s.rng * 4))) return rc;
-        if ((rc = ensure(ws, ws.dh, s.dcol * 64))) return rc;
-        if ((rc = ensure(ws, ws.dl, s.dcol * 64))) return rc;
-        if ((rc = ensure(ws, ws.wd, s.dcol * 4))) return rc;
-        if ((rc = ensure(ws, ws.cw, s.dcol * 4))) return rc;
     }
     return FIC_OK;
 }
@@ -384,13 +425,16 @@ Lvl make_lvl(Workspace& ws, const Level& v, const uint8_t* img, int H, int W, in
     }
     a.thr = thr;
     a.capacity = capacity;
+    PoolBufs& pb = ws.pl[v.lv];
     a.ctrl = ws.ctrl;
-    a.key = P<int64_t>(ws.key);
-    a.pool = P<int32_t>(ws.pool);
-    a.hl = P<uint32_t>(ws.hl);
-    a.sd = P<uint32_t>(ws.sd);
-    a.ad = P<int64_t>(ws.ad);
-    a.jd = P<int32_t>(ws.jd);
+    a.pctrl = ws.ctrl + 1 + v.lv;
+    a.key = P<int64_t>(pb.key);
+    a.pool = P<int32_t>(pb.pool);
+    a.hl = P<uint32_t>(pb.hl);
+    a.sd = P<uint32_t>(pb.sd);
+    a.ad = P<int64_t>(pb.ad);
+    a.jd = P<int32_t>(pb.jd);
+    a.pblk = P<int2>(pb.blk);
     a.part = P<Partial>(ws.part);
     a.sr = P<int32_t>(ws.sr);
     a.cr = P<int64_t>(ws.cr);
@@ -403,10 +447,10 @@ Lvl make_lvl(Workspace& ws, const Level& v, const uint8_t* img, int H, int W, in
     a.stats = stats;
     a.ar = P<int8_t>(ws.ar);
     a.srp = P<int32_t>(ws.srp);
-    a.dh = P<int8_t>(ws.dh);
-    a.dl = P<int8_t>(ws.dl);
-    a.gd = P<float>(ws.wd);
-    a.af = P<float>(ws.cw);
+    a.dh = P<int8_t>(pb.dh);
+    a.dl = P<int8_t>(pb.dl);
+    a.gd = P<float>(pb.wd);
+    a.af = P<float>(pb.cw);
     a.ks = v.ks;
     return a;
 }
@@ -436,18 +480,28 @@ void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hi
     kt_pool_score<SIDE, TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt, T);
 }
 
+// Domain-side moments of the level's pool (they depend only on the image).
 template <int B, bool TAB>
-void launch_prep_match(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, hipStream_t st) {
+void launch_pool_prep(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, hipStream_t st) {
+    const int n = (int)h.size();
+    ProfScope ps("pool_prep", st);
+    if (B == 8 && h[0].var == kVarMfma) {
+        const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * 4, kBlock); });
+        kt_pool_prep_i8<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
+        return;
+    }
+    const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * PrepShape<B>::TPD, kBlock); });
+    kt_pool_prep<B, TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
+}
+
+// The matcher over the level's active ranges (after its pool is ready).
+template <int B, bool TAB>
+void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
     const int n = (int)h.size();
     const Lvl& a0 = h[0];
     const int max_act = max_over(h, [](const Lvl& a) { return a.max_act; });
     const int max_nc = max_over(h, [](const Lvl& a) { return a.nc; });
     if (B == 8 && a0.var == kVarMfma) {
-        {
-            ProfScope ps("pool_prep", st);
-            const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * 4, kBlock); });
-            kt_pool_prep_i8<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
-        }
         {
             ProfScope ps("range_prep", st);
             kt_range_prep_i8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kBlock), 1, n), kBlock, 0, st>>>(h[0], dt);
@@ -455,11 +509,6 @@ void launch_prep_match(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, 
         ProfScope ps("match_b8_mfma", st);
         kt_match_mfma8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n), kM8Waves * 64, 0, st>>>(h[0], dt);
         return;
-    }
-    {
-        ProfScope ps("pool_prep", st);
-        const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * PrepShape<B>::TPD, kBlock); });
-        kt_pool_prep<B, TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
     }
     const dim3 grid(cdiv(max_act, kBlock / 8), max_nc, n);
     if (B == 8 && a0.var == kVarFp32) {
@@ -474,11 +523,12 @@ void launch_prep_match(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, 
     else kt_match<B, kModeList, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
 }
 
-// Pool of one level (entropy filter of Section 3, or the whole grid), pool
-// moments and the matcher, for h.size() images whose arguments are at dt.
+// Pool of one level: the entropy (or variance) filter of Section 3, or the
+// whole grid, and the pool's moments, for h.size() images whose arguments are
+// at dt (by value when dt is NULL).
 template <bool TAB>
-int launch_level_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
-                   hipStream_t st) {
+int launch_pool_phase_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
+                        hipStream_t st) {
     const int n = (int)h.size();
     const int B = h[0].B;
     if (filtered) {
@@ -512,20 +562,43 @@ int launch_level_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, b
         }
     }
     switch (B) {
-        case 2: launch_prep_match<2, TAB>(dt, h, filtered, st); break;
-        case 4: launch_prep_match<4, TAB>(dt, h, filtered, st); break;
-        case 8: launch_prep_match<8, TAB>(dt, h, filtered, st); break;
-        default: launch_prep_match<16, TAB>(dt, h, filtered, st); break;
+        case 2: launch_pool_prep<2, TAB>(dt, h, filtered, st); break;
+        case 4: launch_pool_prep<4, TAB>(dt, h, filtered, st); break;
+        case 8: launch_pool_prep<8, TAB>(dt, h, filtered, st); break;
+        default: launch_pool_prep<16, TAB>(dt, h, filtered, st); break;
     }
     LAUNCH_CHECK();
     return FIC_OK;
 }
 
-// Pool, moments and matcher of one level for h.size() images (arguments at
-// dt for a batch, by value when dt is NULL).
+template <bool TAB>
+int launch_match_phase_t(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
+    switch (h[0].B) {
+        case 2: launch_match<2, TAB>(dt, h, st); break;
+        case 4: launch_match<4, TAB>(dt, h, st); break;
+        case 8: launch_match<8, TAB>(dt, h, st); break;
+        default: launch_match<16, TAB>(dt, h, st); break;
+    }
+    LAUNCH_CHECK();
+    return FIC_OK;
+}
+
+int launch_pool_phase(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
+                      hipStream_t st) {
+    return dt ? launch_pool_phase_t<true>(dt, h, T, filtered, st)
+              : launch_pool_phase_t<false>(dt, h, T, filtered, st);
+}
+
+int launch_match_phase(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
+    return dt ? launch_match_phase_t<true>(dt, h, st) : launch_match_phase_t<false>(dt, h, st);
+}
+
+// Pool, moments and matcher of one level, in order on one stream.
 int launch_level(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
                  hipStream_t st) {
-    return dt ? launch_level_t<true>(dt, h, T, filtered, st) : launch_level_t<false>(dt, h, T, filtered, st);
+    int rc = launch_pool_phase(dt, h, T, filtered, st);
+    if (rc) return rc;
+    return launch_match_phase(dt, h, st);
 }
 
 // Keep/split decisions and compaction for a quadtree level.
@@ -617,8 +690,13 @@ struct Group {
     int start, count;
 };
 
+// The pools of all levels depend only on the images, so with `fork` (its level
+// streams and events) each level's pool phase runs on its own stream, started
+// after the work already queued on st; st waits for level l's pool right
+// before level l's matcher.
 int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, const int64_t* T,
-                    bool filtered, hipStream_t st, const std::vector<Group>* groups = nullptr) {
+                    bool filtered, hipStream_t st, const std::vector<Group>* groups = nullptr,
+                    Workspace* fork = nullptr) {
     const int nl = (int)t.size() / n_images;
     const std::vector<Group> all{{0, n_images}};
     const std::vector<Group>& gs = groups ? *groups : all;
@@ -630,12 +708,27 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
         else
             kt_act_full<false><<<dim3(gx, 1, g.count), kBlock, 0, st>>>(h0[0], dt, 1);
     }
+    const bool conc = fork && nl > 1 && nl <= kLevels;
+    if (conc) HIP_TRY(hipEventRecord(fork->ev_fork, st));
     for (int l = 0; l < nl; ++l) {
+        hipStream_t ps = conc ? fork->side[l] : st;
+        if (conc) HIP_TRY(hipStreamWaitEvent(ps, fork->ev_fork, 0));
         for (const Group& g : gs) {
             std::vector<Lvl> h(t.begin() + l * n_images + g.start,
                                t.begin() + l * n_images + g.start + g.count);
             const Lvl* dl = dt ? dt + l * n_images + g.start : nullptr;
-            int rc = launch_level(dl, h, T, filtered, st);
+            int rc = launch_pool_phase(dl, h, T, filtered, ps);
+            if (rc) return rc;
+        }
+        if (conc) HIP_TRY(hipEventRecord(fork->ev_pool[l], ps));
+    }
+    for (int l = 0; l < nl; ++l) {
+        if (conc) HIP_TRY(hipStreamWaitEvent(st, fork->ev_pool[l], 0));
+        for (const Group& g : gs) {
+            std::vector<Lvl> h(t.begin() + l * n_images + g.start,
+                               t.begin() + l * n_images + g.start + g.count);
+            const Lvl* dl = dt ? dt + l * n_images + g.start : nullptr;
+            int rc = launch_match_phase(dl, h, st);
             if (rc) return rc;
             if ((rc = launch_quad(dl, h, st))) return rc;
         }
@@ -669,7 +762,8 @@ int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch
             k_fill_i32<<<cdiv(nw, kBlock), kBlock, 0, ws.stream>>>(reinterpret_cast<int32_t*>(flags), (int)nw, 0);
     }
     std::vector<Lvl> t = quad_tables(ws, lv, img, H, W, pitch, p, codes, capacity, stats, flags, pools);
-    return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode != 0, ws.stream);
+    if ((rc = ensure_fork(ws))) return rc;
+    return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode != 0, ws.stream, nullptr, &ws);
 }
 
 }  // namespace
@@ -733,14 +827,14 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     }
     LAUNCH_CHECK();
     if (pool_count)
-        HIP_TRY(hipMemcpyAsync(pool_count, &ws->ctrl->pool_count, sizeof(int32_t),
+        HIP_TRY(hipMemcpyAsync(pool_count, &(ws->ctrl + 1)->pool_count, sizeof(int32_t),
                                hipMemcpyDeviceToDevice, st));
     if (pool_out) {
         if (entropy_mode != 0)
-            HIP_TRY(hipMemcpyAsync(pool_out, ws->pool.p, sizeof(int32_t) * v.total,
+            HIP_TRY(hipMemcpyAsync(pool_out, ws->pl[0].pool.p, sizeof(int32_t) * v.total,
                                    hipMemcpyDeviceToDevice, st));
         else
-            HIP_TRY(hipMemcpyAsync(pool_out, ws->jd.p, sizeof(int32_t) * v.total,
+            HIP_TRY(hipMemcpyAsync(pool_out, ws->pl[0].jd.p, sizeof(int32_t) * v.total,
                                    hipMemcpyDeviceToDevice, st));
     }
     return FIC_OK;
@@ -1082,7 +1176,9 @@ void batch_drop_graph(fic_batch* b) {
 int batch_launch(fic_batch* b, hipStream_t st) {
     const Lvl* dt = static_cast<const Lvl*>(b->dtab);
     const int n = (int)b->im.size();
-    int rc = launch_quadtree(dt, b->htab, n, b->im[0].ws->T, b->p.entropy_mode != 0, st, &b->groups);
+    // Single stream: the batch graph is captured without the per-level pool streams.
+    int rc = launch_quadtree(dt, b->htab, n, b->im[0].ws->T, b->p.entropy_mode != 0, st, &b->groups,
+                             nullptr);
     if (rc) return rc;
     kt_copy_counts<<<cdiv(n, kBlock), kBlock, 0, st>>>(dt, n, b->dorig, b->n_codes);
     LAUNCH_CHECK();
