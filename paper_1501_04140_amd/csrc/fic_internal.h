@@ -23,7 +23,7 @@ struct Ctrl {
     int32_t pass_count;    // running count of the entropy score kernel (reset by it)
     int32_t passed;        // domains above the entropy threshold at this level
     int32_t n_codes;       // codes emitted so far (may exceed capacity)
-    int32_t code_base;     // first code slot of the current level
+    int32_t lvl_base[5];   // codes emitted before each quadtree level
     int32_t err;
     int32_t sel_rank;      // rank still to find inside the current key prefix
     uint32_t ticket;       // last-workgroup ticket (each kernel resets it)

@@ -80,7 +80,7 @@ __device__ __forceinline__ void k_act_full_body(int32_t* act, int gy, int gx, in
         ctrl->act_count[lv] = gy * gx;
         if (reset) {
             ctrl->n_codes = 0;
-            ctrl->code_base = 0;
+            ctrl->lvl_base[lv] = 0;
         }
     }
     if (q >= gy * gx) return;
@@ -274,7 +274,9 @@ struct CompactArgs {
 };
 
 constexpr int kPoolItems = 8;   // domains per thread in the pool compaction
-constexpr int kQuadItems = 4;   // ranges per thread in the quadtree step
+constexpr int kQuadItems = 4;   // ranges per thread in the quadtree compaction
+constexpr int kRqLanes = 4;     // lanes per range in the quadtree decision step
+constexpr int kRqRanges = kBlock / kRqLanes;  // ranges per workgroup of that step
 
 __device__ inline void item_flags(const CompactArgs& a, const Ctrl* ctrl, int mode, int i, int& f0,
                                   int& f1) {
@@ -589,13 +591,17 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
     }
 }
 
-// Quadtree compaction: kept leaves to the code list (after code_base), the
-// four children of each split range to the next active list, in order.
-__device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, const Ctrl* ctrl,
+// Quadtree compaction: kept leaves to the code list (after the codes of the
+// earlier levels), the four children of each split range to the next active
+// list, in order. A workgroup's offsets are the sums of the decision step's
+// per-workgroup counts before its first range; the last workgroup, which also
+// sees the totals, sets the next level's code base and active count.
+__device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, Ctrl* ctrl, const Ctrl* pctrl,
+                                                         int lv, int nblk,
                                                          const int2* blk, const fic_code* tmp_codes,
                                                          fic_code* codes, int capacity,
                                                          const int32_t* act, int32_t* act_next,
-                                                         int half) {
+                                                         int half, fic_level_stats* stats) {
     const int base = blockIdx.x * kBlock * kQuadItems + threadIdx.x * kQuadItems;
     int f0[kQuadItems], f1[kQuadItems];
     int c0 = 0, c1 = 0;
@@ -605,11 +611,21 @@ __device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, const Ctrl* c
         c0 += f0[u];
         c1 += f1[u];
     }
+    // kept and split ranges before this workgroup
+    constexpr int kPer = kBlock * kQuadItems / kRqRanges;  // decision workgroups per workgroup
+    const int nprev = blockIdx.x * kPer;
+    int p0 = 0, p1 = 0;
+    for (int i = threadIdx.x; i < nprev; i += kBlock) {
+        const int2 v = blk[i];
+        p0 += v.x;
+        p1 += v.y;
+    }
     int e0, e1, t0, t1;
+    block_scan2(p0, p1, e0, e1, t0, t1);
+    const int off0 = t0, off1 = t1;
     block_scan2(c0, c1, e0, e1, t0, t1);
-    const int2 off = blk[blockIdx.x];
-    int r0 = off.x + e0, r1 = off.y + e1;
-    const int cb = ctrl->code_base;
+    int r0 = off0 + e0, r1 = off1 + e1;
+    const int cb = ctrl->lvl_base[lv];
 #pragma unroll
     for (int u = 0; u < kQuadItems; ++u) {
         const int i = base + u;
@@ -627,6 +643,23 @@ __device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, const Ctrl* c
             dst[2] = ((y + half) << 16) | x;
             dst[3] = ((y + half) << 16) | (x + half);
             ++r1;
+        }
+    }
+    if ((int)blockIdx.x == nblk - 1 && threadIdx.x == 0) {
+        const int tot0 = off0 + t0, tot1 = off1 + t1;
+        const int nact = *a.act_count;
+        ctrl->lvl_base[lv + 1] = cb + tot0;
+        ctrl->n_codes = cb + tot0;
+        ctrl->act_count[lv + 1] = 4 * tot1;
+        if (stats) {
+            const int pool = pctrl->pool_count;
+            fic_level_stats st;
+            st.matches = (int64_t)nact * pool * 8;
+            st.pool = pool;
+            st.passed = pctrl->passed;
+            st.active = nact;
+            st.accepted = tot0;
+            stats[lv] = st;
         }
     }
 }
@@ -763,6 +796,41 @@ __device__ inline int active_chunks(int P, int TN, int n_chunks) {
     return max(1, min(n_chunks, (P + TN - 1) / TN));
 }
 
+// Domain loop of the B = 2 small-set matcher. Records {d'0 | d'1 << 16,
+// d'2 | d'3 << 16, kf A' - 80 p, p} with p the pool position and kf the first
+// contrast value in use; TWO adds the second value through (k1 - k0) A'.
+// Seeding the first dot product with p (in a register already) and removing
+// 80 p through the record keeps G exact: G = 80 (sum_i d'_i w_i + p) + kf A' - 80 p.
+// Running minimum of G and the pool position of its first occurrence.
+template <bool TWO>
+__device__ __forceinline__ void match_b2_loop(const int4* sRec, const int32_t* sE1, int cnt,
+                                              uint32_t w01, uint32_t w23, int& g0, int& p0,
+                                              int& g1, int& p1) {
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    const s2 a01 = __builtin_bit_cast(s2, w01), a23 = __builtin_bit_cast(s2, w23);
+    int bg0 = g0, bp0 = p0, bg1 = g1, bp1 = p1;
+#pragma unroll 4
+    for (int d = 0; d < cnt; ++d) {
+        const int4 rec = sRec[d];
+        int dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.x), a01, rec.w, false);
+        dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.y), a23, dsum, false);
+        const int g = __mul24(dsum, 80) + rec.z;
+        const bool lt = g < bg0;
+        bp0 = lt ? rec.w : bp0;
+        bg0 = lt ? g : bg0;
+        if constexpr (TWO) {
+            const int h = g + sE1[d];
+            const bool lt1 = h < bg1;
+            bp1 = lt1 ? rec.w : bp1;
+            bg1 = lt1 ? h : bg1;
+        }
+    }
+    g0 = bg0;
+    p0 = bp0;
+    g1 = bg1;
+    p1 = bp1;
+}
+
 // grid: x = row blocks of 256 rows (32 ranges x 8 isometries), y = pool chunks.
 // The workgroup stages its 32 range blocks in LDS; thread (range q, iso t)
 // keeps row[m] = R[iso_src(inverse(t), m)] in registers as packed bytes, so
@@ -871,15 +939,19 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
             const int64_t a = Ad[base + i];
             if constexpr (kFast && B == 2) {
                 // B = 2: the 4 sums d' as two pairs of 16-bit values (from the high and
-                // low bytes), S, and k0 A' + 80 sum r S is formed per thread below
+                // low bytes), k0 A', the pool position, and (k1 - k0) A' aside
                 const uint32_t h = HL[(int64_t)(base + i) * 2], l = HL[(int64_t)(base + i) * 2 + 1];
+                // the first value in use is kf; the loop seeds its dot product with
+                // the pool position, so kf A' - 80 position is stored
+                const int k0 = ks.n > 0 ? ks.k[0] : 0, k1 = ks.n > 1 ? ks.k[1] : 0;
+                const int kf = k0 != 0 ? k0 : k1;
                 int4 rec;
                 rec.x = (int)__builtin_amdgcn_perm(h, l, 0x05010400u);  // d0 | d1 << 16
                 rec.y = (int)__builtin_amdgcn_perm(h, l, 0x07030602u);  // d2 | d3 << 16
-                rec.z = (int)Sd[base + i];
-                rec.w = (int)((uint32_t)(ks.n > 0 ? ks.k[0] : 0) * (uint32_t)a);
+                rec.z = (int)((int64_t)kf * a - 80 * (int64_t)(base + i));
+                rec.w = base + i;
                 sRec[i] = rec;
-                sE1[i] = (int)((uint32_t)(ks.n > 1 ? ks.k[1] : 0) * (uint32_t)a) - rec.w;
+                sE1[i] = (int)((int64_t)(k1 - k0) * a);
             } else if constexpr (kFast) {
                 // k A' may wrap in 32 bits; G = k A' - 80 B' fits (|G| < 2^31) and is
                 // computed modulo 2^32
@@ -907,35 +979,17 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
             const int c1 = 80 * (int)srum;
             constexpr int kPh = 80 * n * 256, kPl = 80 * n;
             if constexpr (B == 2) {
-                // P = r . d' with two v_dot2_u32_u16; G0 = k0 A' + 80 sum r S - 320 P,
-                // G1 = G0 + (k1 - k0) A'
-                typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+                // G_u = k_u A' + 80 sum_i d'_i (sum r - 4 r_i): the weights sum r - 4 r_i
+                // lie in [-765, 765], so two v_dot2_i32_i16 give the sum exactly, and
+                // |sum + p| < 2^22 leaves one 24-bit multiply-add for G
                 const uint32_t rw = r[0];
-                const uint32_t r01 = (rw & 0xffu) | ((rw & 0xff00u) << 8);
-                const uint32_t r23 = ((rw >> 16) & 0xffu) | ((rw >> 8) & 0xff0000u);
-#pragma unroll 4
-                for (int d = 0; d < cnt; ++d) {
-                    const int4 rec = sRec[d];
-                    uint32_t pv = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, r01),
-                                                         __builtin_bit_cast(us2, (uint32_t)rec.x), 0u, false);
-                    pv = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, r23),
-                                                __builtin_bit_cast(us2, (uint32_t)rec.y), pv, false);
-                    const uint32_t g0u = (uint32_t)rec.w + (uint32_t)__mul24(c1, rec.z) -
-                                         (uint32_t)__mul24(kPl, (int)pv);
-                    const int dd = base + d;
-                    if (use0) {
-                        const int g = (int)g0u;
-                        const bool lt = g < bestG[0];
-                        bestG[0] = lt ? g : bestG[0];
-                        bestPs[0] = lt ? dd : bestPs[0];
-                    }
-                    if (use1) {
-                        const int g = (int)(g0u + (uint32_t)sE1[d]);
-                        const bool lt = g < bestG[1];
-                        bestG[1] = lt ? g : bestG[1];
-                        bestPs[1] = lt ? dd : bestPs[1];
-                    }
-                }
+                const int r0 = rw & 0xff, r1 = (rw >> 8) & 0xff, r2 = (rw >> 16) & 0xff, r3 = rw >> 24;
+                const int sr4 = r0 + r1 + r2 + r3;
+                const uint32_t w01 = (uint32_t)(uint16_t)(sr4 - 4 * r0) | ((uint32_t)(uint16_t)(sr4 - 4 * r1) << 16);
+                const uint32_t w23 = (uint32_t)(uint16_t)(sr4 - 4 * r2) | ((uint32_t)(uint16_t)(sr4 - 4 * r3) << 16);
+                if (use0 && use1) match_b2_loop<true>(sRec, sE1, cnt, w01, w23, bestG[0], bestPs[0], bestG[1], bestPs[1]);
+                else if (use0) match_b2_loop<false>(sRec, sE1, cnt, w01, w23, bestG[0], bestPs[0], bestG[1], bestPs[1]);
+                else if (use1) match_b2_loop<false>(sRec, sE1, cnt, w01, w23, bestG[1], bestPs[1], bestG[0], bestPs[0]);
                 continue;
             }
 #pragma unroll 4
@@ -1111,103 +1165,80 @@ __device__ __forceinline__ void k_reduce_level_body(int B, int L, int gx,
 }
 
 // Quadtree step: the leaf record and the keep/split decision of each active
-// range, kQuadItems consecutive ranges per thread. Per-workgroup counts of
-// kept and split ranges go to blk; the last workgroup scans them, advances the
-// code counter and sets the next level's active count (4 children per split).
+// range. kRqLanes lanes share a range: they take its pool chunks in turn (all
+// loads of a workgroup in flight together), combine their bests, and each
+// stores a quarter of the range's 32-byte code. Per-workgroup counts of kept
+// and split ranges go to blk (the compaction that follows sums them).
 __device__ __forceinline__ void k_reduce_quad_body(
     int B, int L, int gx, int lv, int last, int64_t thr, const int32_t* __restrict__ act,
-    Ctrl* ctrl, const Ctrl* pctrl, const Partial* __restrict__ part, int n_chunks, int CG,
+    const Ctrl* ctrl, const Ctrl* pctrl, const Partial* __restrict__ part, int n_chunks, int CG,
     const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, KSet ks,
-    fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk, fic_level_stats* stats,
-    int nblk, uint32_t* __restrict__ flags) {
-    const int base = blockIdx.x * kBlock * kQuadItems + threadIdx.x * kQuadItems;
+    fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk,
+    uint32_t* __restrict__ flags) {
+    static_assert(sizeof(fic_code) == 32 && kRqLanes == 4, "one 8-byte word of a code per lane");
+    static_assert(offsetof(fic_code, dom) == 8 && offsetof(fic_code, y) == 12 &&
+                      offsetof(fic_code, x) == 14 && offsetof(fic_code, dy) == 16 &&
+                      offsetof(fic_code, q_o) == 20 && offsetof(fic_code, log2B) == 22 &&
+                      offsetof(fic_code, k) == 24 && offsetof(fic_code, level) == 26,
+                  "fic_code layout");
+    const int lane = threadIdx.x % kRqLanes;
+    const int q = blockIdx.x * kRqRanges + threadIdx.x / kRqLanes;
     const int nact = ctrl->act_count[lv];
     int fbase = 0;  // first flag bit of this level
     for (int l = 0; l < lv; ++l) fbase += ctrl->act_count[l];
     const int nca = active_chunks(pctrl->pool_count, CG, n_chunks);
-    // best (F, key) of the thread's ranges over the pool chunks, loads of all
-    // ranges of a chunk in flight together
-    int64_t bF[kQuadItems], bK[kQuadItems], cr[kQuadItems];
-    int yxs[kQuadItems], srs[kQuadItems];
-#pragma unroll
-    for (int u = 0; u < kQuadItems; ++u) {
-        const int q = base + u;
-        const bool v = q < nact;
-        bF[u] = INT64_MAX;
-        bK[u] = INT64_MAX;
-        yxs[u] = v ? act[q] : -1;
-        cr[u] = v ? CR[q] : 0;
-        srs[u] = v ? SR[q] : 0;
-    }
-    for (int c = 0; c < nca; ++c) {
-        Partial pr[kQuadItems];
-#pragma unroll
-        for (int u = 0; u < kQuadItems; ++u) {
-            const int q = base + u;
-            if (q < nact) pr[u] = part[(int64_t)q * n_chunks + c];
-            else pr[u] = Partial{INT64_MAX, INT64_MAX};
-        }
-#pragma unroll
-        for (int u = 0; u < kQuadItems; ++u)
-            if (pair_less(pr[u].F, pr[u].key, bF[u], bK[u])) {
-                bF[u] = pr[u].F;
-                bK[u] = pr[u].key;
+    const bool valid = q < nact;
+    int64_t bF = INT64_MAX, bK = INT64_MAX;
+    if (valid) {
+        const Partial* pr = part + (int64_t)q * n_chunks;
+#pragma unroll 4
+        for (int c = lane; c < nca; c += kRqLanes) {
+            const Partial v = pr[c];
+            if (pair_less(v.F, v.key, bF, bK)) {
+                bF = v.F;
+                bK = v.key;
             }
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < kRqLanes; m <<= 1) {
+        const int64_t of = __shfl_xor(bF, m, 64), ok = __shfl_xor(bK, m, 64);
+        if (pair_less(of, ok, bF, bK)) {
+            bF = of;
+            bK = ok;
+        }
     }
     int kept = 0, split = 0;
-#pragma unroll
-    for (int u = 0; u < kQuadItems; ++u) {
-        const int q = base + u;
-        if (q >= nact) break;
+    if (valid) {
         fic_match m;
         int dy, dx;
-        const int yx = yxs[u];
-        const bool ok = finish_best(yx, B, L, gx, bF[u], bK[u], cr[u], srs[u], ks, m, dy, dx);
+        const int yx = act[q];
+        const bool ok = finish_best(yx, B, L, gx, bF, bK, CR[q], SR[q], ks, m, dy, dx);
         uint8_t d = 2;
         if (ok) {
-            fic_code c;
-            c.e_num = m.e_num;
-            c.dom = m.dom;
-            c.y = (int16_t)(yx >> 16);
-            c.x = (int16_t)(yx & 0xffff);
-            c.dy = (int16_t)dy;
-            c.dx = (int16_t)dx;
-            c.q_o = m.q_o;
-            c.log2B = (uint8_t)(31 - __clz(B));
-            c.iso = m.iso;
-            c.k = m.k;
-            c.s_idx = m.s_idx;
-            c.level = (uint8_t)lv;
-            for (int i = 0; i < 5; ++i) c.pad_[i] = 0;
-            tmp[q] = c;
+            // the code's 8-byte words (little-endian fic_code layout): e_num |
+            // dom, y, x | dy, dx, q_o, log2B, iso | k, s_idx, level, zero padding
+            const uint64_t w0 = (uint64_t)m.e_num;
+            const uint64_t w1 = (uint64_t)(uint32_t)m.dom | ((uint64_t)(uint32_t)(yx >> 16) << 32) |
+                                ((uint64_t)(yx & 0xffff) << 48);
+            const uint64_t w2 = (uint64_t)(uint16_t)dy | ((uint64_t)(uint16_t)dx << 16) |
+                                ((uint64_t)(uint16_t)m.q_o << 32) |
+                                ((uint64_t)(31 - __clz(B)) << 48) | ((uint64_t)m.iso << 56);
+            const uint64_t w3 = (uint64_t)m.k | ((uint64_t)m.s_idx << 8) | ((uint64_t)lv << 16);
+            const uint64_t w = lane == 0 ? w0 : lane == 1 ? w1 : lane == 2 ? w2 : w3;
+            reinterpret_cast<uint64_t*>(tmp + q)[lane] = w;
             d = (last || m.e_num <= thr) ? 1 : 0;
         }
-        dec[q] = d;
-        kept += d == 1;
-        split += d == 0;
-        if (flags && d == 0) atomicOr(&flags[(fbase + q) >> 5], 1u << ((fbase + q) & 31));
+        if (lane == 0) {
+            dec[q] = d;
+            kept = d == 1;
+            split = d == 0;
+            if (flags && d == 0) atomicOr(&flags[(fbase + q) >> 5], 1u << ((fbase + q) & 31));
+        }
     }
     int e0, e1, t0, t1;
     block_scan2(kept, split, e0, e1, t0, t1);
-    publish_count(blk, t0, t1);
-    if (!last_workgroup(&ctrl->ticket, nblk)) return;
-    int tot0, tot1;
-    scan_block_counts(blk, nblk, tot0, tot1);
-    if (threadIdx.x == 0) {
-        const int pool = pctrl->pool_count;
-        ctrl->code_base = ctrl->n_codes;
-        ctrl->n_codes += tot0;
-        ctrl->act_count[lv + 1] = 4 * tot1;
-        if (stats) {
-            fic_level_stats st;
-            st.matches = (int64_t)nact * pool * 8;
-            st.pool = pool;
-            st.passed = pctrl->passed;
-            st.active = nact;
-            st.accepted = tot0;
-            stats[lv] = st;
-        }
-    }
+    if (threadIdx.x == 0) blk[blockIdx.x] = make_int2(t0, t1);
 }
 
 // ---------------------------------------------------------------- decoder
@@ -2011,10 +2042,10 @@ __global__ __launch_bounds__(kBlock) void kt_reduce_fp32(Lvl a0, const Lvl* __re
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_reduce_quad(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    const int nblk = (a.max_act + kBlock * kQuadItems - 1) / (kBlock * kQuadItems);
+    const int nblk = (a.max_act + kRqRanges - 1) / kRqRanges;
     if ((int)blockIdx.x >= nblk) return;
     k_reduce_quad_body(a.B, a.L, a.gx, a.lv, a.last, a.thr, a.act, a.ctrl, a.pctrl, a.part, a.nc,
-                       a.cg, a.cr, a.sr, a.ks, a.tmpc, a.dec, a.blk, a.stats, nblk, a.flags);
+                       a.cg, a.cr, a.sr, a.ks, a.tmpc, a.dec, a.blk, a.flags);
 }
 
 template <bool TAB>
@@ -2026,7 +2057,8 @@ __global__ __launch_bounds__(kBlock) void kt_quad_scatter(Lvl a0, const Lvl* __r
     c.kind = 1;
     c.act_count = a.ctrl->act_count + a.lv;
     c.decision = a.dec;
-    k_quad_scatter_body(c, a.ctrl, a.blk, a.tmpc, a.codes, a.capacity, a.act, a.act_next, a.B / 2);
+    k_quad_scatter_body(c, a.ctrl, a.pctrl, a.lv, nblk, a.blk, a.tmpc, a.codes, a.capacity, a.act,
+                        a.act_next, a.B / 2, a.stats);
 }
 
 #undef FIC_LV

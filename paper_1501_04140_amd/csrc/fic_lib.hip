@@ -340,7 +340,7 @@ void grow(Sizes& s, const Level& v) {
     s.pblk[l] = std::max(s.pblk[l], (size_t)cdiv(v.total, kBlock * kPoolItems) * sizeof(int2));
     s.rng = std::max(s.rng, (size_t)v.max_act);
     s.part = std::max(s.part, (size_t)v.max_act * v.nc * sizeof(Partial));
-    s.blk = std::max(s.blk, (size_t)cdiv(v.max_act, kBlock * kQuadItems) * sizeof(int2));
+    s.blk = std::max(s.blk, (size_t)cdiv(v.max_act, kRqRanges) * sizeof(int2));
     s.act = std::max(s.act, (size_t)v.max_act);
     if (v.var == kVarMfma) {
         s.ar = std::max(s.ar, (size_t)v.max_act * 8 * 64);
@@ -604,10 +604,11 @@ int launch_level(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, boo
 // Keep/split decisions and compaction for a quadtree level.
 template <bool TAB>
 int launch_quad_t(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
+    const int gr = max_over(h, [](const Lvl& a) { return cdiv(a.max_act, kRqRanges); });
     const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.max_act, kBlock * kQuadItems); });
     {
         ProfScope ps("reduce_quad", st);
-        kt_reduce_quad<TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
+        kt_reduce_quad<TAB><<<dim3(gr, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
     }
     {
         ProfScope ps("quad_compact", st);
@@ -710,6 +711,9 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
     }
     const bool conc = fork && nl > 1 && nl <= kLevels;
     if (conc) HIP_TRY(hipEventRecord(fork->ev_fork, st));
+    // Level l's pool is queued right before level l's matcher: the host then
+    // reaches the first matcher early, and later pools are queued (and run)
+    // while the earlier levels match.
     for (int l = 0; l < nl; ++l) {
         hipStream_t ps = conc ? fork->side[l] : st;
         if (conc) HIP_TRY(hipStreamWaitEvent(ps, fork->ev_fork, 0));
@@ -721,8 +725,6 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
             if (rc) return rc;
         }
         if (conc) HIP_TRY(hipEventRecord(fork->ev_pool[l], ps));
-    }
-    for (int l = 0; l < nl; ++l) {
         if (conc) HIP_TRY(hipStreamWaitEvent(st, fork->ev_pool[l], 0));
         for (const Group& g : gs) {
             std::vector<Lvl> h(t.begin() + l * n_images + g.start,
