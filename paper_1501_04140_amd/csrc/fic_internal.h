@@ -26,7 +26,6 @@ struct Ctrl {
     int32_t lvl_base[5];   // codes emitted before each quadtree level
     int32_t err;
     int32_t sel_rank;      // rank still to find inside the current key prefix
-    uint32_t ticket;       // last-workgroup ticket (each kernel resets it)
     uint64_t sel_prefix;   // unused, kept for layout
     uint64_t cut_bound;    // floor mode: upper bound on the min_pool-th smallest key
     uint32_t ghist[kSelBins];

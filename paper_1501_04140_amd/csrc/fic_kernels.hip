@@ -48,29 +48,6 @@ __device__ inline int floordiv32(int a, int b) {  // b > 0
     return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
-// ---------------------------------------------------------------- coherent loads
-// Reads of values that other workgroups of the same launch published with
-// atomics, after a ticket showed they are complete.
-template <typename T>
-__device__ inline T ld_agent(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// True in the last of `nblocks` participating workgroups to get here
-// (self-resetting ticket).
-__device__ inline bool last_workgroup(uint32_t* ticket, int nblocks) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s_last = atomicAdd(ticket, 1u) == (uint32_t)nblocks - 1;
-        if (s_last) *ticket = 0u;
-    }
-    __syncthreads();
-    if (s_last) __threadfence();
-    return s_last;
-}
-
 // ---------------------------------------------------------------- active range lists
 // Packed corner: (y << 16) | x. Block 0 also sets the level's active count
 // and, when asked, clears the code counter of a new quadtree.
@@ -330,38 +307,27 @@ __device__ inline void block_scan2(int v0, int v1, int& e0, int& e1, int& t0, in
     __syncthreads();
 }
 
-// The last workgroup turns per-workgroup counts blk[0..nblk) into exclusive
-// offsets and returns the totals.
-__device__ inline void scan_block_counts(int2* blk, int nblk, int& tot0, int& tot1) {
-    __shared__ int carry0, carry1;
-    if (threadIdx.x == 0) {
-        carry0 = 0;
-        carry1 = 0;
-    }
-    __syncthreads();
-    for (int base = 0; base < nblk; base += kBlock) {
-        const int i = base + threadIdx.x;
-        int2 v = make_int2(0, 0);
-        if (i < nblk) v = make_int2(ld_agent(&blk[i].x), ld_agent(&blk[i].y));
-        int e0, e1, t0, t1;
-        block_scan2(v.x, v.y, e0, e1, t0, t1);
-        if (i < nblk) blk[i] = make_int2(carry0 + e0, carry1 + e1);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            carry0 += t0;
-            carry1 += t1;
+// Sums of the per-workgroup counts blk[0..n) over the whole workgroup: the
+// offsets of the workgroup that follows them. Each thread issues its loads
+// together. Every thread gets the sums.
+__device__ inline int2 counts_before(const int2* blk, int n) {
+    int s0 = 0, s1 = 0;
+    for (int i = threadIdx.x; i < n; i += 4 * kBlock) {
+        int2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = i + u * kBlock;
+            v[u] = k < n ? blk[k] : make_int2(0, 0);
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s0 += v[u].x;
+            s1 += v[u].y;
+        }
     }
-    tot0 = carry0;
-    tot1 = carry1;
-}
-
-__device__ inline void publish_count(int2* blk, int t0, int t1) {
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(&blk[blockIdx.x].x, t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&blk[blockIdx.x].y, t1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    int e0, e1, t0, t1;
+    block_scan2(s0, s1, e0, e1, t0, t1);
+    return make_int2(t0, t1);
 }
 
 // Pool compaction. A workgroup covers kBlock * kPoolItems consecutive
@@ -387,27 +353,25 @@ __device__ inline uint32_t pool_flag_bits(const CompactArgs& a, const Ctrl* ctrl
     return bits;
 }
 
-// Pass 1: per-workgroup counts; the last workgroup scans them and sets
-// pool_count (the pool, or the floor candidates).
-__device__ __forceinline__ void k_pool_count_body(CompactArgs a, Ctrl* ctrl, int2* blk, int nblk) {
+// Pass 1: per-workgroup counts of kept domains.
+__device__ __forceinline__ void k_pool_count_body(CompactArgs a, const Ctrl* ctrl, int2* blk) {
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
     const int base = blockIdx.x * kBlock * kPoolItems;
     const uint32_t bits = pool_flag_bits(a, ctrl, mode, base);
     int e0, e1, t0, t1;
     block_scan2(__popc(bits), 0, e0, e1, t0, t1);
-    publish_count(blk, t0, t1);
-    if (!last_workgroup(&ctrl->ticket, nblk)) return;
-    int tot0, tot1;
-    scan_block_counts(blk, nblk, tot0, tot1);
-    if (threadIdx.x == 0) ctrl->pool_count = tot0;
+    if (threadIdx.x == 0) blk[blockIdx.x] = make_int2(t0, 0);
 }
 
 // Pass 2: kept domains in ascending index order. Items are ordered (u, wave,
-// lane); the per-(u, wave) counts come from wave ballots.
-__device__ __forceinline__ void k_pool_scatter_body(CompactArgs a, const Ctrl* ctrl,
-                                                         const int2* blk, int32_t* pool_out) {
+// lane); the per-(u, wave) counts come from wave ballots, the workgroup's
+// offset from the counts of the workgroups before it. The last workgroup sets
+// pool_count (the pool, or the floor candidates).
+__device__ __forceinline__ void k_pool_scatter_body(CompactArgs a, Ctrl* ctrl, const int2* blk,
+                                                         int nblk, int32_t* pool_out) {
     constexpr int NW = kBlock / 64;
-    __shared__ int s_off[kPoolItems * NW];
+    __shared__ int s_off[kPoolItems * NW + 1];
+    const int boff = counts_before(blk, blockIdx.x).x;
     const int mode = pool_mode(ctrl->pass_count, a.total, a.min_pool);
     const int base = blockIdx.x * kBlock * kPoolItems;
     const uint32_t bits = pool_flag_bits(a, ctrl, mode, base);
@@ -440,9 +404,10 @@ __device__ __forceinline__ void k_pool_scatter_body(CompactArgs a, const Ctrl* c
             if (lane * PER + e < NE) s_off[lane * PER + e] = run;
             run += v[e];
         }
+        if (lane == 63) s_off[NE] = incl;  // the workgroup's total
     }
     __syncthreads();
-    const int boff = blk[blockIdx.x].x;
+    if ((int)blockIdx.x == nblk - 1 && threadIdx.x == 0) ctrl->pool_count = boff + s_off[kPoolItems * NW];
     const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll 8
     for (int u = 0; u < kPoolItems; ++u) {
@@ -613,16 +578,9 @@ __device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, Ctrl* ctrl, c
     }
     // kept and split ranges before this workgroup
     constexpr int kPer = kBlock * kQuadItems / kRqRanges;  // decision workgroups per workgroup
-    const int nprev = blockIdx.x * kPer;
-    int p0 = 0, p1 = 0;
-    for (int i = threadIdx.x; i < nprev; i += kBlock) {
-        const int2 v = blk[i];
-        p0 += v.x;
-        p1 += v.y;
-    }
+    const int2 off = counts_before(blk, blockIdx.x * kPer);
+    const int off0 = off.x, off1 = off.y;
     int e0, e1, t0, t1;
-    block_scan2(p0, p1, e0, e1, t0, t1);
-    const int off0 = t0, off1 = t1;
     block_scan2(c0, c1, e0, e1, t0, t1);
     int r0 = off0 + e0, r1 = off1 + e1;
     const int cb = ctrl->lvl_base[lv];
@@ -1963,7 +1921,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_count(Lvl a0, const Lvl* __res
     FIC_LV;
     const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
     if ((int)blockIdx.x >= nblk) return;
-    k_pool_count_body(pool_args(a), a.pctrl, a.pblk, nblk);
+    k_pool_count_body(pool_args(a), a.pctrl, a.pblk);
 }
 
 template <bool TAB>
@@ -1971,7 +1929,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_scatter(Lvl a0, const Lvl* __r
     FIC_LV;
     const int nblk = (a.total + kBlock * kPoolItems - 1) / (kBlock * kPoolItems);
     if ((int)blockIdx.x >= nblk) return;
-    k_pool_scatter_body(pool_args(a), a.pctrl, a.pblk, a.pool);
+    k_pool_scatter_body(pool_args(a), a.pctrl, a.pblk, nblk, a.pool);
 }
 
 template <bool TAB>
