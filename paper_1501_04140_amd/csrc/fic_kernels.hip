@@ -138,6 +138,93 @@ __device__ __forceinline__ void k_pool_score_body(const uint8_t* __restrict__ im
     if (threadIdx.x == 0 && cnt) atomicAdd(&ctrl->pass_count, cnt);
 }
 
+// The same keys by cells. With stride L and side 4L, domain (dy, dx) is the
+// 4 x 4 block of L x L cells starting at cell (dy, dx). A workgroup scores a
+// tile of kScTY x kScTX domains from the histograms of the (kScTY + 3) x
+// (kScTX + 3) cells they cover: a wave reads 64 consecutive pixels of a row
+// (L lanes per cell, 8-bit counters over the cell's L rows), cells are widened
+// to 16-bit counters, summed 4 at a time along x, then 4 rows at a time along y.
+// Each cell is read once per tile instead of once per domain that covers it.
+constexpr int kScTX = 64, kScTY = kBlock / kScTX;
+
+template <int L>
+__device__ __forceinline__ void k_pool_score_cells_body(const uint8_t* __restrict__ img, int pitch,
+                                                             int gx, int gy,
+                                                             const int64_t* __restrict__ T, int64_t M,
+                                                             int64_t* __restrict__ key, Ctrl* ctrl) {
+    constexpr int CX = kScTX + 3, CY = kScTY + 3;  // cells of the tile
+    constexpr int NPIX = 16 * L * L;               // pixels of a domain
+    constexpr int CPW = 64 / L;                    // cells across a wave's 64 pixels
+    constexpr int XCH = (CX + CPW - 1) / CPW;      // wave chunks per row of cells
+    constexpr int NCH = CY * XCH;
+    __shared__ uint64_t sc[CY * CX * 2];           // cells: bins 0-3 | bins 4-7, 16 bits each
+    __shared__ uint64_t sh[CY * kScTX * 2];        // sums of 4 cells along x
+    __shared__ int64_t sT[NPIX + 1];
+    const int dx0 = blockIdx.x * kScTX, dy0 = blockIdx.y * kScTY;
+    if (dx0 >= gx || dy0 >= gy) return;
+    for (int i = threadIdx.x; i <= NPIX; i += kBlock) sT[i] = T[i];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int t = wid; t < NCH; t += kBlock / 64) {
+        const int cr = t / XCH, lc = (t % XCH) * CPW + lane / L;
+        const int cy = dy0 + cr, cx = dx0 + lc;
+        uint64_t acc = 0;
+        if (lc < CX && cy < gy + 3 && cx < gx + 3) {
+            const uint8_t* p = img + (int64_t)cy * L * pitch + (int64_t)cx * L + lane % L;
+            uint32_t v[L];
+#pragma unroll
+            for (int r = 0; r < L; ++r) v[r] = p[(int64_t)r * pitch];
+#pragma unroll
+            for (int r = 0; r < L; ++r) acc += 1ull << (8 * (v[r] >> 5));
+        }
+#pragma unroll
+        for (int m = 1; m < L; m <<= 1) acc += __shfl_xor(acc, m, 64);
+        if (lane % L == 0 && lc < CX) {
+            uint64_t lo = 0, hi = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                lo |= ((acc >> (8 * b)) & 0xffull) << (16 * b);
+                hi |= ((acc >> (8 * (b + 4))) & 0xffull) << (16 * b);
+            }
+            sc[(cr * CX + lc) * 2] = lo;
+            sc[(cr * CX + lc) * 2 + 1] = hi;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < CY * kScTX; i += kBlock) {
+        const int r = i / kScTX, c = i % kScTX;
+        uint64_t lo = 0, hi = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lo += sc[(r * CX + c + k) * 2];
+            hi += sc[(r * CX + c + k) * 2 + 1];
+        }
+        sh[i * 2] = lo;
+        sh[i * 2 + 1] = hi;
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / kScTX, tx = threadIdx.x % kScTX;
+    const int dy = dy0 + ty, dx = dx0 + tx;
+    int pass = 0;
+    if (dy < gy && dx < gx) {
+        uint64_t lo = 0, hi = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lo += sh[((ty + k) * kScTX + tx) * 2];
+            hi += sh[((ty + k) * kScTX + tx) * 2 + 1];
+        }
+        int64_t s = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            s += sT[(lo >> (16 * b)) & 0xffff];
+            s += sT[(hi >> (16 * b)) & 0xffff];
+        }
+        key[(int64_t)dy * gx + dx] = s;
+        pass = s < M;
+    }
+    const int cnt = __syncthreads_count(pass);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&ctrl->pass_count, cnt);
+}
+
 // Variance filter (an alternative to the entropy filter of Section 3): key[j]
 // = kv - V' with V' = N sum p^2 - (sum p)^2 over the N = SIDE^2 pixels of the
 // domain (N^2 times its variance, exact), so smaller keys mean higher variance
@@ -1875,6 +1962,13 @@ template <bool TAB>
 __global__ void kt_act_from_yx(Lvl a0, const Lvl* __restrict__ tab, const int32_t* yx, int n) {
     FIC_LV;
     k_act_from_yx_body(a.act, yx, n, a.H, a.W, a.B, a.ctrl);
+}
+
+template <int L, bool TAB>
+__global__ __launch_bounds__(kBlock) void kt_pool_score_cells(Lvl a0, const Lvl* __restrict__ tab,
+                                                              const int64_t* __restrict__ T) {
+    FIC_LV;
+    k_pool_score_cells_body<L>(a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl);
 }
 
 template <int SIDE, bool TAB>

@@ -469,11 +469,24 @@ int max_over(const std::vector<Lvl>& h, F f) {
     return m;
 }
 
+// Domains at or above which the entropy keys come from cell histograms.
+constexpr int kScoreCellsMin = 32768;
+
 template <int SIDE, bool TAB>
 void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
     if (h[0].pmode == 2) {
         const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });
         kt_pool_var<SIDE, TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
+        return;
+    }
+    // large grids with stride L = SIDE / 4: keys from cell histograms
+    constexpr int L = SIDE / 4;
+    const bool cells = max_over(h, [](const Lvl& a) { return a.total; }) >= kScoreCellsMin &&
+                       std::all_of(h.begin(), h.end(), [](const Lvl& a) { return a.L == L; });
+    if (cells) {
+        const int bx = max_over(h, [](const Lvl& a) { return cdiv(a.gx, kScTX); });
+        const int by = max_over(h, [](const Lvl& a) { return cdiv(a.gy, kScTY); });
+        kt_pool_score_cells<L, TAB><<<dim3(bx, by, h.size()), kBlock, 0, st>>>(h[0], dt, T);
         return;
     }
     const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });

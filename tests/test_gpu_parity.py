@@ -146,6 +146,26 @@ def test_entropy_threshold_variants(dev):
         check_level(dev, img, 4, 2, (1,), entropy=1, min_pool=8, bits=bits)
 
 
+@pytest.mark.parametrize("B,L,H,W", [(2, 1, 200, 300), (4, 2, 392, 520), (8, 4, 760, 776),
+                                     (16, 8, 1488, 1520)])
+def test_entropy_pool_large_grids(dev, B, L, H, W):
+    """Grids of 32768 domains or more, whose entropy keys come from cell histograms;
+    both grid sides leave a partial tile. Threshold mode (most domains pass at 1 bit)
+    and floor mode (the 5000 lowest keys, nothing passing at 2.5 bits)."""
+    img = synth.power_law(max(H, W), beta=2.0, seed=7, n_rect=3)[:H, :W].copy()
+    gy, gx = oracle.domain_grid(H, W, B, L)
+    assert gy * gx >= 32768 and gx % 64 and gy % 4
+    x = torch.from_numpy(img).to(dev)
+    corner = torch.tensor([[0, 0]], dtype=torch.int32, device=dev)
+    for bits, min_pool in ((1.0, 16), (2.5, 5000)):
+        say(f"[entropy] {H}x{W} B={B} L={L} bits={bits} min_pool={min_pool}")
+        _, pool, pc = fic.encode_level(x, B, L, (2, 4), 1, bits, min_pool, ranges=corner,
+                                       return_pool=True)
+        torch.cuda.synchronize()
+        ref, _ = oracle.entropy_pool(img, B, L, bits, min_pool)
+        assert np.array_equal(pool.cpu().numpy()[:int(pc.item())], ref)
+
+
 @pytest.mark.parametrize("B,L,vmin,min_pool", [(2, 1, 50.0, 256), (4, 2, 300.0, 64), (8, 4, 900.0, 16),
                                                (16, 8, 1e9, 32), (4, 2, -1.0, 8), (2, 1, 0.0, 10 ** 6)])
 def test_variance_pool_levels(dev, B, L, vmin, min_pool):
