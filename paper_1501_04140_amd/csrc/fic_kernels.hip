@@ -791,31 +791,38 @@ __device__ inline bool pair_less(int64_t fa, int64_t ka, int64_t fb, int64_t kb)
 // 16 Q^2 n E(k) minus the row constant 16 Q^2 C. For a consecutive set
 // k0..k1 the minimiser is the smallest k with (2k+1) A' >= 8Q B' (F is a
 // convex quadratic in k); an FP32 estimate is corrected exactly.
-__device__ inline void best_contrast(int64_t Bp, int64_t Ap, const KSet& ks, int64_t& F, int& s) {
-    if (ks.consecutive) {
-        int k = ks.k0;
-        if (Ap > 0) {
-            float xf = (float)Bp * (40.0f / (float)Ap);
-            float kf = fminf(fmaxf(rintf(xf), (float)ks.k0), (float)ks.k1);
-            k = (int)kf;
-            const int64_t b80 = 80 * Bp;
-            while (k > ks.k0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
-            while (k < ks.k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
-        }
-        F = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
-        s = k - ks.k0;
-    } else {
-        F = INT64_MAX;
-        s = 0;
-        for (int i = 0; i < ks.n; ++i) {
-            const int k = ks.k[i];
-            int64_t f = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
-            if (f < F) {
-                F = f;
-                s = i;
-            }
+__device__ inline void best_contrast_grid(int64_t Bp, int64_t Ap, int k0, int k1, int64_t& F, int& s) {
+    int k = k0;
+    if (Ap > 0) {
+        float xf = (float)Bp * (40.0f / (float)Ap);
+        float kf = fminf(fmaxf(rintf(xf), (float)k0), (float)k1);
+        k = (int)kf;
+        const int64_t b80 = 80 * Bp;
+        while (k > k0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
+        while (k < k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
+    }
+    F = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
+    s = k - k0;
+}
+
+// Every value of the set in turn; ks refers to the kernel argument (a local
+// copy indexed in a loop would live in scratch memory).
+__device__ inline void best_contrast_list(int64_t Bp, int64_t Ap, const KSet& ks, int64_t& F, int& s) {
+    F = INT64_MAX;
+    s = 0;
+    for (int i = 0; i < ks.n; ++i) {
+        const int k = ks.k[i];
+        const int64_t f = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
+        if (f < F) {
+            F = f;
+            s = i;
         }
     }
+}
+
+__device__ inline void best_contrast(int64_t Bp, int64_t Ap, const KSet& ks, int64_t& F, int& s) {
+    if (ks.consecutive) best_contrast_grid(Bp, Ap, ks.k0, ks.k1, F, s);
+    else best_contrast_list(Bp, Ap, ks, F, s);
 }
 
 template <int B>
@@ -893,7 +900,7 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
                                                   const uint32_t* __restrict__ Sd,
                                                   const int64_t* __restrict__ Ad,
                                                   const int32_t* __restrict__ Jd, const Ctrl* ctrl,
-                                                  KSet ks, int n_chunks, Partial* __restrict__ part,
+                                                  const KSet& ks, int n_chunks, Partial* __restrict__ part,
                                                   int32_t* __restrict__ SRout,
                                                   int64_t* __restrict__ CRout, int cg) {
     using Tl = MatchTile<B>;
@@ -1090,15 +1097,8 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
             } else {
                 int64_t F;
                 int sidx;
-                if (MODE == kModeGrid) {
-                    KSet kg = ks;
-                    kg.consecutive = 1;
-                    best_contrast((int64_t)Bp, sA[d], kg, F, sidx);
-                } else {
-                    KSet kl = ks;
-                    kl.consecutive = 0;
-                    best_contrast((int64_t)Bp, sA[d], kl, F, sidx);
-                }
+                if (MODE == kModeGrid) best_contrast_grid((int64_t)Bp, sA[d], ks.k0, ks.k1, F, sidx);
+                else best_contrast_list((int64_t)Bp, sA[d], ks, F, sidx);
                 if (F < bestF) {
                     bestF = F;
                     bestP = base + d;
@@ -1147,6 +1147,13 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
 }
 
 // ---------------------------------------------------------------- per-range result
+// Contrast numerator at position s of a set. Callers pass the set by
+// reference to the kernel argument: a by-value copy indexed per lane would be
+// placed in LDS, one copy per thread.
+__device__ inline int kset_value(const KSet& ks, int s) {
+    return ks.consecutive ? ks.k0 + s : ks.k[s];
+}
+
 // Fill the match of a range from its best (F, key) over all pool chunks.
 __device__ inline bool finish_best(int yx, int B, int L, int gx, int64_t F, int64_t K, int64_t CRq,
                                    int32_t SRq, const KSet& ks, fic_match& m, int& dy, int& dx) {
@@ -1166,7 +1173,7 @@ __device__ inline bool finish_best(int yx, int B, int L, int gx, int64_t F, int6
     const int n = B * B;
     const int j = (int)(K >> 27), t = (int)((K >> 24) & 7), s = (int)((K >> 20) & 15);
     const int64_t sd = K & 0xfffff;
-    const int k = ks.consecutive ? ks.k0 + s : ks.k[s];
+    const int k = kset_value(ks, s);
     dy = (j / gx) * L;
     dx = (j % gx) * L;
     m.e_num = F + 1600 * CRq;
@@ -1198,7 +1205,7 @@ __device__ __forceinline__ void k_reduce_level_body(int B, int L, int gx,
                                                          const Partial* __restrict__ part,
                                                          int n_chunks, int CG, const Ctrl* ctrl,
                                                          const int64_t* __restrict__ CR,
-                                                         const int32_t* __restrict__ SR, KSet ks,
+                                                         const int32_t* __restrict__ SR, const KSet& ks,
                                                          fic_match* __restrict__ out) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= *act_count) return;
@@ -1217,7 +1224,7 @@ __device__ __forceinline__ void k_reduce_level_body(int B, int L, int gx,
 __device__ __forceinline__ void k_reduce_quad_body(
     int B, int L, int gx, int lv, int last, int64_t thr, const int32_t* __restrict__ act,
     const Ctrl* ctrl, const Ctrl* pctrl, const Partial* __restrict__ part, int n_chunks, int CG,
-    const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, KSet ks,
+    const int64_t* __restrict__ CR, const int32_t* __restrict__ SR, const KSet& ks,
     fic_code* __restrict__ tmp, uint8_t* __restrict__ dec, int2* blk,
     uint32_t* __restrict__ flags) {
     static_assert(sizeof(fic_code) == 32 && kRqLanes == 4, "one 8-byte word of a code per lane");
@@ -1230,7 +1237,8 @@ __device__ __forceinline__ void k_reduce_quad_body(
     const int q = blockIdx.x * kRqRanges + threadIdx.x / kRqLanes;
     const int nact = ctrl->act_count[lv];
     int fbase = 0;  // first flag bit of this level
-    for (int l = 0; l < lv; ++l) fbase += ctrl->act_count[l];
+    if (flags)
+        for (int l = 0; l < lv; ++l) fbase += ctrl->act_count[l];
     const int nca = active_chunks(pctrl->pool_count, CG, n_chunks);
     const bool valid = q < nact;
     int64_t bF = INT64_MAX, bK = INT64_MAX;
