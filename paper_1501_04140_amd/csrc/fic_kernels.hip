@@ -537,29 +537,58 @@ constexpr int kSelStage = 8192;  // floor candidates held in LDS by the select
 // bit a candidate can have, and the select stops as soon as the chosen bucket
 // is taken whole. Always launched: it also publishes the number of domains
 // that passed the threshold and clears the per-level counters.
+// direct (grids of at most kSelStage domains, launched without the bound and
+// compaction steps): every domain is a candidate, and the threshold and
+// whole-grid pools are compacted here too.
 __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ key, int total,
                                                        int min_pool, int r,
-                                                       int32_t* __restrict__ pool, Ctrl* ctrl) {
+                                                       int32_t* __restrict__ pool, Ctrl* ctrl,
+                                                       bool direct, int64_t M) {
     __shared__ uint64_t sk[kSelStage];
     __shared__ int32_t sj[kSelStage];
     __shared__ uint32_t h[kSelBins];
     __shared__ int s_w[16];
     __shared__ uint64_t s_prefix;
+    __shared__ unsigned long long s_max;
     __shared__ uint32_t s_rank;
     __shared__ int s_lo, s_done, s_c0, s_c1;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int passed = ctrl->pass_count;
     const int mode = pool_mode(passed, total, min_pool);
+    if (direct && mode != 1) {
+        // every domain (mode 2) or the threshold passers (mode 0), in index order
+        if (tid == 0) s_c0 = 0;
+        __syncthreads();
+        for (int base = 0; base < total; base += nt) {
+            const int i = base + tid;
+            const int f = i < total && (mode == 2 || key[i] < M);
+            int tot;
+            const int off = scan1024(f, s_w, tot);
+            if (f) pool[s_c0 + off] = i;
+            __syncthreads();
+            if (tid == 0) s_c0 += tot;
+            __syncthreads();
+        }
+        if (tid == 0) ctrl->pool_count = s_c0;
+    }
     if (mode == 1) {
-        const int C = ctrl->pool_count;
+        const int C = direct ? total : ctrl->pool_count;
         const bool staged = C <= kSelStage;
-        if (staged)
+        if (tid == 0) s_max = 0ull;
+        __syncthreads();
+        if (staged) {
+            uint64_t kmax = 0;
             for (int i = tid; i < C; i += nt) {
-                const int j = pool[i];
+                const int j = direct ? i : pool[i];
+                const uint64_t u = (uint64_t)key[j];
                 sj[i] = j;
-                sk[i] = (uint64_t)key[j];
+                sk[i] = u;
+                kmax = u > kmax ? u : kmax;
             }
-        const uint64_t ub = ctrl->cut_bound;
+            if (direct) atomicMax(&s_max, (unsigned long long)kmax);
+        }
+        __syncthreads();
+        const uint64_t ub = direct ? (uint64_t)s_max : ctrl->cut_bound;
         const int top = min(62, ub ? 63 - __clzll((long long)ub) : 0);
         if (tid == 0) {
             s_prefix = 0;
@@ -2035,9 +2064,10 @@ __global__ __launch_bounds__(kBlock) void kt_pool_scatter(Lvl a0, const Lvl* __r
 }
 
 template <bool TAB>
-__global__ __launch_bounds__(1024) void kt_floor_select(Lvl a0, const Lvl* __restrict__ tab) {
+__global__ __launch_bounds__(1024) void kt_floor_select(Lvl a0, const Lvl* __restrict__ tab, int direct) {
     FIC_LV;
-    k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.pctrl);
+    k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.pctrl,
+                        direct && a.total <= kSelStage, a.M);
 }
 
 template <int B, bool TAB>

@@ -554,20 +554,24 @@ int launch_pool_phase_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t*
                 default: launch_score<32, TAB>(dt, h, T, st); break;
             }
         }
-        {
-            ProfScope ps("pool_select", st);
-            const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, a.bound_chunk); });
-            kt_floor_bound<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+        // small grids: one workgroup stages every key and builds the pool itself
+        const bool direct = max_over(h, [](const Lvl& a) { return a.total; }) <= kSelStage;
+        if (!direct) {
+            {
+                ProfScope ps("pool_select", st);
+                const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, a.bound_chunk); });
+                kt_floor_bound<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+            }
+            {
+                ProfScope ps("pool_compact", st);
+                const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
+                kt_pool_count<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+                kt_pool_scatter<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+            }
         }
         {
-            ProfScope ps("pool_compact", st);
-            const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
-            kt_pool_count<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
-            kt_pool_scatter<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
-        }
-        {
             ProfScope ps("pool_select", st);
-            kt_floor_select<TAB><<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt);
+            kt_floor_select<TAB><<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt, direct ? 1 : 0);
         }
         if (h[0].pools_out) {
             const int gx = max_over(h, [](const Lvl& a) { return std::min(cdiv(a.total, kBlock), 1024); });
@@ -724,10 +728,7 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
     }
     const bool conc = fork && nl > 1 && nl <= kLevels;
     if (conc) HIP_TRY(hipEventRecord(fork->ev_fork, st));
-    // Level l's pool is queued right before level l's matcher: the host then
-    // reaches the first matcher early, and later pools are queued (and run)
-    // while the earlier levels match.
-    for (int l = 0; l < nl; ++l) {
+    auto pool = [&](int l) -> int {
         hipStream_t ps = conc ? fork->side[l] : st;
         if (conc) HIP_TRY(hipStreamWaitEvent(ps, fork->ev_fork, 0));
         for (const Group& g : gs) {
@@ -738,6 +739,9 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
             if (rc) return rc;
         }
         if (conc) HIP_TRY(hipEventRecord(fork->ev_pool[l], ps));
+        return FIC_OK;
+    };
+    auto match = [&](int l) -> int {
         if (conc) HIP_TRY(hipStreamWaitEvent(st, fork->ev_pool[l], 0));
         for (const Group& g : gs) {
             std::vector<Lvl> h(t.begin() + l * n_images + g.start,
@@ -747,6 +751,19 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
             if (rc) return rc;
             if ((rc = launch_quad(dl, h, st))) return rc;
         }
+        return FIC_OK;
+    };
+    // Level 0's pool and matcher are queued first, so the host reaches the
+    // first matcher early; the other pools follow at once and run on their
+    // streams while level 0 matches. On one stream the order is level by level.
+    int rc;
+    if ((rc = pool(0)) || (rc = match(0))) return rc;
+    if (conc)
+        for (int l = 1; l < nl; ++l)
+            if ((rc = pool(l))) return rc;
+    for (int l = 1; l < nl; ++l) {
+        if (!conc && (rc = pool(l))) return rc;
+        if ((rc = match(l))) return rc;
     }
     return FIC_OK;
 }
