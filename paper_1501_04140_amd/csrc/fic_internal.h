@@ -90,6 +90,7 @@ struct Lvl {
     float* af;
     uint32_t* flags;    // optional: split flags, one bit per active range, levels in order
     int32_t* pools_out; // optional: this level's pool list
+    int32_t* n_out;     // optional, last level: the number of codes, written by the compaction
     KSet ks;
 };
 

@@ -682,7 +682,8 @@ __device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, Ctrl* ctrl, c
                                                          const int2* blk, const fic_code* tmp_codes,
                                                          fic_code* codes, int capacity,
                                                          const int32_t* act, int32_t* act_next,
-                                                         int half, fic_level_stats* stats) {
+                                                         int half, fic_level_stats* stats,
+                                                         int32_t* n_out) {
     const int base = blockIdx.x * kBlock * kQuadItems + threadIdx.x * kQuadItems;
     int f0[kQuadItems], f1[kQuadItems];
     int c0 = 0, c1 = 0;
@@ -724,6 +725,7 @@ __device__ __forceinline__ void k_quad_scatter_body(CompactArgs a, Ctrl* ctrl, c
         const int nact = *a.act_count;
         ctrl->lvl_base[lv + 1] = cb + tot0;
         ctrl->n_codes = cb + tot0;
+        if (n_out) *n_out = cb + tot0;
         ctrl->act_count[lv + 1] = 4 * tot1;
         if (stats) {
             const int pool = pctrl->pool_count;
@@ -2148,7 +2150,7 @@ __global__ __launch_bounds__(kBlock) void kt_quad_scatter(Lvl a0, const Lvl* __r
     c.act_count = a.ctrl->act_count + a.lv;
     c.decision = a.dec;
     k_quad_scatter_body(c, a.ctrl, a.pctrl, a.lv, nblk, a.blk, a.tmpc, a.codes, a.capacity, a.act,
-                        a.act_next, a.B / 2, a.stats);
+                        a.act_next, a.B / 2, a.stats, a.n_out);
 }
 
 #undef FIC_LV

@@ -782,7 +782,7 @@ int64_t flag_words(int H, int W, const fic_params* p) {
 int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch,
                       const fic_params* p, const std::vector<KSet>& ks, fic_code* codes,
                       int capacity, fic_level_stats* stats, uint32_t* flags = nullptr,
-                      int32_t* pools = nullptr) {
+                      int32_t* pools = nullptr, int32_t* n_out = nullptr) {
     std::vector<Level> lv = quad_levels(H, W, p, ks);
     Sizes sz;
     for (const Level& v : lv) grow(sz, v);
@@ -794,6 +794,7 @@ int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch
             k_fill_i32<<<cdiv(nw, kBlock), kBlock, 0, ws.stream>>>(reinterpret_cast<int32_t*>(flags), (int)nw, 0);
     }
     std::vector<Lvl> t = quad_tables(ws, lv, img, H, W, pitch, p, codes, capacity, stats, flags, pools);
+    t.back().n_out = n_out;
     if ((rc = ensure_fork(ws))) return rc;
     return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode != 0, ws.stream, nullptr, &ws);
 }
@@ -895,10 +896,8 @@ FIC_API int fic_encode_image(const uint8_t* img, int32_t H, int32_t W, int32_t p
         return fail(FIC_ECAPACITY, "capacity %d below the %d codes of the first level", capacity, lower);
     Workspace* ws;
     if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
-    if ((rc = encode_image_impl(*ws, img, H, W, pitch, p, ks, codes, capacity, stats))) return rc;
-    HIP_TRY(hipMemcpyAsync(n_codes, &ws->ctrl->n_codes, sizeof(int32_t), hipMemcpyDeviceToDevice,
-                           ws->stream));
-    return FIC_OK;
+    return encode_image_impl(*ws, img, H, W, pitch, p, ks, codes, capacity, stats, nullptr, nullptr,
+                             n_codes);
 }
 
 FIC_API int fic_encode_image_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
@@ -915,11 +914,8 @@ FIC_API int fic_encode_image_ex(const uint8_t* img, int32_t H, int32_t W, int32_
         return fail(FIC_ECAPACITY, "capacity %d below the %d codes of the first level", capacity, lower);
     Workspace* ws;
     if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
-    if ((rc = encode_image_impl(*ws, img, H, W, pitch, p, ks, codes, capacity, stats, flags, pools)))
-        return rc;
-    HIP_TRY(hipMemcpyAsync(n_codes, &ws->ctrl->n_codes, sizeof(int32_t), hipMemcpyDeviceToDevice,
-                           ws->stream));
-    return FIC_OK;
+    return encode_image_impl(*ws, img, H, W, pitch, p, ks, codes, capacity, stats, flags, pools,
+                             n_codes);
 }
 
 FIC_API int fic_decode(const fic_code* codes, int32_t n_codes, int32_t H, int32_t W, int32_t iters,
