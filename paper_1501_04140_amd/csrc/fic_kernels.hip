@@ -863,7 +863,7 @@ struct MatchTile {
     // domains per LDS tile: 8-34 KiB of LDS
     static constexpr int TN = B == 16 ? 64 : (B == 8 ? 128 : 256);
     // target domains per pool chunk (one workgroup's share of the pool)
-    static constexpr int CG = B == 16 ? 16 : (B == 8 ? 32 : (B == 4 ? 128 : 256));
+    static constexpr int CG = B == 16 ? 16 : (B == 8 ? 32 : (B == 4 ? 64 : 128));
     // exact integer widths (bounds by Cauchy-Schwarz: |B'| <= sqrt(A' C))
     using BpT = typename std::conditional<(B <= 8), int32_t, int64_t>::type;   // B'
     using GT = typename std::conditional<(B <= 4), int32_t, int64_t>::type;    // k A' - 80 B'
@@ -873,51 +873,75 @@ struct MatchTile {
 enum { kModeSmall = 0, kModeGrid = 1, kModeList = 2 };
 constexpr int kSmallMax = 2;
 
+// Isometries per thread: 2 for small sets at B <= 4, where a domain's LDS
+// record would otherwise cost more LDS bandwidth than its arithmetic; the
+// workgroup then covers 64 ranges instead of 32.
+constexpr int match_isos_per_thread(int B, int mode) { return mode == kModeSmall && B <= 4 ? 2 : 1; }
+constexpr int match_ranges_per_block(int B, int mode) { return kBlock * match_isos_per_thread(B, mode) / 8; }
+
 // Number of pool chunks actually used: about one LDS tile each, at most the
 // chunks the grid was launched with.
 __device__ inline int active_chunks(int P, int TN, int n_chunks) {
     return max(1, min(n_chunks, (P + TN - 1) / TN));
 }
 
-// Domain loop of the B = 2 small-set matcher. Records {d'0 | d'1 << 16,
-// d'2 | d'3 << 16, kf A' - 80 p, p} with p the pool position and kf the first
-// contrast value in use; TWO adds the second value through (k1 - k0) A'.
-// Seeding the first dot product with p (in a register already) and removing
-// 80 p through the record keeps G exact: G = 80 (sum_i d'_i w_i + p) + kf A' - 80 p.
-// Running minimum of G and the pool position of its first occurrence.
-template <bool TWO>
+// Domain loop of the B = 2 small-set matcher for IT isometries of one range.
+// Records {d'0 | d'1 << 16, d'2 | d'3 << 16, kf A' - 80 p, p} with p the pool
+// position and kf the first contrast value in use; TWO adds the second value
+// through (k1 - k0) A'. Seeding the first dot product with p (in a register
+// already) and removing 80 p through the record keeps G exact:
+// G = 80 (sum_i d'_i w_i + p) + kf A' - 80 p. Running minimum of G and the
+// pool position of its first occurrence, per isometry.
+template <int IT, bool TWO>
 __device__ __forceinline__ void match_b2_loop(const int4* sRec, const int32_t* sE1, int cnt,
-                                              uint32_t w01, uint32_t w23, int& g0, int& p0,
-                                              int& g1, int& p1) {
+                                              const uint32_t* w01, const uint32_t* w23, int* g0,
+                                              int* p0, int* g1, int* p1) {
     typedef short s2 __attribute__((ext_vector_type(2)));
-    const s2 a01 = __builtin_bit_cast(s2, w01), a23 = __builtin_bit_cast(s2, w23);
-    int bg0 = g0, bp0 = p0, bg1 = g1, bp1 = p1;
+    s2 a01[IT], a23[IT];
+    int bg0[IT], bp0[IT], bg1[IT], bp1[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        a01[i] = __builtin_bit_cast(s2, w01[i]);
+        a23[i] = __builtin_bit_cast(s2, w23[i]);
+        bg0[i] = g0[i];
+        bp0[i] = p0[i];
+        bg1[i] = g1[i];
+        bp1[i] = p1[i];
+    }
 #pragma unroll 4
     for (int d = 0; d < cnt; ++d) {
         const int4 rec = sRec[d];
-        int dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.x), a01, rec.w, false);
-        dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.y), a23, dsum, false);
-        const int g = __mul24(dsum, 80) + rec.z;
-        const bool lt = g < bg0;
-        bp0 = lt ? rec.w : bp0;
-        bg0 = lt ? g : bg0;
-        if constexpr (TWO) {
-            const int h = g + sE1[d];
-            const bool lt1 = h < bg1;
-            bp1 = lt1 ? rec.w : bp1;
-            bg1 = lt1 ? h : bg1;
+        const int e1 = TWO ? sE1[d] : 0;
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            int dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.x), a01[i], rec.w, false);
+            dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.y), a23[i], dsum, false);
+            const int g = __mul24(dsum, 80) + rec.z;
+            const bool lt = g < bg0[i];
+            bp0[i] = lt ? rec.w : bp0[i];
+            bg0[i] = lt ? g : bg0[i];
+            if constexpr (TWO) {
+                const int h = g + e1;
+                const bool lt1 = h < bg1[i];
+                bp1[i] = lt1 ? rec.w : bp1[i];
+                bg1[i] = lt1 ? h : bg1[i];
+            }
         }
     }
-    g0 = bg0;
-    p0 = bp0;
-    g1 = bg1;
-    p1 = bp1;
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        g0[i] = bg0[i];
+        p0[i] = bp0[i];
+        g1[i] = bg1[i];
+        p1[i] = bp1[i];
+    }
 }
 
-// grid: x = row blocks of 256 rows (32 ranges x 8 isometries), y = pool chunks.
-// The workgroup stages its 32 range blocks in LDS; thread (range q, iso t)
-// keeps row[m] = R[iso_src(inverse(t), m)] in registers as packed bytes, so
-// that <row, d'> = <R, T_t(d')>.
+// grid: x = row blocks of RPB ranges (RPB = 32, or 64 with two isometries
+// per thread), y = pool chunks. The workgroup stages its range blocks in LDS;
+// thread (range q, isometry t) keeps row[m] = R[iso_src(inverse(t), m)] in
+// registers as packed bytes, so that <row, d'> = <R, T_t(d')>. With IT
+// isometries per thread, thread j of a range takes t = j, j + 8 / IT, ...
 //  kModeSmall: at most kSmallMax contrast values. For each value k > 0 the
 //    thread keeps the smallest G = k A' - 80 B' (F = k G), in 32-bit integers
 //    for B <= 4; k = 0 gives F = 0 everywhere, so its best is the first domain.
@@ -937,7 +961,9 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
     using Tl = MatchTile<B>;
     using BpT = typename Tl::BpT;
     using GT = typename Tl::GT;
-    constexpr int n = Tl::n, NW = Tl::NW, TN = Tl::TN, RPB = kBlock / 8;
+    constexpr int n = Tl::n, NW = Tl::NW, TN = Tl::TN;
+    constexpr int IT = match_isos_per_thread(B, MODE), TPR = 8 / IT;
+    constexpr int RPB = match_ranges_per_block(B, MODE);
     constexpr int NKA = MODE == kModeSmall ? kSmallMax : 1;
     // small sets at B <= 4: per domain (S, k0 A', k1 A') in one 16-byte record
     constexpr bool kFast = MODE == kModeSmall && B <= 4;
@@ -967,13 +993,14 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
         sR[e] = v;
     }
     __syncthreads();
-    const int lq = threadIdx.x >> 3, t = threadIdx.x & 7, q = q0 + lq;
+    const int lq = threadIdx.x / TPR, tsub = threadIdx.x % TPR, q = q0 + lq;
     const bool valid = q < nact;
     const uint8_t* rr = sR + lq * n;
-    uint32_t r[NW];
-    {
+    uint32_t rI[IT][NW];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
         // T_u is affine in (i, c): source index = a0 + a1 i + a2 c
-        const int u = iso_inverse(t);
+        const int u = iso_inverse(tsub + it * TPR);
         const int a0 = iso_src(B, u, 0, 0);
         const int a1 = iso_src(B, u, 1, 0) - a0, a2 = iso_src(B, u, 0, 1) - a0;
 #pragma unroll
@@ -984,9 +1011,10 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
                 const int m = 4 * w + b;
                 v |= (uint32_t)rr[a0 + a1 * (m / B) + a2 * (m % B)] << (8 * b);
             }
-            r[w] = v;
+            rI[it][w] = v;
         }
     }
+    uint32_t* r = rI[0];
     // sum r and sum r^2 (the same for every isometry)
     uint32_t srum = 0, sq = 0;
 #pragma unroll
@@ -994,7 +1022,7 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
         srum = __builtin_amdgcn_udot4(r[w], 0x01010101u, srum, false);
         sq = __builtin_amdgcn_udot4(r[w], r[w], sq, false);
     }
-    if (valid && t == 0 && c == 0) {
+    if (valid && tsub == 0 && c == 0) {
         SRout[q] = (int32_t)srum;
         CRout[q] = (int64_t)n * sq - (int64_t)srum * srum;
     }
@@ -1002,14 +1030,16 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
     const int lo = (int)((int64_t)P * c / nca);
     const int hi = (int)((int64_t)P * (c + 1) / nca);
 
-    // kModeSmall state
-    GT bestG[kSmallMax];
-    int bestPs[kSmallMax];
+    // kModeSmall state, per isometry of the thread
+    GT bestG[IT][kSmallMax];
+    int bestPs[IT][kSmallMax];
 #pragma unroll
-    for (int u = 0; u < kSmallMax; ++u) {
-        bestG[u] = std::numeric_limits<GT>::max();
-        bestPs[u] = lo;  // k = 0: every domain ties, the first one wins
-    }
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int u = 0; u < kSmallMax; ++u) {
+            bestG[it][u] = std::numeric_limits<GT>::max();
+            bestPs[it][u] = lo;  // k = 0: every domain ties, the first one wins
+        }
     // other modes
     int64_t bestF = INT64_MAX;
     int bestP = -1, bestS = 0;
@@ -1065,40 +1095,61 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
                 // G_u = k_u A' + 80 sum_i d'_i (sum r - 4 r_i): the weights sum r - 4 r_i
                 // lie in [-765, 765], so two v_dot2_i32_i16 give the sum exactly, and
                 // |sum + p| < 2^22 leaves one 24-bit multiply-add for G
-                const uint32_t rw = r[0];
-                const int r0 = rw & 0xff, r1 = (rw >> 8) & 0xff, r2 = (rw >> 16) & 0xff, r3 = rw >> 24;
-                const int sr4 = r0 + r1 + r2 + r3;
-                const uint32_t w01 = (uint32_t)(uint16_t)(sr4 - 4 * r0) | ((uint32_t)(uint16_t)(sr4 - 4 * r1) << 16);
-                const uint32_t w23 = (uint32_t)(uint16_t)(sr4 - 4 * r2) | ((uint32_t)(uint16_t)(sr4 - 4 * r3) << 16);
-                if (use0 && use1) match_b2_loop<true>(sRec, sE1, cnt, w01, w23, bestG[0], bestPs[0], bestG[1], bestPs[1]);
-                else if (use0) match_b2_loop<false>(sRec, sE1, cnt, w01, w23, bestG[0], bestPs[0], bestG[1], bestPs[1]);
-                else if (use1) match_b2_loop<false>(sRec, sE1, cnt, w01, w23, bestG[1], bestPs[1], bestG[0], bestPs[0]);
+                uint32_t w01[IT], w23[IT];
+                int g0[IT], p0[IT], g1[IT], p1[IT];
+#pragma unroll
+                for (int it = 0; it < IT; ++it) {
+                    const uint32_t rw = rI[it][0];
+                    const int r0 = rw & 0xff, r1 = (rw >> 8) & 0xff, r2 = (rw >> 16) & 0xff, r3 = rw >> 24;
+                    const int sr4 = r0 + r1 + r2 + r3;
+                    w01[it] = (uint32_t)(uint16_t)(sr4 - 4 * r0) | ((uint32_t)(uint16_t)(sr4 - 4 * r1) << 16);
+                    w23[it] = (uint32_t)(uint16_t)(sr4 - 4 * r2) | ((uint32_t)(uint16_t)(sr4 - 4 * r3) << 16);
+                    // the slot of the first value in use comes first
+                    const int f = use0 ? 0 : 1;
+                    g0[it] = bestG[it][f];
+                    p0[it] = bestPs[it][f];
+                    g1[it] = bestG[it][1 - f];
+                    p1[it] = bestPs[it][1 - f];
+                }
+                if (use0 && use1) match_b2_loop<IT, true>(sRec, sE1, cnt, w01, w23, g0, p0, g1, p1);
+                else if (use0 || use1) match_b2_loop<IT, false>(sRec, sE1, cnt, w01, w23, g0, p0, g1, p1);
+#pragma unroll
+                for (int it = 0; it < IT; ++it) {
+                    const int f = use0 ? 0 : 1;
+                    bestG[it][f] = g0[it];
+                    bestPs[it][f] = p0[it];
+                    bestG[it][1 - f] = g1[it];
+                    bestPs[it][1 - f] = p1[it];
+                }
                 continue;
             }
-#pragma unroll 4
+#pragma unroll 2
             for (int d = 0; d < cnt; ++d) {
                 const uint32_t* hl = sHL + d * 2 * NW;
-                uint32_t ph = 0, pl = 0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    ph = __builtin_amdgcn_udot4(r[w], hl[w], ph, false);
-                    pl = __builtin_amdgcn_udot4(r[w], hl[NW + w], pl, false);
-                }
                 const int4 rec = sRec[d];
                 const uint32_t cs = (uint32_t)__mul24(c1, rec.x);
-                const uint32_t pt = (uint32_t)__mul24(kPh, (int)ph) + (uint32_t)__mul24(kPl, (int)pl);
                 const int dd = base + d;
-                if (use0) {
-                    const int g = (int)((uint32_t)rec.y + cs - pt);
-                    const bool lt = g < bestG[0];
-                    bestG[0] = lt ? g : bestG[0];
-                    bestPs[0] = lt ? dd : bestPs[0];
-                }
-                if (use1) {
-                    const int g = (int)((uint32_t)rec.z + cs - pt);
-                    const bool lt = g < bestG[1];
-                    bestG[1] = lt ? g : bestG[1];
-                    bestPs[1] = lt ? dd : bestPs[1];
+#pragma unroll
+                for (int it = 0; it < IT; ++it) {
+                    uint32_t ph = 0, pl = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        ph = __builtin_amdgcn_udot4(rI[it][w], hl[w], ph, false);
+                        pl = __builtin_amdgcn_udot4(rI[it][w], hl[NW + w], pl, false);
+                    }
+                    const uint32_t pt = (uint32_t)__mul24(kPh, (int)ph) + (uint32_t)__mul24(kPl, (int)pl);
+                    if (use0) {
+                        const int g = (int)((uint32_t)rec.y + cs - pt);
+                        const bool lt = g < bestG[it][0];
+                        bestG[it][0] = lt ? g : bestG[it][0];
+                        bestPs[it][0] = lt ? dd : bestPs[it][0];
+                    }
+                    if (use1) {
+                        const int g = (int)((uint32_t)rec.z + cs - pt);
+                        const bool lt = g < bestG[it][1];
+                        bestG[it][1] = lt ? g : bestG[it][1];
+                        bestPs[it][1] = lt ? dd : bestPs[it][1];
+                    }
                 }
             }
             continue;
@@ -1119,9 +1170,9 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
                 for (int u = 0; u < kSmallMax; ++u) {
                     if (u < ks.n && ks.k[u] != 0) {
                         const GT g = sKA[u][d] - b80;
-                        if (g < bestG[u]) {
-                            bestG[u] = g;
-                            bestPs[u] = base + d;
+                        if (g < bestG[0][u]) {
+                            bestG[0][u] = g;
+                            bestPs[0][u] = base + d;
                         }
                     }
                 }
@@ -1142,26 +1193,28 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
     if (lo < hi) {
         if (MODE == kModeSmall) {
 #pragma unroll
-            for (int u = 0; u < kSmallMax; ++u) {
-                if (u >= ks.n) continue;
-                const int k = ks.k[u];
-                if (k != 0 && bestG[u] == std::numeric_limits<GT>::max()) continue;
-                const int64_t F = k == 0 ? 0 : (int64_t)k * (int64_t)bestG[u];
-                const int p = bestPs[u];
-                const int64_t K = make_key(Jd[p], t, u, Sd[p]);
-                if (pair_less(F, K, outF, outK)) {
-                    outF = F;
-                    outK = K;
+            for (int it = 0; it < IT; ++it)
+#pragma unroll
+                for (int u = 0; u < kSmallMax; ++u) {
+                    if (u >= ks.n) continue;
+                    const int k = ks.k[u];
+                    if (k != 0 && bestG[it][u] == std::numeric_limits<GT>::max()) continue;
+                    const int64_t F = k == 0 ? 0 : (int64_t)k * (int64_t)bestG[it][u];
+                    const int p = bestPs[it][u];
+                    const int64_t K = make_key(Jd[p], tsub + it * TPR, u, Sd[p]);
+                    if (pair_less(F, K, outF, outK)) {
+                        outF = F;
+                        outK = K;
+                    }
                 }
-            }
         } else if (bestP >= 0) {
             outF = bestF;
-            outK = make_key(Jd[bestP], t, bestS, Sd[bestP]);
+            outK = make_key(Jd[bestP], tsub, bestS, Sd[bestP]);
         }
     }
-    // reduce the 8 isometry rows of each range (8 consecutive lanes)
+    // reduce over the TPR consecutive lanes of each range
 #pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
+    for (int m = 1; m < TPR; m <<= 1) {
         const int64_t of = __shfl_xor(outF, m, 64);
         const int64_t ok = __shfl_xor(outK, m, 64);
         if (pair_less(of, ok, outF, outK)) {
@@ -1169,7 +1222,7 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
             outK = ok;
         }
     }
-    if (valid && t == 0) {
+    if (valid && tsub == 0) {
         Partial pr;
         pr.F = outF;
         pr.key = outK;

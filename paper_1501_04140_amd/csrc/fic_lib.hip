@@ -276,6 +276,11 @@ int check_kset(const int8_t* k, int n, KSet* ks) {
 
 bool valid_B(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
 
+// Matcher mode for a contrast set (kt_match's MODE).
+int match_mode(const KSet& ks) {
+    return ks.n <= kSmallMax ? kModeSmall : (ks.consecutive ? kModeGrid : kModeList);
+}
+
 // ---------------------------------------------------------------- one level
 // Matcher selected for a level (fic_encode_level_ex's variant).
 enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3 };
@@ -316,7 +321,9 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
     v.cg = cg > 0 ? cg : default_cg(B, v.var);
     // enough workgroups to fill the chip when the pool is large, at most one
     // chunk per cg domains and 64 chunks
-    const int rows_per_block = v.var == kVarMfma ? kM8Rows : kBlock;
+    const int rows_per_block = v.var == kVarMfma ? kM8Rows
+                               : v.var == kVarFp32 ? kBlock
+                                                   : 8 * match_ranges_per_block(B, match_mode(ks));
     const int row_blocks = cdiv((int64_t)8 * max_act, rows_per_block);
     int nc = cdiv(2048, row_blocks);
     nc = std::max(1, std::min(nc, 64));
@@ -523,16 +530,16 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
         kt_match_mfma8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n), kM8Waves * 64, 0, st>>>(h[0], dt);
         return;
     }
-    const dim3 grid(cdiv(max_act, kBlock / 8), max_nc, n);
     if (B == 8 && a0.var == kVarFp32) {
         ProfScope ps("match_b8_fp32", st);
-        kt_match_fp32<TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
+        kt_match_fp32<TAB><<<dim3(cdiv(max_act, kBlock / 8), max_nc, n), kBlock, 0, st>>>(h[0], dt);
         return;
     }
     ProfScope ps(match_label(B), st);
-    const KSet& ks = a0.ks;
-    if (ks.n <= kSmallMax) kt_match<B, kModeSmall, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
-    else if (ks.consecutive) kt_match<B, kModeGrid, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
+    const int mode = match_mode(a0.ks);
+    const dim3 grid(cdiv(max_act, match_ranges_per_block(B, mode)), max_nc, n);
+    if (mode == kModeSmall) kt_match<B, kModeSmall, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
+    else if (mode == kModeGrid) kt_match<B, kModeGrid, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
     else kt_match<B, kModeList, TAB><<<grid, kBlock, 0, st>>>(h[0], dt);
 }
 
