@@ -151,15 +151,17 @@ enum fic_match_variant {
     FIC_MATCH_AUTO = 0,     /* the library's choice (what fic_encode_level uses)          */
     FIC_MATCH_VALU = 1,     /* dot4 correlation, exact 32/64-bit integer epilogue        */
     FIC_MATCH_MFMA_I8 = 2,  /* int8 MFMA correlation (hi/lo split of the 2x2 sums),      */
-                            /* FP32 screen with a proven margin, exact int64 rescoring   */
+                            /* screen by the continuous bound of F, exact int64 decision */
     FIC_MATCH_FP32 = 3      /* FP32 FMA correlation and FP32 E, no exact rescoring: a    */
                             /* comparator whose result may differ from the exact search  */
 };
 
 /*
  * fic_encode_level with an explicit matcher. FIC_MATCH_MFMA_I8 and
- * FIC_MATCH_FP32 need B = 8 and a contrast set 0, 1, ..., k1 with k1 >= 2
- * (FIC_EINVAL otherwise). VALU, MFMA_I8 and AUTO return the exact result.
+ * FIC_MATCH_FP32 need B = 8 and a contrast set 0, 1, ..., k1 with k1 >= 2;
+ * MFMA_I8 also needs a domain grid of fewer than 2^22 domains (FIC_EINVAL
+ * otherwise; AUTO then takes the VALU matcher). VALU, MFMA_I8 and AUTO return
+ * the exact result.
  * FP32 returns its own FP32 argmin with its FP32 E in `E` and, in e_num, the
  * exact 1600 n E of the candidate it chose.
  */

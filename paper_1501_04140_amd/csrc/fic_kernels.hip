@@ -1525,6 +1525,9 @@ constexpr int kM8Rows = kM8Waves * 16 * kM8RowTiles;   // 128 rows = 16 ranges x
 constexpr int kM8ColTiles = 4;                         // 16-column tiles per LDS stage
 constexpr int kM8Cols = 16 * kM8ColTiles;              // 64 pool domains per LDS stage
 constexpr int kM8Chunk = 1024;                         // target pool domains per chunk
+// (1 - 2^-18): a factor that puts an FP32 square root or product (a few ulps
+// of error each) safely below the exact real value.
+constexpr float kM8Shrink = 1.0f - 1.0f / 262144.0f;
 
 // Rows r' = r - 128 of the 8 inverse-isometry arrangements of each range:
 // Ar[(8q + t) * 64 + m] = R[iso_src(8, inverse(t), m)] - 128. Thread per row.
@@ -1580,9 +1583,10 @@ __device__ __forceinline__ void k_range_prep_i8_body(const uint8_t* __restrict__
     }
 }
 
-// Columns for the int8 matcher: h and l rows of each pool domain, and
-// G = 40 / A' (0 for a constant domain) and A' in FP32 for the screen. Four
-// lanes share a domain, 16 decimated values each.
+// Columns for the int8 matcher: h and l rows of each pool domain, and in
+// FP32 G = 40 / A' (0 for a constant domain) and Q = sqrt(A') (1 - 2^-18),
+// rounded below sqrt(A') for the screen. Four lanes share a domain, 16
+// decimated values each.
 __device__ __forceinline__ void k_pool_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
                                                          int L, int gx, const int32_t* __restrict__ pool,
                                                          int identity_total, Ctrl* ctrl,
@@ -1635,7 +1639,7 @@ __device__ __forceinline__ void k_pool_prep_i8_body(const uint8_t* __restrict__ 
         Ad[p] = A;
         Jd[p] = j;
         Gd[p] = A > 0 ? 40.0f / (float)A : 0.0f;
-        Af[p] = (float)A;
+        Af[p] = sqrtf((float)A) * kM8Shrink;
     }
 }
 
@@ -1658,31 +1662,79 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
     }
 }
 
-// grid: x = workgroups of 256 rows, y = pool chunks. The contrast set is
+// grid: x = workgroups of kM8Rows rows, y = pool chunks. The contrast set is
 // k = 0..k1. Each wavefront keeps 32 rows; each lane holds 4 rows x 1 column
-// of every 16x16 output tile. Per element the screen evaluates
-//   F~ = k~ (k~ A' - 80 B'),  k~ = clamp(rint(40 B' / A'), 0, k1)
-// in FP32 from the exact integer B'. For n = 64, |F~ - F(k~)| <= 2.4e5 (five
-// roundings of values below 2^40) and F(k~) - F(k*) <= 6e3 (k~ can only be off
-// by one next to a half-integer), so F* >= F~ - 2.5e5. The row threshold is
-// F~(best) + kM8ScreenMargin >= F_best + 7.5e5, and an element with F~ at or
-// above it has F* > F_best: it cannot win or tie and is skipped. The others are
-// decided exactly in int64 (the FP32 k corrected by one step). The 16 lanes of
-// a row share their thresholds every kM8Share stages.
-constexpr float kM8ScreenMargin = 1.0e6f;
-constexpr int kM8Share = 4;
+// of every 16x16 output tile.
+// Screen: for any k, F = k^2 A' - 80 k B' is at least the continuous minimum
+// -1600 B'^2 / A', so an element can match or beat a row's best F_b <= 0 only
+// if B' >= s_b sqrt(A'), s_b = sqrt(-F_b / 1600). A lane takes the smallest
+// s_b of its 4 rows (they share the column) and a threshold T rounded below
+// s_b sqrt(A') (both factors shrunk by kM8Shrink, truncated to an integer, at
+// least 1 since F < 0 needs B' > 0); with B' = 64 X + toff this is one integer
+// bound U on the MFMA output X: per element, one compare. The bound is not
+// strict, so ties stay candidates.
+// Candidates go to a per-wavefront queue in LDS and are decided exactly in
+// int64 64 at a time, one per lane (the FP32 k corrected by one step). Each
+// row's best is one packed word (F + 2^37) << 26 | position << 4 | k, which
+// orders as (F, key) does within a row (0 >= F >= -1600 C > -2^37 for n = 64,
+// positions below kM8MaxPool); lanes lower it with an LDS atomic minimum, and
+// every lane of a row reads its bound back from it.
+constexpr int kM8Queue = 64 + 4 * 64;  // a flush at 64 entries, then up to one tile's 256
+constexpr int kM8MaxPool = 1 << 22;    // pool positions the packed best can hold
+
+__device__ inline uint64_t m8_pack(int64_t F, int pos, int k) {
+    return ((uint64_t)(F + (1ll << 37)) << 26) | ((uint64_t)pos << 4) | (uint64_t)k;
+}
+
+__device__ inline int64_t m8_unpack_F(uint64_t v) { return (int64_t)(v >> 26) - (1ll << 37); }
+
+// s_b of a packed best, rounded below the exact value.
+__device__ inline float m8_sigma(uint64_t v) {
+    const int64_t F = m8_unpack_F(v);
+    return F < 0 ? sqrtf((float)(-F) * (1.0f / 1600.0f)) * kM8Shrink : 0.0f;
+}
+
+// Exact decision of the wavefront's queued candidates (entry: row | position
+// << 5, X), one per lane, then the lane's row bounds re-read.
+__device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint64_t* best,
+                                const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
+                                const float* __restrict__ Gd, int k1, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int i = lane; i < n; i += 64) {
+        const uint2 en = q[i];
+        const int row = (int)(en.x & 31u), pos = (int)(en.x >> 5), X = (int)en.y;
+        const int64_t Ap = Ad[pos];
+        const int bi = (X << 6) + nsr[row] * (int)Sd[pos];  // B' = 64 X - sum r' S, exact
+        const int64_t Bp = bi, b80 = 80 * Bp;
+        int k = (int)__builtin_amdgcn_fmed3f(rintf((float)bi * Gd[pos]), 0.0f, (float)k1);
+        if (Ap <= 0) k = 0;
+        else if (k > 0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
+        else if (k < k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
+        const int64_t F = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
+        if (F <= 0) atomicMin(reinterpret_cast<unsigned long long*>(best + row),
+                              (unsigned long long)m8_pack(F, pos, k));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 __device__ __forceinline__ void k_match_mfma8_body(
     const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int32_t* act_count,
     const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
-    const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Af,
+    const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Qd,
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
     Partial* __restrict__ part, int cg) {
+    static_assert(kM8RowTiles == 2, "32 rows per wavefront");
     __shared__ v4i sH[kM8Cols * 4];  // column c, K-group g at [c * 4 + g]
     __shared__ v4i sL[kM8Cols * 4];
-    __shared__ float sG[kM8Cols], sAf[kM8Cols];
-    __shared__ int32_t sS[kM8Cols];
-    __shared__ int64_t sA[kM8Cols];
+    __shared__ float sQ[kM8Cols];
+    __shared__ int32_t sS[kM8Cols], sTm[kM8Cols];
+    __shared__ uint2 sQueue[kM8Waves][kM8Queue];
+    __shared__ uint64_t sBest[kM8Waves][32];
+    __shared__ int32_t sNsr[kM8Waves][32];
 
     const int nrows = 8 * *act_count;
     const int row_blk = blockIdx.x * kM8Rows;
@@ -1695,13 +1747,13 @@ __device__ __forceinline__ void k_match_mfma8_body(
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int wrow0 = row_blk + wave * 16 * kM8RowTiles;
-    const float kmax = (float)k1;
+    uint2* queue = sQueue[wave];
+    uint64_t* best = sBest[wave];
+    int32_t* nsr = sNsr[wave];
 
     v4i a[kM8RowTiles];
     int nsrp[kM8RowTiles];  // -sum r' of the lane's output range, per row tile
-    int64_t bestF[kM8RowTiles][4];
-    int bestPK[kM8RowTiles][4];
-    float thr[kM8RowTiles][4];
+    float sigm[kM8RowTiles];
 #pragma unroll
     for (int rt = 0; rt < kM8RowTiles; ++rt) {
         const int arow = wrow0 + 16 * rt + c16;
@@ -1709,16 +1761,17 @@ __device__ __forceinline__ void k_match_mfma8_body(
         a[rt] = arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 16 * g) : z;
         const int orow = wrow0 + 16 * rt + 4 * g;
         nsrp[rt] = orow < nrows ? -SRp[orow >> 3] : 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            bestF[rt][e] = 0;          // k = 0 gives F = 0 for every domain;
-            bestPK[rt][e] = lo * 16;   // its smallest key is the chunk's first domain
-            thr[rt][e] = kM8ScreenMargin;
-        }
+        sigm[rt] = 0.0f;
     }
+    if (lane < 32) {
+        // k = 0 gives F = 0 for every domain; its smallest key is the chunk's first domain
+        best[lane] = m8_pack(0, lo, 0);
+        const int r = wrow0 + lane;
+        nsr[lane] = r < nrows ? -SRp[r >> 3] : 0;
+    }
+    int qn = 0;  // queued candidates (the same in every lane)
 
-    int stage = 0;
-    for (int base = lo; base < hi; base += kM8Cols, ++stage) {
+    for (int base = lo; base < hi; base += kM8Cols) {
         const int cnt = min(kM8Cols, hi - base);
         __syncthreads();
         for (int idx = threadIdx.x; idx < 2 * kM8Cols * 4; idx += kM8Waves * 64) {
@@ -1735,11 +1788,10 @@ __device__ __forceinline__ void k_match_mfma8_body(
         if (threadIdx.x < kM8Cols) {
             const int col = threadIdx.x;
             const bool ok = col < cnt;
-            // a padded column gets g = 0 and A'f = 1e30: F~ = 0 * ... = huge, never a candidate
-            sG[col] = ok ? Gd[base + col] : 0.0f;
-            sAf[col] = ok ? Af[base + col] : 1.0e30f;
+            // a padded column gets the bound 2^30 > |B'|: never a candidate
+            sQ[col] = ok ? Qd[base + col] : 0.0f;
+            sTm[col] = ok ? 1 : (1 << 30);
             sS[col] = ok ? (int32_t)Sd[base + col] : 0;
-            sA[col] = ok ? Ad[base + col] : 0;
         }
         __syncthreads();
         v4i bh[kM8ColTiles], bl[kM8ColTiles];
@@ -1764,80 +1816,67 @@ __device__ __forceinline__ void k_match_mfma8_body(
 #pragma unroll
         for (int ct = 0; ct < kM8ColTiles; ++ct) {
             const int col = 16 * ct + c16;
-            const float gj = sG[col], aj = sAf[col];
-            const int sj = sS[col];
+            const float qj = sQ[col];
+            const int sj = sS[col], tmj = sTm[col];
 #pragma unroll
             for (int rt = 0; rt < kM8RowTiles; ++rt) {
                 const int toff = __mul24(nsrp[rt], sj);  // -sum r' * S (24-bit operands)
-                int bi[4];
-                float kk[4], ft[4];
+                // B' >= T for every element that can match or beat the lane's rows
+                const int T = max((int)fminf(sigm[rt] * qj, 1.0e9f), tmj);
+                const int U = (T - toff + 63) >> 6;      // 64 X + toff >= T  <=>  X >= U
                 bool cand[4];
+                uint64_t m[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    bi[e] = (acc[rt][ct][e] << 6) + toff;  // B' = 64 X - sum r' S, exact
-                    const float bf = (float)bi[e];
-                    kk[e] = __builtin_amdgcn_fmed3f(rintf(bf * gj), 0.0f, kmax);
-                    ft[e] = kk[e] * fmaf(kk[e], aj, -80.0f * bf);
-                    cand[e] = ft[e] < thr[rt][e];
+                    cand[e] = acc[rt][ct][e] >= U;
+                    m[e] = __ballot(cand[e]);
                 }
-                if (__any(cand[0] | cand[1] | cand[2] | cand[3])) {
+                if (m[0] | m[1] | m[2] | m[3]) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        if (cand[e]) {
-                            // exact: the FP32 k is within one of the minimiser
-                            const int64_t Bp = bi[e];
-                            const int64_t Ap = sA[col];
-                            const int64_t b80 = 80 * Bp;
-                            int k = (int)kk[e];
-                            if (Ap <= 0) k = 0;
-                            else if (k > 0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
-                            else if (k < k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
-                            const int64_t F = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
-                            if (F < bestF[rt][e]) {
-                                bestF[rt][e] = F;
-                                bestPK[rt][e] = (base + col) * 16 + k;
-                                thr[rt][e] = fminf(thr[rt][e], ft[e] + kM8ScreenMargin);
-                            }
+                        if (m[e]) {
+                            const int slot = qn + __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
+                            if (cand[e])
+                                queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
+                                                             ((uint32_t)(base + col) << 5),
+                                                         (uint32_t)acc[rt][ct][e]);
+                            qn += __popcll(m[e]);
+                        }
+                    }
+                    if (qn >= 64) {
+                        m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
+                        qn = 0;
+#pragma unroll
+                        for (int r2 = 0; r2 < kM8RowTiles; ++r2) {
+                            const uint64_t* bb = best + 16 * r2 + 4 * g;
+                            sigm[r2] = fminf(fminf(m8_sigma(bb[0]), m8_sigma(bb[1])),
+                                             fminf(m8_sigma(bb[2]), m8_sigma(bb[3])));
                         }
                     }
                 }
             }
         }
-        if ((stage % kM8Share) == kM8Share - 1) {
-            // the 16 lanes of a row (same g) share the smallest threshold
-#pragma unroll
-            for (int rt = 0; rt < kM8RowTiles; ++rt)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    float t = thr[rt][e];
-                    t = fminf(t, __shfl_xor(t, 1, 64));
-                    t = fminf(t, __shfl_xor(t, 2, 64));
-                    t = fminf(t, __shfl_xor(t, 4, 64));
-                    t = fminf(t, __shfl_xor(t, 8, 64));
-                    thr[rt][e] = t;
-                }
-        }
     }
-    // per range: 4 rows per lane, 16 lanes per row, 2 lane groups per range
+    if (qn > 0) m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
+    // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
 #pragma unroll
     for (int rt = 0; rt < kM8RowTiles; ++rt) {
         const int orow = wrow0 + 16 * rt + 4 * g;
         int64_t F = INT64_MAX, K = INT64_MAX;
-        if (lo < hi && orow < nrows) {
+        if (lo < hi && orow < nrows && c16 == 0) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int p = bestPK[rt][e] >> 4, k = bestPK[rt][e] & 15;
-                const int64_t key = make_key(Jd[p], (orow + e) & 7, k, Sd[p]);
-                if (pair_less(bestF[rt][e], key, F, K)) {
-                    F = bestF[rt][e];
+                const uint64_t v = best[16 * rt + 4 * g + e];
+                const int pos = (int)((v >> 4) & (uint64_t)(kM8MaxPool - 1)), k = (int)(v & 15u);
+                const int64_t Fe = m8_unpack_F(v);
+                const int64_t key = make_key(Jd[pos], (orow + e) & 7, k, Sd[pos]);
+                if (pair_less(Fe, key, F, K)) {
+                    F = Fe;
                     K = key;
                 }
             }
         }
-        lex_min_shfl(F, K, 1);
-        lex_min_shfl(F, K, 2);
-        lex_min_shfl(F, K, 4);
-        lex_min_shfl(F, K, 8);
         lex_min_shfl(F, K, 16);
         if (c16 == 0 && (g & 1) == 0 && orow < nrows) {
             Partial pr;

@@ -285,9 +285,10 @@ int match_mode(const KSet& ks) {
 // Matcher selected for a level (fic_encode_level_ex's variant).
 enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3 };
 
-// The int8 MFMA matcher serves B = 8 with a contrast grid 0..k1 (k1 >= 2).
-bool mfma_eligible(int B, const KSet& ks) {
-    return B == 8 && ks.consecutive && ks.k0 == 0 && ks.n >= 3;
+// The int8 MFMA matcher serves B = 8 with a contrast grid 0..k1 (k1 >= 2) on
+// domain grids it can index (fewer than kM8MaxPool domains).
+bool mfma_eligible(int B, const KSet& ks, int64_t total = 0) {
+    return B == 8 && ks.consecutive && ks.k0 == 0 && ks.n >= 3 && total < kM8MaxPool;
 }
 
 // Host plan of one level of one image.
@@ -309,7 +310,9 @@ int default_cg(int B, int var) {
 Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks, int variant = 0,
                  int cg = 0) {
     Level v;
-    v.var = variant != 0 ? variant : (mfma_eligible(B, ks) ? kVarMfma : kVarValu);
+    v.var = variant != 0 ? variant
+                         : (mfma_eligible(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1))
+                                ? kVarMfma : kVarValu);
     v.lv = lv;
     v.B = B;
     v.L = L;
@@ -837,6 +840,9 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     if ((variant == FIC_MATCH_MFMA_I8 || variant == FIC_MATCH_FP32) && !mfma_eligible(B, ks))
         return fail(FIC_EINVAL, "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2)",
                     variant);
+    if (variant == FIC_MATCH_MFMA_I8 &&
+        !mfma_eligible(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1)))
+        return fail(FIC_EINVAL, "the int8 MFMA matcher takes domain grids below %d domains", kM8MaxPool);
     if (n_ranges == 0) return FIC_OK;
     Workspace* ws;
     if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
