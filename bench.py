@@ -551,23 +551,35 @@ def run_level(args, torch, which):
         fic.encode_level(x, B, L, ks)
     torch.cuda.synchronize()
     prof = fic.profile_end()
+    # MFMA forms: the correlation's 2n ops per match are the contraction (the int8
+    # form's hi/lo split issues it twice; the FP16 form once, at half the int8 peak)
+    mfma_ops = {f"match_b{B}_mfma": (matches * 2 * B * B, "mfma", PEAK_INT8_TOPS, "TOP/s"),
+                f"match_b{B}_mfma16": (matches * 2 * B * B, "mfma", PEAK_FP16_TFLOPS, "TFLOP/s")}
     roof = roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")},
-                                 {f"match_b{B}": matches * match_ops(B * B, 1),
-                                  # int8 MFMA form: the correlation's 2n ops per match are the
-                                  # contraction; the hi/lo split issues it twice
-                                  f"match_b{B}_mfma": (matches * 2 * B * B, "mfma", PEAK_INT8_TOPS,
-                                                       "TOP/s")})
+                                 {f"match_b{B}": matches * match_ops(B * B, 1), **mfma_ops})
     roof = with_traffic(roof, which)
     res = {
         "metric": "matches/s (range×domain×isometry)",
-        "dtype": ("u8 -> int8 MFMA (hi/lo split), i32 accumulate, i64 exact" if which == "precision1024"
-                  else "u8 dot4 -> i32, i64 exact"),
+        "dtype": ("u8 -> fp16 MFMA (exact: integer partial sums below 2^24), f32 accumulate, i64 exact"
+                  if which == "precision1024" else "u8 dot4 -> i32, i64 exact"),
         "value": matches / (ms / 1e3), "unit": "matches/s", "encode_ms": ms,
         "encode_ms_wall": wall_ms, "step_ms_spread": spread, "matches_per_step": matches,
         "config": {"workload": desc}, "roofline": roof,
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()},
     }
     if which == "precision1024":
+        # the int8 MFMA form (hi/lo split) on the same input: time and roofline
+        i8 = lambda: fic.encode_level(x, B, L, ks, variant=fic.MATCH_MFMA_I8)
+        i8_ms, _ = time_steps(i8, args.steps, args.warmup, torch)
+        fic.profile_begin()
+        for _ in range(args.steps):
+            i8()
+        torch.cuda.synchronize()
+        prof8 = fic.profile_end()
+        roof8 = roofline_from_profile({k: v for k, v in prof8.items() if k.startswith("match")}, mfma_ops)
+        res["int8_mfma_form"] = {"ms": i8_ms, "matches_per_s": matches / (i8_ms / 1e3),
+                                 "roofline": with_traffic(roof8, which),
+                                 "dtype": "u8 -> int8 MFMA (hi/lo split), i32 accumulate, i64 exact"}
         # the FP32-FMA comparator on the same input against the exact int8-MFMA result
         import numpy as np
         exact = fic.matches_numpy(fic.encode_level(x, B, L, ks, variant=fic.MATCH_MFMA_I8))

@@ -152,16 +152,19 @@ enum fic_match_variant {
     FIC_MATCH_VALU = 1,     /* dot4 correlation, exact 32/64-bit integer epilogue        */
     FIC_MATCH_MFMA_I8 = 2,  /* int8 MFMA correlation (hi/lo split of the 2x2 sums),      */
                             /* screen by the continuous bound of F, exact int64 decision */
-    FIC_MATCH_FP32 = 3      /* FP32 FMA correlation and FP32 E, no exact rescoring: a    */
+    FIC_MATCH_FP32 = 3,     /* FP32 FMA correlation and FP32 E, no exact rescoring: a    */
                             /* comparator whose result may differ from the exact search  */
+    FIC_MATCH_MFMA_F16 = 4  /* FP16 MFMA correlation, FP32 accumulation (exact at B = 8:*/
+                            /* every partial sum is an integer below 2^24), same screen  */
+                            /* and exact decision as MFMA_I8; AUTO takes it at B = 8     */
 };
 
 /*
- * fic_encode_level with an explicit matcher. FIC_MATCH_MFMA_I8 and
+ * fic_encode_level with an explicit matcher. FIC_MATCH_MFMA_I8, MFMA_F16 and
  * FIC_MATCH_FP32 need B = 8 and a contrast set 0, 1, ..., k1 with k1 >= 2;
- * MFMA_I8 also needs a domain grid of fewer than 2^22 domains (FIC_EINVAL
- * otherwise; AUTO then takes the VALU matcher). VALU, MFMA_I8 and AUTO return
- * the exact result.
+ * the MFMA matchers also need a domain grid of fewer than 2^22 domains
+ * (FIC_EINVAL otherwise; AUTO then takes the VALU matcher). VALU, MFMA_I8,
+ * MFMA_F16 and AUTO return the exact result.
  * FP32 returns its own FP32 argmin with its FP32 E in `E` and, in e_num, the
  * exact 1600 n E of the candidate it chose.
  */

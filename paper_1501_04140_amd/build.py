@@ -27,6 +27,10 @@ def build(verbose: bool = False) -> str:
            "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
            # packed FP32 instructions are kept out of every kernel
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # MFMA accumulators in VGPRs: the matchers' epilogues read and rescale
+           # them with plain VALU instructions, without AGPR copies
+           "-mllvm", "-amdgpu-mfma-vgpr-form",
+
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-o", tmp, os.path.join(CSRC, "fic_lib.hip")]
     if verbose:

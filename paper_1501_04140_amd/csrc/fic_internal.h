@@ -48,6 +48,10 @@ struct Partial {
 // Arguments of the quadtree kernels for one image at one level. Kernels read
 // tab[blockIdx.z]: a table of one for a single image, one entry per image for
 // a batch.
+// Matcher of a level: dot4 VALU, int8 MFMA (hi/lo split), FP32 comparator,
+// FP16 MFMA (exact for B = 8).
+enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3, kVarMfma16 = 4 };
+
 struct Lvl {
     const uint8_t* img;
     int32_t pitch, H, W;
@@ -58,7 +62,7 @@ struct Lvl {
     int32_t min_pool, rank;       // entropy floor: pool size wanted, min(min_pool, total)
     int32_t sel_shift, bound_chunk;
     int32_t capacity;
-    int32_t var;                  // matcher: 1 dot4 VALU, 2 int8 MFMA, 3 FP32 comparator
+    int32_t var;                  // matcher: kVarValu, kVarMfma, kVarFp32 or kVarMfma16
     int32_t pmode;                // pool filter: 0 none, 1 entropy, 2 variance
     int64_t M;                    // filter cut (keep iff key < M)
     int64_t kv;                   // variance filter: key = kv - (N sum p^2 - (sum p)^2)

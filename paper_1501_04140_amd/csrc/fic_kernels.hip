@@ -1530,8 +1530,10 @@ constexpr int kM8Chunk = 1024;                         // target pool domains pe
 constexpr float kM8Shrink = 1.0f - 1.0f / 262144.0f;
 
 // Rows r' = r - 128 of the 8 inverse-isometry arrangements of each range:
-// Ar[(8q + t) * 64 + m] = R[iso_src(8, inverse(t), m)] - 128. Thread per row.
-__device__ __forceinline__ void k_range_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
+// Ar[(8q + t) * 64 + m] = R[iso_src(8, inverse(t), m)] - 128, as int8 or (F16)
+// as FP16 (exact: integers of 8 bits). Thread per row.
+template <bool F16>
+__device__ __forceinline__ void k_range_prep_m8_body(const uint8_t* __restrict__ img, int pitch,
                                                           const int32_t* __restrict__ act,
                                                           const int32_t* act_count,
                                                           int8_t* __restrict__ Ar,
@@ -1543,9 +1545,10 @@ __device__ __forceinline__ void k_range_prep_i8_body(const uint8_t* __restrict__
     if (row >= 8 * *act_count) return;
     const int q = row >> 3, t = row & 7;
     const int yx = act[q];
-    uint32_t* dst = reinterpret_cast<uint32_t*>(Ar + (int64_t)row * n);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(Ar + (int64_t)row * n * (F16 ? 2 : 1));
     if (yx < 0) {
-        for (int w = 0; w < n / 4; ++w) dst[w] = 0x80808080u;  // r = 0 -> r' = -128
+        // r = 0 -> r' = -128 (0x80 as int8, 0xd800 as FP16)
+        for (int w = 0; w < (F16 ? n / 2 : n / 4); ++w) dst[w] = F16 ? 0xd800d800u : 0x80808080u;
         if (t == 0) {
             SR[q] = 0;
             SRp[q] = -128 * n;
@@ -1557,16 +1560,31 @@ __device__ __forceinline__ void k_range_prep_i8_body(const uint8_t* __restrict__
     const int u = iso_inverse(t);
     const int a0 = iso_src(B, u, 0, 0);
     const int a1 = iso_src(B, u, 1, 0) - a0, a2 = iso_src(B, u, 0, 1) - a0;
+    if constexpr (F16) {
 #pragma unroll
-    for (int w = 0; w < n / 4; ++w) {
-        uint32_t v = 0;
+        for (int w = 0; w < n / 2; ++w) {
+            uint32_t v = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int m = 4 * w + b;
-            const int src = a0 + a1 * (m / B) + a2 * (m % B);
-            v |= (uint32_t)(uint8_t)((int)r[(src / B) * pitch + src % B] - 128) << (8 * b);
+            for (int b = 0; b < 2; ++b) {
+                const int m = 2 * w + b;
+                const int src = a0 + a1 * (m / B) + a2 * (m % B);
+                const _Float16 h = (_Float16)((int)r[(src / B) * pitch + src % B] - 128);
+                v |= (uint32_t)__builtin_bit_cast(uint16_t, h) << (16 * b);
+            }
+            dst[w] = v;
         }
-        dst[w] = v;
+    } else {
+#pragma unroll
+        for (int w = 0; w < n / 4; ++w) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int m = 4 * w + b;
+                const int src = a0 + a1 * (m / B) + a2 * (m % B);
+                v |= (uint32_t)(uint8_t)((int)r[(src / B) * pitch + src % B] - 128) << (8 * b);
+            }
+            dst[w] = v;
+        }
     }
     if (t == 0) {
         int s = 0;
@@ -1583,11 +1601,13 @@ __device__ __forceinline__ void k_range_prep_i8_body(const uint8_t* __restrict__
     }
 }
 
-// Columns for the int8 matcher: h and l rows of each pool domain, and in
-// FP32 G = 40 / A' (0 for a constant domain) and Q = sqrt(A') (1 - 2^-18),
-// rounded below sqrt(A') for the screen. Four lanes share a domain, 16
-// decimated values each.
-__device__ __forceinline__ void k_pool_prep_i8_body(const uint8_t* __restrict__ img, int pitch,
+// Columns for the MFMA matchers: h and l rows of each pool domain (int8), or
+// (F16) the 64 sums d' in FP16 (exact: integers below 2^11) at Dh, 128 bytes
+// per domain; and in FP32 G = 40 / A' (0 for a constant domain) and
+// Q = sqrt(A') (1 - 2^-18), rounded below sqrt(A') for the screen. Four lanes
+// share a domain, 16 decimated values each.
+template <bool F16>
+__device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ img, int pitch,
                                                          int L, int gx, const int32_t* __restrict__ pool,
                                                          int identity_total, Ctrl* ctrl,
                                                          int8_t* __restrict__ Dh, int8_t* __restrict__ Dl,
@@ -1609,11 +1629,11 @@ __device__ __forceinline__ void k_pool_prep_i8_body(const uint8_t* __restrict__ 
     if (ok) {
         j = identity_total >= 0 ? p : pool[p];
         const int y = (j / gx) * L, x = (j % gx) * L;
-        uint32_t* hd = reinterpret_cast<uint32_t*>(Dh + (int64_t)p * n + sub * PER);
+        uint32_t* hd = reinterpret_cast<uint32_t*>(Dh + ((int64_t)p * n + sub * PER) * (F16 ? 2 : 1));
         uint32_t* ld = reinterpret_cast<uint32_t*>(Dl + (int64_t)p * n + sub * PER);
 #pragma unroll
         for (int w = 0; w < PER / 4; ++w) {
-            uint32_t hw = 0, lw = 0;
+            uint32_t hw = 0, lw = 0, f16w[2] = {0u, 0u};
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int m = sub * PER + 4 * w + b, i = m / B, c = m % B;
@@ -1623,9 +1643,15 @@ __device__ __forceinline__ void k_pool_prep_i8_body(const uint8_t* __restrict__ 
                 q += (uint64_t)d * d;
                 hw |= (d >> 7) << (8 * b);
                 lw |= (d & 127u) << (8 * b);
+                f16w[b >> 1] |= (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(int)d) << (16 * (b & 1));
             }
-            hd[w] = hw;
-            ld[w] = lw;
+            if constexpr (F16) {
+                hd[2 * w] = f16w[0];
+                hd[2 * w + 1] = f16w[1];
+            } else {
+                hd[w] = hw;
+                ld[w] = lw;
+            }
         }
     }
 #pragma unroll
@@ -1721,6 +1747,18 @@ __device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint6
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// F16: the same search with X from FP16 MFMAs (v_mfma_f32_16x16x32_f16, two
+// K halves): r' and d' are exact in FP16 and every partial sum of X is an
+// integer below 64 * 128 * 1020 < 2^24, so the FP32 accumulator holds X
+// exactly, with no hi/lo split. With toff = -sum r' S the screen bound
+// (T - toff) / 64 becomes, in FP32,
+//   U~ = s_b (Q / 64) + (sum r') (S / 64) - 8,
+// at most U - 5.5 after its roundings (below 2.5 in all), so X >= U~ keeps
+// every element with X >= U; a padded column adds 2^100 instead of -8.
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool F16>
 __device__ __forceinline__ void k_match_mfma8_body(
     const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int32_t* act_count,
     const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
@@ -1728,9 +1766,11 @@ __device__ __forceinline__ void k_match_mfma8_body(
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
     Partial* __restrict__ part, int cg) {
     static_assert(kM8RowTiles == 2, "32 rows per wavefront");
-    __shared__ v4i sH[kM8Cols * 4];  // column c, K-group g at [c * 4 + g]
-    __shared__ v4i sL[kM8Cols * 4];
-    __shared__ float sQ[kM8Cols];
+    // int8: column c, K-group g at [c * 4 + g]; FP16: 16-byte chunk u of column c
+    // at [c * 9 + u] (one chunk of padding per column against bank conflicts)
+    __shared__ v4i sH[F16 ? kM8Cols * 9 : kM8Cols * 4];
+    __shared__ v4i sL[F16 ? 1 : kM8Cols * 4];
+    __shared__ float sQ[kM8Cols], sSf[F16 ? kM8Cols : 1], sBias[F16 ? kM8Cols : 1];
     __shared__ int32_t sS[kM8Cols], sTm[kM8Cols];
     __shared__ uint2 sQueue[kM8Waves][kM8Queue];
     __shared__ uint64_t sBest[kM8Waves][32];
@@ -1752,13 +1792,22 @@ __device__ __forceinline__ void k_match_mfma8_body(
     int32_t* nsr = sNsr[wave];
 
     v4i a[kM8RowTiles];
+    v8h af[kM8RowTiles][2];  // F16: the lane's 8 values of each K half
     int nsrp[kM8RowTiles];  // -sum r' of the lane's output range, per row tile
     float sigm[kM8RowTiles];
 #pragma unroll
     for (int rt = 0; rt < kM8RowTiles; ++rt) {
         const int arow = wrow0 + 16 * rt + c16;
         const v4i z = {0, 0, 0, 0};
-        a[rt] = arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 16 * g) : z;
+        if constexpr (F16) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                af[rt][h] = __builtin_bit_cast(
+                    v8h, arow < nrows ? *reinterpret_cast<const v4i*>(Ar + ((int64_t)arow * 64 + 32 * h + 8 * g) * 2)
+                                      : z);
+        } else {
+            a[rt] = arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 16 * g) : z;
+        }
         const int orow = wrow0 + 16 * rt + 4 * g;
         nsrp[rt] = orow < nrows ? -SRp[orow >> 3] : 0;
         sigm[rt] = 0.0f;
@@ -1774,62 +1823,105 @@ __device__ __forceinline__ void k_match_mfma8_body(
     for (int base = lo; base < hi; base += kM8Cols) {
         const int cnt = min(kM8Cols, hi - base);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < 2 * kM8Cols * 4; idx += kM8Waves * 64) {
-            // 256 16-byte chunks of h, then 256 of l
-            const int e = idx & (kM8Cols * 4 - 1), col = e >> 2, gg = e & 3;
-            const bool is_h = idx < kM8Cols * 4;
-            v4i v = {0, 0, 0, 0};
-            if (col < cnt)
-                v = *reinterpret_cast<const v4i*>((is_h ? Dh : Dl) + (int64_t)(base + col) * 64 +
-                                                   16 * gg);
-            if (is_h) sH[e] = v;
-            else sL[e] = v;
+        if constexpr (F16) {
+            for (int idx = threadIdx.x; idx < kM8Cols * 8; idx += kM8Waves * 64) {
+                // 512 16-byte chunks: 8 per column
+                const int col = idx >> 3, u = idx & 7;
+                v4i v = {0, 0, 0, 0};
+                if (col < cnt) v = *reinterpret_cast<const v4i*>(Dh + ((int64_t)(base + col) * 64 + 8 * u) * 2);
+                sH[col * 9 + u] = v;
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < 2 * kM8Cols * 4; idx += kM8Waves * 64) {
+                // 256 16-byte chunks of h, then 256 of l
+                const int e = idx & (kM8Cols * 4 - 1), col = e >> 2, gg = e & 3;
+                const bool is_h = idx < kM8Cols * 4;
+                v4i v = {0, 0, 0, 0};
+                if (col < cnt)
+                    v = *reinterpret_cast<const v4i*>((is_h ? Dh : Dl) + (int64_t)(base + col) * 64 +
+                                                       16 * gg);
+                if (is_h) sH[e] = v;
+                else sL[e] = v;
+            }
         }
         if (threadIdx.x < kM8Cols) {
             const int col = threadIdx.x;
             const bool ok = col < cnt;
-            // a padded column gets the bound 2^30 > |B'|: never a candidate
-            sQ[col] = ok ? Qd[base + col] : 0.0f;
+            // a padded column gets the bound 2^30 > |B'| (2^100 in FP32): never a candidate
+            const float qv = ok ? Qd[base + col] : 0.0f;
+            const int sv = ok ? (int32_t)Sd[base + col] : 0;
+            sQ[col] = F16 ? qv * (1.0f / 64.0f) : qv;
             sTm[col] = ok ? 1 : (1 << 30);
-            sS[col] = ok ? (int32_t)Sd[base + col] : 0;
+            sS[col] = sv;
+            if constexpr (F16) {
+                sSf[col] = (float)sv * (1.0f / 64.0f);
+                sBias[col] = ok ? -8.0f : 0x1p100f;
+            }
         }
         __syncthreads();
-        v4i bh[kM8ColTiles], bl[kM8ColTiles];
-#pragma unroll
-        for (int ct = 0; ct < kM8ColTiles; ++ct) {
-            bh[ct] = sH[(16 * ct + c16) * 4 + g];
-            bl[ct] = sL[(16 * ct + c16) * 4 + g];
-        }
         v4i acc[kM8RowTiles][kM8ColTiles];
-        const v4i z = {0, 0, 0, 0};
-#pragma unroll
-        for (int rt = 0; rt < kM8RowTiles; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < kM8ColTiles; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bh[ct], z, 0, 0, 0);
-#pragma unroll
-        for (int rt = 0; rt < kM8RowTiles; ++rt)
+        if constexpr (F16) {
+            v8h b16[kM8ColTiles][2];
 #pragma unroll
             for (int ct = 0; ct < kM8ColTiles; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bl[ct], acc[rt][ct] << 7,
-                                                                    0, 0, 0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) b16[ct][h] = __builtin_bit_cast(v8h, sH[(16 * ct + c16) * 9 + 4 * h + g]);
+            const v4f zf = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int rt = 0; rt < kM8RowTiles; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < kM8ColTiles; ++ct) {
+                    v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b16[ct][0], zf, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b16[ct][1], x, 0, 0, 0);
+                    acc[rt][ct] = __builtin_bit_cast(v4i, x);
+                }
+        } else {
+            v4i bh[kM8ColTiles], bl[kM8ColTiles];
+#pragma unroll
+            for (int ct = 0; ct < kM8ColTiles; ++ct) {
+                bh[ct] = sH[(16 * ct + c16) * 4 + g];
+                bl[ct] = sL[(16 * ct + c16) * 4 + g];
+            }
+            const v4i z = {0, 0, 0, 0};
+#pragma unroll
+            for (int rt = 0; rt < kM8RowTiles; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < kM8ColTiles; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bh[ct], z, 0, 0, 0);
+#pragma unroll
+            for (int rt = 0; rt < kM8RowTiles; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < kM8ColTiles; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bl[ct], acc[rt][ct] << 7,
+                                                                        0, 0, 0);
+        }
 #pragma unroll
         for (int ct = 0; ct < kM8ColTiles; ++ct) {
             const int col = 16 * ct + c16;
             const float qj = sQ[col];
             const int sj = sS[col], tmj = sTm[col];
+            const float sjf = F16 ? sSf[col] : 0.0f, bj = F16 ? sBias[col] : 0.0f;
 #pragma unroll
             for (int rt = 0; rt < kM8RowTiles; ++rt) {
                 const int toff = __mul24(nsrp[rt], sj);  // -sum r' * S (24-bit operands)
-                // B' >= T for every element that can match or beat the lane's rows
-                const int T = max((int)fminf(sigm[rt] * qj, 1.0e9f), tmj);
-                const int U = (T - toff + 63) >> 6;      // 64 X + toff >= T  <=>  X >= U
                 bool cand[4];
                 uint64_t m[4];
+                if constexpr (F16) {
+                    const float Uf = fmaf(sigm[rt], qj, fmaf((float)-nsrp[rt], sjf, bj));
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    cand[e] = acc[rt][ct][e] >= U;
-                    m[e] = __ballot(cand[e]);
+                    for (int e = 0; e < 4; ++e) {
+                        cand[e] = __int_as_float(acc[rt][ct][e]) >= Uf;
+                        m[e] = __ballot(cand[e]);
+                    }
+                } else {
+                    // B' >= T for every element that can match or beat the lane's rows
+                    const int T = max((int)fminf(sigm[rt] * qj, 1.0e9f), tmj);
+                    const int U = (T - toff + 63) >> 6;      // 64 X + toff >= T  <=>  X >= U
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        cand[e] = acc[rt][ct][e] >= U;
+                        m[e] = __ballot(cand[e]);
+                    }
                 }
                 if (m[0] | m[1] | m[2] | m[3]) {
 #pragma unroll
@@ -1837,10 +1929,13 @@ __device__ __forceinline__ void k_match_mfma8_body(
                         if (m[e]) {
                             const int slot = qn + __builtin_amdgcn_mbcnt_hi(
                                 (uint32_t)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
-                            if (cand[e])
+                            if (cand[e]) {
+                                const int X = F16 ? (int)__int_as_float(acc[rt][ct][e])
+                                                  : acc[rt][ct][e];
                                 queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
                                                              ((uint32_t)(base + col) << 5),
-                                                         (uint32_t)acc[rt][ct][e]);
+                                                         (uint32_t)X);
+                            }
                             qn += __popcll(m[e]);
                         }
                     }
@@ -2183,21 +2278,28 @@ template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_prep_i8(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
     FIC_LV;
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * 4) return;
-    k_pool_prep_i8_body(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl, a.dh,
-                        a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
+    if (a.var == kVarMfma16)
+        k_pool_prep_m8_body<true>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl,
+                                  a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
+    else
+        k_pool_prep_m8_body<false>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl,
+                                   a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
 }
 
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_range_prep_i8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_range_prep_i8_body(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
+    if (a.var == kVarMfma16)
+        k_range_prep_m8_body<true>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
+    else
+        k_range_prep_m8_body<false>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
 }
 
-template <bool TAB>
+template <bool F16, bool TAB>
 __global__ __launch_bounds__(kM8Waves * 64) void kt_match_mfma8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_match_mfma8_body(a.ar, a.srp, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
-                       a.jd, a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
+    k_match_mfma8_body<F16>(a.ar, a.srp, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
+                            a.jd, a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
 }
 
 template <bool TAB>

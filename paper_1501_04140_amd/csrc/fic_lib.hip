@@ -283,7 +283,6 @@ int match_mode(const KSet& ks) {
 
 // ---------------------------------------------------------------- one level
 // Matcher selected for a level (fic_encode_level_ex's variant).
-enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3 };
 
 // The int8 MFMA matcher serves B = 8 with a contrast grid 0..k1 (k1 >= 2) on
 // domain grids it can index (fewer than kM8MaxPool domains).
@@ -297,12 +296,14 @@ struct Level {
     int max_act;                  // worst-case active ranges
     int nc;                       // pool chunks of the matcher
     int cg;                       // domains per pool chunk
-    int var;                      // kVarValu, kVarMfma or kVarFp32
+    int var;                      // kVarValu, kVarMfma, kVarFp32 or kVarMfma16
     KSet ks;
 };
 
+bool is_mfma8(int var) { return var == kVarMfma || var == kVarMfma16; }
+
 int default_cg(int B, int var) {
-    if (var == kVarMfma) return kM8Chunk;
+    if (is_mfma8(var)) return kM8Chunk;
     if (var == kVarFp32) return 256;
     return match_chunk_domains(B);
 }
@@ -312,7 +313,7 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
     Level v;
     v.var = variant != 0 ? variant
                          : (mfma_eligible(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1))
-                                ? kVarMfma : kVarValu);
+                                ? kVarMfma16 : kVarValu);
     v.lv = lv;
     v.B = B;
     v.L = L;
@@ -324,7 +325,7 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
     v.cg = cg > 0 ? cg : default_cg(B, v.var);
     // enough workgroups to fill the chip when the pool is large, at most one
     // chunk per cg domains and 64 chunks
-    const int rows_per_block = v.var == kVarMfma ? kM8Rows
+    const int rows_per_block = is_mfma8(v.var) ? kM8Rows
                                : v.var == kVarFp32 ? kBlock
                                                    : 8 * match_ranges_per_block(B, match_mode(ks));
     const int row_blocks = cdiv((int64_t)8 * max_act, rows_per_block);
@@ -352,8 +353,8 @@ void grow(Sizes& s, const Level& v) {
     s.part = std::max(s.part, (size_t)v.max_act * v.nc * sizeof(Partial));
     s.blk = std::max(s.blk, (size_t)cdiv(v.max_act, kRqRanges) * sizeof(int2));
     s.act = std::max(s.act, (size_t)v.max_act);
-    if (v.var == kVarMfma) {
-        s.ar = std::max(s.ar, (size_t)v.max_act * 8 * 64);
+    if (is_mfma8(v.var)) {
+        s.ar = std::max(s.ar, (size_t)v.max_act * 8 * 64 * 2);  // int8 rows, or FP16 (2 bytes)
         s.dcol[l] = std::max(s.dcol[l], (size_t)v.total);
     }
 }
@@ -371,7 +372,7 @@ int ensure_sizes(Workspace& ws, const Sizes& s) {
         if ((rc = ensure(ws, pb.jd, s.dom[l] * 4))) return rc;
         if ((rc = ensure(ws, pb.blk, s.pblk[l]))) return rc;
         if (s.dcol[l]) {
-            if ((rc = ensure(ws, pb.dh, s.dcol[l] * 64))) return rc;
+            if ((rc = ensure(ws, pb.dh, s.dcol[l] * 128))) return rc;  // h rows, or FP16 columns
             if ((rc = ensure(ws, pb.dl, s.dcol[l] * 64))) return rc;
             if ((rc = ensure(ws, pb.wd, s.dcol[l] * 4))) return rc;
             if ((rc = ensure(ws, pb.cw, s.dcol[l] * 4))) return rc;
@@ -508,7 +509,7 @@ template <int B, bool TAB>
 void launch_pool_prep(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, hipStream_t st) {
     const int n = (int)h.size();
     ProfScope ps("pool_prep", st);
-    if (B == 8 && h[0].var == kVarMfma) {
+    if (B == 8 && is_mfma8(h[0].var)) {
         const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * 4, kBlock); });
         kt_pool_prep_i8<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
         return;
@@ -524,13 +525,19 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
     const Lvl& a0 = h[0];
     const int max_act = max_over(h, [](const Lvl& a) { return a.max_act; });
     const int max_nc = max_over(h, [](const Lvl& a) { return a.nc; });
-    if (B == 8 && a0.var == kVarMfma) {
+    if (B == 8 && is_mfma8(a0.var)) {
         {
             ProfScope ps("range_prep", st);
             kt_range_prep_i8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kBlock), 1, n), kBlock, 0, st>>>(h[0], dt);
         }
-        ProfScope ps("match_b8_mfma", st);
-        kt_match_mfma8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n), kM8Waves * 64, 0, st>>>(h[0], dt);
+        const dim3 grid(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n);
+        if (a0.var == kVarMfma16) {
+            ProfScope ps("match_b8_mfma16", st);
+            kt_match_mfma8<true, TAB><<<grid, kM8Waves * 64, 0, st>>>(h[0], dt);
+        } else {
+            ProfScope ps("match_b8_mfma", st);
+            kt_match_mfma8<false, TAB><<<grid, kM8Waves * 64, 0, st>>>(h[0], dt);
+        }
         return;
     }
     if (B == 8 && a0.var == kVarFp32) {
@@ -835,19 +842,20 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     if (!range_yx && n_ranges != (H / B) * (W / B))
         return fail(FIC_EINVAL, "range_yx is NULL but n_ranges %d != %d", n_ranges, (H / B) * (W / B));
     if (n_ranges > 0 && !out) return fail(FIC_EINVAL, "out is NULL");
-    if (variant < FIC_MATCH_AUTO || variant > FIC_MATCH_FP32)
+    if (variant < FIC_MATCH_AUTO || variant > FIC_MATCH_MFMA_F16)
         return fail(FIC_EINVAL, "matcher variant %d unknown", variant);
-    if ((variant == FIC_MATCH_MFMA_I8 || variant == FIC_MATCH_FP32) && !mfma_eligible(B, ks))
+    const bool mf = variant == FIC_MATCH_MFMA_I8 || variant == FIC_MATCH_MFMA_F16;
+    if ((mf || variant == FIC_MATCH_FP32) && !mfma_eligible(B, ks))
         return fail(FIC_EINVAL, "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2)",
                     variant);
-    if (variant == FIC_MATCH_MFMA_I8 &&
-        !mfma_eligible(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1)))
-        return fail(FIC_EINVAL, "the int8 MFMA matcher takes domain grids below %d domains", kM8MaxPool);
+    if (mf && !mfma_eligible(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1)))
+        return fail(FIC_EINVAL, "the MFMA matchers take domain grids below %d domains", kM8MaxPool);
     if (n_ranges == 0) return FIC_OK;
     Workspace* ws;
     if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
     const int var = variant == FIC_MATCH_VALU ? kVarValu
                     : variant == FIC_MATCH_MFMA_I8 ? kVarMfma
+                    : variant == FIC_MATCH_MFMA_F16 ? kVarMfma16
                     : variant == FIC_MATCH_FP32 ? kVarFp32 : 0;
     Level v = make_level(0, H, W, B, L, n_ranges, ks, var);
     Sizes sz;
@@ -1290,7 +1298,7 @@ int batch_time(fic_batch* b, hipStream_t s, int reps, float* ms) {
 int batch_chunk(const fic_batch* b, int l) {
     if (b->cg[l] > 0) return b->cg[l];
     const int B = b->p.B0 >> l;
-    return default_cg(B, mfma_eligible(B, b->ks[l]) ? kVarMfma : kVarValu);
+    return default_cg(B, mfma_eligible(B, b->ks[l]) ? kVarMfma16 : kVarValu);
 }
 
 uint64_t fnv1a(uint64_t h, const void* data, size_t n) {

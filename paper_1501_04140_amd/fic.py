@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfic.so")
 
 FIC_OK, FIC_EINVAL, FIC_ECAPACITY, FIC_EDEVICE, FIC_ENOMEM = 0, -1, -2, -3, -4
-MATCH_AUTO, MATCH_VALU, MATCH_MFMA_I8, MATCH_FP32 = 0, 1, 2, 3
+MATCH_AUTO, MATCH_VALU, MATCH_MFMA_I8, MATCH_FP32, MATCH_MFMA_F16 = 0, 1, 2, 3, 4
 MAX_S = 11
 PLAIN_K = tuple(range(11))                   # s = 0, 0.1, ..., 1.0 (Section 2)
 PAPER_K = ((1,), (2, 4), (3, 8), (5, 9))     # predefined s per step (Section 3.1)

@@ -114,10 +114,11 @@ def test_encode_level_ex_rejects_variants(lib):
     def call(B, n_s, variant):
         return lib.fic_encode_level_ex(1, 64, 64, 64, B, 4, ks, n_s, 0, 2.5, 1, None,
                                        (64 // B) ** 2, 1, None, None, variant, None)
-    assert call(8, 11, 4) == fic.FIC_EINVAL and "variant" in lib.fic_last_error().decode()
+    assert call(8, 11, 5) == fic.FIC_EINVAL and "variant" in lib.fic_last_error().decode()
     assert call(8, 11, -1) == fic.FIC_EINVAL
-    assert call(4, 11, fic.MATCH_MFMA_I8) == fic.FIC_EINVAL and "B = 8" in lib.fic_last_error().decode()
-    assert call(8, 2, fic.MATCH_MFMA_I8) == fic.FIC_EINVAL
+    for v in (fic.MATCH_MFMA_I8, fic.MATCH_MFMA_F16):
+        assert call(4, 11, v) == fic.FIC_EINVAL and "B = 8" in lib.fic_last_error().decode()
+        assert call(8, 2, v) == fic.FIC_EINVAL
     assert call(16, 11, fic.MATCH_FP32) == fic.FIC_EINVAL
 
 

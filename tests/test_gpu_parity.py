@@ -306,15 +306,19 @@ def test_precision_workload_sampled(dev):
 
 
 # ------------------------------------------------------------------ precision form (B = 8)
-@pytest.mark.parametrize("variant", [fic.MATCH_VALU, fic.MATCH_MFMA_I8])
+MFMA_FORMS = [fic.MATCH_MFMA_I8, fic.MATCH_MFMA_F16]
+
+
+@pytest.mark.parametrize("variant", [fic.MATCH_VALU] + MFMA_FORMS)
 def test_single_level_workload_variants(dev, variant):
     img = synth.single_level_image(0)
     check_level(dev, img, 8, 4, oracle.PLAIN_K, variant=variant)
 
 
+@pytest.mark.parametrize("variant", MFMA_FORMS)
 @pytest.mark.parametrize("kind", ["constant", "replicated", "noise", "two_tone", "blobs", "copy"])
 @pytest.mark.parametrize("ks", [oracle.PLAIN_K, (0, 1, 2), (0, 1, 2, 3, 4, 5)])
-def test_mfma_exact_on_adversarial(dev, kind, ks):
+def test_mfma_exact_on_adversarial(dev, kind, ks, variant):
     rng = np.random.default_rng(11)
     if kind == "constant":
         img = np.full((72, 88), 201, np.uint8)
@@ -333,16 +337,17 @@ def test_mfma_exact_on_adversarial(dev, kind, ks):
         img[0:8, 8:16] = 10 * np.fliplr(np.rot90(m, -1)) + 5
         img = img.astype(np.uint8)
     for L in (1, 3):
-        check_level(dev, img, 8, L, ks, variant=fic.MATCH_MFMA_I8)
+        check_level(dev, img, 8, L, ks, variant=variant)
 
 
-def test_mfma_ragged_ranges_and_pool(dev):
+@pytest.mark.parametrize("variant", MFMA_FORMS)
+def test_mfma_ragged_ranges_and_pool(dev, variant):
     img = synth.power_law(120, 136, beta=1.8, seed=9)
     rng = np.random.default_rng(2)
     corners = oracle.full_ranges(120, 136, 8)
     sub = corners[np.sort(rng.choice(len(corners), 37, replace=False))]
-    check_level(dev, img, 8, 5, oracle.PLAIN_K, ranges=sub, variant=fic.MATCH_MFMA_I8)
-    check_level(dev, img, 8, 2, oracle.PLAIN_K, entropy=1, min_pool=300, variant=fic.MATCH_MFMA_I8)
+    check_level(dev, img, 8, 5, oracle.PLAIN_K, ranges=sub, variant=variant)
+    check_level(dev, img, 8, 2, oracle.PLAIN_K, entropy=1, min_pool=300, variant=variant)
 
 
 def test_mfma_in_quadtree_unfiltered(dev):
@@ -354,12 +359,14 @@ def test_mfma_in_quadtree_unfiltered(dev):
     assert_codes_equal(got, ref)
 
 
-def test_precision_workload_mfma_sampled(dev):
-    """1024x1024 1/f^1.8, 8x8 ranges, step 2: int8 MFMA over the whole image,
-    a deterministic sample of ranges through the oracle."""
+@pytest.mark.parametrize("variant", MFMA_FORMS)
+def test_precision_workload_mfma_sampled(dev, variant):
+    """1024x1024 1/f^1.8, 8x8 ranges, step 2: int8 or FP16 MFMA over the whole
+    image, equal to the VALU matcher everywhere, a deterministic sample of ranges
+    through the oracle."""
     img = synth.precision_image(0)
-    say("[level] 1024 precision workload, MFMA")
-    got, _ = gpu_level(dev, img, 8, 2, oracle.PLAIN_K, variant=fic.MATCH_MFMA_I8)
+    say(f"[level] 1024 precision workload, MFMA variant {variant}")
+    got, _ = gpu_level(dev, img, 8, 2, oracle.PLAIN_K, variant=variant)
     valu, _ = gpu_level(dev, img, 8, 2, oracle.PLAIN_K, variant=fic.MATCH_VALU)
     for f in ("e_num", "dom", "iso", "k", "q_o"):
         assert np.array_equal(got[f], valu[f]), f
