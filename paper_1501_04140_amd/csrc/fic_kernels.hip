@@ -1766,12 +1766,14 @@ __device__ __forceinline__ void k_match_mfma8_body(
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
     Partial* __restrict__ part, int cg) {
     static_assert(kM8RowTiles == 2, "32 rows per wavefront");
-    // int8: column c, K-group g at [c * 4 + g]; FP16: 16-byte chunk u of column c
-    // at [c * 9 + u] (one chunk of padding per column against bank conflicts)
-    __shared__ v4i sH[F16 ? kM8Cols * 9 : kM8Cols * 4];
-    __shared__ v4i sL[F16 ? 1 : kM8Cols * 4];
-    __shared__ float sQ[kM8Cols], sSf[F16 ? kM8Cols : 1], sBias[F16 ? kM8Cols : 1];
-    __shared__ int32_t sS[kM8Cols], sTm[kM8Cols];
+    // Two buffers of the pool stage (the next stage is loaded while this one is
+    // matched). int8: column c, K-group g at [c * 4 + g]; FP16: 16-byte chunk u
+    // of column c at [c * 9 + u] (one chunk of padding per column against bank
+    // conflicts)
+    __shared__ v4i sH[2][F16 ? kM8Cols * 9 : kM8Cols * 4];
+    __shared__ v4i sL[2][F16 ? 1 : kM8Cols * 4];
+    __shared__ float sQ[2][kM8Cols], sSf[2][F16 ? kM8Cols : 1], sBias[2][F16 ? kM8Cols : 1];
+    __shared__ int32_t sS[2][kM8Cols], sTm[2][kM8Cols];
     __shared__ uint2 sQueue[kM8Waves][kM8Queue];
     __shared__ uint64_t sBest[kM8Waves][32];
     __shared__ int32_t sNsr[kM8Waves][32];
@@ -1820,52 +1822,68 @@ __device__ __forceinline__ void k_match_mfma8_body(
     }
     int qn = 0;  // queued candidates (the same in every lane)
 
-    for (int base = lo; base < hi; base += kM8Cols) {
-        const int cnt = min(kM8Cols, hi - base);
-        __syncthreads();
+    // a thread's share of one stage: two 16-byte chunks (FP16: column tid / 8 and
+    // tid / 8 + 32, chunk tid % 8; int8: h and l chunk tid of 256) and, in the
+    // first 64 threads, its column's Q and S
+    v4i ld0, ld1;
+    float ldq = 0.0f;
+    int lds_ = 0;
+    auto load_stage = [&](int b0, int n) {
+        const v4i zz = {0, 0, 0, 0};
+        const int t = threadIdx.x;
         if constexpr (F16) {
-            for (int idx = threadIdx.x; idx < kM8Cols * 8; idx += kM8Waves * 64) {
-                // 512 16-byte chunks: 8 per column
-                const int col = idx >> 3, u = idx & 7;
-                v4i v = {0, 0, 0, 0};
-                if (col < cnt) v = *reinterpret_cast<const v4i*>(Dh + ((int64_t)(base + col) * 64 + 8 * u) * 2);
-                sH[col * 9 + u] = v;
-            }
+            const int c0 = t >> 3, c1 = c0 + 32, u = t & 7;
+            ld0 = c0 < n ? *reinterpret_cast<const v4i*>(Dh + ((int64_t)(b0 + c0) * 64 + 8 * u) * 2) : zz;
+            ld1 = c1 < n ? *reinterpret_cast<const v4i*>(Dh + ((int64_t)(b0 + c1) * 64 + 8 * u) * 2) : zz;
         } else {
-            for (int idx = threadIdx.x; idx < 2 * kM8Cols * 4; idx += kM8Waves * 64) {
-                // 256 16-byte chunks of h, then 256 of l
-                const int e = idx & (kM8Cols * 4 - 1), col = e >> 2, gg = e & 3;
-                const bool is_h = idx < kM8Cols * 4;
-                v4i v = {0, 0, 0, 0};
-                if (col < cnt)
-                    v = *reinterpret_cast<const v4i*>((is_h ? Dh : Dl) + (int64_t)(base + col) * 64 +
-                                                       16 * gg);
-                if (is_h) sH[e] = v;
-                else sL[e] = v;
-            }
+            const int col = t >> 2, gg = t & 3;
+            ld0 = col < n ? *reinterpret_cast<const v4i*>(Dh + (int64_t)(b0 + col) * 64 + 16 * gg) : zz;
+            ld1 = col < n ? *reinterpret_cast<const v4i*>(Dl + (int64_t)(b0 + col) * 64 + 16 * gg) : zz;
         }
-        if (threadIdx.x < kM8Cols) {
-            const int col = threadIdx.x;
-            const bool ok = col < cnt;
+        if (t < kM8Cols) {
+            ldq = t < n ? Qd[b0 + t] : 0.0f;
+            lds_ = t < n ? (int32_t)Sd[b0 + t] : 0;
+        }
+    };
+    auto store_stage = [&](int buf, int n) {
+        const int t = threadIdx.x;
+        if constexpr (F16) {
+            const int c0 = t >> 3, u = t & 7;
+            sH[buf][c0 * 9 + u] = ld0;
+            sH[buf][(c0 + 32) * 9 + u] = ld1;
+        } else {
+            sH[buf][t] = ld0;
+            sL[buf][t] = ld1;
+        }
+        if (t < kM8Cols) {
             // a padded column gets the bound 2^30 > |B'| (2^100 in FP32): never a candidate
-            const float qv = ok ? Qd[base + col] : 0.0f;
-            const int sv = ok ? (int32_t)Sd[base + col] : 0;
-            sQ[col] = F16 ? qv * (1.0f / 64.0f) : qv;
-            sTm[col] = ok ? 1 : (1 << 30);
-            sS[col] = sv;
+            const bool ok = t < n;
+            sQ[buf][t] = F16 ? ldq * (1.0f / 64.0f) : ldq;
+            sTm[buf][t] = ok ? 1 : (1 << 30);
+            sS[buf][t] = lds_;
             if constexpr (F16) {
-                sSf[col] = (float)sv * (1.0f / 64.0f);
-                sBias[col] = ok ? -8.0f : 0x1p100f;
+                sSf[buf][t] = (float)lds_ * (1.0f / 64.0f);
+                sBias[buf][t] = ok ? -8.0f : 0x1p100f;
             }
         }
-        __syncthreads();
+    };
+    static_assert(kM8Waves * 64 == 4 * kM8Cols, "one stage is two chunks per thread");
+    if (lo < hi) {
+        load_stage(lo, min(kM8Cols, hi - lo));
+        store_stage(0, min(kM8Cols, hi - lo));
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int base = lo; base < hi; base += kM8Cols, buf ^= 1) {
+        const int nb = base + kM8Cols;
+        if (nb < hi) load_stage(nb, min(kM8Cols, hi - nb));  // in flight while this stage is matched
         v4i acc[kM8RowTiles][kM8ColTiles];
         if constexpr (F16) {
             v8h b16[kM8ColTiles][2];
 #pragma unroll
             for (int ct = 0; ct < kM8ColTiles; ++ct)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) b16[ct][h] = __builtin_bit_cast(v8h, sH[(16 * ct + c16) * 9 + 4 * h + g]);
+                for (int h = 0; h < 2; ++h) b16[ct][h] = __builtin_bit_cast(v8h, sH[buf][(16 * ct + c16) * 9 + 4 * h + g]);
             const v4f zf = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int rt = 0; rt < kM8RowTiles; ++rt)
@@ -1879,8 +1897,8 @@ __device__ __forceinline__ void k_match_mfma8_body(
             v4i bh[kM8ColTiles], bl[kM8ColTiles];
 #pragma unroll
             for (int ct = 0; ct < kM8ColTiles; ++ct) {
-                bh[ct] = sH[(16 * ct + c16) * 4 + g];
-                bl[ct] = sL[(16 * ct + c16) * 4 + g];
+                bh[ct] = sH[buf][(16 * ct + c16) * 4 + g];
+                bl[ct] = sL[buf][(16 * ct + c16) * 4 + g];
             }
             const v4i z = {0, 0, 0, 0};
 #pragma unroll
@@ -1898,9 +1916,9 @@ __device__ __forceinline__ void k_match_mfma8_body(
 #pragma unroll
         for (int ct = 0; ct < kM8ColTiles; ++ct) {
             const int col = 16 * ct + c16;
-            const float qj = sQ[col];
-            const int sj = sS[col], tmj = sTm[col];
-            const float sjf = F16 ? sSf[col] : 0.0f, bj = F16 ? sBias[col] : 0.0f;
+            const float qj = sQ[buf][col];
+            const int sj = sS[buf][col], tmj = sTm[buf][col];
+            const float sjf = F16 ? sSf[buf][col] : 0.0f, bj = F16 ? sBias[buf][col] : 0.0f;
 #pragma unroll
             for (int rt = 0; rt < kM8RowTiles; ++rt) {
                 const int toff = __mul24(nsrp[rt], sj);  // -sum r' * S (24-bit operands)
@@ -1952,6 +1970,9 @@ __device__ __forceinline__ void k_match_mfma8_body(
                 }
             }
         }
+        // the other buffer was last read in the previous stage, before its barrier
+        if (nb < hi) store_stage(buf ^ 1, min(kM8Cols, hi - nb));
+        __syncthreads();
     }
     if (qn > 0) m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
     // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
