@@ -1520,8 +1520,11 @@ __global__ void k_calib_hist(const uint8_t* __restrict__ img, int pitch,
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kM8Waves = 4;                            // wavefronts per workgroup
-constexpr int kM8RowTiles = 2;                         // 16-row MFMA tiles per wavefront
-constexpr int kM8Rows = kM8Waves * 16 * kM8RowTiles;   // 128 rows = 16 ranges x 8 isometries
+// 16-row MFMA tiles per wavefront: 4 for the int8 form, 2 for FP16 (whose
+// register budget would otherwise halve its occupancy)
+constexpr int m8_row_tiles(bool f16) { return f16 ? 2 : 4; }
+constexpr int m8_rows(bool f16) { return kM8Waves * 16 * m8_row_tiles(f16); }  // rows per workgroup
+constexpr int kM8RowBits = 6;                           // queue entry: row | position << kM8RowBits
 constexpr int kM8ColTiles = 4;                         // 16-column tiles per LDS stage
 constexpr int kM8Cols = 16 * kM8ColTiles;              // 64 pool domains per LDS stage
 constexpr int kM8Chunk = 1024;                         // target pool domains per chunk
@@ -1688,8 +1691,8 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
     }
 }
 
-// grid: x = workgroups of kM8Rows rows, y = pool chunks. The contrast set is
-// k = 0..k1. Each wavefront keeps 32 rows; each lane holds 4 rows x 1 column
+// grid: x = workgroups of m8_rows rows, y = pool chunks. The contrast set is
+// k = 0..k1. Each wavefront keeps kM8WaveRows rows; each lane holds 4 rows x 1 column
 // of every 16x16 output tile.
 // Screen: for any k, F = k^2 A' - 80 k B' is at least the continuous minimum
 // -1600 B'^2 / A', so an element can match or beat a row's best F_b <= 0 only
@@ -1714,14 +1717,15 @@ __device__ inline uint64_t m8_pack(int64_t F, int pos, int k) {
 
 __device__ inline int64_t m8_unpack_F(uint64_t v) { return (int64_t)(v >> 26) - (1ll << 37); }
 
-// s_b of a packed best, rounded below the exact value.
+// s_b of a packed best, rounded below the exact value (the hardware square
+// root is within a few ulps; kM8Shrink takes off 64 ulps).
 __device__ inline float m8_sigma(uint64_t v) {
     const int64_t F = m8_unpack_F(v);
-    return F < 0 ? sqrtf((float)(-F) * (1.0f / 1600.0f)) * kM8Shrink : 0.0f;
+    return F < 0 ? __builtin_amdgcn_sqrtf((float)(-F) * (1.0f / 1600.0f)) * kM8Shrink : 0.0f;
 }
 
 // Exact decision of the wavefront's queued candidates (entry: row | position
-// << 5, X), one per lane, then the lane's row bounds re-read.
+// << kM8RowBits, X), one per lane, then the lane's row bounds re-read.
 __device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint64_t* best,
                                 const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
                                 const float* __restrict__ Gd, int k1, int lane) {
@@ -1730,7 +1734,7 @@ __device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint6
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     for (int i = lane; i < n; i += 64) {
         const uint2 en = q[i];
-        const int row = (int)(en.x & 31u), pos = (int)(en.x >> 5), X = (int)en.y;
+        const int row = (int)(en.x & ((1u << kM8RowBits) - 1u)), pos = (int)(en.x >> kM8RowBits), X = (int)en.y;
         const int64_t Ap = Ad[pos];
         const int bi = (X << 6) + nsr[row] * (int)Sd[pos];  // B' = 64 X - sum r' S, exact
         const int64_t Bp = bi, b80 = 80 * Bp;
@@ -1765,7 +1769,8 @@ __device__ __forceinline__ void k_match_mfma8_body(
     const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Qd,
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
     Partial* __restrict__ part, int cg) {
-    static_assert(kM8RowTiles == 2, "32 rows per wavefront");
+    constexpr int kM8RowTiles = m8_row_tiles(F16), kM8WaveRows = 16 * kM8RowTiles;
+    static_assert(kM8WaveRows <= (1 << kM8RowBits), "row index of a queue entry");
     // Two buffers of the pool stage (the next stage is loaded while this one is
     // matched). int8: column c, K-group g at [c * 4 + g]; FP16: 16-byte chunk u
     // of column c at [c * 9 + u] (one chunk of padding per column against bank
@@ -1775,11 +1780,11 @@ __device__ __forceinline__ void k_match_mfma8_body(
     __shared__ float sQ[2][kM8Cols], sSf[2][F16 ? kM8Cols : 1], sBias[2][F16 ? kM8Cols : 1];
     __shared__ int32_t sS[2][kM8Cols], sTm[2][kM8Cols];
     __shared__ uint2 sQueue[kM8Waves][kM8Queue];
-    __shared__ uint64_t sBest[kM8Waves][32];
-    __shared__ int32_t sNsr[kM8Waves][32];
+    __shared__ uint64_t sBest[kM8Waves][kM8WaveRows];
+    __shared__ int32_t sNsr[kM8Waves][kM8WaveRows];
 
     const int nrows = 8 * *act_count;
-    const int row_blk = blockIdx.x * kM8Rows;
+    const int row_blk = blockIdx.x * m8_rows(F16);
     if (row_blk >= nrows) return;
     const int P = ctrl->pool_count;
     const int nca = active_chunks(P, cg, n_chunks);
@@ -1814,11 +1819,11 @@ __device__ __forceinline__ void k_match_mfma8_body(
         nsrp[rt] = orow < nrows ? -SRp[orow >> 3] : 0;
         sigm[rt] = 0.0f;
     }
-    if (lane < 32) {
+    for (int i = lane; i < kM8WaveRows; i += 64) {
         // k = 0 gives F = 0 for every domain; its smallest key is the chunk's first domain
-        best[lane] = m8_pack(0, lo, 0);
-        const int r = wrow0 + lane;
-        nsr[lane] = r < nrows ? -SRp[r >> 3] : 0;
+        best[i] = m8_pack(0, lo, 0);
+        const int r = wrow0 + i;
+        nsr[i] = r < nrows ? -SRp[r >> 3] : 0;
     }
     int qn = 0;  // queued candidates (the same in every lane)
 
@@ -1951,7 +1956,7 @@ __device__ __forceinline__ void k_match_mfma8_body(
                                 const int X = F16 ? (int)__int_as_float(acc[rt][ct][e])
                                                   : acc[rt][ct][e];
                                 queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
-                                                             ((uint32_t)(base + col) << 5),
+                                                             ((uint32_t)(base + col) << kM8RowBits),
                                                          (uint32_t)X);
                             }
                             qn += __popcll(m[e]);

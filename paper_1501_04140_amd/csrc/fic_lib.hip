@@ -325,7 +325,7 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
     v.cg = cg > 0 ? cg : default_cg(B, v.var);
     // enough workgroups to fill the chip when the pool is large, at most one
     // chunk per cg domains and 64 chunks
-    const int rows_per_block = is_mfma8(v.var) ? kM8Rows
+    const int rows_per_block = is_mfma8(v.var) ? m8_rows(v.var == kVarMfma16)
                                : v.var == kVarFp32 ? kBlock
                                                    : 8 * match_ranges_per_block(B, match_mode(ks));
     const int row_blocks = cdiv((int64_t)8 * max_act, rows_per_block);
@@ -530,7 +530,7 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
             ProfScope ps("range_prep", st);
             kt_range_prep_i8<TAB><<<dim3(cdiv((int64_t)8 * max_act, kBlock), 1, n), kBlock, 0, st>>>(h[0], dt);
         }
-        const dim3 grid(cdiv((int64_t)8 * max_act, kM8Rows), max_nc, n);
+        const dim3 grid(cdiv((int64_t)8 * max_act, m8_rows(a0.var == kVarMfma16)), max_nc, n);
         if (a0.var == kVarMfma16) {
             ProfScope ps("match_b8_mfma16", st);
             kt_match_mfma8<true, TAB><<<grid, kM8Waves * 64, 0, st>>>(h[0], dt);
