@@ -1702,6 +1702,12 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
 // least 1 since F < 0 needs B' > 0); with B' = 64 X + toff this is one integer
 // bound U on the MFMA output X: per element, one compare. The bound is not
 // strict, so ties stay candidates.
+// F = 0 never improves a row: its best starts at (F = 0, the chunk's first
+// position, k = 0) and positions only grow. So a row of a constant range
+// (C = 0, hence B' = 0 and F >= 0 everywhere) and a padded row start from the
+// mark kM8Excl in place of F = 0 (s_b near 9300: no element reaches its bound)
+// and report F = 0 at the end; and (FP16, whose rounding slack would let B' = 0
+// pass) a constant domain (A' = 0, hence B' = 0) never queues either.
 // Candidates go to a per-wavefront queue in LDS and are decided exactly in
 // int64 64 at a time, one per lane (the FP32 k corrected by one step). Each
 // row's best is one packed word (F + 2^37) << 26 | position << 4 | k, which
@@ -1710,6 +1716,8 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
 // every lane of a row reads its bound back from it.
 constexpr int kM8Queue = 64 + 4 * 64;  // a flush at 64 entries, then up to one tile's 256
 constexpr int kM8MaxPool = 1 << 22;    // pool positions the packed best can hold
+// F of a row that never queues (below every real F >= -1600 C > -2^37)
+constexpr int64_t kM8Excl = -(1ll << 37) + 1;
 
 __device__ inline uint64_t m8_pack(int64_t F, int pos, int k) {
     return ((uint64_t)(F + (1ll << 37)) << 26) | ((uint64_t)pos << 4) | (uint64_t)k;
@@ -1764,8 +1772,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <bool F16>
 __device__ __forceinline__ void k_match_mfma8_body(
-    const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int32_t* act_count,
-    const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
+    const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int64_t* __restrict__ CR,
+    const int32_t* act_count, const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
     const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Qd,
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
     Partial* __restrict__ part, int cg) {
@@ -1817,13 +1825,21 @@ __device__ __forceinline__ void k_match_mfma8_body(
         }
         const int orow = wrow0 + 16 * rt + 4 * g;
         nsrp[rt] = orow < nrows ? -SRp[orow >> 3] : 0;
-        sigm[rt] = 0.0f;
     }
     for (int i = lane; i < kM8WaveRows; i += 64) {
         // k = 0 gives F = 0 for every domain; its smallest key is the chunk's first domain
-        best[i] = m8_pack(0, lo, 0);
         const int r = wrow0 + i;
+        const bool live = r < nrows && CR[r >> 3] != 0;
+        best[i] = m8_pack(live ? 0 : kM8Excl, lo, 0);
         nsr[i] = r < nrows ? -SRp[r >> 3] : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int rt = 0; rt < kM8RowTiles; ++rt) {
+        const uint64_t* bb = best + 16 * rt + 4 * g;
+        sigm[rt] = fminf(fminf(m8_sigma(bb[0]), m8_sigma(bb[1])), fminf(m8_sigma(bb[2]), m8_sigma(bb[3])));
     }
     int qn = 0;  // queued candidates (the same in every lane)
 
@@ -1861,14 +1877,15 @@ __device__ __forceinline__ void k_match_mfma8_body(
             sL[buf][t] = ld1;
         }
         if (t < kM8Cols) {
-            // a padded column gets the bound 2^30 > |B'| (2^100 in FP32): never a candidate
+            // a padded column gets the bound 2^30 > |B'| (2^100 in FP32, as does a
+            // constant domain): never a candidate
             const bool ok = t < n;
             sQ[buf][t] = F16 ? ldq * (1.0f / 64.0f) : ldq;
             sTm[buf][t] = ok ? 1 : (1 << 30);
             sS[buf][t] = lds_;
             if constexpr (F16) {
                 sSf[buf][t] = (float)lds_ * (1.0f / 64.0f);
-                sBias[buf][t] = ok ? -8.0f : 0x1p100f;
+                sBias[buf][t] = ok && ldq > 0.0f ? -8.0f : 0x1p100f;  // Q > 0 iff A' > 0
             }
         }
     };
@@ -1990,7 +2007,7 @@ __device__ __forceinline__ void k_match_mfma8_body(
             for (int e = 0; e < 4; ++e) {
                 const uint64_t v = best[16 * rt + 4 * g + e];
                 const int pos = (int)((v >> 4) & (uint64_t)(kM8MaxPool - 1)), k = (int)(v & 15u);
-                const int64_t Fe = m8_unpack_F(v);
+                const int64_t Fe = m8_unpack_F(v) == kM8Excl ? 0 : m8_unpack_F(v);
                 const int64_t key = make_key(Jd[pos], (orow + e) & 7, k, Sd[pos]);
                 if (pair_less(Fe, key, F, K)) {
                     F = Fe;
@@ -2324,7 +2341,7 @@ __global__ __launch_bounds__(kBlock) void kt_range_prep_i8(Lvl a0, const Lvl* __
 template <bool F16, bool TAB>
 __global__ __launch_bounds__(kM8Waves * 64) void kt_match_mfma8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_match_mfma8_body<F16>(a.ar, a.srp, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
+    k_match_mfma8_body<F16>(a.ar, a.srp, a.cr, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
                             a.jd, a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
 }
 

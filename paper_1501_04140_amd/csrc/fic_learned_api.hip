@@ -425,9 +425,9 @@ FIC_API int fic_encode_level_learned(fic_mlp* M, const uint8_t* img, int32_t H, 
     int32_t* fb_count = ws->ctrl->act_count;  // level 0 of this workspace
     {
         ProfScope ps("learned_rescore", st);
-        k_fill_i32<<<1, 64, 0, st>>>(fb_count, 1, 0);
-        k_rescore<<<nr, 256, 0, st>>>(img, pitch, W, L, gx, nd, cand, topk, nr, ks,
-                                      keep_threshold(rms_thresh, 8), out, act, P<int32_t>(M->fbq), fb_count);
+        k_rescore<<<nr, 256, 0, st>>>(img, pitch, W, L, gx, nd, cand, topk, nr, ks, out);
+        k_fallback_list<<<1, 1024, 0, st>>>(out, nr, W, keep_threshold(rms_thresh, 8), act, P<int32_t>(M->fbq),
+                                            fb_count);
         LAUNCH_CHECK();
     }
     // exhaustive search for the ranges on the fallback list

@@ -549,16 +549,12 @@ __global__ __launch_bounds__(256) void k_topk_merge(const uint64_t* __restrict__
 // One workgroup per 8 x 8 range of the grid; thread = (proposal c = tid / 8,
 // isometry t = tid % 8). Evaluates the distance of eq. (1) exactly over the
 // range's proposals, isometries and contrast values (same moment form and tie
-// order as the exhaustive matcher), writes the match, and appends the range to
-// the fallback list when 1600 n E > thr.
+// order as the exhaustive matcher) and writes the match; e_num = -1 when the
+// range has no proposal.
 __global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img, int pitch,
                                                  int W, int L, int gx, int total,
                                                  const int32_t* __restrict__ cand, int kc,
-                                                 int nr, KSet ks, int64_t thr,
-                                                 fic_match* __restrict__ out,
-                                                 int32_t* __restrict__ fb_act,
-                                                 int32_t* __restrict__ fb_q,
-                                                 int32_t* __restrict__ fb_count) {
+                                                 int nr, KSet ks, fic_match* __restrict__ out) {
     __shared__ int sr[64];
     __shared__ int sd[kTopK][64];
     __shared__ int64_t redF[4], redK[4];
@@ -645,11 +641,44 @@ __global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img
         m.E = (float)m.e_num / (1600.0f * 64.0f);
     }
     out[q] = m;
-    if (K == INT64_MAX || m.e_num > thr) {
-        const int pos = atomicAdd(fb_count, 1);
-        fb_act[pos] = (y << 16) | x;
-        fb_q[pos] = q;
+}
+
+// The fallback list: ranges with no proposal or with 1600 n E > thr, in grid
+// order (so that neighbouring ranges, which cost the exhaustive matcher alike,
+// share its workgroups). One workgroup, rounds of 1024 ranges.
+__global__ __launch_bounds__(1024) void k_fallback_list(const fic_match* __restrict__ m, int nr, int W,
+                                                        int64_t thr, int32_t* __restrict__ fb_act,
+                                                        int32_t* __restrict__ fb_q,
+                                                        int32_t* __restrict__ fb_count) {
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, rgx = W / 8;
+    int done = 0;
+    for (int b = 0; b < nr; b += 1024) {
+        const int q = b + tid;
+        bool f = false;
+        if (q < nr) {
+            const int64_t e = m[q].e_num;
+            f = e < 0 || e > thr;
+        }
+        const uint64_t bal = __ballot(f);
+        if (lane == 0) wsum[w] = __popcll(bal);
+        __syncthreads();
+        int before = done, tot = 0;
+        for (int i = 0; i < 16; ++i) {
+            const int c = wsum[i];
+            before += i < w ? c : 0;
+            tot += c;
+        }
+        if (f) {
+            const int pos = before + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            fb_act[pos] = (((q / rgx) * 8) << 16) | ((q % rgx) * 8);
+            fb_q[pos] = q;
+        }
+        done += tot;
+        __syncthreads();  // wsum is rewritten next round
     }
+    if (tid == 0) *fb_count = done;
 }
 
 // out[fb_q[p]] = exhaustive match p, flagged as a fallback

@@ -316,12 +316,18 @@ def test_single_level_workload_variants(dev, variant):
 
 
 @pytest.mark.parametrize("variant", MFMA_FORMS)
-@pytest.mark.parametrize("kind", ["constant", "replicated", "noise", "two_tone", "blobs", "copy"])
+@pytest.mark.parametrize("kind", ["constant", "half_flat", "replicated", "noise", "two_tone", "blobs",
+                                  "copy"])
 @pytest.mark.parametrize("ks", [oracle.PLAIN_K, (0, 1, 2), (0, 1, 2, 3, 4, 5)])
 def test_mfma_exact_on_adversarial(dev, kind, ks, variant):
     rng = np.random.default_rng(11)
     if kind == "constant":
         img = np.full((72, 88), 201, np.uint8)
+    elif kind == "half_flat":
+        # constant ranges and constant domains beside textured ones (F = 0 ties)
+        img = rng.integers(0, 256, size=(72, 88)).astype(np.uint8)
+        img[:, :44] = 77
+        img[:16, 60:] = 3
     elif kind == "replicated":
         img = np.kron(rng.integers(0, 256, size=(36, 44)), np.ones((2, 2))).astype(np.uint8)
     elif kind == "noise":
