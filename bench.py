@@ -36,6 +36,17 @@ def match_ops(n: int, n_s: int) -> int:
     return 2 * n + 2 + 3 * n_s
 
 
+def level_ops(B: int, matches: int, n_s: int) -> dict:
+    """Algorithmic work of one level's matcher, by the label it is profiled under:
+    the VALU matcher's integer ops, or (B = 8 and 16 with small sets, on FP16 MFMA)
+    the correlation's 2n flops per match against the FP16 MFMA peak."""
+    n = B * B
+    out = {f"match_b{B}": matches * match_ops(n, n_s)}
+    if B in (8, 16):
+        out[f"match_b{B}_mfq"] = (matches * 2 * n, "mfma", PEAK_FP16_TFLOPS, "TFLOP/s")
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,8 +200,7 @@ def run_quadtree(args, torch):
     prof = fic.profile_end()
     per_label = {}
     for lv, B in enumerate(params.levels):
-        n = B * B
-        per_label[f"match_b{B}"] = int(st["matches"][lv]) * match_ops(n, len(s_sets[lv]))
+        per_label.update(level_ops(B, int(st["matches"][lv]), len(s_sets[lv])))
     match_prof = {k: v for k, v in prof.items() if k.startswith("match")}
     roof = with_traffic(roofline_from_profile(match_prof, per_label, steps=args.steps), "quadtree512")
 
@@ -279,8 +289,9 @@ def run_batch(args, torch):
         b.run_eager()
     torch.cuda.synchronize()
     prof = fic.profile_end()
-    per_label = {f"match_b{B}": int(matches_lv[lv]) * match_ops(B * B, len(params.s_sets[lv]))
-                 for lv, B in enumerate(params.levels)}
+    per_label = {}
+    for lv, B in enumerate(params.levels):
+        per_label.update(level_ops(B, int(matches_lv[lv]), len(params.s_sets[lv])))
     roof = with_traffic(roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")},
                                               per_label, steps=args.steps), "batch64")
     eager_ms = sum(v[1] for v in prof.values()) / args.steps

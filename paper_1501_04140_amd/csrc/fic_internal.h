@@ -50,7 +50,8 @@ struct Partial {
 // a batch.
 // Matcher of a level: dot4 VALU, int8 MFMA (hi/lo split), FP32 comparator,
 // FP16 MFMA (exact for B = 8).
-enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3, kVarMfma16 = 4 };
+// kVarMfq: the FP16 MFMA matcher of B = 8 and 16 levels with one or two contrast values
+enum { kVarValu = 1, kVarMfma = 2, kVarFp32 = 3, kVarMfma16 = 4, kVarMfq = 5 };
 
 struct Lvl {
     const uint8_t* img;
@@ -62,7 +63,7 @@ struct Lvl {
     int32_t min_pool, rank;       // entropy floor: pool size wanted, min(min_pool, total)
     int32_t sel_shift, bound_chunk;
     int32_t capacity;
-    int32_t var;                  // matcher: kVarValu, kVarMfma, kVarFp32 or kVarMfma16
+    int32_t var;                  // matcher: kVarValu, kVarMfma, kVarFp32, kVarMfma16 or kVarMfq
     int32_t pmode;                // pool filter: 0 none, 1 entropy, 2 variance
     int64_t M;                    // filter cut (keep iff key < M)
     int64_t kv;                   // variance filter: key = kv - (N sum p^2 - (sum p)^2)

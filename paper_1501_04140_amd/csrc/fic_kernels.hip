@@ -983,6 +983,7 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
     if (c >= active_chunks(P, cg, n_chunks)) return;
     const int nca = active_chunks(P, cg, n_chunks);
 
+#pragma unroll
     for (int e = threadIdx.x; e < RPB * n; e += kBlock) {
         const int lq = e / n, m = e % n, q = q0 + lq;
         uint8_t v = 0;
@@ -2060,6 +2061,7 @@ __device__ __forceinline__ void k_match_fp32_body(const uint8_t* __restrict__ im
     const int c = blockIdx.y;
     if (c >= nca) return;
     const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
+#pragma unroll
     for (int e = threadIdx.x; e < RPB * n; e += kBlock) {
         const int lq = e / n, m = e % n, q = q0 + lq;
         uint8_t v = 0;
@@ -2196,6 +2198,341 @@ __device__ __forceinline__ void k_reduce_fp32_body(const uint8_t* __restrict__ i
     out[q] = m;
 }
 
+
+// ================================================================ FP16 MFMA matcher for small contrast sets
+// The 8 x 8 and 16 x 16 quadtree levels with one or two predefined contrast
+// values (Section 3.1), on v_mfma_f32_16x16x32_f16. Operands are centred:
+// r' = r - 128 in [-128, 127] and d'' = d' - 510 in [-510, 510] are exact in
+// FP16, and every partial sum of X = sum r' d'' is an integer of magnitude at
+// most n * 128 * 510 < 2^24 (n <= 256), so the FP32 accumulator holds X
+// exactly whatever the order of the additions. B' is a covariance, so
+// B' = n X - (sum r')(sum d''), an integer below 2^33 in magnitude, and
+// F = k^2 A' - 80 k B' is an integer below 2^44: both come out of FP64 FMAs
+// exactly (53-bit significand). Each lane keeps, for its 4 rows, the running
+// minimum of (F, position, contrast index) over its columns in registers,
+// visiting positions in ascending order with strict compares, so the first
+// occurrence wins; the 16 lanes of a row are merged lexicographically at the
+// end. k = 0 gives F = 0 for every domain: a set holding 0 (its first value,
+// the set being increasing) starts each row from (0, the chunk's first
+// position, 0). The pool is short at these levels (a few hundred domains),
+// where a screen would send a large share of the elements to an exact
+// decision; this epilogue is a handful of VALU instructions per element.
+// The range blocks are staged in LDS and turned into the inverse-isometry
+// rows in registers by the kernel itself.
+constexpr int kMqWaves = 4;
+constexpr int mq_row_tiles(int B) { return B == 16 ? 1 : 2; }
+constexpr int mq_rows(int B) { return kMqWaves * 16 * mq_row_tiles(B); }  // rows per workgroup
+constexpr int mq_cols(int B) { return B == 16 ? 32 : 64; }               // pool domains per LDS stage
+constexpr int kMqMaxPool = 1 << 21;
+
+// Columns of the small-set MFMA matcher: the n values d'' = d' - 510 of each
+// pool domain in FP16 at Dh (2n bytes per domain), and S, A', j as for the
+// VALU matcher. n / 16 lanes per domain, 16 values each.
+template <int B>
+__device__ __forceinline__ void k_pool_prep_mq_body(const uint8_t* __restrict__ img, int pitch, int L,
+                                                         int gx, const int32_t* __restrict__ pool,
+                                                         int identity_total, Ctrl* ctrl,
+                                                         _Float16* __restrict__ Dh, uint32_t* __restrict__ Sd,
+                                                         int64_t* __restrict__ Ad, int32_t* __restrict__ Jd) {
+    constexpr int n = B * B, PER = 16, TPD = n / PER;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (identity_total >= 0 && g == 0) {
+        ctrl->pool_count = identity_total;
+        ctrl->passed = identity_total;
+    }
+    const int count = identity_total >= 0 ? identity_total : ctrl->pool_count;
+    const int p = g / TPD, sub = g % TPD;
+    const bool ok = p < count;
+    uint32_t s = 0;
+    uint64_t q = 0;
+    int j = 0;
+    if (ok) {
+        j = identity_total >= 0 ? p : pool[p];
+        const int y = (j / gx) * L, x = (j % gx) * L;
+        uint32_t* hd = reinterpret_cast<uint32_t*>(Dh + (int64_t)p * n + sub * PER);
+#pragma unroll
+        for (int w = 0; w < PER / 2; ++w) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int m = sub * PER + 2 * w + b, i = m / B, c = m % B;
+                const uint8_t* px = img + (int64_t)(y + 2 * i) * pitch + x + 2 * c;
+                const uint32_t d = (uint32_t)px[0] + px[1] + px[pitch] + px[pitch + 1];
+                s += d;
+                q += (uint64_t)d * d;
+                v |= (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)((int)d - 510)) << (16 * b);
+            }
+            hd[w] = v;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < TPD; m <<= 1) {
+        s += __shfl_xor(s, m, 64);
+        q += __shfl_xor(q, m, 64);
+    }
+    if (ok && sub == 0) {
+        Sd[p] = s;
+        Ad[p] = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
+        Jd[p] = j;
+    }
+}
+
+// grid: x = workgroups of mq_rows(B) rows (8 per range), y = pool chunks.
+// NK: the number of nonzero values in the set (1 or 2).
+template <int B, int NK>
+__device__ __forceinline__ void k_match_mfq_body(
+    const uint8_t* __restrict__ img, int pitch, const int32_t* __restrict__ act, const int32_t* act_count,
+    const _Float16* __restrict__ Dh, const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad,
+    const int32_t* __restrict__ Jd, const Ctrl* ctrl, const KSet& ks, int n_chunks, int cg,
+    Partial* __restrict__ part, int32_t* __restrict__ SRout, int64_t* __restrict__ CRout) {
+    constexpr int n = B * B, KG = n / 32, RT = mq_row_tiles(B), ROWS = mq_rows(B);
+    constexpr int NR = ROWS / 8;                // ranges per workgroup
+    constexpr int COLS = mq_cols(B), CT = COLS / 16;
+    constexpr int CPC = n / 8;                  // 16-byte chunks per column
+    constexpr int CH = CPC + 1;                 // LDS stride per column (one chunk of padding)
+    constexpr int NT = kMqWaves * 64;
+    constexpr int NLD = COLS * CPC / NT;        // chunks per thread per stage
+    static_assert(COLS * CPC % NT == 0 && COLS <= NT, "stage split over the workgroup");
+    __shared__ v4i sB[2][COLS * CH];
+    __shared__ double sKA[2][NK][COLS];         // k^2 A' per column and nonzero value
+    __shared__ double sSdd[2][COLS];            // sum d'' = S - 510 n
+    __shared__ uint8_t sPix[NR * n];
+    __shared__ int32_t sSR[NR];
+
+    const int nact = *act_count, nrows = 8 * nact;
+    const int row_blk = blockIdx.x * ROWS;
+    if (row_blk >= nrows) return;
+    const int P = ctrl->pool_count;
+    const int nca = active_chunks(P, cg, n_chunks);
+    const int c = blockIdx.y;
+    if (c >= nca) return;
+    const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
+
+    // the set: its nonzero values in order (with their indices), and whether it holds 0
+    int kz0 = 0, kz1 = 0, u0 = 0, u1 = 0;
+    bool zero_in = false, have0 = false;
+#pragma unroll
+    for (int u = 0; u < kSmallMax; ++u) {
+        if (u < ks.n) {
+            const int k = ks.k[u];
+            if (k == 0) {
+                zero_in = true;
+            } else if (!have0) {
+                kz0 = k;
+                u0 = u;
+                have0 = true;
+            } else {
+                kz1 = k;
+                u1 = u;
+            }
+        }
+    }
+
+    // a thread's share of one stage: NLD 16-byte chunks, and (first COLS threads)
+    // its column's A' and S
+    v4i ld[NLD];
+    int64_t ldA = 0;
+    uint32_t ldS = 0;
+    auto load_stage = [&](int b0, int cnt) {
+        const v4i zz = {0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int ci = threadIdx.x + NT * i, col = ci / CPC, uu = ci % CPC;
+            ld[i] = col < cnt ? *reinterpret_cast<const v4i*>(Dh + (int64_t)(b0 + col) * n + 8 * uu) : zz;
+        }
+        if (threadIdx.x < COLS) {
+            ldA = (int)threadIdx.x < cnt ? Ad[b0 + threadIdx.x] : 0;
+            ldS = (int)threadIdx.x < cnt ? Sd[b0 + threadIdx.x] : 0u;
+        }
+    };
+    auto store_stage = [&](int bf) {
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int ci = threadIdx.x + NT * i, col = ci / CPC, uu = ci % CPC;
+            sB[bf][col * CH + uu] = ld[i];
+        }
+        if (threadIdx.x < COLS) {
+            const int t = threadIdx.x;
+#pragma unroll
+            for (int m = 0; m < NK; ++m) sKA[bf][m][t] = (double)(m == 0 ? kz0 * kz0 : kz1 * kz1) * (double)ldA;
+            sSdd[bf][t] = (double)((int)ldS - 510 * n);
+        }
+    };
+    // the first stage's loads are in flight while the ranges are staged
+    if (lo < hi) load_stage(lo, min(COLS, hi - lo));
+
+    // the workgroup's range blocks, their sums and C (written out by chunk 0):
+    // each thread stages SPT consecutive pixels of one range row, all its loads
+    // issued together
+    const int q0 = row_blk >> 3;
+    {
+        constexpr int SPT = NR * n / NT;
+        static_assert(B % SPT == 0 && NR * n == SPT * NT, "a thread's pixels lie in one row");
+        const int lq = threadIdx.x / (n / SPT), m0 = (threadIdx.x % (n / SPT)) * SPT, q = q0 + lq;
+        const int yx = q < nact ? act[q] : -1;
+        uint8_t v[SPT];
+        const uint8_t* src = img + (yx >= 0 ? (int64_t)((yx >> 16) + m0 / B) * pitch + (yx & 0xffff) + m0 % B : 0);
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) v[i] = yx >= 0 ? src[i] : 0;
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) sPix[lq * n + m0 + i] = v[i];
+    }
+    __syncthreads();
+    {
+        constexpr int TPQ = NT / NR, PPT = n / TPQ;  // threads per range, pixels per thread
+        static_assert(64 % TPQ == 0, "a range's threads share a wavefront");
+        const int lq = threadIdx.x / TPQ, sub = threadIdx.x % TPQ;
+        int s = 0, s2 = 0;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int v = sPix[lq * n + sub * PPT + i];
+            s += v;
+            s2 += v * v;
+        }
+#pragma unroll
+        for (int m = 1; m < TPQ; m <<= 1) {
+            s += __shfl_xor(s, m, 64);
+            s2 += __shfl_xor(s2, m, 64);
+        }
+        if (sub == 0) {
+            sSR[lq] = s;
+            const int q = q0 + lq;
+            if (c == 0 && q < nact) {
+                SRout[q] = s;
+                CRout[q] = (int64_t)n * s2 - (int64_t)s * s;
+            }
+        }
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int wrow0 = row_blk + wave * 16 * RT;
+
+    // A operands: row 16 rt + c16 of the wave, K = 32 kg + 8 g + e
+    v8h af[RT][KG];
+    double srd[RT];  // sum r' of the lane's output range
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int arow = wrow0 + 16 * rt + c16;
+        const int lq = (arow - row_blk) >> 3, t = arow & 7;
+        const int u = iso_inverse(t);
+        const int a0 = iso_src(B, u, 0, 0);
+        const int a1 = iso_src(B, u, 1, 0) - a0, a2 = iso_src(B, u, 0, 1) - a0;
+        const uint8_t* rr = sPix + lq * n;
+#pragma unroll
+        for (int kg = 0; kg < KG; ++kg)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int m = 32 * kg + 8 * g + e;
+                af[rt][kg][e] = (_Float16)((int)rr[a0 + a1 * (m / B) + a2 * (m % B)] - 128);
+            }
+        const int orow = wrow0 + 16 * rt + 4 * g;
+        srd[rt] = (double)(sSR[(orow - row_blk) >> 3] - 128 * n);
+    }
+    // running best per row of the lane: F, and position << 1 | contrast index
+    double bF[RT][4];
+    int bPU[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            bF[rt][e] = zero_in ? 0.0 : INFINITY;
+            bPU[rt][e] = lo << 1;
+        }
+    const double m80k0 = -80.0 * kz0, m80k1 = NK > 1 ? -80.0 * kz1 : 0.0;
+
+    if (lo < hi) store_stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int base = lo; base < hi; base += COLS, buf ^= 1) {
+        const int nb = base + COLS;
+        if (nb < hi) load_stage(nb, min(COLS, hi - nb));  // in flight while this stage is matched
+        const int cnt = min(COLS, hi - base);
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int col = 16 * ct + c16;
+            v8h bq[KG];
+#pragma unroll
+            for (int kg = 0; kg < KG; ++kg) bq[kg] = __builtin_bit_cast(v8h, sB[buf][col * CH + 4 * kg + g]);
+            v4f acc[RT];
+            const v4f zf = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                v4f x = zf;
+#pragma unroll
+                for (int kg = 0; kg < KG; ++kg) x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][kg], bq[kg], x, 0, 0, 0);
+                acc[rt] = x;
+            }
+            if (col < cnt) {
+                const double ka0 = sKA[buf][0][col], ka1 = NK > 1 ? sKA[buf][NK - 1][col] : 0.0;
+                const double sdd = sSdd[buf][col];
+                const int pu0 = ((base + col) << 1) | u0, pu1 = ((base + col) << 1) | u1;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const double srsd = srd[rt] * sdd;  // exact: below 2^33
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double Bp = fma((double)n, (double)acc[rt][e], -srsd);
+                        const double F0 = fma(m80k0, Bp, ka0);
+                        if (F0 < bF[rt][e]) {
+                            bF[rt][e] = F0;
+                            bPU[rt][e] = pu0;
+                        }
+                        if constexpr (NK > 1) {
+                            const double F1 = fma(m80k1, Bp, ka1);
+                            if (F1 < bF[rt][e]) {
+                                bF[rt][e] = F1;
+                                bPU[rt][e] = pu1;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // the other buffer was last read in the previous stage, before its barrier
+        if (nb < hi) store_stage(buf ^ 1);
+        __syncthreads();
+    }
+    // merge the 16 column lanes of each row: (F, position, index) lexicographic
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int m = 1; m < 16; m <<= 1) {
+                const double of = __shfl_xor(bF[rt][e], m, 64);
+                const int op = __shfl_xor(bPU[rt][e], m, 64);
+                if (of < bF[rt][e] || (of == bF[rt][e] && op < bPU[rt][e])) {
+                    bF[rt][e] = of;
+                    bPU[rt][e] = op;
+                }
+            }
+    // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int orow = wrow0 + 16 * rt + 4 * g;
+        int64_t F = INT64_MAX, K = INT64_MAX;
+        if (lo < hi && orow < nrows && c16 == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int pos = bPU[rt][e] >> 1, u = bPU[rt][e] & 1;
+                const int64_t Fe = (int64_t)bF[rt][e];
+                const int64_t key = make_key(Jd[pos], (orow + e) & 7, u, Sd[pos]);
+                if (pair_less(Fe, key, F, K)) {
+                    F = Fe;
+                    K = key;
+                }
+            }
+        }
+        lex_min_shfl(F, K, 16);
+        if (c16 == 0 && (g & 1) == 0 && orow < nrows) {
+            Partial pr;
+            pr.F = F;
+            pr.key = K;
+            part[(int64_t)(orow >> 3) * n_chunks + c] = pr;
+        }
+    }
+}
 
 // ================================================================ table-driven launches
 // Every quadtree kernel reads its image's arguments from tab[blockIdx.z] (a
@@ -2336,6 +2673,22 @@ __global__ __launch_bounds__(kBlock) void kt_range_prep_i8(Lvl a0, const Lvl* __
         k_range_prep_m8_body<true>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
     else
         k_range_prep_m8_body<false>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
+}
+
+template <int B, bool TAB>
+__global__ __launch_bounds__(kBlock) void kt_pool_prep_mq(Lvl a0, const Lvl* __restrict__ tab, int filtered) {
+    FIC_LV;
+    if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * (B * B / 16)) return;
+    k_pool_prep_mq_body<B>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl,
+                           reinterpret_cast<_Float16*>(a.dh), a.sd, a.ad, a.jd);
+}
+
+template <int B, int NK, bool TAB>
+__global__ __launch_bounds__(kMqWaves * 64) void kt_match_mfq(Lvl a0, const Lvl* __restrict__ tab) {
+    FIC_LV;
+    k_match_mfq_body<B, NK>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv,
+                            reinterpret_cast<const _Float16*>(a.dh), a.sd, a.ad, a.jd, a.pctrl, a.ks, a.nc,
+                            a.cg, a.part, a.sr, a.cr);
 }
 
 template <bool F16, bool TAB>

@@ -290,13 +290,34 @@ bool mfma_eligible(int B, const KSet& ks, int64_t total = 0) {
     return B == 8 && ks.consecutive && ks.k0 == 0 && ks.n >= 3 && total < kM8MaxPool;
 }
 
+// Nonzero values of a contrast set.
+int nonzero_values(const KSet& ks) {
+    int c = 0;
+    for (int u = 0; u < ks.n; ++u) c += ks.k[u] != 0;
+    return c;
+}
+
+// The FP16 MFMA matcher for small sets serves B = 8 and 16 with one or two
+// values, at least one of them nonzero, on grids below kMqMaxPool domains.
+bool mfq_eligible(int B, const KSet& ks, int64_t total = 0) {
+    return (B == 8 || B == 16) && match_mode(ks) == kModeSmall && nonzero_values(ks) >= 1 &&
+           total < kMqMaxPool;
+}
+
+// Matcher a level gets by default.
+int auto_var(int B, const KSet& ks, int64_t total) {
+    if (mfma_eligible(B, ks, total)) return kVarMfma16;
+    if (mfq_eligible(B, ks, total)) return kVarMfq;
+    return kVarValu;
+}
+
 // Host plan of one level of one image.
 struct Level {
     int lv, B, L, gy, gx, total;  // domain grid
     int max_act;                  // worst-case active ranges
     int nc;                       // pool chunks of the matcher
     int cg;                       // domains per pool chunk
-    int var;                      // kVarValu, kVarMfma, kVarFp32 or kVarMfma16
+    int var;                      // kVarValu, kVarMfma, kVarFp32, kVarMfma16 or kVarMfq
     KSet ks;
 };
 
@@ -304,6 +325,7 @@ bool is_mfma8(int var) { return var == kVarMfma || var == kVarMfma16; }
 
 int default_cg(int B, int var) {
     if (is_mfma8(var)) return kM8Chunk;
+    if (var == kVarMfq) return mq_cols(B);
     if (var == kVarFp32) return 256;
     return match_chunk_domains(B);
 }
@@ -311,9 +333,7 @@ int default_cg(int B, int var) {
 Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks, int variant = 0,
                  int cg = 0) {
     Level v;
-    v.var = variant != 0 ? variant
-                         : (mfma_eligible(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1))
-                                ? kVarMfma16 : kVarValu);
+    v.var = variant != 0 ? variant : auto_var(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1));
     v.lv = lv;
     v.B = B;
     v.L = L;
@@ -326,6 +346,7 @@ Level make_level(int lv, int H, int W, int B, int L, int max_act, const KSet& ks
     // enough workgroups to fill the chip when the pool is large, at most one
     // chunk per cg domains and 64 chunks
     const int rows_per_block = is_mfma8(v.var) ? m8_rows(v.var == kVarMfma16)
+                               : v.var == kVarMfq ? mq_rows(B)
                                : v.var == kVarFp32 ? kBlock
                                                    : 8 * match_ranges_per_block(B, match_mode(ks));
     const int row_blocks = cdiv((int64_t)8 * max_act, rows_per_block);
@@ -340,6 +361,7 @@ struct Sizes {
     size_t rng = 0, part = 0, blk = 0, act = 0, ar = 0;                // range side, all levels
     size_t key[kLevels] = {}, hl[kLevels] = {}, dom[kLevels] = {};      // domain side, per level
     size_t pblk[kLevels] = {}, dcol[kLevels] = {};
+    size_t dq[kLevels] = {};  // FP16 pool columns of the small-set MFMA matcher, bytes
 };
 
 void grow(Sizes& s, const Level& v) {
@@ -357,6 +379,7 @@ void grow(Sizes& s, const Level& v) {
         s.ar = std::max(s.ar, (size_t)v.max_act * 8 * 64 * 2);  // int8 rows, or FP16 (2 bytes)
         s.dcol[l] = std::max(s.dcol[l], (size_t)v.total);
     }
+    if (v.var == kVarMfq) s.dq[l] = std::max(s.dq[l], (size_t)v.total * n * 2);
 }
 
 int ensure_sizes(Workspace& ws, const Sizes& s) {
@@ -371,6 +394,7 @@ int ensure_sizes(Workspace& ws, const Sizes& s) {
         if ((rc = ensure(ws, pb.ad, s.dom[l] * 8))) return rc;
         if ((rc = ensure(ws, pb.jd, s.dom[l] * 4))) return rc;
         if ((rc = ensure(ws, pb.blk, s.pblk[l]))) return rc;
+        if (s.dq[l] && (rc = ensure(ws, pb.dh, s.dq[l]))) return rc;
         if (s.dcol[l]) {
             if ((rc = ensure(ws, pb.dh, s.dcol[l] * 128))) return rc;  // h rows, or FP16 columns
             if ((rc = ensure(ws, pb.dl, s.dcol[l] * 64))) return rc;
@@ -514,6 +538,13 @@ void launch_pool_prep(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, h
         kt_pool_prep_i8<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
         return;
     }
+    if constexpr (B == 8 || B == 16) {
+        if (h[0].var == kVarMfq) {
+            const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * (B * B / 16), kBlock); });
+            kt_pool_prep_mq<B, TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
+            return;
+        }
+    }
     const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * PrepShape<B>::TPD, kBlock); });
     kt_pool_prep<B, TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
 }
@@ -544,6 +575,15 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
         ProfScope ps("match_b8_fp32", st);
         kt_match_fp32<TAB><<<dim3(cdiv(max_act, kBlock / 8), max_nc, n), kBlock, 0, st>>>(h[0], dt);
         return;
+    }
+    if constexpr (B == 8 || B == 16) {
+        if (a0.var == kVarMfq) {
+            ProfScope ps(B == 8 ? "match_b8_mfq" : "match_b16_mfq", st);
+            const dim3 grid(cdiv((int64_t)8 * max_act, mq_rows(B)), max_nc, n);
+            if (nonzero_values(a0.ks) > 1) kt_match_mfq<B, 2, TAB><<<grid, kMqWaves * 64, 0, st>>>(h[0], dt);
+            else kt_match_mfq<B, 1, TAB><<<grid, kMqWaves * 64, 0, st>>>(h[0], dt);
+            return;
+        }
     }
     ProfScope ps(match_label(B), st);
     const int mode = match_mode(a0.ks);
@@ -687,11 +727,12 @@ int check_params(const fic_params* p, std::vector<KSet>& ks) {
 
 // Per-level plans of one image's quadtree.
 std::vector<Level> quad_levels(int H, int W, const fic_params* p, const std::vector<KSet>& ks,
-                               const int* cg = nullptr) {
+                               const int* cg = nullptr, const int* var = nullptr) {
     std::vector<Level> lv;
     for (int l = 0; l < p->n_levels; ++l) {
         const int B = p->B0 >> l;
-        lv.push_back(make_level(l, H, W, B, p->L[l], (H / B) * (W / B), ks[l], 0, cg ? cg[l] : 0));
+        lv.push_back(make_level(l, H, W, B, p->L[l], (H / B) * (W / B), ks[l], var ? var[l] : 0,
+                                cg ? cg[l] : 0));
     }
     return lv;
 }
@@ -844,18 +885,27 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     if (n_ranges > 0 && !out) return fail(FIC_EINVAL, "out is NULL");
     if (variant < FIC_MATCH_AUTO || variant > FIC_MATCH_MFMA_F16)
         return fail(FIC_EINVAL, "matcher variant %d unknown", variant);
-    const bool mf = variant == FIC_MATCH_MFMA_I8 || variant == FIC_MATCH_MFMA_F16;
+    const int64_t grid_total = (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1);
+    // FP16 MFMA: the grid form (B = 8, 0..k1) or the small-set form (B = 8, 16)
+    const bool f16_small = variant == FIC_MATCH_MFMA_F16 && !mfma_eligible(B, ks) && mfq_eligible(B, ks);
+    const bool mf = variant == FIC_MATCH_MFMA_I8 || (variant == FIC_MATCH_MFMA_F16 && !f16_small);
     if ((mf || variant == FIC_MATCH_FP32) && !mfma_eligible(B, ks))
-        return fail(FIC_EINVAL, "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2)",
+        return fail(FIC_EINVAL,
+                    variant == FIC_MATCH_MFMA_F16
+                        ? "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2), or B = 8 or 16 "
+                          "and one or two values, one of them nonzero"
+                        : "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2)",
                     variant);
-    if (mf && !mfma_eligible(B, ks, (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1)))
+    if (mf && !mfma_eligible(B, ks, grid_total))
         return fail(FIC_EINVAL, "the MFMA matchers take domain grids below %d domains", kM8MaxPool);
+    if (f16_small && !mfq_eligible(B, ks, grid_total))
+        return fail(FIC_EINVAL, "the small-set MFMA matcher takes domain grids below %d domains", kMqMaxPool);
     if (n_ranges == 0) return FIC_OK;
     Workspace* ws;
     if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
     const int var = variant == FIC_MATCH_VALU ? kVarValu
                     : variant == FIC_MATCH_MFMA_I8 ? kVarMfma
-                    : variant == FIC_MATCH_MFMA_F16 ? kVarMfma16
+                    : variant == FIC_MATCH_MFMA_F16 ? (f16_small ? kVarMfq : kVarMfma16)
                     : variant == FIC_MATCH_FP32 ? kVarFp32 : 0;
     Level v = make_level(0, H, W, B, L, n_ranges, ks, var);
     Sizes sz;
@@ -1241,9 +1291,15 @@ int batch_build(fic_batch* b) {
     batch_drop_graph(b);
     const int n = (int)b->im.size(), nl = b->p.n_levels;
     std::vector<Lvl> tab((size_t)nl * n);
+    // one matcher per level for the whole batch: the one the largest image (first) gets
+    std::vector<int> var(nl);
+    {
+        const std::vector<Level> lv0 = quad_levels(b->im[0].H, b->im[0].W, &b->p, b->ks, b->cg.data());
+        for (int l = 0; l < nl; ++l) var[l] = lv0[l].var;
+    }
     for (int i = 0; i < n; ++i) {
         BatchImage& m = b->im[i];
-        std::vector<Level> lv = quad_levels(m.H, m.W, &b->p, b->ks, b->cg.data());
+        std::vector<Level> lv = quad_levels(m.H, m.W, &b->p, b->ks, b->cg.data(), var.data());
         Sizes sz;
         for (const Level& v : lv) grow(sz, v);
         int rc = ensure_sizes(*m.ws, sz);
@@ -1298,7 +1354,7 @@ int batch_time(fic_batch* b, hipStream_t s, int reps, float* ms) {
 int batch_chunk(const fic_batch* b, int l) {
     if (b->cg[l] > 0) return b->cg[l];
     const int B = b->p.B0 >> l;
-    return default_cg(B, mfma_eligible(B, b->ks[l]) ? kVarMfma16 : kVarValu);
+    return default_cg(B, auto_var(B, b->ks[l], 0));
 }
 
 uint64_t fnv1a(uint64_t h, const void* data, size_t n) {

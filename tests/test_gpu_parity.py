@@ -356,6 +356,58 @@ def test_mfma_ragged_ranges_and_pool(dev, variant):
     check_level(dev, img, 8, 2, oracle.PLAIN_K, entropy=1, min_pool=300, variant=variant)
 
 
+# ------------------------------------------------------------------ FP16 MFMA, small sets (B = 8, 16)
+SMALL_SETS = [(1,), (3,), (2, 4), (5, 9), (0, 7), (9,)]
+
+
+@pytest.mark.parametrize("B", [8, 16])
+@pytest.mark.parametrize("kind", ["constant", "half_flat", "noise", "two_tone", "blobs"])
+def test_mfq_small_sets_adversarial(dev, B, kind):
+    """The small-set FP16 MFMA matcher against the oracle: constant ranges and
+    domains (F = 0 ties, B' = 0), saturated noise, and every preset shape of set
+    (one value, two values, a set holding 0)."""
+    rng = np.random.default_rng(5)
+    if kind == "constant":
+        img = np.full((80, 96), 201, np.uint8)
+    elif kind == "half_flat":
+        img = rng.integers(0, 256, size=(80, 96)).astype(np.uint8)
+        img[:, :48] = 77
+        img[:32, 64:] = 3
+    elif kind == "noise":
+        img = rng.integers(0, 256, size=(80, 96)).astype(np.uint8)
+    elif kind == "two_tone":
+        img = (rng.integers(0, 2, size=(80, 96)) * 255).astype(np.uint8)
+    else:
+        img = synth.gradients_blobs(96, seed=4)[:80]
+    for ks in SMALL_SETS:
+        check_level(dev, img, B, 3, ks, variant=fic.MATCH_MFMA_F16)
+
+
+@pytest.mark.parametrize("B", [8, 16])
+def test_mfq_ragged_ranges_and_pool(dev, B):
+    img = synth.power_law(144, 160, beta=1.8, seed=9)
+    rng = np.random.default_rng(3)
+    corners = oracle.full_ranges(144, 160, B)
+    sub = corners[np.sort(rng.choice(len(corners), min(37, len(corners) - 3), replace=False))]
+    check_level(dev, img, B, 5, (2, 4), ranges=sub, variant=fic.MATCH_MFMA_F16)
+    check_level(dev, img, B, 2, (3,), entropy=1, min_pool=200, variant=fic.MATCH_MFMA_F16)
+    check_level(dev, img, B, 1, (0, 9), entropy=1, min_pool=3000, variant=fic.MATCH_MFMA_F16)
+
+
+@pytest.mark.parametrize("B,L,ks", [(16, 8, (1,)), (16, 4, (5, 9)), (8, 4, (3,)), (8, 2, (2, 4)),
+                                    (8, 4, (0, 5))])
+def test_mfq_equals_valu_at_512(dev, B, L, ks):
+    """The quadtree image at full size: the FP16 small-set matcher equals the dot4
+    VALU matcher on every range, with the whole grid and with the entropy pool."""
+    img = synth.quadtree_image(0)
+    for entropy in (0, 1):
+        say(f"[level] 512 B={B} L={L} ks={ks} entropy={entropy}: FP16 MFMA vs VALU")
+        got, _ = gpu_level(dev, img, B, L, ks, entropy=entropy, variant=fic.MATCH_MFMA_F16)
+        valu, _ = gpu_level(dev, img, B, L, ks, entropy=entropy, variant=fic.MATCH_VALU)
+        for f in ("e_num", "dom", "iso", "s_idx", "k", "q_o"):
+            assert np.array_equal(got[f], valu[f]), f
+
+
 def test_mfma_in_quadtree_unfiltered(dev):
     img = synth.power_law(96, beta=2.0, seed=5, n_rect=2)
     say("[quadtree] plain grid, MFMA level")
