@@ -38,11 +38,11 @@ def match_ops(n: int, n_s: int) -> int:
 
 def level_ops(B: int, matches: int, n_s: int) -> dict:
     """Algorithmic work of one level's matcher, by the label it is profiled under:
-    the VALU matcher's integer ops, or (B = 8 and 16 with small sets, on FP16 MFMA)
+    the VALU matcher's integer ops, or (B = 4, 8 and 16 with small sets, on FP16 MFMA)
     the correlation's 2n flops per match against the FP16 MFMA peak."""
     n = B * B
     out = {f"match_b{B}": matches * match_ops(n, n_s)}
-    if B in (8, 16):
+    if B in (4, 8, 16):
         out[f"match_b{B}_mfq"] = (matches * 2 * n, "mfma", PEAK_FP16_TFLOPS, "TFLOP/s")
     return out
 

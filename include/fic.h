@@ -157,15 +157,15 @@ enum fic_match_variant {
     FIC_MATCH_MFMA_F16 = 4  /* FP16 MFMA correlation, FP32 accumulation (exact: every   */
                             /* partial sum is an integer below 2^24). Contrast grid at   */
                             /* B = 8: same screen and exact decision as MFMA_I8. One or  */
-                            /* two values at B = 8 or 16 (centred operands): F exact in  */
-                            /* FP64 per element. AUTO takes it wherever it applies       */
+                            /* two values at B = 4, 8 or 16 (centred operands): F exact  */
+                            /* in FP64 per element. AUTO takes it wherever it applies    */
 };
 
 /*
  * fic_encode_level with an explicit matcher. FIC_MATCH_MFMA_I8, MFMA_F16 and
  * FIC_MATCH_FP32 need B = 8 and a contrast set 0, 1, ..., k1 with k1 >= 2;
  * the MFMA matchers also need a domain grid of fewer than 2^22 domains.
- * FIC_MATCH_MFMA_F16 also takes B = 8 or 16 with one or two contrast values,
+ * FIC_MATCH_MFMA_F16 also takes B = 4, 8 or 16 with one or two contrast values,
  * at least one nonzero, on a domain grid of fewer than 2^21 domains
  * (FIC_EINVAL otherwise; AUTO then takes the VALU matcher). VALU, MFMA_I8,
  * MFMA_F16 and AUTO return the exact result.

@@ -2200,8 +2200,8 @@ __device__ __forceinline__ void k_reduce_fp32_body(const uint8_t* __restrict__ i
 
 
 // ================================================================ FP16 MFMA matcher for small contrast sets
-// The 8 x 8 and 16 x 16 quadtree levels with one or two predefined contrast
-// values (Section 3.1), on v_mfma_f32_16x16x32_f16. Operands are centred:
+// The 4 x 4, 8 x 8 and 16 x 16 quadtree levels with one or two predefined
+// contrast values (Section 3.1), on FP16 MFMA. Operands are centred:
 // r' = r - 128 in [-128, 127] and d'' = d' - 510 in [-510, 510] are exact in
 // FP16, and every partial sum of X = sum r' d'' is an integer of magnitude at
 // most n * 128 * 510 < 2^24 (n <= 256), so the FP32 accumulator holds X
@@ -2222,8 +2222,26 @@ __device__ __forceinline__ void k_reduce_fp32_body(const uint8_t* __restrict__ i
 constexpr int kMqWaves = 4;
 constexpr int mq_row_tiles(int B) { return B == 16 ? 1 : 2; }
 constexpr int mq_rows(int B) { return kMqWaves * 16 * mq_row_tiles(B); }  // rows per workgroup
-constexpr int mq_cols(int B) { return B == 16 ? 32 : 64; }               // pool domains per LDS stage
+constexpr int mq_cols(int B) { return B == 16 ? 32 : (B == 8 ? 64 : 128); }  // pool domains per LDS stage
 constexpr int kMqMaxPool = 1 << 21;
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+
+// Operand shapes: B = 8, 16 take v_mfma_f32_16x16x32_f16 (K = 32 per
+// instruction, 8 halves per lane); B = 4 (n = 16) takes
+// v_mfma_f32_16x16x16_f16 (K = 16, 4 halves per lane). LDS holds each column
+// in U-byte units, one unit of padding per column.
+template <int B> struct MqShape {
+    static constexpr int KW = 32, KG = B * B / 32, U = 16;
+    using AF = v8h;
+    using LU = v4i;
+    __device__ static v4f mfma(AF a, AF b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <> struct MqShape<4> {
+    static constexpr int KW = 16, KG = 1, U = 8;
+    using AF = v4h;
+    using LU = uint2;
+    __device__ static v4f mfma(AF a, AF b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+};
 
 // Columns of the small-set MFMA matcher: the n values d'' = d' - 510 of each
 // pool domain in FP16 at Dh (2n bytes per domain), and S, A', j as for the
@@ -2285,15 +2303,19 @@ __device__ __forceinline__ void k_match_mfq_body(
     const _Float16* __restrict__ Dh, const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad,
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, const KSet& ks, int n_chunks, int cg,
     Partial* __restrict__ part, int32_t* __restrict__ SRout, int64_t* __restrict__ CRout) {
-    constexpr int n = B * B, KG = n / 32, RT = mq_row_tiles(B), ROWS = mq_rows(B);
+    using Sh = MqShape<B>;
+    using AF = typename Sh::AF;
+    using LU = typename Sh::LU;
+    constexpr int n = B * B, KG = Sh::KG, KW = Sh::KW, RT = mq_row_tiles(B), ROWS = mq_rows(B);
     constexpr int NR = ROWS / 8;                // ranges per workgroup
     constexpr int COLS = mq_cols(B), CT = COLS / 16;
-    constexpr int CPC = n / 8;                  // 16-byte chunks per column
-    constexpr int CH = CPC + 1;                 // LDS stride per column (one chunk of padding)
+    constexpr int CPC = n / 8;                  // 16-byte chunks per column in memory
+    constexpr int UPC = 2 * n / Sh::U;          // LDS units per column
+    constexpr int CH = UPC + 1;                 // LDS stride per column (one unit of padding)
     constexpr int NT = kMqWaves * 64;
     constexpr int NLD = COLS * CPC / NT;        // chunks per thread per stage
     static_assert(COLS * CPC % NT == 0 && COLS <= NT, "stage split over the workgroup");
-    __shared__ v4i sB[2][COLS * CH];
+    __shared__ LU sB[2][COLS * CH];
     __shared__ double sKA[2][NK][COLS];         // k^2 A' per column and nonzero value
     __shared__ double sSdd[2][COLS];            // sum d'' = S - 510 n
     __shared__ uint8_t sPix[NR * n];
@@ -2349,7 +2371,12 @@ __device__ __forceinline__ void k_match_mfq_body(
 #pragma unroll
         for (int i = 0; i < NLD; ++i) {
             const int ci = threadIdx.x + NT * i, col = ci / CPC, uu = ci % CPC;
-            sB[bf][col * CH + uu] = ld[i];
+            if constexpr (Sh::U == 16) {
+                sB[bf][col * CH + uu] = ld[i];
+            } else {  // two 8-byte units per 16-byte chunk
+                sB[bf][col * CH + 2 * uu] = make_uint2((uint32_t)ld[i][0], (uint32_t)ld[i][1]);
+                sB[bf][col * CH + 2 * uu + 1] = make_uint2((uint32_t)ld[i][2], (uint32_t)ld[i][3]);
+            }
         }
         if (threadIdx.x < COLS) {
             const int t = threadIdx.x;
@@ -2408,8 +2435,8 @@ __device__ __forceinline__ void k_match_mfq_body(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int wrow0 = row_blk + wave * 16 * RT;
 
-    // A operands: row 16 rt + c16 of the wave, K = 32 kg + 8 g + e
-    v8h af[RT][KG];
+    // A operands: row 16 rt + c16 of the wave, K = KW kg + (KW / 4) g + e
+    AF af[RT][KG];
     double srd[RT];  // sum r' of the lane's output range
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -2422,8 +2449,8 @@ __device__ __forceinline__ void k_match_mfq_body(
 #pragma unroll
         for (int kg = 0; kg < KG; ++kg)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int m = 32 * kg + 8 * g + e;
+            for (int e = 0; e < KW / 4; ++e) {
+                const int m = KW * kg + (KW / 4) * g + e;
                 af[rt][kg][e] = (_Float16)((int)rr[a0 + a1 * (m / B) + a2 * (m % B)] - 128);
             }
         const int orow = wrow0 + 16 * rt + 4 * g;
@@ -2451,16 +2478,16 @@ __device__ __forceinline__ void k_match_mfq_body(
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             const int col = 16 * ct + c16;
-            v8h bq[KG];
+            AF bq[KG];
 #pragma unroll
-            for (int kg = 0; kg < KG; ++kg) bq[kg] = __builtin_bit_cast(v8h, sB[buf][col * CH + 4 * kg + g]);
+            for (int kg = 0; kg < KG; ++kg) bq[kg] = __builtin_bit_cast(AF, sB[buf][col * CH + 4 * kg + g]);
             v4f acc[RT];
             const v4f zf = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 v4f x = zf;
 #pragma unroll
-                for (int kg = 0; kg < KG; ++kg) x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][kg], bq[kg], x, 0, 0, 0);
+                for (int kg = 0; kg < KG; ++kg) x = Sh::mfma(af[rt][kg], bq[kg], x);
                 acc[rt] = x;
             }
             if (col < cnt) {

@@ -297,10 +297,10 @@ int nonzero_values(const KSet& ks) {
     return c;
 }
 
-// The FP16 MFMA matcher for small sets serves B = 8 and 16 with one or two
+// The FP16 MFMA matcher for small sets serves B = 4, 8 and 16 with one or two
 // values, at least one of them nonzero, on grids below kMqMaxPool domains.
 bool mfq_eligible(int B, const KSet& ks, int64_t total = 0) {
-    return (B == 8 || B == 16) && match_mode(ks) == kModeSmall && nonzero_values(ks) >= 1 &&
+    return (B == 4 || B == 8 || B == 16) && match_mode(ks) == kModeSmall && nonzero_values(ks) >= 1 &&
            total < kMqMaxPool;
 }
 
@@ -538,7 +538,7 @@ void launch_pool_prep(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, h
         kt_pool_prep_i8<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
         return;
     }
-    if constexpr (B == 8 || B == 16) {
+    if constexpr (B == 4 || B == 8 || B == 16) {
         if (h[0].var == kVarMfq) {
             const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * (B * B / 16), kBlock); });
             kt_pool_prep_mq<B, TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
@@ -576,9 +576,9 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
         kt_match_fp32<TAB><<<dim3(cdiv(max_act, kBlock / 8), max_nc, n), kBlock, 0, st>>>(h[0], dt);
         return;
     }
-    if constexpr (B == 8 || B == 16) {
+    if constexpr (B == 4 || B == 8 || B == 16) {
         if (a0.var == kVarMfq) {
-            ProfScope ps(B == 8 ? "match_b8_mfq" : "match_b16_mfq", st);
+            ProfScope ps(B == 4 ? "match_b4_mfq" : (B == 8 ? "match_b8_mfq" : "match_b16_mfq"), st);
             const dim3 grid(cdiv((int64_t)8 * max_act, mq_rows(B)), max_nc, n);
             if (nonzero_values(a0.ks) > 1) kt_match_mfq<B, 2, TAB><<<grid, kMqWaves * 64, 0, st>>>(h[0], dt);
             else kt_match_mfq<B, 1, TAB><<<grid, kMqWaves * 64, 0, st>>>(h[0], dt);
@@ -886,13 +886,13 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     if (variant < FIC_MATCH_AUTO || variant > FIC_MATCH_MFMA_F16)
         return fail(FIC_EINVAL, "matcher variant %d unknown", variant);
     const int64_t grid_total = (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1);
-    // FP16 MFMA: the grid form (B = 8, 0..k1) or the small-set form (B = 8, 16)
+    // FP16 MFMA: the grid form (B = 8, 0..k1) or the small-set form (B = 4, 8, 16)
     const bool f16_small = variant == FIC_MATCH_MFMA_F16 && !mfma_eligible(B, ks) && mfq_eligible(B, ks);
     const bool mf = variant == FIC_MATCH_MFMA_I8 || (variant == FIC_MATCH_MFMA_F16 && !f16_small);
     if ((mf || variant == FIC_MATCH_FP32) && !mfma_eligible(B, ks))
         return fail(FIC_EINVAL,
                     variant == FIC_MATCH_MFMA_F16
-                        ? "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2), or B = 8 or 16 "
+                        ? "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2), or B = 4, 8 or 16 "
                           "and one or two values, one of them nonzero"
                         : "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2)",
                     variant);

@@ -119,8 +119,8 @@ def test_encode_level_ex_rejects_variants(lib):
     for v in (fic.MATCH_MFMA_I8, fic.MATCH_MFMA_F16):
         assert call(4, 11, v) == fic.FIC_EINVAL and "B = 8" in lib.fic_last_error().decode()
     assert call(8, 2, fic.MATCH_MFMA_I8) == fic.FIC_EINVAL
-    # the FP16 form also takes one or two values at B = 8 and 16, one of them nonzero
-    assert call(4, 2, fic.MATCH_MFMA_F16) == fic.FIC_EINVAL
+    # the FP16 form also takes one or two values at B = 4, 8 and 16, one of them nonzero
+    assert call(2, 2, fic.MATCH_MFMA_F16) == fic.FIC_EINVAL
     assert call(16, 11, fic.MATCH_MFMA_F16) == fic.FIC_EINVAL
     assert call(8, 1, fic.MATCH_MFMA_F16) == fic.FIC_EINVAL  # {0}: nothing to screen
     assert call(16, 11, fic.MATCH_FP32) == fic.FIC_EINVAL

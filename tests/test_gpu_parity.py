@@ -356,11 +356,11 @@ def test_mfma_ragged_ranges_and_pool(dev, variant):
     check_level(dev, img, 8, 2, oracle.PLAIN_K, entropy=1, min_pool=300, variant=variant)
 
 
-# ------------------------------------------------------------------ FP16 MFMA, small sets (B = 8, 16)
+# ------------------------------------------------------------------ FP16 MFMA, small sets (B = 4, 8, 16)
 SMALL_SETS = [(1,), (3,), (2, 4), (5, 9), (0, 7), (9,)]
 
 
-@pytest.mark.parametrize("B", [8, 16])
+@pytest.mark.parametrize("B", [4, 8, 16])
 @pytest.mark.parametrize("kind", ["constant", "half_flat", "noise", "two_tone", "blobs"])
 def test_mfq_small_sets_adversarial(dev, B, kind):
     """The small-set FP16 MFMA matcher against the oracle: constant ranges and
@@ -383,7 +383,7 @@ def test_mfq_small_sets_adversarial(dev, B, kind):
         check_level(dev, img, B, 3, ks, variant=fic.MATCH_MFMA_F16)
 
 
-@pytest.mark.parametrize("B", [8, 16])
+@pytest.mark.parametrize("B", [4, 8, 16])
 def test_mfq_ragged_ranges_and_pool(dev, B):
     img = synth.power_law(144, 160, beta=1.8, seed=9)
     rng = np.random.default_rng(3)
@@ -395,7 +395,7 @@ def test_mfq_ragged_ranges_and_pool(dev, B):
 
 
 @pytest.mark.parametrize("B,L,ks", [(16, 8, (1,)), (16, 4, (5, 9)), (8, 4, (3,)), (8, 2, (2, 4)),
-                                    (8, 4, (0, 5))])
+                                    (8, 4, (0, 5)), (4, 2, (9,)), (4, 2, (3, 8)), (4, 1, (0, 4))])
 def test_mfq_equals_valu_at_512(dev, B, L, ks):
     """The quadtree image at full size: the FP16 small-set matcher equals the dot4
     VALU matcher on every range, with the whole grid and with the entropy pool."""
