@@ -2623,6 +2623,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_var(Lvl a0, const Lvl* __restr
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_copy_pool(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
+    if (!a.pools_out) return;
     const int n = a.pctrl->pool_count;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) a.pools_out[i] = a.pool[i];
 }

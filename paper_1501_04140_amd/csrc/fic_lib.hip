@@ -76,6 +76,11 @@ struct Workspace {
     Buf plan;     // bitstream section offsets
     hipStream_t side[kLevels] = {};  // one per level's pool phase (default priority)
     hipEvent_t ev_fork = nullptr, ev_pool[kLevels] = {};
+    // device copy of one image's level arguments (the pool steps of several
+    // levels share launches through it) and its host mirror
+    Lvl* dlv = nullptr;
+    Lvl hlv[kLevels];
+    int nlv = 0;
 };
 
 std::mutex g_mu;
@@ -130,6 +135,24 @@ int ensure_fork(Workspace& ws) {
         HIP_TRY(hipEventCreateWithFlags(&ws.ev_pool[l], hipEventDisableTiming));
     }
     HIP_TRY(hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming));
+    if (hipMalloc(&ws.dlv, sizeof(Lvl) * kLevels) != hipSuccess) {
+        ws.dlv = nullptr;
+        return fail(FIC_ENOMEM, "hipMalloc of the level table failed");
+    }
+    return FIC_OK;
+}
+
+// Device copy of an image's level arguments, rewritten only when they change
+// (after the work that may still read the old copy has finished).
+int upload_levels(Workspace& ws, const std::vector<Lvl>& t) {
+    const int n = (int)t.size();
+    if (n == ws.nlv && std::memcmp(ws.hlv, t.data(), sizeof(Lvl) * n) == 0) return FIC_OK;
+    HIP_TRY(hipStreamSynchronize(ws.stream));
+    for (hipStream_t sd : ws.side)
+        if (sd) HIP_TRY(hipStreamSynchronize(sd));
+    std::memcpy(ws.hlv, t.data(), sizeof(Lvl) * n);
+    ws.nlv = n;
+    HIP_TRY(hipMemcpy(ws.dlv, ws.hlv, sizeof(Lvl) * n, hipMemcpyHostToDevice));
     return FIC_OK;
 }
 
@@ -166,6 +189,7 @@ void free_ws(Workspace* ws) {
         if (ws->ev_pool[l]) (void)hipEventDestroy(ws->ev_pool[l]);
     }
     if (ws->ev_fork) (void)hipEventDestroy(ws->ev_fork);
+    if (ws->dlv) (void)hipFree(ws->dlv);
     (void)hipFree(ws->ctrl);
     (void)hipFree(ws->T);
     delete ws;
@@ -595,52 +619,66 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
 
 // Pool of one level: the entropy (or variance) filter of Section 3, or the
 // whole grid, and the pool's moments, for h.size() images whose arguments are
-// at dt (by value when dt is NULL).
+// at dt (by value when dt is NULL). Three steps: the keys, the selection
+// (which reads only the level's arguments, so levels of different B can share
+// its launches), and the moments.
 template <bool TAB>
-int launch_pool_phase_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
-                        hipStream_t st) {
+void launch_score_step(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
+    ProfScope ps("pool_score", st);
+    switch (2 * h[0].B) {
+        case 4: launch_score<4, TAB>(dt, h, T, st); break;
+        case 8: launch_score<8, TAB>(dt, h, T, st); break;
+        case 16: launch_score<16, TAB>(dt, h, T, st); break;
+        default: launch_score<32, TAB>(dt, h, T, st); break;
+    }
+}
+
+template <bool TAB>
+void launch_select_steps(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
     const int n = (int)h.size();
-    const int B = h[0].B;
-    if (filtered) {
-        {
-            ProfScope ps("pool_score", st);
-            switch (2 * B) {
-                case 4: launch_score<4, TAB>(dt, h, T, st); break;
-                case 8: launch_score<8, TAB>(dt, h, T, st); break;
-                case 16: launch_score<16, TAB>(dt, h, T, st); break;
-                default: launch_score<32, TAB>(dt, h, T, st); break;
-            }
-        }
-        // small grids: one workgroup stages every key and builds the pool itself
-        const bool direct = max_over(h, [](const Lvl& a) { return a.total; }) <= kSelStage;
-        if (!direct) {
-            {
-                ProfScope ps("pool_select", st);
-                const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, a.bound_chunk); });
-                kt_floor_bound<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
-            }
-            {
-                ProfScope ps("pool_compact", st);
-                const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
-                kt_pool_count<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
-                kt_pool_scatter<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
-            }
-        }
+    // small grids: one workgroup stages every key and builds the pool itself
+    const bool direct = max_over(h, [](const Lvl& a) { return a.total; }) <= kSelStage;
+    if (!direct) {
         {
             ProfScope ps("pool_select", st);
-            kt_floor_select<TAB><<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt, direct ? 1 : 0);
+            const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, a.bound_chunk); });
+            kt_floor_bound<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
-        if (h[0].pools_out) {
-            const int gx = max_over(h, [](const Lvl& a) { return std::min(cdiv(a.total, kBlock), 1024); });
-            kt_copy_pool<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+        {
+            ProfScope ps("pool_compact", st);
+            const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
+            kt_pool_count<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+            kt_pool_scatter<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
     }
-    switch (B) {
+    {
+        ProfScope ps("pool_select", st);
+        kt_floor_select<TAB><<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt, direct ? 1 : 0);
+    }
+    if (std::any_of(h.begin(), h.end(), [](const Lvl& a) { return a.pools_out != nullptr; })) {
+        const int gx = max_over(h, [](const Lvl& a) { return std::min(cdiv(a.total, kBlock), 1024); });
+        kt_copy_pool<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+    }
+}
+
+template <bool TAB>
+void launch_prep_step(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, hipStream_t st) {
+    switch (h[0].B) {
         case 2: launch_pool_prep<2, TAB>(dt, h, filtered, st); break;
         case 4: launch_pool_prep<4, TAB>(dt, h, filtered, st); break;
         case 8: launch_pool_prep<8, TAB>(dt, h, filtered, st); break;
         default: launch_pool_prep<16, TAB>(dt, h, filtered, st); break;
     }
+}
+
+template <bool TAB>
+int launch_pool_phase_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
+                        hipStream_t st) {
+    if (filtered) {
+        launch_score_step<TAB>(dt, h, T, st);
+        launch_select_steps<TAB>(dt, h, st);
+    }
+    launch_prep_step<TAB>(dt, h, filtered, st);
     LAUNCH_CHECK();
     return FIC_OK;
 }
@@ -766,6 +804,53 @@ struct Group {
     int start, count;
 };
 
+// One image with its level arguments also on the device (fork->dlv): level
+// 0's pool and matcher on the caller's stream; level 1's pool on a side
+// stream of its own (its matcher comes next); the pools of levels 2.. on a
+// second side stream, their selection steps shared by those levels (level =
+// blockIdx.z). Fewer launches and events than a stream per level: the host
+// queues the encode sooner.
+int launch_quadtree_one(const std::vector<Lvl>& t, const int64_t* T, bool filtered, hipStream_t st,
+                        Workspace& fork) {
+    const int nl = (int)t.size();
+    int rc;
+    {
+        const int gx = cdiv((t[0].H / t[0].B) * (t[0].W / t[0].B), kBlock);
+        kt_act_full<false><<<gx, kBlock, 0, st>>>(t[0], nullptr, 1);
+    }
+    HIP_TRY(hipEventRecord(fork.ev_fork, st));
+    const std::vector<Lvl> h0{t[0]};
+    if ((rc = launch_pool_phase(nullptr, h0, T, filtered, st))) return rc;
+    if ((rc = launch_match_phase(nullptr, h0, st))) return rc;
+    if ((rc = launch_quad(nullptr, h0, st))) return rc;
+    // level 1
+    hipStream_t p1 = fork.side[1];
+    HIP_TRY(hipStreamWaitEvent(p1, fork.ev_fork, 0));
+    const std::vector<Lvl> h1{t[1]};
+    if ((rc = launch_pool_phase(nullptr, h1, T, filtered, p1))) return rc;
+    HIP_TRY(hipEventRecord(fork.ev_pool[1], p1));
+    // levels 2..
+    if (nl > 2) {
+        hipStream_t p2 = fork.side[2];
+        HIP_TRY(hipStreamWaitEvent(p2, fork.ev_fork, 0));
+        const std::vector<Lvl> rest(t.begin() + 2, t.end());
+        if (filtered) {
+            for (const Lvl& a : rest) launch_score_step<false>(nullptr, {a}, T, p2);
+            launch_select_steps<true>(fork.dlv + 2, rest, p2);
+        }
+        for (const Lvl& a : rest) launch_prep_step<false>(nullptr, {a}, filtered, p2);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(fork.ev_pool[2], p2));
+    }
+    for (int l = 1; l < nl; ++l) {
+        if (l <= 2) HIP_TRY(hipStreamWaitEvent(st, fork.ev_pool[l], 0));
+        const std::vector<Lvl> h{t[l]};
+        if ((rc = launch_match_phase(nullptr, h, st))) return rc;
+        if ((rc = launch_quad(nullptr, h, st))) return rc;
+    }
+    return FIC_OK;
+}
+
 // The pools of all levels depend only on the images, so with `fork` (its level
 // streams and events) each level's pool phase runs on its own stream, started
 // after the work already queued on st; st waits for level l's pool right
@@ -774,6 +859,9 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
                     bool filtered, hipStream_t st, const std::vector<Group>* groups = nullptr,
                     Workspace* fork = nullptr) {
     const int nl = (int)t.size() / n_images;
+    if (fork && dt == nullptr && n_images == 1 && nl > 1 && nl <= kLevels && fork->dlv &&
+        fork->nlv == nl)
+        return launch_quadtree_one(t, T, filtered, st, *fork);
     const std::vector<Group> all{{0, n_images}};
     const std::vector<Group>& gs = groups ? *groups : all;
     for (const Group& g : gs) {
@@ -854,6 +942,7 @@ int encode_image_impl(Workspace& ws, const uint8_t* img, int H, int W, int pitch
     std::vector<Lvl> t = quad_tables(ws, lv, img, H, W, pitch, p, codes, capacity, stats, flags, pools);
     t.back().n_out = n_out;
     if ((rc = ensure_fork(ws))) return rc;
+    if ((rc = upload_levels(ws, t))) return rc;
     return launch_quadtree(nullptr, t, 1, ws.T, p->entropy_mode != 0, ws.stream, nullptr, &ws);
 }
 
