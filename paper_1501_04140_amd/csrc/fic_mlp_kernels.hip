@@ -401,6 +401,7 @@ constexpr int kTopK = 32;    // largest proposal count
 constexpr int kTkRows = 32;  // ranges per wave
 constexpr int kTkCap = 64;   // candidate slots per range
 constexpr int kTkWaves = 4;
+constexpr int kTkAhead = 4;  // groups of 16 domains in flight per wave
 
 // Ordered key: larger key = larger score, then lower domain index.
 __device__ inline uint64_t tk_key(float s, int d) {
@@ -483,11 +484,24 @@ __global__ __launch_bounds__(256) void k_topk_sim(const _Float16* __restrict__ G
 #pragma unroll
         for (int e = 0; e < 4; ++e) rowok[rt][e] = r0 + 16 * rt + 4 * (lane >> 4) + e < nr;
 
-    for (int d0 = d_lo; d0 < d_hi; d0 += 16) {
+    // domain fragments: a ring of kTkAhead groups of 16 columns, each loaded
+    // kTkAhead groups before its use (the loads' latency hides behind the work)
+    h8 rb0[kTkAhead], rb1[kTkAhead];
+    auto fetch = [&](int d, h8& x0, h8& x1) {
+        const _Float16* pb = GD + (int64_t)min(d + (lane & 15), nd - 1) * 64 + kq;
+        x0 = *reinterpret_cast<const h8*>(pb);
+        x1 = *reinterpret_cast<const h8*>(pb + 32);
+    };
+#pragma unroll
+    for (int i = 0; i < kTkAhead; ++i) fetch(d_lo + 16 * i, rb0[i], rb1[i]);
+    for (int dg = d_lo; dg < d_hi; dg += 16 * kTkAhead)
+#pragma unroll
+    for (int it = 0; it < kTkAhead; ++it) {
+        const int d0 = dg + 16 * it;
+        if (d0 >= d_hi) break;
+        const h8 b0 = rb0[it], b1 = rb1[it];
+        fetch(d0 + 16 * kTkAhead, rb0[it], rb1[it]);
         const int dcol = d0 + (lane & 15);
-        const _Float16* pb = GD + (int64_t)min(dcol, nd - 1) * 64 + kq;
-        const h8 b0 = *reinterpret_cast<const h8*>(pb);
-        const h8 b1 = *reinterpret_cast<const h8*>(pb + 32);
         const bool colok = dcol < d_hi;
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
