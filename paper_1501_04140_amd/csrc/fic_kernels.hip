@@ -1523,7 +1523,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kM8Waves = 4;                            // wavefronts per workgroup
 // 16-row MFMA tiles per wavefront: 4 for the int8 form, 2 for FP16 (whose
 // register budget would otherwise halve its occupancy)
-constexpr int m8_row_tiles(bool f16) { return f16 ? 2 : 4; }
+constexpr int m8_row_tiles(bool) { return 4; }
 constexpr int m8_rows(bool f16) { return kM8Waves * 16 * m8_row_tiles(f16); }  // rows per workgroup
 constexpr int kM8RowBits = 6;                           // queue entry: row | position << kM8RowBits
 constexpr int kM8ColTiles = 4;                         // 16-column tiles per LDS stage
@@ -1900,44 +1900,30 @@ __device__ __forceinline__ void k_match_mfma8_body(
     for (int base = lo; base < hi; base += kM8Cols, buf ^= 1) {
         const int nb = base + kM8Cols;
         if (nb < hi) load_stage(nb, min(kM8Cols, hi - nb));  // in flight while this stage is matched
-        v4i acc[kM8RowTiles][kM8ColTiles];
-        if constexpr (F16) {
-            v8h b16[kM8ColTiles][2];
-#pragma unroll
-            for (int ct = 0; ct < kM8ColTiles; ++ct)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) b16[ct][h] = __builtin_bit_cast(v8h, sH[buf][(16 * ct + c16) * 9 + 4 * h + g]);
-            const v4f zf = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int rt = 0; rt < kM8RowTiles; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < kM8ColTiles; ++ct) {
-                    v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b16[ct][0], zf, 0, 0, 0);
-                    x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b16[ct][1], x, 0, 0, 0);
-                    acc[rt][ct] = __builtin_bit_cast(v4i, x);
-                }
-        } else {
-            v4i bh[kM8ColTiles], bl[kM8ColTiles];
-#pragma unroll
-            for (int ct = 0; ct < kM8ColTiles; ++ct) {
-                bh[ct] = sH[buf][(16 * ct + c16) * 4 + g];
-                bl[ct] = sL[buf][(16 * ct + c16) * 4 + g];
-            }
-            const v4i z = {0, 0, 0, 0};
-#pragma unroll
-            for (int rt = 0; rt < kM8RowTiles; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < kM8ColTiles; ++ct)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bh[ct], z, 0, 0, 0);
-#pragma unroll
-            for (int rt = 0; rt < kM8RowTiles; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < kM8ColTiles; ++ct)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bl[ct], acc[rt][ct] << 7,
-                                                                        0, 0, 0);
-        }
+        // one column tile at a time: its MFMAs for every row tile, then its screen
 #pragma unroll
         for (int ct = 0; ct < kM8ColTiles; ++ct) {
+            v4i acc[kM8RowTiles];
+            if constexpr (F16) {
+                v8h b16[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) b16[h] = __builtin_bit_cast(v8h, sH[buf][(16 * ct + c16) * 9 + 4 * h + g]);
+                const v4f zf = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int rt = 0; rt < kM8RowTiles; ++rt) {
+                    v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b16[0], zf, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b16[1], x, 0, 0, 0);
+                    acc[rt] = __builtin_bit_cast(v4i, x);
+                }
+            } else {
+                const v4i bh = sH[buf][(16 * ct + c16) * 4 + g], bl = sL[buf][(16 * ct + c16) * 4 + g];
+                const v4i z = {0, 0, 0, 0};
+#pragma unroll
+                for (int rt = 0; rt < kM8RowTiles; ++rt) {
+                    acc[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bh, z, 0, 0, 0);
+                    acc[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bl, acc[rt] << 7, 0, 0, 0);
+                }
+            }
             const int col = 16 * ct + c16;
             const float qj = sQ[buf][col];
             const int sj = sS[buf][col], tmj = sTm[buf][col];
@@ -1951,7 +1937,7 @@ __device__ __forceinline__ void k_match_mfma8_body(
                     const float Uf = fmaf(sigm[rt], qj, fmaf((float)-nsrp[rt], sjf, bj));
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        cand[e] = __int_as_float(acc[rt][ct][e]) >= Uf;
+                        cand[e] = __int_as_float(acc[rt][e]) >= Uf;
                         m[e] = __ballot(cand[e]);
                     }
                 } else {
@@ -1960,7 +1946,7 @@ __device__ __forceinline__ void k_match_mfma8_body(
                     const int U = (T - toff + 63) >> 6;      // 64 X + toff >= T  <=>  X >= U
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        cand[e] = acc[rt][ct][e] >= U;
+                        cand[e] = acc[rt][e] >= U;
                         m[e] = __ballot(cand[e]);
                     }
                 }
@@ -1971,8 +1957,8 @@ __device__ __forceinline__ void k_match_mfma8_body(
                             const int slot = qn + __builtin_amdgcn_mbcnt_hi(
                                 (uint32_t)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
                             if (cand[e]) {
-                                const int X = F16 ? (int)__int_as_float(acc[rt][ct][e])
-                                                  : acc[rt][ct][e];
+                                const int X = F16 ? (int)__int_as_float(acc[rt][e])
+                                                  : acc[rt][e];
                                 queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
                                                              ((uint32_t)(base + col) << kM8RowBits),
                                                          (uint32_t)X);
