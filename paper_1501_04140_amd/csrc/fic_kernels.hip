@@ -1932,7 +1932,8 @@ __device__ __forceinline__ void k_match_mfma8_body(
             for (int rt = 0; rt < kM8RowTiles; ++rt) {
                 const int toff = __mul24(nsrp[rt], sj);  // -sum r' * S (24-bit operands)
                 bool cand[4];
-                uint64_t m[4];
+                uint64_t m[4] = {0, 0, 0, 0};
+                bool any;
                 if constexpr (F16) {
                     const float Uf = fmaf(sigm[rt], qj, fmaf((float)-nsrp[rt], sjf, bj));
 #pragma unroll
@@ -1940,17 +1941,24 @@ __device__ __forceinline__ void k_match_mfma8_body(
                         cand[e] = __int_as_float(acc[rt][e]) >= Uf;
                         m[e] = __ballot(cand[e]);
                     }
+                    any = (m[0] | m[1] | m[2] | m[3]) != 0;
                 } else {
+                    // one compare of the lane's largest element first; the four
+                    // compares only when some lane has a candidate (rare)
                     // B' >= T for every element that can match or beat the lane's rows
                     const int T = max((int)fminf(sigm[rt] * qj, 1.0e9f), tmj);
                     const int U = (T - toff + 63) >> 6;      // 64 X + toff >= T  <=>  X >= U
+                    const int mx = max(max(acc[rt][0], acc[rt][1]), max(acc[rt][2], acc[rt][3]));
+                    any = __ballot(mx >= U) != 0;
+                    if (any) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        cand[e] = acc[rt][e] >= U;
-                        m[e] = __ballot(cand[e]);
+                        for (int e = 0; e < 4; ++e) {
+                            cand[e] = acc[rt][e] >= U;
+                            m[e] = __ballot(cand[e]);
+                        }
                     }
                 }
-                if (m[0] | m[1] | m[2] | m[3]) {
+                if (any) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (m[e]) {
