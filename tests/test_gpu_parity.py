@@ -216,6 +216,28 @@ def test_quadtree_matches_oracle(dev, size, seed, min_pool, sets):
     assert np.array_equal(rec.cpu().numpy(), oracle.decode(ref, size, size, iters=24))
 
 
+def test_quadtree_alternating_arguments(dev):
+    """The encoder keeps a device copy of each image's level arguments and
+    rewrites it only when they change: alternating images, sizes and
+    parameters on one stream must each give the oracle's codes, also when an
+    earlier argument set comes back (same buffers, same image)."""
+    a = synth.power_law(96, beta=2.0, seed=7, n_rect=2)
+    b = synth.power_law(128, beta=1.6, seed=8, n_rect=1)
+    pa = fic.EncoderParams(s_sets=oracle.PAPER_K, min_pool=64)
+    pb = fic.EncoderParams(s_sets=((3,), (2, 4), (9,), (5, 9)), min_pool=100)
+    xa = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    xb = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    ref = {}
+    for key, img, p in (("a", a, pa), ("b", b, pb), ("ab", a, pb)):
+        ref[key], _ = oracle.encode_image(img, s_sets=p.s_sets, min_pool=p.min_pool)
+    out_a = fic.encode_image(xa, pa)
+    for key, x, p in (("a", xa, pa), ("b", xb, pb), ("a", xa, pa), ("ab", xa, pb), ("a", xa, pa)):
+        say(f"[quadtree] alternating arguments: {key}")
+        codes, n, _ = fic.encode_image(x, p, out=out_a if key == "a" else None)
+        torch.cuda.synchronize()
+        assert_codes_equal(fic.codes_numpy(codes, n), ref[key])
+
+
 def test_quadtree_variance_pool(dev):
     img = synth.power_law(96, beta=2.0, seed=2, n_rect=3)
     params = fic.EncoderParams(s_sets=oracle.PAPER_K, entropy_mode=2, entropy_bits=200.0, min_pool=48)
