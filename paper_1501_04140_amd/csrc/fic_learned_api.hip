@@ -47,7 +47,9 @@ void gemm(const _Float16* A, int lda, const _Float16* B, int ldb, int M, int N, 
           hipStream_t st) {
     const int kchunk = rup(cdiv(K, splits), 32);
     const int nz = cdiv(K, kchunk);
-    k_gemm_nt<EPI><<<dim3(cdiv(M, 64), cdiv(N, 64), nz), 256, 0, st>>>(
+    // x: column blocks fastest, so that the workgroups sharing a block of A rows
+    // run together and its re-reads come from L2
+    k_gemm_nt<EPI><<<dim3(cdiv(M, 64) * cdiv(N, 64), 1, nz), 256, 0, st>>>(
         A, lda, B, ldb, M, N, kchunk, K, alpha, bias, mask, ldm, C, ldc);
 }
 

@@ -125,7 +125,8 @@ enum { kEpiRelu16 = 0, kEpiF32 = 1, kEpiMask16 = 2, kEpiPart32 = 3 };
 //   kEpiF32:    C32 = C + bias[n] (bias may be NULL)
 //   kEpiMask16: C16 = C if mask[m][n] > 0 else 0   (ReLU derivative)
 //   kEpiPart32: C32[split][m][n] = C               (split-K partial sums)
-// Workgroup tile 64 x 64 (2 x 2 waves of 32 x 32). Rows and columns past M, N
+// Workgroup tile 64 x 64 (2 x 2 waves of 32 x 32), the column blocks of a row
+// block in consecutive workgroups. Rows and columns past M, N
 // read the last valid row and are not stored. The K range of every split must
 // be a multiple of 32, and lda, ldb multiples of 8.
 template <int EPI>
@@ -136,8 +137,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const _Float16* __restrict__ A,
                                                  const _Float16* __restrict__ mask, int ldm,
                                                  void* __restrict__ C, int ldc) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
-    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int nbn = (N + 63) / 64;  // column blocks; blockIdx.x = row block * nbn + column block
+    const int m0 = (int)(blockIdx.x / nbn) * 64 + (wave & 1) * 32;
+    const int n0 = (int)(blockIdx.x % nbn) * 64 + (wave >> 1) * 32;
     const int kb = blockIdx.z * kchunk;
     const int ke = min(ktot, kb + kchunk);
     const int r = lane & 15, kq = (lane >> 4) * 8;
