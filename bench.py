@@ -36,6 +36,34 @@ def match_ops(n: int, n_s: int) -> int:
     return 2 * n + 2 + 3 * n_s
 
 
+def cpu_info() -> dict:
+    """The host CPU the oracle baseline ran on: model name and logical CPU count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def single_thread_rate(fn, matches: int) -> dict:
+    """The oracle on one thread over a small sample (matches/s), then its threads restored."""
+    import oracle
+    n = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(n)
+    return {"value": matches / dt, "seconds": dt}
+
+
 def level_ops(B: int, matches: int, n_s: int) -> dict:
     """Algorithmic work of one level's matcher, by the label it is profiled under:
     the VALU matcher's integer ops, or (B = 4, 8 and 16 with small sets, on FP16 MFMA)
@@ -263,7 +291,16 @@ def run_quadtree(args, torch):
             reps += 1
         res["cpu_baseline"] = {"value": om / dt, "unit": "matches/s", "cores": oracle.num_threads(),
                                "kind": "oracle", "seconds": dt,
-                               "sample": f"the whole 512x512 encode, {reps} times, same image and s values"}
+                               "sample": f"the whole 512x512 encode, {reps} times, same image and s values",
+                               **cpu_info()}
+        # one thread: the first level's search (16x16 ranges, its entropy pool)
+        pool0, _ = oracle.entropy_pool(img, params.levels[0], max(params.levels[0] // 2, 1), 2.5, 256)
+        r0 = oracle.full_ranges(H, W, params.levels[0])
+        st1 = single_thread_rate(
+            lambda: oracle.match_level(img, params.levels[0], max(params.levels[0] // 2, 1), s_sets[0],
+                                       pool0, r0), len(r0) * len(pool0) * 8)
+        res["cpu_baseline"]["single_thread"] = {
+            **st1, "unit": "matches/s", "sample": "the first level (16x16 ranges, entropy pool) of the same image"}
     return res
 
 
@@ -328,7 +365,7 @@ def run_batch(args, torch):
         res["cpu_baseline"] = {"value": om / dt, "unit": "matches/s", "cores": oracle.num_threads(),
                                "kind": "oracle", "seconds": dt,
                                "sample": f"whole encodes of {len(done)} of the 64 images "
-                                         f"(smallest first, sides {done})"}
+                                         f"(smallest first, sides {done})", **cpu_info()}
     b.close()
     return res
 
@@ -470,7 +507,7 @@ def run_learned(args, torch):
         res["cpu_baseline"] = {"value": len(ranges) / dt, "unit": "ranges/s",
                                "cores": oracle.num_threads(), "kind": "oracle", "seconds": dt,
                                "sample": f"{len(ranges)} ranges of a 512x512 crop of eval image 0 "
-                                         "(embeddings of all 15625 crop domains included)"}
+                                         "(embeddings of all 15625 crop domains included)", **cpu_info()}
     net.close()
     base.close()
     return res
@@ -627,7 +664,11 @@ def run_level(args, torch, which):
         om = len(ranges) * gy * gx * 8
         res["cpu_baseline"] = {"value": om / dt, "unit": "matches/s", "cores": oracle.num_threads(),
                                "kind": "oracle", "seconds": dt,
-                               "sample": f"{len(ranges)} of {n_r} ranges, every domain"}
+                               "sample": f"{len(ranges)} of {n_r} ranges, every domain", **cpu_info()}
+        r1 = ranges[::64]
+        st1 = single_thread_rate(lambda: oracle.match_level(img, B, L, ks, None, r1), len(r1) * gy * gx * 8)
+        res["cpu_baseline"]["single_thread"] = {**st1, "unit": "matches/s",
+                                                "sample": f"{len(r1)} of those ranges, every domain"}
     return res
 
 

@@ -77,12 +77,19 @@ def _load():
         lib.orc_isometry.argtypes = [i32p, ctypes.c_int, ctypes.c_int, i32p]
         lib.orc_isometry.restype = None
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the C search (OpenMP); timing only, results do not depend on it."""
+    _load().orc_set_threads(int(n))
 
 
 def _ptr(a, ctype):

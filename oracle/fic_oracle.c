@@ -185,6 +185,16 @@ int orc_match_level(const uint8_t *img, int H, int W, int pitch, int B, int L,
     return 0;
 }
 
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
