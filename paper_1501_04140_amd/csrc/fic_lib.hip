@@ -851,10 +851,10 @@ int launch_quadtree_one(const std::vector<Lvl>& t, const int64_t* T, bool filter
     return FIC_OK;
 }
 
-// The pools of all levels depend only on the images, so with `fork` (its level
-// streams and events) each level's pool phase runs on its own stream, started
-// after the work already queued on st; st waits for level l's pool right
-// before level l's matcher.
+// The quadtree of n_images images whose level arguments are t ([level][image],
+// also at dt when not NULL). With `fork` (one image, its level arguments
+// uploaded to fork->dlv) the pools run on side streams (launch_quadtree_one);
+// otherwise everything runs on st, level by level.
 int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, const int64_t* T,
                     bool filtered, hipStream_t st, const std::vector<Group>* groups = nullptr,
                     Workspace* fork = nullptr) {
@@ -872,44 +872,18 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
         else
             kt_act_full<false><<<dim3(gx, 1, g.count), kBlock, 0, st>>>(h0[0], dt, 1);
     }
-    const bool conc = fork && nl > 1 && nl <= kLevels;
-    if (conc) HIP_TRY(hipEventRecord(fork->ev_fork, st));
-    auto pool = [&](int l) -> int {
-        hipStream_t ps = conc ? fork->side[l] : st;
-        if (conc) HIP_TRY(hipStreamWaitEvent(ps, fork->ev_fork, 0));
-        for (const Group& g : gs) {
-            std::vector<Lvl> h(t.begin() + l * n_images + g.start,
-                               t.begin() + l * n_images + g.start + g.count);
-            const Lvl* dl = dt ? dt + l * n_images + g.start : nullptr;
-            int rc = launch_pool_phase(dl, h, T, filtered, ps);
-            if (rc) return rc;
-        }
-        if (conc) HIP_TRY(hipEventRecord(fork->ev_pool[l], ps));
-        return FIC_OK;
-    };
-    auto match = [&](int l) -> int {
-        if (conc) HIP_TRY(hipStreamWaitEvent(st, fork->ev_pool[l], 0));
-        for (const Group& g : gs) {
-            std::vector<Lvl> h(t.begin() + l * n_images + g.start,
-                               t.begin() + l * n_images + g.start + g.count);
-            const Lvl* dl = dt ? dt + l * n_images + g.start : nullptr;
-            int rc = launch_match_phase(dl, h, st);
-            if (rc) return rc;
-            if ((rc = launch_quad(dl, h, st))) return rc;
-        }
-        return FIC_OK;
-    };
-    // Level 0's pool and matcher are queued first, so the host reaches the
-    // first matcher early; the other pools follow at once and run on their
-    // streams while level 0 matches. On one stream the order is level by level.
-    int rc;
-    if ((rc = pool(0)) || (rc = match(0))) return rc;
-    if (conc)
-        for (int l = 1; l < nl; ++l)
-            if ((rc = pool(l))) return rc;
-    for (int l = 1; l < nl; ++l) {
-        if (!conc && (rc = pool(l))) return rc;
-        if ((rc = match(l))) return rc;
+    for (int l = 0; l < nl; ++l) {
+        // every group's pool, then every group's matcher and decisions
+        for (int phase = 0; phase < 2; ++phase)
+            for (const Group& g : gs) {
+                std::vector<Lvl> h(t.begin() + l * n_images + g.start,
+                                   t.begin() + l * n_images + g.start + g.count);
+                const Lvl* dl = dt ? dt + l * n_images + g.start : nullptr;
+                int rc = phase == 0 ? launch_pool_phase(dl, h, T, filtered, st)
+                                    : launch_match_phase(dl, h, st);
+                if (rc) return rc;
+                if (phase == 1 && (rc = launch_quad(dl, h, st))) return rc;
+            }
     }
     return FIC_OK;
 }
