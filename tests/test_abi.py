@@ -124,6 +124,13 @@ def test_encode_level_ex_rejects_variants(lib):
     assert call(16, 11, fic.MATCH_MFMA_F16) == fic.FIC_EINVAL
     assert call(8, 1, fic.MATCH_MFMA_F16) == fic.FIC_EINVAL  # {0}: nothing to screen
     assert call(16, 11, fic.MATCH_FP32) == fic.FIC_EINVAL
+    # the small-set form indexes fewer than 2^21 grid domains: 1456^2 at B = 8, L = 1
+    # is (1456 - 16 + 1)^2 = 2076481 < 2^21 = 2097152, 1464^2 gives 2099601
+    small = (ctypes.c_int8 * 16)(3, 8)
+    side = 1464
+    rc = lib.fic_encode_level_ex(1, side, side, side, 8, 1, small, 2, 0, 2.5, 1, None,
+                                 (side // 8) ** 2, 1, None, None, fic.MATCH_MFMA_F16, None)
+    assert rc == fic.FIC_EINVAL and "2097152" in lib.fic_last_error().decode()
 
 
 def test_decode_and_sse_reject(lib):
