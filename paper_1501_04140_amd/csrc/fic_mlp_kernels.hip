@@ -162,6 +162,42 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const _Float16* __restrict__ A,
         acc[1][0] = mfma16(fa1, fb0, acc[1][0]);
         acc[1][1] = mfma16(fa1, fb1, acc[1][1]);
     }
+    if constexpr (EPI == kEpiRelu16 || EPI == kEpiF32) {
+        // full 64-column tiles: the workgroup's 64 x 64 outputs go through LDS and
+        // out as whole rows, 16 bytes per store
+        const int bm = (int)(blockIdx.x / nbn) * 64, bn = (int)(blockIdx.x % nbn) * 64;
+        if (bn + 64 <= N && ldc % 8 == 0 && ((uintptr_t)C & 15) == 0) {
+            constexpr int ES = EPI == kEpiRelu16 ? 2 : 4;   // output bytes per element
+            constexpr int RB = 64 * ES + 16;                // LDS row stride in bytes (padded)
+            __shared__ __align__(16) unsigned char tile[64 * RB];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int cl = (wave >> 1) * 32 + 16 * j + (lane & 15);
+                    const float bv = bias ? bias[bn + cl] : 0.0f;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int rl = (wave & 1) * 32 + 16 * i + 4 * (lane >> 4) + e;
+                        const float v = alpha * acc[i][j][e] + bv;
+                        if constexpr (EPI == kEpiRelu16)
+                            reinterpret_cast<_Float16*>(tile + rl * RB)[cl] = (_Float16)fmaxf(v, 0.0f);
+                        else
+                            reinterpret_cast<float*>(tile + rl * RB)[cl] = v;
+                    }
+                }
+            __syncthreads();
+            constexpr int CPR = 64 * ES / 16;  // 16-byte chunks per row
+#pragma unroll
+            for (int c = threadIdx.x; c < 64 * CPR; c += 256) {
+                const int rl = c / CPR, ch = c % CPR, row = bm + rl;
+                if (row < M)
+                    *reinterpret_cast<uint4*>(static_cast<unsigned char*>(C) + ((int64_t)row * ldc + bn) * ES +
+                                              16 * ch) = *reinterpret_cast<const uint4*>(tile + rl * RB + 16 * ch);
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
