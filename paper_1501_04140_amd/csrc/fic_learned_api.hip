@@ -126,8 +126,11 @@ int block_rows(fic_mlp* M, const uint8_t* img, int H, int W, int pitch, int L,
 // Top-k of GR [nq x 64] against GD [nk x 64] -> idx, score [nq x k]
 int topk_launch(fic_mlp* M, const _Float16* GR, int nq, const _Float16* GD, int nk, int k,
                 int32_t* idx, float* score, hipStream_t st) {
+    // domain segments only where the ranges alone leave SIMDs idle (2 waves
+    // per SIMD fill the chip): every segment restarts the running thresholds,
+    // so each one pays its own warm-up of appends and prunes
     const int row_waves = cdiv(nq, kTkRows);
-    int nseg = std::max(1, std::min(16, cdiv(4096, row_waves)));
+    int nseg = std::max(1, std::min(16, cdiv(2048, row_waves)));
     int seg_len = rup(cdiv(nk, nseg), 16);
     seg_len = std::max(seg_len, 256);
     nseg = cdiv(nk, seg_len);

@@ -511,19 +511,28 @@ __global__ __launch_bounds__(256) void k_topk_sim(const _Float16* __restrict__ G
         a[rt][0] = *reinterpret_cast<const h8*>(pa);
         a[rt][1] = *reinterpret_cast<const h8*>(pa + 32);
     }
-    float th[2][4];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) th[rt][e] = -INFINITY;
+    // running thresholds and slot counts of this lane's 8 rows (rows 16 rt +
+    // 4 g + e); +inf thresholds for rows past the end, so their scores never pass
+    const int g = lane >> 4, cl = lane & 15;
+    const uint32_t below = (1u << cl) - 1u;
     bool rowok[2][4];
+    float th[2][4];
+    int cnt[2][4];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rowok[rt][e] = r0 + 16 * rt + 4 * (lane >> 4) + e < nr;
+        for (int e = 0; e < 4; ++e) {
+            rowok[rt][e] = r0 + 16 * rt + 4 * g + e < nr;
+            th[rt][e] = rowok[rt][e] ? -INFINITY : INFINITY;
+            cnt[rt][e] = 0;
+        }
 
     // domain fragments: a ring of kTkAhead groups of 16 columns, each loaded
-    // kTkAhead groups before its use (the loads' latency hides behind the work)
+    // kTkAhead groups before its use (the loads' latency hides behind the
+    // work). A slot is refilled only after the MFMAs have read it, so the ring
+    // needs no register copies (a copy would wait for the load in flight).
+    // Groups past the segment's end (at most kTkAhead - 1) read clamped,
+    // in-bounds columns and keep nothing.
     h8 rb0[kTkAhead], rb1[kTkAhead];
     auto fetch = [&](int d, h8& x0, h8& x1) {
         const _Float16* pb = GD + (int64_t)min(d + (lane & 15), nd - 1) * 64 + kq;
@@ -536,30 +545,52 @@ __global__ __launch_bounds__(256) void k_topk_sim(const _Float16* __restrict__ G
 #pragma unroll
     for (int it = 0; it < kTkAhead; ++it) {
         const int d0 = dg + 16 * it;
-        if (d0 >= d_hi) break;
-        const h8 b0 = rb0[it], b1 = rb1[it];
-        fetch(d0 + 16 * kTkAhead, rb0[it], rb1[it]);
         const int dcol = d0 + (lane & 15);
         const bool colok = dcol < d_hi;
+        f4 acc[2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
-            f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            acc = mfma16(a[rt][0], b0, acc);
-            acc = mfma16(a[rt][1], b1, acc);
+            acc[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            acc[rt] = mfma16(a[rt][0], rb0[it], acc[rt]);
+            acc[rt] = mfma16(a[rt][1], rb1[it], acc[rt]);
+        }
+        fetch(d0 + 16 * kTkAhead, rb0[it], rb1[it]);
+        bool hit = false;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) hit |= acc[rt][e] > th[rt][e];
+        // once the thresholds have risen most groups hold no passing score:
+        // the appends and the slot check run only when one does
+        if (!__ballot(colok && hit)) continue;
+        // row (rt, e) of lane group g sits in lanes [16g, 16g + 16), one column
+        // per lane: a passing lane's slot is the row's count plus the passing
+        // lanes below it in that segment of the ballot
+        bool full = false;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float s = acc[e];
-                if (colok && rowok[rt][e] && s > th[rt][e]) {
-                    const int row = 16 * rt + 4 * (lane >> 4) + e;
-                    const int pos = atomicAdd(&scnt[wave][row], 1);
-                    sbuf[wave][row][pos] = tk_key(s, dcol);
-                }
+                const float s = acc[rt][e];
+                const bool p = colok && s > th[rt][e];
+                const uint64_t bal = __ballot(p);
+                if (!bal) continue;  // most element slots of a group append nothing
+                const uint32_t seg = (uint32_t)(bal >> (16 * g)) & 0xffffu;
+                if (p) sbuf[wave][16 * rt + 4 * g + e][cnt[rt][e] + __popc(seg & below)] = tk_key(s, dcol);
+                cnt[rt][e] += __popc(seg);
+                full |= cnt[rt][e] > kTkCap - 16;
             }
-        }
-        wave_lds_sync();
-        const int c = lane < kTkRows ? scnt[wave][lane] : 0;
-        uint64_t need = __ballot(c > kTkCap - 16);
-        if (need) {
+        if (__ballot(full)) {
+            // publish the counts, prune the rows that could overflow on the
+            // next group, then take back their counts and thresholds
+            if (cl == 0)
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) scnt[wave][16 * rt + 4 * g + e] = cnt[rt][e];
+            wave_lds_sync();
+            const int c = lane < kTkRows ? scnt[wave][lane] : 0;
+            uint64_t need = __ballot(c > kTkCap - 16);
             while (need) {
                 const int row = __ffsll((unsigned long long)need) - 1;
                 need &= need - 1;
@@ -568,9 +599,18 @@ __global__ __launch_bounds__(256) void k_topk_sim(const _Float16* __restrict__ G
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) th[rt][e] = sthr[wave][16 * rt + 4 * (lane >> 4) + e];
+                for (int e = 0; e < 4; ++e) {
+                    cnt[rt][e] = scnt[wave][16 * rt + 4 * g + e];
+                    th[rt][e] = rowok[rt][e] ? sthr[wave][16 * rt + 4 * g + e] : INFINITY;
+                }
         }
     }
+    if (cl == 0)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) scnt[wave][16 * rt + 4 * g + e] = cnt[rt][e];
+    wave_lds_sync();
     for (int row = 0; row < kTkRows && r0 + row < nr; ++row) {
         const int c = scnt[wave][row];
         uint64_t v = lane < c ? sbuf[wave][row][lane] : 0ull;
