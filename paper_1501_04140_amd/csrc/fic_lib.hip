@@ -349,7 +349,9 @@ bool is_mfma8(int var) { return var == kVarMfma || var == kVarMfma16; }
 
 int default_cg(int B, int var) {
     if (is_mfma8(var)) return kM8Chunk;
-    if (var == kVarMfq) return mq_cols(B);
+    // several LDS stages per workgroup: its range staging, A operands and
+    // the final merge across column lanes are paid once per chunk
+    if (var == kVarMfq) return B == 16 ? 4 * mq_cols(B) : 256;
     if (var == kVarFp32) return 256;
     return match_chunk_domains(B);
 }
