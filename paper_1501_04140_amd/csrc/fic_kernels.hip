@@ -528,15 +528,40 @@ __device__ inline int scan1024(int v, int* s_w, int& total) {
     return base + s - v;
 }
 
+// The same without the closing barrier: callers alternate between two s_w
+// buffers, so a barrier of their own always separates two uses of one buffer.
+__device__ inline int scan1024_open(int v, int* s_w, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int s = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(s, d, 64);
+        if (lane >= d) s += t;
+    }
+    if (lane == 63) s_w[wid] = s;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const int x = s_w[w];
+        base += w < wid ? x : 0;
+        tot += x;
+    }
+    total = tot;
+    return base + s - v;
+}
+
 constexpr int kSelStage = 8192;  // floor candidates held in LDS by the select
 
 // Floor, step 3 (one workgroup of 1024): exact radix select of the r-th
-// smallest key among the C candidates (all keys <= cut_bound), then in-place
+// smallest key among the C candidates (all keys <= cut_bound), then
 // compaction to the keys below it plus the first ties in index order. The
 // candidates are staged in LDS when they fit; the digits start at the highest
 // bit a candidate can have, and the select stops as soon as the chosen bucket
-// is taken whole. Always launched: it also publishes the number of domains
-// that passed the threshold and clears the per-level counters.
+// is taken whole. Staged candidates are compacted with one scan: thread t
+// takes a run of up to 8 consecutive candidates. Always launched: it also
+// publishes the number of domains that passed the threshold and clears the
+// per-level counters.
 // direct (grids of at most kSelStage domains, launched without the bound and
 // compaction steps): every domain is a candidate, and the threshold and
 // whole-grid pools are compacted here too.
@@ -547,37 +572,36 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
     __shared__ uint64_t sk[kSelStage];
     __shared__ int32_t sj[kSelStage];
     __shared__ uint32_t h[kSelBins];
-    __shared__ int s_w[16];
+    __shared__ int s_w[2][16];
+    __shared__ uint64_t s_wmax[16];
     __shared__ uint64_t s_prefix;
-    __shared__ unsigned long long s_max;
     __shared__ uint32_t s_rank;
     __shared__ int s_lo, s_done, s_c0, s_c1;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
     const int passed = ctrl->pass_count;
     const int mode = pool_mode(passed, total, min_pool);
     if (direct && mode != 1) {
         // every domain (mode 2) or the threshold passers (mode 0), in index order
-        if (tid == 0) s_c0 = 0;
-        __syncthreads();
-        for (int base = 0; base < total; base += nt) {
-            const int i = base + tid;
-            const int f = i < total && (mode == 2 || key[i] < M);
-            int tot;
-            const int off = scan1024(f, s_w, tot);
-            if (f) pool[s_c0 + off] = i;
-            __syncthreads();
-            if (tid == 0) s_c0 += tot;
-            __syncthreads();
+        const int kpt = (total + nt - 1) / nt;  // at most kSelStage / 1024 = 8
+        const int b = min(total, tid * kpt), e = min(total, b + kpt);
+        uint32_t bits = 0;
+        int cnt = 0;
+        for (int i = b; i < e; ++i) {
+            const int f = mode == 2 || key[i] < M;
+            bits |= (uint32_t)f << (i - b);
+            cnt += f;
         }
-        if (tid == 0) ctrl->pool_count = s_c0;
+        int tot;
+        int off = scan1024_open(cnt, s_w[0], tot);
+        for (int i = b; i < e; ++i)
+            if ((bits >> (i - b)) & 1u) pool[off++] = i;
+        if (tid == 0) ctrl->pool_count = tot;
     }
     if (mode == 1) {
         const int C = direct ? total : ctrl->pool_count;
         const bool staged = C <= kSelStage;
-        if (tid == 0) s_max = 0ull;
-        __syncthreads();
-        if (staged) {
-            uint64_t kmax = 0;
+        uint64_t kmax = 0;
+        if (staged)
             for (int i = tid; i < C; i += nt) {
                 const int j = direct ? i : pool[i];
                 const uint64_t u = (uint64_t)key[j];
@@ -585,25 +609,33 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
                 sk[i] = u;
                 kmax = u > kmax ? u : kmax;
             }
-            if (direct) atomicMax(&s_max, (unsigned long long)kmax);
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            const uint64_t o = __shfl_xor(kmax, m, 64);
+            kmax = o > kmax ? o : kmax;
         }
-        __syncthreads();
-        const uint64_t ub = direct ? (uint64_t)s_max : ctrl->cut_bound;
-        const int top = min(62, ub ? 63 - __clzll((long long)ub) : 0);
+        if (lane == 0) s_wmax[wid] = kmax;
         if (tid == 0) {
             s_prefix = 0;
             s_rank = (uint32_t)r;
             s_done = 0;
             s_lo = 0;
         }
+        for (int i = tid; i < kSelBins; i += nt) h[i] = 0u;
         __syncthreads();
-        for (int p = top - (kSelBits - 1);; p -= kSelBits) {
+        uint64_t ub = ctrl->cut_bound;
+        if (direct) {
+            ub = 0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) ub = s_wmax[w] > ub ? s_wmax[w] : ub;
+        }
+        const int top = min(62, ub ? 63 - __clzll((long long)ub) : 0);
+        int par = 0;
+        for (int p = top - (kSelBits - 1);; p -= kSelBits, par ^= 1) {
             const int lo = max(p, 0);
             const int hs = p + kSelBits;  // bits >= hs are already decided
             const uint32_t dmask = (1u << (hs - lo)) - 1u;
             const uint64_t prefix = s_prefix;
-            for (int i = tid; i < kSelBins; i += nt) h[i] = 0u;
-            __syncthreads();
             for (int i = tid; i < C; i += nt) {
                 const uint64_t u = staged ? sk[i] : (uint64_t)key[pool[i]];
                 if ((u >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(u >> lo) & dmask], 1u);
@@ -616,8 +648,11 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
                 c4[b] = h[tid * 4 + b];
                 mine += c4[b];
             }
+            // only this thread reads these bins: clear them for the next digit
+#pragma unroll
+            for (int b = 0; b < 4; ++b) h[tid * 4 + b] = 0u;
             int tot;
-            const uint32_t excl = (uint32_t)scan1024((int)mine, s_w, tot);
+            const uint32_t excl = (uint32_t)scan1024_open((int)mine, s_w[par], tot);
             if (excl < rank && rank <= excl + mine) {
                 uint32_t cum = excl;
                 int b = 0;
@@ -634,34 +669,61 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
             if (s_done) break;
         }
         // keep keys whose bits >= s_lo are below the chosen prefix, and the
-        // first s_rank (in index order) of those equal to it
+        // first s_rank (in index order) of those equal to it; a kept key's
+        // place is (keys below before it) + min(ties before it, s_rank)
         const uint64_t hmask = ~((1ull << s_lo) - 1ull);
         const uint64_t cut = s_prefix;
         const int take = (int)s_rank;
-        if (tid == 0) {
-            s_c0 = 0;
-            s_c1 = 0;
-        }
-        __syncthreads();
-        for (int base = 0; base < C; base += nt) {
-            const int i = base + tid;
-            int j = 0, less = 0, tie = 0;
-            if (i < C) {
-                j = staged ? sj[i] : pool[i];
-                const uint64_t u = (staged ? sk[i] : (uint64_t)key[j]) & hmask;
-                less = u < cut;
-                tie = u == cut;
+        if (staged) {
+            const int kpt = (C + nt - 1) / nt;  // at most 8
+            const int b = min(C, tid * kpt), e = min(C, b + kpt);
+            int nl = 0, ntie = 0;
+            for (int i = b; i < e; ++i) {
+                const uint64_t u = sk[i] & hmask;
+                nl += u < cut;
+                ntie += u == cut;
             }
             int tot;
-            const int packed = scan1024(less | (tie << 16), s_w, tot);
-            const int lr = s_c0 + (packed & 0xffff), tr = s_c1 + (packed >> 16);
-            if (i < C && (less || (tie && tr < take))) pool[lr + min(tr, take)] = j;
-            __syncthreads();
+            const int packed = scan1024_open(nl | (ntie << 16), s_w[par ^ 1], tot);
+            int lr = packed & 0xffff, tr = packed >> 16;
+            for (int i = b; i < e; ++i) {
+                const uint64_t u = sk[i] & hmask;
+                if (u < cut) {
+                    pool[lr + min(tr, take)] = sj[i];
+                    ++lr;
+                } else if (u == cut) {
+                    if (tr < take) pool[lr + tr] = sj[i];
+                    ++tr;
+                }
+            }
+        } else {
+            // more candidates than LDS holds: rounds of 1024 in index order,
+            // compacted in place (a round writes only below its own reads)
             if (tid == 0) {
-                s_c0 += tot & 0xffff;
-                s_c1 += tot >> 16;
+                s_c0 = 0;
+                s_c1 = 0;
             }
             __syncthreads();
+            for (int base = 0; base < C; base += nt) {
+                const int i = base + tid;
+                int j = 0, less = 0, tie = 0;
+                if (i < C) {
+                    j = pool[i];
+                    const uint64_t u = (uint64_t)key[j] & hmask;
+                    less = u < cut;
+                    tie = u == cut;
+                }
+                int tot;
+                const int packed = scan1024(less | (tie << 16), s_w[par ^ 1], tot);
+                const int lr = s_c0 + (packed & 0xffff), tr = s_c1 + (packed >> 16);
+                if (i < C && (less || (tie && tr < take))) pool[lr + min(tr, take)] = j;
+                __syncthreads();
+                if (tid == 0) {
+                    s_c0 += tot & 0xffff;
+                    s_c1 += tot >> 16;
+                }
+                __syncthreads();
+            }
         }
         if (tid == 0) ctrl->pool_count = r;
     }
