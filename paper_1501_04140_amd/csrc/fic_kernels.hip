@@ -551,28 +551,33 @@ __device__ inline int scan1024_open(int v, int* s_w, int& total) {
     return base + s - v;
 }
 
-constexpr int kSelStage = 8192;  // floor candidates held in LDS by the select
+constexpr int kSelStage = 8192;    // floor candidates (key and index) held in LDS by the select
+constexpr int kSelDirect = 16384;  // grid domains the select takes directly (keys only in LDS)
 
 // Floor, step 3 (one workgroup of 1024): exact radix select of the r-th
 // smallest key among the C candidates (all keys <= cut_bound), then
 // compaction to the keys below it plus the first ties in index order. The
 // candidates are staged in LDS when they fit; the digits start at the highest
 // bit a candidate can have, and the select stops as soon as the chosen bucket
-// is taken whole. Staged candidates are compacted with one scan: thread t
-// takes a run of up to 8 consecutive candidates. Always launched: it also
-// publishes the number of domains that passed the threshold and clears the
-// per-level counters.
-// direct (grids of at most kSelStage domains, launched without the bound and
-// compaction steps): every domain is a candidate, and the threshold and
-// whole-grid pools are compacted here too.
+// is taken whole. Staged candidates are compacted in one pass per wave over a
+// contiguous segment (ballot ranks, 64 candidates a step), with one barrier
+// for the waves' totals. Always launched: it also publishes the number of
+// domains that passed the threshold and clears the per-level counters.
+// direct (grids of at most kSelDirect domains, launched without the bound and
+// compaction steps): every domain is a candidate (its index is its place, so
+// only keys are staged), and the threshold and whole-grid pools are compacted
+// here too.
 __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ key, int total,
                                                        int min_pool, int r,
                                                        int32_t* __restrict__ pool, Ctrl* ctrl,
                                                        bool direct, int64_t M) {
-    __shared__ uint64_t sk[kSelStage];
-    __shared__ int32_t sj[kSelStage];
+    // staged keys; indices (non-direct candidates only) in the upper part
+    __shared__ uint64_t sk[kSelDirect];
+    int32_t* const sj = reinterpret_cast<int32_t*>(sk + kSelStage);
+    static_assert(kSelStage * 12 <= kSelDirect * 8, "keys and indices share the stage");
     __shared__ uint32_t h[kSelBins];
     __shared__ int s_w[2][16];
+    __shared__ int s_wl[16], s_wt[16];
     __shared__ uint64_t s_wmax[16];
     __shared__ uint64_t s_prefix;
     __shared__ uint32_t s_rank;
@@ -580,32 +585,41 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
     const int passed = ctrl->pass_count;
     const int mode = pool_mode(passed, total, min_pool);
+    const uint64_t below = (1ull << lane) - 1ull;
     if (direct && mode != 1) {
-        // every domain (mode 2) or the threshold passers (mode 0), in index order
-        const int kpt = (total + nt - 1) / nt;  // at most kSelStage / 1024 = 8
-        const int b = min(total, tid * kpt), e = min(total, b + kpt);
-        uint32_t bits = 0;
+        // every domain (mode 2) or the threshold passers (mode 0), in index
+        // order: wave w counts, then writes, its own contiguous segment
+        const int S = (total + 15) / 16, wb = min(total, wid * S), we = min(total, wb + S);
         int cnt = 0;
-        for (int i = b; i < e; ++i) {
-            const int f = mode == 2 || key[i] < M;
-            bits |= (uint32_t)f << (i - b);
-            cnt += f;
+        for (int i0 = wb; i0 < we; i0 += 64) {
+            const int i = i0 + lane;
+            cnt += __popcll(__ballot(i < we && (mode == 2 || key[i] < M)));
         }
-        int tot;
-        int off = scan1024_open(cnt, s_w[0], tot);
-        for (int i = b; i < e; ++i)
-            if ((bits >> (i - b)) & 1u) pool[off++] = i;
+        if (lane == 0) s_wl[wid] = cnt;
+        __syncthreads();
+        int off = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            off += w < wid ? s_wl[w] : 0;
+            tot += s_wl[w];
+        }
+        for (int i0 = wb; i0 < we; i0 += 64) {
+            const int i = i0 + lane;
+            const bool f = i < we && (mode == 2 || key[i] < M);
+            const uint64_t m = __ballot(f);
+            if (f) pool[off + __popcll(m & below)] = i;
+            off += __popcll(m);
+        }
         if (tid == 0) ctrl->pool_count = tot;
     }
     if (mode == 1) {
         const int C = direct ? total : ctrl->pool_count;
-        const bool staged = C <= kSelStage;
+        const bool staged = direct || C <= kSelStage;
         uint64_t kmax = 0;
         if (staged)
             for (int i = tid; i < C; i += nt) {
-                const int j = direct ? i : pool[i];
-                const uint64_t u = (uint64_t)key[j];
-                sj[i] = j;
+                const uint64_t u = (uint64_t)key[direct ? i : pool[i]];
+                if (!direct) sj[i] = pool[i];
                 sk[i] = u;
                 kmax = u > kmax ? u : kmax;
             }
@@ -675,26 +689,37 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
         const uint64_t cut = s_prefix;
         const int take = (int)s_rank;
         if (staged) {
-            const int kpt = (C + nt - 1) / nt;  // at most 8
-            const int b = min(C, tid * kpt), e = min(C, b + kpt);
+            // wave w takes a contiguous segment: its counts of keys below
+            // and equal to the cut, then (after the waves' totals) its writes
+            const int S = (C + 15) / 16, wb = min(C, wid * S), we = min(C, wb + S);
             int nl = 0, ntie = 0;
-            for (int i = b; i < e; ++i) {
-                const uint64_t u = sk[i] & hmask;
-                nl += u < cut;
-                ntie += u == cut;
+            for (int i0 = wb; i0 < we; i0 += 64) {
+                const int i = i0 + lane;
+                const uint64_t u = i < we ? sk[i] & hmask : ~0ull;
+                nl += __popcll(__ballot(i < we && u < cut));
+                ntie += __popcll(__ballot(i < we && u == cut));
             }
-            int tot;
-            const int packed = scan1024_open(nl | (ntie << 16), s_w[par ^ 1], tot);
-            int lr = packed & 0xffff, tr = packed >> 16;
-            for (int i = b; i < e; ++i) {
-                const uint64_t u = sk[i] & hmask;
-                if (u < cut) {
-                    pool[lr + min(tr, take)] = sj[i];
-                    ++lr;
-                } else if (u == cut) {
-                    if (tr < take) pool[lr + tr] = sj[i];
-                    ++tr;
-                }
+            if (lane == 0) {
+                s_wl[wid] = nl;
+                s_wt[wid] = ntie;
+            }
+            __syncthreads();
+            int lr = 0, tr = 0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) {
+                lr += w < wid ? s_wl[w] : 0;
+                tr += w < wid ? s_wt[w] : 0;
+            }
+            for (int i0 = wb; i0 < we; i0 += 64) {
+                const int i = i0 + lane;
+                const uint64_t u = i < we ? sk[i] & hmask : ~0ull;
+                const bool less = i < we && u < cut, tie = i < we && u == cut;
+                const uint64_t bl = __ballot(less), bt = __ballot(tie);
+                const int l = lr + __popcll(bl & below), t = tr + __popcll(bt & below);
+                if (less) pool[l + min(t, take)] = direct ? i : sj[i];
+                if (tie && t < take) pool[l + t] = direct ? i : sj[i];
+                lr += __popcll(bl);
+                tr += __popcll(bt);
             }
         } else {
             // more candidates than LDS holds: rounds of 1024 in index order,
@@ -2720,7 +2745,7 @@ template <bool TAB>
 __global__ __launch_bounds__(1024) void kt_floor_select(Lvl a0, const Lvl* __restrict__ tab, int direct) {
     FIC_LV;
     k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.pctrl,
-                        direct && a.total <= kSelStage, a.M);
+                        direct && a.total <= kSelDirect, a.M);
 }
 
 template <int B, bool TAB>

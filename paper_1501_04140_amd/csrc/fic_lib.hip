@@ -639,7 +639,7 @@ template <bool TAB>
 void launch_select_steps(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
     const int n = (int)h.size();
     // small grids: one workgroup stages every key and builds the pool itself
-    const bool direct = max_over(h, [](const Lvl& a) { return a.total; }) <= kSelStage;
+    const bool direct = max_over(h, [](const Lvl& a) { return a.total; }) <= kSelDirect;
     if (!direct) {
         {
             ProfScope ps("pool_select", st);
