@@ -166,6 +166,35 @@ def test_entropy_pool_large_grids(dev, B, L, H, W):
         assert np.array_equal(pool.cpu().numpy()[:int(pc.item())], ref)
 
 
+@pytest.mark.parametrize("L,H,W", [(2, 188, 188), (2, 204, 308), (4, 516, 516)])
+def test_direct_select_mid_grids(dev, L, H, W):
+    """Grids of 8193..16384 domains (B = 4: 8281 and 14949 at L = 2, exactly 16384 at L = 4), which
+    the pool select takes in one launch with only the keys staged: threshold mode, floor
+    mode (nothing passes at 9 bits), a floor that the passers may or may not reach, the
+    whole grid, and the variance filter's threshold and floor; a three-valued image puts many equal keys at the
+    cut, whose first ones in index order must be kept."""
+    B = 4
+    gy, gx = oracle.domain_grid(H, W, B, L)
+    assert 8192 < gy * gx <= 16384
+    img = synth.power_law(max(H, W), beta=1.8, seed=11, n_rect=3)[:H, :W].copy()
+    rng = np.random.default_rng(3)
+    ties = (rng.integers(0, 3, size=(H, W)) * 100).astype(np.uint8)
+    corner = torch.tensor([[0, 0]], dtype=torch.int32, device=dev)
+    for name, im in (("power_law", img), ("three_valued", ties)):
+        x = torch.from_numpy(np.ascontiguousarray(im)).to(dev)
+        for entropy, bits, min_pool in ((1, 1.0, 16), (1, 2.5, 700), (1, 9.0, 5000),
+                                        (1, 2.5, 10 ** 6), (2, 300.0, 4096), (2, 1e9, 4096)):
+            say(f"[direct select] {name} {H}x{W} entropy={entropy} bits={bits} min_pool={min_pool}")
+            _, pool, pc = fic.encode_level(x, B, L, (2, 4), entropy, bits, min_pool, ranges=corner,
+                                           return_pool=True)
+            torch.cuda.synchronize()
+            if entropy == 2:
+                ref, _ = oracle.variance_pool(im, B, L, bits, min_pool)
+            else:
+                ref, _ = oracle.entropy_pool(im, B, L, bits, min_pool)
+            assert np.array_equal(pool.cpu().numpy()[:int(pc.item())], ref)
+
+
 @pytest.mark.parametrize("B,L,vmin,min_pool", [(2, 1, 50.0, 256), (4, 2, 300.0, 64), (8, 4, 900.0, 16),
                                                (16, 8, 1e9, 32), (4, 2, -1.0, 8), (2, 1, 0.0, 10 ** 6)])
 def test_variance_pool_levels(dev, B, L, vmin, min_pool):
