@@ -456,13 +456,40 @@ __device__ inline float tk_score(uint64_t key) {
 
 __device__ inline int tk_index(uint64_t key) { return (int)(~(uint32_t)key); }
 
+// A 64-bit value moved by a DPP lane pattern (CTRL: quad_perm = 0x00..0xff,
+// row_ror:n = 0x120 + n); every pattern used here reads a lane of the same row.
+template <int CTRL>
+__device__ inline uint64_t dpp_u64(uint64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// v of lane ^ j. Distances 1 and 2 are quad permutations and 8 the rotation
+// of a 16-lane row by 8 (DPP: no LDS round trip). Distance 4 takes the
+// rotation by 4 or by 12, whichever came from lane ^ 4 (from4, found once by
+// rotating the lane ids). 16 and 32 go through ds_bpermute.
+__device__ inline uint64_t xor_lane_u64(uint64_t v, int j, bool from4) {
+    switch (j) {
+        case 1: return dpp_u64<0xb1>(v);  // quad_perm [1, 0, 3, 2]
+        case 2: return dpp_u64<0x4e>(v);  // quad_perm [2, 3, 0, 1]
+        case 4: {
+            const uint64_t a = dpp_u64<0x124>(v), b = dpp_u64<0x12c>(v);
+            return from4 ? a : b;
+        }
+        case 8: return dpp_u64<0x128>(v);
+        default: return shfl_xor_u64(v, j);
+    }
+}
+
 // Bitonic sort of one key per lane, descending across the wave.
 __device__ inline uint64_t wave_sort_desc(uint64_t v, int lane) {
+    const bool from4 = __builtin_amdgcn_update_dpp(0, lane, 0x124, 0xf, 0xf, false) == (lane ^ 4);
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1)
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t o = shfl_xor_u64(v, j);
+            const uint64_t o = xor_lane_u64(v, j, from4);
             const bool take_max = ((lane & j) == 0) == ((lane & k) == 0);
             v = take_max ? (v > o ? v : o) : (v < o ? v : o);
         }
