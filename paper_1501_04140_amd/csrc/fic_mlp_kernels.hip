@@ -224,6 +224,138 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const _Float16* __restrict__ A,
         }
 }
 
+// ---------------------------------------------------------------- fused forward
+// The whole network on a tile of 64 rows with the hidden layers in LDS only:
+// the encode path, which keeps no activations for a backward pass. The same
+// MFMAs in the same order as the three k_gemm_nt launches (16x16x32 over k in
+// ascending steps of 32 from zero) and the same epilogues, so Y is bit for
+// bit theirs. Layers 1 and 2: wave w computes columns [64 w, 64 w + 64) of all
+// 64 rows; layer 3: rows [16 w, 16 w + 16). Weight fragments come from L2,
+// the next k step's in flight during the current one. Rows past M read the
+// last row and are not stored.
+constexpr int kFuseRows = 64;
+constexpr int kFuseLd = kMlpHid + 8;  // LDS row stride of a hidden layer in halves (16 bytes of padding)
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const _Float16* __restrict__ X, int M,
+                                                     const _Float16* __restrict__ w16,
+                                                     const float* __restrict__ w,
+                                                     float* __restrict__ Y) {
+    __shared__ __align__(16) _Float16 sH1[kFuseRows * kFuseLd];
+    __shared__ __align__(16) _Float16 sH2[kFuseRows * kFuseLd];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4, kq = g * 8;
+    const int m0 = blockIdx.x * kFuseRows;
+    const _Float16* W1 = w16 + kH16W1;
+    const _Float16* W2 = w16 + kH16W2;
+    const _Float16* W3 = w16 + kH16W3;
+    f4 acc[4][4];
+
+    // layer 1: H1 = max(X W1^T + b1, 0), K = 64
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < kMlpIn; k += 32) {
+        h8 fa[4], fb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            fa[i] = *reinterpret_cast<const h8*>(X + (int64_t)min(m0 + 16 * i + r, M - 1) * kMlpIn + k + kq);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            fb[j] = *reinterpret_cast<const h8*>(W1 + (64 * wave + 16 * j + r) * kMlpIn + k + kq);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(fa[i], fb[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = 64 * wave + 16 * j + r;
+        const float bv = w[kOffB1 + col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                sH1[(16 * i + 4 * g + e) * kFuseLd + col] = (_Float16)fmaxf(1.0f * acc[i][j][e] + bv, 0.0f);
+    }
+    __syncthreads();
+
+    // layer 2: H2 = max(H1 W2^T + b2, 0), K = 256
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    {
+        h8 fb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const h8*>(W2 + (64 * wave + 16 * j + r) * kMlpHid + kq);
+#pragma unroll
+        for (int k = 0; k < kMlpHid; k += 32) {
+            h8 nb[4];
+            if (k + 32 < kMlpHid)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    nb[j] = *reinterpret_cast<const h8*>(W2 + (64 * wave + 16 * j + r) * kMlpHid + k + 32 + kq);
+            h8 fa[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fa[i] = *reinterpret_cast<const h8*>(sH1 + (16 * i + r) * kFuseLd + k + kq);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(fa[i], fb[j], acc[i][j]);
+            if (k + 32 < kMlpHid)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) fb[j] = nb[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = 64 * wave + 16 * j + r;
+        const float bv = w[kOffB2 + col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                sH2[(16 * i + 4 * g + e) * kFuseLd + col] = (_Float16)fmaxf(1.0f * acc[i][j][e] + bv, 0.0f);
+    }
+    __syncthreads();
+
+    // layer 3: Y = H2 W3^T + b3, K = 256; this wave's 16 rows, all 64 columns
+    f4 out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    {
+        h8 fb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const h8*>(W3 + (16 * j + r) * kMlpHid + kq);
+#pragma unroll
+        for (int k = 0; k < kMlpHid; k += 32) {
+            h8 nb[4];
+            if (k + 32 < kMlpHid)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    nb[j] = *reinterpret_cast<const h8*>(W3 + (16 * j + r) * kMlpHid + k + 32 + kq);
+            const h8 fa = *reinterpret_cast<const h8*>(sH2 + (16 * wave + r) * kFuseLd + k + kq);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[j] = mfma16(fa, fb[j], out[j]);
+            if (k + 32 < kMlpHid)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) fb[j] = nb[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = 16 * j + r;
+        const float bv = w[kOffB3 + col];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = m0 + 16 * wave + 4 * g + e;
+            if (row < M) Y[(int64_t)row * kMlpOut + col] = 1.0f * out[j][e] + bv;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- embedding
 // S_q = sum_t Y[8 q + t]; G_q = S_q / |S_q| (0 if S_q = 0). One wave per block.
 __global__ __launch_bounds__(256) void k_iso_norm(const float* __restrict__ Y, int n,
