@@ -74,16 +74,15 @@ int mlp_forward(fic_mlp* M, int nblk, bool keep, hipStream_t st) {
     const int64_t rows = (int64_t)nblk * 8;
     if (rows > INT32_MAX / 2) return fail(FIC_EINVAL, "too many blocks (%d)", nblk);
     int rc;
-    if ((rc = mgrow(M->Y, rows * kMlpOut * 4)) || (rc = mgrow(M->G16, (int64_t)nblk * 64 * 2))) return rc;
+    if ((rc = mgrow(M->G16, (int64_t)nblk * 64 * 2))) return rc;
     if (!keep) {
-        // no backward pass follows: the hidden layers never leave the chip
+        // no backward pass follows: the hidden layers and Y never leave the chip
         k_mlp_forward<<<cdiv(rows, kFuseRows), 256, 0, st>>>(P<_Float16>(M->X), (int)rows, M->w16, M->w,
-                                                             P<float>(M->Y));
-        k_iso_norm<<<cdiv((int64_t)nblk * 64, 256), 256, 0, st>>>(P<float>(M->Y), nblk, nullptr, nullptr,
-                                                                 P<_Float16>(M->G16));
+                                                             P<_Float16>(M->G16));
         LAUNCH_CHECK();
         return FIC_OK;
     }
+    if ((rc = mgrow(M->Y, rows * kMlpOut * 4))) return rc;
     if ((rc = mgrow(M->H1, rows * kMlpHid * 2)) || (rc = mgrow(M->H2, rows * kMlpHid * 2))) return rc;
     if (keep && ((rc = mgrow(M->G32, (int64_t)nblk * 64 * 4)) || (rc = mgrow(M->nrm, (int64_t)nblk * 4))))
         return rc;

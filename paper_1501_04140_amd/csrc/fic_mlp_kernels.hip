@@ -232,14 +232,17 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const _Float16* __restrict__ A,
 // bit theirs. Layers 1 and 2: wave w computes columns [64 w, 64 w + 64) of all
 // 64 rows; layer 3: rows [16 w, 16 w + 16). Weight fragments come from L2,
 // the next k step's in flight during the current one. Rows past M read the
-// last row and are not stored.
+// last row and are not stored. The 64 rows are 8 blocks of 8 isometry rows:
+// the layer-3 tile goes through LDS and each wave finishes two blocks' sums
+// and norms with the arithmetic of k_iso_norm, in the same order, so the
+// embeddings G16 are bit for bit those of k_iso_norm on Y.
 constexpr int kFuseRows = 64;
 constexpr int kFuseLd = kMlpHid + 8;  // LDS row stride of a hidden layer in halves (16 bytes of padding)
 
 __global__ __launch_bounds__(256) void k_mlp_forward(const _Float16* __restrict__ X, int M,
                                                      const _Float16* __restrict__ w16,
                                                      const float* __restrict__ w,
-                                                     float* __restrict__ Y) {
+                                                     _Float16* __restrict__ G16) {
     __shared__ __align__(16) _Float16 sH1[kFuseRows * kFuseLd];
     __shared__ __align__(16) _Float16 sH2[kFuseRows * kFuseLd];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -344,15 +347,28 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const _Float16* __restrict_
                 for (int j = 0; j < 4; ++j) fb[j] = nb[j];
         }
     }
+    // Y tile in LDS (H1's space, read for the last time before the barrier above)
+    constexpr int kYLd = kMlpOut + 4;
+    float* tY = reinterpret_cast<float*>(sH1);
+    static_assert(kFuseRows * kYLd * 4 <= kFuseRows * kFuseLd * 2, "Y tile fits in H1's space");
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = 16 * j + r;
         const float bv = w[kOffB3 + col];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int row = m0 + 16 * wave + 4 * g + e;
-            if (row < M) Y[(int64_t)row * kMlpOut + col] = 1.0f * out[j][e] + bv;
-        }
+        for (int e = 0; e < 4; ++e) tY[(16 * wave + 4 * g + e) * kYLd + col] = 1.0f * out[j][e] + bv;
+    }
+    __syncthreads();
+    // S_q = sum_t Y[8 q + t], G_q = S_q / |S_q|: wave w takes blocks 2 w and 2 w + 1
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int q = 2 * wave + b, row0 = m0 + 8 * q;
+        float sum = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) sum += tY[(8 * q + t) * kYLd + lane];
+        const float nn = sqrtf(wave_sum_f32(sum * sum));
+        const float gq = nn > 0.0f ? sum / nn : 0.0f;
+        if (row0 < M) G16[(int64_t)(row0 / 8) * 64 + lane] = (_Float16)gq;
     }
 }
 
