@@ -823,13 +823,21 @@ __global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img
                                                  const int32_t* __restrict__ cand, int kc,
                                                  int nr, KSet ks, fic_match* __restrict__ out) {
     __shared__ int sr[64];
-    __shared__ int sd[kTopK][64];
+    __shared__ __align__(16) int srp[8][64];  // <srp[t], d> = <R, T_t d>
+    __shared__ __align__(16) int sd[kTopK][64];
     __shared__ int64_t redF[4], redK[4];
     const int q = blockIdx.x, tid = threadIdx.x;
     if (q >= nr) return;
     const int rgx = W / 8;
     const int y = (q / rgx) * 8, x = (q % rgx) * 8;
     if (tid < 64) sr[tid] = img[(int64_t)(y + (tid >> 3)) * pitch + x + (tid & 7)];
+    __syncthreads();
+    // the range permuted once per isometry: T_t d takes d[src_t(e)] to place e,
+    // so R[e] goes to place src_t(e) of copy t
+    for (int i = tid; i < 8 * 64; i += 256) {
+        const int t = i >> 6, e = i & 63;
+        srp[t][iso_src(8, t, e >> 3, e & 7)] = sr[e];
+    }
     for (int e = tid; e < kTopK * 64; e += 256) {
         const int c = e >> 6, m = e & 63;
         const int j = c < kc ? cand[(int64_t)q * kc + c] : -1;
@@ -844,21 +852,35 @@ __global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img
     const int c = tid >> 3, t = tid & 7;
     const int j = c < kc ? cand[(int64_t)q * kc + c] : -1;
     int64_t F = INT64_MAX, K = INT64_MAX;
-    int SR = 0, SR2 = 0;
-    for (int e = 0; e < 64; ++e) {
-        SR += sr[e];
-        SR2 += sr[e] * sr[e];
+    // the 8 threads of a candidate (consecutive lanes) each sum one eighth of the
+    // range and of the domain, then combine; every sum is exact in 32 bits
+    // (S2 <= 64 * 1020^2, |Pc| <= 64 * 255 * 1020)
+    int SR = 0, SR2 = 0, S = 0, S2 = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = sr[8 * t + u], d = sd[c][8 * t + u];
+        SR += r;
+        SR2 += r * r;
+        S += d;
+        S2 += d * d;
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+        SR += __shfl_xor(SR, o, 64);
+        SR2 += __shfl_xor(SR2, o, 64);
+        S += __shfl_xor(S, o, 64);
+        S2 += __shfl_xor(S2, o, 64);
     }
     if (j >= 0 && j < total) {
-        int S = 0, Pc = 0;
-        int64_t S2 = 0;
-        for (int e = 0; e < 64; ++e) {
-            const int d = sd[c][e];
-            S += d;
-            S2 += d * d;
-            Pc += sr[e] * sd[c][iso_src(8, t, e >> 3, e & 7)];
+        int Pc = 0;
+        const int4* pr = reinterpret_cast<const int4*>(srp[t]);
+        const int4* pd = reinterpret_cast<const int4*>(sd[c]);
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int4 a = pr[e], b = pd[e];
+            Pc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
         }
-        const int64_t Ap = 64 * S2 - (int64_t)S * S;
+        const int64_t Ap = 64 * (int64_t)S2 - (int64_t)S * S;
         const int64_t Bp = 64 * (int64_t)Pc - (int64_t)SR * S;
         int s;
         best_contrast(Bp, Ap, ks, F, s);
