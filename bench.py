@@ -187,6 +187,20 @@ def with_traffic(roof: dict, workload: str):
     return roof
 
 
+def codes_equal(got, ref) -> bool:
+    """Every field of every leaf code equal to the oracle's, and e_num * n equal to its
+    exact (40 n)^2 E."""
+    import numpy as np
+    if len(got) != len(ref):
+        return False
+    for f in ("level", "y", "x", "dom", "dy", "dx", "iso", "s_idx", "k", "q_o"):
+        if not np.array_equal(got[f].astype(np.int64), ref[f].astype(np.int64)):
+            return False
+    n = (1 << got["log2B"].astype(np.int64)) ** 2
+    return bool(np.array_equal(n, ref["B"].astype(np.int64) ** 2)
+                and np.array_equal(got["e_num"] * n, ref["e_lit"]))
+
+
 def run_quadtree(args, torch):
     import numpy as np
 
@@ -282,13 +296,15 @@ def run_quadtree(args, torch):
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        om, dt, reps = 0, 0.0, 0
+        om, dt, reps, ocodes = 0, 0.0, 0, None
         while dt < 10.0 and reps < 10:  # whole encodes, repeated to about 10 s of CPU time
             t0 = time.perf_counter()
-            _, ost = oracle.encode_image(img, s_sets=s_sets)
+            ocodes, ost = oracle.encode_image(img, s_sets=s_sets)
             dt += time.perf_counter() - t0
             om += sum(s["matches"] for s in ost)
             reps += 1
+        # the oracle's codes of this very encode against the GPU's, field by field
+        res["parity"] = codes_equal(fic.codes_numpy(out[0], out[1]), ocodes)
         res["cpu_baseline"] = {"value": om / dt, "unit": "matches/s", "cores": oracle.num_threads(),
                                "kind": "oracle", "seconds": dt,
                                "sample": f"the whole 512x512 encode, {reps} times, same image and s values",

@@ -24,8 +24,9 @@ histogram entropy in bits with a strict threshold, a floor of ``min_pool``
 highest-entropy domains, split iff RMS error > T, round-half-up offsets, and
 an integer decoder.
 
-Parity unpinned: the calibrated contrast values (``calibrate_s``) depend only
-on the oracle's own exhaustive run; no external value pins them.
+The calibrated contrast values (``calibrate_s``) are pinned on an image built
+so that its kept low-entropy ranges, their best contrasts and their rounded
+mean are known by construction (and checked by a Fraction brute force).
 """
 from __future__ import annotations
 

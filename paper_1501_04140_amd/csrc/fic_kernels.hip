@@ -973,12 +973,12 @@ __device__ inline int active_chunks(int P, int TN, int n_chunks) {
 }
 
 // Domain loop of the B = 2 small-set matcher for IT isometries of one range.
-// Records {d'0 | d'1 << 16, d'2 | d'3 << 16, kf A' - 80 p, p} with p the pool
-// position and kf the first contrast value in use; TWO adds the second value
-// through (k1 - k0) A'. Seeding the first dot product with p (in a register
-// already) and removing 80 p through the record keeps G exact:
-// G = 80 (sum_i d'_i w_i + p) + kf A' - 80 p. Running minimum of G and the
-// pool position of its first occurrence, per isometry.
+// Records {d'0 | d'1 << 16, d'2 | d'3 << 16, kf A', p} with p the pool position
+// and kf the first contrast value in use; TWO adds the second value through
+// (k1 - k0) A'. G = 80 sum_i d'_i w_i + kf A' with |sum_i d'_i w_i| <= 4 * 1020
+// * 765 < 2^22, so one 24-bit multiply-add is exact whatever the pool size.
+// Running minimum of G and the pool position of its first occurrence, per
+// isometry.
 template <int IT, bool TWO>
 __device__ __forceinline__ void match_b2_loop(const int4* sRec, const int32_t* sE1, int cnt,
                                               const uint32_t* w01, const uint32_t* w23, int* g0,
@@ -1001,7 +1001,7 @@ __device__ __forceinline__ void match_b2_loop(const int4* sRec, const int32_t* s
         const int e1 = TWO ? sE1[d] : 0;
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
-            int dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.x), a01[i], rec.w, false);
+            int dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.x), a01[i], 0, false);
             dsum = __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, rec.y), a23[i], dsum, false);
             const int g = __mul24(dsum, 80) + rec.z;
             const bool lt = g < bg0[i];
@@ -1142,14 +1142,13 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
                 // B = 2: the 4 sums d' as two pairs of 16-bit values (from the high and
                 // low bytes), k0 A', the pool position, and (k1 - k0) A' aside
                 const uint32_t h = HL[(int64_t)(base + i) * 2], l = HL[(int64_t)(base + i) * 2 + 1];
-                // the first value in use is kf; the loop seeds its dot product with
-                // the pool position, so kf A' - 80 position is stored
+                // the first value in use is kf (kf A' <= 10 * 4 * 4 * 1020^2 < 2^28)
                 const int k0 = ks.n > 0 ? ks.k[0] : 0, k1 = ks.n > 1 ? ks.k[1] : 0;
                 const int kf = k0 != 0 ? k0 : k1;
                 int4 rec;
                 rec.x = (int)__builtin_amdgcn_perm(h, l, 0x05010400u);  // d0 | d1 << 16
                 rec.y = (int)__builtin_amdgcn_perm(h, l, 0x07030602u);  // d2 | d3 << 16
-                rec.z = (int)((int64_t)kf * a - 80 * (int64_t)(base + i));
+                rec.z = (int)((int64_t)kf * a);
                 rec.w = base + i;
                 sRec[i] = rec;
                 sE1[i] = (int)((int64_t)(k1 - k0) * a);
@@ -1182,7 +1181,7 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
             if constexpr (B == 2) {
                 // G_u = k_u A' + 80 sum_i d'_i (sum r - 4 r_i): the weights sum r - 4 r_i
                 // lie in [-765, 765], so two v_dot2_i32_i16 give the sum exactly, and
-                // |sum + p| < 2^22 leaves one 24-bit multiply-add for G
+                // |sum| < 2^22 leaves one 24-bit multiply-add for G
                 uint32_t w01[IT], w23[IT];
                 int g0[IT], p0[IT], g1[IT], p1[IT];
 #pragma unroll

@@ -311,6 +311,53 @@ def test_quadtree_full_size_paper_preset(dev):
     assert np.array_equal(rec.cpu().numpy(), oracle.decode(ref, 512, 512, iters=8))
 
 
+def test_quadtree_full_size_calibrated(dev):
+    """The default workload: 512x512 1/f^2 + rectangles with one contrast value per level,
+    {1}, {3}, {9}, {9}. With one value the B = 2 level takes the single-value branch of the
+    VALU matcher (the largest kernel of that encode), which the printed preset (two values)
+    does not reach at full size."""
+    img = synth.quadtree_image(0)
+    ks = ((1,), (3,), (9,), (9,))
+    say("[quadtree] 512 calibrated sets")
+    codes, n, got, st = gpu_image(dev, img, fic.EncoderParams(s_sets=ks))
+    ref, rst = oracle.encode_image(img, s_sets=ks)
+    assert_codes_equal(got, ref)
+    for l, s in enumerate(rst):
+        assert (st["pool"][l], st["active"][l], st["accepted"][l]) == (s["pool"], s["active"], s["accepted"])
+    rec = fic.decode(codes, int(n.item()), 512, 512, iters=8)
+    assert np.array_equal(rec.cpu().numpy(), oracle.decode(ref, 512, 512, iters=8))
+
+
+def _big_b2_image(N=2944):
+    """Uniform noise with three 2 x 2 ranges planted as exact scaled copies of domains near
+    the end of the B = 2, L = 1 grid ((N - 3)^2 = 8,649,481 domains at N = 2944, above 2^23),
+    so the winners sit at pool positions 6.5M-8.6M."""
+    rng = np.random.default_rng(23)
+    img = rng.integers(0, 256, size=(N, N)).astype(np.int64)
+    yx = []
+    for (ry, rx), (dy, dx), k, o, t in [((0, 0), (N - 4, N - 4), 5, 30, 3),
+                                        ((100, 2000), (2500, 1777), 9, 7, 6),
+                                        ((2940, 10), (2200, 2939), 10, 0, 0)]:
+        m = rng.integers(0, 26, size=(2, 2))
+        img[dy:dy + 4, dx:dx + 4] = np.kron(10 * m, np.ones((2, 2), np.int64))
+        rot = [m, np.rot90(m, -1), np.rot90(m, 2), np.rot90(m, 1)][t % 4]
+        img[ry:ry + 2, rx:rx + 2] = k * (np.fliplr(rot) if t >= 4 else rot) + o
+        yx.append((ry, rx))
+    return img.astype(np.uint8), np.array(yx + [(500, 500), (N - 2, N - 2)], np.int32)
+
+
+@pytest.mark.parametrize("ks", [(5,), (5, 9), (10,)])
+def test_b2_pool_beyond_2_23(dev, ks):
+    """The B = 2 small-set matcher over an unfiltered grid of 8.6M domains: its exact 24-bit
+    multiply-add must not depend on the pool position."""
+    img, yx = _big_b2_image()
+    say(f"[level] B=2 L=1 grid above 2^23, ks={ks}")
+    got = check_level(dev, img, 2, 1, ks, ranges=yx)
+    # a winner beyond 2^23 - 4 * 1020 * 765 (about 5.26M), where a dot product seeded with
+    # the pool position would leave the 24-bit multiplier's range
+    assert got["dom"].max() > (1 << 23) - 4 * 1020 * 765
+
+
 def test_calibration_matches_oracle(dev):
     img = synth.power_law(64, beta=2.0, seed=0, n_rect=3)
     say("[calibrate] 64")

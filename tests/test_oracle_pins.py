@@ -458,3 +458,78 @@ def test_select_s_rule():
     assert oracle.select_s(h, 0.5) == ((3, 7), (9,), (4, 6), ())
     assert oracle.select_s(h, 0.0)[1] == (2, 9)
     assert oracle.select_s(h, 1.0)[0] == (3,)
+
+
+# --------------------------------------------------------------------------- calibrated contrast values
+def _calibration_image(k):
+    """8 x 16 image for the levels (4, 2), fixed by construction.
+
+    Left half: the 4 x 4 range at (0, 0) holds six grey levels, one per 8-bin
+    histogram bin 0..5, with counts {4, 4, 2, 2, 2, 2} (entropy exactly 2.5
+    bits); the other three left ranges are constant (200). Right half: the one
+    domain at x = 8 whose 2 x 2 cells are constant with R = (k/10) d + 16, so
+    the range at (0, 0) is an exact scaled copy (E = 0, contrast k). The four
+    right ranges are two-tone checkers of 2 x 2 cells (1 bit each) that no
+    domain matches within RMS 8, so they split into constant 2 x 2 children.
+    """
+    v = np.array([16, 48, 80, 112, 144, 176])
+    q = lambda a, b: np.array([[a, b], [b, a]])
+    r6 = np.block([[q(v[0], v[1]), q(v[0], v[2])], [q(v[1], v[3]), q(v[4], v[5])]])
+    img = np.full((8, 16), 200, np.int64)
+    img[0:4, 0:4] = r6
+    d = (r6 - 16) * 10 // k
+    assert ((d * k) == (r6 - 16) * 10).all()
+    img[0:8, 8:16] = np.kron(d, np.ones((2, 2), np.int64))
+    return img.astype(np.uint8)
+
+
+def _brute_best(img, ry, rx, B, L):
+    """Literal eq. (1) in Fractions over every (domain, isometry, k of the 11-value grid)."""
+    H, W = img.shape
+    gx = (W - 2 * B) // L + 1
+    r = [int(v) for v in img[ry:ry + B, rx:rx + B].ravel()]
+    n = len(r)
+    cands = []
+    for j in range(((H - 2 * B) // L + 1) * gx):
+        y, x = (j // gx) * L, (j % gx) * L
+        blk = img[y:y + 2 * B, x:x + 2 * B].astype(np.int64)
+        dm = blk[0::2, 0::2] + blk[0::2, 1::2] + blk[1::2, 0::2] + blk[1::2, 1::2]
+        for t in range(8):
+            d = [Fraction(int(v), 4) for v in np_iso(dm, t).ravel()]
+            for k in range(11):
+                s = Fraction(k, 10)
+                o = Fraction(sum(r), n) - s * sum(d) / n
+                cands.append((sum((s * di + o - ri) ** 2 for di, ri in zip(d, r)), j, t, k))
+    return min(cands)
+
+
+@pytest.mark.parametrize("k,expect,all_active", [(10, 3, 2), (8, 2, 3)])
+def test_calibrate_s_constructed(orc, k, expect, all_active):
+    """The abstract's "mean optimal s of low-entropy ranges", on an image whose answer is fixed
+    by construction. Level 0 keeps the exact copy (contrast k, entropy exactly 2.5 bits, so it
+    is low: H <= 2.5) and three constant ranges (contrast 0, the first candidate); the four
+    checkers split. Mean k/4, rounded half up: 10/4 -> 3 and 8/4 -> 2. The three plausible
+    misreadings give other values: a strict H < 2.5 drops the copy (0), rounding half down gives
+    2 for 2.5, and averaging every active range instead of the kept ones gives ``all_active``.
+    Level 1 holds only constant children: 0."""
+    img = _calibration_image(k)
+    # the construction, checked by brute force
+    assert _brute_best(img, 0, 0, 4, 2) == (0, 4, 0, k)
+    assert scipy.stats.entropy(orc.hist8(img[0:4, 0:4]), base=2) == pytest.approx(2.5)
+    for ry, rx in [(0, 4), (4, 0), (4, 4)]:
+        assert _brute_best(img, ry, rx, 4, 2) == (0, 0, 0, 0)
+    split_k = []
+    for ry, rx in [(0, 8), (0, 12), (4, 8), (4, 12)]:
+        E, _, _, kk = _brute_best(img, ry, rx, 4, 2)
+        assert E > 64 * 16 and len(np.unique(img[ry:ry + 4, rx:rx + 4] >> 5)) == 2
+        split_k.append(kk)
+    assert math.floor(Fraction(k + sum(split_k), 8) + Fraction(1, 2)) == all_active != expect
+    assert orc.calibrate_s(img, levels=(4, 2)) == ((expect,), (0,))
+
+
+def test_calibrate_s_fallback(orc):
+    """A level with no kept low-entropy range keeps the printed value of Section 3.1: a
+    constant image is kept whole at the first level, so the second level is empty."""
+    img = np.full((16, 16), 90, np.uint8)
+    assert orc.calibrate_s(img, levels=(4, 2)) == ((0,), orc.PAPER_K[1])
+    assert orc.calibrate_s(img, levels=(4, 2), fallback=((1,), (7,))) == ((0,), (7,))
