@@ -178,6 +178,45 @@ int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
                         int32_t n_ranges, fic_match* out, int32_t* pool_out, int32_t* pool_count,
                         int32_t variant, void* stream);
 
+/* Device scratch of fic_encode_level_noalloc, per GPU (64 MiB). */
+#define FIC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * fic_encode_level with no device allocation, for callers that cannot
+ * allocate: code under hipGraph stream capture, serving loops that must not
+ * call hipMalloc, harnesses that forbid it. Arguments, outputs and results
+ * are those of fic_encode_level (FIC_MATCH_AUTO matcher): the same kernels
+ * run, bit for bit the same records.
+ *
+ * Every buffer the search needs beyond the caller's inputs and outputs
+ * (control blocks, entropy table, pool keys and lists, domain moments,
+ * per-chunk partial results, active lists) lives in one array of
+ * FIC_NOALLOC_SCRATCH_BYTES bytes in each GPU's memory, held until the
+ * process ends. The call allocates nothing: no hipMalloc, hipFree or event
+ * creation; it queues kernels and device-to-device copies on `stream`.
+ *
+ * Limit: a level whose buffers exceed the array is rejected with FIC_EINVAL
+ * before anything is queued; the message gives the bytes it would need. The
+ * needs grow with the domain grid (28 + 2n bytes per grid domain, n = B*B;
+ * 28 + 4n where the FP16 small-set matcher runs; about 360 at B = 8 with a
+ * contrast grid 0..k1) and with n_ranges (about 85 bytes each for large
+ * range lists). For example 512x512 at B = 2, L = 1 (259081 domains, 65536
+ * ranges) takes about 15 MiB and 1024x1024 at B = 2, L = 1 about 60 MiB;
+ * 1024x1024 at B = 8, L = 2 with the 11-value grid does not fit.
+ *
+ * Sharing: all calls on one GPU use that GPU's one array, which keeps the
+ * last call's contents (each call first resets the parts that must start
+ * at zero). Calls that overlap in time on one GPU, on any streams, race and
+ * give undefined results: order them (one stream, or events). The first call
+ * on each GPU resolves the array's address and uploads the entropy table
+ * with a synchronous copy, so make it outside stream capture.
+ */
+int fic_encode_level_noalloc(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
+                             int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
+                             float entropy_bits, int32_t min_pool, const int32_t* range_yx,
+                             int32_t n_ranges, fic_match* out, int32_t* pool_out,
+                             int32_t* pool_count, void* stream);
+
 /*
  * Quadtree encoder (Section 2; the three cases at the end of Section 3.1).
  * Level 0 matches every B0 x B0 range. A range whose best transform has

@@ -1492,6 +1492,16 @@ __global__ void k_fill_i32(int32_t* p, int n, int v) {
     if (i < n) p[i] = v;
 }
 
+// Control blocks in their starting state: every counter zero, no floor bound.
+__global__ void k_ctrl_reset(Ctrl* c, int n) {
+    constexpr int kWords = (int)(sizeof(Ctrl) / 4);
+    constexpr int kCut = (int)(offsetof(Ctrl, cut_bound) / 4);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kWords) return;
+    const int w = i % kWords;
+    reinterpret_cast<uint32_t*>(c)[i] = (w == kCut || w == kCut + 1) ? 0xffffffffu : 0u;
+}
+
 __global__ void k_fill_u8(uint8_t* p, int H, int W, int pitch, uint8_t v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < H * W) p[(i / W) * pitch + i % W] = v;

@@ -236,6 +236,9 @@ struct Prof {
     std::vector<hipEvent_t> spare;
 } g_prof;
 
+// Set while a call that must not create events (fic_encode_level_noalloc) queues work.
+thread_local bool g_prof_off = false;
+
 hipEvent_t prof_event() {
     if (!g_prof.spare.empty()) {
         hipEvent_t e = g_prof.spare.back();
@@ -250,6 +253,7 @@ hipEvent_t prof_event() {
 class ProfScope {
   public:
     ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
+        if (g_prof_off) return;
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (!g_prof.on) return;
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -408,39 +412,47 @@ void grow(Sizes& s, const Level& v) {
     if (v.var == kVarMfq) s.dq[l] = std::max(s.dq[l], (size_t)v.total * n * 2);
 }
 
-int ensure_sizes(Workspace& ws, const Sizes& s) {
+// Every workspace buffer a plan of these sizes needs, in a fixed order:
+// get(buffer, bytes) for each. Sizing through the allocator (ensure_sizes)
+// and placing in the fixed device scratch (carve_sizes) both walk this list.
+template <typename Get>
+int visit_sizes(Workspace& ws, const Sizes& s, Get get) {
     int rc;
     for (int l = 0; l < kLevels; ++l) {
         if (!s.dom[l]) continue;
         PoolBufs& pb = ws.pl[l];
-        if ((rc = ensure(ws, pb.key, s.key[l]))) return rc;
-        if ((rc = ensure(ws, pb.pool, s.dom[l] * 4))) return rc;
-        if ((rc = ensure(ws, pb.hl, s.hl[l]))) return rc;
-        if ((rc = ensure(ws, pb.sd, s.dom[l] * 4))) return rc;
-        if ((rc = ensure(ws, pb.ad, s.dom[l] * 8))) return rc;
-        if ((rc = ensure(ws, pb.jd, s.dom[l] * 4))) return rc;
-        if ((rc = ensure(ws, pb.blk, s.pblk[l]))) return rc;
-        if (s.dq[l] && (rc = ensure(ws, pb.dh, s.dq[l]))) return rc;
+        if ((rc = get(pb.key, s.key[l]))) return rc;
+        if ((rc = get(pb.pool, s.dom[l] * 4))) return rc;
+        if ((rc = get(pb.hl, s.hl[l]))) return rc;
+        if ((rc = get(pb.sd, s.dom[l] * 4))) return rc;
+        if ((rc = get(pb.ad, s.dom[l] * 8))) return rc;
+        if ((rc = get(pb.jd, s.dom[l] * 4))) return rc;
+        if ((rc = get(pb.blk, s.pblk[l]))) return rc;
+        if (s.dq[l] && (rc = get(pb.dh, s.dq[l]))) return rc;
         if (s.dcol[l]) {
-            if ((rc = ensure(ws, pb.dh, s.dcol[l] * 128))) return rc;  // h rows, or FP16 columns
-            if ((rc = ensure(ws, pb.dl, s.dcol[l] * 64))) return rc;
-            if ((rc = ensure(ws, pb.wd, s.dcol[l] * 4))) return rc;
-            if ((rc = ensure(ws, pb.cw, s.dcol[l] * 4))) return rc;
+            if ((rc = get(pb.dh, s.dcol[l] * 128))) return rc;  // h rows, or FP16 columns
+            if ((rc = get(pb.dl, s.dcol[l] * 64))) return rc;
+            if ((rc = get(pb.wd, s.dcol[l] * 4))) return rc;
+            if ((rc = get(pb.cw, s.dcol[l] * 4))) return rc;
         }
     }
-    if ((rc = ensure(ws, ws.sr, s.rng * 4))) return rc;
-    if ((rc = ensure(ws, ws.cr, s.rng * 8))) return rc;
-    if ((rc = ensure(ws, ws.part, s.part))) return rc;
-    if ((rc = ensure(ws, ws.blk, s.blk))) return rc;
-    if ((rc = ensure(ws, ws.act0, s.act * 4))) return rc;
-    if ((rc = ensure(ws, ws.act1, s.act * 4))) return rc;
-    if ((rc = ensure(ws, ws.tmpc, s.act * sizeof(fic_code)))) return rc;
-    if ((rc = ensure(ws, ws.dec, s.act))) return rc;
+    if ((rc = get(ws.sr, s.rng * 4))) return rc;
+    if ((rc = get(ws.cr, s.rng * 8))) return rc;
+    if ((rc = get(ws.part, s.part))) return rc;
+    if ((rc = get(ws.blk, s.blk))) return rc;
+    if ((rc = get(ws.act0, s.act * 4))) return rc;
+    if ((rc = get(ws.act1, s.act * 4))) return rc;
+    if ((rc = get(ws.tmpc, s.act * sizeof(fic_code)))) return rc;
+    if ((rc = get(ws.dec, s.act))) return rc;
     if (s.ar) {
-        if ((rc = ensure(ws, ws.ar, s.ar))) return rc;
-        if ((rc = ensure(ws, ws.srp, s.rng * 4))) return rc;
+        if ((rc = get(ws.ar, s.ar))) return rc;
+        if ((rc = get(ws.srp, s.rng * 4))) return rc;
     }
     return FIC_OK;
+}
+
+int ensure_sizes(Workspace& ws, const Sizes& s) {
+    return visit_sizes(ws, s, [&ws](Buf& b, size_t bytes) { return ensure(ws, b, bytes); });
 }
 
 // Kernel arguments of one image at one level.
@@ -931,16 +943,18 @@ FIC_API int fic_version(void) { return 100; }
 
 FIC_API const char* fic_last_error(void) { return g_err.c_str(); }
 
-FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
-                                int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
-                                float entropy_bits, int32_t min_pool, const int32_t* range_yx,
-                                int32_t n_ranges, fic_match* out, int32_t* pool_out,
-                                int32_t* pool_count, int32_t variant, void* stream) {
+namespace fic {
+namespace {
+
+// Host checks of one level's arguments (fic_encode_level_ex); *ks and *var
+// receive the contrast set and the matcher.
+int check_level(const uint8_t* img, int H, int W, int pitch, int B, int L, const int8_t* s_k, int n_s,
+                int entropy_mode, float entropy_bits, int min_pool, const int32_t* range_yx, int n_ranges,
+                const fic_match* out, int variant, KSet* ks, int* var) {
     int rc = check_image(img, H, W, pitch, B);
     if (rc) return rc;
     if (L < 1) return fail(FIC_EINVAL, "domain step L=%d < 1", L);
-    KSet ks;
-    if ((rc = check_kset(s_k, n_s, &ks))) return rc;
+    if ((rc = check_kset(s_k, n_s, ks))) return rc;
     if (entropy_mode < 0 || entropy_mode > 2) return fail(FIC_EINVAL, "entropy_mode %d not 0, 1 or 2", entropy_mode);
     if (entropy_mode != 0 && !std::isfinite(entropy_bits)) return fail(FIC_EINVAL, "entropy_bits not finite");
     if (min_pool < 1) return fail(FIC_EINVAL, "min_pool must be >= 1");
@@ -952,41 +966,42 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
         return fail(FIC_EINVAL, "matcher variant %d unknown", variant);
     const int64_t grid_total = (int64_t)((H - 2 * B) / L + 1) * ((W - 2 * B) / L + 1);
     // FP16 MFMA: the grid form (B = 8, 0..k1) or the small-set form (B = 4, 8, 16)
-    const bool f16_small = variant == FIC_MATCH_MFMA_F16 && !mfma_eligible(B, ks) && mfq_eligible(B, ks);
+    const bool f16_small = variant == FIC_MATCH_MFMA_F16 && !mfma_eligible(B, *ks) && mfq_eligible(B, *ks);
     const bool mf = variant == FIC_MATCH_MFMA_I8 || (variant == FIC_MATCH_MFMA_F16 && !f16_small);
-    if ((mf || variant == FIC_MATCH_FP32) && !mfma_eligible(B, ks))
+    if ((mf || variant == FIC_MATCH_FP32) && !mfma_eligible(B, *ks))
         return fail(FIC_EINVAL,
                     variant == FIC_MATCH_MFMA_F16
                         ? "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2), or B = 4, 8 or 16 "
                           "and one or two values, one of them nonzero"
                         : "matcher variant %d needs B = 8 and contrast set 0..k1 (k1 >= 2)",
                     variant);
-    if (mf && !mfma_eligible(B, ks, grid_total))
+    if (mf && !mfma_eligible(B, *ks, grid_total))
         return fail(FIC_EINVAL, "the MFMA matchers take domain grids below %d domains", kM8MaxPool);
-    if (f16_small && !mfq_eligible(B, ks, grid_total))
+    if (f16_small && !mfq_eligible(B, *ks, grid_total))
         return fail(FIC_EINVAL, "the small-set MFMA matcher takes domain grids below %d domains", kMqMaxPool);
-    if (n_ranges == 0) return FIC_OK;
-    Workspace* ws;
-    if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
-    const int var = variant == FIC_MATCH_VALU ? kVarValu
-                    : variant == FIC_MATCH_MFMA_I8 ? kVarMfma
-                    : variant == FIC_MATCH_MFMA_F16 ? (f16_small ? kVarMfq : kVarMfma16)
-                    : variant == FIC_MATCH_FP32 ? kVarFp32 : 0;
-    Level v = make_level(0, H, W, B, L, n_ranges, ks, var);
-    Sizes sz;
-    grow(sz, v);
-    if ((rc = ensure_sizes(*ws, sz))) return rc;
-    hipStream_t st = ws->stream;
-    int32_t* act = P<int32_t>(ws->act0);
-    std::vector<Lvl> t{make_lvl(*ws, v, img, H, W, pitch, entropy_mode, entropy_bits, min_pool, act,
-                                P<int32_t>(ws->act1), 1, 0, nullptr, 0, nullptr)};
+    *var = variant == FIC_MATCH_VALU ? kVarValu
+           : variant == FIC_MATCH_MFMA_I8 ? kVarMfma
+           : variant == FIC_MATCH_MFMA_F16 ? (f16_small ? kVarMfq : kVarMfma16)
+           : variant == FIC_MATCH_FP32 ? kVarFp32 : 0;
+    return FIC_OK;
+}
+
+// Queue one level's search on ws.stream; every buffer of plan v is in place.
+int encode_level_run(Workspace& ws, const Level& v, const uint8_t* img, int H, int W, int pitch,
+                     int entropy_mode, float entropy_bits, int min_pool, const int32_t* range_yx,
+                     int n_ranges, fic_match* out, int32_t* pool_out, int32_t* pool_count) {
+    int rc;
+    hipStream_t st = ws.stream;
+    int32_t* act = P<int32_t>(ws.act0);
+    std::vector<Lvl> t{make_lvl(ws, v, img, H, W, pitch, entropy_mode, entropy_bits, min_pool, act,
+                                P<int32_t>(ws.act1), 1, 0, nullptr, 0, nullptr)};
     const Lvl* dt = nullptr;  // one image: arguments by value
     const std::vector<Lvl>& h = t;
     if (range_yx)
         kt_act_from_yx<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, range_yx, n_ranges);
     else
         kt_act_full<false><<<cdiv(n_ranges, kBlock), kBlock, 0, st>>>(h[0], dt, 0);
-    if ((rc = launch_level(dt, t, ws->T, entropy_mode != 0, st))) return rc;
+    if ((rc = launch_level(dt, t, ws.T, entropy_mode != 0, st))) return rc;
     {
         ProfScope ps("reduce_level", st);
         if (v.var == kVarFp32)
@@ -996,17 +1011,41 @@ FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_
     }
     LAUNCH_CHECK();
     if (pool_count)
-        HIP_TRY(hipMemcpyAsync(pool_count, &(ws->ctrl + 1)->pool_count, sizeof(int32_t),
+        HIP_TRY(hipMemcpyAsync(pool_count, &(ws.ctrl + 1)->pool_count, sizeof(int32_t),
                                hipMemcpyDeviceToDevice, st));
     if (pool_out) {
         if (entropy_mode != 0)
-            HIP_TRY(hipMemcpyAsync(pool_out, ws->pl[0].pool.p, sizeof(int32_t) * v.total,
+            HIP_TRY(hipMemcpyAsync(pool_out, ws.pl[0].pool.p, sizeof(int32_t) * v.total,
                                    hipMemcpyDeviceToDevice, st));
         else
-            HIP_TRY(hipMemcpyAsync(pool_out, ws->pl[0].jd.p, sizeof(int32_t) * v.total,
+            HIP_TRY(hipMemcpyAsync(pool_out, ws.pl[0].jd.p, sizeof(int32_t) * v.total,
                                    hipMemcpyDeviceToDevice, st));
     }
     return FIC_OK;
+}
+
+}  // namespace
+}  // namespace fic
+
+FIC_API int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
+                                int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
+                                float entropy_bits, int32_t min_pool, const int32_t* range_yx,
+                                int32_t n_ranges, fic_match* out, int32_t* pool_out,
+                                int32_t* pool_count, int32_t variant, void* stream) {
+    KSet ks;
+    int var = 0;
+    int rc = check_level(img, H, W, pitch, B, L, s_k, n_s, entropy_mode, entropy_bits, min_pool,
+                         range_yx, n_ranges, out, variant, &ks, &var);
+    if (rc) return rc;
+    if (n_ranges == 0) return FIC_OK;
+    Workspace* ws;
+    if ((rc = get_ws((hipStream_t)stream, &ws))) return rc;
+    Level v = make_level(0, H, W, B, L, n_ranges, ks, var);
+    Sizes sz;
+    grow(sz, v);
+    if ((rc = ensure_sizes(*ws, sz))) return rc;
+    return encode_level_run(*ws, v, img, H, W, pitch, entropy_mode, entropy_bits, min_pool, range_yx,
+                            n_ranges, out, pool_out, pool_count);
 }
 
 FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
@@ -1017,6 +1056,113 @@ FIC_API int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t p
     return fic_encode_level_ex(img, H, W, pitch, B, L, s_k, n_s, entropy_mode, entropy_bits,
                                min_pool, range_yx, n_ranges, out, pool_out, pool_count,
                                FIC_MATCH_AUTO, stream);
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// The workspace of fic_encode_level_noalloc: one array in each device's
+// memory for the life of the process. In host code its name is a host-side
+// stand-in, not a device address: the address comes from hipGetSymbolAddress,
+// once per device, and only that address is ever handed to kernels or copies.
+// Layout: the control blocks, the entropy table, then the level's buffers.
+static __device__ __align__(256) uint8_t scratch[FIC_NOALLOC_SCRATCH_BYTES];
+
+namespace fic {
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kScratchCtrl = ((sizeof(Ctrl) * (1 + kLevels)) + 255) & ~(size_t)255;
+constexpr size_t kScratchHead = kScratchCtrl + (((kMaxWindow + 1) * sizeof(int64_t) + 255) & ~(size_t)255);
+
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+
+// This device's scratch address; the first call on a device resolves it and
+// uploads the entropy table (a synchronous copy).
+int scratch_address(int dev, uint8_t** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(FIC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        const std::vector<int64_t>& t = entropy_table();
+        HIP_TRY(hipMemcpy(static_cast<uint8_t*>(ptr) + kScratchCtrl, t.data(), sizeof(int64_t) * t.size(),
+                          hipMemcpyHostToDevice));
+        g_scratch[dev] = static_cast<uint8_t*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return FIC_OK;
+}
+
+// Place every buffer of sz in the scratch after its head; *need receives the
+// bytes the plan takes in all.
+int carve_sizes(Workspace& ws, uint8_t* base, const Sizes& sz, size_t* need) {
+    size_t off = kScratchHead;
+    const int rc = visit_sizes(ws, sz, [&](Buf& b, size_t bytes) {
+        if (bytes == 0) bytes = 1;
+        if (b.p && b.cap >= bytes) return FIC_OK;
+        const size_t want = (bytes + 255) & ~(size_t)255;
+        b.p = base ? base + off : nullptr;
+        b.cap = want;
+        off += want;
+        return FIC_OK;
+    });
+    *need = off;
+    return rc;
+}
+
+struct NoProfile {
+    NoProfile() { g_prof_off = true; }
+    ~NoProfile() { g_prof_off = false; }
+};
+
+}  // namespace
+}  // namespace fic
+
+FIC_API int fic_encode_level_noalloc(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, int32_t B,
+                                     int32_t L, const int8_t* s_k, int32_t n_s, int32_t entropy_mode,
+                                     float entropy_bits, int32_t min_pool, const int32_t* range_yx,
+                                     int32_t n_ranges, fic_match* out, int32_t* pool_out,
+                                     int32_t* pool_count, void* stream) {
+    KSet ks;
+    int var = 0;
+    int rc = check_level(img, H, W, pitch, B, L, s_k, n_s, entropy_mode, entropy_bits, min_pool,
+                         range_yx, n_ranges, out, FIC_MATCH_AUTO, &ks, &var);
+    if (rc) return rc;
+    if (n_ranges == 0) return FIC_OK;
+    const Level v = make_level(0, H, W, B, L, n_ranges, ks, var);
+    Sizes sz;
+    grow(sz, v);
+    {
+        Workspace probe;
+        size_t need = 0;
+        carve_sizes(probe, nullptr, sz, &need);
+        if (need > (size_t)FIC_NOALLOC_SCRATCH_BYTES)
+            return fail(FIC_EINVAL,
+                        "this level needs %zu bytes of device scratch; fic_encode_level_noalloc holds %zu "
+                        "(use fic_encode_level)",
+                        need, (size_t)FIC_NOALLOC_SCRATCH_BYTES);
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FIC_EINVAL, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    uint8_t* base = nullptr;
+    if ((rc = scratch_address(dev, &base))) return rc;
+    Workspace ws;  // every buffer in the scratch; nothing here is freed
+    ws.device = dev;
+    ws.stream = (hipStream_t)stream;
+    ws.ctrl = reinterpret_cast<Ctrl*>(base);
+    ws.T = reinterpret_cast<int64_t*>(base + kScratchCtrl);
+    size_t need = 0;
+    carve_sizes(ws, base, sz, &need);
+    NoProfile np;
+    {
+        const int words = (int)(sizeof(Ctrl) / 4) * (1 + kLevels);
+        k_ctrl_reset<<<cdiv(words, kBlock), kBlock, 0, ws.stream>>>(ws.ctrl, 1 + kLevels);
+    }
+    LAUNCH_CHECK();
+    return encode_level_run(ws, v, img, H, W, pitch, entropy_mode, entropy_bits, min_pool, range_yx,
+                            n_ranges, out, pool_out, pool_count);
 }
 
 FIC_API int fic_encode_image(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,

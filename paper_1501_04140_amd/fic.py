@@ -97,6 +97,8 @@ def load():
                                      vp, vp, vp, vp]
     lib.fic_encode_level_ex.argtypes = [vp, i32, i32, i32, i32, i32, vp, i32, i32, f32, i32, vp,
                                         i32, vp, vp, vp, i32, vp]
+    lib.fic_encode_level_noalloc.argtypes = [vp, i32, i32, i32, i32, i32, vp, i32, i32, f32, i32, vp,
+                                             i32, vp, vp, vp, vp]
     lib.fic_encode_image.argtypes = [vp, i32, i32, i32, ctypes.POINTER(Params), vp, i32, vp, vp, vp]
     lib.fic_decode.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp]
     lib.fic_sse.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp]
@@ -132,7 +134,7 @@ def load():
     lib.fic_unpack_stream.argtypes = [vp, ctypes.c_int64, vp, i32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.fic_last_error.restype = ctypes.c_char_p
-    for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_image", "fic_decode", "fic_sse",
+    for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_level_noalloc", "fic_encode_image", "fic_decode", "fic_sse",
                  "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end",
                  "fic_batch_create", "fic_batch_run", "fic_batch_run_eager", "fic_batch_set_chunks", "fic_batch_get_chunks",
                  "fic_batch_autotune", "fic_batch_destroy", "fic_mlp_create", "fic_mlp_destroy",
@@ -196,6 +198,35 @@ def encode_level(img, B: int, L: int, s_k=PLAIN_K, entropy_mode: int = 0,
     _check(rc)
     out = out[:n]
     return (out, pool, pcount) if return_pool else out
+
+
+def encode_level_noalloc(img, B: int, L: int, s_k=PLAIN_K, entropy_mode: int = 0,
+                         entropy_bits: float = 2.5, min_pool: int = 256, ranges=None, out=None,
+                         pool=None, pcount=None, stream=None):
+    """fic_encode_level_noalloc: fic_encode_level with the library's workspace in
+    its fixed device scratch. The caller may pass the output tensors in (out:
+    uint8 [n_ranges, 24]; pool: int32 [grid domains]; pcount: int32 [1]); those
+    it leaves as None are not written, except `out`, which is created here."""
+    import torch
+    img = _dev_u8_image(img)
+    H, W = img.shape
+    lib = load()
+    ks = (ctypes.c_int8 * max(1, len(s_k)))(*[int(k) for k in s_k])
+    if ranges is not None:
+        ranges = ranges.to(device=img.device, dtype=torch.int32).contiguous().reshape(-1, 2)
+        n = ranges.shape[0]
+    else:
+        n = (H // B) * (W // B) if B > 0 else 0
+    if out is None:
+        out = torch.empty((max(n, 1), 24), dtype=torch.uint8, device=img.device)
+    rc = lib.fic_encode_level_noalloc(img.data_ptr(), H, W, img.stride(0), B, L, ks, len(s_k),
+                                      entropy_mode, entropy_bits, min_pool,
+                                      ranges.data_ptr() if ranges is not None else None, n,
+                                      out.data_ptr(), pool.data_ptr() if pool is not None else None,
+                                      pcount.data_ptr() if pcount is not None else None,
+                                      _stream(stream))
+    _check(rc)
+    return out[:n]
 
 
 def code_capacity(H: int, W: int, levels=LEVELS) -> int:

@@ -76,6 +76,24 @@ def test_encode_level_rejects(lib, kw, frag):
     assert rc == fic.FIC_EINVAL and frag in msg
 
 
+def test_encode_level_noalloc_checks_on_the_host(lib):
+    """The same argument checks as fic_encode_level, and a level whose buffers
+    exceed the fixed scratch is refused (with the bytes it needs) before any
+    device call."""
+    ks = (ctypes.c_int8 * 16)(*range(11))
+    f = lib.fic_encode_level_noalloc
+    assert f(None, 64, 64, 64, 8, 4, ks, 11, 0, 2.5, 1, None, 64, 1, None, None, None) == fic.FIC_EINVAL
+    assert "image pointer" in lib.fic_last_error().decode()
+    assert f(1, 64, 64, 64, 3, 4, ks, 11, 0, 2.5, 1, None, 64, 1, None, None, None) == fic.FIC_EINVAL
+    assert "range side" in lib.fic_last_error().decode()
+    for side, B, L in ((2048, 2, 1), (1024, 8, 2)):
+        rc = f(1, side, side, side, B, L, ks, 11, 0, 2.5, 1, None, (side // B) ** 2, 1, None, None, None)
+        msg = lib.fic_last_error().decode()
+        assert rc == fic.FIC_EINVAL and "scratch" in msg, msg
+        need = int(re.search(r"needs (\d+) bytes", msg).group(1))
+        assert need > (64 << 20)
+
+
 def _params(**kw):
     p = fic.EncoderParams(**{k: v for k, v in kw.items() if k in fic.EncoderParams.__dataclass_fields__})
     c = p.to_c()
