@@ -158,7 +158,7 @@ enum fic_match_variant {
                             /* partial sum is an integer below 2^24). Contrast grid at   */
                             /* B = 8: same screen and exact decision as MFMA_I8. One or  */
                             /* two values at B = 4, 8 or 16 (centred operands): F exact  */
-                            /* in FP64 per element. AUTO takes it wherever it applies    */
+                            /* in 32/64-bit integers. AUTO takes it wherever it applies  */
 };
 
 /*

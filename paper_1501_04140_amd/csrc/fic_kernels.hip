@@ -2296,17 +2296,22 @@ __device__ __forceinline__ void k_reduce_fp32_body(const uint8_t* __restrict__ i
 // FP16, and every partial sum of X = sum r' d'' is an integer of magnitude at
 // most n * 128 * 510 < 2^24 (n <= 256), so the FP32 accumulator holds X
 // exactly whatever the order of the additions. B' is a covariance, so
-// B' = n X - (sum r')(sum d''), an integer below 2^33 in magnitude, and
-// F = k^2 A' - 80 k B' is an integer below 2^44: both come out of FP64 FMAs
-// exactly (53-bit significand). Each lane keeps, for its 4 rows, the running
-// minimum of (F, position, contrast index) over its columns in registers,
-// visiting positions in ascending order with strict compares, so the first
-// occurrence wins; the 16 lanes of a row are merged lexicographically at the
+// B' = n X - (sum r')(sum d''), and for each nonzero value k of the set
+// G = k A' - 80 B' = (k A' + 80 (sum r')(sum d'')) - 80 n X is an integer:
+// |G| < 2^31 at B = 4 (Cauchy-Schwarz, |B'| <= sqrt(A' C)), so it is computed
+// in 32-bit integers there, and in 64-bit integers (one multiply-add of the
+// converted X into a per-column term) at B = 8 and 16. The 4 rows a lane
+// holds are isometries of one range, so the per-column term k A' + 80 (sum
+// r')(sum d'') is formed once per column. F = k G orders like G for a fixed
+// k > 0, so each lane keeps, per row and per nonzero value, the running
+// minimum of G and its position, visiting positions in ascending order with
+// strict compares (the first occurrence wins); the values and the 16 lanes of
+// a row are merged lexicographically on (F, position, contrast index) at the
 // end. k = 0 gives F = 0 for every domain: a set holding 0 (its first value,
-// the set being increasing) starts each row from (0, the chunk's first
+// the set being increasing) adds the candidate (0, the chunk's first
 // position, 0). The pool is short at these levels (a few hundred domains),
 // where a screen would send a large share of the elements to an exact
-// decision; this epilogue is a handful of VALU instructions per element.
+// decision; this epilogue is a handful of integer instructions per element.
 // The range blocks are staged in LDS and turned into the inverse-isometry
 // rows in registers by the kernel itself.
 constexpr int kMqWaves = 4;
@@ -2385,38 +2390,52 @@ __device__ __forceinline__ void k_pool_prep_mq_body(const uint8_t* __restrict__ 
     }
 }
 
-// grid: x = workgroups of mq_rows(B) rows (8 per range), y = pool chunks.
+// LDS of the small-set MFMA matcher (one struct, so that a kernel holding
+// several matchers can overlay them).
+template <int B, int NK>
+struct MqSmem {
+    static constexpr int n = B * B, COLS = mq_cols(B), CH = 2 * n / MqShape<B>::U + 1;
+    static constexpr int NR = mq_rows(B) / 8;
+    using GT = typename std::conditional<(B <= 4), int32_t, int64_t>::type;
+    typename MqShape<B>::LU sB[2][COLS * CH];
+    GT sKA[2][NK][COLS];      // k A' per column and nonzero value
+    int32_t sSdd[2][COLS];    // sum d'' = S - 510 n
+    uint8_t sPix[NR * n];
+    int32_t sSR[NR];
+};
+
+// Workgroup (bx, by): rows bx * mq_rows(B) .. (8 per range), pool chunk by.
 // NK: the number of nonzero values in the set (1 or 2).
 template <int B, int NK>
 __device__ __forceinline__ void k_match_mfq_body(
-    const uint8_t* __restrict__ img, int pitch, const int32_t* __restrict__ act, const int32_t* act_count,
-    const _Float16* __restrict__ Dh, const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad,
-    const int32_t* __restrict__ Jd, const Ctrl* ctrl, const KSet& ks, int n_chunks, int cg,
-    Partial* __restrict__ part, int32_t* __restrict__ SRout, int64_t* __restrict__ CRout) {
+    MqSmem<B, NK>& sm, int bx, int by, const uint8_t* __restrict__ img, int pitch,
+    const int32_t* __restrict__ act, const int32_t* act_count, const _Float16* __restrict__ Dh,
+    const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad, const int32_t* __restrict__ Jd,
+    const Ctrl* ctrl, const KSet& ks, int n_chunks, int cg, Partial* __restrict__ part,
+    int32_t* __restrict__ SRout, int64_t* __restrict__ CRout) {
     using Sh = MqShape<B>;
     using AF = typename Sh::AF;
-    using LU = typename Sh::LU;
+    using GT = typename MqSmem<B, NK>::GT;
     constexpr int n = B * B, KG = Sh::KG, KW = Sh::KW, RT = mq_row_tiles(B), ROWS = mq_rows(B);
     constexpr int NR = ROWS / 8;                // ranges per workgroup
     constexpr int COLS = mq_cols(B), CT = COLS / 16;
     constexpr int CPC = n / 8;                  // 16-byte chunks per column in memory
-    constexpr int UPC = 2 * n / Sh::U;          // LDS units per column
-    constexpr int CH = UPC + 1;                 // LDS stride per column (one unit of padding)
+    constexpr int CH = MqSmem<B, NK>::CH;       // LDS stride per column (one unit of padding)
     constexpr int NT = kMqWaves * 64;
     constexpr int NLD = COLS * CPC / NT;        // chunks per thread per stage
     static_assert(COLS * CPC % NT == 0 && COLS <= NT, "stage split over the workgroup");
-    __shared__ LU sB[2][COLS * CH];
-    __shared__ double sKA[2][NK][COLS];         // k^2 A' per column and nonzero value
-    __shared__ double sSdd[2][COLS];            // sum d'' = S - 510 n
-    __shared__ uint8_t sPix[NR * n];
-    __shared__ int32_t sSR[NR];
+    auto& sB = sm.sB;
+    auto& sKA = sm.sKA;
+    auto& sSdd = sm.sSdd;
+    auto& sPix = sm.sPix;
+    auto& sSR = sm.sSR;
 
     const int nact = *act_count, nrows = 8 * nact;
-    const int row_blk = blockIdx.x * ROWS;
+    const int row_blk = bx * ROWS;
     if (row_blk >= nrows) return;
     const int P = ctrl->pool_count;
     const int nca = active_chunks(P, cg, n_chunks);
-    const int c = blockIdx.y;
+    const int c = by;
     if (c >= nca) return;
     const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
 
@@ -2470,9 +2489,10 @@ __device__ __forceinline__ void k_match_mfq_body(
         }
         if (threadIdx.x < COLS) {
             const int t = threadIdx.x;
+            // k A' <= 10 n^2 510^2: below 2^31 for n = 16
 #pragma unroll
-            for (int m = 0; m < NK; ++m) sKA[bf][m][t] = (double)(m == 0 ? kz0 * kz0 : kz1 * kz1) * (double)ldA;
-            sSdd[bf][t] = (double)((int)ldS - 510 * n);
+            for (int m = 0; m < NK; ++m) sKA[bf][m][t] = (GT)(m == 0 ? kz0 : kz1) * (GT)ldA;
+            sSdd[bf][t] = (int)ldS - 510 * n;
         }
     };
     // the first stage's loads are in flight while the ranges are staged
@@ -2527,7 +2547,7 @@ __device__ __forceinline__ void k_match_mfq_body(
 
     // A operands: row 16 rt + c16 of the wave, K = KW kg + (KW / 4) g + e
     AF af[RT][KG];
-    double srd[RT];  // sum r' of the lane's output range
+    int srd80[RT];  // 80 sum r' of the range of the lane's 4 output rows
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int arow = wrow0 + 16 * rt + c16;
@@ -2544,19 +2564,21 @@ __device__ __forceinline__ void k_match_mfq_body(
                 af[rt][kg][e] = (_Float16)((int)rr[a0 + a1 * (m / B) + a2 * (m % B)] - 128);
             }
         const int orow = wrow0 + 16 * rt + 4 * g;
-        srd[rt] = (double)(sSR[(orow - row_blk) >> 3] - 128 * n);
+        srd80[rt] = 80 * (sSR[(orow - row_blk) >> 3] - 128 * n);
     }
-    // running best per row of the lane: F, and position << 1 | contrast index
-    double bF[RT][4];
-    int bPU[RT][4];
+    // running minimum of G per row of the lane and nonzero value, with its position
+    GT bG[RT][4][NK];
+    int bP[RT][4][NK];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            bF[rt][e] = zero_in ? 0.0 : INFINITY;
-            bPU[rt][e] = lo << 1;
-        }
-    const double m80k0 = -80.0 * kz0, m80k1 = NK > 1 ? -80.0 * kz1 : 0.0;
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int m = 0; m < NK; ++m) {
+                bG[rt][e][m] = std::numeric_limits<GT>::max();
+                bP[rt][e][m] = lo;
+            }
+    constexpr int kN80 = 80 * n;
 
     if (lo < hi) store_stage(0);
     __syncthreads();
@@ -2581,25 +2603,34 @@ __device__ __forceinline__ void k_match_mfq_body(
                 acc[rt] = x;
             }
             if (col < cnt) {
-                const double ka0 = sKA[buf][0][col], ka1 = NK > 1 ? sKA[buf][NK - 1][col] : 0.0;
-                const double sdd = sSdd[buf][col];
-                const int pu0 = ((base + col) << 1) | u0, pu1 = ((base + col) << 1) | u1;
+                GT ka[NK];
+#pragma unroll
+                for (int m = 0; m < NK; ++m) ka[m] = sKA[buf][m][col];
+                const int sdd = sSdd[buf][col];
+                const int pos = base + col;
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
-                    const double srsd = srd[rt] * sdd;  // exact: below 2^33
+                    GT yc[NK];  // k A' + 80 (sum r')(sum d'')
+#pragma unroll
+                    for (int m = 0; m < NK; ++m) {
+                        if constexpr (B <= 4)
+                            yc[m] = (GT)((uint32_t)ka[m] + (uint32_t)srd80[rt] * (uint32_t)sdd);
+                        else
+                            yc[m] = ka[m] + (int64_t)srd80[rt] * (int64_t)sdd;
+                    }
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const double Bp = fma((double)n, (double)acc[rt][e], -srsd);
-                        const double F0 = fma(m80k0, Bp, ka0);
-                        if (F0 < bF[rt][e]) {
-                            bF[rt][e] = F0;
-                            bPU[rt][e] = pu0;
-                        }
-                        if constexpr (NK > 1) {
-                            const double F1 = fma(m80k1, Bp, ka1);
-                            if (F1 < bF[rt][e]) {
-                                bF[rt][e] = F1;
-                                bPU[rt][e] = pu1;
+                        const int x = (int)acc[rt][e];  // an exact integer below 2^24
+#pragma unroll
+                        for (int m = 0; m < NK; ++m) {
+                            GT gv;
+                            if constexpr (B <= 4)
+                                gv = (GT)((uint32_t)yc[m] - (uint32_t)kN80 * (uint32_t)x);
+                            else
+                                gv = yc[m] - (int64_t)kN80 * (int64_t)x;
+                            if (gv < bG[rt][e][m]) {
+                                bG[rt][e][m] = gv;
+                                bP[rt][e][m] = pos;
                             }
                         }
                     }
@@ -2610,20 +2641,36 @@ __device__ __forceinline__ void k_match_mfq_body(
         if (nb < hi) store_stage(buf ^ 1);
         __syncthreads();
     }
-    // merge the 16 column lanes of each row: (F, position, index) lexicographic
+    // per row: the lane's best (F, position << 1 | contrast index) over its values,
+    // then over the 16 column lanes of the row, lexicographic
+    int64_t bF[RT][4];
+    int bPU[RT][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 4; ++e) {
+            bF[rt][e] = zero_in ? 0 : INT64_MAX;
+            bPU[rt][e] = lo << 1;
+#pragma unroll
+            for (int m = 0; m < NK; ++m) {
+                if (bG[rt][e][m] == std::numeric_limits<GT>::max()) continue;
+                const int64_t F = (int64_t)(m == 0 ? kz0 : kz1) * (int64_t)bG[rt][e][m];
+                const int pu = (bP[rt][e][m] << 1) | (m == 0 ? u0 : u1);
+                if (F < bF[rt][e] || (F == bF[rt][e] && pu < bPU[rt][e])) {
+                    bF[rt][e] = F;
+                    bPU[rt][e] = pu;
+                }
+            }
 #pragma unroll
             for (int m = 1; m < 16; m <<= 1) {
-                const double of = __shfl_xor(bF[rt][e], m, 64);
+                const int64_t of = __shfl_xor(bF[rt][e], m, 64);
                 const int op = __shfl_xor(bPU[rt][e], m, 64);
                 if (of < bF[rt][e] || (of == bF[rt][e] && op < bPU[rt][e])) {
                     bF[rt][e] = of;
                     bPU[rt][e] = op;
                 }
             }
+        }
     // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -2632,11 +2679,11 @@ __device__ __forceinline__ void k_match_mfq_body(
         if (lo < hi && orow < nrows && c16 == 0) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
+                if (bF[rt][e] == INT64_MAX) continue;
                 const int pos = bPU[rt][e] >> 1, u = bPU[rt][e] & 1;
-                const int64_t Fe = (int64_t)bF[rt][e];
                 const int64_t key = make_key(Jd[pos], (orow + e) & 7, u, Sd[pos]);
-                if (pair_less(Fe, key, F, K)) {
-                    F = Fe;
+                if (pair_less(bF[rt][e], key, F, K)) {
+                    F = bF[rt][e];
                     K = key;
                 }
             }
@@ -2804,7 +2851,8 @@ __global__ __launch_bounds__(kBlock) void kt_pool_prep_mq(Lvl a0, const Lvl* __r
 template <int B, int NK, bool TAB>
 __global__ __launch_bounds__(kMqWaves * 64) void kt_match_mfq(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_match_mfq_body<B, NK>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv,
+    __shared__ MqSmem<B, NK> sm;
+    k_match_mfq_body<B, NK>(sm, blockIdx.x, blockIdx.y, a.img, a.pitch, a.act, a.ctrl->act_count + a.lv,
                             reinterpret_cast<const _Float16*>(a.dh), a.sd, a.ad, a.jd, a.pctrl, a.ks, a.nc,
                             a.cg, a.part, a.sr, a.cr);
 }
