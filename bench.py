@@ -90,6 +90,8 @@ def parse():
                     help="only copy a 1 GiB device buffer 3 times (reference for the HBM byte counters)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines autotune cache for batch64 (default: none, always tune)")
+    ap.add_argument("--batch-form", default="persistent", choices=["persistent", "levels"],
+                    help="batch64: the batch's execution form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
     ap.add_argument("--preset", default="calibrated", choices=["calibrated", "paper"])
@@ -329,13 +331,25 @@ def run_batch(args, torch):
     xs = [torch.from_numpy(im).cuda() for im in imgs]
     params = fic.EncoderParams(s_sets=fic.PAPER_K)
     b = fic.Batch(xs, params)
+    # the level-synchronous form (tuned), timed as the comparison
+    b.set_form(fic.FORM_LEVELS)
+    levels_tune_ms = b.autotune(reps=2, cache_path=args.tune_cache)
+    levels_chunks = b.chunks()
+    b.run()
+    torch.cuda.synchronize()
+    levels_ms, _ = time_steps(lambda: b.run(), args.steps, args.warmup, torch)
+    ref_codes = [b.image_codes(i).cpu().numpy().copy() for i in range(len(xs))]
+    if args.batch_form == "persistent":
+        b.set_form(fic.FORM_PERSISTENT)
     tune_ms = b.autotune(reps=2, cache_path=args.tune_cache)
     b.run()
     torch.cuda.synchronize()
+    same = all(np.array_equal(b.image_codes(i).cpu().numpy(), ref_codes[i]) for i in range(len(xs)))
     st = np.stack([fic.stats_numpy(b.stats[i]) for i in range(len(xs))])
     matches_lv = st["matches"].sum(0)
     matches = int(matches_lv.sum())
     ms, wall_ms = time_steps(lambda: b.run(), args.steps, args.warmup, torch)
+    form, tiles, wgs = b.form()
     # the graph's kernels queued one by one, with HIP events around each launch
     fic.profile_begin()
     for _ in range(args.steps):
@@ -345,8 +359,23 @@ def run_batch(args, torch):
     per_label = {}
     for lv, B in enumerate(params.levels):
         per_label.update(level_ops(B, int(matches_lv[lv]), len(params.s_sets[lv])))
-    roof = with_traffic(roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")},
-                                              per_label, steps=args.steps), "batch64")
+    if form == fic.FORM_PERSISTENT:
+        # one kernel runs every level: its MFMA levels (B >= 4, small sets) and VALU level
+        # (B = 2) priced each against its own peak; peak = the rate at which the same mix of
+        # work would take the same share of time at every level's peak
+        ops, at_peak_s = 0.0, 0.0
+        for lv, B in enumerate(params.levels):
+            small = len(params.s_sets[lv]) <= 2
+            spec = per_label.get(f"match_b{B}_mfq") if (B in (4, 8, 16) and small) else None
+            o, pk = (spec[0], spec[2]) if spec else (per_label[f"match_b{B}"], PEAK_ALU_TOPS)
+            ops += o
+            at_peak_s += o / (pk * 1e12)
+        per_label["pq_quadtree"] = (ops, "alu+mfma", ops / at_peak_s / 1e12, "TOP/s")
+        roof = roofline_from_profile({k: v for k, v in prof.items() if k == "pq_quadtree"}, per_label,
+                                     steps=args.steps)
+    else:
+        roof = with_traffic(roofline_from_profile({k: v for k, v in prof.items() if k.startswith("match")},
+                                                  per_label, steps=args.steps), "batch64")
     eager_ms = sum(v[1] for v in prof.values()) / args.steps
     sides = [int(im.shape[0]) for im in imgs]
     res = {
@@ -357,10 +386,14 @@ def run_batch(args, torch):
         "config": {"workload": "batch64: 64 1/f^beta images, beta~U[1.5,2.5], sides from "
                                "{256,384,512,768,1024,2048} (seeded), paper's method, one hipGraph",
                    "sides": {str(v): sides.count(v) for v in sorted(set(sides))},
-                   "pixels": int(sum(v * v for v in sides)), "chunks": b.chunks(),
+                   "pixels": int(sum(v * v for v in sides)),
+                   "form": "persistent" if form == fic.FORM_PERSISTENT else "levels",
+                   "tiles": tiles, "workgroups": wgs, "levels_form_chunks": levels_chunks,
                    "s_k": [list(s) for s in params.s_sets],
                    "matches_per_level": [int(v) for v in matches_lv]},
         "roofline": roof,
+        "levels_form": {"encode_ms": levels_ms, "autotune_ms": levels_tune_ms,
+                        "same_codes_as_this_form": bool(same)},
         "kernel_ms_per_step_eager": {k: v[1] / args.steps for k, v in sorted(
             prof.items(), key=lambda kv: -kv[1][1])},
         "eager_kernel_sum_ms": eager_ms,

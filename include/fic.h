@@ -358,6 +358,8 @@ int fic_unpack_stream(const uint8_t* data, int64_t n_bytes, fic_code* codes, int
  * stats              optional device fic_level_stats[n * p->n_levels].
  * The batch owns one workspace per image and a private stream for capture.
  * Replays on one batch must not overlap. Only the device memory is per call.
+ * A new batch runs in the level form (FIC_BATCH_LEVELS); fic_batch_set_form
+ * selects the persistent form.
  */
 typedef struct fic_batch fic_batch;
 int fic_batch_create(int32_t n, const uint8_t* const* imgs, const int32_t* H, const int32_t* W,
@@ -379,13 +381,44 @@ int fic_batch_run_eager(fic_batch* b, void* stream);
  */
 int fic_batch_set_chunks(fic_batch* b, const int32_t* chunks);
 int fic_batch_get_chunks(const fic_batch* b, int32_t* chunks);
+
+/* How a batch's encode runs (the quadtree of Section 2 either way; the
+   codes, counts and statistics are identical). */
+enum fic_batch_form {
+    /* per level, shared launches over all images: pools, matcher, keep/split
+       decisions, compaction of the next level's active list */
+    FIC_BATCH_LEVELS = 0,
+    /* the pools of every level, then ONE persistent kernel: resident
+       workgroups drain a device queue of (image, level, range tile) tasks,
+       matching each tile over its level's pool, deciding keep/split, and
+       queueing the four children of every split range on the device (a tile
+       of the next level is queued as soon as it fills); then an ordered
+       compaction of the results into codes */
+    FIC_BATCH_PERSISTENT = 1
+};
 /*
- * Autotuner: coordinate descent over each level's chunk size, timing `reps`
- * graph replays on `stream` per candidate, then keeping the fastest.
- * The choice is cached in cache_path (JSON lines; may be NULL), keyed by GPU
- * architecture, HIP runtime version, image sizes and parameters. A cached
- * entry is applied without tuning. *best_ms (may be NULL) receives the mean
- * replay time. Synchronises `stream`.
+ * Select the form and, for the persistent form, its tile shape: tiles[l]
+ * ranges per tile at level l ([host] p->n_levels values or NULL; 0 = the
+ * library default; a multiple of the level matcher's range block, at most
+ * 256) and the number of resident workgroups (0 = every one that fits on
+ * the device; larger values are clamped to that). Rebuilds the graph; on an
+ * error the previous form is kept. Levels whose automatic matcher is an
+ * MFMA grid form (B = 8 with a contrast grid) run the VALU matcher in the
+ * persistent form; results are the same (both exact).
+ */
+int fic_batch_set_form(fic_batch* b, int32_t form, const int32_t* tiles, int32_t workgroups);
+/* The current form, tile shape (ranges per tile per level, 0 for the level
+   form) and workgroup count (0 for the level form); pointers may be NULL. */
+int fic_batch_get_form(const fic_batch* b, int32_t* form, int32_t* tiles, int32_t* workgroups);
+/*
+ * Autotuner of the current form, timing `reps` graph replays on `stream` per
+ * candidate and keeping the fastest. Level form: coordinate descent over each
+ * level's chunk size. Persistent form: coordinate descent over each level's
+ * ranges per tile (1, 2, 4 or 8 matcher blocks), then over the resident
+ * workgroups per compute unit. The choice is cached in cache_path (JSON
+ * lines; may be NULL), keyed by GPU architecture, HIP runtime version, image
+ * sizes, parameters and form. A cached entry is applied without tuning.
+ * *best_ms (may be NULL) receives the mean replay time. Synchronises `stream`.
  */
 int fic_batch_autotune(fic_batch* b, void* stream, int32_t reps, const char* cache_path,
                        float* best_ms);

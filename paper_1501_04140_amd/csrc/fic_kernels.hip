@@ -1034,8 +1034,28 @@ __device__ __forceinline__ void match_b2_loop(const int4* sRec, const int32_t* s
 //    for B <= 4; k = 0 gives F = 0 everywhere, so its best is the first domain.
 //  kModeGrid: consecutive k0..k1, closed-form minimiser, exact in int64.
 //  kModeList: any set, every value evaluated in int64.
-template <int B, int MODE>
-__device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, int pitch,
+// LDS of the VALU matcher (one struct, so that a kernel holding several
+// matchers can overlay them).
+template <int B, int MODE, int TN_ = MatchTile<B>::TN>
+struct MatchSmem {
+    using Tl = MatchTile<B>;
+    static constexpr int TN = TN_, NW = Tl::NW, n = Tl::n;
+    static constexpr int RPB = match_ranges_per_block(B, MODE);
+    static constexpr int NKA = MODE == kModeSmall ? kSmallMax : 1;
+    static constexpr bool kFast = MODE == kModeSmall && B <= 4;
+    uint32_t sHL[TN * 2 * NW];
+    uint32_t sS[kFast ? 1 : TN];
+    int64_t sA[MODE == kModeSmall ? 1 : TN];
+    typename Tl::GT sKA[NKA][kFast ? 1 : TN];
+    int4 sRec[kFast ? TN : 1];
+    int32_t sE1[kFast && B == 2 ? TN : 1];
+    uint8_t sR[RPB * n];
+};
+
+// TN_: pool domains per LDS stage (the level default, or fewer where LDS is short).
+template <int B, int MODE, int TN_ = MatchTile<B>::TN>
+__device__ __forceinline__ void k_match_body(MatchSmem<B, MODE, TN_>& sm, int bx, int by,
+                                                  const uint8_t* __restrict__ img, int pitch,
                                                   const int32_t* __restrict__ act,
                                                   const int32_t* act_count,
                                                   const uint32_t* __restrict__ HL,
@@ -1048,25 +1068,26 @@ __device__ __forceinline__ void k_match_body(const uint8_t* __restrict__ img, in
     using Tl = MatchTile<B>;
     using BpT = typename Tl::BpT;
     using GT = typename Tl::GT;
-    constexpr int n = Tl::n, NW = Tl::NW, TN = Tl::TN;
+    constexpr int n = Tl::n, NW = Tl::NW, TN = TN_;
     constexpr int IT = match_isos_per_thread(B, MODE), TPR = 8 / IT;
     constexpr int RPB = match_ranges_per_block(B, MODE);
     constexpr int NKA = MODE == kModeSmall ? kSmallMax : 1;
     // small sets at B <= 4: per domain (S, k0 A', k1 A') in one 16-byte record
     constexpr bool kFast = MODE == kModeSmall && B <= 4;
-    __shared__ uint32_t sHL[TN * 2 * NW];
-    __shared__ uint32_t sS[kFast ? 1 : TN];
-    __shared__ int64_t sA[MODE == kModeSmall ? 1 : TN];
-    __shared__ GT sKA[NKA][kFast ? 1 : TN];
-    __shared__ int4 sRec[kFast ? TN : 1];
-    __shared__ int32_t sE1[kFast && B == 2 ? TN : 1];
-    __shared__ uint8_t sR[RPB * n];
+    static_assert(NKA == MatchSmem<B, MODE, TN_>::NKA, "LDS layout");
+    auto& sHL = sm.sHL;
+    auto& sS = sm.sS;
+    auto& sA = sm.sA;
+    auto& sKA = sm.sKA;
+    auto& sRec = sm.sRec;
+    auto& sE1 = sm.sE1;
+    auto& sR = sm.sR;
 
     const int nact = *act_count;
-    const int q0 = blockIdx.x * RPB;
+    const int q0 = bx * RPB;
     if (q0 >= nact) return;
     const int P = ctrl->pool_count;
-    const int c = blockIdx.y;
+    const int c = by;
     if (c >= active_chunks(P, cg, n_chunks)) return;
     const int nca = active_chunks(P, cg, n_chunks);
 
@@ -2392,9 +2413,9 @@ __device__ __forceinline__ void k_pool_prep_mq_body(const uint8_t* __restrict__ 
 
 // LDS of the small-set MFMA matcher (one struct, so that a kernel holding
 // several matchers can overlay them).
-template <int B, int NK>
+template <int B, int NK, int COLS_ = mq_cols(B)>
 struct MqSmem {
-    static constexpr int n = B * B, COLS = mq_cols(B), CH = 2 * n / MqShape<B>::U + 1;
+    static constexpr int n = B * B, COLS = COLS_, CH = 2 * n / MqShape<B>::U + 1;
     static constexpr int NR = mq_rows(B) / 8;
     using GT = typename std::conditional<(B <= 4), int32_t, int64_t>::type;
     typename MqShape<B>::LU sB[2][COLS * CH];
@@ -2406,21 +2427,22 @@ struct MqSmem {
 
 // Workgroup (bx, by): rows bx * mq_rows(B) .. (8 per range), pool chunk by.
 // NK: the number of nonzero values in the set (1 or 2).
-template <int B, int NK>
+// COLS_: pool domains per LDS stage (the level default, or fewer where LDS is short).
+template <int B, int NK, int COLS_ = mq_cols(B)>
 __device__ __forceinline__ void k_match_mfq_body(
-    MqSmem<B, NK>& sm, int bx, int by, const uint8_t* __restrict__ img, int pitch,
+    MqSmem<B, NK, COLS_>& sm, int bx, int by, const uint8_t* __restrict__ img, int pitch,
     const int32_t* __restrict__ act, const int32_t* act_count, const _Float16* __restrict__ Dh,
     const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad, const int32_t* __restrict__ Jd,
     const Ctrl* ctrl, const KSet& ks, int n_chunks, int cg, Partial* __restrict__ part,
     int32_t* __restrict__ SRout, int64_t* __restrict__ CRout) {
     using Sh = MqShape<B>;
     using AF = typename Sh::AF;
-    using GT = typename MqSmem<B, NK>::GT;
+    using GT = typename MqSmem<B, NK, COLS_>::GT;
     constexpr int n = B * B, KG = Sh::KG, KW = Sh::KW, RT = mq_row_tiles(B), ROWS = mq_rows(B);
     constexpr int NR = ROWS / 8;                // ranges per workgroup
-    constexpr int COLS = mq_cols(B), CT = COLS / 16;
+    constexpr int COLS = COLS_, CT = COLS / 16;
     constexpr int CPC = n / 8;                  // 16-byte chunks per column in memory
-    constexpr int CH = MqSmem<B, NK>::CH;       // LDS stride per column (one unit of padding)
+    constexpr int CH = MqSmem<B, NK, COLS_>::CH;  // LDS stride per column (one unit of padding)
     constexpr int NT = kMqWaves * 64;
     constexpr int NLD = COLS * CPC / NT;        // chunks per thread per stage
     static_assert(COLS * CPC % NT == 0 && COLS <= NT, "stage split over the workgroup");
@@ -2815,7 +2837,8 @@ __global__ __launch_bounds__(kBlock) void kt_pool_prep(Lvl a0, const Lvl* __rest
 template <int B, int MODE, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_match(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_match_body<B, MODE>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.hl, a.sd, a.ad, a.jd,
+    __shared__ MatchSmem<B, MODE> sm;
+    k_match_body<B, MODE>(sm, blockIdx.x, blockIdx.y, a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.hl, a.sd, a.ad, a.jd,
                           a.pctrl, a.ks, a.nc, a.part, a.sr, a.cr, a.cg);
 }
 

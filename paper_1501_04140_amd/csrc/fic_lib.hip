@@ -19,6 +19,7 @@
 #include "fic_internal.h"
 #include "fic_kernels.hip"
 #include "fic_mlp_kernels.hip"
+#include "fic_persist.hip"
 
 #define FIC_API extern "C" __attribute__((visibility("default")))
 
@@ -1470,10 +1471,178 @@ struct fic_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t matches_hint = 0;
+    // persistent form
+    int form = FIC_BATCH_LEVELS;
+    std::vector<int> tiles;  // per level: ranges per tile (0 = default)
+    int wgs = 0;             // resident workgroups (0 = every one that fits)
+    void* pq_mem = nullptr;
+    size_t pq_bytes = 0;
+    fic::PqArgs pa{};
+    int32_t* blk_seg = nullptr;
+    int32_t* blk_z0 = nullptr;
+    int32_t* blk_first = nullptr;
+    int32_t* blko = nullptr;
+    int2* blkc = nullptr;
+    int n_blk = 0;
+    int pq_grid = 0;
 };
 
 namespace fic {
 namespace {
+
+// ---------------------------------------------------------------- persistent form
+// Matcher of a level inside the persistent kernel.
+int pq_kind(int var, const KSet& ks) {
+    if (var == kVarMfq) return nonzero_values(ks) > 1 ? kPqMfq2 : kPqMfq1;
+    const int mode = match_mode(ks);
+    return mode == kModeSmall ? kPqValuSmall : (mode == kModeGrid ? kPqValuGrid : kPqValuList);
+}
+
+// Ranges per tile a level takes by default: one matcher call at level 0 (so
+// that a single image's first level spreads over many workgroups), about 64
+// below it.
+int pq_default_tile(int B, int kind, int l) {
+    const int per = pq_block_ranges(B, kind);
+    return l == 0 ? per : per * std::max(1, 64 / per);
+}
+
+int pq_tile(const fic_batch* b, int l, int kind) {
+    const int B = b->p.B0 >> l;
+    return (b->tiles.size() > (size_t)l && b->tiles[l] > 0) ? b->tiles[l] : pq_default_tile(B, kind, l);
+}
+
+// Sizes, tile and slot tables, the device buffers (zeroed once: every queue
+// word then carries an old epoch) and the launch shape of the persistent form.
+int pq_build(fic_batch* b, const std::vector<int>& var) {
+    const int n = (int)b->im.size(), nl = b->p.n_levels;
+    PqArgs pa{};
+    pa.n_img = n;
+    pa.n_levels = nl;
+    pa.B0 = b->p.B0;
+    for (int l = 0; l < nl; ++l) {
+        pa.kind[l] = pq_kind(var[l], b->ks[l]);
+        pa.R[l] = pq_tile(b, l, pa.kind[l]);
+        const int per = pq_block_ranges(b->p.B0 >> l, pa.kind[l]);
+        if (pa.R[l] % per != 0 || pa.R[l] > kPqMaxTile)
+            return fail(FIC_EINVAL, "level %d: %d ranges per tile is not a multiple of %d up to %d", l, pa.R[l],
+                        per, kPqMaxTile);
+    }
+    std::vector<int32_t> tile_base((size_t)nl * n), blk_first((size_t)nl * n + 1);
+    std::vector<int64_t> slot_base((size_t)nl * n);
+    std::vector<int32_t> blk_seg, blk_z0;
+    int64_t tiles = 0, slots = 0;
+    for (int l = 0; l < nl; ++l) {
+        if (l == 1) pa.T0 = (int32_t)tiles;
+        for (int i = 0; i < n; ++i) {
+            const int B = b->p.B0 >> l;
+            const int64_t N = (int64_t)(b->im[i].H / B) * (b->im[i].W / B);
+            const size_t seg = (size_t)l * n + i;
+            tile_base[seg] = (int32_t)tiles;
+            slot_base[seg] = slots;
+            blk_first[seg] = (int32_t)blk_seg.size();
+            tiles += (N + pa.R[l] - 1) / pa.R[l];
+            slots += N;
+            for (int64_t z = 0; z < N; z += kPqEmitSlots) {
+                blk_seg.push_back((int32_t)seg);
+                blk_z0.push_back((int32_t)z);
+            }
+        }
+    }
+    if (nl == 1) pa.T0 = (int32_t)tiles;
+    blk_first[(size_t)nl * n] = (int32_t)blk_seg.size();
+    if (tiles >= INT32_MAX || blk_seg.size() >= (size_t)INT32_MAX)
+        return fail(FIC_EINVAL, "batch too large for the persistent form");
+    pa.T = (int32_t)tiles;
+    // launch shape: every workgroup that fits, or the caller's count
+    int dev_cus = 0, per_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kt_pq, kBlock, 0));
+    const int fit = std::max(1, dev_cus * std::max(1, per_cu));
+    b->pq_grid = b->wgs > 0 ? std::min(b->wgs, fit) : fit;
+    pa.gq_cap = (int32_t)(tiles - pa.T0) + b->pq_grid + 1;
+    // one allocation, carved
+    const size_t nb = blk_seg.size();
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_ctl = take(sizeof(PqCtl)), o_tb = take(4 * tile_base.size()), o_sb = take(8 * slot_base.size());
+    const size_t o_rec = take(sizeof(PqRec) * slots), o_st = take(slots), o_qe = take(8 * slots);
+    const size_t o_fill = take(4 * (size_t)tiles), o_gq = take(8 * (size_t)pa.gq_cap);
+    const size_t o_enq = take(16 * (size_t)n), o_rem = take(16 * (size_t)n);
+    const size_t o_bs = take(4 * nb), o_bz = take(4 * nb), o_bf = take(4 * blk_first.size());
+    const size_t o_bc = take(8 * nb), o_bo = take(4 * nb);
+    if (b->pq_bytes < off) {
+        if (b->pq_mem) (void)hipFree(b->pq_mem);
+        b->pq_mem = nullptr;
+        b->pq_bytes = 0;
+        if (hipMalloc(&b->pq_mem, off) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FIC_ENOMEM, "hipMalloc(%zu) for the persistent form failed", off);
+        }
+        b->pq_bytes = off;
+    }
+    uint8_t* m = static_cast<uint8_t*>(b->pq_mem);
+    HIP_TRY(hipMemset(m, 0, off));
+    HIP_TRY(hipMemcpy(m + o_tb, tile_base.data(), 4 * tile_base.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m + o_sb, slot_base.data(), 8 * slot_base.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m + o_bs, blk_seg.data(), 4 * nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m + o_bz, blk_z0.data(), 4 * nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m + o_bf, blk_first.data(), 4 * blk_first.size(), hipMemcpyHostToDevice));
+    pa.ctl = reinterpret_cast<PqCtl*>(m + o_ctl);
+    pa.tile_base = reinterpret_cast<const int32_t*>(m + o_tb);
+    pa.slot_base = reinterpret_cast<const int64_t*>(m + o_sb);
+    pa.rec = reinterpret_cast<PqRec*>(m + o_rec);
+    pa.state = m + o_st;
+    pa.qe = reinterpret_cast<uint64_t*>(m + o_qe);
+    pa.fill = reinterpret_cast<int32_t*>(m + o_fill);
+    pa.gq = reinterpret_cast<uint64_t*>(m + o_gq);
+    pa.enq = reinterpret_cast<int32_t*>(m + o_enq);
+    pa.rem = reinterpret_cast<int32_t*>(m + o_rem);
+    b->pa = pa;
+    b->blk_seg = reinterpret_cast<int32_t*>(m + o_bs);
+    b->blk_z0 = reinterpret_cast<int32_t*>(m + o_bz);
+    b->blk_first = reinterpret_cast<int32_t*>(m + o_bf);
+    b->blkc = reinterpret_cast<int2*>(m + o_bc);
+    b->blko = reinterpret_cast<int32_t*>(m + o_bo);
+    b->n_blk = (int)nb;
+    return FIC_OK;
+}
+
+// Every kernel of the persistent form, in order, on stream st: the pools of
+// every level (they depend only on the images), the reset, the persistent
+// kernel, the ordered compaction.
+int batch_launch_pq(fic_batch* b, hipStream_t st) {
+    const Lvl* dt = static_cast<const Lvl*>(b->dtab);
+    const int n = (int)b->im.size(), nl = b->p.n_levels;
+    const bool filtered = b->p.entropy_mode != 0;
+    for (int l = 0; l < nl; ++l)
+        for (const Group& g : b->groups) {
+            std::vector<Lvl> h(b->htab.begin() + l * n + g.start, b->htab.begin() + l * n + g.start + g.count);
+            int rc = launch_pool_phase(dt + l * n + g.start, h, b->im[0].ws->T, filtered, st);
+            if (rc) return rc;
+        }
+    const PqArgs& pa = b->pa;
+    {
+        ProfScope ps("pq_reset", st);
+        const int grid = std::max(1, std::min(1024, cdiv(std::max<int64_t>(pa.T, 4 * (int64_t)n), kBlock)));
+        kt_pq_reset<<<grid, kBlock, 0, st>>>(dt, pa);
+    }
+    {
+        ProfScope ps("pq_quadtree", st);
+        kt_pq<<<b->pq_grid, kBlock, 0, st>>>(dt, pa);
+    }
+    {
+        ProfScope ps("pq_emit", st);
+        kt_pq_count<<<b->n_blk, kBlock, 0, st>>>(dt, pa, b->blk_seg, b->blk_z0, b->blkc);
+        kt_pq_scan<<<n, kBlock, 0, st>>>(dt, pa, b->blk_first, b->blkc, b->blko, b->dorig, b->n_codes);
+        kt_pq_scatter<<<b->n_blk, kBlock, 0, st>>>(dt, pa, b->blk_seg, b->blk_z0, b->blko);
+    }
+    LAUNCH_CHECK();
+    return FIC_OK;
+}
 
 void batch_drop_graph(fic_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1483,7 +1652,10 @@ void batch_drop_graph(fic_batch* b) {
 }
 
 // Every kernel of the batch, in order, on stream st.
+int batch_launch_pq(fic_batch* b, hipStream_t st);
+
 int batch_launch(fic_batch* b, hipStream_t st) {
+    if (b->form == FIC_BATCH_PERSISTENT) return batch_launch_pq(b, st);
     const Lvl* dt = static_cast<const Lvl*>(b->dtab);
     const int n = (int)b->im.size();
     // Single stream: the batch graph is captured without the per-level pool streams.
@@ -1508,6 +1680,10 @@ int batch_build(fic_batch* b) {
         const std::vector<Level> lv0 = quad_levels(b->im[0].H, b->im[0].W, &b->p, b->ks, b->cg.data());
         for (int l = 0; l < nl; ++l) var[l] = lv0[l].var;
     }
+    // the persistent kernel holds the VALU and small-set MFMA matchers
+    if (b->form == FIC_BATCH_PERSISTENT)
+        for (int l = 0; l < nl; ++l)
+            if (var[l] != kVarMfq) var[l] = kVarValu;
     for (int i = 0; i < n; ++i) {
         BatchImage& m = b->im[i];
         std::vector<Level> lv = quad_levels(m.H, m.W, &b->p, b->ks, b->cg.data(), var.data());
@@ -1530,6 +1706,10 @@ int batch_build(fic_batch* b) {
     }
     HIP_TRY(hipMemcpy(b->dtab, tab.data(), bytes, hipMemcpyHostToDevice));
     b->htab = tab;
+    if (b->form == FIC_BATCH_PERSISTENT) {
+        int rc = pq_build(b, var);
+        if (rc) return rc;
+    }
     HIP_TRY(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
     int rc = batch_launch(b, b->st);
     hipGraph_t g = nullptr;
@@ -1545,18 +1725,19 @@ int batch_build(fic_batch* b) {
 }
 
 int batch_time(fic_batch* b, hipStream_t s, int reps, float* ms) {
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipGraphLaunch(b->exec, s));  // warm-up
-    HIP_TRY(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(b->exec, s));
-    HIP_TRY(hipEventRecord(e1, s));
-    HIP_TRY(hipEventSynchronize(e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(FIC_EDEVICE, "timing the batch: %s", hipGetErrorString(e));
     *ms = t / reps;
     return FIC_OK;
 }
@@ -1697,37 +1878,145 @@ FIC_API int fic_batch_get_chunks(const fic_batch* b, int32_t* cg) {
     return FIC_OK;
 }
 
+FIC_API int fic_batch_set_form(fic_batch* b, int32_t form, const int32_t* tiles, int32_t workgroups) {
+    if (!b) return fail(FIC_EINVAL, "batch is NULL");
+    if (form != FIC_BATCH_LEVELS && form != FIC_BATCH_PERSISTENT) return fail(FIC_EINVAL, "form %d unknown", form);
+    if (workgroups < 0) return fail(FIC_EINVAL, "workgroups < 0");
+    const int nl = b->p.n_levels;
+    std::vector<int> t(nl, 0);
+    for (int l = 0; l < nl && tiles; ++l) {
+        if (tiles[l] < 0 || tiles[l] > fic::kPqMaxTile)
+            return fail(FIC_EINVAL, "tile of %d ranges not in 0..%d", tiles[l], fic::kPqMaxTile);
+        t[l] = tiles[l];
+    }
+    const int keep_form = b->form, keep_wgs = b->wgs;
+    const std::vector<int> keep_tiles = b->tiles;
+    b->form = form;
+    b->tiles = t;
+    b->wgs = workgroups;
+    const int rc = fic::batch_build(b);
+    if (rc) {
+        // restore the previous form (its graph is rebuilt)
+        const std::string msg = fic::g_err;
+        b->form = keep_form;
+        b->tiles = keep_tiles;
+        b->wgs = keep_wgs;
+        (void)fic::batch_build(b);
+        return fail(rc, "%s", msg.c_str());
+    }
+    return FIC_OK;
+}
+
+FIC_API int fic_batch_get_form(const fic_batch* b, int32_t* form, int32_t* tiles, int32_t* workgroups) {
+    if (!b) return fail(FIC_EINVAL, "batch is NULL");
+    if (form) *form = b->form;
+    if (workgroups) *workgroups = b->form == FIC_BATCH_PERSISTENT ? b->pq_grid : 0;
+    if (tiles)
+        for (int l = 0; l < b->p.n_levels; ++l) tiles[l] = b->form == FIC_BATCH_PERSISTENT ? b->pa.R[l] : 0;
+    return FIC_OK;
+}
+
+namespace fic {
+namespace {
+
+// Persistent form: coordinate descent over each level's ranges per tile (1,
+// 2, 4 or 8 matcher calls) and then the resident workgroups per compute unit.
+int pq_autotune(fic_batch* b, hipStream_t s, int reps, float* best_out) {
+    const int nl = b->p.n_levels;
+    float best;
+    int rc = batch_time(b, s, reps, &best);
+    if (rc) return rc;
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    const int fit = b->pq_grid;
+    b->tiles.assign(nl, 0);
+    for (int l = 0; l < nl; ++l) b->tiles[l] = b->pa.R[l];
+    for (int l = 0; l < nl; ++l) {
+        const int per = pq_block_ranges(b->p.B0 >> l, b->pa.kind[l]);
+        const int keep = b->tiles[l];
+        int best_t = keep;
+        for (int m : {1, 2, 4, 8}) {
+            const int t = per * m;
+            if (t == keep || t > kPqMaxTile) continue;
+            b->tiles[l] = t;
+            if ((rc = batch_build(b))) return rc;
+            float ms;
+            if ((rc = batch_time(b, s, reps, &ms))) return rc;
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+        b->tiles[l] = best_t;
+    }
+    const int keep_w = b->wgs;
+    int best_w = keep_w;
+    for (int per_cu = 1; per_cu * cus < fit; ++per_cu) {
+        b->wgs = per_cu * cus;
+        if ((rc = batch_build(b))) return rc;
+        float ms;
+        if ((rc = batch_time(b, s, reps, &ms))) return rc;
+        if (ms < best) {
+            best = ms;
+            best_w = b->wgs;
+        }
+    }
+    b->wgs = best_w;
+    if ((rc = batch_build(b))) return rc;
+    *best_out = best;
+    return FIC_OK;
+}
+
+}  // namespace
+}  // namespace fic
+
+namespace fic {
+namespace {
+
+// Integers of the JSON list that follows `tag` in line ln (at most want of them).
+std::vector<int> parse_list(const std::string& ln, const std::string& tag, int want) {
+    std::vector<int> out;
+    const size_t q = ln.find(tag);
+    if (q == std::string::npos) return out;
+    const char* c = ln.c_str() + q + tag.size();
+    for (int l = 0; l < want; ++l) {
+        char* end = nullptr;
+        const long v = std::strtol(c, &end, 10);
+        if (end == c) break;
+        out.push_back((int)v);
+        c = end;
+        while (*c == ',' || *c == ' ') ++c;
+    }
+    return out;
+}
+
+}  // namespace
+}  // namespace fic
+
 FIC_API int fic_batch_autotune(fic_batch* b, void* stream, int32_t reps, const char* cache_path,
                                float* best_ms) {
     if (!b) return fail(FIC_EINVAL, "batch is NULL");
     if (reps < 1) return fail(FIC_EINVAL, "reps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
-    const std::string key = batch_key(b);
+    const bool pq = b->form == FIC_BATCH_PERSISTENT;
+    const std::string key = batch_key(b) + (pq ? "|persistent" : "|levels");
     const int nl = b->p.n_levels;
+    int rc;
     // cached choice?
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "r")) {
             char line[1024];
-            std::vector<int> found;
+            std::vector<int> found, wg;
             while (std::fgets(line, sizeof line, f)) {
                 std::string ln(line);
                 if (ln.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
-                size_t q = ln.find("\"chunks\": [");
-                if (q == std::string::npos) continue;
-                found.clear();
-                const char* c = ln.c_str() + q + 11;
-                for (int l = 0; l < nl; ++l) {
-                    char* end = nullptr;
-                    long v = std::strtol(c, &end, 10);
-                    if (end == c) break;
-                    found.push_back((int)v);
-                    c = end;
-                    while (*c == ',' || *c == ' ') ++c;
-                }
+                found = parse_list(ln, pq ? "\"tiles\": [" : "\"chunks\": [", nl);
+                wg = parse_list(ln, "\"workgroups\": ", 1);
             }
             std::fclose(f);
-            if ((int)found.size() == nl) {
-                int rc = fic_batch_set_chunks(b, found.data());
+            if ((int)found.size() == nl && (!pq || wg.size() == 1)) {
+                rc = pq ? fic_batch_set_form(b, FIC_BATCH_PERSISTENT, found.data(), wg[0])
+                        : fic_batch_set_chunks(b, found.data());
                 if (rc) return rc;
                 if (best_ms) {
                     float ms;
@@ -1738,34 +2027,39 @@ FIC_API int fic_batch_autotune(fic_batch* b, void* stream, int32_t reps, const c
             }
         }
     }
-    // coordinate descent over the matcher chunk of each level
-    static const int cand[] = {32, 64, 128, 256, 512, 1024, 2048, 4096};
     float best;
-    int rc = batch_time(b, s, reps, &best);
-    if (rc) return rc;
-    for (int l = 0; l < nl; ++l) b->cg[l] = batch_chunk(b, l);
-    for (int l = 0; l < nl; ++l) {
-        const int keep = b->cg[l];
-        int best_cg = keep;
-        for (int c : cand) {
-            b->cg[l] = c;
-            if ((rc = batch_build(b))) return rc;
-            float ms;
-            if ((rc = batch_time(b, s, reps, &ms))) return rc;
-            if (ms < best) {
-                best = ms;
-                best_cg = c;
+    if (pq) {
+        if ((rc = pq_autotune(b, s, reps, &best))) return rc;
+    } else {
+        // coordinate descent over the matcher chunk of each level
+        static const int cand[] = {32, 64, 128, 256, 512, 1024, 2048, 4096};
+        if ((rc = batch_time(b, s, reps, &best))) return rc;
+        for (int l = 0; l < nl; ++l) b->cg[l] = batch_chunk(b, l);
+        for (int l = 0; l < nl; ++l) {
+            const int keep = b->cg[l];
+            int best_cg = keep;
+            for (int c : cand) {
+                b->cg[l] = c;
+                if ((rc = batch_build(b))) return rc;
+                float ms;
+                if ((rc = batch_time(b, s, reps, &ms))) return rc;
+                if (ms < best) {
+                    best = ms;
+                    best_cg = c;
+                }
             }
+            b->cg[l] = best_cg;
         }
-        b->cg[l] = best_cg;
+        if ((rc = batch_build(b))) return rc;
     }
-    if ((rc = batch_build(b))) return rc;
     if (best_ms) *best_ms = best;
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "{\"key\": \"%s\", \"chunks\": [", key.c_str());
-            for (int l = 0; l < nl; ++l) std::fprintf(f, "%s%d", l ? ", " : "", b->cg[l]);
-            std::fprintf(f, "], \"ms\": %.4f}\n", best);
+            std::fprintf(f, "{\"key\": \"%s\", \"%s\": [", key.c_str(), pq ? "tiles" : "chunks");
+            for (int l = 0; l < nl; ++l) std::fprintf(f, "%s%d", l ? ", " : "", pq ? b->pa.R[l] : b->cg[l]);
+            std::fprintf(f, "]");
+            if (pq) std::fprintf(f, ", \"workgroups\": %d", b->wgs);
+            std::fprintf(f, ", \"ms\": %.4f}\n", best);
             std::fclose(f);
         }
     }
@@ -1780,6 +2074,7 @@ FIC_API int fic_batch_destroy(fic_batch* b) {
         if (m.ws) fic::free_ws(m.ws);
     if (b->dtab) (void)hipFree(b->dtab);
     if (b->dorig) (void)hipFree(b->dorig);
+    if (b->pq_mem) (void)hipFree(b->pq_mem);
     if (b->st) (void)hipStreamDestroy(b->st);
     delete b;
     return FIC_OK;

@@ -112,6 +112,8 @@ def load():
     lib.fic_batch_get_chunks.argtypes = [vp, vp]
     lib.fic_batch_autotune.argtypes = [vp, vp, i32, ctypes.c_char_p, ctypes.POINTER(f32)]
     lib.fic_batch_destroy.argtypes = [vp]
+    lib.fic_batch_set_form.argtypes = [vp, i32, vp, i32]
+    lib.fic_batch_get_form.argtypes = [vp, vp, vp, vp]
     lib.fic_mlp_create.argtypes = [vp, f32, ctypes.POINTER(vp)]
     lib.fic_mlp_destroy.argtypes = [vp]
     lib.fic_mlp_get_params.argtypes = [vp, vp]
@@ -137,7 +139,7 @@ def load():
     for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_level_noalloc", "fic_encode_image", "fic_decode", "fic_sse",
                  "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end",
                  "fic_batch_create", "fic_batch_run", "fic_batch_run_eager", "fic_batch_set_chunks", "fic_batch_get_chunks",
-                 "fic_batch_autotune", "fic_batch_destroy", "fic_mlp_create", "fic_mlp_destroy",
+                 "fic_batch_autotune", "fic_batch_destroy", "fic_batch_set_form", "fic_batch_get_form", "fic_mlp_create", "fic_mlp_destroy",
                  "fic_mlp_get_params", "fic_mlp_embed", "fic_mlp_loss_grad", "fic_mlp_adam",
                  "fic_mlp_train_step", "fic_topk_similar", "fic_encode_level_learned",
                  "fic_level_codes", "fic_encode_image_ex", "fic_pack_stream", "fic_unpack_stream",
@@ -259,6 +261,10 @@ def encode_image(img, params: EncoderParams | None = None, capacity: int | None 
     return codes, ncodes, stats
 
 
+FORM_LEVELS = 0
+FORM_PERSISTENT = 1
+
+
 class Batch:
     """fic_batch_*: n images (any sizes the encoder accepts) encoded by one
     captured hipGraph. The images must stay alive and in place; ``codes`` holds
@@ -306,6 +312,23 @@ class Batch:
     def set_chunks(self, chunks):
         arr = (ctypes.c_int32 * len(self.params.levels))(*[int(c) for c in chunks])
         _check(load().fic_batch_set_chunks(self._h, arr))
+
+    def set_form(self, form: int, tiles=None, workgroups: int = 0):
+        """fic_batch_set_form: FORM_LEVELS or FORM_PERSISTENT, with the persistent
+        form's ranges per tile per level (None or 0 = default) and resident
+        workgroups (0 = every one that fits)."""
+        nl = len(self.params.levels)
+        arr = None if tiles is None else (ctypes.c_int32 * nl)(*[int(t) for t in tiles])
+        _check(load().fic_batch_set_form(self._h, int(form), arr, int(workgroups)))
+
+    def form(self):
+        """(form, ranges per tile per level, workgroups) in use."""
+        nl = len(self.params.levels)
+        f = ctypes.c_int32(0)
+        w = ctypes.c_int32(0)
+        t = (ctypes.c_int32 * nl)()
+        _check(load().fic_batch_get_form(self._h, ctypes.byref(f), t, ctypes.byref(w)))
+        return f.value, list(t), w.value
 
     def autotune(self, reps: int = 3, cache_path: str | None = None, stream=None) -> float:
         ms = ctypes.c_float(0.0)

@@ -147,3 +147,96 @@ def test_batch_workload_images_match_single_path_and_sampled_oracle(dev):
             assert np.array_equal(lv0["e_num"][pick].astype(np.int64) * 256, ref["e_lit"])
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("min_pool,sets", [(64, "paper"), (16, "plain"), (32, "calibrated")])
+def test_persistent_form_matches_oracle_and_level_form_over_replays(dev, min_pool, sets):
+    """The persistent form (one kernel draining a device queue of range tiles)
+    gives the level form's codes, counts and statistics bit for bit, and the
+    oracle's, on mixed sizes, over replays with eager work in between."""
+    imgs = mixed_images()
+    ks = {"paper": oracle.PAPER_K, "plain": (oracle.PLAIN_K,) * 4, "calibrated": ((1,), (3,), (9,), (9,))}[sets]
+    params = fic.EncoderParams(s_sets=ks, min_pool=min_pool)
+    refs = [oracle.encode_image(im, s_sets=ks, min_pool=min_pool) for im in imgs]
+    xs = [torch.from_numpy(im).to(dev) for im in imgs]
+    say(f"[persistent] mixed sizes min_pool={min_pool} sets={sets}")
+    lv = fic.Batch(xs, params)
+    pq = fic.Batch(xs, params)
+    try:
+        lv.set_form(fic.FORM_LEVELS)
+        lv.run()
+        pq.set_form(fic.FORM_PERSISTENT)
+        form, tiles, wgs = pq.form()
+        say(f"[persistent] tiles {tiles} workgroups {wgs}")
+        assert form == fic.FORM_PERSISTENT and all(t > 0 for t in tiles) and wgs > 0
+        torch.cuda.synchronize()
+        for rep in range(3):
+            pq.codes.fill_(0xAB)
+            pq.n_codes.fill_(-1)
+            pq.stats.fill_(0)
+            pq.run()
+            torch.cuda.synchronize()
+            say(f"[persistent] replay {rep}")
+            assert torch.equal(pq.n_codes, lv.n_codes)
+            assert torch.equal(pq.stats, lv.stats)
+            for i, (ref, rst) in enumerate(refs):
+                got = fic.codes_numpy(pq.image_codes(i), int(pq.n_codes[i].item()))
+                assert np.array_equal(pq.image_codes(i).cpu().numpy(), lv.image_codes(i).cpu().numpy())
+                assert_codes_equal(got, ref)
+            fic.encode_image(xs[0], params)  # other work on the torch stream in between
+            torch.cuda.synchronize()
+    finally:
+        lv.close()
+        pq.close()
+
+
+@pytest.mark.parametrize("tiles,wgs", [([8, 16, 16, 64], 1), ([16, 64, 128, 256], 7), ([8, 128, 256, 256], 0)])
+def test_persistent_tile_shapes_do_not_change_codes(dev, tiles, wgs):
+    """Ranges per tile and the number of resident workgroups change only the
+    schedule (one workgroup runs every tile itself; seven share them)."""
+    imgs = mixed_images()[:4]
+    params = fic.EncoderParams(s_sets=oracle.PAPER_K, min_pool=32)
+    xs = [torch.from_numpy(im).to(dev) for im in imgs]
+    b = fic.Batch(xs, params)
+    try:
+        b.set_form(fic.FORM_LEVELS)
+        b.run()
+        torch.cuda.synchronize()
+        base = [b.image_codes(i).cpu().numpy().copy() for i in range(len(xs))]
+        nb = b.n_codes.clone()
+        say(f"[persistent] tiles {tiles} workgroups {wgs}")
+        b.set_form(fic.FORM_PERSISTENT, tiles, wgs)
+        f, t, w = b.form()
+        assert t == tiles and (w == wgs if wgs else w > 0)
+        for _ in range(2):
+            b.run()
+            torch.cuda.synchronize()
+            assert torch.equal(b.n_codes, nb)
+            for i in range(len(xs)):
+                assert np.array_equal(b.image_codes(i).cpu().numpy(), base[i])
+    finally:
+        b.close()
+
+
+def test_persistent_form_workload_images_match_level_form(dev):
+    """Eight images of the 64-image batch workload (sides 256..2048), paper's
+    preset: persistent form == level form bit for bit (the level form is
+    oracle-checked on the same images above)."""
+    imgs = synth.batch_images(8)
+    xs = [torch.from_numpy(im).to(dev) for im in imgs]
+    params = fic.EncoderParams(s_sets=fic.PAPER_K)
+    b = fic.Batch(xs, params)
+    try:
+        b.set_form(fic.FORM_LEVELS)
+        b.run()
+        torch.cuda.synchronize()
+        base = [b.image_codes(i).cpu().numpy().copy() for i in range(len(xs))]
+        nb, sb = b.n_codes.clone(), b.stats.clone()
+        b.set_form(fic.FORM_PERSISTENT)
+        b.run()
+        torch.cuda.synchronize()
+        assert torch.equal(b.n_codes, nb) and torch.equal(b.stats, sb)
+        for i in range(len(xs)):
+            assert np.array_equal(b.image_codes(i).cpu().numpy(), base[i])
+    finally:
+        b.close()
