@@ -23,7 +23,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_ALU_TOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 ops (32-bit multiply-add per lane per clock)
+PEAK_ALU_TOPS = 157.3  # published fp32 vector rate: 256 CU x 128 lanes x 2.4 GHz x 2 ops (multiply-add)
 PEAK_INT8_TOPS = 5000.0  # dense int8 MFMA
 PEAK_FP16_TFLOPS = 2500.0  # dense fp16 MFMA
 PEAK_HBM_GBS = 8000.0
@@ -75,6 +75,67 @@ def level_ops(B: int, matches: int, n_s: int) -> dict:
     return out
 
 
+def step_bytes(label_base: str, B: int, H: int, W: int, L: int, pool: int, active: int, kept: int) -> int:
+    """Algorithmic HBM bytes of one pool or quadtree step of one level: the data it must
+    read and write at least once (keys 8 B per grid domain, pool entries 4 B, a prepared
+    domain 2n + 16 B from its 4n pixels, a decision 16 + 12 B in and a 32-byte code out)."""
+    n = B * B
+    grid = ((H - 2 * B) // L + 1) * ((W - 2 * B) // L + 1)
+    return {
+        "pool_score": H * W + 8 * grid,
+        "pool_bound": 8 * grid,
+        "pool_count": 8 * grid,
+        "pool_scatter": 8 * grid + 4 * pool,
+        "pool_select": 8 * min(grid, 16384) + 4 * pool,
+        "pool_prep": pool * (4 * n + 2 * n + 16),
+        "reduce_quad": active * (16 + 12 + 32 + 1),
+        "quad_compact": active + kept * 64 + (active - kept) * 16,
+    }[label_base]
+
+
+def level_specs(levels, s_sets, steps_L, H, W, st) -> dict:
+    """Roofline spec per profile label of one image's quadtree: matchers as ops against
+    their ALU or MFMA peak, the pool and quadtree steps as bytes against HBM."""
+    specs = {}
+    for lv, B in enumerate(levels):
+        specs.update(level_ops(B, int(st["matches"][lv]), len(s_sets[lv])))
+        for base in ("pool_score", "pool_bound", "pool_count", "pool_scatter", "pool_select", "pool_prep",
+                     "reduce_quad", "quad_compact"):
+            b = step_bytes(base, B, H, W, steps_L[lv], int(st["pool"][lv]), int(st["active"][lv]),
+                           int(st["accepted"][lv]))
+            specs[f"{base}_b{B}"] = (b / 1e9, "hbm", PEAK_HBM_GBS, "GB/s")
+    return specs
+
+
+def kernel_rooflines(prof, specs, steps) -> list:
+    """Every profiled label: time per step, share of the profiled step, and its fraction
+    of the bound that prices it (None where no algorithmic count is defined)."""
+    total = sum(v[1] for v in prof.values())
+    rows = []
+    for label, (launches, total_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        row = {"kernel": label, "us_per_step": total_ms / steps * 1e3, "share": total_ms / total,
+               "launches_per_step": launches / steps}
+        spec = specs.get(label)
+        if spec is not None:
+            work, bound, peak, unit = spec if isinstance(spec, tuple) else (spec, "alu", PEAK_ALU_TOPS, "TOP/s")
+            scale = 1e12 if unit in ("TOP/s", "TFLOP/s") else 1e9
+            achieved = work / (total_ms / steps / 1e3) / (scale if unit != "GB/s" else 1.0)
+            row.update({"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                        "frac": achieved / peak})
+        rows.append(row)
+    return rows
+
+
+def measured_peaks(fic) -> dict:
+    """This device's rates from the library's probes, beside the published figures used as `peak`."""
+    p = fic.peak_probe()
+    return {"valu_fma_tops": p["valu_fma_ops"] / 1e12, "dot2_tops": p["dot2_ops"] / 1e12,
+            "mfma_f16_tflops": p["mfma_f16_flops"] / 1e12, "mfma_i8_tops": p["mfma_i8_ops"] / 1e12,
+            "hbm_copy_gbs": p["hbm_copy_bytes"] / 1e9,
+            "published": {"valu_fma_tops": PEAK_ALU_TOPS, "mfma_f16_tflops": PEAK_FP16_TFLOPS,
+                          "mfma_i8_tops": PEAK_INT8_TOPS, "hbm_gbs": PEAK_HBM_GBS}}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +155,7 @@ def parse():
                     help="batch64: the batch's execution form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the device peak-rate probes")
     ap.add_argument("--preset", default="calibrated", choices=["calibrated", "paper"])
     return ap.parse_args()
 
@@ -147,9 +209,10 @@ def roofline_from_profile(prof, per_label_ops, steps=None):
         return out
     ops, bound, peak, unit = spec if isinstance(spec, tuple) else (spec, "alu", PEAK_ALU_TOPS, "TOP/s")
     avg_s = total_ms / per / 1e3
-    achieved = ops / avg_s / 1e12
+    achieved = ops / avg_s / (1.0 if unit == "GB/s" else 1e12)
     out.update({"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "ops_per_step": ops})
+                "frac": achieved / peak, "traffic": None,
+                ("gbytes_per_step" if unit == "GB/s" else "ops_per_step"): ops})
     return out
 
 
@@ -160,7 +223,7 @@ def kernel_source_digest() -> str:
     """Digest of the kernel sources; traffic counters only apply to the kernels they were taken on."""
     import hashlib
     h = hashlib.sha1()
-    for name in ("fic_kernels.hip", "fic_mlp_kernels.hip"):
+    for name in ("fic_kernels.hip", "fic_mlp_kernels.hip", "fic_persist.hip"):
         with open(os.path.join(ROOT, "paper_1501_04140_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:12]
@@ -236,17 +299,18 @@ def run_quadtree(args, torch):
         nc = int(n.item())
         c[:nc].cpu()
         e2e.append((time.perf_counter() - t0) * 1e3)
-    # same steps again with HIP events around every matcher launch
+    # same steps again with HIP events around every kernel launch (the library queues a
+    # profiled encode on one stream, so each interval is that kernel's own)
     fic.profile_begin()
     for _ in range(args.steps):
         fic.encode_image(x, params, out=out)
     torch.cuda.synchronize()
     prof = fic.profile_end()
-    per_label = {}
-    for lv, B in enumerate(params.levels):
-        per_label.update(level_ops(B, int(st["matches"][lv]), len(s_sets[lv])))
-    match_prof = {k: v for k, v in prof.items() if k.startswith("match")}
-    roof = with_traffic(roofline_from_profile(match_prof, per_label, steps=args.steps), "quadtree512")
+    steps_L = [max(B // 2, 1) for B in params.levels]
+    per_label = level_specs(params.levels, s_sets, steps_L, H, W, st)
+    # the dominant kernel over every label of the step (matchers, pool steps, quadtree steps)
+    roof = with_traffic(roofline_from_profile(prof, per_label, steps=args.steps), "quadtree512")
+    by_kernel = kernel_rooflines(prof, per_label, args.steps)
 
     res = {
         "metric": "matches/s (range×domain×isometry) + 512² encode ms; PSNR Δ vs exhaustive",
@@ -267,9 +331,11 @@ def run_quadtree(args, torch):
             "accepted": [int(v) for v in st["accepted"]],
         },
         "roofline": roof,
-        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(
-            prof.items(), key=lambda kv: -kv[1][1])},
+        "roofline_by_kernel": by_kernel,
+        "profiled_step_ms": sum(v[1] for v in prof.values()) / args.steps,
     }
+    if not args.no_peaks:
+        res["peaks_measured"] = measured_peaks(fic)
     if not args.no_psnr:
         codes, n, _ = out
         rec = fic.decode(codes, int(n.item()), H, W, iters=64)
@@ -359,6 +425,13 @@ def run_batch(args, torch):
     per_label = {}
     for lv, B in enumerate(params.levels):
         per_label.update(level_ops(B, int(matches_lv[lv]), len(params.s_sets[lv])))
+        L = max(B // 2, 1)
+        for base in ("pool_score", "pool_bound", "pool_count", "pool_scatter", "pool_select", "pool_prep",
+                     "reduce_quad", "quad_compact"):
+            gb = sum(step_bytes(base, B, int(im.shape[0]), int(im.shape[1]), L, int(st["pool"][i][lv]),
+                                int(st["active"][i][lv]), int(st["accepted"][i][lv]))
+                     for i, im in enumerate(imgs)) / 1e9
+            per_label[f"{base}_b{B}"] = (gb, "hbm", PEAK_HBM_GBS, "GB/s")
     if form == fic.FORM_PERSISTENT:
         # one kernel runs every level: its MFMA levels (B >= 4, small sets) and VALU level
         # (B = 2) priced each against its own peak; peak = the rate at which the same mix of
@@ -394,8 +467,7 @@ def run_batch(args, torch):
         "roofline": roof,
         "levels_form": {"encode_ms": levels_ms, "autotune_ms": levels_tune_ms,
                         "same_codes_as_this_form": bool(same)},
-        "kernel_ms_per_step_eager": {k: v[1] / args.steps for k, v in sorted(
-            prof.items(), key=lambda kv: -kv[1][1])},
+        "roofline_by_kernel": kernel_rooflines(prof, per_label, args.steps),
         "eager_kernel_sum_ms": eager_ms,
     }
     if not args.no_cpu_baseline:

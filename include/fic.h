@@ -178,6 +178,23 @@ int fic_encode_level_ex(const uint8_t* img, int32_t H, int32_t W, int32_t pitch,
                         int32_t n_ranges, fic_match* out, int32_t* pool_out, int32_t* pool_count,
                         int32_t variant, void* stream);
 
+/*
+ * Measured peak rates of this device, the denominators of roofline
+ * fractions (not part of the paper's method). Each probe keeps one unit busy
+ * with independent chains over the whole chip, times 5 launches after 2
+ * warm-ups with HIP events on `stream`, and synchronises. *rate receives:
+ *   FIC_PEAK_VALU_FMA  32-bit multiply-add rate (fp32 FMA, unpacked), ops/s
+ *                      (2 per lane per instruction)
+ *   FIC_PEAK_DOT2      v_dot2_i32_i16 rate, ops/s (4 per lane per instruction)
+ *   FIC_PEAK_MFMA_F16  v_mfma_f32_16x16x32_f16 rate, flop/s
+ *   FIC_PEAK_MFMA_I8   v_mfma_i32_16x16x64_i8 rate, ops/s
+ *   FIC_PEAK_HBM_COPY  device-to-device copy of 1 GiB, bytes read + written
+ *                      per second (allocates and frees 2 GiB)
+ */
+enum fic_peak { FIC_PEAK_VALU_FMA = 0, FIC_PEAK_DOT2 = 1, FIC_PEAK_MFMA_F16 = 2, FIC_PEAK_MFMA_I8 = 3,
+                FIC_PEAK_HBM_COPY = 4 };
+int fic_peak_probe(int32_t what, void* stream, double* rate);
+
 /* Device scratch of fic_encode_level_noalloc, per GPU (64 MiB). */
 #define FIC_NOALLOC_SCRATCH_BYTES (64u << 20)
 

@@ -20,6 +20,7 @@
 #include "fic_kernels.hip"
 #include "fic_mlp_kernels.hip"
 #include "fic_persist.hip"
+#include "fic_peaks.hip"
 
 #define FIC_API extern "C" __attribute__((visibility("default")))
 
@@ -275,6 +276,31 @@ class ProfScope {
     hipStream_t s_;
     hipEvent_t a_ = nullptr, b_ = nullptr;
 };
+
+// Profile label of a per-level pool or quadtree step: "<step>_b<B>".
+const char* level_label(const char* step, int B) {
+    static const char* const names[][4] = {
+        {"pool_score_b2", "pool_score_b4", "pool_score_b8", "pool_score_b16"},
+        {"pool_bound_b2", "pool_bound_b4", "pool_bound_b8", "pool_bound_b16"},
+        {"pool_count_b2", "pool_count_b4", "pool_count_b8", "pool_count_b16"},
+        {"pool_scatter_b2", "pool_scatter_b4", "pool_scatter_b8", "pool_scatter_b16"},
+        {"pool_select_b2", "pool_select_b4", "pool_select_b8", "pool_select_b16"},
+        {"pool_prep_b2", "pool_prep_b4", "pool_prep_b8", "pool_prep_b16"},
+        {"reduce_quad_b2", "reduce_quad_b4", "reduce_quad_b8", "reduce_quad_b16"},
+        {"quad_compact_b2", "quad_compact_b4", "quad_compact_b8", "quad_compact_b16"}};
+    static const char* const steps[] = {"pool_score", "pool_bound", "pool_count", "pool_scatter",
+                                        "pool_select", "pool_prep", "reduce_quad", "quad_compact"};
+    const int b = B == 2 ? 0 : B == 4 ? 1 : B == 8 ? 2 : 3;
+    for (int i = 0; i < 8; ++i)
+        if (std::strcmp(step, steps[i]) == 0) return names[i][b];
+    return step;
+}
+
+// Whether kernel profiling is on (the one-image encode then queues on one stream).
+bool prof_active() {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    return g_prof.on;
+}
 
 const char* match_label(int B) {
     switch (B) {
@@ -571,7 +597,7 @@ void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hi
 template <int B, bool TAB>
 void launch_pool_prep(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, hipStream_t st) {
     const int n = (int)h.size();
-    ProfScope ps("pool_prep", st);
+    ProfScope ps(level_label("pool_prep", B), st);
     if (B == 8 && is_mfma8(h[0].var)) {
         const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * 4, kBlock); });
         kt_pool_prep_i8<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt, filtered ? 1 : 0);
@@ -639,7 +665,7 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
 // its launches), and the moments.
 template <bool TAB>
 void launch_score_step(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
-    ProfScope ps("pool_score", st);
+    ProfScope ps(level_label("pool_score", h[0].B), st);
     switch (2 * h[0].B) {
         case 4: launch_score<4, TAB>(dt, h, T, st); break;
         case 8: launch_score<8, TAB>(dt, h, T, st); break;
@@ -655,19 +681,22 @@ void launch_select_steps(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t s
     const bool direct = max_over(h, [](const Lvl& a) { return a.total; }) <= kSelDirect;
     if (!direct) {
         {
-            ProfScope ps("pool_select", st);
+            ProfScope ps(level_label("pool_bound", h[0].B), st);
             const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, a.bound_chunk); });
             kt_floor_bound<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
+        const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
         {
-            ProfScope ps("pool_compact", st);
-            const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.total, kBlock * kPoolItems); });
+            ProfScope ps(level_label("pool_count", h[0].B), st);
             kt_pool_count<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
+        }
+        {
+            ProfScope ps(level_label("pool_scatter", h[0].B), st);
             kt_pool_scatter<TAB><<<dim3(gx, 1, n), kBlock, 0, st>>>(h[0], dt);
         }
     }
     {
-        ProfScope ps("pool_select", st);
+        ProfScope ps(level_label("pool_select", h[0].B), st);
         kt_floor_select<TAB><<<dim3(1, 1, n), 1024, 0, st>>>(h[0], dt, direct ? 1 : 0);
     }
     if (std::any_of(h.begin(), h.end(), [](const Lvl& a) { return a.pools_out != nullptr; })) {
@@ -734,11 +763,11 @@ int launch_quad_t(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
     const int gr = max_over(h, [](const Lvl& a) { return cdiv(a.max_act, kRqRanges); });
     const int gx = max_over(h, [](const Lvl& a) { return cdiv(a.max_act, kBlock * kQuadItems); });
     {
-        ProfScope ps("reduce_quad", st);
+        ProfScope ps(level_label("reduce_quad", h[0].B), st);
         kt_reduce_quad<TAB><<<dim3(gr, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
     }
     {
-        ProfScope ps("quad_compact", st);
+        ProfScope ps(level_label("quad_compact", h[0].B), st);
         kt_quad_scatter<TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
     }
     LAUNCH_CHECK();
@@ -874,8 +903,9 @@ int launch_quadtree(const Lvl* dt, const std::vector<Lvl>& t, int n_images, cons
                     bool filtered, hipStream_t st, const std::vector<Group>* groups = nullptr,
                     Workspace* fork = nullptr) {
     const int nl = (int)t.size() / n_images;
+    // (while profiling, everything stays on st, so that each kernel's event interval is its own)
     if (fork && dt == nullptr && n_images == 1 && nl > 1 && nl <= kLevels && fork->dlv &&
-        fork->nlv == nl)
+        fork->nlv == nl && !prof_active())
         return launch_quadtree_one(t, T, filtered, st, *fork);
     const std::vector<Group> all{{0, n_images}};
     const std::vector<Group>& gs = groups ? *groups : all;
@@ -1366,6 +1396,71 @@ FIC_API int fic_select_s(const uint64_t* hist, int32_t n_levels, float second_fr
         s_k[2 * l + 1] = (int8_t)(two ? std::max(a, b) : 0);
         n_s[l] = two ? 2 : 1;
     }
+    return FIC_OK;
+}
+
+FIC_API int fic_peak_probe(int32_t what, void* stream, double* rate) {
+    if (!rate) return fail(FIC_EINVAL, "rate is NULL");
+    if (what < FIC_PEAK_VALU_FMA || what > FIC_PEAK_HBM_COPY) return fail(FIC_EINVAL, "probe %d unknown", what);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    void* out = nullptr;
+    void* src = nullptr;
+    void* dst = nullptr;
+    const size_t copy_bytes = (size_t)1 << 30;
+    if (hipMalloc(&out, 256) != hipSuccess) return fail(FIC_ENOMEM, "hipMalloc failed");
+    if (what == FIC_PEAK_HBM_COPY) {
+        if (hipMalloc(&src, copy_bytes) != hipSuccess || hipMalloc(&dst, copy_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            if (src) (void)hipFree(src);
+            (void)hipFree(out);
+            return fail(FIC_ENOMEM, "hipMalloc of the copy buffers failed");
+        }
+    }
+    const int grid = cus * 8;
+    auto launch = [&]() {
+        switch (what) {
+            case FIC_PEAK_VALU_FMA: k_peak_fma<<<grid, 256, 0, st>>>(1.0f, static_cast<float*>(out)); break;
+            case FIC_PEAK_DOT2: k_peak_dot2<<<grid, 256, 0, st>>>(3, static_cast<int*>(out)); break;
+            case FIC_PEAK_MFMA_F16: k_peak_mfma_f16<<<grid, 256, 0, st>>>(0.5f, static_cast<float*>(out)); break;
+            case FIC_PEAK_MFMA_I8: k_peak_mfma_i8<<<grid, 256, 0, st>>>(3, static_cast<int*>(out)); break;
+            default:
+                k_peak_copy<<<cus * 16, 256, 0, st>>>(static_cast<const uint4*>(src), static_cast<uint4*>(dst),
+                                                      copy_bytes / 16);
+        }
+    };
+    const double lanes = (double)grid * 256, waves = (double)grid * 4;
+    const double work = what == FIC_PEAK_VALU_FMA ? lanes * 8 * kPeakIters * 2
+                        : what == FIC_PEAK_DOT2 ? lanes * 8 * kPeakIters * 4
+                        : what == FIC_PEAK_MFMA_F16 ? waves * kPeakIters * (2.0 * 16 * 16 * 32)
+                        : what == FIC_PEAK_MFMA_I8 ? waves * kPeakIters * (2.0 * 16 * 16 * 64)
+                                                   : 2.0 * (double)copy_bytes;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int reps = 5;
+    if (e == hipSuccess) {
+        launch();  // warm-up
+        launch();
+        e = hipEventRecord(e0, st);
+    }
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        launch();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (src) (void)hipFree(src);
+    if (dst) (void)hipFree(dst);
+    if (e != hipSuccess) return fail(FIC_EDEVICE, "peak probe: %s", hipGetErrorString(e));
+    *rate = work * reps / (ms * 1e-3);
     return FIC_OK;
 }
 

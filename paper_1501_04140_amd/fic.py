@@ -113,6 +113,7 @@ def load():
     lib.fic_batch_autotune.argtypes = [vp, vp, i32, ctypes.c_char_p, ctypes.POINTER(f32)]
     lib.fic_batch_destroy.argtypes = [vp]
     lib.fic_batch_set_form.argtypes = [vp, i32, vp, i32]
+    lib.fic_peak_probe.argtypes = [i32, vp, ctypes.POINTER(ctypes.c_double)]
     lib.fic_batch_get_form.argtypes = [vp, vp, vp, vp]
     lib.fic_mlp_create.argtypes = [vp, f32, ctypes.POINTER(vp)]
     lib.fic_mlp_destroy.argtypes = [vp]
@@ -139,7 +140,7 @@ def load():
     for name in ("fic_encode_level", "fic_encode_level_ex", "fic_encode_level_noalloc", "fic_encode_image", "fic_decode", "fic_sse",
                  "fic_calibrate_s", "fic_version", "fic_profile_begin", "fic_profile_end",
                  "fic_batch_create", "fic_batch_run", "fic_batch_run_eager", "fic_batch_set_chunks", "fic_batch_get_chunks",
-                 "fic_batch_autotune", "fic_batch_destroy", "fic_batch_set_form", "fic_batch_get_form", "fic_mlp_create", "fic_mlp_destroy",
+                 "fic_batch_autotune", "fic_batch_destroy", "fic_batch_set_form", "fic_batch_get_form", "fic_peak_probe", "fic_mlp_create", "fic_mlp_destroy",
                  "fic_mlp_get_params", "fic_mlp_embed", "fic_mlp_loss_grad", "fic_mlp_adam",
                  "fic_mlp_train_step", "fic_topk_similar", "fic_encode_level_learned",
                  "fic_level_codes", "fic_encode_image_ex", "fic_pack_stream", "fic_unpack_stream",
@@ -229,6 +230,19 @@ def encode_level_noalloc(img, B: int, L: int, s_k=PLAIN_K, entropy_mode: int = 0
                                       _stream(stream))
     _check(rc)
     return out[:n]
+
+
+PEAK_PROBES = {"valu_fma_ops": 0, "dot2_ops": 1, "mfma_f16_flops": 2, "mfma_i8_ops": 3, "hbm_copy_bytes": 4}
+
+
+def peak_probe(stream=None) -> dict:
+    """fic_peak_probe for every probe: measured rates per second of this device."""
+    out = {}
+    for name, what in PEAK_PROBES.items():
+        v = ctypes.c_double(0.0)
+        _check(load().fic_peak_probe(what, _stream(stream), ctypes.byref(v)))
+        out[name] = v.value
+    return out
 
 
 def code_capacity(H: int, W: int, levels=LEVELS) -> int:
