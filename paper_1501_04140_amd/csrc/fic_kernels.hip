@@ -1046,6 +1046,7 @@ struct MatchSmem {
     uint32_t sHL[TN * 2 * NW];
     uint32_t sS[kFast ? 1 : TN];
     int64_t sA[MODE == kModeSmall ? 1 : TN];
+    float sAf[MODE == kModeSmall ? 1 : TN];  // A' in FP32, for the screen
     typename Tl::GT sKA[NKA][kFast ? 1 : TN];
     int4 sRec[kFast ? TN : 1];
     int32_t sE1[kFast && B == 2 ? TN : 1];
@@ -1078,6 +1079,7 @@ __device__ __forceinline__ void k_match_body(MatchSmem<B, MODE, TN_>& sm, int bx
     auto& sHL = sm.sHL;
     auto& sS = sm.sS;
     auto& sA = sm.sA;
+    auto& sAf = sm.sAf;
     auto& sKA = sm.sKA;
     auto& sRec = sm.sRec;
     auto& sE1 = sm.sE1;
@@ -1152,6 +1154,12 @@ __device__ __forceinline__ void k_match_body(MatchSmem<B, MODE, TN_>& sm, int bx
     // other modes
     int64_t bestF = INT64_MAX;
     int bestP = -1, bestS = 0;
+    // screen: over real k, F >= -1600 B'^2 / A', so an element can go below a best
+    // F_b <= 0 only if B' > 0 and 1600 B'^2 > -F_b A'. thrF = -F_b / 1600 shrunk by
+    // 2^-18 (below the FP32 roundings of B'^2, A' and the product), so no element that
+    // could win is skipped; while F_b > 0 (no candidate yet, or a set without 0)
+    // every element goes to the exact step.
+    float thrF = 0.0f;
 
     for (int base = lo; base < hi; base += TN) {
         const int cnt = min(TN, hi - base);
@@ -1189,6 +1197,7 @@ __device__ __forceinline__ void k_match_body(MatchSmem<B, MODE, TN_>& sm, int bx
                     for (int u = 0; u < kSmallMax; ++u) sKA[u][i] = (GT)(u < ks.n ? ks.k[u] : 0) * (GT)a;
                 } else {
                     sA[i] = a;
+                    sAf[i] = (float)a;
                 }
             }
         }
@@ -1285,14 +1294,18 @@ __device__ __forceinline__ void k_match_body(MatchSmem<B, MODE, TN_>& sm, int bx
                     }
                 }
             } else {
-                int64_t F;
-                int sidx;
-                if (MODE == kModeGrid) best_contrast_grid((int64_t)Bp, sA[d], ks.k0, ks.k1, F, sidx);
-                else best_contrast_list((int64_t)Bp, sA[d], ks, F, sidx);
-                if (F < bestF) {
-                    bestF = F;
-                    bestP = base + d;
-                    bestS = sidx;
+                const float bf = (float)Bp;
+                if (bestF > 0 || (Bp > 0 && bf * bf >= thrF * sAf[d])) {
+                    int64_t F;
+                    int sidx;
+                    if (MODE == kModeGrid) best_contrast_grid((int64_t)Bp, sA[d], ks.k0, ks.k1, F, sidx);
+                    else best_contrast_list((int64_t)Bp, sA[d], ks, F, sidx);
+                    if (F < bestF) {
+                        bestF = F;
+                        bestP = base + d;
+                        bestS = sidx;
+                        thrF = bestF > 0 ? 0.0f : (float)(-bestF) * (1.0f / 1600.0f) * (1.0f - 1.0f / 262144.0f);
+                    }
                 }
             }
         }

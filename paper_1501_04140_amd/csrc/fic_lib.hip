@@ -570,7 +570,9 @@ int max_over(const std::vector<Lvl>& h, F f) {
 }
 
 // Domains at or above which the entropy keys come from cell histograms.
-constexpr int kScoreCellsMin = 32768;
+// (every such grid: at 512^2 the per-window kernel took 13 us at levels 0 and 1, where the
+// cell kernel scores level 3's 259081 domains in 5 us)
+constexpr int kScoreCellsMin = 0;
 
 template <int SIDE, bool TAB>
 void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
