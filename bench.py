@@ -156,6 +156,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the device peak-rate probes")
+    ap.add_argument("--no-also", action="store_true",
+                    help="quadtree512: skip the short precision1024 and batch64 runs")
     ap.add_argument("--preset", default="calibrated", choices=["calibrated", "paper"])
     return ap.parse_args()
 
@@ -838,7 +840,33 @@ def main():
         "vs_baseline": None, "dtype": res.pop("dtype", "u8 dot4 -> i32, i64 exact"), "data": "synthetic",
     }
     line.update(res)
+    if args.workload == "quadtree512" and not args.no_also:
+        line["also"] = other_workloads(args, torch)
     print(json.dumps(line), flush=True)
+
+
+def other_workloads(args, torch) -> dict:
+    """Short runs of the precision and batched workloads (no CPU baselines), so that one
+    default run also times them: their own --workload runs give the full lines."""
+    import copy
+    sub = copy.copy(args)
+    sub.steps, sub.warmup, sub.no_cpu_baseline = min(args.steps, 5), 1, True
+    out = {}
+    p = run_level(sub, torch, "precision1024")
+    out["precision1024"] = {
+        "workload": p["config"]["workload"], "fp16_mfma_ms": p["encode_ms"], "matches_per_s": p["value"],
+        "fp16_roofline": {k: p["roofline"].get(k) for k in ("kernel", "achieved", "peak", "unit", "frac", "traffic")},
+        "int8_mfma_ms": p["int8_mfma_form"]["ms"],
+        "int8_roofline": {k: p["int8_mfma_form"]["roofline"].get(k)
+                          for k in ("kernel", "achieved", "peak", "unit", "frac", "traffic")},
+        "fp32_comparator": p["fp32_comparator"]}
+    b = run_batch(sub, torch)
+    out["batch64"] = {
+        "workload": b["config"]["workload"], "form": b["config"]["form"], "ms": b["encode_ms"],
+        "matches_per_s": b["value"], "images_per_s": b["images_per_s"], "tiles": b["config"]["tiles"],
+        "workgroups": b["config"]["workgroups"], "levels_form": b["levels_form"],
+        "roofline": {k: b["roofline"].get(k) for k in ("kernel", "achieved", "peak", "unit", "frac")}}
+    return out
 
 
 if __name__ == "__main__":

@@ -92,7 +92,7 @@ struct Lvl {
     int8_t* dh;
     int8_t* dl;
     float* gd;
-    float* af;
+    float4* cq;  // int8 / FP16 MFMA matchers: per-domain screen constants
     uint32_t* flags;    // optional: split flags, one bit per active range, levels in order
     int32_t* pools_out; // optional: this level's pool list
     int32_t* n_out;     // optional, last level: the number of codes, written by the compaction

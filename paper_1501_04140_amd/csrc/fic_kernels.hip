@@ -1736,10 +1736,10 @@ __device__ __forceinline__ void k_range_prep_m8_body(const uint8_t* __restrict__
 }
 
 // Columns for the MFMA matchers: h and l rows of each pool domain (int8), or
-// (F16) the 64 sums d' in FP16 (exact: integers below 2^11) at Dh, 128 bytes
-// per domain; and in FP32 G = 40 / A' (0 for a constant domain) and
-// Q = sqrt(A') (1 - 2^-18), rounded below sqrt(A') for the screen. Four lanes
-// share a domain, 16 decimated values each.
+// (F16) the 64 sums d' in FP16 (exact: integers below 2^11) at Dh and their
+// normalized form at Dl, 128 bytes per domain each; in FP32 G = 40 / A' (0 for
+// a constant domain); and the int8 screen's per-domain constants (below). Four
+// lanes share a domain, 16 decimated values each.
 template <bool F16>
 __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ img, int pitch,
                                                          int L, int gx, const int32_t* __restrict__ pool,
@@ -1747,7 +1747,7 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
                                                          int8_t* __restrict__ Dh, int8_t* __restrict__ Dl,
                                                          uint32_t* __restrict__ Sd, int64_t* __restrict__ Ad,
                                                          int32_t* __restrict__ Jd, float* __restrict__ Gd,
-                                                         float* __restrict__ Af) {
+                                                         float4* __restrict__ Cq) {
     constexpr int B = 8, n = 64, TPD = 4, PER = 16;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (identity_total >= 0 && g == 0) {
@@ -1760,6 +1760,7 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
     uint32_t s = 0;
     uint64_t q = 0;
     int j = 0;
+    int dv[PER];  // F16: the lane's d', normalized once the domain's moments are known
     if (ok) {
         j = identity_total >= 0 ? p : pool[p];
         const int y = (j / gx) * L, x = (j % gx) * L;
@@ -1773,6 +1774,7 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
                 const int m = sub * PER + 4 * w + b, i = m / B, c = m % B;
                 const uint8_t* px = img + (int64_t)(y + 2 * i) * pitch + x + 2 * c;
                 const uint32_t d = (uint32_t)px[0] + px[1] + px[pitch] + px[pitch + 1];
+                dv[4 * w + b] = (int)d;
                 s += d;
                 q += (uint64_t)d * d;
                 hw |= (d >> 7) << (8 * b);
@@ -1793,13 +1795,32 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
         s += __shfl_xor(s, m, 64);
         q += __shfl_xor(q, m, 64);
     }
+    if constexpr (F16) {
+        // the screen's columns d^_i = (64 d'_i - S) / Q in FP16 (Q = sqrt(A')
+        // rounded below; 0 for a constant domain)
+        if (ok) {
+            const int64_t A = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
+            const float inv = A > 0 ? 1.0f / (sqrtf((float)A) * kM8Shrink) : 0.0f;
+            uint32_t* nd = reinterpret_cast<uint32_t*>(Dl + ((int64_t)p * n + sub * PER) * 2);
+#pragma unroll
+            for (int w = 0; w < PER / 2; ++w) {
+                const _Float16 h0 = (_Float16)((float)(64 * dv[2 * w] - (int)s) * inv);
+                const _Float16 h1 = (_Float16)((float)(64 * dv[2 * w + 1] - (int)s) * inv);
+                nd[w] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+            }
+        }
+    }
     if (ok && sub == 0) {
         const int64_t A = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
         Sd[p] = s;
         Ad[p] = A;
         Jd[p] = j;
         Gd[p] = A > 0 ? 40.0f / (float)A : 0.0f;
-        Af[p] = sqrtf((float)A) * kM8Shrink;
+        // screen constants: Q / 64 with Q = sqrt(A') (1 - 2^-18) rounded below
+        // sqrt(A'), S / 64, and the rounding margin (2^100 for a constant domain)
+        if constexpr (!F16)
+            Cq[p] = make_float4(sqrtf((float)A) * kM8Shrink * (1.0f / 64.0f), (float)s * (1.0f / 64.0f),
+                                A > 0 ? -8.0f : 0x1p100f, 0.0f);
     }
 }
 
@@ -1823,29 +1844,35 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
 }
 
 // grid: x = workgroups of m8_rows rows, y = pool chunks. The contrast set is
-// k = 0..k1. Each wavefront keeps kM8WaveRows rows; each lane holds 4 rows x 1 column
-// of every 16x16 output tile.
+// k = 0..k1. Each wavefront keeps kM8WaveRows rows; each lane holds 4 rows x 1
+// column of every 16x16 output tile: lane group g = lane / 16 holds rows
+// 4g..4g+3 of a tile, so groups g and g ^ 1 hold the 8 rows of one range.
 // Screen: for any k, F = k^2 A' - 80 k B' is at least the continuous minimum
-// -1600 B'^2 / A', so an element can match or beat a row's best F_b <= 0 only
-// if B' >= s_b sqrt(A'), s_b = sqrt(-F_b / 1600). A lane takes the smallest
-// s_b of its 4 rows (they share the column) and a threshold T rounded below
-// s_b sqrt(A') (both factors shrunk by kM8Shrink, truncated to an integer, at
-// least 1 since F < 0 needs B' > 0); with B' = 64 X + toff this is one integer
-// bound U on the MFMA output X: per element, one compare. The bound is not
-// strict, so ties stay candidates.
+// -1600 B'^2 / A', so an element can match or beat a best F_b <= 0 only if
+// B' >= s_b sqrt(A'), s_b = sqrt(-F_b / 1600). A range's code is the minimum
+// over its 8 rows, so every row is screened against the smallest F_b among its
+// range's rows (the largest s_b). The int8 form bounds its MFMA output X
+// (B' = 64 X - (sum r') S) in FP32 by
+//   U~ = s_b (Q / 64) + (sum r') (S / 64) - 8,   Q = sqrt(A') (1 - 2^-18),
+// whose roundings stay below 2.5, so U~ <= U - 5.5 for the exact
+// U = (s_b sqrt(A') + (sum r') S) / 64, and X >= U~ keeps every element with
+// X >= U (X is an integer below 2^24, exact in FP32). The bound is not strict,
+// so ties stay candidates. A constant domain (A' = 0, so B' = 0 and F = 0:
+// never an improvement) has 2^100 in place of -8.
+// Per 16-column tile a lane compares the largest of its 4 elements of each row
+// tile, and the wavefront takes the tile's slow path only when some lane
+// passes: there each element is compared, and candidates go to a
+// per-wavefront queue in LDS, decided exactly in int64, one per lane (the FP32
+// k corrected by one step).
 // F = 0 never improves a row: its best starts at (F = 0, the chunk's first
 // position, k = 0) and positions only grow. So a row of a constant range
 // (C = 0, hence B' = 0 and F >= 0 everywhere) and a padded row start from the
 // mark kM8Excl in place of F = 0 (s_b near 9300: no element reaches its bound)
-// and report F = 0 at the end; and (FP16, whose rounding slack would let B' = 0
-// pass) a constant domain (A' = 0, hence B' = 0) never queues either.
-// Candidates go to a per-wavefront queue in LDS and are decided exactly in
-// int64 64 at a time, one per lane (the FP32 k corrected by one step). Each
-// row's best is one packed word (F + 2^37) << 26 | position << 4 | k, which
-// orders as (F, key) does within a row (0 >= F >= -1600 C > -2^37 for n = 64,
-// positions below kM8MaxPool); lanes lower it with an LDS atomic minimum, and
-// every lane of a row reads its bound back from it.
-constexpr int kM8Queue = 64 + 4 * 64;  // a flush at 64 entries, then up to one tile's 256
+// and report F = 0 at the end. Each row's best is one packed word
+// (F + 2^37) << 26 | position << 4 | k, which orders as (F, key) does within a
+// row (0 >= F >= -1600 C > -2^37 for n = 64, positions below kM8MaxPool); lanes
+// lower it with an LDS atomic minimum.
+constexpr int kM8Queue = 64 + 4 * 64;  // a flush at 16 entries, then up to one tile's 256
 constexpr int kM8MaxPool = 1 << 22;    // pool positions the packed best can hold
 // F of a row that never queues (below every real F >= -1600 C > -2^37)
 constexpr int64_t kM8Excl = -(1ll << 37) + 1;
@@ -1863,8 +1890,33 @@ __device__ inline float m8_sigma(uint64_t v) {
     return F < 0 ? __builtin_amdgcn_sqrtf((float)(-F) * (1.0f / 1600.0f)) * kM8Shrink : 0.0f;
 }
 
+// The largest s_b over the 8 rows of the range that lane group g holds in row
+// tile rt (rows 16 rt + 8 (g / 2) + 0..7 of the wavefront).
+__device__ inline float m8_range_sigma(const uint64_t* best, int rt, int g) {
+    const uint64_t* bb = best + 16 * rt + 8 * (g >> 1);
+    uint64_t m = bb[0];
+#pragma unroll
+    for (int e = 1; e < 8; ++e) m = bb[e] < m ? bb[e] : m;  // smallest packed word: smallest F
+    return m8_sigma(m);
+}
+
+// The exact decision of one candidate (row, pool position) given X = sum r' d'.
+__device__ inline void m8_decide(int row, int pos, int X, const int32_t* nsr, uint64_t* best,
+                                 const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
+                                 const float* __restrict__ Gd, int k1) {
+    const int64_t Ap = Ad[pos];
+    const int bi = (X << 6) + nsr[row] * (int)Sd[pos];  // B' = 64 X - sum r' S, exact
+    const int64_t Bp = bi, b80 = 80 * Bp;
+    int k = (int)__builtin_amdgcn_fmed3f(rintf((float)bi * Gd[pos]), 0.0f, (float)k1);
+    if (Ap <= 0) k = 0;
+    else if (k > 0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
+    else if (k < k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
+    const int64_t F = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
+    if (F <= 0) atomicMin(reinterpret_cast<unsigned long long*>(best + row), (unsigned long long)m8_pack(F, pos, k));
+}
+
 // Exact decision of the wavefront's queued candidates (entry: row | position
-// << kM8RowBits, X), one per lane, then the lane's row bounds re-read.
+// << kM8RowBits, X), one per lane.
 __device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint64_t* best,
                                 const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
                                 const float* __restrict__ Gd, int k1, int lane) {
@@ -1873,57 +1925,65 @@ __device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint6
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     for (int i = lane; i < n; i += 64) {
         const uint2 en = q[i];
-        const int row = (int)(en.x & ((1u << kM8RowBits) - 1u)), pos = (int)(en.x >> kM8RowBits), X = (int)en.y;
-        const int64_t Ap = Ad[pos];
-        const int bi = (X << 6) + nsr[row] * (int)Sd[pos];  // B' = 64 X - sum r' S, exact
-        const int64_t Bp = bi, b80 = 80 * Bp;
-        int k = (int)__builtin_amdgcn_fmed3f(rintf((float)bi * Gd[pos]), 0.0f, (float)k1);
-        if (Ap <= 0) k = 0;
-        else if (k > 0 && (int64_t)(2 * k - 1) * Ap >= b80) --k;
-        else if (k < k1 && (int64_t)(2 * k + 1) * Ap < b80) ++k;
-        const int64_t F = (int64_t)(k * k) * Ap - (int64_t)(80 * k) * Bp;
-        if (F <= 0) atomicMin(reinterpret_cast<unsigned long long*>(best + row),
-                              (unsigned long long)m8_pack(F, pos, k));
+        m8_decide((int)(en.x & ((1u << kM8RowBits) - 1u)), (int)(en.x >> kM8RowBits), (int)en.y, nsr, best, Ad, Sd,
+                  Gd, k1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// F16: the same search with X from FP16 MFMAs (v_mfma_f32_16x16x32_f16, two
-// K halves): r' and d' are exact in FP16 and every partial sum of X is an
-// integer below 64 * 128 * 1020 < 2^24, so the FP32 accumulator holds X
-// exactly, with no hi/lo split. With toff = -sum r' S the screen bound
-// (T - toff) / 64 becomes, in FP32,
-//   U~ = s_b (Q / 64) + (sum r') (S / 64) - 8,
-// at most U - 5.5 after its roundings (below 2.5 in all), so X >= U~ keeps
-// every element with X >= U; a padded column adds 2^100 instead of -8.
+// int8: two independent MFMAs (v_mfma_i32_16x16x64_i8) give the h and l sums
+// of a tile, X = 128 Xh + Xl, exact in int32.
+// A pool stage (kM8Cols domains) is copied from global memory straight into
+// LDS (global_load_lds, 16 bytes a lane, no registers on the way) while the
+// previous stage is matched: 8 chunks of 16 bytes per domain (u < 4 the h
+// values 16u.., u >= 4 the l values 16(u - 4)..; the FP16 matcher below: the
+// normalized values 8u..8u+7), chunk u of column c at c * 8 + (u ^ ((c >> 1) &
+// 7)), so that 16 consecutive columns read one chunk each from distinct
+// banks; beside them the int8 screen's column constants (Q / 64, S / 64, -8 or
+// 2^100).
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <bool F16>
-__device__ __forceinline__ void k_match_mfma8_body(
+__device__ inline int m8_chunk(int c, int u) { return c * 8 + (u ^ ((c >> 1) & 7)); }
+
+// One copy of 16 bytes a lane from global memory into LDS: lane i's 16 bytes
+// at gaddr land at lds + 16 i (lds the same in every lane, passed in m0). The
+// compiler's builtin for this instruction makes every later LDS read of the
+// kernel wait for the copy to land, which would stall each stage on its
+// successor's copy; issued here, nothing waits for it but the explicit
+// vmcnt(0) before the barrier that publishes the stage. It has no register
+// results (its only outputs are in LDS), and its address registers are read
+// when it issues. It writes m0, a register the compiler reserves and does not
+// restore after inline assembly: the kernels that use it must not use m0
+// otherwise (none of their other instructions reads it: a test checks their
+// assembly).
+__device__ __forceinline__ void m8_copy_to_lds(const void* gaddr,
+                                               const void __attribute__((address_space(3)))* lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(gaddr), "s"((uint32_t)(uintptr_t)lds)
+                 : "memory");
+}
+
+__device__ __forceinline__ void k_match_i8_body(
     const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int64_t* __restrict__ CR,
     const int32_t* act_count, const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
-    const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float* __restrict__ Qd,
+    const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float4* __restrict__ Cq,
     const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
     Partial* __restrict__ part, int cg) {
-    constexpr int kM8RowTiles = m8_row_tiles(F16), kM8WaveRows = 16 * kM8RowTiles;
-    static_assert(kM8WaveRows <= (1 << kM8RowBits), "row index of a queue entry");
-    // Two buffers of the pool stage (the next stage is loaded while this one is
-    // matched). int8: column c, K-group g at [c * 4 + g]; FP16: 16-byte chunk u
-    // of column c at [c * 9 + u] (one chunk of padding per column against bank
-    // conflicts)
-    __shared__ v4i sH[2][F16 ? kM8Cols * 9 : kM8Cols * 4];
-    __shared__ v4i sL[2][F16 ? 1 : kM8Cols * 4];
-    __shared__ float sQ[2][kM8Cols], sSf[2][F16 ? kM8Cols : 1], sBias[2][F16 ? kM8Cols : 1];
-    __shared__ int32_t sS[2][kM8Cols], sTm[2][kM8Cols];
+    constexpr int RT = m8_row_tiles(false), WR = 16 * RT;
+    static_assert(WR <= (1 << kM8RowBits), "row index of a queue entry");
+    static_assert(kM8Waves * 2 * 64 == kM8Cols * 8, "a stage is two 16-byte chunks per lane");
+    __shared__ v4i sD[2][kM8Cols * 8];
+    __shared__ float4 sC[2][kM8Cols];
     __shared__ uint2 sQueue[kM8Waves][kM8Queue];
-    __shared__ uint64_t sBest[kM8Waves][kM8WaveRows];
-    __shared__ int32_t sNsr[kM8Waves][kM8WaveRows];
+    __shared__ uint64_t sBest[kM8Waves][WR];
+    __shared__ int32_t sNsr[kM8Waves][WR];
 
     const int nrows = 8 * *act_count;
-    const int row_blk = blockIdx.x * m8_rows(F16);
+    const int row_blk = blockIdx.x * m8_rows(false);
     if (row_blk >= nrows) return;
     const int P = ctrl->pool_count;
     const int nca = active_chunks(P, cg, n_chunks);
@@ -1931,33 +1991,25 @@ __device__ __forceinline__ void k_match_mfma8_body(
     if (c >= nca) return;
     const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
-    const int wrow0 = row_blk + wave * 16 * kM8RowTiles;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    const int wrow0 = row_blk + wave * WR;
     uint2* queue = sQueue[wave];
     uint64_t* best = sBest[wave];
     int32_t* nsr = sNsr[wave];
 
-    v4i a[kM8RowTiles];
-    v8h af[kM8RowTiles][2];  // F16: the lane's 8 values of each K half
-    int nsrp[kM8RowTiles];  // -sum r' of the lane's output range, per row tile
-    float sigm[kM8RowTiles];
+    v4i a[RT];
+    float tr[RT];   // sum r' of the lane's output range, in FP32
+    float sig[RT];  // s_b of the lane's range, per row tile
 #pragma unroll
-    for (int rt = 0; rt < kM8RowTiles; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
         const int arow = wrow0 + 16 * rt + c16;
         const v4i z = {0, 0, 0, 0};
-        if constexpr (F16) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-                af[rt][h] = __builtin_bit_cast(
-                    v8h, arow < nrows ? *reinterpret_cast<const v4i*>(Ar + ((int64_t)arow * 64 + 32 * h + 8 * g) * 2)
-                                      : z);
-        } else {
-            a[rt] = arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 16 * g) : z;
-        }
+        a[rt] = arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 16 * g) : z;
         const int orow = wrow0 + 16 * rt + 4 * g;
-        nsrp[rt] = orow < nrows ? -SRp[orow >> 3] : 0;
+        tr[rt] = orow < nrows ? (float)SRp[orow >> 3] : 0.0f;
     }
-    for (int i = lane; i < kM8WaveRows; i += 64) {
+    for (int i = lane; i < WR; i += 64) {
         // k = 0 gives F = 0 for every domain; its smallest key is the chunk's first domain
         const int r = wrow0 + i;
         const bool live = r < nrows && CR[r >> 3] != 0;
@@ -1967,164 +2019,462 @@ __device__ __forceinline__ void k_match_mfma8_body(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // X of 16 columns for every row tile from the lane's two 16-byte chunks of
+    // its column (h and l values 16g..)
+    auto tile = [&](const v4i q0, const v4i q1, v4i (&acc)[RT]) {
+        const v4i z = {0, 0, 0, 0};
+        v4i xh[RT], xl[RT];
 #pragma unroll
-    for (int rt = 0; rt < kM8RowTiles; ++rt) {
-        const uint64_t* bb = best + 16 * rt + 4 * g;
-        sigm[rt] = fminf(fminf(m8_sigma(bb[0]), m8_sigma(bb[1])), fminf(m8_sigma(bb[2]), m8_sigma(bb[3])));
+        for (int rt = 0; rt < RT; ++rt) {
+            xh[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], q0, z, 0, 0, 0);
+            xl[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], q1, z, 0, 0, 0);
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[rt][e] = (xh[rt][e] << 7) + xl[rt][e];
+    };
+    // a first bound before the search: 4 tiles of 16 domains spread over the
+    // chunk, decided exactly (without it every chunk would open with half of
+    // its first elements queued)
+    if (lo < hi) {
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            const int pos = lo + (int)((int64_t)(hi - lo) * (16 * st + c16) / 64);
+            v4i acc[RT];
+            tile(*reinterpret_cast<const v4i*>(Dh + (int64_t)pos * 64 + 16 * g),
+                 *reinterpret_cast<const v4i*>(Dl + (int64_t)pos * 64 + 16 * g), acc);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                if (wrow0 + 16 * rt + 4 * g < nrows) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) m8_decide(16 * rt + 4 * g + e, pos, acc[rt][e], nsr, best, Ad, Sd, Gd, k1);
+                }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
+    auto set_bounds = [&] {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) sig[rt] = m8_range_sigma(best, rt, g);
+    };
+    set_bounds();
     int qn = 0;  // queued candidates (the same in every lane)
 
-    // a thread's share of one stage: two 16-byte chunks (FP16: column tid / 8 and
-    // tid / 8 + 32, chunk tid % 8; int8: h and l chunk tid of 256) and, in the
-    // first 64 threads, its column's Q and S
-    v4i ld0, ld1;
-    float ldq = 0.0f;
-    int lds_ = 0;
-    auto load_stage = [&](int b0, int n) {
-        const v4i zz = {0, 0, 0, 0};
-        const int t = threadIdx.x;
-        if constexpr (F16) {
-            const int c0 = t >> 3, c1 = c0 + 32, u = t & 7;
-            ld0 = c0 < n ? *reinterpret_cast<const v4i*>(Dh + ((int64_t)(b0 + c0) * 64 + 8 * u) * 2) : zz;
-            ld1 = c1 < n ? *reinterpret_cast<const v4i*>(Dh + ((int64_t)(b0 + c1) * 64 + 8 * u) * 2) : zz;
-        } else {
-            const int col = t >> 2, gg = t & 3;
-            ld0 = col < n ? *reinterpret_cast<const v4i*>(Dh + (int64_t)(b0 + col) * 64 + 16 * gg) : zz;
-            ld1 = col < n ? *reinterpret_cast<const v4i*>(Dl + (int64_t)(b0 + col) * 64 + 16 * gg) : zz;
+    // this wavefront's share of a stage: chunks (2 wave + l) * 64 + lane, l = 0, 1
+    // (columns past the chunk's end copy its last domain and are never queued);
+    // wavefront 0 also copies the 64 columns' screen constants
+    auto stage_dma = [&](v4i* dD, float4* dC, int b0, int n) {
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const int i = (2 * wave + l) * 64 + lane, col = i >> 3, u = (i & 7) ^ ((col >> 1) & 7);
+            const int64_t pos = b0 + min(col, n - 1);
+            const int8_t* src = u < 4 ? Dh + pos * 64 + 16 * u : Dl + pos * 64 + 16 * (u - 4);
+            m8_copy_to_lds(src, (const __attribute__((address_space(3))) void*)(dD + (2 * wave + l) * 64));
         }
-        if (t < kM8Cols) {
-            ldq = t < n ? Qd[b0 + t] : 0.0f;
-            lds_ = t < n ? (int32_t)Sd[b0 + t] : 0;
-        }
+        if (wave == 0)
+            m8_copy_to_lds(Cq + b0 + min(lane, n - 1), (const __attribute__((address_space(3))) void*)dC);
     };
-    auto store_stage = [&](int buf, int n) {
-        const int t = threadIdx.x;
-        if constexpr (F16) {
-            const int c0 = t >> 3, u = t & 7;
-            sH[buf][c0 * 9 + u] = ld0;
-            sH[buf][(c0 + 32) * 9 + u] = ld1;
-        } else {
-            sH[buf][t] = ld0;
-            sL[buf][t] = ld1;
-        }
-        if (t < kM8Cols) {
-            // a padded column gets the bound 2^30 > |B'| (2^100 in FP32, as does a
-            // constant domain): never a candidate
-            const bool ok = t < n;
-            sQ[buf][t] = F16 ? ldq * (1.0f / 64.0f) : ldq;
-            sTm[buf][t] = ok ? 1 : (1 << 30);
-            sS[buf][t] = lds_;
-            if constexpr (F16) {
-                sSf[buf][t] = (float)lds_ * (1.0f / 64.0f);
-                sBias[buf][t] = ok && ldq > 0.0f ? -8.0f : 0x1p100f;  // Q > 0 iff A' > 0
-            }
-        }
-    };
-    static_assert(kM8Waves * 64 == 4 * kM8Cols, "one stage is two chunks per thread");
+    // vmcnt(0): this wavefront's copies have landed in LDS
+    auto dma_wait = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
+
+    // nothing of the set-up may still be in flight in the loop (its waits would
+    // otherwise wait for every copy)
+    dma_wait();
     if (lo < hi) {
-        load_stage(lo, min(kM8Cols, hi - lo));
-        store_stage(0, min(kM8Cols, hi - lo));
+        stage_dma(sD[0], sC[0], lo, min(kM8Cols, hi - lo));
+        dma_wait();
     }
     __syncthreads();
-    int buf = 0;
-    for (int base = lo; base < hi; base += kM8Cols, buf ^= 1) {
-        const int nb = base + kM8Cols;
-        if (nb < hi) load_stage(nb, min(kM8Cols, hi - nb));  // in flight while this stage is matched
-        // one column tile at a time: its MFMAs for every row tile, then its screen
+    // the screen of one tile (column col of the stage at base), and its slow path
+    auto screen = [&](const v4i (&acc)[RT], const float4 cc, int base, int col) {
+        float U[RT];
+        uint64_t hit = 0;
 #pragma unroll
-        for (int ct = 0; ct < kM8ColTiles; ++ct) {
-            v4i acc[kM8RowTiles];
-            if constexpr (F16) {
-                v8h b16[2];
+        for (int rt = 0; rt < RT; ++rt) {
+            U[rt] = fmaf(sig[rt], cc.x, fmaf(tr[rt], cc.y, cc.z));
+            const int mx = max(max(acc[rt][0], acc[rt][1]), max(acc[rt][2], acc[rt][3]));
+            hit |= __ballot((float)mx >= U[rt]);
+        }
+        if (!hit) return;
+        // slow path: every element of the tile, queued by ballot
+        const bool colok = base + col < hi;
 #pragma unroll
-                for (int h = 0; h < 2; ++h) b16[h] = __builtin_bit_cast(v8h, sH[buf][(16 * ct + c16) * 9 + 4 * h + g]);
-                const v4f zf = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int rt = 0; rt < RT; ++rt) {
+            bool cand[4];
+            uint64_t m[4];
 #pragma unroll
-                for (int rt = 0; rt < kM8RowTiles; ++rt) {
-                    v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b16[0], zf, 0, 0, 0);
-                    x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b16[1], x, 0, 0, 0);
-                    acc[rt] = __builtin_bit_cast(v4i, x);
-                }
-            } else {
-                const v4i bh = sH[buf][(16 * ct + c16) * 4 + g], bl = sL[buf][(16 * ct + c16) * 4 + g];
-                const v4i z = {0, 0, 0, 0};
+            for (int e = 0; e < 4; ++e) {
+                cand[e] = colok && (float)acc[rt][e] >= U[rt];
+                m[e] = __ballot(cand[e]);
+            }
+            if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
 #pragma unroll
-                for (int rt = 0; rt < kM8RowTiles; ++rt) {
-                    acc[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bh, z, 0, 0, 0);
-                    acc[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], bl, acc[rt] << 7, 0, 0, 0);
+            for (int e = 0; e < 4; ++e) {
+                if (m[e]) {
+                    const int slot = qn + __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
+                    if (cand[e])
+                        queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
+                                                     ((uint32_t)(base + col) << kM8RowBits),
+                                                 (uint32_t)acc[rt][e]);
+                    qn += __popcll(m[e]);
                 }
             }
-            const int col = 16 * ct + c16;
-            const float qj = sQ[buf][col];
-            const int sj = sS[buf][col], tmj = sTm[buf][col];
-            const float sjf = F16 ? sSf[buf][col] : 0.0f, bj = F16 ? sBias[buf][col] : 0.0f;
-#pragma unroll
-            for (int rt = 0; rt < kM8RowTiles; ++rt) {
-                const int toff = __mul24(nsrp[rt], sj);  // -sum r' * S (24-bit operands)
-                bool cand[4];
-                uint64_t m[4] = {0, 0, 0, 0};
-                bool any;
-                if constexpr (F16) {
-                    const float Uf = fmaf(sigm[rt], qj, fmaf((float)-nsrp[rt], sjf, bj));
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        cand[e] = __int_as_float(acc[rt][e]) >= Uf;
-                        m[e] = __ballot(cand[e]);
-                    }
-                    any = (m[0] | m[1] | m[2] | m[3]) != 0;
-                } else {
-                    // one compare of the lane's largest element first; the four
-                    // compares only when some lane has a candidate (rare)
-                    // B' >= T for every element that can match or beat the lane's rows
-                    const int T = max((int)fminf(sigm[rt] * qj, 1.0e9f), tmj);
-                    const int U = (T - toff + 63) >> 6;      // 64 X + toff >= T  <=>  X >= U
-                    const int mx = max(max(acc[rt][0], acc[rt][1]), max(acc[rt][2], acc[rt][3]));
-                    any = __ballot(mx >= U) != 0;
-                    if (any) {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            cand[e] = acc[rt][e] >= U;
-                            m[e] = __ballot(cand[e]);
-                        }
-                    }
-                }
-                if (any) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if (m[e]) {
-                            const int slot = qn + __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
-                            if (cand[e]) {
-                                const int X = F16 ? (int)__int_as_float(acc[rt][e])
-                                                  : acc[rt][e];
-                                queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
-                                                             ((uint32_t)(base + col) << kM8RowBits),
-                                                         (uint32_t)X);
-                            }
-                            qn += __popcll(m[e]);
-                        }
-                    }
-                    if (qn >= 64) {
-                        m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
-                        qn = 0;
-#pragma unroll
-                        for (int r2 = 0; r2 < kM8RowTiles; ++r2) {
-                            const uint64_t* bb = best + 16 * r2 + 4 * g;
-                            sigm[r2] = fminf(fminf(m8_sigma(bb[0]), m8_sigma(bb[1])),
-                                             fminf(m8_sigma(bb[2]), m8_sigma(bb[3])));
-                        }
-                    }
-                }
+            // decided every 16 candidates: the bounds tighten early
+            if (qn >= 16) {
+                m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
+                qn = 0;
+                set_bounds();
             }
         }
-        // the other buffer was last read in the previous stage, before its barrier
-        if (nb < hi) store_stage(buf ^ 1, min(kM8Cols, hi - nb));
+    };
+    // one stage: the copy of the next one started, this one matched
+    auto stage = [&](const v4i* cD, const float4* cC, v4i* nD, float4* nC, int base) {
+        const int nb = base + kM8Cols;
+        if (nb < hi) stage_dma(nD, nC, nb, min(kM8Cols, hi - nb));  // lands while this stage is matched
+#pragma unroll
+        for (int ct = 0; ct < kM8ColTiles; ++ct) {
+            const int col = 16 * ct + c16;
+            v4i acc[RT];
+            tile(cD[m8_chunk(col, g)], cD[m8_chunk(col, 4 + g)], acc);
+            screen(acc, cC[col], base, col);
+        }
+    };
+    int buf = 0;
+    for (int base = lo; base < hi; base += kM8Cols, buf ^= 1) {
+        stage(sD[buf], sC[buf], sD[buf ^ 1], sC[buf ^ 1], base);
+        dma_wait();
         __syncthreads();
     }
     if (qn > 0) m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
     // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
 #pragma unroll
-    for (int rt = 0; rt < kM8RowTiles; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
+        const int orow = wrow0 + 16 * rt + 4 * g;
+        int64_t F = INT64_MAX, K = INT64_MAX;
+        if (lo < hi && orow < nrows && c16 == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint64_t v = best[16 * rt + 4 * g + e];
+                const int pos = (int)((v >> 4) & (uint64_t)(kM8MaxPool - 1)), k = (int)(v & 15u);
+                const int64_t Fe = m8_unpack_F(v) == kM8Excl ? 0 : m8_unpack_F(v);
+                const int64_t key = make_key(Jd[pos], (orow + e) & 7, k, Sd[pos]);
+                if (pair_less(Fe, key, F, K)) {
+                    F = Fe;
+                    K = key;
+                }
+            }
+        }
+        lex_min_shfl(F, K, 16);
+        if (c16 == 0 && (g & 1) == 0 && orow < nrows) {
+            Partial pr;
+            pr.F = F;
+            pr.key = K;
+            part[(int64_t)(orow >> 3) * n_chunks + c] = pr;
+        }
+    }
+}
+
+// ================================================================ FP16 MFMA matcher, normalized screen (B = 8)
+// The FP16 grid matcher. Its screen runs on normalized operands: each pool
+// domain's column holds d^_i = (64 d'_i - S) / Q in FP16, Q = sqrt(A') rounded
+// below (0 for a constant domain), and each range row holds r^ = r' - c with c
+// the range's mean of r' rounded to an integer (exact in FP16: |r^| <= 255).
+// In exact arithmetic their product is
+//   X^ = sum r^_i d^_i = (64 sum r^ d' - S sum r^) / Q = B' / Q
+// (B' does not change when r is shifted), so an element can match or beat a
+// range's best F_b <= 0, which needs B' >= s_b sqrt(A') >= s_b Q, only if
+// X^ >= s_b: a bound that depends on the range alone. The FP16 roundings of d^
+// (relative 2^-11, its FP32 product 2^-23) move X^ by at most
+// 2^-10.99 ||r^|| ||d^|| + 2^-25 sum |r^| with ||d^|| = 8 sqrt(A') / Q, about
+// 8; the FP32 accumulation of 64 products and the start value adds below 0.3;
+// so E = ||r^|| / 120 + 0.5 bounds the error, and an element with computed
+// X^ >= s_b - E is a candidate. The bound enters the accumulators' start
+// value: they start at 2^15 - (s_b - E) (one start value per lane and row tile,
+// rewritten when s_b changes), hold 2^15 + X^ - (s_b - E) in (0, 2^16) (|X^| <=
+// 8 sqrt(A_r)/8 and s_b <= sqrt(A_r) <= 8160), and the screen of a 16-column
+// tile is the largest FP32 bit pattern of the lane's 16 elements against that
+// of 2^15: positive floats order as their bit patterns do. Candidates are then
+// decided exactly: X = sum r' d' from the integer data (FP16 dot products of
+// integers below 2^24, exact), as in the int8 form.
+constexpr float kN16Off = 32768.0f;   // 2^15
+constexpr int kN16OffBits = 0x47000000;  // its FP32 bit pattern
+
+// Exact decision of the wavefront's queued candidates (entry: row | position
+// << kM8RowBits), one per lane: X from the FP16 rows r' (Ar, row wrow0 + row)
+// and columns d' (Dh).
+__device__ inline void n16_flush(int n, const uint2* q, const int32_t* nsr, uint64_t* best,
+                                 const _Float16* __restrict__ Ar, int wrow0, const _Float16* __restrict__ Dh,
+                                 const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
+                                 const float* __restrict__ Gd, int k1, int lane) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int i = lane; i < n; i += 64) {
+        const uint2 en = q[i];
+        const int row = (int)(en.x & ((1u << kM8RowBits) - 1u)), pos = (int)(en.x >> kM8RowBits);
+        // (pairs read as FP16 vectors: a bit cast of one element of a wider
+        // vector register is not reliable here)
+        const h2* r = reinterpret_cast<const h2*>(Ar + (int64_t)(wrow0 + row) * 64);
+        const h2* d = reinterpret_cast<const h2*>(Dh + (int64_t)pos * 64);
+        float x = 0.0f;  // integer partial sums below 2^24: exact
+#pragma unroll 4
+        for (int c = 0; c < 32; ++c) x = __builtin_amdgcn_fdot2(r[c], d[c], x, false);
+        m8_decide(row, pos, (int)x, nsr, best, Ad, Sd, Gd, k1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One copy of 16 bytes a lane from base + off (off per lane) into LDS at
+// lds + 16 i; as m8_copy_to_lds, with the base in SGPRs.
+__device__ __forceinline__ void n16_copy_to_lds(const void* base, uint32_t off,
+                                                const void __attribute__((address_space(3)))* lds) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :
+                 : "v"(off), "s"(base), "s"((uint32_t)(uintptr_t)lds)
+                 : "memory");
+}
+
+// grid: x = workgroups of m8_rows rows, y = pool chunks, as the int8 form; a
+// stage of kM8Cols normalized columns is copied into LDS (chunk u of column c
+// at m8_chunk(c, u)) while the previous one is matched.
+__device__ __forceinline__ void k_match_n16_body(
+    const _Float16* __restrict__ Ar, const int32_t* __restrict__ SR, const int32_t* __restrict__ SRp,
+    const int64_t* __restrict__ CR, const int32_t* act_count, const _Float16* __restrict__ Dh,
+    const _Float16* __restrict__ Dn, const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad,
+    const float* __restrict__ Gd, const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
+    Partial* __restrict__ part, int cg) {
+    constexpr int RT = m8_row_tiles(true), WR = 16 * RT;
+    constexpr int kLoads = kM8Cols * 8 / (kM8Waves * 64);
+    static_assert(WR <= (1 << kM8RowBits), "row index of a queue entry");
+    static_assert(kM8Waves * kLoads * 64 == kM8Cols * 8, "a stage is whole 16-byte chunks per lane");
+    __shared__ v4i sD[2][kM8Cols * 8];
+    __shared__ uint2 sQueue[kM8Waves][kM8Queue];
+    __shared__ uint64_t sBest[kM8Waves][WR];
+    __shared__ int32_t sNsr[kM8Waves][WR];
+
+    const int nrows = 8 * *act_count;
+    const int row_blk = blockIdx.x * m8_rows(true);
+    if (row_blk >= nrows) return;
+    const int P = ctrl->pool_count;
+    const int nca = active_chunks(P, cg, n_chunks);
+    const int c = blockIdx.y;
+    if (c >= nca) return;
+    const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    const int wrow0 = row_blk + wave * WR;
+    uint2* queue = sQueue[wave];
+    uint64_t* best = sBest[wave];
+    int32_t* nsr = sNsr[wave];
+
+    // A operands r^ = r' - c (c = the row's range mean of r', rounded)
+    v8h af[RT][2];
+    float E[RT];    // error bound of X^ for the lane's output range
+    float sig[RT];  // s_b of the lane's range
+    int cw[RT];     // c of the lane's output range
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int arow = wrow0 + 16 * rt + c16;
+        const v4i z = {0, 0, 0, 0};
+        const _Float16 ca = arow < nrows ? (_Float16)rintf((float)SRp[arow >> 3] * (1.0f / 64.0f)) : (_Float16)0.0f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const v8h v = __builtin_bit_cast(
+                v8h, arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 32 * h + 8 * g) : z);
+            af[rt][h] = v - ca;
+        }
+        const int orow = wrow0 + 16 * rt + 4 * g;
+        E[rt] = 0.0f;
+        cw[rt] = 0;
+        if (orow < nrows) {
+            const int q = orow >> 3;
+            // ||r^||^2 = sum r'^2 - 2 c sum r' + 64 c^2, sum r'^2 from sum r and C = 64 sum r^2 - (sum r)^2
+            const int64_t s = SR[q], sp = SRp[q];
+            const int64_t co = (int64_t)rintf((float)sp * (1.0f / 64.0f));
+            cw[rt] = (int)co;
+            const int64_t r2 = (CR[q] + s * s) / 64 - 256 * s + 64 * 16384;
+            const int64_t n2 = r2 - 2 * co * sp + 64 * co * co;
+            E[rt] = sqrtf((float)n2) * (1.0f / 120.0f) + 0.5f;
+        }
+    }
+    for (int i = lane; i < WR; i += 64) {
+        // k = 0 gives F = 0 for every domain; its smallest key is the chunk's first domain
+        const int r = wrow0 + i;
+        const bool live = r < nrows && CR[r >> 3] != 0;
+        best[i] = m8_pack(live ? 0 : kM8Excl, lo, 0);
+        nsr[i] = r < nrows ? -SRp[r >> 3] : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // A first bound before the search: 4 tiles of 16 domains spread over the
+    // chunk, decided exactly (X = sum r^ d' + c S: FP16 products of integers with
+    // partial sums below 64 * 255 * 1020 < 2^24, exact). Without it every
+    // chunk would open with half of its first elements queued.
+    if (lo < hi) {
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            const int pos = lo + (int)((int64_t)(hi - lo) * (16 * st + c16) / 64);
+            const v8h b0 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(Dh + (int64_t)pos * 64 + 8 * g));
+            const v8h b1 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(Dh + (int64_t)pos * 64 + 32 + 8 * g));
+            const int S = (int)Sd[pos];
+            const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b0, z, 0, 0, 0);
+                x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b1, x, 0, 0, 0);
+                if (wrow0 + 16 * rt + 4 * g < nrows) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        m8_decide(16 * rt + 4 * g + e, pos, (int)x[e] + cw[rt] * S, nsr, best, Ad, Sd, Gd, k1);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    v4f C[RT];  // accumulator start values 2^15 - (s_b - E)
+    auto set_bounds = [&] {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            sig[rt] = m8_range_sigma(best, rt, g);
+            const float c0 = kN16Off - (sig[rt] - E[rt]);
+            C[rt] = v4f{c0, c0, c0, c0};
+        }
+    };
+    set_bounds();
+    int qn = 0;  // queued candidates (the same in every lane)
+
+    // this wavefront's share of a stage: chunks (kLoads wave + l) * 64 + lane
+    // (columns past the chunk's end copy its last domain and are never queued)
+    uint32_t off[kLoads];  // byte offsets of a full stage's chunks, from the stage's first column
+#pragma unroll
+    for (int l = 0; l < kLoads; ++l) {
+        const int i = (kLoads * wave + l) * 64 + lane, col = i >> 3, u = (i & 7) ^ ((col >> 1) & 7);
+        off[l] = (uint32_t)(col * 128 + 16 * u);
+    }
+    auto stage_dma = [&](v4i* dD, int b0, int n) {
+        // the same in every lane; read from the first so that it sits in SGPRs
+        const uint64_t bu = (uint64_t)(uintptr_t)(Dn + (int64_t)b0 * 64);
+        const void* base = (const void*)(uintptr_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bu >> 32)) << 32) |
+                                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bu));
+        if (n == kM8Cols) {
+#pragma unroll
+            for (int l = 0; l < kLoads; ++l)
+                n16_copy_to_lds(base, off[l], (const __attribute__((address_space(3))) void*)(dD + (kLoads * wave + l) * 64));
+        } else {  // the chunk's last stage: columns past its end copy its last one
+#pragma unroll
+            for (int l = 0; l < kLoads; ++l) {
+                const uint32_t o = (uint32_t)(min((int)(off[l] >> 7), n - 1) * 128) + (off[l] & 127u);
+                n16_copy_to_lds(base, o, (const __attribute__((address_space(3))) void*)(dD + (kLoads * wave + l) * 64));
+            }
+        }
+    };
+    auto dma_wait = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
+
+    // nothing of the set-up may still be in flight in the loop
+    dma_wait();
+    if (lo < hi) {
+        stage_dma(sD[0], lo, min(kM8Cols, hi - lo));
+        dma_wait();
+    }
+    __syncthreads();
+    // X^ of one 16-column tile for every row tile, from the start values C
+    auto tile = [&](const v4i* cD, int ct, const v4f (&C)[RT], v4i (&acc)[RT]) {
+        const int col = 16 * ct + c16;
+        const v8h b0 = __builtin_bit_cast(v8h, cD[m8_chunk(col, g)]);
+        const v8h b1 = __builtin_bit_cast(v8h, cD[m8_chunk(col, 4 + g)]);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b0, C[rt], 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b1, x, 0, 0, 0);
+            acc[rt] = __builtin_bit_cast(v4i, x);
+        }
+    };
+    auto stage = [&](const v4i* cD, v4i* nD, int base) {
+        const int nb = base + kM8Cols;
+        if (nb < hi) stage_dma(nD, nb, min(kM8Cols, hi - nb));  // lands while this stage is matched
+        // the start values as the stage begins, kept in registers (not rebuilt
+        // from constants at every tile); a bound raised within the stage takes
+        // effect at the next: the older one is looser, so the screen stays safe
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) asm volatile("" : "+v"(C[rt]));
+        const v4f (&Cs)[RT] = C;
+        // the screen of every tile, without a branch: a bit per tile with a candidate
+        uint32_t hits = 0;
+#pragma unroll
+        for (int ct = 0; ct < kM8ColTiles; ++ct) {
+            v4i acc[RT];
+            tile(cD, ct, Cs, acc);
+            int mx = max(max(acc[0][0], acc[0][1]), acc[0][2]);
+            mx = max(mx, acc[0][3]);
+#pragma unroll
+            for (int rt = 1; rt < RT; ++rt) {
+                mx = max(max(mx, acc[rt][0]), acc[rt][1]);
+                mx = max(max(mx, acc[rt][2]), acc[rt][3]);
+            }
+            hits |= __ballot(mx >= kN16OffBits) ? 1u << ct : 0u;
+        }
+        if (!hits) return;
+        // slow path: the tiles with a candidate again, every element queued by ballot
+        bool flushed = false;
+        for (int ct = 0; ct < kM8ColTiles; ++ct) {
+            if (!(hits & (1u << ct))) continue;
+            v4i acc[RT];
+            tile(cD, ct, Cs, acc);
+            const int col = 16 * ct + c16;
+            const bool colok = base + col < hi;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                bool cand[4];
+                uint64_t m[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    cand[e] = colok && acc[rt][e] >= kN16OffBits;
+                    m[e] = __ballot(cand[e]);
+                }
+                if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (m[e]) {
+                        const int slot = qn + __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
+                        if (cand[e])
+                            queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
+                                                         ((uint32_t)(base + col) << kM8RowBits),
+                                                     0u);
+                        qn += __popcll(m[e]);
+                    }
+                }
+                // decided every 16 candidates: the bounds tighten early, so fewer
+                // tiles take this path
+                if (qn >= 16) {
+                    n16_flush(qn, queue, nsr, best, Ar, wrow0, Dh, Ad, Sd, Gd, k1, lane);
+                    qn = 0;
+                    flushed = true;
+                }
+            }
+        }
+        if (flushed) set_bounds();  // for the next stage
+    };
+    int buf = 0;
+    for (int base = lo; base < hi; base += kM8Cols, buf ^= 1) {
+        stage(sD[buf], sD[buf ^ 1], base);
+        dma_wait();
+        __syncthreads();
+    }
+    if (qn > 0) n16_flush(qn, queue, nsr, best, Ar, wrow0, Dh, Ad, Sd, Gd, k1, lane);
+    // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
         const int orow = wrow0 + 16 * rt + 4 * g;
         int64_t F = INT64_MAX, K = INT64_MAX;
         if (lo < hi && orow < nrows && c16 == 0) {
@@ -2861,10 +3211,10 @@ __global__ __launch_bounds__(kBlock) void kt_pool_prep_i8(Lvl a0, const Lvl* __r
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * 4) return;
     if (a.var == kVarMfma16)
         k_pool_prep_m8_body<true>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl,
-                                  a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
+                                  a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.cq);
     else
         k_pool_prep_m8_body<false>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl,
-                                   a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.af);
+                                   a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.cq);
 }
 
 template <bool TAB>
@@ -2896,8 +3246,13 @@ __global__ __launch_bounds__(kMqWaves * 64) void kt_match_mfq(Lvl a0, const Lvl*
 template <bool F16, bool TAB>
 __global__ __launch_bounds__(kM8Waves * 64) void kt_match_mfma8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    k_match_mfma8_body<F16>(a.ar, a.srp, a.cr, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.af,
-                            a.jd, a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
+    if constexpr (F16)
+        k_match_n16_body(reinterpret_cast<const _Float16*>(a.ar), a.sr, a.srp, a.cr, a.ctrl->act_count + a.lv,
+                         reinterpret_cast<const _Float16*>(a.dh), reinterpret_cast<const _Float16*>(a.dl), a.sd,
+                         a.ad, a.gd, a.jd, a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
+    else
+        k_match_i8_body(a.ar, a.srp, a.cr, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.cq, a.jd,
+                        a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
 }
 
 template <bool TAB>

@@ -458,9 +458,9 @@ int visit_sizes(Workspace& ws, const Sizes& s, Get get) {
         if (s.dq[l] && (rc = get(pb.dh, s.dq[l]))) return rc;
         if (s.dcol[l]) {
             if ((rc = get(pb.dh, s.dcol[l] * 128))) return rc;  // h rows, or FP16 columns
-            if ((rc = get(pb.dl, s.dcol[l] * 64))) return rc;
+            if ((rc = get(pb.dl, s.dcol[l] * 128))) return rc;  // l rows, or normalized FP16 columns
             if ((rc = get(pb.wd, s.dcol[l] * 4))) return rc;
-            if ((rc = get(pb.cw, s.dcol[l] * 4))) return rc;
+            if ((rc = get(pb.cw, s.dcol[l] * 16))) return rc;
         }
     }
     if ((rc = get(ws.sr, s.rng * 4))) return rc;
@@ -550,7 +550,7 @@ Lvl make_lvl(Workspace& ws, const Level& v, const uint8_t* img, int H, int W, in
     a.dh = P<int8_t>(pb.dh);
     a.dl = P<int8_t>(pb.dl);
     a.gd = P<float>(pb.wd);
-    a.af = P<float>(pb.cw);
+    a.cq = P<float4>(pb.cw);
     a.ks = v.ks;
     return a;
 }
