@@ -89,10 +89,11 @@ struct Lvl {
     fic_level_stats* stats;
     int8_t* ar;  // int8 MFMA matcher (B = 8)
     int32_t* srp;
+    int64_t* gb;  // MFMA grid matchers: each range's best F so far over all pool chunks
+    int2* rc;     // int8 MFMA grid matcher: each range's row offset c and sum |r' - c|
     int8_t* dh;
     int8_t* dl;
     float* gd;
-    float4* cq;  // int8 / FP16 MFMA matchers: per-domain screen constants
     uint32_t* flags;    // optional: split flags, one bit per active range, levels in order
     int32_t* pools_out; // optional: this level's pool list
     int32_t* n_out;     // optional, last level: the number of codes, written by the compaction

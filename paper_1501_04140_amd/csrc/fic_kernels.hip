@@ -1662,6 +1662,9 @@ constexpr int kM8Chunk = 1024;                         // target pool domains pe
 // (1 - 2^-18): a factor that puts an FP32 square root or product (a few ulps
 // of error each) safely below the exact real value.
 constexpr float kM8Shrink = 1.0f - 1.0f / 262144.0f;
+// The int8 screen's column scale: its normalized columns are at most 8 * 4079
+// < 2^15 in size, two int8 halves.
+constexpr float kI8Scale = 4079.0f;
 
 // Rows r' = r - 128 of the 8 inverse-isometry arrangements of each range:
 // Ar[(8q + t) * 64 + m] = R[iso_src(8, inverse(t), m)] - 128, as int8 or (F16)
@@ -1673,24 +1676,49 @@ __device__ __forceinline__ void k_range_prep_m8_body(const uint8_t* __restrict__
                                                           int8_t* __restrict__ Ar,
                                                           int32_t* __restrict__ SR,
                                                           int32_t* __restrict__ SRp,
-                                                          int64_t* __restrict__ CR) {
+                                                          int64_t* __restrict__ CR,
+                                                          int64_t* __restrict__ GB,
+                                                          int2* __restrict__ RC) {
     constexpr int B = 8, n = 64;
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= 8 * *act_count) return;
     const int q = row >> 3, t = row & 7;
     const int yx = act[q];
+    if (t == 0) GB[q] = 0;  // the matcher's shared bound: F = 0 (k = 0) is always reached
     uint32_t* dst = reinterpret_cast<uint32_t*>(Ar + (int64_t)row * n * (F16 ? 2 : 1));
     if (yx < 0) {
-        // r = 0 -> r' = -128 (0x80 as int8, 0xd800 as FP16)
-        for (int w = 0; w < (F16 ? n / 2 : n / 4); ++w) dst[w] = F16 ? 0xd800d800u : 0x80808080u;
+        // r = 0 -> r' = -128 (0xd800 as FP16; int8: r' - c = 0 with c = -128)
+        for (int w = 0; w < (F16 ? n / 2 : n / 4); ++w) dst[w] = F16 ? 0xd800d800u : 0u;
         if (t == 0) {
             SR[q] = 0;
             SRp[q] = -128 * n;
             CR[q] = 0;
+            if constexpr (!F16) RC[q] = make_int2(-128, 0);
         }
         return;
     }
     const uint8_t* r = img + (int64_t)(yx >> 16) * pitch + (yx & 0xffff);
+    // int8 rows are r' - c with c the range's mean of r' rounded, moved into
+    // [max r' - 127, min r' + 128] so that every r' - c fits in int8 (a range's
+    // values span at most 255)
+    int cc = 0;
+    if constexpr (!F16) {
+        int s = 0, mn = 255, mx = 0;
+        for (int i = 0; i < B; ++i)
+            for (int c = 0; c < B; ++c) {
+                const int v = r[i * pitch + c];
+                s += v;
+                mn = min(mn, v);
+                mx = max(mx, v);
+            }
+        cc = min(max((s - 128 * n + 32) >> 6, mx - 255), mn);
+        if (t == 0) {
+            int sa = 0;
+            for (int i = 0; i < B; ++i)
+                for (int c = 0; c < B; ++c) sa += abs((int)r[i * pitch + c] - 128 - cc);
+            RC[q] = make_int2(cc, sa);
+        }
+    }
     const int u = iso_inverse(t);
     const int a0 = iso_src(B, u, 0, 0);
     const int a1 = iso_src(B, u, 1, 0) - a0, a2 = iso_src(B, u, 0, 1) - a0;
@@ -1715,7 +1743,7 @@ __device__ __forceinline__ void k_range_prep_m8_body(const uint8_t* __restrict__
             for (int b = 0; b < 4; ++b) {
                 const int m = 4 * w + b;
                 const int src = a0 + a1 * (m / B) + a2 * (m % B);
-                v |= (uint32_t)(uint8_t)((int)r[(src / B) * pitch + src % B] - 128) << (8 * b);
+                v |= (uint32_t)(uint8_t)((int)r[(src / B) * pitch + src % B] - 128 - cc) << (8 * b);
             }
             dst[w] = v;
         }
@@ -1735,10 +1763,10 @@ __device__ __forceinline__ void k_range_prep_m8_body(const uint8_t* __restrict__
     }
 }
 
-// Columns for the MFMA matchers: h and l rows of each pool domain (int8), or
-// (F16) the 64 sums d' in FP16 (exact: integers below 2^11) at Dh and their
-// normalized form at Dl, 128 bytes per domain each; in FP32 G = 40 / A' (0 for
-// a constant domain); and the int8 screen's per-domain constants (below). Four
+// Columns for the MFMA matchers, 128 bytes per domain in each of two arrays:
+// at Dh the exact sums d' (FP16, exact: integers below 2^11; or int8 as
+// d' = 128 h + l with h in 0..7 and l in 0..127), at Dl their normalized form
+// for the screen (below); in FP32 G = 40 / A' (0 for a constant domain). Four
 // lanes share a domain, 16 decimated values each.
 template <bool F16>
 __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ img, int pitch,
@@ -1746,8 +1774,7 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
                                                          int identity_total, Ctrl* ctrl,
                                                          int8_t* __restrict__ Dh, int8_t* __restrict__ Dl,
                                                          uint32_t* __restrict__ Sd, int64_t* __restrict__ Ad,
-                                                         int32_t* __restrict__ Jd, float* __restrict__ Gd,
-                                                         float4* __restrict__ Cq) {
+                                                         int32_t* __restrict__ Jd, float* __restrict__ Gd) {
     constexpr int B = 8, n = 64, TPD = 4, PER = 16;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (identity_total >= 0 && g == 0) {
@@ -1760,12 +1787,13 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
     uint32_t s = 0;
     uint64_t q = 0;
     int j = 0;
-    int dv[PER];  // F16: the lane's d', normalized once the domain's moments are known
+    int dv[PER];  // the lane's d', normalized once the domain's moments are known
     if (ok) {
         j = identity_total >= 0 ? p : pool[p];
         const int y = (j / gx) * L, x = (j % gx) * L;
-        uint32_t* hd = reinterpret_cast<uint32_t*>(Dh + ((int64_t)p * n + sub * PER) * (F16 ? 2 : 1));
-        uint32_t* ld = reinterpret_cast<uint32_t*>(Dl + (int64_t)p * n + sub * PER);
+        // FP16: d' at Dh + 128 p; int8: h at Dh + 128 p, l 64 bytes further
+        uint32_t* hd = reinterpret_cast<uint32_t*>(Dh + (int64_t)p * 128 + sub * PER * (F16 ? 2 : 1));
+        uint32_t* ld = reinterpret_cast<uint32_t*>(Dh + (int64_t)p * 128 + 64 + sub * PER);
 #pragma unroll
         for (int w = 0; w < PER / 4; ++w) {
             uint32_t hw = 0, lw = 0, f16w[2] = {0u, 0u};
@@ -1795,18 +1823,36 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
         s += __shfl_xor(s, m, 64);
         q += __shfl_xor(q, m, 64);
     }
-    if constexpr (F16) {
-        // the screen's columns d^_i = (64 d'_i - S) / Q in FP16 (Q = sqrt(A')
-        // rounded below; 0 for a constant domain)
-        if (ok) {
-            const int64_t A = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
-            const float inv = A > 0 ? 1.0f / (sqrtf((float)A) * kM8Shrink) : 0.0f;
-            uint32_t* nd = reinterpret_cast<uint32_t*>(Dl + ((int64_t)p * n + sub * PER) * 2);
+    // the screen's normalized columns d^_i = (64 d'_i - S) s at Dl + 128 p, s =
+    // 1 / Q (FP16) or 4079 / Q (int8: rounded to integers, |d^| <= 32632, as
+    // 256 h + l with h, l in -128..127: h at Dl + 128 p, l 64 bytes further),
+    // Q = sqrt(A') rounded below; s = 0 for a constant domain
+    if (ok) {
+        const int64_t A = (int64_t)n * (int64_t)q - (int64_t)s * (int64_t)s;
+        const float sc = A > 0 ? (F16 ? 1.0f : kI8Scale) / (sqrtf((float)A) * kM8Shrink) : 0.0f;
+        if constexpr (F16) {
+            uint32_t* nd = reinterpret_cast<uint32_t*>(Dl + (int64_t)p * 128 + sub * PER * 2);
 #pragma unroll
             for (int w = 0; w < PER / 2; ++w) {
-                const _Float16 h0 = (_Float16)((float)(64 * dv[2 * w] - (int)s) * inv);
-                const _Float16 h1 = (_Float16)((float)(64 * dv[2 * w + 1] - (int)s) * inv);
+                const _Float16 h0 = (_Float16)((float)(64 * dv[2 * w] - (int)s) * sc);
+                const _Float16 h1 = (_Float16)((float)(64 * dv[2 * w + 1] - (int)s) * sc);
                 nd[w] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+            }
+        } else {
+            uint32_t* nh = reinterpret_cast<uint32_t*>(Dl + (int64_t)p * 128 + sub * PER);
+            uint32_t* nl = reinterpret_cast<uint32_t*>(Dl + (int64_t)p * 128 + 64 + sub * PER);
+#pragma unroll
+            for (int w = 0; w < PER / 4; ++w) {
+                uint32_t hw = 0, lw = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int v = (int)rintf((float)(64 * dv[4 * w + b] - (int)s) * sc);
+                    const int h = (v + 128) >> 8, l = v - 256 * h;
+                    hw |= (uint32_t)(uint8_t)h << (8 * b);
+                    lw |= (uint32_t)(uint8_t)l << (8 * b);
+                }
+                nh[w] = hw;
+                nl[w] = lw;
             }
         }
     }
@@ -1816,11 +1862,6 @@ __device__ __forceinline__ void k_pool_prep_m8_body(const uint8_t* __restrict__ 
         Ad[p] = A;
         Jd[p] = j;
         Gd[p] = A > 0 ? 40.0f / (float)A : 0.0f;
-        // screen constants: Q / 64 with Q = sqrt(A') (1 - 2^-18) rounded below
-        // sqrt(A'), S / 64, and the rounding margin (2^100 for a constant domain)
-        if constexpr (!F16)
-            Cq[p] = make_float4(sqrtf((float)A) * kM8Shrink * (1.0f / 64.0f), (float)s * (1.0f / 64.0f),
-                                A > 0 ? -8.0f : 0x1p100f, 0.0f);
     }
 }
 
@@ -1890,16 +1931,6 @@ __device__ inline float m8_sigma(uint64_t v) {
     return F < 0 ? __builtin_amdgcn_sqrtf((float)(-F) * (1.0f / 1600.0f)) * kM8Shrink : 0.0f;
 }
 
-// The largest s_b over the 8 rows of the range that lane group g holds in row
-// tile rt (rows 16 rt + 8 (g / 2) + 0..7 of the wavefront).
-__device__ inline float m8_range_sigma(const uint64_t* best, int rt, int g) {
-    const uint64_t* bb = best + 16 * rt + 8 * (g >> 1);
-    uint64_t m = bb[0];
-#pragma unroll
-    for (int e = 1; e < 8; ++e) m = bb[e] < m ? bb[e] : m;  // smallest packed word: smallest F
-    return m8_sigma(m);
-}
-
 // The exact decision of one candidate (row, pool position) given X = sum r' d'.
 __device__ inline void m8_decide(int row, int pos, int X, const int32_t* nsr, uint64_t* best,
                                  const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
@@ -1915,300 +1946,79 @@ __device__ inline void m8_decide(int row, int pos, int X, const int32_t* nsr, ui
     if (F <= 0) atomicMin(reinterpret_cast<unsigned long long*>(best + row), (unsigned long long)m8_pack(F, pos, k));
 }
 
-// Exact decision of the wavefront's queued candidates (entry: row | position
-// << kM8RowBits, X), one per lane.
-__device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint64_t* best,
-                                const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
-                                const float* __restrict__ Gd, int k1, int lane) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    for (int i = lane; i < n; i += 64) {
-        const uint2 en = q[i];
-        m8_decide((int)(en.x & ((1u << kM8RowBits) - 1u)), (int)(en.x >> kM8RowBits), (int)en.y, nsr, best, Ad, Sd,
-                  Gd, k1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// int8: two independent MFMAs (v_mfma_i32_16x16x64_i8) give the h and l sums
-// of a tile, X = 128 Xh + Xl, exact in int32.
-// A pool stage (kM8Cols domains) is copied from global memory straight into
-// LDS (global_load_lds, 16 bytes a lane, no registers on the way) while the
-// previous stage is matched: 8 chunks of 16 bytes per domain (u < 4 the h
-// values 16u.., u >= 4 the l values 16(u - 4)..; the FP16 matcher below: the
-// normalized values 8u..8u+7), chunk u of column c at c * 8 + (u ^ ((c >> 1) &
-// 7)), so that 16 consecutive columns read one chunk each from distinct
-// banks; beside them the int8 screen's column constants (Q / 64, S / 64, -8 or
-// 2^100).
+// ================================================================ MFMA grid matchers, normalized screen (B = 8)
+// The grid matchers screen on normalized operands. Each pool domain's column
+// holds d^_i = (64 d'_i - S) s with s = 1 / Q (FP16 form) or 4079 / Q (int8
+// form, rounded to integers below 2^15 and split as 256 h + l, both int8), Q =
+// sqrt(A') rounded below (s = 0 for a constant domain). The FP16 form's rows
+// are r^ = r' - c, c the range's mean of r' rounded (exact in FP16: |r^| <=
+// 255); the int8 form's rows are r' itself. In exact arithmetic
+//   X^ = sum r_i d^_i = s (64 sum r' d' - S sum r') = s B'
+// (the d^ of a column sum to zero, so a shift of the rows changes nothing),
+// and an element can match or beat a range's best F_b <= 0, which needs
+// B' >= s_b sqrt(A'), only if X^ >= s_b s sqrt(A') >= s_b (FP16) or 4079 s_b
+// (int8): a bound of the range alone. Computed X^ differ from the exact one by
+// at most E per range:
+//  * FP16: the FP16 roundings of d^ (relative 2^-11, the FP32 product 2^-23)
+//    move it by at most 2^-10.99 ||r^|| ||d^|| + 2^-25 sum |r^| with ||d^|| = 8
+//    sqrt(A') / Q, about 8, and the FP32 accumulation of 64 products and the
+//    start value by below 0.3: E = ||r^|| / 120 + 0.5;
+//  * int8: the rounding to integers moves each d^ by at most 0.5 (plus 2^-23
+//    of it from the FP32 product), so E = 0.5 sum |r'| + 2^-23 ||r'|| 8 * 4079
+//    <= 4.02 ||r'|| + 2 (sum |r'| <= 8 ||r'||); the int32 sums are exact.
+// The bound enters the accumulators: the FP16 form's start at 2^15 - (s_b - E)
+// and hold 2^15 + X^ - (s_b - E) in (0, 2^16) (|X^| <= 8 sqrt(A_r) / 8, s_b <=
+// sqrt(A_r) <= 8160), compared as FP32 bit patterns with that of 2^15
+// (positive floats order as their bit patterns); the int8 form's second MFMA
+// starts from 256 Xh - T, T = floor(4079 s_b - E), so the element is a
+// candidate iff the result is >= 0 (|values| < 2^29). The screen of a 16-column
+// tile is one maximum over the lane's 16 elements. Candidates are then decided
+// exactly from the integer data: X = sum r' d' (FP16 dot products of integers
+// with partial sums below 2^24, or int8 dot products).
+// A pool stage (kM8Cols normalized columns) is copied from global memory
+// straight into LDS (global_load_lds, 16 bytes a lane, no registers on the
+// way) while the previous stage is matched: 8 chunks of 16 bytes per domain
+// (FP16: the values 8u..8u+7; int8: u < 4 the h values 16u.., u >= 4 the l
+// values 16(u - 4)..), chunk u of column c at c * 8 + (u ^ ((c >> 1) & 7)), so
+// that 16 consecutive columns read one chunk each from distinct banks.
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+constexpr float kN16Off = 32768.0f;      // 2^15
+constexpr int kN16OffBits = 0x47000000;  // its FP32 bit pattern
+
 __device__ inline int m8_chunk(int c, int u) { return c * 8 + (u ^ ((c >> 1) & 7)); }
 
-// One copy of 16 bytes a lane from global memory into LDS: lane i's 16 bytes
-// at gaddr land at lds + 16 i (lds the same in every lane, passed in m0). The
-// compiler's builtin for this instruction makes every later LDS read of the
-// kernel wait for the copy to land, which would stall each stage on its
-// successor's copy; issued here, nothing waits for it but the explicit
-// vmcnt(0) before the barrier that publishes the stage. It has no register
-// results (its only outputs are in LDS), and its address registers are read
-// when it issues. It writes m0, a register the compiler reserves and does not
-// restore after inline assembly: the kernels that use it must not use m0
-// otherwise (none of their other instructions reads it: a test checks their
+// One copy of 16 bytes a lane from base + off (off per lane) into LDS: lane
+// i's 16 bytes land at lds + 16 i (base and lds the same in every lane; lds
+// passed in m0). The compiler's builtin for this instruction makes every
+// later LDS read of the kernel wait for the copy to land, which would stall
+// each stage on its successor's copy; issued here, nothing waits for it but
+// the explicit vmcnt before the barrier that publishes the stage. It has no
+// register results (its only outputs are in LDS), and its address registers
+// are read when it issues. It writes m0, a register the compiler reserves and
+// does not restore after inline assembly: the kernels that use it must not use
+// m0 otherwise (none of their other instructions reads it: a test checks their
 // assembly).
-__device__ __forceinline__ void m8_copy_to_lds(const void* gaddr,
+__device__ __forceinline__ void m8_copy_to_lds(const void* base, uint32_t off,
                                                const void __attribute__((address_space(3)))* lds) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
                  :
-                 : "v"(gaddr), "s"((uint32_t)(uintptr_t)lds)
+                 : "v"(off), "s"(base), "s"((uint32_t)(uintptr_t)lds)
                  : "memory");
 }
 
-__device__ __forceinline__ void k_match_i8_body(
-    const int8_t* __restrict__ Ar, const int32_t* __restrict__ SRp, const int64_t* __restrict__ CR,
-    const int32_t* act_count, const int8_t* __restrict__ Dh, const int8_t* __restrict__ Dl, const uint32_t* __restrict__ Sd,
-    const int64_t* __restrict__ Ad, const float* __restrict__ Gd, const float4* __restrict__ Cq,
-    const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
-    Partial* __restrict__ part, int cg) {
-    constexpr int RT = m8_row_tiles(false), WR = 16 * RT;
-    static_assert(WR <= (1 << kM8RowBits), "row index of a queue entry");
-    static_assert(kM8Waves * 2 * 64 == kM8Cols * 8, "a stage is two 16-byte chunks per lane");
-    __shared__ v4i sD[2][kM8Cols * 8];
-    __shared__ float4 sC[2][kM8Cols];
-    __shared__ uint2 sQueue[kM8Waves][kM8Queue];
-    __shared__ uint64_t sBest[kM8Waves][WR];
-    __shared__ int32_t sNsr[kM8Waves][WR];
-
-    const int nrows = 8 * *act_count;
-    const int row_blk = blockIdx.x * m8_rows(false);
-    if (row_blk >= nrows) return;
-    const int P = ctrl->pool_count;
-    const int nca = active_chunks(P, cg, n_chunks);
-    const int c = blockIdx.y;
-    if (c >= nca) return;
-    const int lo = (int)((int64_t)P * c / nca), hi = (int)((int64_t)P * (c + 1) / nca);
-
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int g = lane >> 4, c16 = lane & 15;
-    const int wrow0 = row_blk + wave * WR;
-    uint2* queue = sQueue[wave];
-    uint64_t* best = sBest[wave];
-    int32_t* nsr = sNsr[wave];
-
-    v4i a[RT];
-    float tr[RT];   // sum r' of the lane's output range, in FP32
-    float sig[RT];  // s_b of the lane's range, per row tile
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-        const int arow = wrow0 + 16 * rt + c16;
-        const v4i z = {0, 0, 0, 0};
-        a[rt] = arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 16 * g) : z;
-        const int orow = wrow0 + 16 * rt + 4 * g;
-        tr[rt] = orow < nrows ? (float)SRp[orow >> 3] : 0.0f;
-    }
-    for (int i = lane; i < WR; i += 64) {
-        // k = 0 gives F = 0 for every domain; its smallest key is the chunk's first domain
-        const int r = wrow0 + i;
-        const bool live = r < nrows && CR[r >> 3] != 0;
-        best[i] = m8_pack(live ? 0 : kM8Excl, lo, 0);
-        nsr[i] = r < nrows ? -SRp[r >> 3] : 0;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    // X of 16 columns for every row tile from the lane's two 16-byte chunks of
-    // its column (h and l values 16g..)
-    auto tile = [&](const v4i q0, const v4i q1, v4i (&acc)[RT]) {
-        const v4i z = {0, 0, 0, 0};
-        v4i xh[RT], xl[RT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            xh[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], q0, z, 0, 0, 0);
-            xl[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt], q1, z, 0, 0, 0);
-        }
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc[rt][e] = (xh[rt][e] << 7) + xl[rt][e];
-    };
-    // a first bound before the search: 4 tiles of 16 domains spread over the
-    // chunk, decided exactly (without it every chunk would open with half of
-    // its first elements queued)
-    if (lo < hi) {
-#pragma unroll 1
-        for (int st = 0; st < 4; ++st) {
-            const int pos = lo + (int)((int64_t)(hi - lo) * (16 * st + c16) / 64);
-            v4i acc[RT];
-            tile(*reinterpret_cast<const v4i*>(Dh + (int64_t)pos * 64 + 16 * g),
-                 *reinterpret_cast<const v4i*>(Dl + (int64_t)pos * 64 + 16 * g), acc);
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-                if (wrow0 + 16 * rt + 4 * g < nrows) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) m8_decide(16 * rt + 4 * g + e, pos, acc[rt][e], nsr, best, Ad, Sd, Gd, k1);
-                }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-    auto set_bounds = [&] {
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) sig[rt] = m8_range_sigma(best, rt, g);
-    };
-    set_bounds();
-    int qn = 0;  // queued candidates (the same in every lane)
-
-    // this wavefront's share of a stage: chunks (2 wave + l) * 64 + lane, l = 0, 1
-    // (columns past the chunk's end copy its last domain and are never queued);
-    // wavefront 0 also copies the 64 columns' screen constants
-    auto stage_dma = [&](v4i* dD, float4* dC, int b0, int n) {
-#pragma unroll
-        for (int l = 0; l < 2; ++l) {
-            const int i = (2 * wave + l) * 64 + lane, col = i >> 3, u = (i & 7) ^ ((col >> 1) & 7);
-            const int64_t pos = b0 + min(col, n - 1);
-            const int8_t* src = u < 4 ? Dh + pos * 64 + 16 * u : Dl + pos * 64 + 16 * (u - 4);
-            m8_copy_to_lds(src, (const __attribute__((address_space(3))) void*)(dD + (2 * wave + l) * 64));
-        }
-        if (wave == 0)
-            m8_copy_to_lds(Cq + b0 + min(lane, n - 1), (const __attribute__((address_space(3))) void*)dC);
-    };
-    // vmcnt(0): this wavefront's copies have landed in LDS
-    auto dma_wait = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
-
-    // nothing of the set-up may still be in flight in the loop (its waits would
-    // otherwise wait for every copy)
-    dma_wait();
-    if (lo < hi) {
-        stage_dma(sD[0], sC[0], lo, min(kM8Cols, hi - lo));
-        dma_wait();
-    }
-    __syncthreads();
-    // the screen of one tile (column col of the stage at base), and its slow path
-    auto screen = [&](const v4i (&acc)[RT], const float4 cc, int base, int col) {
-        float U[RT];
-        uint64_t hit = 0;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            U[rt] = fmaf(sig[rt], cc.x, fmaf(tr[rt], cc.y, cc.z));
-            const int mx = max(max(acc[rt][0], acc[rt][1]), max(acc[rt][2], acc[rt][3]));
-            hit |= __ballot((float)mx >= U[rt]);
-        }
-        if (!hit) return;
-        // slow path: every element of the tile, queued by ballot
-        const bool colok = base + col < hi;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            bool cand[4];
-            uint64_t m[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                cand[e] = colok && (float)acc[rt][e] >= U[rt];
-                m[e] = __ballot(cand[e]);
-            }
-            if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (m[e]) {
-                    const int slot = qn + __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
-                    if (cand[e])
-                        queue[slot] = make_uint2((uint32_t)(16 * rt + 4 * g + e) |
-                                                     ((uint32_t)(base + col) << kM8RowBits),
-                                                 (uint32_t)acc[rt][e]);
-                    qn += __popcll(m[e]);
-                }
-            }
-            // decided every 16 candidates: the bounds tighten early
-            if (qn >= 16) {
-                m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
-                qn = 0;
-                set_bounds();
-            }
-        }
-    };
-    // one stage: the copy of the next one started, this one matched
-    auto stage = [&](const v4i* cD, const float4* cC, v4i* nD, float4* nC, int base) {
-        const int nb = base + kM8Cols;
-        if (nb < hi) stage_dma(nD, nC, nb, min(kM8Cols, hi - nb));  // lands while this stage is matched
-#pragma unroll
-        for (int ct = 0; ct < kM8ColTiles; ++ct) {
-            const int col = 16 * ct + c16;
-            v4i acc[RT];
-            tile(cD[m8_chunk(col, g)], cD[m8_chunk(col, 4 + g)], acc);
-            screen(acc, cC[col], base, col);
-        }
-    };
-    int buf = 0;
-    for (int base = lo; base < hi; base += kM8Cols, buf ^= 1) {
-        stage(sD[buf], sC[buf], sD[buf ^ 1], sC[buf ^ 1], base);
-        dma_wait();
-        __syncthreads();
-    }
-    if (qn > 0) m8_flush(qn, queue, nsr, best, Ad, Sd, Gd, k1, lane);
-    // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-        const int orow = wrow0 + 16 * rt + 4 * g;
-        int64_t F = INT64_MAX, K = INT64_MAX;
-        if (lo < hi && orow < nrows && c16 == 0) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint64_t v = best[16 * rt + 4 * g + e];
-                const int pos = (int)((v >> 4) & (uint64_t)(kM8MaxPool - 1)), k = (int)(v & 15u);
-                const int64_t Fe = m8_unpack_F(v) == kM8Excl ? 0 : m8_unpack_F(v);
-                const int64_t key = make_key(Jd[pos], (orow + e) & 7, k, Sd[pos]);
-                if (pair_less(Fe, key, F, K)) {
-                    F = Fe;
-                    K = key;
-                }
-            }
-        }
-        lex_min_shfl(F, K, 16);
-        if (c16 == 0 && (g & 1) == 0 && orow < nrows) {
-            Partial pr;
-            pr.F = F;
-            pr.key = K;
-            part[(int64_t)(orow >> 3) * n_chunks + c] = pr;
-        }
-    }
-}
-
-// ================================================================ FP16 MFMA matcher, normalized screen (B = 8)
-// The FP16 grid matcher. Its screen runs on normalized operands: each pool
-// domain's column holds d^_i = (64 d'_i - S) / Q in FP16, Q = sqrt(A') rounded
-// below (0 for a constant domain), and each range row holds r^ = r' - c with c
-// the range's mean of r' rounded to an integer (exact in FP16: |r^| <= 255).
-// In exact arithmetic their product is
-//   X^ = sum r^_i d^_i = (64 sum r^ d' - S sum r^) / Q = B' / Q
-// (B' does not change when r is shifted), so an element can match or beat a
-// range's best F_b <= 0, which needs B' >= s_b sqrt(A') >= s_b Q, only if
-// X^ >= s_b: a bound that depends on the range alone. The FP16 roundings of d^
-// (relative 2^-11, its FP32 product 2^-23) move X^ by at most
-// 2^-10.99 ||r^|| ||d^|| + 2^-25 sum |r^| with ||d^|| = 8 sqrt(A') / Q, about
-// 8; the FP32 accumulation of 64 products and the start value adds below 0.3;
-// so E = ||r^|| / 120 + 0.5 bounds the error, and an element with computed
-// X^ >= s_b - E is a candidate. The bound enters the accumulators' start
-// value: they start at 2^15 - (s_b - E) (one start value per lane and row tile,
-// rewritten when s_b changes), hold 2^15 + X^ - (s_b - E) in (0, 2^16) (|X^| <=
-// 8 sqrt(A_r)/8 and s_b <= sqrt(A_r) <= 8160), and the screen of a 16-column
-// tile is the largest FP32 bit pattern of the lane's 16 elements against that
-// of 2^15: positive floats order as their bit patterns do. Candidates are then
-// decided exactly: X = sum r' d' from the integer data (FP16 dot products of
-// integers below 2^24, exact), as in the int8 form.
-constexpr float kN16Off = 32768.0f;   // 2^15
-constexpr int kN16OffBits = 0x47000000;  // its FP32 bit pattern
-
 // Exact decision of the wavefront's queued candidates (entry: row | position
-// << kM8RowBits), one per lane: X from the FP16 rows r' (Ar, row wrow0 + row)
-// and columns d' (Dh).
-__device__ inline void n16_flush(int n, const uint2* q, const int32_t* nsr, uint64_t* best,
-                                 const _Float16* __restrict__ Ar, int wrow0, const _Float16* __restrict__ Dh,
-                                 const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
-                                 const float* __restrict__ Gd, int k1, int lane) {
+// << kM8RowBits), one per lane, with X = sum r' d' from the integer rows (Ar,
+// row wrow0 + row) and columns (Dx): FP16 r' and d' (dot products of pairs;
+// partial sums below 2^24, exact), or int8 r' - c and the h | l halves of d' =
+// 128 h + l (dot products of fours; X = sum (r' - c) d' + c S). Pairs and fours are read as whole words:
+// a bit cast of one element of a wider vector register is not reliable here.
+template <bool I8>
+__device__ inline void m8_flush(int n, const uint2* q, const int32_t* nsr, uint64_t* best,
+                                const void* __restrict__ Ar, int wrow0, const void* __restrict__ Dx,
+                                const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
+                                const float* __restrict__ Gd, const int2* __restrict__ RC, int k1, int lane) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -2216,40 +2026,44 @@ __device__ inline void n16_flush(int n, const uint2* q, const int32_t* nsr, uint
     for (int i = lane; i < n; i += 64) {
         const uint2 en = q[i];
         const int row = (int)(en.x & ((1u << kM8RowBits) - 1u)), pos = (int)(en.x >> kM8RowBits);
-        // (pairs read as FP16 vectors: a bit cast of one element of a wider
-        // vector register is not reliable here)
-        const h2* r = reinterpret_cast<const h2*>(Ar + (int64_t)(wrow0 + row) * 64);
-        const h2* d = reinterpret_cast<const h2*>(Dh + (int64_t)pos * 64);
-        float x = 0.0f;  // integer partial sums below 2^24: exact
+        int X;
+        if constexpr (I8) {
+            const int* r = reinterpret_cast<const int*>(static_cast<const int8_t*>(Ar) + (int64_t)(wrow0 + row) * 64);
+            const int* d = reinterpret_cast<const int*>(static_cast<const int8_t*>(Dx) + (int64_t)pos * 128);
+            int xh = 0, xl = 0;
 #pragma unroll 4
-        for (int c = 0; c < 32; ++c) x = __builtin_amdgcn_fdot2(r[c], d[c], x, false);
-        m8_decide(row, pos, (int)x, nsr, best, Ad, Sd, Gd, k1);
+            for (int c = 0; c < 16; ++c) {
+                const int rv = r[c];
+                xh = __builtin_amdgcn_sdot4(rv, d[c], xh, false);
+                xl = __builtin_amdgcn_sdot4(rv, d[16 + c], xl, false);
+            }
+            X = (xh << 7) + xl + RC[(wrow0 + row) >> 3].x * (int)Sd[pos];  // rows are r' - c
+        } else {
+            const h2* r = reinterpret_cast<const h2*>(static_cast<const _Float16*>(Ar) + (int64_t)(wrow0 + row) * 64);
+            const h2* d = reinterpret_cast<const h2*>(static_cast<const _Float16*>(Dx) + (int64_t)pos * 64);
+            float x = 0.0f;
+#pragma unroll 4
+            for (int c = 0; c < 32; ++c) x = __builtin_amdgcn_fdot2(r[c], d[c], x, false);
+            X = (int)x;
+        }
+        m8_decide(row, pos, X, nsr, best, Ad, Sd, Gd, k1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// One copy of 16 bytes a lane from base + off (off per lane) into LDS at
-// lds + 16 i; as m8_copy_to_lds, with the base in SGPRs.
-__device__ __forceinline__ void n16_copy_to_lds(const void* base, uint32_t off,
-                                                const void __attribute__((address_space(3)))* lds) {
-    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
-                 :
-                 : "v"(off), "s"(base), "s"((uint32_t)(uintptr_t)lds)
-                 : "memory");
-}
-
-// grid: x = workgroups of m8_rows rows, y = pool chunks, as the int8 form; a
-// stage of kM8Cols normalized columns is copied into LDS (chunk u of column c
-// at m8_chunk(c, u)) while the previous one is matched.
-__device__ __forceinline__ void k_match_n16_body(
-    const _Float16* __restrict__ Ar, const int32_t* __restrict__ SR, const int32_t* __restrict__ SRp,
-    const int64_t* __restrict__ CR, const int32_t* act_count, const _Float16* __restrict__ Dh,
-    const _Float16* __restrict__ Dn, const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad,
+// grid: x = workgroups of m8_rows rows, y = pool chunks. Ar: the rows r' (FP16
+// or int8); Dx: the exact columns (FP16 d', or int8 h | l); Dn: the normalized
+// columns.
+template <bool I8>
+__device__ __forceinline__ void k_match_grid_body(
+    const void* __restrict__ Ar, const int32_t* __restrict__ SR, const int32_t* __restrict__ SRp,
+    const int64_t* __restrict__ CR, const int32_t* act_count, const void* __restrict__ Dx,
+    const void* __restrict__ Dn, const uint32_t* __restrict__ Sd, const int64_t* __restrict__ Ad,
     const float* __restrict__ Gd, const int32_t* __restrict__ Jd, const Ctrl* ctrl, int k1, int n_chunks,
-    Partial* __restrict__ part, int cg) {
-    constexpr int RT = m8_row_tiles(true), WR = 16 * RT;
+    Partial* __restrict__ part, int cg, int64_t* __restrict__ GB, const int2* __restrict__ RC) {
+    constexpr int RT = m8_row_tiles(!I8), WR = 16 * RT;
     constexpr int kLoads = kM8Cols * 8 / (kM8Waves * 64);
     static_assert(WR <= (1 << kM8RowBits), "row index of a queue entry");
     static_assert(kM8Waves * kLoads * 64 == kM8Cols * 8, "a stage is whole 16-byte chunks per lane");
@@ -2259,7 +2073,7 @@ __device__ __forceinline__ void k_match_n16_body(
     __shared__ int32_t sNsr[kM8Waves][WR];
 
     const int nrows = 8 * *act_count;
-    const int row_blk = blockIdx.x * m8_rows(true);
+    const int row_blk = blockIdx.x * m8_rows(!I8);
     if (row_blk >= nrows) return;
     const int P = ctrl->pool_count;
     const int nca = active_chunks(P, cg, n_chunks);
@@ -2274,34 +2088,55 @@ __device__ __forceinline__ void k_match_n16_body(
     uint64_t* best = sBest[wave];
     int32_t* nsr = sNsr[wave];
 
-    // A operands r^ = r' - c (c = the row's range mean of r', rounded)
+    // A operands: FP16 r^ = r' - c (c = the row's range mean of r', rounded), 8
+    // values of each K half; int8 r', 16 values
     v8h af[RT][2];
+    v4i a8[RT];
     float E[RT];    // error bound of X^ for the lane's output range
+    int Lr[RT];     // int8: 128 sum |r' - c| of the lane's output range (the l part's largest size)
     float sig[RT];  // s_b of the lane's range
     int cw[RT];     // c of the lane's output range
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int arow = wrow0 + 16 * rt + c16;
         const v4i z = {0, 0, 0, 0};
-        const _Float16 ca = arow < nrows ? (_Float16)rintf((float)SRp[arow >> 3] * (1.0f / 64.0f)) : (_Float16)0.0f;
+        if constexpr (I8) {
+            a8[rt] = arow < nrows
+                         ? *reinterpret_cast<const v4i*>(static_cast<const int8_t*>(Ar) + (int64_t)arow * 64 + 16 * g)
+                         : z;
+        } else {
+            const _Float16 ca =
+                arow < nrows ? (_Float16)rintf((float)SRp[arow >> 3] * (1.0f / 64.0f)) : (_Float16)0.0f;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const v8h v = __builtin_bit_cast(
-                v8h, arow < nrows ? *reinterpret_cast<const v4i*>(Ar + (int64_t)arow * 64 + 32 * h + 8 * g) : z);
-            af[rt][h] = v - ca;
+            for (int h = 0; h < 2; ++h) {
+                const v8h v = __builtin_bit_cast(
+                    v8h, arow < nrows ? *reinterpret_cast<const v4i*>(static_cast<const _Float16*>(Ar) +
+                                                                    (int64_t)arow * 64 + 32 * h + 8 * g)
+                                      : z);
+                af[rt][h] = v - ca;
+            }
         }
         const int orow = wrow0 + 16 * rt + 4 * g;
         E[rt] = 0.0f;
+        Lr[rt] = 0;
         cw[rt] = 0;
         if (orow < nrows) {
             const int q = orow >> 3;
-            // ||r^||^2 = sum r'^2 - 2 c sum r' + 64 c^2, sum r'^2 from sum r and C = 64 sum r^2 - (sum r)^2
+            // sum r'^2 from sum r and C = 64 sum r^2 - (sum r)^2
             const int64_t s = SR[q], sp = SRp[q];
-            const int64_t co = (int64_t)rintf((float)sp * (1.0f / 64.0f));
-            cw[rt] = (int)co;
             const int64_t r2 = (CR[q] + s * s) / 64 - 256 * s + 64 * 16384;
-            const int64_t n2 = r2 - 2 * co * sp + 64 * co * co;
-            E[rt] = sqrtf((float)n2) * (1.0f / 120.0f) + 0.5f;
+            if constexpr (I8) {
+                const int2 rc = RC[q];
+                cw[rt] = rc.x;
+                E[rt] = 0.51f * (float)rc.y + 2.0f;
+                Lr[rt] = 128 * rc.y;
+                (void)r2;
+            } else {
+                // ||r^||^2 = sum r'^2 - 2 c sum r' + 64 c^2
+                const int64_t co = (int64_t)rintf((float)sp * (1.0f / 64.0f));
+                cw[rt] = (int)co;
+                E[rt] = sqrtf((float)(r2 - 2 * co * sp + 64 * co * co)) * (1.0f / 120.0f) + 0.5f;
+            }
         }
     }
     for (int i = lane; i < WR; i += 64) {
@@ -2315,25 +2150,45 @@ __device__ __forceinline__ void k_match_n16_body(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     // A first bound before the search: 4 tiles of 16 domains spread over the
-    // chunk, decided exactly (X = sum r^ d' + c S: FP16 products of integers with
-    // partial sums below 64 * 255 * 1020 < 2^24, exact). Without it every
-    // chunk would open with half of its first elements queued.
+    // chunk, decided exactly (FP16: X = sum r^ d' + c S, products of integers
+    // with partial sums below 64 * 255 * 1020 < 2^24; int8: X = 128 sum r' h +
+    // sum r' l). Without it every chunk would open with half of its first
+    // elements queued.
     if (lo < hi) {
 #pragma unroll 1
         for (int st = 0; st < 4; ++st) {
             const int pos = lo + (int)((int64_t)(hi - lo) * (16 * st + c16) / 64);
-            const v8h b0 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(Dh + (int64_t)pos * 64 + 8 * g));
-            const v8h b1 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(Dh + (int64_t)pos * 64 + 32 + 8 * g));
-            const int S = (int)Sd[pos];
-            const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+            if constexpr (I8) {
+                const int8_t* d = static_cast<const int8_t*>(Dx) + (int64_t)pos * 128 + 16 * g;
+                const v4i bh = *reinterpret_cast<const v4i*>(d), bl = *reinterpret_cast<const v4i*>(d + 64);
+                const int S = (int)Sd[pos];
+                const v4i z = {0, 0, 0, 0};
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b0, z, 0, 0, 0);
-                x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b1, x, 0, 0, 0);
-                if (wrow0 + 16 * rt + 4 * g < nrows) {
+                for (int rt = 0; rt < RT; ++rt) {
+                    const v4i xh = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8[rt], bh, z, 0, 0, 0);
+                    const v4i xl = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8[rt], bl, z, 0, 0, 0);
+                    if (wrow0 + 16 * rt + 4 * g < nrows) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        m8_decide(16 * rt + 4 * g + e, pos, (int)x[e] + cw[rt] * S, nsr, best, Ad, Sd, Gd, k1);
+                        for (int e = 0; e < 4; ++e)
+                            m8_decide(16 * rt + 4 * g + e, pos, (xh[e] << 7) + xl[e] + cw[rt] * S, nsr, best, Ad, Sd,
+                                      Gd, k1);
+                    }
+                }
+            } else {
+                const _Float16* d = static_cast<const _Float16*>(Dx) + (int64_t)pos * 64 + 8 * g;
+                const v8h b0 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(d));
+                const v8h b1 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(d + 32));
+                const int S = (int)Sd[pos];
+                const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b0, z, 0, 0, 0);
+                    x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b1, x, 0, 0, 0);
+                    if (wrow0 + 16 * rt + 4 * g < nrows) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            m8_decide(16 * rt + 4 * g + e, pos, (int)x[e] + cw[rt] * S, nsr, best, Ad, Sd, Gd, k1);
+                    }
                 }
             }
         }
@@ -2341,13 +2196,44 @@ __device__ __forceinline__ void k_match_n16_body(
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    v4f C[RT];  // accumulator start values 2^15 - (s_b - E)
+    // accumulator start values: FP16 2^15 - (s_b - E) in four lanes of a tile
+    // row; int8 -T (fine screen: 256 Xh + Xl - T >= 0) and -Th (coarse screen
+    // on the h part alone: Xh - Th >= 0, Th = ceil((T - Lr) / 256), since
+    // |Xl| <= 128 sum |r' - c| = Lr)
+    v4f C[RT];
+    int Ci[RT], Ch[RT];
+    // A range's bound is the smallest F found for it so far, here or in any
+    // other pool chunk: after each batch of decisions a workgroup publishes its
+    // ranges' best F (real matches) with an atomic minimum and reads the
+    // others' back, so chunks do not each rediscover what one has found. A
+    // value read late is only looser.
     auto set_bounds = [&] {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            sig[rt] = m8_range_sigma(best, rt, g);
-            const float c0 = kN16Off - (sig[rt] - E[rt]);
-            C[rt] = v4f{c0, c0, c0, c0};
+            const uint64_t* bb = best + 16 * rt + 8 * (g >> 1);
+            uint64_t mb = bb[0];
+#pragma unroll
+            for (int e = 1; e < 8; ++e) mb = bb[e] < mb ? bb[e] : mb;
+            int64_t F = m8_unpack_F(mb);
+            const int orow = wrow0 + 16 * rt + 4 * g;
+            if (orow < nrows && F != kM8Excl) {
+                int64_t* gp = GB + (orow >> 3);
+                if (F < 0 && c16 == 0 && (g & 1) == 0)
+                    __hip_atomic_fetch_min(gp, F, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int64_t Fg = __hip_atomic_load(gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                F = Fg < F ? Fg : F;
+            }
+            sig[rt] = F < 0 ? __builtin_amdgcn_sqrtf((float)(-F) * (1.0f / 1600.0f)) * kM8Shrink : 0.0f;
+            if constexpr (I8) {
+                // 4079 s_b - E in FP32 (values below 2^25: roundings below 4, and
+                // 8 taken off), then integers: Th = ceil((T - Lr) / 256)
+                const int T = (int)floorf(kI8Scale * sig[rt] - E[rt] - 8.0f);
+                Ci[rt] = -T;
+                Ch[rt] = -((T - Lr[rt] + 255) >> 8);
+            } else {
+                const float c0 = kN16Off - (sig[rt] - E[rt]);
+                C[rt] = v4f{c0, c0, c0, c0};
+            }
         }
     };
     set_bounds();
@@ -2363,18 +2249,18 @@ __device__ __forceinline__ void k_match_n16_body(
     }
     auto stage_dma = [&](v4i* dD, int b0, int n) {
         // the same in every lane; read from the first so that it sits in SGPRs
-        const uint64_t bu = (uint64_t)(uintptr_t)(Dn + (int64_t)b0 * 64);
+        const uint64_t bu = (uint64_t)(uintptr_t)(static_cast<const int8_t*>(Dn) + (int64_t)b0 * 128);
         const void* base = (const void*)(uintptr_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bu >> 32)) << 32) |
                                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bu));
         if (n == kM8Cols) {
 #pragma unroll
             for (int l = 0; l < kLoads; ++l)
-                n16_copy_to_lds(base, off[l], (const __attribute__((address_space(3))) void*)(dD + (kLoads * wave + l) * 64));
+                m8_copy_to_lds(base, off[l], (const __attribute__((address_space(3))) void*)(dD + (kLoads * wave + l) * 64));
         } else {  // the chunk's last stage: columns past its end copy its last one
 #pragma unroll
             for (int l = 0; l < kLoads; ++l) {
                 const uint32_t o = (uint32_t)(min((int)(off[l] >> 7), n - 1) * 128) + (off[l] & 127u);
-                n16_copy_to_lds(base, o, (const __attribute__((address_space(3))) void*)(dD + (kLoads * wave + l) * 64));
+                m8_copy_to_lds(base, o, (const __attribute__((address_space(3))) void*)(dD + (kLoads * wave + l) * 64));
             }
         }
     };
@@ -2387,18 +2273,40 @@ __device__ __forceinline__ void k_match_n16_body(
         dma_wait();
     }
     __syncthreads();
-    // X^ of one 16-column tile for every row tile, from the start values C
-    auto tile = [&](const v4i* cD, int ct, const v4f (&C)[RT], v4i (&acc)[RT]) {
+    // one 16-column tile for every row tile: the screen's value per element
+    // (FP16: FP32 bits of 2^15 + X^ - (s_b - E); int8 fine: X^ - T; int8
+    // coarse, the h part only: Xh - Th)
+    auto tile = [&](const v4i* cD, int ct, bool coarse, v4i (&acc)[RT]) {
         const int col = 16 * ct + c16;
-        const v8h b0 = __builtin_bit_cast(v8h, cD[m8_chunk(col, g)]);
-        const v8h b1 = __builtin_bit_cast(v8h, cD[m8_chunk(col, 4 + g)]);
+        const v4i q0 = cD[m8_chunk(col, g)];
+        if constexpr (I8) {
+            if (coarse) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b0, C[rt], 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b1, x, 0, 0, 0);
-            acc[rt] = __builtin_bit_cast(v4i, x);
+                for (int rt = 0; rt < RT; ++rt) {
+                    const v4i ch = {Ch[rt], Ch[rt], Ch[rt], Ch[rt]};
+                    acc[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8[rt], q0, ch, 0, 0, 0);
+                }
+            } else {
+                const v4i q1 = cD[m8_chunk(col, 4 + g)];
+                const v4i z = {0, 0, 0, 0};
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const v4i xh = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8[rt], q0, z, 0, 0, 0);
+                    acc[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8[rt], q1, (xh << 8) + Ci[rt], 0, 0, 0);
+                }
+            }
+        } else {
+            const v4i q1 = cD[m8_chunk(col, 4 + g)];
+            const v8h b0 = __builtin_bit_cast(v8h, q0), b1 = __builtin_bit_cast(v8h, q1);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                v4f x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][0], b0, C[rt], 0, 0, 0);
+                x = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[rt][1], b1, x, 0, 0, 0);
+                acc[rt] = __builtin_bit_cast(v4i, x);
+            }
         }
     };
+    constexpr int kPass = I8 ? 0 : kN16OffBits;  // a candidate's screen value is at least this
     auto stage = [&](const v4i* cD, v4i* nD, int base) {
         const int nb = base + kM8Cols;
         if (nb < hi) stage_dma(nD, nb, min(kM8Cols, hi - nb));  // lands while this stage is matched
@@ -2406,14 +2314,16 @@ __device__ __forceinline__ void k_match_n16_body(
         // from constants at every tile); a bound raised within the stage takes
         // effect at the next: the older one is looser, so the screen stays safe
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) asm volatile("" : "+v"(C[rt]));
-        const v4f (&Cs)[RT] = C;
+        for (int rt = 0; rt < RT; ++rt) {
+            if constexpr (I8) asm volatile("" : "+v"(Ch[rt]));
+            else asm volatile("" : "+v"(C[rt]));
+        }
         // the screen of every tile, without a branch: a bit per tile with a candidate
         uint32_t hits = 0;
 #pragma unroll
         for (int ct = 0; ct < kM8ColTiles; ++ct) {
             v4i acc[RT];
-            tile(cD, ct, Cs, acc);
+            tile(cD, ct, true, acc);
             int mx = max(max(acc[0][0], acc[0][1]), acc[0][2]);
             mx = max(mx, acc[0][3]);
 #pragma unroll
@@ -2421,7 +2331,7 @@ __device__ __forceinline__ void k_match_n16_body(
                 mx = max(max(mx, acc[rt][0]), acc[rt][1]);
                 mx = max(max(mx, acc[rt][2]), acc[rt][3]);
             }
-            hits |= __ballot(mx >= kN16OffBits) ? 1u << ct : 0u;
+            hits |= __ballot(mx >= kPass) ? 1u << ct : 0u;
         }
         if (!hits) return;
         // slow path: the tiles with a candidate again, every element queued by ballot
@@ -2429,7 +2339,7 @@ __device__ __forceinline__ void k_match_n16_body(
         for (int ct = 0; ct < kM8ColTiles; ++ct) {
             if (!(hits & (1u << ct))) continue;
             v4i acc[RT];
-            tile(cD, ct, Cs, acc);
+            tile(cD, ct, false, acc);
             const int col = 16 * ct + c16;
             const bool colok = base + col < hi;
 #pragma unroll
@@ -2438,7 +2348,7 @@ __device__ __forceinline__ void k_match_n16_body(
                 uint64_t m[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    cand[e] = colok && acc[rt][e] >= kN16OffBits;
+                    cand[e] = colok && acc[rt][e] >= kPass;
                     m[e] = __ballot(cand[e]);
                 }
                 if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
@@ -2457,7 +2367,7 @@ __device__ __forceinline__ void k_match_n16_body(
                 // decided every 16 candidates: the bounds tighten early, so fewer
                 // tiles take this path
                 if (qn >= 16) {
-                    n16_flush(qn, queue, nsr, best, Ar, wrow0, Dh, Ad, Sd, Gd, k1, lane);
+                    m8_flush<I8>(qn, queue, nsr, best, Ar, wrow0, Dx, Ad, Sd, Gd, RC, k1, lane);
                     qn = 0;
                     flushed = true;
                 }
@@ -2471,7 +2381,7 @@ __device__ __forceinline__ void k_match_n16_body(
         dma_wait();
         __syncthreads();
     }
-    if (qn > 0) n16_flush(qn, queue, nsr, best, Ar, wrow0, Dh, Ad, Sd, Gd, k1, lane);
+    if (qn > 0) m8_flush<I8>(qn, queue, nsr, best, Ar, wrow0, Dx, Ad, Sd, Gd, RC, k1, lane);
     // per range: rows 8q..8q+7 are the 4 rows of lane group g and of g ^ 1
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -3211,19 +3121,21 @@ __global__ __launch_bounds__(kBlock) void kt_pool_prep_i8(Lvl a0, const Lvl* __r
     if ((int64_t)blockIdx.x * kBlock >= (int64_t)a.total * 4) return;
     if (a.var == kVarMfma16)
         k_pool_prep_m8_body<true>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl,
-                                  a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.cq);
+                                  a.dh, a.dl, a.sd, a.ad, a.jd, a.gd);
     else
         k_pool_prep_m8_body<false>(a.img, a.pitch, a.L, a.gx, a.pool, filtered ? -1 : a.total, a.pctrl,
-                                   a.dh, a.dl, a.sd, a.ad, a.jd, a.gd, a.cq);
+                                   a.dh, a.dl, a.sd, a.ad, a.jd, a.gd);
 }
 
 template <bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_range_prep_i8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
     if (a.var == kVarMfma16)
-        k_range_prep_m8_body<true>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
+        k_range_prep_m8_body<true>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr, a.gb,
+                                   a.rc);
     else
-        k_range_prep_m8_body<false>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr);
+        k_range_prep_m8_body<false>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr, a.gb,
+                                    a.rc);
 }
 
 template <int B, bool TAB>
@@ -3246,13 +3158,8 @@ __global__ __launch_bounds__(kMqWaves * 64) void kt_match_mfq(Lvl a0, const Lvl*
 template <bool F16, bool TAB>
 __global__ __launch_bounds__(kM8Waves * 64) void kt_match_mfma8(Lvl a0, const Lvl* __restrict__ tab) {
     FIC_LV;
-    if constexpr (F16)
-        k_match_n16_body(reinterpret_cast<const _Float16*>(a.ar), a.sr, a.srp, a.cr, a.ctrl->act_count + a.lv,
-                         reinterpret_cast<const _Float16*>(a.dh), reinterpret_cast<const _Float16*>(a.dl), a.sd,
-                         a.ad, a.gd, a.jd, a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
-    else
-        k_match_i8_body(a.ar, a.srp, a.cr, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.cq, a.jd,
-                        a.pctrl, a.ks.k1, a.nc, a.part, a.cg);
+    k_match_grid_body<!F16>(a.ar, a.sr, a.srp, a.cr, a.ctrl->act_count + a.lv, a.dh, a.dl, a.sd, a.ad, a.gd, a.jd,
+                            a.pctrl, a.ks.k1, a.nc, a.part, a.cg, a.gb, a.rc);
 }
 
 template <bool TAB>

@@ -62,7 +62,7 @@ struct Buf {
 // so the pools of all levels are built concurrently.
 struct PoolBufs {
     Buf key, pool, hl, sd, ad, jd, blk;
-    Buf dh, dl, wd, cw;  // int8 MFMA matcher (B = 8)
+    Buf dh, dl, wd;  // MFMA grid matchers (B = 8): exact and normalized columns, 40 / A'
 };
 
 constexpr int kLevels = 4;
@@ -74,7 +74,7 @@ struct Workspace {
     int64_t* T = nullptr;  // entropy table, kMaxWindow + 1 entries
     PoolBufs pl[kLevels];
     Buf arow, sr, cr, part, blk, act0, act1, tmpc, dec, codes, map, imgA, imgB, acc, mr;
-    Buf ar, srp;  // int8 MFMA matcher (B = 8)
+    Buf ar, srp, gb, rc;  // MFMA grid matchers (B = 8): rows, sum r', shared bounds, int8 row offsets
     Buf plan;     // bitstream section offsets
     hipStream_t side[kLevels] = {};  // one per level's pool phase (default priority)
     hipEvent_t ev_fork = nullptr, ev_pool[kLevels] = {};
@@ -182,7 +182,7 @@ void free_ws(Workspace* ws) {
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (PoolBufs& pb : ws->pl) {
-        Buf* pbs[] = {&pb.key, &pb.pool, &pb.hl, &pb.sd, &pb.ad, &pb.jd, &pb.blk, &pb.dh, &pb.dl, &pb.wd, &pb.cw};
+        Buf* pbs[] = {&pb.key, &pb.pool, &pb.hl, &pb.sd, &pb.ad, &pb.jd, &pb.blk, &pb.dh, &pb.dl, &pb.wd};
         for (Buf* b : pbs)
             if (b->p) (void)hipFree(b->p);
     }
@@ -460,7 +460,6 @@ int visit_sizes(Workspace& ws, const Sizes& s, Get get) {
             if ((rc = get(pb.dh, s.dcol[l] * 128))) return rc;  // h rows, or FP16 columns
             if ((rc = get(pb.dl, s.dcol[l] * 128))) return rc;  // l rows, or normalized FP16 columns
             if ((rc = get(pb.wd, s.dcol[l] * 4))) return rc;
-            if ((rc = get(pb.cw, s.dcol[l] * 16))) return rc;
         }
     }
     if ((rc = get(ws.sr, s.rng * 4))) return rc;
@@ -474,6 +473,8 @@ int visit_sizes(Workspace& ws, const Sizes& s, Get get) {
     if (s.ar) {
         if ((rc = get(ws.ar, s.ar))) return rc;
         if ((rc = get(ws.srp, s.rng * 4))) return rc;
+        if ((rc = get(ws.gb, s.rng * 8))) return rc;
+        if ((rc = get(ws.rc, s.rng * 8))) return rc;
     }
     return FIC_OK;
 }
@@ -547,10 +548,11 @@ Lvl make_lvl(Workspace& ws, const Level& v, const uint8_t* img, int H, int W, in
     a.stats = stats;
     a.ar = P<int8_t>(ws.ar);
     a.srp = P<int32_t>(ws.srp);
+    a.gb = P<int64_t>(ws.gb);
+    a.rc = P<int2>(ws.rc);
     a.dh = P<int8_t>(pb.dh);
     a.dl = P<int8_t>(pb.dl);
     a.gd = P<float>(pb.wd);
-    a.cq = P<float4>(pb.cw);
     a.ks = v.ks;
     return a;
 }
