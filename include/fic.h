@@ -150,15 +150,17 @@ int fic_encode_level(const uint8_t* img, int32_t H, int32_t W, int32_t pitch, in
 enum fic_match_variant {
     FIC_MATCH_AUTO = 0,     /* the library's choice (what fic_encode_level uses)          */
     FIC_MATCH_VALU = 1,     /* dot4 correlation, exact 32/64-bit integer epilogue        */
-    FIC_MATCH_MFMA_I8 = 2,  /* int8 MFMA correlation (hi/lo split of the 2x2 sums),      */
-                            /* screen by the continuous bound of F, exact int64 decision */
+    FIC_MATCH_MFMA_I8 = 2,  /* int8 MFMA screen of normalized domains (15-bit, two     */
+                            /* bytes; the high byte first) against a bound of the range */
+                            /* alone, candidates decided exactly from the integer data. */
+                            /* AUTO takes it for the B = 8 contrast grid                */
     FIC_MATCH_FP32 = 3,     /* FP32 FMA correlation and FP32 E, no exact rescoring: a    */
                             /* comparator whose result may differ from the exact search  */
-    FIC_MATCH_MFMA_F16 = 4  /* FP16 MFMA correlation, FP32 accumulation (exact: every   */
-                            /* partial sum is an integer below 2^24). Contrast grid at   */
-                            /* B = 8: same screen and exact decision as MFMA_I8. One or  */
-                            /* two values at B = 4, 8 or 16 (centred operands): F exact  */
-                            /* in 32/64-bit integers. AUTO takes it wherever it applies  */
+    FIC_MATCH_MFMA_F16 = 4  /* FP16 MFMA. Contrast grid at B = 8: the same screen with   */
+                            /* FP16 normalized domains (one pass), exact decisions. One  */
+                            /* or two values at B = 4, 8 or 16 (centred operands, FP32   */
+                            /* accumulation exact: partial sums are integers below      */
+                            /* 2^24): F exact in 32/64-bit integers; AUTO takes it there */
 };
 
 /*

@@ -361,7 +361,7 @@ bool mfq_eligible(int B, const KSet& ks, int64_t total = 0) {
 
 // Matcher a level gets by default.
 int auto_var(int B, const KSet& ks, int64_t total) {
-    if (mfma_eligible(B, ks, total)) return kVarMfma16;
+    if (mfma_eligible(B, ks, total)) return kVarMfma;
     if (mfq_eligible(B, ks, total)) return kVarMfq;
     return kVarValu;
 }
