@@ -221,13 +221,39 @@ def roofline_from_profile(prof, per_label_ops, steps=None):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
 
 
+def _strip_comments(src: str) -> str:
+    """C++ source without its comments and with whitespace runs collapsed (string and
+    character literals kept as they are)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c == "/" and src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif c == "/" and src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_digest() -> str:
-    """Digest of the kernel sources; traffic counters only apply to the kernels they were taken on."""
+    """Digest of the kernel sources' code (comments and layout left out); traffic counters
+    only apply to the kernels they were taken on."""
     import hashlib
     h = hashlib.sha1()
     for name in ("fic_kernels.hip", "fic_mlp_kernels.hip", "fic_persist.hip"):
-        with open(os.path.join(ROOT, "paper_1501_04140_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1501_04140_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(_strip_comments(f.read()).encode())
     return h.hexdigest()[:12]
 
 

@@ -1885,26 +1885,18 @@ __device__ inline void lex_min_shfl(int64_t& F, int64_t& K, int mask) {
 }
 
 // grid: x = workgroups of m8_rows rows, y = pool chunks. The contrast set is
-// k = 0..k1. Each wavefront keeps kM8WaveRows rows; each lane holds 4 rows x 1
+// k = 0..k1. Each wavefront keeps 16 RT rows; each lane holds 4 rows x 1
 // column of every 16x16 output tile: lane group g = lane / 16 holds rows
 // 4g..4g+3 of a tile, so groups g and g ^ 1 hold the 8 rows of one range.
 // Screen: for any k, F = k^2 A' - 80 k B' is at least the continuous minimum
 // -1600 B'^2 / A', so an element can match or beat a best F_b <= 0 only if
 // B' >= s_b sqrt(A'), s_b = sqrt(-F_b / 1600). A range's code is the minimum
 // over its 8 rows, so every row is screened against the smallest F_b among its
-// range's rows (the largest s_b). The int8 form bounds its MFMA output X
-// (B' = 64 X - (sum r') S) in FP32 by
-//   U~ = s_b (Q / 64) + (sum r') (S / 64) - 8,   Q = sqrt(A') (1 - 2^-18),
-// whose roundings stay below 2.5, so U~ <= U - 5.5 for the exact
-// U = (s_b sqrt(A') + (sum r') S) / 64, and X >= U~ keeps every element with
-// X >= U (X is an integer below 2^24, exact in FP32). The bound is not strict,
-// so ties stay candidates. A constant domain (A' = 0, so B' = 0 and F = 0:
-// never an improvement) has 2^100 in place of -8.
-// Per 16-column tile a lane compares the largest of its 4 elements of each row
-// tile, and the wavefront takes the tile's slow path only when some lane
-// passes: there each element is compared, and candidates go to a
-// per-wavefront queue in LDS, decided exactly in int64, one per lane (the FP32
-// k corrected by one step).
+// range's rows (the largest s_b), rounded below. The bound is not strict, so
+// ties stay candidates. How the matchers evaluate it on normalized columns is
+// described with them below. Candidates go to a per-wavefront queue in LDS and
+// are decided exactly in int64, one per lane (the FP32 k corrected by one
+// step).
 // F = 0 never improves a row: its best starts at (F = 0, the chunk's first
 // position, k = 0) and positions only grow. So a row of a constant range
 // (C = 0, hence B' = 0 and F >= 0 everywhere) and a padded row start from the
@@ -1949,11 +1941,12 @@ __device__ inline void m8_decide(int row, int pos, int X, const int32_t* nsr, ui
 // ================================================================ MFMA grid matchers, normalized screen (B = 8)
 // The grid matchers screen on normalized operands. Each pool domain's column
 // holds d^_i = (64 d'_i - S) s with s = 1 / Q (FP16 form) or 4079 / Q (int8
-// form, rounded to integers below 2^15 and split as 256 h + l, both int8), Q =
-// sqrt(A') rounded below (s = 0 for a constant domain). The FP16 form's rows
-// are r^ = r' - c, c the range's mean of r' rounded (exact in FP16: |r^| <=
-// 255); the int8 form's rows are r' itself. In exact arithmetic
-//   X^ = sum r_i d^_i = s (64 sum r' d' - S sum r') = s B'
+// form, rounded to integers: |d^| <= 4079 sqrt(63) < 2^15, split as 256 h + l
+// with h, l in -128..127), Q = sqrt(A') rounded below (s = 0 for a constant
+// domain). The rows are r^ = r' - c with c the range's mean of r' rounded
+// (FP16: |r^| <= 255, exact), for int8 moved into [max r' - 127, min r' + 128]
+// so that every r^ fits in int8. In exact arithmetic
+//   X^ = sum r^_i d^_i = s (64 sum r' d' - S sum r') = s B'
 // (the d^ of a column sum to zero, so a shift of the rows changes nothing),
 // and an element can match or beat a range's best F_b <= 0, which needs
 // B' >= s_b sqrt(A'), only if X^ >= s_b s sqrt(A') >= s_b (FP16) or 4079 s_b
@@ -1963,18 +1956,22 @@ __device__ inline void m8_decide(int row, int pos, int X, const int32_t* nsr, ui
 //    move it by at most 2^-10.99 ||r^|| ||d^|| + 2^-25 sum |r^| with ||d^|| = 8
 //    sqrt(A') / Q, about 8, and the FP32 accumulation of 64 products and the
 //    start value by below 0.3: E = ||r^|| / 120 + 0.5;
-//  * int8: the rounding to integers moves each d^ by at most 0.5 (plus 2^-23
-//    of it from the FP32 product), so E = 0.5 sum |r'| + 2^-23 ||r'|| 8 * 4079
-//    <= 4.02 ||r'|| + 2 (sum |r'| <= 8 ||r'||); the int32 sums are exact.
-// The bound enters the accumulators: the FP16 form's start at 2^15 - (s_b - E)
-// and hold 2^15 + X^ - (s_b - E) in (0, 2^16) (|X^| <= 8 sqrt(A_r) / 8, s_b <=
-// sqrt(A_r) <= 8160), compared as FP32 bit patterns with that of 2^15
-// (positive floats order as their bit patterns); the int8 form's second MFMA
-// starts from 256 Xh - T, T = floor(4079 s_b - E), so the element is a
-// candidate iff the result is >= 0 (|values| < 2^29). The screen of a 16-column
-// tile is one maximum over the lane's 16 elements. Candidates are then decided
-// exactly from the integer data: X = sum r' d' (FP16 dot products of integers
-// with partial sums below 2^24, or int8 dot products).
+//  * int8: the rounding to integers moves each d^ by at most 0.5, the FP32
+//    arithmetic before it by below 0.01: E = 0.51 sum |r^| + 2; the int32 sums
+//    are exact.
+// The bound enters the accumulators. The FP16 form's start at 2^15 - (s_b - E)
+// and hold 2^15 + X^ - (s_b - E) in (0, 2^16) (|X^| and s_b are at most
+// sqrt(C) <= 8160), compared as FP32 bit patterns with that of 2^15 (positive
+// floats order as their bit patterns). The int8 form takes T = floor(4079 s_b
+// - E - 8) and screens in two steps: one MFMA over the h parts alone, started
+// at -Th with Th = ceil((T - 128 sum |r^|) / 256) (|sum r^ l| is at most 128
+// sum |r^|), rules a tile out when every Xh - Th < 0; a tile that passes is
+// redone with its second MFMA started at 256 Xh - T, and an element is a
+// candidate iff the result is >= 0 (|values| < 2^29). The screen of a
+// 16-column tile is one maximum over the lane's elements. Candidates are then
+// decided exactly from the integer data: X = sum r' d' (FP16 dot products of
+// integers with partial sums below 2^24), or int8 dot products of r^ with the
+// columns d' = 128 h + l, X = sum r^ d' + c S.
 // A pool stage (kM8Cols normalized columns) is copied from global memory
 // straight into LDS (global_load_lds, 16 bytes a lane, no registers on the
 // way) while the previous stage is matched: 8 chunks of 16 bytes per domain
@@ -2089,7 +2086,7 @@ __device__ __forceinline__ void k_match_grid_body(
     int32_t* nsr = sNsr[wave];
 
     // A operands: FP16 r^ = r' - c (c = the row's range mean of r', rounded), 8
-    // values of each K half; int8 r', 16 values
+    // values of each K half; int8 r^ as the rows were prepared, 16 values
     v8h af[RT][2];
     v4i a8[RT];
     float E[RT];    // error bound of X^ for the lane's output range
@@ -2151,8 +2148,8 @@ __device__ __forceinline__ void k_match_grid_body(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     // A first bound before the search: 4 tiles of 16 domains spread over the
     // chunk, decided exactly (FP16: X = sum r^ d' + c S, products of integers
-    // with partial sums below 64 * 255 * 1020 < 2^24; int8: X = 128 sum r' h +
-    // sum r' l). Without it every chunk would open with half of its first
+    // with partial sums below 64 * 255 * 1020 < 2^24; int8: X = 128 sum r^ h +
+    // sum r^ l + c S). Without it every chunk would open with half of its first
     // elements queued.
     if (lo < hi) {
 #pragma unroll 1
