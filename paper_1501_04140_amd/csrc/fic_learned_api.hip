@@ -14,7 +14,7 @@ struct fic_mlp {
     _Float16* w16 = nullptr;
     uint32_t* maxbits = nullptr;
     fic::Buf X, H1, H2, Y, G32, nrm, G16, Z, Pm, Pt, GDt, GRt, dG, dS, dY, D1, D2, T1, T2, part,
-        sums, loss, keys, cand, fbq, tmpm;
+        sums, loss, keys, cand, fbq, tmpm, tkgm, tkth, tkcnt;
 };
 
 namespace fic {
@@ -130,22 +130,32 @@ int block_rows(fic_mlp* M, const uint8_t* img, int H, int W, int pitch, int L,
     return FIC_OK;
 }
 
-// Top-k of GR [nq x 64] against GD [nk x 64] -> idx, score [nq x k]
+// Top-k of GR [nq x 64] against GD [nk x 64] -> idx, score [nq x k]: the key
+// norm bound, the group maxima, theta and delta, the lists, their merge.
 int topk_launch(fic_mlp* M, const _Float16* GR, int nq, const _Float16* GD, int nk, int k,
                 int32_t* idx, float* score, hipStream_t st) {
-    // domain segments only where the ranges alone leave SIMDs idle (2 waves
-    // per SIMD fill the chip): every segment restarts the running thresholds,
-    // so each one pays its own warm-up of appends and prunes
-    const int row_waves = cdiv(nq, kTkRows);
-    int nseg = std::max(1, std::min(16, cdiv(2048, row_waves)));
-    int seg_len = rup(cdiv(nk, nseg), 16);
-    seg_len = std::max(seg_len, 256);
-    nseg = cdiv(nk, seg_len);
-    int rc = mgrow(M->keys, (int64_t)nseg * nq * kTopK * 8);
-    if (rc) return rc;
-    uint64_t* keys = P<uint64_t>(M->keys);
-    k_topk_sim<<<dim3(cdiv(row_waves, kTkWaves), nseg), 256, 0, st>>>(GR, nq, GD, nk, seg_len, keys);
-    k_topk_merge<<<cdiv((int64_t)nq * 64, 256), 256, 0, st>>>(keys, nseg, nq, k, idx, score);
+    if (nq <= 0) return FIC_OK;
+    const int xb = cdiv(nq, kTkQ);
+    // about 1024 workgroups; chunks of at least one stage of keys
+    int nc = std::max(1, std::min(16, cdiv(1024, xb)));
+    nc = std::max(1, std::min(nc, nk / kM8Cols));
+    const int G = 16 * nc;
+    int rc;
+    if ((rc = mgrow(M->tkgm, (int64_t)nq * G * 4)) || (rc = mgrow(M->tkth, 256 + (int64_t)nq * 8)) ||
+        (rc = mgrow(M->keys, (int64_t)nc * nq * kTkCap * 8)) || (rc = mgrow(M->tkcnt, (int64_t)nc * nq * 4)))
+        return rc;
+    float* gm = P<float>(M->tkgm);
+    uint32_t* dn = P<uint32_t>(M->tkth);
+    float* th = reinterpret_cast<float*>(P<uint8_t>(M->tkth) + 256);
+    float* dl = th + nq;
+    uint64_t* list = P<uint64_t>(M->keys);
+    int32_t* cnt = P<int32_t>(M->tkcnt);
+    k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(dn), 1, 0);
+    if (nk > 0) k_tk_keynorm<<<std::min(1024, cdiv((int64_t)nk * 8, 256)), 256, 0, st>>>(GD, nk, dn);
+    k_tk_max<<<dim3(xb, nc), kTkWaves * 64, 0, st>>>(GR, nq, GD, nk, gm);
+    k_tk_theta<<<cdiv((int64_t)nq * 64, 256), 256, 0, st>>>(gm, nq, G, GR, dn, th, dl);
+    k_tk_collect<<<dim3(xb, nc), kTkWaves * 64, 0, st>>>(GR, nq, GD, nk, th, dl, list, cnt);
+    k_tk_merge<<<cdiv((int64_t)nq * 64, 256), 256, 0, st>>>(list, cnt, nc, nq, k, idx, score);
     LAUNCH_CHECK();
     return FIC_OK;
 }
@@ -305,7 +315,8 @@ FIC_API int fic_mlp_destroy(fic_mlp* M) {
         if (p) (void)hipFree(p);
     fic::Buf* bufs[] = {&M->X, &M->H1, &M->H2, &M->Y, &M->G32, &M->nrm, &M->G16, &M->Z, &M->Pm, &M->Pt,
                         &M->GDt, &M->GRt, &M->dG, &M->dS, &M->dY, &M->D1, &M->D2, &M->T1, &M->T2,
-                        &M->part, &M->sums, &M->loss, &M->keys, &M->cand, &M->fbq, &M->tmpm};
+                        &M->part, &M->sums, &M->loss, &M->keys, &M->cand, &M->fbq, &M->tmpm,
+                        &M->tkgm, &M->tkth, &M->tkcnt};
     for (fic::Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     delete M;

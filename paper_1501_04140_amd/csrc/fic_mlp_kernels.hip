@@ -583,11 +583,32 @@ __global__ __launch_bounds__(256) void k_weights16(const float* __restrict__ w, 
 }
 
 // ---------------------------------------------------------------- top-k similarity
+// The k best keys of each query by the dot product of fp16 rows, accumulated
+// in fp32 by two v_mfma_f32_16x16x32_f16 from a zero accumulator (K = 0..31,
+// then 32..63): every pass computes an element's score this same way, so all
+// passes see the same value for it. Two passes over the keys, split into nc
+// chunks:
+//  1. per query, the largest score of each group of keys, a group being the
+//     keys of one chunk and one column lane (index mod 16 within the chunk's
+//     64-key stages): 16 nc disjoint groups. Each maximum is the score of a
+//     key of its group, so at least 32 keys score at least theta, the 32nd
+//     largest maximum (of the lanes' maxima when there are more than 64
+//     groups; -inf with fewer than 32): no key scoring below theta is among
+//     the best 32;
+//  2. the keys scoring at least theta: a screen on the MFMA output started at
+//     delta - theta (delta above the roundings that this start adds, so no
+//     such key is screened out), then the passing elements recomputed from a
+//     zero accumulator and kept in a list per (query, chunk) when their key
+//     (score, then lower index) is above the list's threshold. A list that
+//     could overflow keeps its best 32 and takes the 32nd as its threshold.
+// A merge sorts each query's lists. With theta near the 32nd best score a
+// query keeps a few dozen keys; a running top-32 admits every key that beats
+// the keys seen before it, hundreds per query.
 constexpr int kTopK = 32;    // largest proposal count
-constexpr int kTkRows = 32;  // ranges per wave
-constexpr int kTkCap = 64;   // candidate slots per range
-constexpr int kTkWaves = 4;
-constexpr int kTkAhead = 4;  // groups of 16 domains in flight per wave
+constexpr int kTkRT = 4;     // 16-row tiles per wave: 64 queries
+constexpr int kTkWaves = 4;  // waves per workgroup
+constexpr int kTkQ = kTkWaves * 16 * kTkRT;
+constexpr int kTkCap = 48;   // list slots per (query, chunk)
 
 // Ordered key: larger key = larger score, then lower domain index.
 __device__ inline uint64_t tk_key(float s, int d) {
@@ -644,171 +665,403 @@ __device__ inline uint64_t wave_sort_desc(uint64_t v, int lane) {
     return v;
 }
 
-// Keep the 32 best of a range's slots; its threshold becomes the 32nd best
-// score (none while fewer than 32 are held).
-__device__ inline void tk_merge_row(uint64_t* buf, int* cnt, float* thr, int lane) {
-    const int c = *cnt;
-    uint64_t v = lane < c ? buf[lane] : 0ull;
-    v = wave_sort_desc(v, lane);
-    wave_lds_sync();
-    if (lane < kTopK) buf[lane] = v;
-    if (lane == kTopK - 1) *thr = c >= kTopK ? tk_score(v) : -INFINITY;
-    if (lane == 0) *cnt = min(c, kTopK);
-    wave_lds_sync();
+// Ordered bits of a score (the high word of its key).
+__device__ inline uint32_t tk_ord(float s) {
+    const uint32_t u = __float_as_uint(s);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Each wave scores 32 ranges against the domains of one segment with MFMA and
-// keeps, per range, every score above the range's running threshold in LDS;
-// the slots are pruned back to the best 32 before they can overflow. Exact:
-// a domain is dropped only when 32 domains of lower index score at least as
-// high. Output: the segment's best 32 keys per range, descending (0 = none).
-__global__ __launch_bounds__(256) void k_topk_sim(const _Float16* __restrict__ GR, int nr,
-                                                  const _Float16* __restrict__ GD, int nd,
-                                                  int seg_len, uint64_t* __restrict__ out) {
-    __shared__ uint64_t sbuf[kTkWaves][kTkRows][kTkCap];
-    __shared__ int scnt[kTkWaves][kTkRows];
-    __shared__ float sthr[kTkWaves][kTkRows];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r0 = (blockIdx.x * kTkWaves + wave) * kTkRows;
-    if (r0 >= nr) return;
-    const int seg = blockIdx.y;
-    const int d_lo = seg * seg_len, d_hi = min(nd, d_lo + seg_len);
-    if (lane < kTkRows) {
-        scnt[wave][lane] = 0;
-        sthr[wave][lane] = -INFINITY;
-    }
-    wave_lds_sync();
-    const int kq = (lane >> 4) * 8;
-    h8 a[2][2];
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Shared by the two passes: the query rows as A operands, the stage copies
+// and the tiles. grid: x = blocks of kTkQ queries, y = key chunks; the keys of
+// a chunk stream through LDS in stages of kM8Cols (64) rows, copied straight
+// from global memory as the MFMA grid matchers copy their columns (the same
+// swizzled 16-byte chunks).
+constexpr int kTkLoads = kM8Cols * 8 / (kTkWaves * 64);
+static_assert(kTkWaves * kTkLoads * 64 == kM8Cols * 8, "a stage is whole 16-byte chunks per lane");
+
+struct TkWave {
+    int nq, lo, hi, wave, lane, g, c16, wq0;
+    h8 af[kTkRT][2];
+    uint32_t off[kTkLoads];  // byte offsets of a full stage's chunks, from the stage's first key
+};
+
+__device__ __forceinline__ bool tk_setup(TkWave& w, const _Float16* __restrict__ GR, int nq, int nk) {
+    const int q0 = blockIdx.x * kTkQ;
+    if (q0 >= nq) return false;
+    const int nc = gridDim.y, c = blockIdx.y;
+    w.nq = nq;
+    w.lo = (int)((int64_t)nk * c / nc);
+    w.hi = (int)((int64_t)nk * (c + 1) / nc);
+    w.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    w.lane = threadIdx.x & 63;
+    w.g = w.lane >> 4;
+    w.c16 = w.lane & 15;
+    w.wq0 = q0 + w.wave * 16 * kTkRT;
+    // query rows past the end read the last row and are never written
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        const _Float16* pa = GR + (int64_t)min(r0 + 16 * rt + (lane & 15), nr - 1) * 64 + kq;
-        a[rt][0] = *reinterpret_cast<const h8*>(pa);
-        a[rt][1] = *reinterpret_cast<const h8*>(pa + 32);
+    for (int rt = 0; rt < kTkRT; ++rt) {
+        const _Float16* pa = GR + (int64_t)min(w.wq0 + 16 * rt + w.c16, nq - 1) * 64 + 8 * w.g;
+        w.af[rt][0] = *reinterpret_cast<const h8*>(pa);
+        w.af[rt][1] = *reinterpret_cast<const h8*>(pa + 32);
     }
-    // running thresholds and slot counts of this lane's 8 rows (rows 16 rt +
-    // 4 g + e); +inf thresholds for rows past the end, so their scores never pass
-    const int g = lane >> 4, cl = lane & 15;
-    const uint32_t below = (1u << cl) - 1u;
-    bool rowok[2][4];
-    float th[2][4];
-    int cnt[2][4];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int l = 0; l < kTkLoads; ++l) {
+        const int i = (kTkLoads * w.wave + l) * 64 + w.lane, col = i >> 3, u = (i & 7) ^ ((col >> 1) & 7);
+        w.off[l] = (uint32_t)(col * 128 + 16 * u);
+    }
+    return true;
+}
+
+// Copy keys b0 .. b0 + n - 1 (n <= kM8Cols; rows past n copy row n - 1) into dD.
+__device__ __forceinline__ void tk_stage_copy(const TkWave& w, const _Float16* __restrict__ GD, v4i* dD, int b0,
+                                              int n) {
+    // the same in every lane: read from the first so that they sit in SGPRs
+    const uint64_t bu = (uint64_t)(uintptr_t)(reinterpret_cast<const int8_t*>(GD) + (int64_t)b0 * 128);
+    const void* base = (const void*)(uintptr_t)(
+        ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bu >> 32)) << 32) |
+        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bu));
+#pragma unroll
+    for (int l = 0; l < kTkLoads; ++l) {
+        const uint32_t o =
+            n == kM8Cols ? w.off[l] : (uint32_t)(min((int)(w.off[l] >> 7), n - 1) * 128) + (w.off[l] & 127u);
+        const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)(
+            (const __attribute__((address_space(3))) void*)(dD + (kTkLoads * w.wave + l) * 64)));
+        m8_copy_to_lds(base, o, (const __attribute__((address_space(3))) void*)(uintptr_t)la);
+    }
+}
+
+__device__ __forceinline__ void tk_wait_copies() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// One 16-key tile (ct) for every row tile, the accumulators started at c0.
+__device__ __forceinline__ void tk_tile(const TkWave& w, const v4i* cD, int ct, const f4 (&c0)[kTkRT],
+                                        f4 (&acc)[kTkRT]) {
+    const int col = 16 * ct + w.c16;
+    const h8 b0 = __builtin_bit_cast(h8, cD[m8_chunk(col, w.g)]);
+    const h8 b1 = __builtin_bit_cast(h8, cD[m8_chunk(col, 4 + w.g)]);
+#pragma unroll
+    for (int rt = 0; rt < kTkRT; ++rt) {
+        acc[rt] = mfma16(w.af[rt][0], b0, c0[rt]);
+        acc[rt] = mfma16(w.af[rt][1], b1, acc[rt]);
+    }
+}
+
+// The chunk's stages, double-buffered: fn(buffer, first key, parity) on each
+// while the next one is copied in.
+template <class Fn>
+__device__ __forceinline__ void tk_stages(const TkWave& w, const _Float16* __restrict__ GD, v4i (*sD)[kM8Cols * 8],
+                                          Fn&& fn) {
+    tk_wait_copies();
+    if (w.lo < w.hi) {
+        tk_stage_copy(w, GD, sD[0], w.lo, min(kM8Cols, w.hi - w.lo));
+        tk_wait_copies();
+    }
+    __syncthreads();
+    for (int base = w.lo; base < w.hi; base += 2 * kM8Cols) {
+        int nb = base + kM8Cols;
+        if (nb < w.hi) tk_stage_copy(w, GD, sD[1], nb, min(kM8Cols, w.hi - nb));
+        fn(sD[0], base, 0);
+        tk_wait_copies();
+        __syncthreads();
+        if (nb >= w.hi) break;
+        const int b1 = nb;
+        nb = b1 + kM8Cols;
+        if (nb < w.hi) tk_stage_copy(w, GD, sD[0], nb, min(kM8Cols, w.hi - nb));
+        fn(sD[1], b1, 1);
+        tk_wait_copies();
+        __syncthreads();
+    }
+}
+
+// Pass 1: GM [nq][16 nc], the largest score of each (chunk, column lane)
+// group of keys per query (-inf for an empty group).
+__global__ __launch_bounds__(kTkWaves * 64) void k_tk_max(const _Float16* __restrict__ GR, int nq,
+                                                          const _Float16* __restrict__ GD, int nk,
+                                                          float* __restrict__ GM) {
+    __shared__ v4i sD[2][kM8Cols * 8];
+    TkWave w;
+    if (!tk_setup(w, GR, nq, nk)) return;
+    constexpr int RT = kTkRT;
+    const f4 zero[RT] = {};
+    float m[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m[rt][e] = -INFINITY;
+    // fold a stage into m, two tiles at a time (keys past the chunk's end count as -inf)
+    tk_stages(w, GD, sD, [&](const v4i* cD, int base, int) {
+        const bool tail = base + kM8Cols > w.hi;
+#pragma unroll
+        for (int ct = 0; ct < kM8ColTiles; ct += 2) {
+            f4 x0[RT], x1[RT];
+            tk_tile(w, cD, ct, zero, x0);
+            tk_tile(w, cD, ct + 1, zero, x1);
+            if (tail) {
+                const bool ok0 = base + 16 * ct + w.c16 < w.hi, ok1 = base + 16 * ct + 16 + w.c16 < w.hi;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        x0[rt][e] = ok0 ? x0[rt][e] : -INFINITY;
+                        x1[rt][e] = ok1 ? x1[rt][e] : -INFINITY;
+                    }
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) m[rt][e] = fmaxf(fmaxf(m[rt][e], x0[rt][e]), x1[rt][e]);
+        }
+    });
+    const int c = blockIdx.y, G = 16 * gridDim.y;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            rowok[rt][e] = r0 + 16 * rt + 4 * g + e < nr;
-            th[rt][e] = rowok[rt][e] ? -INFINITY : INFINITY;
-            cnt[rt][e] = 0;
+            const int q = w.wq0 + 16 * rt + 4 * w.g + e;
+            if (q < nq) GM[(int64_t)q * G + 16 * c + w.c16] = m[rt][e];
         }
+}
 
-    // domain fragments: a ring of kTkAhead groups of 16 columns, each loaded
-    // kTkAhead groups before its use (the loads' latency hides behind the
-    // work). A slot is refilled only after the MFMAs have read it, so the ring
-    // needs no register copies (a copy would wait for the load in flight).
-    // Groups past the segment's end (at most kTkAhead - 1) read clamped,
-    // in-bounds columns and keep nothing.
-    h8 rb0[kTkAhead], rb1[kTkAhead];
-    auto fetch = [&](int d, h8& x0, h8& x1) {
-        const _Float16* pb = GD + (int64_t)min(d + (lane & 15), nd - 1) * 64 + kq;
-        x0 = *reinterpret_cast<const h8*>(pb);
-        x1 = *reinterpret_cast<const h8*>(pb + 32);
+// Pass 2: per (query, chunk) the list [kTkCap] of keys scoring at least
+// theta, and its count.
+__global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const _Float16* __restrict__ GR, int nq,
+                                                              const _Float16* __restrict__ GD, int nk,
+                                                              const float* __restrict__ th_in,
+                                                              const float* __restrict__ dl_in,
+                                                              uint64_t* __restrict__ list,
+                                                              int32_t* __restrict__ lcount) {
+    constexpr int RT = kTkRT, WR = 16 * RT;
+    static_assert(WR == 64, "one query per lane in the list bookkeeping");
+    __shared__ v4i sD[2][kM8Cols * 8];
+    __shared__ uint64_t sThr[kTkWaves][WR];  // keys above this enter the query's list
+    __shared__ __align__(16) float sTf[kTkWaves][WR];  // its score
+    __shared__ float sDl[kTkWaves][WR];      // screen slack delta
+    __shared__ __align__(16) float sCs[kTkWaves][WR];  // screen start: delta - (threshold score)
+    __shared__ int32_t sCnt[kTkWaves][WR];
+    // list entries on their way to global memory: stored in batches, because
+    // the wait for a stage's copy would also wait for every store before it
+    constexpr int kQ = 128;
+    __shared__ uint32_t sQi[kTkWaves][kQ];  // list position (row * kTkCap + slot)
+    __shared__ uint64_t sQk[kTkWaves][kQ];  // key
+    TkWave w;
+    if (!tk_setup(w, GR, nq, nk)) return;
+    const int c = blockIdx.y, wave = w.wave, lane = w.lane, g = w.g, c16 = w.c16;
+    {
+        const int q = w.wq0 + lane;
+        const float t = q < nq ? th_in[q] : INFINITY;
+        const float d = q < nq ? dl_in[q] : 0.0f;
+        // keys of scores >= t: ord(t) << 32 and above; none for padded rows
+        sThr[wave][lane] = q < nq ? ((uint64_t)tk_ord(t) << 32) - 1u : ~0ull;
+        sTf[wave][lane] = t;
+        sDl[wave][lane] = d;
+        sCs[wave][lane] = d - t;
+        sCnt[wave][lane] = 0;
+    }
+    wave_lds_sync();
+    const f4 zero[RT] = {};
+    f4 cs[RT], tf[RT];  // per row 16 rt + 4 g + e: the screen start, the threshold score
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        cs[rt] = *reinterpret_cast<const f4*>(&sCs[wave][16 * rt + 4 * g]);
+        tf[rt] = *reinterpret_cast<const f4*>(&sTf[wave][16 * rt + 4 * g]);
+    }
+    uint64_t* wlist = list + ((int64_t)c * nq + w.wq0) * kTkCap;
+    const uint32_t below = (1u << c16) - 1u;
+    int qn = 0;  // queued list entries (the same in every lane)
+    auto flush = [&] {
+        wave_lds_sync();
+        for (int j = lane; j < qn; j += 64) wlist[sQi[wave][j]] = sQk[wave][j];
+        qn = 0;
+        wave_lds_sync();
     };
-#pragma unroll
-    for (int i = 0; i < kTkAhead; ++i) fetch(d_lo + 16 * i, rb0[i], rb1[i]);
-    for (int dg = d_lo; dg < d_hi; dg += 16 * kTkAhead)
-#pragma unroll
-    for (int it = 0; it < kTkAhead; ++it) {
-        const int d0 = dg + 16 * it;
-        const int dcol = d0 + (lane & 15);
-        const bool colok = dcol < d_hi;
-        f4 acc[2];
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-            acc[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            acc[rt] = mfma16(a[rt][0], rb0[it], acc[rt]);
-            acc[rt] = mfma16(a[rt][1], rb1[it], acc[rt]);
+    // the rows whose list could overflow keep their best 32
+    auto prune = [&] {
+        flush();
+        const int nl = sCnt[wave][lane];
+        uint64_t need = __ballot(nl > kTkCap - 16);
+        tk_wait_copies();  // this wave's list stores have landed
+        while (need) {
+            const int i = __ffsll((unsigned long long)need) - 1;
+            need &= need - 1;
+            const int n = __shfl(nl, i, 64);
+            uint64_t* L = wlist + (int64_t)i * kTkCap;
+            // read from L2, past this CU's vector cache
+            uint64_t v = lane < n ? __hip_atomic_load(L + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+            v = wave_sort_desc(v, lane);
+            if (lane < kTopK) L[lane] = v;
+            const uint64_t t = shfl_u64(v, kTopK - 1);
+            if (lane == 0) {
+                sCnt[wave][i] = kTopK;
+                sThr[wave][i] = t;
+                sTf[wave][i] = tk_score(t);
+                sCs[wave][i] = sDl[wave][i] - tk_score(t);
+            }
         }
-        fetch(d0 + 16 * kTkAhead, rb0[it], rb1[it]);
-        bool hit = false;
+        wave_lds_sync();
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < RT; ++rt) {
+            cs[rt] = *reinterpret_cast<const f4*>(&sCs[wave][16 * rt + 4 * g]);
+            tf[rt] = *reinterpret_cast<const f4*>(&sTf[wave][16 * rt + 4 * g]);
+        }
+    };
+    // a stage: the screen of every tile without a branch (one maximum per
+    // lane, one ballot: a bit per tile with a passing element; a branch per
+    // tile would keep the next tile's LDS reads from being issued early),
+    // then the flagged tiles from a zero accumulator, their elements above
+    // the threshold listed. (LDS operations of one wave take effect in program
+    // order, so the counts and thresholds need no fence here.)
+    tk_stages(w, GD, sD, [&](const v4i* cD, int base, int) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) hit |= acc[rt][e] > th[rt][e];
-        // once the thresholds have risen most groups hold no passing score:
-        // the appends and the slot check run only when one does
-        if (!__ballot(colok && hit)) continue;
-        // row (rt, e) of lane group g sits in lanes [16g, 16g + 16), one column
-        // per lane: a passing lane's slot is the row's count plus the passing
-        // lanes below it in that segment of the ballot
-        bool full = false;
+        for (int rt = 0; rt < RT; ++rt) asm volatile("" : "+v"(cs[rt]), "+v"(tf[rt]));
+        uint32_t hits = 0;  // bit 4 ct + rt: row tile rt of tile ct has a passing element
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int ct = 0; ct < kM8ColTiles; ++ct) {
+            f4 acc[RT];
+            tk_tile(w, cD, ct, cs, acc);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float s = acc[rt][e];
-                const bool p = colok && s > th[rt][e];
-                const uint64_t bal = __ballot(p);
-                if (!bal) continue;  // most element slots of a group append nothing
-                const uint32_t seg = (uint32_t)(bal >> (16 * g)) & 0xffffu;
-                if (p) sbuf[wave][16 * rt + 4 * g + e][cnt[rt][e] + __popc(seg & below)] = tk_key(s, dcol);
-                cnt[rt][e] += __popc(seg);
-                full |= cnt[rt][e] > kTkCap - 16;
+            for (int rt = 0; rt < RT; ++rt) {
+                const float m = fmaxf(fmaxf(fmaxf(acc[rt][0], acc[rt][1]), acc[rt][2]), acc[rt][3]);
+                hits |= __ballot(m >= 0.0f) ? 1u << (RT * ct + rt) : 0u;
             }
-        if (__ballot(full)) {
-            // publish the counts, prune the rows that could overflow on the
-            // next group, then take back their counts and thresholds
-            if (cl == 0)
+        }
+        if (!hits) return;
+        while (hits) {
+            const int ct = (__builtin_ffs(hits) - 1) / RT;
+            const uint32_t rts = (hits >> (RT * ct)) & ((1u << RT) - 1u);
+            hits &= ~(((1u << RT) - 1u) << (RT * ct));
+            const int col = 16 * ct + c16;
+            const h8 b0 = __builtin_bit_cast(h8, cD[m8_chunk(col, g)]);
+            const h8 b1 = __builtin_bit_cast(h8, cD[m8_chunk(col, 4 + g)]);
+            const int kc = base + col;
+            const bool colok = kc < w.hi;
+            bool full = false;
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) scnt[wave][16 * rt + 4 * g + e] = cnt[rt][e];
-            wave_lds_sync();
-            const int c = lane < kTkRows ? scnt[wave][lane] : 0;
-            uint64_t need = __ballot(c > kTkCap - 16);
-            while (need) {
-                const int row = __ffsll((unsigned long long)need) - 1;
-                need &= need - 1;
-                tk_merge_row(sbuf[wave][row], &scnt[wave][row], &sthr[wave][row], lane);
-            }
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < RT; ++rt) {
+                if (!(rts & (1u << rt))) continue;
+                f4 x = mfma16(w.af[rt][0], b0, zero[rt]);
+                x = mfma16(w.af[rt][1], b1, x);
+                // a float compare with the threshold score first (a superset
+                // of the key compare), the key compare for the few that pass
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    cnt[rt][e] = scnt[wave][16 * rt + 4 * g + e];
-                    th[rt][e] = rowok[rt][e] ? sthr[wave][16 * rt + 4 * g + e] : INFINITY;
+                    if (!__ballot(colok && x[e] >= tf[rt][e])) continue;
+                    const int i = 16 * rt + 4 * g + e;
+                    const uint64_t thr = sThr[wave][i];
+                    const int n = sCnt[wave][i];
+                    const bool p = colok && x[e] >= tf[rt][e] && tk_key(x[e], kc) > thr;
+                    const uint64_t bal = __ballot(p);
+                    if (!bal) continue;
+                    const uint32_t seg = (uint32_t)(bal >> (16 * g)) & 0xffffu;
+                    if (p) {
+                        const int qp = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        sQi[wave][qp] = (uint32_t)(i * kTkCap + n + __popc(seg & below));
+                        sQk[wave][qp] = tk_key(x[e], kc);
+                    }
+                    qn += __popcll(bal);
+                    if (c16 == 0) sCnt[wave][i] = n + __popc(seg);
+                    full |= n + __popc(seg) > kTkCap - 16;
+                    if (qn > kQ - 64) flush();
                 }
+            }
+            if (__ballot(full)) prune();
         }
+    });
+    flush();
+    if (w.wq0 + lane < nq) lcount[(int64_t)c * nq + w.wq0 + lane] = sCnt[wave][lane];
+}
+
+// The largest squared L2 norm of the key rows, as float bits (non-negative
+// floats order as unsigned integers), rounded up: the fp32 sum of 64 squares
+// is within 64 ulps, and 2^-16 is added. Eight lanes per key, 16 bytes each.
+// *out starts at 0.
+__global__ __launch_bounds__(256) void k_tk_keynorm(const _Float16* __restrict__ GD, int nk,
+                                                    uint32_t* __restrict__ out) {
+    float mx = 0.0f;
+    // lane groups of 8 take keys in turn (a key's 8 chunks at t .. t + 7, t = 8 key)
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < (int64_t)nk * 8; t += (int64_t)gridDim.x * 256) {
+        const h8 v = reinterpret_cast<const h8*>(GD)[t];
+        float s = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += (float)v[e] * (float)v[e];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        s += __shfl_xor(s, 4, 64);
+        mx = fmaxf(mx, s);
     }
-    if (cl == 0)
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) scnt[wave][16 * rt + 4 * g + e] = cnt[rt][e];
-    wave_lds_sync();
-    for (int row = 0; row < kTkRows && r0 + row < nr; ++row) {
-        const int c = scnt[wave][row];
-        uint64_t v = lane < c ? sbuf[wave][row][lane] : 0ull;
-        v = wave_sort_desc(v, lane);
-        if (lane < kTopK) out[((int64_t)seg * nr + r0 + row) * kTopK + lane] = v;
+    mx = wave_max_f32(mx * (1.0f + 1.0f / 65536.0f));
+    if ((threadIdx.x & 63) == 0 && mx > 0.0f) atomicMax(out, __float_as_uint(mx));
+}
+
+// Per query (one wave): theta, the 32nd largest group maximum (lane maxima
+// over groups lane, lane + 64, ... when there are more than 64; -inf when
+// fewer than 32 are finite), and the screen slack delta = 2^-15 (|theta| +
+// 2 |q| D), D the largest key norm. The screen's start delta - theta changes
+// the roundings of at most 65 additions of terms below |theta| + delta +
+// |q| D, and a score's own roundings stay within 64 ulps of |q| D: together
+// below 2^-17.9 (|theta| + delta + 2 |q| D) < delta.
+__global__ __launch_bounds__(256) void k_tk_theta(const float* __restrict__ GM, int nq, int G,
+                                                  const _Float16* __restrict__ GR,
+                                                  const uint32_t* __restrict__ dnorm2,
+                                                  float* __restrict__ theta, float* __restrict__ delta) {
+    const int q = (int)((blockIdx.x * 256u + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    float m = -INFINITY;
+    for (int j = lane; j < G; j += 64) m = fmaxf(m, GM[(int64_t)q * G + j]);
+    uint64_t v = wave_sort_desc((uint64_t)tk_ord(m) << 32, lane);
+    const float t = tk_score(shfl_u64(v, kTopK - 1));
+    const float x = (float)GR[(int64_t)q * 64 + lane];
+    const float qn = sqrtf(wave_sum_f32(x * x)) * (1.0f + 1.0f / 65536.0f);
+    if (lane == 0) {
+        theta[q] = t;
+        delta[q] = (fabsf(t) + 2.0f * qn * sqrtf(__uint_as_float(*dnorm2))) * (1.0f / 32768.0f);
     }
 }
 
-// Best k of the segments' lists per range (one wave per range).
-__global__ __launch_bounds__(256) void k_topk_merge(const uint64_t* __restrict__ keys, int nseg,
-                                                    int nr, int k, int32_t* __restrict__ idx,
-                                                    float* __restrict__ score) {
-    const int r = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
-    if (r >= nr) return;
-    uint64_t v = lane < kTopK ? keys[(int64_t)r * kTopK + lane] : 0ull;
-    for (int s = 1; s < nseg; ++s) {
-        if (lane >= kTopK) v = keys[((int64_t)s * nr + r) * kTopK + lane - kTopK];
+// Best k of a query's lists, best first (one wave per query): the lists'
+// entries in order, the first 64 sorted, then 32 at a time into the upper
+// lanes, sorted with the best 32 so far.
+__global__ __launch_bounds__(256) void k_tk_merge(const uint64_t* __restrict__ list,
+                                                  const int32_t* __restrict__ lcount, int nc, int nq, int k,
+                                                  int32_t* __restrict__ idx, float* __restrict__ score) {
+    const int q = (int)((blockIdx.x * 256u + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    // chunk counts in lanes 0..nc-1, their exclusive prefix sums
+    const int cn = lane < nc ? lcount[(int64_t)lane * nq + q] : 0;
+    int incl = cn;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    const int excl = incl - cn, total = __shfl(incl, 63, 64);
+    int start[16];  // first entry of each chunk (nc <= 16), in every lane
+#pragma unroll
+    for (int l = 0; l < 16; ++l) start[l] = __shfl(excl, l, 64);
+    auto fetch = [&](int p) -> uint64_t {  // entry p of the chunks' lists in order
+        int cc = 0, o = p;
+#pragma unroll
+        for (int l = 1; l < 16; ++l)
+            if (l < nc && start[l] <= p) {
+                cc = l;
+                o = p - start[l];
+            }
+        return list[((int64_t)cc * nq + q) * kTkCap + o];
+    };
+    uint64_t v = lane < total ? fetch(lane) : 0ull;
+    v = wave_sort_desc(v, lane);
+    for (int p = 64; p < total; p += 32) {
+        if (lane >= 32) v = p + lane - 32 < total ? fetch(p + lane - 32) : 0ull;
         v = wave_sort_desc(v, lane);
     }
     if (lane < k) {
-        idx[(int64_t)r * k + lane] = v ? tk_index(v) : -1;
-        if (score) score[(int64_t)r * k + lane] = v ? tk_score(v) : -INFINITY;
+        idx[(int64_t)q * k + lane] = v ? tk_index(v) : -1;
+        if (score) score[(int64_t)q * k + lane] = v ? tk_score(v) : -INFINITY;
     }
 }
 

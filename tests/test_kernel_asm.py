@@ -1,4 +1,6 @@
-"""Invariants of the MFMA grid matchers' machine code (CPU: hipcc cross-compiles).
+"""Invariants of the machine code of the kernels that copy global memory
+straight into LDS: the MFMA grid matchers and the two top-k passes (CPU: hipcc
+cross-compiles).
 
 Their stage copies are issued from inline assembly that writes m0, a register
 the compiler reserves and does not restore after inline assembly; the kernels
@@ -13,12 +15,14 @@ import pytest
 from paper_1501_04140_amd import build
 
 KERNELS = [f"fic::kt_match_mfma8<{f16}, {tab}>" for f16 in ("true", "false") for tab in ("true", "false")]
+TOPK = ["fic::k_tk_max", "fic::k_tk_collect"]
 
 
 def _device_asm(tmp_path) -> str:
     src = tmp_path / "m8.hip"
-    src.write_text("#include <hip/hip_runtime.h>\n#include \"fic_kernels.hip\"\n" +
-                   "".join(f"template __global__ void {k}(fic::Lvl, const fic::Lvl*);\n" for k in KERNELS))
+    src.write_text("#include <hip/hip_runtime.h>\n#include \"fic_kernels.hip\"\n#include \"fic_mlp_kernels.hip\"\n" +
+                   "".join(f"template __global__ void {k}(fic::Lvl, const fic::Lvl*);\n" for k in KERNELS) +
+                   "")
     out = tmp_path / "m8.s"
     cmd = [build.hipcc(), f"--offload-arch={build.ARCH}", "-O3", "-std=c++17", "--cuda-device-only", "-S",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form",
@@ -28,7 +32,7 @@ def _device_asm(tmp_path) -> str:
 
 
 def _bodies(asm: str):
-    for m in re.finditer(r"^(_ZN3fic14kt_match_mfma8\w*):", asm, re.M):
+    for m in re.finditer(r"^(_ZN3fic(?:14kt_match_mfma8\w*|8k_tk_max\w*|12k_tk_collect\w*)):", asm, re.M):
         end = asm.index("s_endpgm", m.end())
         yield m.group(1), asm[m.end():end]
 
@@ -38,7 +42,7 @@ def _bodies(asm: str):
 def test_m0_only_in_the_stage_copies(tmp_path):
     asm = _device_asm(tmp_path)
     bodies = list(_bodies(asm))
-    assert len(bodies) == len(KERNELS)
+    assert len(bodies) == len(KERNELS) + len(TOPK)
     for name, body in bodies:
         # the inline-assembly blocks with instructions (the others are empty
         # register pins): m0 set, then the copy that reads it
