@@ -614,17 +614,17 @@ def run_learned(args, torch):
     torch.cuda.synchronize()
     prof = fic.profile_end()
     nr, nd = 65536, 259081
-    # similarity top-k: a [ranges x 64] x [64 x domains] fp16 product, 2 flops per MAC
+    # similarity top-k: a [ranges x 64] x [64 x domains] int8 product, 2 ops per MAC
     roof = with_traffic(roofline_from_profile(
         {"learned_topk": prof["learned_topk"]},
-        {"learned_topk": (2 * 64 * nr * nd, "mfma", PEAK_FP16_TFLOPS, "TFLOP/s")}), "learned2048")
+        {"learned_topk": (2 * 64 * nr * nd, "mfma", PEAK_INT8_TOPS, "TOP/s")}), "learned2048")
 
     def mean(key, sub=None):
         return float(np.mean([r[key] if sub is None else r[key][sub] for r in rows]))
 
     res = {
         "metric": "learned-proposal encode of a 2048² image: ms, PSNR Δ vs exhaustive GPU search",
-        "dtype": "fp16 MFMA (f32 accumulate) proposals; u8 -> i64 exact rescoring",
+        "dtype": "fp16 network (f32 accumulate); int8 MFMA proposal scores (exact i32); u8 -> i64 exact rescoring",
         "value": nr / (mean("learned", "ms") / 1e3), "unit": "ranges/s",
         "encode_ms": mean("learned", "ms"),
         "exhaustive_ms": mean("t_exhaustive"),

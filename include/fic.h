@@ -451,7 +451,8 @@ int fic_batch_destroy(fic_batch* b);
  * and scaled to unit norm, zero for a constant block) as
  *     g(x) = S / |S|,  S = sum over the 8 isometries T_t of f(T_t x),
  * which is invariant under the isometries. The k domains whose embeddings
- * have the largest dot product with a range's are its proposals. They are
+ * are most similar to a range's (the integer dot product of their int8 codes,
+ * as fic_topk_similar defines it) are its proposals. They are
  * matched exactly (eq. (1) with the offset of eq. (3), all isometries and
  * contrast values, ties as in the exhaustive matcher). A range whose best
  * proposal fails the RMS test of Section 2 (E > rms^2 n) is matched against
@@ -505,10 +506,14 @@ int fic_mlp_train_step(fic_mlp* m, const uint8_t* img, int32_t H, int32_t W, int
                        int32_t n_ranges, float lr, float* loss_out, void* stream);
 /*
  * For each of nq query rows (device fp16 [nq][64], 16-byte aligned), the k
- * (1..32) key rows (device fp16 [nk][64]) with the largest dot products,
- * best first, ties to the lower key index: idx device int32 [nq][k], score
- * device float [nq][k] (may be NULL). Dot products accumulate in fp32.
- * m provides scratch space only.
+ * (1..32) key rows (device fp16 [nk][64], 16-byte aligned) with the largest
+ * similarity, best first, ties to the lower key index: idx device int32
+ * [nq][k] (-1 past nk), score device float [nq][k] (may be NULL; -inf past
+ * nk). The similarity is the dot product of int8 codes q = rint(x s), with
+ * one scale s = 127 / max |x| over the queries and the keys together (fp32
+ * arithmetic; s = 0 when every value is 0): an integer, returned exactly as a
+ * float. This is the proposal step of the learned form (an extension of the
+ * exhaustive search of Section 2). m provides scratch space only.
  */
 int fic_topk_similar(const uint16_t* q, int32_t nq, const uint16_t* keys, int32_t nk, int32_t k,
                      int32_t* idx, float* score, fic_mlp* m, void* stream);

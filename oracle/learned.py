@@ -20,8 +20,13 @@ the only library step):
   stored as in a linear map y = W x + b with W of shape (out, in);
 * embedding g(x) = S / |S| with S = sum over the 8 isometries T_t of f(T_t x)
   (0 if S = 0). Summing over the isometry group makes g invariant under them;
-* similarity of a range and a domain: the dot product of their embeddings;
-  proposal = the ``k`` most similar domains, ties to the lower domain index;
+* similarity of a range and a domain: the dot product of the int8 codes of
+  their embeddings, q = rint(x s) with one scale s = 127 / max |x| over the
+  ranges' and the domains' embeddings together, evaluated in fp32 (one
+  correctly rounded division, one rounded product per value, ties to even):
+  an integer. Proposal = the ``k`` most similar domains, ties to the lower
+  domain index. (The proposal is this extension's own choice; it does not
+  change what the exact rescoring and the fallback compute.);
 * training loss: mean over ranges of the softmax cross-entropy of the
   similarities / tau over all domains of the image, against the exhaustive
   argmin domain; gradients by hand-derived back-propagation;
@@ -173,9 +178,25 @@ def adam_step(theta, grad, m, v, step: int, lr: float, beta1: float = 0.9,
 
 
 # --------------------------------------------------------------------------- proposals
+def quantize(*sets):
+    """int8 codes (as int64 arrays) of embedding rows and their common scale:
+    q = rint(x s), s = 127 / max |x| over every value of every set (0 when all
+    are 0), in fp32 arithmetic."""
+    xs = [np.asarray(x, np.float32) for x in sets]
+    m = max((float(np.abs(x).max()) for x in xs if x.size), default=0.0)
+    s = np.float32(127.0) / np.float32(m) if m > 0 else np.float32(0.0)
+    return [np.rint(x * s).astype(np.int64) for x in xs], s
+
+
+def similarity(GR, GD) -> np.ndarray:
+    """Integer similarities [ranges, domains]: dot products of the int8 codes."""
+    (qr, qd), _ = quantize(GR, GD)
+    return qr @ qd.T
+
+
 def topk(GR, GD, k: int) -> np.ndarray:
-    """Indices of the k largest dot products per row, best first; ties to the lower index."""
-    S = np.asarray(GR, np.float64) @ np.asarray(GD, np.float64).T
+    """Indices of the k most similar domains per row, best first; ties to the lower index."""
+    S = similarity(GR, GD)
     k = min(k, S.shape[1])
     out = np.empty((S.shape[0], k), dtype=np.int32)
     cols = np.arange(S.shape[1])
@@ -222,6 +243,6 @@ def recall(proposals, labels) -> float:
     return float((proposals == labels).any(axis=1).mean())
 
 
-__all__ = ["N_PARAMS", "SHAPES", "unpack", "iso_perms", "block_vectors", "range_blocks",
+__all__ = ["N_PARAMS", "SHAPES", "unpack", "iso_perms", "block_vectors", "range_blocks", "quantize", "similarity",
            "domain_blocks", "mlp_forward", "embed", "loss_and_grad", "adam_step", "topk",
            "learned_match", "recall", "Q"]

@@ -14,7 +14,7 @@ struct fic_mlp {
     _Float16* w16 = nullptr;
     uint32_t* maxbits = nullptr;
     fic::Buf X, H1, H2, Y, G32, nrm, G16, Z, Pm, Pt, GDt, GRt, dG, dS, dY, D1, D2, T1, T2, part,
-        sums, loss, keys, cand, fbq, tmpm, tkgm, tkth, tkcnt;
+        sums, loss, keys, cand, fbq, tmpm, tkq, tkgm, tkth, tkcnt;
 };
 
 namespace fic {
@@ -77,8 +77,12 @@ int mlp_forward(fic_mlp* M, int nblk, bool keep, hipStream_t st) {
     if ((rc = mgrow(M->G16, (int64_t)nblk * 64 * 2))) return rc;
     if (!keep) {
         // no backward pass follows: the hidden layers and Y never leave the chip
-        k_mlp_forward<<<cdiv(rows, kFuseRows), 256, 0, st>>>(P<_Float16>(M->X), (int)rows, M->w16, M->w,
-                                                             P<_Float16>(M->G16));
+        // persistent: about one workgroup of 8 waves per CU
+        int cus = 0;
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, M->device));
+        const int tiles = (int)cdiv(rows, kFuseRows);
+        k_mlp_forward<<<std::max(1, std::min(tiles, cus)), kFuseWaves * 64, 0, st>>>(
+            P<_Float16>(M->X), (int)rows, M->w16, M->w, P<_Float16>(M->G16));
         LAUNCH_CHECK();
         return FIC_OK;
     }
@@ -130,31 +134,37 @@ int block_rows(fic_mlp* M, const uint8_t* img, int H, int W, int pitch, int L,
     return FIC_OK;
 }
 
-// Top-k of GR [nq x 64] against GD [nk x 64] -> idx, score [nq x k]: the key
-// norm bound, the group maxima, theta and delta, the lists, their merge.
+// Top-k of GR [nq x 64] against GD [nk x 64] -> idx, score [nq x k]: the
+// common scale and the int8 codes, the group maxima, theta, the lists, their
+// merge.
 int topk_launch(fic_mlp* M, const _Float16* GR, int nq, const _Float16* GD, int nk, int k,
                 int32_t* idx, float* score, hipStream_t st) {
     if (nq <= 0) return FIC_OK;
     const int xb = cdiv(nq, kTkQ);
     // about 1024 workgroups; chunks of at least one stage of keys
     int nc = std::max(1, std::min(16, cdiv(1024, xb)));
-    nc = std::max(1, std::min(nc, nk / kM8Cols));
+    nc = std::max(1, std::min(nc, nk / kTkCols));
     const int G = 16 * nc;
     int rc;
-    if ((rc = mgrow(M->tkgm, (int64_t)nq * G * 4)) || (rc = mgrow(M->tkth, 256 + (int64_t)nq * 8)) ||
-        (rc = mgrow(M->keys, (int64_t)nc * nq * kTkCap * 8)) || (rc = mgrow(M->tkcnt, (int64_t)nc * nq * 4)))
+    if ((rc = mgrow(M->tkq, 256 + ((int64_t)nq + nk) * 64)) || (rc = mgrow(M->tkgm, (int64_t)nq * G * 4)) ||
+        (rc = mgrow(M->tkth, (int64_t)nq * 4)) || (rc = mgrow(M->keys, (int64_t)nc * nq * kTkCap * 8)) ||
+        (rc = mgrow(M->tkcnt, (int64_t)nc * nq * 4)))
         return rc;
-    float* gm = P<float>(M->tkgm);
-    uint32_t* dn = P<uint32_t>(M->tkth);
-    float* th = reinterpret_cast<float*>(P<uint8_t>(M->tkth) + 256);
-    float* dl = th + nq;
+    uint32_t* mbits = P<uint32_t>(M->tkq);
+    int8_t* QR = P<int8_t>(M->tkq) + 256;
+    int8_t* QD = QR + (int64_t)nq * 64;
+    int32_t* gm = P<int32_t>(M->tkgm);
+    int32_t* th = P<int32_t>(M->tkth);
     uint64_t* list = P<uint64_t>(M->keys);
     int32_t* cnt = P<int32_t>(M->tkcnt);
-    k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(dn), 1, 0);
-    if (nk > 0) k_tk_keynorm<<<std::min(1024, cdiv((int64_t)nk * 8, 256)), 256, 0, st>>>(GD, nk, dn);
-    k_tk_max<<<dim3(xb, nc), kTkWaves * 64, 0, st>>>(GR, nq, GD, nk, gm);
-    k_tk_theta<<<cdiv((int64_t)nq * 64, 256), 256, 0, st>>>(gm, nq, G, GR, dn, th, dl);
-    k_tk_collect<<<dim3(xb, nc), kTkWaves * 64, 0, st>>>(GR, nq, GD, nk, th, dl, list, cnt);
+    const int64_t nr8 = (int64_t)nq * 8, nk8 = (int64_t)nk * 8;
+    k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(mbits), 1, 0);
+    k_tk_absmax<<<(int)std::min<int64_t>(1024, cdiv(nr8 + nk8, 256)), 256, 0, st>>>(GR, nr8 * 8, GD, nk8 * 8, mbits);
+    k_tk_quant<<<cdiv(nr8, 256), 256, 0, st>>>(GR, nr8, mbits, QR);
+    if (nk > 0) k_tk_quant<<<cdiv(nk8, 256), 256, 0, st>>>(GD, nk8, mbits, QD);
+    k_tk_max<<<dim3(xb, nc), kTkWaves * 64, 0, st>>>(QR, nq, QD, nk, gm);
+    k_tk_theta<<<cdiv((int64_t)nq * 64, 256), 256, 0, st>>>(gm, nq, G, th);
+    k_tk_collect<<<dim3(xb, nc), kTkWaves * 64, 0, st>>>(QR, nq, QD, nk, th, list, cnt);
     k_tk_merge<<<cdiv((int64_t)nq * 64, 256), 256, 0, st>>>(list, cnt, nc, nq, k, idx, score);
     LAUNCH_CHECK();
     return FIC_OK;
@@ -316,7 +326,7 @@ FIC_API int fic_mlp_destroy(fic_mlp* M) {
     fic::Buf* bufs[] = {&M->X, &M->H1, &M->H2, &M->Y, &M->G32, &M->nrm, &M->G16, &M->Z, &M->Pm, &M->Pt,
                         &M->GDt, &M->GRt, &M->dG, &M->dS, &M->dY, &M->D1, &M->D2, &M->T1, &M->T2,
                         &M->part, &M->sums, &M->loss, &M->keys, &M->cand, &M->fbq, &M->tmpm,
-                        &M->tkgm, &M->tkth, &M->tkcnt};
+                        &M->tkq, &M->tkgm, &M->tkth, &M->tkcnt};
     for (fic::Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     delete M;

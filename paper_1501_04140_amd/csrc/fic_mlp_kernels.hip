@@ -225,150 +225,157 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const _Float16* __restrict__ A,
 }
 
 // ---------------------------------------------------------------- fused forward
-// The whole network on a tile of 64 rows with the hidden layers in LDS only:
+// The whole network on tiles of 64 rows with the hidden layers in LDS only:
 // the encode path, which keeps no activations for a backward pass. The same
 // MFMAs in the same order as the three k_gemm_nt launches (16x16x32 over k in
 // ascending steps of 32 from zero) and the same epilogues, so Y is bit for
-// bit theirs. Layers 1 and 2: wave w computes columns [64 w, 64 w + 64) of all
-// 64 rows; layer 3: rows [16 w, 16 w + 16). Weight fragments come from L2,
-// the next k step's in flight during the current one. Rows past M read the
-// last row and are not stored. The 64 rows are 8 blocks of 8 isometry rows:
-// the layer-3 tile goes through LDS and each wave finishes two blocks' sums
-// and norms with the arithmetic of k_iso_norm, in the same order, so the
-// embeddings G16 are bit for bit those of k_iso_norm on Y.
+// bit theirs. A workgroup of 8 waves holds every weight fragment it uses in
+// registers for the whole launch (wave w: layer 1 and 2 columns [32 w, 32 w +
+// 32), layer 3 columns [16 (w & 3), + 16) for rows [32 (w >> 2), + 32)) and
+// walks over the row tiles, so the weights leave L2 once per workgroup rather
+// than once per tile; the next tile's rows are loaded while the current one
+// runs layers 2 and 3. Rows past M read the last row and are not stored. The
+// 64 rows are 8 blocks of 8 isometry rows: the layer-3 tile goes through LDS
+// and each wave finishes one block's sum and norm with the arithmetic of
+// k_iso_norm, in the same order, so the embeddings G16 are bit for bit those
+// of k_iso_norm on Y.
 constexpr int kFuseRows = 64;
+constexpr int kFuseWaves = 8;
 constexpr int kFuseLd = kMlpHid + 8;  // LDS row stride of a hidden layer in halves (16 bytes of padding)
 
-__global__ __launch_bounds__(256) void k_mlp_forward(const _Float16* __restrict__ X, int M,
-                                                     const _Float16* __restrict__ w16,
-                                                     const float* __restrict__ w,
-                                                     _Float16* __restrict__ G16) {
+__global__ __launch_bounds__(kFuseWaves * 64) void k_mlp_forward(const _Float16* __restrict__ X, int M,
+                                                                 const _Float16* __restrict__ w16,
+                                                                 const float* __restrict__ w,
+                                                                 _Float16* __restrict__ G16) {
     __shared__ __align__(16) _Float16 sH1[kFuseRows * kFuseLd];
     __shared__ __align__(16) _Float16 sH2[kFuseRows * kFuseLd];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4, kq = g * 8;
-    const int m0 = blockIdx.x * kFuseRows;
+    const int ntiles = (M + kFuseRows - 1) / kFuseRows;
+    if ((int)blockIdx.x >= ntiles) return;
     const _Float16* W1 = w16 + kH16W1;
     const _Float16* W2 = w16 + kH16W2;
     const _Float16* W3 = w16 + kH16W3;
-    f4 acc[4][4];
+    constexpr int K1 = kMlpIn / 32, K2 = kMlpHid / 32;
+    const int c0 = 32 * wave;                                 // layers 1, 2: this wave's first column
+    const int c3 = 16 * (wave & 3), r3 = 32 * (wave >> 2);  // layer 3: its columns and rows
 
-    // layer 1: H1 = max(X W1^T + b1, 0), K = 64
+    // the weight fragments and biases of this wave, for every tile
+    h8 fb1[K1][2], fb2[K2][2], fb3[K2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int kk = 0; kk < K1; ++kk)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < 2; ++j)
+            fb1[kk][j] = *reinterpret_cast<const h8*>(W1 + (c0 + 16 * j + r) * kMlpIn + 32 * kk + kq);
 #pragma unroll
-    for (int k = 0; k < kMlpIn; k += 32) {
-        h8 fa[4], fb[4];
+    for (int kk = 0; kk < K2; ++kk) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            fa[i] = *reinterpret_cast<const h8*>(X + (int64_t)min(m0 + 16 * i + r, M - 1) * kMlpIn + k + kq);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            fb[j] = *reinterpret_cast<const h8*>(W1 + (64 * wave + 16 * j + r) * kMlpIn + k + kq);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(fa[i], fb[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j)
+            fb2[kk][j] = *reinterpret_cast<const h8*>(W2 + (c0 + 16 * j + r) * kMlpHid + 32 * kk + kq);
+        fb3[kk] = *reinterpret_cast<const h8*>(W3 + (c3 + r) * kMlpHid + 32 * kk + kq);
     }
+    float bias1[2], bias2[2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int col = 64 * wave + 16 * j + r;
-        const float bv = w[kOffB1 + col];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                sH1[(16 * i + 4 * g + e) * kFuseLd + col] = (_Float16)fmaxf(1.0f * acc[i][j][e] + bv, 0.0f);
+    for (int j = 0; j < 2; ++j) {
+        bias1[j] = w[kOffB1 + c0 + 16 * j + r];
+        bias2[j] = w[kOffB2 + c0 + 16 * j + r];
     }
-    __syncthreads();
+    const float bias3 = w[kOffB3 + c3 + r];
 
-    // layer 2: H2 = max(H1 W2^T + b2, 0), K = 256
+    auto load_rows = [&](int m0, h8 (&fa)[K1][4]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int kk = 0; kk < K1; ++kk)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    {
-        h8 fb[4];
+            for (int i = 0; i < 4; ++i)
+                fa[kk][i] = *reinterpret_cast<const h8*>(X + (int64_t)min(m0 + 16 * i + r, M - 1) * kMlpIn + 32 * kk + kq);
+    };
+    h8 fa[K1][4];
+    load_rows((int)blockIdx.x * kFuseRows, fa);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int m0 = tile * kFuseRows;
+        f4 acc[4][2];
+
+        // layer 1: H1 = max(X W1^T + b1, 0), K = 64
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const h8*>(W2 + (64 * wave + 16 * j + r) * kMlpHid + kq);
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int k = 0; k < kMlpHid; k += 32) {
-            h8 nb[4];
-            if (k + 32 < kMlpHid)
+            for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    nb[j] = *reinterpret_cast<const h8*>(W2 + (64 * wave + 16 * j + r) * kMlpHid + k + 32 + kq);
-            h8 fa[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = *reinterpret_cast<const h8*>(sH1 + (16 * i + r) * kFuseLd + k + kq);
+        for (int kk = 0; kk < K1; ++kk)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(fa[i], fb[j], acc[i][j]);
-            if (k + 32 < kMlpHid)
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(fa[kk][i], fb1[kk][j], acc[i][j]);
+        // the next tile's rows, in flight during layers 2 and 3
+        if (tile + (int)gridDim.x < ntiles) load_rows((tile + gridDim.x) * kFuseRows, fa);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fb[j] = nb[j];
+        for (int j = 0; j < 2; ++j) {
+            const int col = c0 + 16 * j + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    sH1[(16 * i + 4 * g + e) * kFuseLd + col] = (_Float16)fmaxf(1.0f * acc[i][j][e] + bias1[j], 0.0f);
         }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int col = 64 * wave + 16 * j + r;
-        const float bv = w[kOffB2 + col];
+        __syncthreads();
+
+        // layer 2: H2 = max(H1 W2^T + b2, 0), K = 256
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                sH2[(16 * i + 4 * g + e) * kFuseLd + col] = (_Float16)fmaxf(1.0f * acc[i][j][e] + bv, 0.0f);
-    }
-    __syncthreads();
-
-    // layer 3: Y = H2 W3^T + b3, K = 256; this wave's 16 rows, all 64 columns
-    f4 out[4];
+            for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) out[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    {
-        h8 fb[4];
+        for (int kk = 0; kk < K2; ++kk) {
+            h8 a[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const h8*>(W3 + (16 * j + r) * kMlpHid + kq);
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const h8*>(sH1 + (16 * i + r) * kFuseLd + 32 * kk + kq);
 #pragma unroll
-        for (int k = 0; k < kMlpHid; k += 32) {
-            h8 nb[4];
-            if (k + 32 < kMlpHid)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    nb[j] = *reinterpret_cast<const h8*>(W3 + (16 * j + r) * kMlpHid + k + 32 + kq);
-            const h8 fa = *reinterpret_cast<const h8*>(sH2 + (16 * wave + r) * kFuseLd + k + kq);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) out[j] = mfma16(fa, fb[j], out[j]);
-            if (k + 32 < kMlpHid)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) fb[j] = nb[j];
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], fb2[kk][j], acc[i][j]);
         }
-    }
-    // Y tile in LDS (H1's space, read for the last time before the barrier above)
-    constexpr int kYLd = kMlpOut + 4;
-    float* tY = reinterpret_cast<float*>(sH1);
-    static_assert(kFuseRows * kYLd * 4 <= kFuseRows * kFuseLd * 2, "Y tile fits in H1's space");
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int col = 16 * j + r;
-        const float bv = w[kOffB3 + col];
+        for (int j = 0; j < 2; ++j) {
+            const int col = c0 + 16 * j + r;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) tY[(16 * wave + 4 * g + e) * kYLd + col] = 1.0f * out[j][e] + bv;
-    }
-    __syncthreads();
-    // S_q = sum_t Y[8 q + t], G_q = S_q / |S_q|: wave w takes blocks 2 w and 2 w + 1
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int q = 2 * wave + b, row0 = m0 + 8 * q;
-        float sum = 0.0f;
+                for (int e = 0; e < 4; ++e)
+                    sH2[(16 * i + 4 * g + e) * kFuseLd + col] = (_Float16)fmaxf(1.0f * acc[i][j][e] + bias2[j], 0.0f);
+        }
+        __syncthreads();
+
+        // layer 3: Y = H2 W3^T + b3, K = 256; rows [r3, r3 + 32), columns [c3, c3 + 16)
+        f4 out[2];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) sum += tY[(8 * q + t) * kYLd + lane];
-        const float nn = sqrtf(wave_sum_f32(sum * sum));
-        const float gq = nn > 0.0f ? sum / nn : 0.0f;
-        if (row0 < M) G16[(int64_t)(row0 / 8) * 64 + lane] = (_Float16)gq;
+        for (int i = 0; i < 2; ++i) out[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < K2; ++kk)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const h8 a = *reinterpret_cast<const h8*>(sH2 + (r3 + 16 * i + r) * kFuseLd + 32 * kk + kq);
+                out[i] = mfma16(a, fb3[kk], out[i]);
+            }
+        // Y tile in LDS (H1's space: every read of H1 is before the barrier above)
+        constexpr int kYLd = kMlpOut + 4;
+        float* tY = reinterpret_cast<float*>(sH1);
+        static_assert(kFuseRows * kYLd * 4 <= kFuseRows * kFuseLd * 2, "Y tile fits in H1's space");
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tY[(r3 + 16 * i + 4 * g + e) * kYLd + c3 + r] = 1.0f * out[i][e] + bias3;
+        __syncthreads();
+        // S_q = sum_t Y[8 q + t], G_q = S_q / |S_q|: wave w takes block w
+        {
+            const int q = wave, row0 = m0 + 8 * q;
+            float sum = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) sum += tY[(8 * q + t) * kYLd + lane];
+            const float nn = sqrtf(wave_sum_f32(sum * sum));
+            const float gq = nn > 0.0f ? sum / nn : 0.0f;
+            if (row0 < M) G16[(int64_t)(row0 / 8) * 64 + lane] = (_Float16)gq;
+        }
+        __syncthreads();  // the Y tile is read before the next tile's H1 overwrites it
     }
 }
 
@@ -583,24 +590,25 @@ __global__ __launch_bounds__(256) void k_weights16(const float* __restrict__ w, 
 }
 
 // ---------------------------------------------------------------- top-k similarity
-// The k best keys of each query by the dot product of fp16 rows, accumulated
-// in fp32 by two v_mfma_f32_16x16x32_f16 from a zero accumulator (K = 0..31,
-// then 32..63): every pass computes an element's score this same way, so all
-// passes see the same value for it. Two passes over the keys, split into nc
-// chunks:
+// Proposals: the k best keys (domain embeddings) of each query (range
+// embedding) by similarity, ties to the lower key index. The similarity is the
+// dot product of int8 codes of the embeddings, q = rint(x s) with one scale s
+// = 127 / max |x| over the queries and the keys together (fp32 arithmetic),
+// so scores are integers (|score| <= 64 * 127^2), exact in int32 in any
+// summation order; one v_mfma_i32_16x16x64_i8 gives a 16 x 16 tile. Two
+// passes over the keys, split into nc chunks:
 //  1. per query, the largest score of each group of keys, a group being the
 //     keys of one chunk and one column lane (index mod 16 within the chunk's
-//     64-key stages): 16 nc disjoint groups. Each maximum is the score of a
-//     key of its group, so at least 32 keys score at least theta, the 32nd
-//     largest maximum (of the lanes' maxima when there are more than 64
-//     groups; -inf with fewer than 32): no key scoring below theta is among
+//     stages): 16 nc disjoint groups. Each maximum is the score of a key of
+//     its group, so at least 32 keys score at least theta, the 32nd largest
+//     maximum (of the lanes' maxima when there are more than 64 groups; below
+//     every score with fewer than 32): no key scoring below theta is among
 //     the best 32;
-//  2. the keys scoring at least theta: a screen on the MFMA output started at
-//     delta - theta (delta above the roundings that this start adds, so no
-//     such key is screened out), then the passing elements recomputed from a
-//     zero accumulator and kept in a list per (query, chunk) when their key
-//     (score, then lower index) is above the list's threshold. A list that
-//     could overflow keeps its best 32 and takes the 32nd as its threshold.
+//  2. the keys scoring at least theta: the MFMA started at -theta gives
+//     score - theta exactly, so a tile's screen is one maximum and a sign;
+//     passing elements whose key (score, then lower index) is above the
+//     list's threshold enter a list per (query, chunk). A list that could
+//     overflow keeps its best 32 and takes the 32nd as its threshold.
 // A merge sorts each query's lists. With theta near the 32nd best score a
 // query keeps a few dozen keys; a running top-32 admits every key that beats
 // the keys seen before it, hundreds per query.
@@ -609,6 +617,9 @@ constexpr int kTkRT = 4;     // 16-row tiles per wave: 64 queries
 constexpr int kTkWaves = 4;  // waves per workgroup
 constexpr int kTkQ = kTkWaves * 16 * kTkRT;
 constexpr int kTkCap = 48;   // list slots per (query, chunk)
+constexpr int kTkCols = 128;  // keys per LDS stage (64 bytes each)
+constexpr int kTkTiles = kTkCols / 16;
+constexpr int kTkScoreCap = 1 << 21;  // above every |score| (64 * 127^2 < 2^20)
 
 // Ordered key: larger key = larger score, then lower domain index.
 __device__ inline uint64_t tk_key(float s, int d) {
@@ -677,21 +688,56 @@ __device__ inline uint64_t shfl_u64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Shared by the two passes: the query rows as A operands, the stage copies
+// max |x| over fp16 arrays a [na] and b [nb] (multiples of 8 values), as
+// float bits (non-negative floats order as unsigned integers); *out starts at 0
+__global__ __launch_bounds__(256) void k_tk_absmax(const _Float16* __restrict__ a, int64_t na,
+                                                   const _Float16* __restrict__ b, int64_t nb,
+                                                   uint32_t* __restrict__ out) {
+    float m = 0.0f;
+    const int64_t n8 = (na + nb) / 8;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n8; t += (int64_t)gridDim.x * 256) {
+        const h8 v = t < na / 8 ? reinterpret_cast<const h8*>(a)[t] : reinterpret_cast<const h8*>(b)[t - na / 8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m = fmaxf(m, fabsf((float)v[e]));
+    }
+    m = wave_max_f32(m);
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
+// int8 codes q = rint(x s), s = 127 / m (m = *mbits as a float; s = 0 when m = 0),
+// 8 values per thread
+__global__ __launch_bounds__(256) void k_tk_quant(const _Float16* __restrict__ x, int64_t n8,
+                                                  const uint32_t* __restrict__ mbits, int8_t* __restrict__ q) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n8) return;
+    const float m = __uint_as_float(*mbits);
+    const float sc = m > 0.0f ? 127.0f / m : 0.0f;
+    const h8 v = reinterpret_cast<const h8*>(x)[t];
+    uint32_t w[2] = {0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e >> 2] |= (uint32_t)(uint8_t)(int8_t)(int)rintf((float)v[e] * sc) << (8 * (e & 3));
+    reinterpret_cast<uint2*>(q)[t] = make_uint2(w[0], w[1]);
+}
+
+// Shared by the two passes: the query codes as A operands, the stage copies
 // and the tiles. grid: x = blocks of kTkQ queries, y = key chunks; the keys of
-// a chunk stream through LDS in stages of kM8Cols (64) rows, copied straight
-// from global memory as the MFMA grid matchers copy their columns (the same
-// swizzled 16-byte chunks).
-constexpr int kTkLoads = kM8Cols * 8 / (kTkWaves * 64);
-static_assert(kTkWaves * kTkLoads * 64 == kM8Cols * 8, "a stage is whole 16-byte chunks per lane");
+// a chunk stream through LDS in stages of kTkCols codes (64 bytes each),
+// copied straight from global memory in 16-byte chunks (no registers on the
+// way, as the MFMA grid matchers copy their columns): chunk u (values 16 u ..
+// 16 u + 15) of key c at c * 4 + (u ^ ((c >> 2) & 3)), so that the 16 keys of
+// a tile read one chunk each from distinct banks.
+constexpr int kTkLoads = kTkCols * 4 / (kTkWaves * 64);
+static_assert(kTkWaves * kTkLoads * 64 == kTkCols * 4, "a stage is whole 16-byte chunks per lane");
+
+__device__ inline int tk_chunk(int c, int u) { return c * 4 + (u ^ ((c >> 2) & 3)); }
 
 struct TkWave {
     int nq, lo, hi, wave, lane, g, c16, wq0;
-    h8 af[kTkRT][2];
+    v4i af[kTkRT];
     uint32_t off[kTkLoads];  // byte offsets of a full stage's chunks, from the stage's first key
 };
 
-__device__ __forceinline__ bool tk_setup(TkWave& w, const _Float16* __restrict__ GR, int nq, int nk) {
+__device__ __forceinline__ bool tk_setup(TkWave& w, const int8_t* __restrict__ QR, int nq, int nk) {
     const int q0 = blockIdx.x * kTkQ;
     if (q0 >= nq) return false;
     const int nc = gridDim.y, c = blockIdx.y;
@@ -705,31 +751,28 @@ __device__ __forceinline__ bool tk_setup(TkWave& w, const _Float16* __restrict__
     w.wq0 = q0 + w.wave * 16 * kTkRT;
     // query rows past the end read the last row and are never written
 #pragma unroll
-    for (int rt = 0; rt < kTkRT; ++rt) {
-        const _Float16* pa = GR + (int64_t)min(w.wq0 + 16 * rt + w.c16, nq - 1) * 64 + 8 * w.g;
-        w.af[rt][0] = *reinterpret_cast<const h8*>(pa);
-        w.af[rt][1] = *reinterpret_cast<const h8*>(pa + 32);
-    }
+    for (int rt = 0; rt < kTkRT; ++rt)
+        w.af[rt] = *reinterpret_cast<const v4i*>(QR + (int64_t)min(w.wq0 + 16 * rt + w.c16, nq - 1) * 64 + 16 * w.g);
 #pragma unroll
     for (int l = 0; l < kTkLoads; ++l) {
-        const int i = (kTkLoads * w.wave + l) * 64 + w.lane, col = i >> 3, u = (i & 7) ^ ((col >> 1) & 7);
-        w.off[l] = (uint32_t)(col * 128 + 16 * u);
+        const int i = (kTkLoads * w.wave + l) * 64 + w.lane, col = i >> 2, u = (i & 3) ^ ((col >> 2) & 3);
+        w.off[l] = (uint32_t)(col * 64 + 16 * u);
     }
     return true;
 }
 
-// Copy keys b0 .. b0 + n - 1 (n <= kM8Cols; rows past n copy row n - 1) into dD.
-__device__ __forceinline__ void tk_stage_copy(const TkWave& w, const _Float16* __restrict__ GD, v4i* dD, int b0,
+// Copy keys b0 .. b0 + n - 1 (n <= kTkCols; keys past n copy key n - 1) into dD.
+__device__ __forceinline__ void tk_stage_copy(const TkWave& w, const int8_t* __restrict__ QD, v4i* dD, int b0,
                                               int n) {
     // the same in every lane: read from the first so that they sit in SGPRs
-    const uint64_t bu = (uint64_t)(uintptr_t)(reinterpret_cast<const int8_t*>(GD) + (int64_t)b0 * 128);
+    const uint64_t bu = (uint64_t)(uintptr_t)(QD + (int64_t)b0 * 64);
     const void* base = (const void*)(uintptr_t)(
         ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(bu >> 32)) << 32) |
         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bu));
 #pragma unroll
     for (int l = 0; l < kTkLoads; ++l) {
         const uint32_t o =
-            n == kM8Cols ? w.off[l] : (uint32_t)(min((int)(w.off[l] >> 7), n - 1) * 128) + (w.off[l] & 127u);
+            n == kTkCols ? w.off[l] : (uint32_t)(min((int)(w.off[l] >> 6), n - 1) * 64) + (w.off[l] & 63u);
         const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)(
             (const __attribute__((address_space(3))) void*)(dD + (kTkLoads * w.wave + l) * 64)));
         m8_copy_to_lds(base, o, (const __attribute__((address_space(3))) void*)(uintptr_t)la);
@@ -739,66 +782,55 @@ __device__ __forceinline__ void tk_stage_copy(const TkWave& w, const _Float16* _
 __device__ __forceinline__ void tk_wait_copies() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
 // One 16-key tile (ct) for every row tile, the accumulators started at c0.
-__device__ __forceinline__ void tk_tile(const TkWave& w, const v4i* cD, int ct, const f4 (&c0)[kTkRT],
-                                        f4 (&acc)[kTkRT]) {
-    const int col = 16 * ct + w.c16;
-    const h8 b0 = __builtin_bit_cast(h8, cD[m8_chunk(col, w.g)]);
-    const h8 b1 = __builtin_bit_cast(h8, cD[m8_chunk(col, 4 + w.g)]);
+__device__ __forceinline__ void tk_tile(const TkWave& w, const v4i* cD, int ct, const v4i (&c0)[kTkRT],
+                                        v4i (&acc)[kTkRT]) {
+    const v4i b = cD[tk_chunk(16 * ct + w.c16, w.g)];
 #pragma unroll
-    for (int rt = 0; rt < kTkRT; ++rt) {
-        acc[rt] = mfma16(w.af[rt][0], b0, c0[rt]);
-        acc[rt] = mfma16(w.af[rt][1], b1, acc[rt]);
-    }
+    for (int rt = 0; rt < kTkRT; ++rt) acc[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(w.af[rt], b, c0[rt], 0, 0, 0);
 }
 
-// The chunk's stages, double-buffered: fn(buffer, first key, parity) on each
-// while the next one is copied in.
+// The chunk's stages, double-buffered: fn(buffer, first key) on each while
+// the next one is copied in.
 template <class Fn>
-__device__ __forceinline__ void tk_stages(const TkWave& w, const _Float16* __restrict__ GD, v4i (*sD)[kM8Cols * 8],
+__device__ __forceinline__ void tk_stages(const TkWave& w, const int8_t* __restrict__ QD, v4i (*sD)[kTkCols * 4],
                                           Fn&& fn) {
     tk_wait_copies();
     if (w.lo < w.hi) {
-        tk_stage_copy(w, GD, sD[0], w.lo, min(kM8Cols, w.hi - w.lo));
+        tk_stage_copy(w, QD, sD[0], w.lo, min(kTkCols, w.hi - w.lo));
         tk_wait_copies();
     }
     __syncthreads();
-    for (int base = w.lo; base < w.hi; base += 2 * kM8Cols) {
-        int nb = base + kM8Cols;
-        if (nb < w.hi) tk_stage_copy(w, GD, sD[1], nb, min(kM8Cols, w.hi - nb));
-        fn(sD[0], base, 0);
-        tk_wait_copies();
-        __syncthreads();
-        if (nb >= w.hi) break;
-        const int b1 = nb;
-        nb = b1 + kM8Cols;
-        if (nb < w.hi) tk_stage_copy(w, GD, sD[0], nb, min(kM8Cols, w.hi - nb));
-        fn(sD[1], b1, 1);
+    int buf = 0;
+    for (int base = w.lo; base < w.hi; base += kTkCols, buf ^= 1) {
+        const int nb = base + kTkCols;
+        if (nb < w.hi) tk_stage_copy(w, QD, sD[buf ^ 1], nb, min(kTkCols, w.hi - nb));
+        fn(sD[buf], base);
         tk_wait_copies();
         __syncthreads();
     }
 }
 
-// Pass 1: GM [nq][16 nc], the largest score of each (chunk, column lane)
-// group of keys per query (-inf for an empty group).
-__global__ __launch_bounds__(kTkWaves * 64) void k_tk_max(const _Float16* __restrict__ GR, int nq,
-                                                          const _Float16* __restrict__ GD, int nk,
-                                                          float* __restrict__ GM) {
-    __shared__ v4i sD[2][kM8Cols * 8];
+// Pass 1: GM [nq][16 nc], the largest score of each (chunk, column lane) group
+// of keys per query (INT_MIN for an empty group).
+__global__ __launch_bounds__(kTkWaves * 64) void k_tk_max(const int8_t* __restrict__ QR, int nq,
+                                                          const int8_t* __restrict__ QD, int nk,
+                                                          int32_t* __restrict__ GM) {
+    __shared__ v4i sD[2][kTkCols * 4];
     TkWave w;
-    if (!tk_setup(w, GR, nq, nk)) return;
+    if (!tk_setup(w, QR, nq, nk)) return;
     constexpr int RT = kTkRT;
-    const f4 zero[RT] = {};
-    float m[RT][4];
+    const v4i zero[RT] = {};
+    int m[RT][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) m[rt][e] = -INFINITY;
-    // fold a stage into m, two tiles at a time (keys past the chunk's end count as -inf)
-    tk_stages(w, GD, sD, [&](const v4i* cD, int base, int) {
-        const bool tail = base + kM8Cols > w.hi;
-#pragma unroll
-        for (int ct = 0; ct < kM8ColTiles; ct += 2) {
-            f4 x0[RT], x1[RT];
+        for (int e = 0; e < 4; ++e) m[rt][e] = INT_MIN;
+    // fold a stage into m, two tiles at a time (keys past the chunk's end count as INT_MIN)
+    tk_stages(w, QD, sD, [&](const v4i* cD, int base) {
+        const bool tail = base + kTkCols > w.hi;
+#pragma unroll 2
+        for (int ct = 0; ct < kTkTiles; ct += 2) {
+            v4i x0[RT], x1[RT];
             tk_tile(w, cD, ct, zero, x0);
             tk_tile(w, cD, ct + 1, zero, x1);
             if (tail) {
@@ -807,14 +839,14 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_max(const _Float16* __rest
                 for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        x0[rt][e] = ok0 ? x0[rt][e] : -INFINITY;
-                        x1[rt][e] = ok1 ? x1[rt][e] : -INFINITY;
+                        x0[rt][e] = ok0 ? x0[rt][e] : INT_MIN;
+                        x1[rt][e] = ok1 ? x1[rt][e] : INT_MIN;
                     }
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) m[rt][e] = fmaxf(fmaxf(m[rt][e], x0[rt][e]), x1[rt][e]);
+                for (int e = 0; e < 4; ++e) m[rt][e] = max(max(m[rt][e], x0[rt][e]), x1[rt][e]);
         }
     });
     const int c = blockIdx.y, G = 16 * gridDim.y;
@@ -827,21 +859,32 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_max(const _Float16* __rest
         }
 }
 
+// Per query (one wave): theta, the 32nd largest group maximum (of the lanes'
+// maxima over groups lane, lane + 64, ... when there are more than 64), or
+// -kTkScoreCap (below every score) when fewer than 32 groups hold a key.
+__global__ __launch_bounds__(256) void k_tk_theta(const int32_t* __restrict__ GM, int nq, int G,
+                                                  int32_t* __restrict__ theta) {
+    const int q = (int)((blockIdx.x * 256u + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    int m = INT_MIN;
+    for (int j = lane; j < G; j += 64) m = max(m, GM[(int64_t)q * G + j]);
+    const uint64_t v = wave_sort_desc((uint64_t)((uint32_t)m ^ 0x80000000u) << 32, lane);
+    const int t = (int)((uint32_t)(shfl_u64(v, kTopK - 1) >> 32) ^ 0x80000000u);
+    if (lane == 0) theta[q] = max(t, -kTkScoreCap);
+}
+
 // Pass 2: per (query, chunk) the list [kTkCap] of keys scoring at least
 // theta, and its count.
-__global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const _Float16* __restrict__ GR, int nq,
-                                                              const _Float16* __restrict__ GD, int nk,
-                                                              const float* __restrict__ th_in,
-                                                              const float* __restrict__ dl_in,
+__global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __restrict__ QR, int nq,
+                                                              const int8_t* __restrict__ QD, int nk,
+                                                              const int32_t* __restrict__ th_in,
                                                               uint64_t* __restrict__ list,
                                                               int32_t* __restrict__ lcount) {
     constexpr int RT = kTkRT, WR = 16 * RT;
     static_assert(WR == 64, "one query per lane in the list bookkeeping");
-    __shared__ v4i sD[2][kM8Cols * 8];
+    __shared__ v4i sD[2][kTkCols * 4];
     __shared__ uint64_t sThr[kTkWaves][WR];  // keys above this enter the query's list
-    __shared__ __align__(16) float sTf[kTkWaves][WR];  // its score
-    __shared__ float sDl[kTkWaves][WR];      // screen slack delta
-    __shared__ __align__(16) float sCs[kTkWaves][WR];  // screen start: delta - (threshold score)
+    __shared__ __align__(16) int32_t sTh[kTkWaves][WR];  // its score
     __shared__ int32_t sCnt[kTkWaves][WR];
     // list entries on their way to global memory: stored in batches, because
     // the wait for a stage's copy would also wait for every store before it
@@ -849,27 +892,20 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const _Float16* __
     __shared__ uint32_t sQi[kTkWaves][kQ];  // list position (row * kTkCap + slot)
     __shared__ uint64_t sQk[kTkWaves][kQ];  // key
     TkWave w;
-    if (!tk_setup(w, GR, nq, nk)) return;
+    if (!tk_setup(w, QR, nq, nk)) return;
     const int c = blockIdx.y, wave = w.wave, lane = w.lane, g = w.g, c16 = w.c16;
     {
         const int q = w.wq0 + lane;
-        const float t = q < nq ? th_in[q] : INFINITY;
-        const float d = q < nq ? dl_in[q] : 0.0f;
-        // keys of scores >= t: ord(t) << 32 and above; none for padded rows
-        sThr[wave][lane] = q < nq ? ((uint64_t)tk_ord(t) << 32) - 1u : ~0ull;
-        sTf[wave][lane] = t;
-        sDl[wave][lane] = d;
-        sCs[wave][lane] = d - t;
+        const int t = q < nq ? th_in[q] : kTkScoreCap;  // padded rows: above every score
+        // keys of scores >= t: ord(t) << 32 and above
+        sThr[wave][lane] = ((uint64_t)tk_ord((float)t) << 32) - 1u;
+        sTh[wave][lane] = t;
         sCnt[wave][lane] = 0;
     }
     wave_lds_sync();
-    const f4 zero[RT] = {};
-    f4 cs[RT], tf[RT];  // per row 16 rt + 4 g + e: the screen start, the threshold score
+    v4i cs[RT];  // per row 16 rt + 4 g + e: the screen start -theta
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-        cs[rt] = *reinterpret_cast<const f4*>(&sCs[wave][16 * rt + 4 * g]);
-        tf[rt] = *reinterpret_cast<const f4*>(&sTf[wave][16 * rt + 4 * g]);
-    }
+    for (int rt = 0; rt < RT; ++rt) cs[rt] = -*reinterpret_cast<const v4i*>(&sTh[wave][16 * rt + 4 * g]);
     uint64_t* wlist = list + ((int64_t)c * nq + w.wq0) * kTkCap;
     const uint32_t below = (1u << c16) - 1u;
     int qn = 0;  // queued list entries (the same in every lane)
@@ -898,62 +934,55 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const _Float16* __
             if (lane == 0) {
                 sCnt[wave][i] = kTopK;
                 sThr[wave][i] = t;
-                sTf[wave][i] = tk_score(t);
-                sCs[wave][i] = sDl[wave][i] - tk_score(t);
+                sTh[wave][i] = (int)tk_score(t);
             }
         }
         wave_lds_sync();
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            cs[rt] = *reinterpret_cast<const f4*>(&sCs[wave][16 * rt + 4 * g]);
-            tf[rt] = *reinterpret_cast<const f4*>(&sTf[wave][16 * rt + 4 * g]);
-        }
+        for (int rt = 0; rt < RT; ++rt) cs[rt] = -*reinterpret_cast<const v4i*>(&sTh[wave][16 * rt + 4 * g]);
     };
-    // a stage: the screen of every tile without a branch (one maximum per
-    // lane, one ballot: a bit per tile with a passing element; a branch per
-    // tile would keep the next tile's LDS reads from being issued early),
-    // then the flagged tiles from a zero accumulator, their elements above
-    // the threshold listed. (LDS operations of one wave take effect in program
-    // order, so the counts and thresholds need no fence here.)
-    tk_stages(w, GD, sD, [&](const v4i* cD, int base, int) {
+    // a stage: the screen of every tile without a branch (per row tile one
+    // maximum and one ballot: a bit per (tile, row tile) with an element at or
+    // above theta; a branch per tile would keep the next tile's LDS reads from
+    // being issued early), then the flagged row tiles again and their
+    // elements above the list threshold queued. (LDS operations of one wave
+    // take effect in program order, so the counts and thresholds need no
+    // fence here.)
+    tk_stages(w, QD, sD, [&](const v4i* cD, int base) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) asm volatile("" : "+v"(cs[rt]), "+v"(tf[rt]));
-        uint32_t hits = 0;  // bit 4 ct + rt: row tile rt of tile ct has a passing element
+        for (int rt = 0; rt < RT; ++rt) asm volatile("" : "+v"(cs[rt]));
+        uint32_t hits = 0;  // bit RT ct + rt
 #pragma unroll
-        for (int ct = 0; ct < kM8ColTiles; ++ct) {
-            f4 acc[RT];
+        for (int ct = 0; ct < kTkTiles; ++ct) {
+            v4i acc[RT];
             tk_tile(w, cD, ct, cs, acc);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                const float m = fmaxf(fmaxf(fmaxf(acc[rt][0], acc[rt][1]), acc[rt][2]), acc[rt][3]);
-                hits |= __ballot(m >= 0.0f) ? 1u << (RT * ct + rt) : 0u;
+                const int mm = max(max(acc[rt][0], acc[rt][1]), max(acc[rt][2], acc[rt][3]));
+                hits |= __ballot(mm >= 0) ? 1u << (RT * ct + rt) : 0u;
             }
         }
-        if (!hits) return;
         while (hits) {
             const int ct = (__builtin_ffs(hits) - 1) / RT;
             const uint32_t rts = (hits >> (RT * ct)) & ((1u << RT) - 1u);
             hits &= ~(((1u << RT) - 1u) << (RT * ct));
             const int col = 16 * ct + c16;
-            const h8 b0 = __builtin_bit_cast(h8, cD[m8_chunk(col, g)]);
-            const h8 b1 = __builtin_bit_cast(h8, cD[m8_chunk(col, 4 + g)]);
+            const v4i b = cD[tk_chunk(col, g)];
             const int kc = base + col;
             const bool colok = kc < w.hi;
             bool full = false;
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 if (!(rts & (1u << rt))) continue;
-                f4 x = mfma16(w.af[rt][0], b0, zero[rt]);
-                x = mfma16(w.af[rt][1], b1, x);
-                // a float compare with the threshold score first (a superset
-                // of the key compare), the key compare for the few that pass
+                const v4i x = __builtin_amdgcn_mfma_i32_16x16x64_i8(w.af[rt], b, cs[rt], 0, 0, 0);  // score - theta
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    if (!__ballot(colok && x[e] >= tf[rt][e])) continue;
+                    if (!__ballot(colok && x[e] >= 0)) continue;
                     const int i = 16 * rt + 4 * g + e;
                     const uint64_t thr = sThr[wave][i];
                     const int n = sCnt[wave][i];
-                    const bool p = colok && x[e] >= tf[rt][e] && tk_key(x[e], kc) > thr;
+                    const uint64_t key = tk_key((float)(x[e] - cs[rt][e]), kc);
+                    const bool p = colok && x[e] >= 0 && key > thr;
                     const uint64_t bal = __ballot(p);
                     if (!bal) continue;
                     const uint32_t seg = (uint32_t)(bal >> (16 * g)) & 0xffffu;
@@ -961,7 +990,7 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const _Float16* __
                         const int qp = qn + (int)__builtin_amdgcn_mbcnt_hi(
                                                 (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                         sQi[wave][qp] = (uint32_t)(i * kTkCap + n + __popc(seg & below));
-                        sQk[wave][qp] = tk_key(x[e], kc);
+                        sQk[wave][qp] = key;
                     }
                     qn += __popcll(bal);
                     if (c16 == 0) sCnt[wave][i] = n + __popc(seg);
@@ -974,53 +1003,6 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const _Float16* __
     });
     flush();
     if (w.wq0 + lane < nq) lcount[(int64_t)c * nq + w.wq0 + lane] = sCnt[wave][lane];
-}
-
-// The largest squared L2 norm of the key rows, as float bits (non-negative
-// floats order as unsigned integers), rounded up: the fp32 sum of 64 squares
-// is within 64 ulps, and 2^-16 is added. Eight lanes per key, 16 bytes each.
-// *out starts at 0.
-__global__ __launch_bounds__(256) void k_tk_keynorm(const _Float16* __restrict__ GD, int nk,
-                                                    uint32_t* __restrict__ out) {
-    float mx = 0.0f;
-    // lane groups of 8 take keys in turn (a key's 8 chunks at t .. t + 7, t = 8 key)
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < (int64_t)nk * 8; t += (int64_t)gridDim.x * 256) {
-        const h8 v = reinterpret_cast<const h8*>(GD)[t];
-        float s = 0.0f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) s += (float)v[e] * (float)v[e];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        s += __shfl_xor(s, 4, 64);
-        mx = fmaxf(mx, s);
-    }
-    mx = wave_max_f32(mx * (1.0f + 1.0f / 65536.0f));
-    if ((threadIdx.x & 63) == 0 && mx > 0.0f) atomicMax(out, __float_as_uint(mx));
-}
-
-// Per query (one wave): theta, the 32nd largest group maximum (lane maxima
-// over groups lane, lane + 64, ... when there are more than 64; -inf when
-// fewer than 32 are finite), and the screen slack delta = 2^-15 (|theta| +
-// 2 |q| D), D the largest key norm. The screen's start delta - theta changes
-// the roundings of at most 65 additions of terms below |theta| + delta +
-// |q| D, and a score's own roundings stay within 64 ulps of |q| D: together
-// below 2^-17.9 (|theta| + delta + 2 |q| D) < delta.
-__global__ __launch_bounds__(256) void k_tk_theta(const float* __restrict__ GM, int nq, int G,
-                                                  const _Float16* __restrict__ GR,
-                                                  const uint32_t* __restrict__ dnorm2,
-                                                  float* __restrict__ theta, float* __restrict__ delta) {
-    const int q = (int)((blockIdx.x * 256u + threadIdx.x) >> 6), lane = threadIdx.x & 63;
-    if (q >= nq) return;
-    float m = -INFINITY;
-    for (int j = lane; j < G; j += 64) m = fmaxf(m, GM[(int64_t)q * G + j]);
-    uint64_t v = wave_sort_desc((uint64_t)tk_ord(m) << 32, lane);
-    const float t = tk_score(shfl_u64(v, kTopK - 1));
-    const float x = (float)GR[(int64_t)q * 64 + lane];
-    const float qn = sqrtf(wave_sum_f32(x * x)) * (1.0f + 1.0f / 65536.0f);
-    if (lane == 0) {
-        theta[q] = t;
-        delta[q] = (fabsf(t) + 2.0f * qn * sqrtf(__uint_as_float(*dnorm2))) * (1.0f / 32768.0f);
-    }
 }
 
 // Best k of a query's lists, best first (one wave per query): the lists'

@@ -443,7 +443,8 @@ class Mlp:
         return loss
 
     def topk(self, q, keys, k: int, stream=None):
-        """(idx int32 [nq, k], score float32 [nq, k]) of fp16 [n, 64] device tensors."""
+        """(idx int32 [nq, k], score float32 [nq, k]) of fp16 [n, 64] device tensors: the
+        k keys of largest int8-code similarity per query (fic_topk_similar)."""
         import torch
         q = q.contiguous()
         keys = keys.contiguous()

@@ -151,17 +151,69 @@ def test_adam_constant_gradient_closed_form():
         assert np.allclose(theta, -step * lr * g / (np.abs(g) + eps), rtol=1e-10, atol=1e-15)
 
 
+def _codes_and_rows(n, seed, n_dup=0):
+    """int8 codes with 127 in row 0 and their rows q * 2^-8 (exact in fp16), so that
+    the common scale is 127 / (127 * 2^-8) = 256 and the codes come back unchanged."""
+    rng = np.random.default_rng(seed)
+    q = rng.integers(-127, 128, size=(n, 64))
+    q[0, 0] = 127
+    for i in range(1, n_dup + 1):
+        q[-i] = q[i]
+    return q, (q * 2.0 ** -8).astype(np.float16)
+
+
+def test_quantize_recovers_exact_codes():
+    qr, xr = _codes_and_rows(9, seed=1)
+    qd, _ = _codes_and_rows(40, seed=2)
+    qd = np.clip(qd, -100, 100)  # the scale is common: the domains' own largest value is 100
+    xd = (qd * 2.0 ** -8).astype(np.float16)
+    (cr, cd), s = ol.quantize(xr, xd)
+    assert s == np.float32(256.0)
+    assert np.array_equal(cr, qr) and np.array_equal(cd, qd)
+
+
+def test_quantize_rounds_half_to_even():
+    # scale 256: x = (2j + 1) 2^-9 lands on j + 1/2
+    x = np.zeros((2, 64), np.float16)
+    x[0, 0] = 127 * 2.0 ** -8
+    x[1, :6] = np.array([1, 3, 5, -1, -3, -5]) * 2.0 ** -9
+    (c,), _ = ol.quantize(x)
+    assert list(c[1, :6]) == [0, 2, 2, 0, -2, -2]
+
+
 def test_topk_brute_force_with_ties():
-    GR = synth.unit_rows_f16(6, seed=1).astype(np.float64)
-    GD = synth.unit_rows_f16(40, seed=2, n_dup=8).astype(np.float64)
-    GD[5] = GR[0]
-    GD[30] = GR[0]  # exact tie at the top for range 0
-    got = ol.topk(GR, GD, 7)
+    qr, xr = _codes_and_rows(6, seed=3)
+    qd, xd = _codes_and_rows(40, seed=4, n_dup=8)
+    qd[5] = qd[30] = qr[0] * (qr[0] != 127)  # an exact tie at the top for range 0 ...
+    qd[5, 0] = qd[30, 0] = 127               # ... keeping 127 as the largest code
+    xd = (qd * 2.0 ** -8).astype(np.float16)
+    got = ol.topk(xr, xd, 7)
     for q in range(6):
-        scores = [(-(GR[q] @ GD[j]), j) for j in range(40)]
+        scores = [(-sum(int(a) * int(b) for a, b in zip(qr[q], qd[j])), j) for j in range(40)]
         ref = [j for _, j in sorted(scores)[:7]]
         assert list(got[q]) == ref
     assert got[0][0] == 5 and got[0][1] == 30
+
+
+def test_topk_equals_exact_ranking_where_separated():
+    """Where the exact (fp64) similarities of the k-th and the (k+1)-th domain differ by
+    more than twice the quantization error bound, the int8 proposals are the exact top-k."""
+    GR = synth.unit_rows_f16(300, seed=5).astype(np.float64)
+    GD = synth.unit_rows_f16(30, seed=6).astype(np.float64)
+    k = 2
+    (_, _), s = ol.quantize(GR, GD)
+    s = float(s)
+    got = ol.topk(GR, GD, k)
+    S = GR @ GD.T
+    checked = 0
+    for q in range(300):
+        # |q_r . q_d / s^2 - x_r . x_d| <= (|x_r|_1 + max |x_d|_1) / (2 s) + 64 / (4 s^2)
+        bound = (np.abs(GR[q]).sum() + np.abs(GD).sum(1).max()) / (2 * s) + 16 / s ** 2
+        order = np.argsort(-S[q], kind="stable")
+        if S[q, order[k - 1]] - S[q, order[k]] > 2 * bound:
+            assert set(got[q]) == set(order[:k].tolist())
+            checked += 1
+    assert checked >= 20
 
 
 @pytest.fixture(scope="module")
