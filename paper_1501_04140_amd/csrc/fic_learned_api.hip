@@ -456,16 +456,24 @@ FIC_API int fic_encode_level_learned(fic_mlp* M, const uint8_t* img, int32_t H, 
         if ((rc = topk_launch(M, G16, nr, G16 + (int64_t)nr * 64, nd, topk, cand, nullptr, st))) return rc;
     }
     int32_t* fb_count = ws->ctrl->act_count;  // level 0 of this workspace
+    // the pool of the exhaustive fallback (every domain of the level): its
+    // columns, S and A' also serve the rescoring when the level has the grid
+    // matchers' layout
+    std::vector<Lvl> t{lv};
+    if ((rc = launch_pool_phase(nullptr, t, ws->T, false, st))) return rc;
     {
         ProfScope ps("learned_rescore", st);
-        k_rescore<<<nr, 256, 0, st>>>(img, pitch, W, L, gx, nd, cand, topk, nr, ks, out);
+        if (lv.var == kVarMfma)
+            k_rescore<1><<<nr, 256, 0, st>>>(img, pitch, W, L, gx, nd, lv.dh, lv.sd, lv.ad, cand, topk, nr, ks, out);
+        else
+            k_rescore<0><<<nr, 256, 0, st>>>(img, pitch, W, L, gx, nd, nullptr, nullptr, nullptr, cand, topk, nr,
+                                             ks, out);
         k_fallback_list<<<1, 1024, 0, st>>>(out, nr, W, keep_threshold(rms_thresh, 8), act, P<int32_t>(M->fbq),
                                             fb_count);
         LAUNCH_CHECK();
     }
     // exhaustive search for the ranges on the fallback list
-    std::vector<Lvl> t{lv};
-    if ((rc = launch_level(nullptr, t, ws->T, false, st))) return rc;
+    if ((rc = launch_match_phase(nullptr, t, st))) return rc;
     {
         ProfScope ps("learned_fallback", st);
         fic_match* tmp = P<fic_match>(M->tmpm);
