@@ -729,7 +729,8 @@ __global__ __launch_bounds__(256) void k_tk_quant(const _Float16* __restrict__ x
 constexpr int kTkLoads = kTkCols * 4 / (kTkWaves * 64);
 static_assert(kTkWaves * kTkLoads * 64 == kTkCols * 4, "a stage is whole 16-byte chunks per lane");
 
-__device__ inline int tk_chunk(int c, int u) { return c * 4 + (u ^ ((c >> 2) & 3)); }
+__device__ inline int tk_swz(int c) { return (c >> 2) & 3; }
+__device__ inline int tk_chunk(int c, int u) { return c * 4 + (u ^ tk_swz(c)); }
 
 struct TkWave {
     int nq, lo, hi, wave, lane, g, c16, wq0;
@@ -755,7 +756,7 @@ __device__ __forceinline__ bool tk_setup(TkWave& w, const int8_t* __restrict__ Q
         w.af[rt] = *reinterpret_cast<const v4i*>(QR + (int64_t)min(w.wq0 + 16 * rt + w.c16, nq - 1) * 64 + 16 * w.g);
 #pragma unroll
     for (int l = 0; l < kTkLoads; ++l) {
-        const int i = (kTkLoads * w.wave + l) * 64 + w.lane, col = i >> 2, u = (i & 3) ^ ((col >> 2) & 3);
+        const int i = (kTkLoads * w.wave + l) * 64 + w.lane, col = i >> 2, u = (i & 3) ^ tk_swz(col);
         w.off[l] = (uint32_t)(col * 64 + 16 * u);
     }
     return true;
@@ -888,9 +889,11 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __re
     __shared__ int32_t sCnt[kTkWaves][WR];
     // list entries on their way to global memory: stored in batches, because
     // the wait for a stage's copy would also wait for every store before it
-    constexpr int kQ = 128;
+    // (room for a whole tile's elements beyond the flush mark)
+    constexpr int kQ = 128 + 4 * 64;
     __shared__ uint32_t sQi[kTkWaves][kQ];  // list position (row * kTkCap + slot)
     __shared__ uint64_t sQk[kTkWaves][kQ];  // key
+    __shared__ int32_t sQn[kTkWaves];       // queued entries
     TkWave w;
     if (!tk_setup(w, QR, nq, nk)) return;
     const int c = blockIdx.y, wave = w.wave, lane = w.lane, g = w.g, c16 = w.c16;
@@ -907,12 +910,14 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __re
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) cs[rt] = -*reinterpret_cast<const v4i*>(&sTh[wave][16 * rt + 4 * g]);
     uint64_t* wlist = list + ((int64_t)c * nq + w.wq0) * kTkCap;
-    const uint32_t below = (1u << c16) - 1u;
-    int qn = 0;  // queued list entries (the same in every lane)
+    if (lane == 0) sQn[wave] = 0;
+    wave_lds_sync();
     auto flush = [&] {
         wave_lds_sync();
+        const int qn = sQn[wave];
         for (int j = lane; j < qn; j += 64) wlist[sQi[wave][j]] = sQk[wave][j];
-        qn = 0;
+        wave_lds_sync();
+        if (lane == 0) sQn[wave] = 0;
         wave_lds_sync();
     };
     // the rows whose list could overflow keep their best 32
@@ -941,64 +946,59 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __re
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) cs[rt] = -*reinterpret_cast<const v4i*>(&sTh[wave][16 * rt + 4 * g]);
     };
-    // a stage: the screen of every tile without a branch (per row tile one
-    // maximum and one ballot: a bit per (tile, row tile) with an element at or
-    // above theta; a branch per tile would keep the next tile's LDS reads from
-    // being issued early), then the flagged row tiles again and their
-    // elements above the list threshold queued. (LDS operations of one wave
-    // take effect in program order, so the counts and thresholds need no
-    // fence here.)
+    // a stage: the screen of every tile without a branch (one maximum per
+    // lane and one ballot: a bit per tile with an element at or above theta;
+    // a branch per tile would keep the next tile's LDS reads from being issued
+    // early), then the flagged tiles again and their elements above the list
+    // threshold queued. (LDS operations of one wave take effect in program
+    // order, so the counts and thresholds need no fence here.)
     tk_stages(w, QD, sD, [&](const v4i* cD, int base) {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) asm volatile("" : "+v"(cs[rt]));
-        uint32_t hits = 0;  // bit RT ct + rt
+        uint32_t hits = 0;  // bit ct: tile ct has an element at or above theta
 #pragma unroll
         for (int ct = 0; ct < kTkTiles; ++ct) {
             v4i acc[RT];
             tk_tile(w, cD, ct, cs, acc);
+            int mm = max(max(acc[0][0], acc[0][1]), acc[0][2]);
+            mm = max(mm, acc[0][3]);
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const int mm = max(max(acc[rt][0], acc[rt][1]), max(acc[rt][2], acc[rt][3]));
-                hits |= __ballot(mm >= 0) ? 1u << (RT * ct + rt) : 0u;
+            for (int rt = 1; rt < RT; ++rt) {
+                mm = max(max(mm, acc[rt][0]), acc[rt][1]);
+                mm = max(max(mm, acc[rt][2]), acc[rt][3]);
             }
+            hits |= __ballot(mm >= 0) ? 1u << ct : 0u;
         }
         while (hits) {
-            const int ct = (__builtin_ffs(hits) - 1) / RT;
-            const uint32_t rts = (hits >> (RT * ct)) & ((1u << RT) - 1u);
-            hits &= ~(((1u << RT) - 1u) << (RT * ct));
+            const int ct = __builtin_ffs(hits) - 1;
+            hits &= hits - 1;
             const int col = 16 * ct + c16;
             const v4i b = cD[tk_chunk(col, g)];
             const int kc = base + col;
             const bool colok = kc < w.hi;
-            bool full = false;
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                if (!(rts & (1u << rt))) continue;
                 const v4i x = __builtin_amdgcn_mfma_i32_16x16x64_i8(w.af[rt], b, cs[rt], 0, 0, 0);  // score - theta
+                // each lane lists its own elements at or above theta whose key is
+                // above the row's threshold: slots and queue places from LDS atomics
+                if (colok && max(max(x[0], x[1]), max(x[2], x[3])) >= 0) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (!__ballot(colok && x[e] >= 0)) continue;
-                    const int i = 16 * rt + 4 * g + e;
-                    const uint64_t thr = sThr[wave][i];
-                    const int n = sCnt[wave][i];
-                    const uint64_t key = tk_key((float)(x[e] - cs[rt][e]), kc);
-                    const bool p = colok && x[e] >= 0 && key > thr;
-                    const uint64_t bal = __ballot(p);
-                    if (!bal) continue;
-                    const uint32_t seg = (uint32_t)(bal >> (16 * g)) & 0xffffu;
-                    if (p) {
-                        const int qp = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                        sQi[wave][qp] = (uint32_t)(i * kTkCap + n + __popc(seg & below));
+                    for (int e = 0; e < 4; ++e) {
+                        if (x[e] < 0) continue;
+                        const int i = 16 * rt + 4 * g + e;
+                        const uint64_t key = tk_key((float)(x[e] - cs[rt][e]), kc);
+                        if (key <= sThr[wave][i]) continue;
+                        const int slot = atomicAdd(&sCnt[wave][i], 1);
+                        const int qp = atomicAdd(&sQn[wave], 1);
+                        sQi[wave][qp] = (uint32_t)(i * kTkCap + slot);
                         sQk[wave][qp] = key;
                     }
-                    qn += __popcll(bal);
-                    if (c16 == 0) sCnt[wave][i] = n + __popc(seg);
-                    full |= n + __popc(seg) > kTkCap - 16;
-                    if (qn > kQ - 64) flush();
                 }
             }
-            if (__ballot(full)) prune();
+            // a tile adds at most 16 entries to a row and 4 * 64 to the queue
+            wave_lds_sync();
+            if (__ballot(sCnt[wave][lane] > kTkCap - 16)) prune();
+            if (sQn[wave] > kQ - 4 * 64) flush();
         }
     });
     flush();
