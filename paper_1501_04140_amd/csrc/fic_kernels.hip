@@ -1916,13 +1916,6 @@ __device__ inline uint64_t m8_pack(int64_t F, int pos, int k) {
 
 __device__ inline int64_t m8_unpack_F(uint64_t v) { return (int64_t)(v >> 26) - (1ll << 37); }
 
-// s_b of a packed best, rounded below the exact value (the hardware square
-// root is within a few ulps; kM8Shrink takes off 64 ulps).
-__device__ inline float m8_sigma(uint64_t v) {
-    const int64_t F = m8_unpack_F(v);
-    return F < 0 ? __builtin_amdgcn_sqrtf((float)(-F) * (1.0f / 1600.0f)) * kM8Shrink : 0.0f;
-}
-
 // The exact decision of one candidate (row, pool position) given X = sum r' d'.
 __device__ inline void m8_decide(int row, int pos, int X, const int32_t* nsr, uint64_t* best,
                                  const int64_t* __restrict__ Ad, const uint32_t* __restrict__ Sd,
