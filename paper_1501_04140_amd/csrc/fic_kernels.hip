@@ -1656,8 +1656,8 @@ constexpr int kM8Waves = 4;                            // wavefronts per workgro
 constexpr int m8_row_tiles(bool) { return 4; }
 constexpr int m8_rows(bool f16) { return kM8Waves * 16 * m8_row_tiles(f16); }  // rows per workgroup
 constexpr int kM8RowBits = 6;                           // queue entry: row | position << kM8RowBits
-constexpr int kM8ColTiles = 4;                         // 16-column tiles per LDS stage
-constexpr int kM8Cols = 16 * kM8ColTiles;              // 64 pool domains per LDS stage
+constexpr int kM8ColTiles = 6;                         // 16-column tiles per LDS stage
+constexpr int kM8Cols = 16 * kM8ColTiles;              // 96 pool domains per LDS stage
 constexpr int kM8Chunk = 1024;                         // target pool domains per chunk
 // (1 - 2^-18): a factor that puts an FP32 square root or product (a few ulps
 // of error each) safely below the exact real value.
