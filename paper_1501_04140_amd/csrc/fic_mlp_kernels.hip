@@ -889,7 +889,7 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __re
     __shared__ int32_t sCnt[kTkWaves][WR];
     // list entries on their way to global memory: stored in batches, because
     // the wait for a stage's copy would also wait for every store before it
-    // (room for a whole tile's elements beyond the flush mark)
+    // (room for a row tile's elements, 4 per lane, beyond the flush mark)
     constexpr int kQ = 128 + 4 * 64;
     __shared__ uint32_t sQi[kTkWaves][kQ];  // list position (row * kTkCap + slot)
     __shared__ uint64_t sQk[kTkWaves][kQ];  // key
@@ -994,11 +994,12 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __re
                         sQk[wave][qp] = key;
                     }
                 }
+                // a row tile adds at most 4 entries per lane to the queue
+                wave_lds_sync();
+                if (sQn[wave] > kQ - 4 * 64) flush();
             }
-            // a tile adds at most 16 entries to a row and 4 * 64 to the queue
-            wave_lds_sync();
+            // a tile adds at most 16 entries to a row
             if (__ballot(sCnt[wave][lane] > kTkCap - 16)) prune();
-            if (sQn[wave] > kQ - 4 * 64) flush();
         }
     });
     flush();

@@ -204,6 +204,30 @@ def test_topk_matches_oracle(dev, nq, nk, k, dup):
     assert list(idx[0, :len(top)]) == top
 
 
+@pytest.mark.parametrize("nq,nk", [(70, 5000), (3, 300)])
+def test_topk_all_ties(dev, nq, nk):
+    """Every similarity equal (zero codes): the lists fill and are pruned again and
+    again, and the answer is the k lowest indices; a second query set shares the keys
+    with one nonzero key that must come first."""
+    q = np.zeros((nq, 64), np.float16)
+    keys = np.zeros((nk, 64), np.float16)
+    m = fic.Mlp(synth.mlp_init(0))
+    try:
+        idx, score = m.topk(torch.from_numpy(q).to(dev), torch.from_numpy(keys).to(dev), 32)
+        torch.cuda.synchronize()
+        assert (idx.cpu().numpy() == np.arange(32)[None, :]).all()
+        assert (score.cpu().numpy() == 0).all()
+        q[:, 0] = 1.0
+        keys[nk - 7, 0] = 1.0
+        idx, score = m.topk(torch.from_numpy(q).to(dev), torch.from_numpy(keys).to(dev), 32)
+        torch.cuda.synchronize()
+    finally:
+        m.close()
+    ref = ol.topk(q, keys, 32)
+    assert np.array_equal(idx.cpu().numpy(), ref)
+    assert (ref[:, 0] == nk - 7).all() and (ref[:, 1:] == np.arange(31)[None, :]).all()
+
+
 def gpu_learned(dev, img, theta, L, k, rms=8.0, s_k=oracle.PLAIN_K):
     x = torch.from_numpy(img).to(dev)
     m = fic.Mlp(theta)
