@@ -981,7 +981,8 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __re
                 const v4i x = __builtin_amdgcn_mfma_i32_16x16x64_i8(w.af[rt], b, cs[rt], 0, 0, 0);  // score - theta
                 // each lane lists its own elements at or above theta whose key is
                 // above the row's threshold: slots and queue places from LDS atomics
-                if (colok && max(max(x[0], x[1]), max(x[2], x[3])) >= 0) {
+                const bool has = colok && max(max(x[0], x[1]), max(x[2], x[3])) >= 0;
+                if (has) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (x[e] < 0) continue;
@@ -995,8 +996,10 @@ __global__ __launch_bounds__(kTkWaves * 64) void k_tk_collect(const int8_t* __re
                     }
                 }
                 // a row tile adds at most 4 entries per lane to the queue
-                wave_lds_sync();
-                if (sQn[wave] > kQ - 4 * 64) flush();
+                if (__ballot(has)) {
+                    wave_lds_sync();
+                    if (sQn[wave] > kQ - 4 * 64) flush();
+                }
             }
             // a tile adds at most 16 entries to a row
             if (__ballot(sCnt[wave][lane] > kTkCap - 16)) prune();
