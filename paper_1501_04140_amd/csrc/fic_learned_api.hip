@@ -464,9 +464,9 @@ FIC_API int fic_encode_level_learned(fic_mlp* M, const uint8_t* img, int32_t H, 
     {
         ProfScope ps("learned_rescore", st);
         if (lv.var == kVarMfma)
-            k_rescore<1><<<nr, 256, 0, st>>>(img, pitch, W, L, gx, nd, lv.dh, lv.sd, lv.ad, cand, topk, nr, ks, out);
+            k_rescore<1><<<nr, kRsThreads, 0, st>>>(img, pitch, W, L, gx, nd, lv.dh, lv.sd, lv.ad, cand, topk, nr, ks, out);
         else
-            k_rescore<0><<<nr, 256, 0, st>>>(img, pitch, W, L, gx, nd, nullptr, nullptr, nullptr, cand, topk, nr,
+            k_rescore<0><<<nr, kRsThreads, 0, st>>>(img, pitch, W, L, gx, nd, nullptr, nullptr, nullptr, cand, topk, nr,
                                              ks, out);
         k_fallback_list<<<1, 1024, 0, st>>>(out, nr, W, keep_threshold(rms_thresh, 8), act, P<int32_t>(M->fbq),
                                             fb_count);

@@ -1052,35 +1052,44 @@ __global__ __launch_bounds__(256) void k_tk_merge(const uint64_t* __restrict__ l
 }
 
 // ---------------------------------------------------------------- exact rescoring
-// One workgroup per 8 x 8 range of the grid; thread = (proposal c = tid / 8,
-// isometry t = tid % 8). Evaluates the distance of eq. (1) exactly over the
+// One workgroup per 8 x 8 range of the grid; thread (c = tid / 8, t = tid % 8)
+// takes isometry t of proposals c, c + 16. Evaluates the distance of eq. (1) exactly over the
 // range's proposals, isometries and contrast values (same moment form and tie
 // order as the exhaustive matcher) and writes the match; e_num = -1 when the
 // range has no proposal. The domains' 2x2 sums d' come from the image (COLS
 // 0) or (COLS 1) from the columns that the int8 grid matcher's pool
 // preparation already holds for every domain of the level (h and l, d' =
 // 128 h + l), with S and A'.
+constexpr int kRsThreads = 128;               // threads per range
+constexpr int kRsPairs = kTopK * 8 / kRsThreads;  // (proposal, isometry) pairs per thread
+
 template <int COLS>
-__global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img, int pitch,
-                                                 int W, int L, int gx, int total,
-                                                 const int8_t* __restrict__ Dh, const uint32_t* __restrict__ Sd,
-                                                 const int64_t* __restrict__ Ad,
-                                                 const int32_t* __restrict__ cand, int kc,
-                                                 int nr, KSet ks, fic_match* __restrict__ out) {
+__global__ __launch_bounds__(kRsThreads) void k_rescore(const uint8_t* __restrict__ img, int pitch,
+                                                        int W, int L, int gx, int total,
+                                                        const int8_t* __restrict__ Dh, const uint32_t* __restrict__ Sd,
+                                                        const int64_t* __restrict__ Ad,
+                                                        const int32_t* __restrict__ cand, int kc,
+                                                        int nr, KSet ks, fic_match* __restrict__ out) {
+    constexpr int NW = kRsThreads / 64;
     __shared__ int sr[64];
     __shared__ __align__(16) int srp[8][64];  // <srp[t], d> = <R, T_t d>
     __shared__ __align__(16) int sd[kTopK][64];
-    __shared__ int64_t redF[4], redK[4];
+    __shared__ int64_t redF[NW], redK[NW];
     const int q = blockIdx.x, tid = threadIdx.x;
     if (q >= nr) return;
     const int rgx = W / 8;
     const int y = (q / rgx) * 8, x = (q % rgx) * 8;
     if (tid < 64) sr[tid] = img[(int64_t)(y + (tid >> 3)) * pitch + x + (tid & 7)];
-    const int c = tid >> 3, t = tid & 7;
-    const int j = c < kc ? cand[(int64_t)q * kc + c] : -1;
-    const bool ok = j >= 0 && j < total;
+    // thread (c0, t) takes the pairs (c0 + 16 u, t), u < kRsPairs
+    const int c0 = tid >> 3, t = tid & 7;
+    int jv[kRsPairs];
+#pragma unroll
+    for (int u = 0; u < kRsPairs; ++u) {
+        const int c = c0 + (kRsThreads / 8) * u;
+        jv[u] = c < kc ? cand[(int64_t)q * kc + c] : -1;
+    }
     if constexpr (COLS == 0) {
-        for (int e = tid; e < kTopK * 64; e += 256) {
+        for (int e = tid; e < kTopK * 64; e += kRsThreads) {
             const int cc = e >> 6, m = e & 63;
             const int jj = cc < kc ? cand[(int64_t)q * kc + cc] : -1;
             int v = 0;
@@ -1091,73 +1100,91 @@ __global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img
             sd[cc][m] = v;
         }
     } else {
-        // thread (c, t) takes values 8 t .. 8 t + 7 of proposal c
-        int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (ok) {
-            const uint2 hw = *reinterpret_cast<const uint2*>(Dh + (int64_t)j * 128 + 8 * t);
-            const uint2 lw = *reinterpret_cast<const uint2*>(Dh + (int64_t)j * 128 + 64 + 8 * t);
+        // values 8 t .. 8 t + 7 of each of the thread's proposals
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t hh = (e < 4 ? hw.x : hw.y) >> (8 * (e & 3)), ll = (e < 4 ? lw.x : lw.y) >> (8 * (e & 3));
-                v[e] = 128 * (int)(hh & 255u) + (int)(ll & 255u);
+        for (int u = 0; u < kRsPairs; ++u) {
+            const int c = c0 + (kRsThreads / 8) * u, j = jv[u];
+            int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (j >= 0 && j < total) {
+                const uint2 hw = *reinterpret_cast<const uint2*>(Dh + (int64_t)j * 128 + 8 * t);
+                const uint2 lw = *reinterpret_cast<const uint2*>(Dh + (int64_t)j * 128 + 64 + 8 * t);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t hh = (e < 4 ? hw.x : hw.y) >> (8 * (e & 3)), ll = (e < 4 ? lw.x : lw.y) >> (8 * (e & 3));
+                    v[e] = 128 * (int)(hh & 255u) + (int)(ll & 255u);
+                }
             }
+            *reinterpret_cast<int4*>(&sd[c][8 * t]) = make_int4(v[0], v[1], v[2], v[3]);
+            *reinterpret_cast<int4*>(&sd[c][8 * t + 4]) = make_int4(v[4], v[5], v[6], v[7]);
         }
-        *reinterpret_cast<int4*>(&sd[c][8 * t]) = make_int4(v[0], v[1], v[2], v[3]);
-        *reinterpret_cast<int4*>(&sd[c][8 * t + 4]) = make_int4(v[4], v[5], v[6], v[7]);
     }
     __syncthreads();
     // the range permuted once per isometry: T_t d takes d[src_t(e)] to place e,
     // so R[e] goes to place src_t(e) of copy t
-    for (int i = tid; i < 8 * 64; i += 256) {
+    for (int i = tid; i < 8 * 64; i += kRsThreads) {
         const int tt = i >> 6, e = i & 63;
         srp[tt][iso_src(8, tt, e >> 3, e & 7)] = sr[e];
     }
     __syncthreads();
     int64_t F = INT64_MAX, K = INT64_MAX;
-    // the 8 threads of a candidate (consecutive lanes) each sum one eighth of the
-    // range (and of the domain), then combine; every sum is exact in 32 bits
-    // (S2 <= 64 * 1020^2, |Pc| <= 64 * 255 * 1020)
-    int SR = 0, SR2 = 0, S = 0, S2 = 0;
+    // the 8 threads of a proposal group (consecutive lanes) each sum one eighth
+    // of the range, then combine; every sum is exact in 32 bits (S2 <= 64 *
+    // 1020^2, |Pc| <= 64 * 255 * 1020)
+    int SR = 0, SR2 = 0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int r = sr[8 * t + u];
         SR += r;
         SR2 += r * r;
-        if constexpr (COLS == 0) {
-            const int d = sd[c][8 * t + u];
-            S += d;
-            S2 += d * d;
-        }
     }
 #pragma unroll
     for (int o = 1; o < 8; o <<= 1) {
         SR += __shfl_xor(SR, o, 64);
         SR2 += __shfl_xor(SR2, o, 64);
-        if constexpr (COLS == 0) {
-            S += __shfl_xor(S, o, 64);
-            S2 += __shfl_xor(S2, o, 64);
-        }
     }
-    if (ok) {
-        int Pc = 0;
-        const int4* pr = reinterpret_cast<const int4*>(srp[t]);
-        const int4* pd = reinterpret_cast<const int4*>(sd[c]);
-#pragma unroll 4
-        for (int e = 0; e < 16; ++e) {
-            const int4 a = pr[e], b = pd[e];
-            Pc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
-        }
-        int64_t Ap;
+#pragma unroll
+    for (int u = 0; u < kRsPairs; ++u) {
+        const int c = c0 + (kRsThreads / 8) * u, j = jv[u];
+        int S = 0, S2 = 0;
         if constexpr (COLS == 0) {
-            Ap = 64 * (int64_t)S2 - (int64_t)S * S;
-        } else {
-            S = (int)Sd[j];
-            Ap = Ad[j];
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                const int d = sd[c][8 * t + w];
+                S += d;
+                S2 += d * d;
+            }
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                S += __shfl_xor(S, o, 64);
+                S2 += __shfl_xor(S2, o, 64);
+            }
         }
-        const int64_t Bp = 64 * (int64_t)Pc - (int64_t)SR * S;
-        int s;
-        best_contrast(Bp, Ap, ks, F, s);
-        K = make_key(j, t, s, (uint32_t)S);
+        if (j >= 0 && j < total) {
+            int Pc = 0;
+            const int4* pr = reinterpret_cast<const int4*>(srp[t]);
+            const int4* pd = reinterpret_cast<const int4*>(sd[c]);
+#pragma unroll 4
+            for (int e = 0; e < 16; ++e) {
+                const int4 a = pr[e], b = pd[e];
+                Pc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+            }
+            int64_t Ap;
+            if constexpr (COLS == 0) {
+                Ap = 64 * (int64_t)S2 - (int64_t)S * S;
+            } else {
+                S = (int)Sd[j];
+                Ap = Ad[j];
+            }
+            const int64_t Bp = 64 * (int64_t)Pc - (int64_t)SR * S;
+            int64_t Fu;
+            int s;
+            best_contrast(Bp, Ap, ks, Fu, s);
+            const int64_t Ku = make_key(j, t, s, (uint32_t)S);
+            if (pair_less(Fu, Ku, F, K)) {
+                F = Fu;
+                K = Ku;
+            }
+        }
     }
     // workgroup argmin of (F, K)
     for (int o = 32; o > 0; o >>= 1) {
@@ -1173,7 +1200,7 @@ __global__ __launch_bounds__(256) void k_rescore(const uint8_t* __restrict__ img
     }
     __syncthreads();
     if (tid != 0) return;
-    for (int w = 1; w < 4; ++w)
+    for (int w = 1; w < NW; ++w)
         if (pair_less(redF[w], redK[w], F, K)) {
             F = redF[w];
             K = redK[w];
