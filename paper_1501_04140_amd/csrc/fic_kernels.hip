@@ -3021,8 +3021,24 @@ __global__ void kt_act_from_yx(Lvl a0, const Lvl* __restrict__ tab, const int32_
 
 template <int L, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_score_cells(Lvl a0, const Lvl* __restrict__ tab,
-                                                              const int64_t* __restrict__ T) {
+                                                              const int64_t* __restrict__ T, int fill_act) {
     FIC_LV;
+    if (fill_act) {
+        // also the level's active list (every range of the grid) and the
+        // encode's counters, as kt_act_full does: one launch fewer on level 0
+        const int nthr = gridDim.x * gridDim.y * kBlock;
+        const int t0 = (blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+        const int gxr = a.W / a.B, n = (a.H / a.B) * gxr;
+        if (t0 == 0) {
+            a.ctrl->act_count[a.lv] = n;
+            a.ctrl->n_codes = 0;
+            a.ctrl->lvl_base[a.lv] = 0;
+        }
+        for (int q = t0; q < n; q += nthr) {
+            const int ry = q / gxr, rx = q - ry * gxr;
+            a.act[q] = ((ry * a.B) << 16) | (rx * a.B);
+        }
+    }
     k_pool_score_cells_body<L>(a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl);
 }
 

@@ -576,8 +576,13 @@ int max_over(const std::vector<Lvl>& h, F f) {
 // cell kernel scores level 3's 259081 domains in 5 us)
 constexpr int kScoreCellsMin = 0;
 
+// Whether the score step of this level runs the cell kernel (which can also
+// write level 0's active list).
+bool score_by_cells(const Lvl& a) { return a.pmode != 2 && 4 * a.L == 2 * a.B; }
+
 template <int SIDE, bool TAB>
-void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
+void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st,
+                  bool fill_act = false) {
     if (h[0].pmode == 2) {
         const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });
         kt_pool_var<SIDE, TAB><<<dim3(gx, 1, h.size()), kBlock, 0, st>>>(h[0], dt);
@@ -590,7 +595,7 @@ void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hi
     if (cells) {
         const int bx = max_over(h, [](const Lvl& a) { return cdiv(a.gx, kScTX); });
         const int by = max_over(h, [](const Lvl& a) { return cdiv(a.gy, kScTY); });
-        kt_pool_score_cells<L, TAB><<<dim3(bx, by, h.size()), kBlock, 0, st>>>(h[0], dt, T);
+        kt_pool_score_cells<L, TAB><<<dim3(bx, by, h.size()), kBlock, 0, st>>>(h[0], dt, T, fill_act ? 1 : 0);
         return;
     }
     const int gx = max_over(h, [](const Lvl& a) { return cdiv((int64_t)a.total * ScoreShape<SIDE>::TPD, kBlock); });
@@ -668,13 +673,14 @@ void launch_match(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
 // (which reads only the level's arguments, so levels of different B can share
 // its launches), and the moments.
 template <bool TAB>
-void launch_score_step(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st) {
+void launch_score_step(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hipStream_t st,
+                       bool fill_act = false) {
     ProfScope ps(level_label("pool_score", h[0].B), st);
     switch (2 * h[0].B) {
-        case 4: launch_score<4, TAB>(dt, h, T, st); break;
-        case 8: launch_score<8, TAB>(dt, h, T, st); break;
-        case 16: launch_score<16, TAB>(dt, h, T, st); break;
-        default: launch_score<32, TAB>(dt, h, T, st); break;
+        case 4: launch_score<4, TAB>(dt, h, T, st, fill_act); break;
+        case 8: launch_score<8, TAB>(dt, h, T, st, fill_act); break;
+        case 16: launch_score<16, TAB>(dt, h, T, st, fill_act); break;
+        default: launch_score<32, TAB>(dt, h, T, st, fill_act); break;
     }
 }
 
@@ -721,9 +727,9 @@ void launch_prep_step(const Lvl* dt, const std::vector<Lvl>& h, bool filtered, h
 
 template <bool TAB>
 int launch_pool_phase_t(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
-                        hipStream_t st) {
+                        hipStream_t st, bool fill_act = false) {
     if (filtered) {
-        launch_score_step<TAB>(dt, h, T, st);
+        launch_score_step<TAB>(dt, h, T, st, fill_act);
         launch_select_steps<TAB>(dt, h, st);
     }
     launch_prep_step<TAB>(dt, h, filtered, st);
@@ -744,9 +750,9 @@ int launch_match_phase_t(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t s
 }
 
 int launch_pool_phase(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, bool filtered,
-                      hipStream_t st) {
-    return dt ? launch_pool_phase_t<true>(dt, h, T, filtered, st)
-              : launch_pool_phase_t<false>(dt, h, T, filtered, st);
+                      hipStream_t st, bool fill_act = false) {
+    return dt ? launch_pool_phase_t<true>(dt, h, T, filtered, st, fill_act)
+              : launch_pool_phase_t<false>(dt, h, T, filtered, st, fill_act);
 }
 
 int launch_match_phase(const Lvl* dt, const std::vector<Lvl>& h, hipStream_t st) {
@@ -862,13 +868,15 @@ int launch_quadtree_one(const std::vector<Lvl>& t, const int64_t* T, bool filter
                         Workspace& fork) {
     const int nl = (int)t.size();
     int rc;
-    {
+    // level 0's active list: written by its score kernel when that is the cell kernel
+    const bool fill = filtered && score_by_cells(t[0]);
+    if (!fill) {
         const int gx = cdiv((t[0].H / t[0].B) * (t[0].W / t[0].B), kBlock);
         kt_act_full<false><<<gx, kBlock, 0, st>>>(t[0], nullptr, 1);
     }
     HIP_TRY(hipEventRecord(fork.ev_fork, st));
     const std::vector<Lvl> h0{t[0]};
-    if ((rc = launch_pool_phase(nullptr, h0, T, filtered, st))) return rc;
+    if ((rc = launch_pool_phase(nullptr, h0, T, filtered, st, fill))) return rc;
     if ((rc = launch_match_phase(nullptr, h0, st))) return rc;
     if ((rc = launch_quad(nullptr, h0, st))) return rc;
     // level 1
