@@ -271,6 +271,25 @@ __device__ inline int pool_mode(int passed, int total, int min_pool) {
     return passed >= min_pool ? 0 : 1;
 }
 
+// Calls f(i, key[i]) for i = i0 + t, i0 + t + nt, ... below i1 (t = this
+// thread's index among nt), issuing KLD loads before the first call, so that a
+// thread waits for one load latency per KLD keys instead of one per key.
+template <int KLD, typename F>
+__device__ __forceinline__ void for_each_key(const int64_t* __restrict__ key, int i0, int i1, int t,
+                                             int nt, F f) {
+    for (int b = i0 + t; b < i1; b += KLD * nt) {
+        uint64_t v[KLD];
+#pragma unroll
+        for (int u = 0; u < KLD; ++u) {
+            const int i = b + u * nt;
+            v[u] = i < i1 ? (uint64_t)key[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < KLD; ++u)
+            if (b + u * nt < i1) f(b + u * nt, v[u]);
+    }
+}
+
 // Floor, step 1. Workgroup b takes keys [b*chunk, (b+1)*chunk) and finds the
 // bucket of key >> shift (shift puts every key below 2^(shift+12)) holding its
 // own r-th smallest key. The chunk alone has r keys not above that bucket's
@@ -291,8 +310,9 @@ __device__ __forceinline__ void k_floor_bound_body(const int64_t* __restrict__ k
         s_cum = 0;
     }
     __syncthreads();
-    for (int i = lo + threadIdx.x; i < hi; i += kBlock)
-        atomicAdd(&h[min((uint64_t)key[i] >> shift, (uint64_t)(kSelBins - 1))], 1u);
+    for_each_key<8>(key, lo, hi, threadIdx.x, kBlock, [&](int, uint64_t u) {
+        atomicAdd(&h[min(u >> shift, (uint64_t)(kSelBins - 1))], 1u);
+    });
     __syncthreads();
     constexpr int per = kSelBins / kBlock;
     uint32_t mine = 0;
@@ -568,7 +588,7 @@ constexpr int kSelDirect = 16384;  // grid domains the select takes directly (ke
 // only keys are staged), and the threshold and whole-grid pools are compacted
 // here too.
 __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ key, int total,
-                                                       int min_pool, int r,
+                                                       int min_pool, int r, int shift,
                                                        int32_t* __restrict__ pool, Ctrl* ctrl,
                                                        bool direct, int64_t M) {
     // staged keys; indices (non-direct candidates only) in the upper part
@@ -578,7 +598,6 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
     __shared__ uint32_t h[kSelBins];
     __shared__ int s_w[2][16];
     __shared__ int s_wl[16], s_wt[16];
-    __shared__ uint64_t s_wmax[16];
     __shared__ uint64_t s_prefix;
     __shared__ uint32_t s_rank;
     __shared__ int s_lo, s_done, s_c0, s_c1;
@@ -615,44 +634,75 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
     if (mode == 1) {
         const int C = direct ? total : ctrl->pool_count;
         const bool staged = direct || C <= kSelStage;
-        uint64_t kmax = 0;
-        if (staged)
-            for (int i = tid; i < C; i += nt) {
-                const uint64_t u = (uint64_t)key[direct ? i : pool[i]];
-                if (!direct) sj[i] = pool[i];
-                sk[i] = u;
-                kmax = u > kmax ? u : kmax;
-            }
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) {
-            const uint64_t o = __shfl_xor(kmax, m, 64);
-            kmax = o > kmax ? o : kmax;
-        }
-        if (lane == 0) s_wmax[wid] = kmax;
-        if (tid == 0) {
-            s_prefix = 0;
-            s_rank = (uint32_t)r;
-            s_done = 0;
-            s_lo = 0;
-        }
-        for (int i = tid; i < kSelBins; i += nt) h[i] = 0u;
-        __syncthreads();
-        uint64_t ub = ctrl->cut_bound;
-        if (direct) {
-            ub = 0;
-#pragma unroll
-            for (int w = 0; w < 16; ++w) ub = s_wmax[w] > ub ? s_wmax[w] : ub;
-        }
+        // The first digit's range is known before staging: every key of a
+        // whole grid is below 2^(shift + kSelBits), every candidate is at most
+        // cut_bound. So the first histogram is taken while staging.
+        const uint64_t ub = direct ? (1ull << min(shift + kSelBits, 63)) - 1ull : ctrl->cut_bound;
         const int top = min(62, ub ? 63 - __clzll((long long)ub) : 0);
+        {
+            for (int i = tid; i < kSelBins; i += nt) h[i] = 0u;
+            if (tid == 0) {
+                s_prefix = 0;
+                s_rank = (uint32_t)r;
+                s_done = 0;
+                s_lo = 0;
+            }
+            __syncthreads();
+            const int p0 = top - (kSelBits - 1), lo0 = max(p0, 0), hs0 = p0 + kSelBits;
+            const uint32_t dmask0 = (1u << (hs0 - lo0)) - 1u;
+            const auto first_digit = [&](uint64_t u) {
+                if ((u >> hs0) == 0) atomicAdd(&h[(uint32_t)(u >> lo0) & dmask0], 1u);
+            };
+            if (staged && direct) {
+                for_each_key<8>(key, 0, C, tid, nt, [&](int i, uint64_t u) {
+                    sk[i] = u;
+                    first_digit(u);
+                });
+            } else if (staged) {
+                // the candidates' indices first (8 loads in flight), then their keys
+                constexpr int KLD = 8;
+                for (int b = tid; b < C; b += KLD * nt) {
+                    int j[KLD];
+                    uint64_t v[KLD];
+#pragma unroll
+                    for (int u = 0; u < KLD; ++u) j[u] = b + u * nt < C ? pool[b + u * nt] : 0;
+#pragma unroll
+                    for (int u = 0; u < KLD; ++u) v[u] = b + u * nt < C ? (uint64_t)key[j[u]] : 0ull;
+#pragma unroll
+                    for (int u = 0; u < KLD; ++u)
+                        if (b + u * nt < C) {
+                            sj[b + u * nt] = j[u];
+                            sk[b + u * nt] = v[u];
+                            first_digit(v[u]);
+                        }
+                }
+            }
+            __syncthreads();
+        }
         int par = 0;
         for (int p = top - (kSelBits - 1);; p -= kSelBits, par ^= 1) {
             const int lo = max(p, 0);
             const int hs = p + kSelBits;  // bits >= hs are already decided
             const uint32_t dmask = (1u << (hs - lo)) - 1u;
             const uint64_t prefix = s_prefix;
-            for (int i = tid; i < C; i += nt) {
-                const uint64_t u = staged ? sk[i] : (uint64_t)key[pool[i]];
-                if ((u >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(u >> lo) & dmask], 1u);
+            if (staged && p == top - (kSelBits - 1)) {
+                // first digit: histogram taken while staging
+            } else if (staged) {
+                // 4 LDS reads in flight per thread
+                for (int b = tid; b < C; b += 4 * nt) {
+                    uint64_t v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = b + u * nt < C ? sk[b + u * nt] : 0ull;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (b + u * nt < C && (v[u] >> hs) == (prefix >> hs))
+                            atomicAdd(&h[(uint32_t)(v[u] >> lo) & dmask], 1u);
+                }
+            } else {
+                for (int i = tid; i < C; i += nt) {
+                    const uint64_t u = (uint64_t)key[pool[i]];
+                    if ((u >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(u >> lo) & dmask], 1u);
+                }
             }
             __syncthreads();
             const uint32_t rank = s_rank;
@@ -693,11 +743,19 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
             // and equal to the cut, then (after the waves' totals) its writes
             const int S = (C + 15) / 16, wb = min(C, wid * S), we = min(C, wb + S);
             int nl = 0, ntie = 0;
-            for (int i0 = wb; i0 < we; i0 += 64) {
-                const int i = i0 + lane;
-                const uint64_t u = i < we ? sk[i] & hmask : ~0ull;
-                nl += __popcll(__ballot(i < we && u < cut));
-                ntie += __popcll(__ballot(i < we && u == cut));
+            for (int i0 = wb; i0 < we; i0 += 4 * 64) {
+                uint64_t v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * 64 + lane;
+                    v[u] = i < we ? sk[i] & hmask : ~0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = i0 + u * 64 + lane < we;
+                    nl += __popcll(__ballot(in && v[u] < cut));
+                    ntie += __popcll(__ballot(in && v[u] == cut));
+                }
             }
             if (lane == 0) {
                 s_wl[wid] = nl;
@@ -710,16 +768,24 @@ __device__ __forceinline__ void k_floor_select_body(const int64_t* __restrict__ 
                 lr += w < wid ? s_wl[w] : 0;
                 tr += w < wid ? s_wt[w] : 0;
             }
-            for (int i0 = wb; i0 < we; i0 += 64) {
-                const int i = i0 + lane;
-                const uint64_t u = i < we ? sk[i] & hmask : ~0ull;
-                const bool less = i < we && u < cut, tie = i < we && u == cut;
-                const uint64_t bl = __ballot(less), bt = __ballot(tie);
-                const int l = lr + __popcll(bl & below), t = tr + __popcll(bt & below);
-                if (less) pool[l + min(t, take)] = direct ? i : sj[i];
-                if (tie && t < take) pool[l + t] = direct ? i : sj[i];
-                lr += __popcll(bl);
-                tr += __popcll(bt);
+            for (int i0 = wb; i0 < we; i0 += 4 * 64) {
+                uint64_t v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * 64 + lane;
+                    v[u] = i < we ? sk[i] & hmask : ~0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * 64 + lane;
+                    const bool less = i < we && v[u] < cut, tie = i < we && v[u] == cut;
+                    const uint64_t bl = __ballot(less), bt = __ballot(tie);
+                    const int l = lr + __popcll(bl & below), t = tr + __popcll(bt & below);
+                    if (less) pool[l + min(t, take)] = direct ? i : sj[i];
+                    if (tie && t < take) pool[l + t] = direct ? i : sj[i];
+                    lr += __popcll(bl);
+                    tr += __popcll(bt);
+                }
             }
         } else {
             // more candidates than LDS holds: rounds of 1024 in index order,
@@ -3101,7 +3167,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_scatter(Lvl a0, const Lvl* __r
 template <bool TAB>
 __global__ __launch_bounds__(1024) void kt_floor_select(Lvl a0, const Lvl* __restrict__ tab, int direct) {
     FIC_LV;
-    k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.pool, a.pctrl,
+    k_floor_select_body(a.key, a.total, a.min_pool, a.rank, a.sel_shift, a.pool, a.pctrl,
                         direct && a.total <= kSelDirect, a.M);
 }
 
