@@ -91,6 +91,9 @@ struct Lvl {
     int32_t* srp;
     int64_t* gb;  // MFMA grid matchers: each range's best F so far over all pool chunks
     int2* rc;     // int8 MFMA grid matcher: each range's row offset c and sum |r' - c|
+    // optional, MFMA grid matchers: per range of the grid (grid order), a match
+    // already reached (e_num >= 0) whose F starts the range's bound gb
+    const fic_match* gbseed;
     int8_t* dh;
     int8_t* dl;
     float* gd;

@@ -164,29 +164,43 @@ __device__ __forceinline__ void k_pool_score_cells_body(const uint8_t* __restric
     if (dx0 >= gx || dy0 >= gy) return;
     for (int i = threadIdx.x; i <= NPIX; i += kBlock) sT[i] = T[i];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int t = wid; t < NCH; t += kBlock / 64) {
-        const int cr = t / XCH, lc = (t % XCH) * CPW + lane / L;
-        const int cy = dy0 + cr, cx = dx0 + lc;
-        uint64_t acc = 0;
-        if (lc < CX && cy < gy + 3 && cx < gx + 3) {
+    // kChunks chunks per wave at a time, their loads all in flight. Cells
+    // (cy, cx) with cy < gy + 3 and cx < gx + 3 lie inside the image ((gy + 3) L
+    // = H), so a chunk's addresses are clamped to such a cell and every load is
+    // issued; cells outside the tile or the grid count zero.
+    constexpr int kChunks = 4, NWV = kBlock / 64;
+    for (int t0 = wid; t0 < NCH; t0 += kChunks * NWV) {
+        uint32_t v[kChunks][L];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const int t = t0 + c * NWV;
+            const int cr = t / XCH, lc = (t % XCH) * CPW + lane / L;
+            const int cy = min(dy0 + cr, gy + 2), cx = min(dx0 + lc, gx + 2);
             const uint8_t* p = img + (int64_t)cy * L * pitch + (int64_t)cx * L + lane % L;
-            uint32_t v[L];
 #pragma unroll
-            for (int r = 0; r < L; ++r) v[r] = p[(int64_t)r * pitch];
-#pragma unroll
-            for (int r = 0; r < L; ++r) acc += 1ull << (8 * (v[r] >> 5));
+            for (int r = 0; r < L; ++r) v[c][r] = p[(int64_t)r * pitch];
         }
 #pragma unroll
-        for (int m = 1; m < L; m <<= 1) acc += __shfl_xor(acc, m, 64);
-        if (lane % L == 0 && lc < CX) {
-            uint64_t lo = 0, hi = 0;
+        for (int c = 0; c < kChunks; ++c) {
+            const int t = t0 + c * NWV;
+            const int cr = t / XCH, lc = (t % XCH) * CPW + lane / L;
+            const int cy = dy0 + cr, cx = dx0 + lc;
+            uint64_t acc = 0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                lo |= ((acc >> (8 * b)) & 0xffull) << (16 * b);
-                hi |= ((acc >> (8 * (b + 4))) & 0xffull) << (16 * b);
+            for (int r = 0; r < L; ++r) acc += 1ull << (8 * (v[c][r] >> 5));
+            if (!(t < NCH && lc < CX && cy < gy + 3 && cx < gx + 3)) acc = 0;
+#pragma unroll
+            for (int m = 1; m < L; m <<= 1) acc += __shfl_xor(acc, m, 64);
+            if (t < NCH && lane % L == 0 && lc < CX) {
+                uint64_t lo = 0, hi = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    lo |= ((acc >> (8 * b)) & 0xffull) << (16 * b);
+                    hi |= ((acc >> (8 * (b + 4))) & 0xffull) << (16 * b);
+                }
+                sc[(cr * CX + lc) * 2] = lo;
+                sc[(cr * CX + lc) * 2 + 1] = hi;
             }
-            sc[(cr * CX + lc) * 2] = lo;
-            sc[(cr * CX + lc) * 2 + 1] = hi;
         }
     }
     __syncthreads();
@@ -1744,7 +1758,8 @@ __device__ __forceinline__ void k_range_prep_m8_body(const uint8_t* __restrict__
                                                           int32_t* __restrict__ SRp,
                                                           int64_t* __restrict__ CR,
                                                           int64_t* __restrict__ GB,
-                                                          int2* __restrict__ RC) {
+                                                          int2* __restrict__ RC,
+                                                          const fic_match* __restrict__ seed, int W) {
     constexpr int B = 8, n = 64;
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= 8 * *act_count) return;
@@ -1825,7 +1840,15 @@ __device__ __forceinline__ void k_range_prep_m8_body(const uint8_t* __restrict__
             }
         SR[q] = s;
         SRp[q] = s - 128 * n;
-        CR[q] = (int64_t)n * s2 - (int64_t)s * s;
+        const int64_t cr = (int64_t)n * s2 - (int64_t)s * s;
+        CR[q] = cr;
+        if (seed) {
+            // a match already reached for this range (e_num = F + 1600 C) bounds
+            // its best F from the start: the screen still passes every element
+            // with F at or below it, so the search's result is unchanged
+            const int64_t e = seed[(int64_t)((yx >> 16) / B) * (W / B) + (yx & 0xffff) / B].e_num;
+            if (e >= 0) GB[q] = min((int64_t)0, e - 1600 * cr);
+        }
     }
 }
 
@@ -3204,10 +3227,10 @@ __global__ __launch_bounds__(kBlock) void kt_range_prep_i8(Lvl a0, const Lvl* __
     FIC_LV;
     if (a.var == kVarMfma16)
         k_range_prep_m8_body<true>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr, a.gb,
-                                   a.rc);
+                                   a.rc, a.gbseed, a.W);
     else
         k_range_prep_m8_body<false>(a.img, a.pitch, a.act, a.ctrl->act_count + a.lv, a.ar, a.sr, a.srp, a.cr, a.gb,
-                                    a.rc);
+                                    a.rc, a.gbseed, a.W);
 }
 
 template <int B, bool TAB>

@@ -472,7 +472,9 @@ FIC_API int fic_encode_level_learned(fic_mlp* M, const uint8_t* img, int32_t H, 
                                             fb_count);
         LAUNCH_CHECK();
     }
-    // exhaustive search for the ranges on the fallback list
+    // exhaustive search for the ranges on the fallback list, each range's
+    // bound started at its rescored match
+    t[0].gbseed = out;
     if ((rc = launch_match_phase(nullptr, t, st))) return rc;
     {
         ProfScope ps("learned_fallback", st);
