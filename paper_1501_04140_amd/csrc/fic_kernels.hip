@@ -147,20 +147,37 @@ __device__ __forceinline__ void k_pool_score_body(const uint8_t* __restrict__ im
 // Each cell is read once per tile instead of once per domain that covers it.
 constexpr int kScTX = 64, kScTY = kBlock / kScTX;
 
+// LDS of the cell kernel at cell side L.
 template <int L>
-__device__ __forceinline__ void k_pool_score_cells_body(const uint8_t* __restrict__ img, int pitch,
+struct CellSmem {
+    static constexpr int CX = kScTX + 3, CY = kScTY + 3;  // cells of the tile
+    uint64_t sc[CY * CX * 2];                              // cells: bins 0-3 | bins 4-7, 16 bits each
+    uint64_t sh[CY * kScTX * 2];                           // sums of 4 cells along x
+    int64_t sT[16 * L * L + 1];                            // the entropy table up to a domain's pixels
+};
+union CellSmemAny {
+    CellSmem<1> l1;
+    CellSmem<2> l2;
+    CellSmem<4> l4;
+    CellSmem<8> l8;
+};
+
+// Tile (tbx, tby) of the level's domain grid.
+template <int L>
+__device__ __forceinline__ void k_pool_score_cells_body(CellSmem<L>& sm, int tbx, int tby,
+                                                             const uint8_t* __restrict__ img, int pitch,
                                                              int gx, int gy,
                                                              const int64_t* __restrict__ T, int64_t M,
                                                              int64_t* __restrict__ key, Ctrl* ctrl) {
-    constexpr int CX = kScTX + 3, CY = kScTY + 3;  // cells of the tile
+    constexpr int CX = CellSmem<L>::CX, CY = CellSmem<L>::CY;
     constexpr int NPIX = 16 * L * L;               // pixels of a domain
     constexpr int CPW = 64 / L;                    // cells across a wave's 64 pixels
     constexpr int XCH = (CX + CPW - 1) / CPW;      // wave chunks per row of cells
     constexpr int NCH = CY * XCH;
-    __shared__ uint64_t sc[CY * CX * 2];           // cells: bins 0-3 | bins 4-7, 16 bits each
-    __shared__ uint64_t sh[CY * kScTX * 2];        // sums of 4 cells along x
-    __shared__ int64_t sT[NPIX + 1];
-    const int dx0 = blockIdx.x * kScTX, dy0 = blockIdx.y * kScTY;
+    uint64_t* const sc = sm.sc;
+    uint64_t* const sh = sm.sh;
+    int64_t* const sT = sm.sT;
+    const int dx0 = tbx * kScTX, dy0 = tby * kScTY;
     if (dx0 >= gx || dy0 >= gy) return;
     for (int i = threadIdx.x; i <= NPIX; i += kBlock) sT[i] = T[i];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -3108,27 +3125,52 @@ __global__ void kt_act_from_yx(Lvl a0, const Lvl* __restrict__ tab, const int32_
     k_act_from_yx_body(a.act, yx, n, a.H, a.W, a.B, a.ctrl);
 }
 
+// The level's active list (every range of the grid) and the encode's
+// counters, as kt_act_full writes them, from thread t0 of nthr.
+__device__ __forceinline__ void act_full_part(const Lvl& a, int t0, int nthr) {
+    const int gxr = a.W / a.B, n = (a.H / a.B) * gxr;
+    if (t0 == 0) {
+        a.ctrl->act_count[a.lv] = n;
+        a.ctrl->n_codes = 0;
+        a.ctrl->lvl_base[a.lv] = 0;
+    }
+    for (int q = t0; q < n; q += nthr) {
+        const int ry = q / gxr, rx = q - ry * gxr;
+        a.act[q] = ((ry * a.B) << 16) | (rx * a.B);
+    }
+}
+
 template <int L, bool TAB>
 __global__ __launch_bounds__(kBlock) void kt_pool_score_cells(Lvl a0, const Lvl* __restrict__ tab,
                                                               const int64_t* __restrict__ T, int fill_act) {
     FIC_LV;
-    if (fill_act) {
-        // also the level's active list (every range of the grid) and the
-        // encode's counters, as kt_act_full does: one launch fewer on level 0
-        const int nthr = gridDim.x * gridDim.y * kBlock;
-        const int t0 = (blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
-        const int gxr = a.W / a.B, n = (a.H / a.B) * gxr;
-        if (t0 == 0) {
-            a.ctrl->act_count[a.lv] = n;
-            a.ctrl->n_codes = 0;
-            a.ctrl->lvl_base[a.lv] = 0;
-        }
-        for (int q = t0; q < n; q += nthr) {
-            const int ry = q / gxr, rx = q - ry * gxr;
-            a.act[q] = ((ry * a.B) << 16) | (rx * a.B);
-        }
+    __shared__ CellSmem<L> sm;
+    // also level 0's active list: one launch fewer
+    if (fill_act)
+        act_full_part(a, (blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x,
+                      gridDim.x * gridDim.y * kBlock);
+    k_pool_score_cells_body<L>(sm, blockIdx.x, blockIdx.y, a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl);
+}
+
+// Every level of one image in one launch (levels at tab[0..], each with cell
+// side L = B / 2 in 1, 2, 4, 8): workgroups [end[l - 1], end[l]) score level
+// l's tiles, row by row of tiles; level 0's also write its active list.
+__global__ __launch_bounds__(kBlock) void kt_pool_score_cells_levels(const Lvl* __restrict__ tab, int4 end,
+                                                                     const int64_t* __restrict__ T) {
+    __shared__ CellSmemAny sm;
+    const int b = blockIdx.x;
+    const int l = (b >= end.x) + (b >= end.y) + (b >= end.z);
+    const int base = l == 0 ? 0 : l == 1 ? end.x : l == 2 ? end.y : end.z;
+    const Lvl& a = tab[l];
+    const int lb = b - base, nbx = (a.gx + kScTX - 1) / kScTX;
+    const int tbx = lb % nbx, tby = lb / nbx;
+    if (l == 0) act_full_part(a, lb * kBlock + threadIdx.x, end.x * kBlock);
+    switch (a.L) {
+        case 1: k_pool_score_cells_body<1>(sm.l1, tbx, tby, a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl); break;
+        case 2: k_pool_score_cells_body<2>(sm.l2, tbx, tby, a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl); break;
+        case 4: k_pool_score_cells_body<4>(sm.l4, tbx, tby, a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl); break;
+        default: k_pool_score_cells_body<8>(sm.l8, tbx, tby, a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl); break;
     }
-    k_pool_score_cells_body<L>(a.img, a.pitch, a.gx, a.gy, T, a.M, a.key, a.pctrl);
 }
 
 template <int SIDE, bool TAB>

@@ -868,22 +868,44 @@ int launch_quadtree_one(const std::vector<Lvl>& t, const int64_t* T, bool filter
                         Workspace& fork) {
     const int nl = (int)t.size();
     int rc;
-    // level 0's active list: written by its score kernel when that is the cell kernel
-    const bool fill = filtered && score_by_cells(t[0]);
-    if (!fill) {
+    // Every level scored by the cell kernel: one launch scores them all (and
+    // writes level 0's active list) before the streams fork.
+    const bool all_cells =
+        filtered && nl <= 4 && std::all_of(t.begin(), t.end(), [](const Lvl& a) { return score_by_cells(a); });
+    // otherwise level 0's active list is written by its score kernel when that is the cell kernel
+    const bool fill = filtered && !all_cells && score_by_cells(t[0]);
+    if (all_cells) {
+        int end[4];
+        for (int l = 0; l < 4; ++l)
+            end[l] = (l ? end[l - 1] : 0) + (l < nl ? cdiv(t[l].gx, kScTX) * cdiv(t[l].gy, kScTY) : 0);
+        kt_pool_score_cells_levels<<<end[nl - 1], kBlock, 0, st>>>(fork.dlv, make_int4(end[0], end[1], end[2], end[3]),
+                                                                   T);
+    } else if (!fill) {
         const int gx = cdiv((t[0].H / t[0].B) * (t[0].W / t[0].B), kBlock);
         kt_act_full<false><<<gx, kBlock, 0, st>>>(t[0], nullptr, 1);
     }
     HIP_TRY(hipEventRecord(fork.ev_fork, st));
     const std::vector<Lvl> h0{t[0]};
-    if ((rc = launch_pool_phase(nullptr, h0, T, filtered, st, fill))) return rc;
+    if (all_cells) {
+        launch_select_steps<false>(nullptr, h0, st);
+        launch_prep_step<false>(nullptr, h0, true, st);
+        LAUNCH_CHECK();
+    } else if ((rc = launch_pool_phase(nullptr, h0, T, filtered, st, fill))) {
+        return rc;
+    }
     if ((rc = launch_match_phase(nullptr, h0, st))) return rc;
     if ((rc = launch_quad(nullptr, h0, st))) return rc;
     // level 1
     hipStream_t p1 = fork.side[1];
     HIP_TRY(hipStreamWaitEvent(p1, fork.ev_fork, 0));
     const std::vector<Lvl> h1{t[1]};
-    if ((rc = launch_pool_phase(nullptr, h1, T, filtered, p1))) return rc;
+    if (all_cells) {
+        launch_select_steps<false>(nullptr, h1, p1);
+        launch_prep_step<false>(nullptr, h1, true, p1);
+        LAUNCH_CHECK();
+    } else if ((rc = launch_pool_phase(nullptr, h1, T, filtered, p1))) {
+        return rc;
+    }
     HIP_TRY(hipEventRecord(fork.ev_pool[1], p1));
     // levels 2..
     if (nl > 2) {
@@ -891,7 +913,8 @@ int launch_quadtree_one(const std::vector<Lvl>& t, const int64_t* T, bool filter
         HIP_TRY(hipStreamWaitEvent(p2, fork.ev_fork, 0));
         const std::vector<Lvl> rest(t.begin() + 2, t.end());
         if (filtered) {
-            for (const Lvl& a : rest) launch_score_step<false>(nullptr, {a}, T, p2);
+            if (!all_cells)
+                for (const Lvl& a : rest) launch_score_step<false>(nullptr, {a}, T, p2);
             launch_select_steps<true>(fork.dlv + 2, rest, p2);
         }
         for (const Lvl& a : rest) launch_prep_step<false>(nullptr, {a}, filtered, p2);
