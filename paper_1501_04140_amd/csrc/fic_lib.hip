@@ -178,7 +178,7 @@ int get_ws(hipStream_t s, Workspace** out) {
 void free_ws(Workspace* ws) {
     Buf* bufs[] = {&ws->arow, &ws->sr, &ws->cr, &ws->part, &ws->blk, &ws->act0, &ws->act1,
                    &ws->tmpc, &ws->dec, &ws->codes, &ws->map, &ws->imgA, &ws->imgB, &ws->acc,
-                   &ws->mr, &ws->ar, &ws->srp, &ws->plan};
+                   &ws->mr, &ws->ar, &ws->srp, &ws->gb, &ws->rc, &ws->plan};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (PoolBufs& pb : ws->pl) {
