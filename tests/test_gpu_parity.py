@@ -245,6 +245,21 @@ def test_quadtree_matches_oracle(dev, size, seed, min_pool, sets):
     assert np.array_equal(rec.cpu().numpy(), oracle.decode(ref, size, size, iters=24))
 
 
+@pytest.mark.parametrize("steps", [(8, 8, 2, 1), (4, 4, 2, 2)])
+def test_quadtree_other_steps(dev, steps):
+    """Steps other than L = B/2: those levels are scored window by window,
+    not from cells, so the one-image encode sets up level 0 another way (its
+    keys by cells without the other levels, or level 0 not by cells)."""
+    img = synth.power_law(96, beta=3.0, seed=5, n_rect=4)  # smooth: levels 1-3 keep ranges
+    say(f"[quadtree] steps {steps}")
+    params = fic.EncoderParams(s_sets=oracle.PAPER_K, min_pool=64, steps=steps)
+    _, _, got, st = gpu_image(dev, img, params)
+    ref, rst = oracle.encode_image(img, s_sets=oracle.PAPER_K, min_pool=64, steps=steps)
+    assert_codes_equal(got, ref)
+    for l, s in enumerate(rst):
+        assert (st["pool"][l], st["passed"][l], st["accepted"][l]) == (s["pool"], s["passed"], s["accepted"])
+
+
 def test_quadtree_alternating_arguments(dev):
     """The encoder keeps a device copy of each image's level arguments and
     rewrites it only when they change: alternating images, sizes and
