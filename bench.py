@@ -875,8 +875,8 @@ def main():
 
 
 def other_workloads(args, torch) -> dict:
-    """Short runs of the precision and batched workloads (no CPU baselines), so that one
-    default run also times them: their own --workload runs give the full lines."""
+    """Short runs of the precision, batched and learned workloads (no CPU baselines), so
+    that one default run also times them: their own --workload runs give the full lines."""
     import copy
     sub = copy.copy(args)
     sub.steps, sub.warmup, sub.no_cpu_baseline = min(args.steps, 5), 1, True
@@ -895,6 +895,14 @@ def other_workloads(args, torch) -> dict:
         "matches_per_s": b["value"], "images_per_s": b["images_per_s"], "tiles": b["config"]["tiles"],
         "workgroups": b["config"]["workgroups"], "levels_form": b["levels_form"],
         "roofline": {k: b["roofline"].get(k) for k in ("kernel", "achieved", "peak", "unit", "frac")}}
+    ln = run_learned(sub, torch)
+    out["learned2048"] = {
+        "workload": ln["config"]["workload"], "eval_images": ln["config"]["eval_images"],
+        "encode_ms": ln["encode_ms"], "exhaustive_ms": ln["exhaustive_ms"],
+        "speedup_vs_exhaustive": ln["speedup_vs_exhaustive"], "psnr_delta_db": ln["psnr_delta_db"],
+        "fallback_frac": ln["fallback_frac"], "recall_at_32": ln["recall_at_32"],
+        "proposals_only": ln["proposals_only"], "untrained_network": ln["untrained_network"],
+        "roofline": {k: ln["roofline"].get(k) for k in ("kernel", "achieved", "peak", "unit", "frac")}}
     return out
 
 
