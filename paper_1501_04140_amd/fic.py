@@ -156,9 +156,16 @@ def _check(rc: int):
 
 
 def _stream(stream):
+    """The HIP stream to queue on: `stream` (a torch stream), else torch's current
+    stream of the current device, read as a raw handle where torch offers that
+    (building the Stream object costs a few microseconds per call)."""
     import torch
-    s = torch.cuda.current_stream() if stream is None else stream
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return ctypes.c_void_p(raw(torch._C._cuda_getDevice()))
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _dev_u8_image(img):
