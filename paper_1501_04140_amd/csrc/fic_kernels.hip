@@ -140,19 +140,25 @@ __device__ __forceinline__ void k_pool_score_body(const uint8_t* __restrict__ im
 
 // The same keys by cells. With stride L and side 4L, domain (dy, dx) is the
 // 4 x 4 block of L x L cells starting at cell (dy, dx). A workgroup scores a
-// tile of kScTY x kScTX domains from the histograms of the (kScTY + 3) x
-// (kScTX + 3) cells they cover: a wave reads 64 consecutive pixels of a row
+// tile of kScTY x TX domains (TX = sc_tx(L)) from the histograms of the
+// (kScTY + 3) x (TX + 3) cells they cover: a wave reads 64 consecutive pixels of a row
 // (L lanes per cell, 8-bit counters over the cell's L rows), cells are widened
 // to 16-bit counters, summed 4 at a time along x, then 4 rows at a time along y.
 // Each cell is read once per tile instead of once per domain that covers it.
-constexpr int kScTX = 64, kScTY = kBlock / kScTX;
+constexpr int kScTY = 4;
+// Tile width at cell side L: 16 domains at L = 8 (the coarsest level has few
+// domains, so narrower tiles give it more workgroups and each fewer cells),
+// else 64. Threads beyond the tile's domains only help load the cells.
+__host__ __device__ constexpr int sc_tx(int L) { return L == 8 ? 16 : 64; }
+static_assert(kScTY * 64 == kBlock, "one thread per domain of the widest tile");
 
 // LDS of the cell kernel at cell side L.
 template <int L>
 struct CellSmem {
-    static constexpr int CX = kScTX + 3, CY = kScTY + 3;  // cells of the tile
-    uint64_t sc[CY * CX * 2];                              // cells: bins 0-3 | bins 4-7, 16 bits each
-    uint64_t sh[CY * kScTX * 2];                           // sums of 4 cells along x
+    static constexpr int TX = sc_tx(L);
+    static constexpr int CX = TX + 3, CY = kScTY + 3;  // cells of the tile
+    uint64_t sc[CY * CX * 2];                           // cells: bins 0-3 | bins 4-7, 16 bits each
+    uint64_t sh[CY * TX * 2];                           // sums of 4 cells along x
     int64_t sT[16 * L * L + 1];                            // the entropy table up to a domain's pixels
 };
 union CellSmemAny {
@@ -177,7 +183,8 @@ __device__ __forceinline__ void k_pool_score_cells_body(CellSmem<L>& sm, int tbx
     uint64_t* const sc = sm.sc;
     uint64_t* const sh = sm.sh;
     int64_t* const sT = sm.sT;
-    const int dx0 = tbx * kScTX, dy0 = tby * kScTY;
+    constexpr int TX = CellSmem<L>::TX;
+    const int dx0 = tbx * TX, dy0 = tby * kScTY;
     if (dx0 >= gx || dy0 >= gy) return;
     for (int i = threadIdx.x; i <= NPIX; i += kBlock) sT[i] = T[i];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -221,8 +228,8 @@ __device__ __forceinline__ void k_pool_score_cells_body(CellSmem<L>& sm, int tbx
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < CY * kScTX; i += kBlock) {
-        const int r = i / kScTX, c = i % kScTX;
+    for (int i = threadIdx.x; i < CY * TX; i += kBlock) {
+        const int r = i / TX, c = i % TX;
         uint64_t lo = 0, hi = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -233,15 +240,15 @@ __device__ __forceinline__ void k_pool_score_cells_body(CellSmem<L>& sm, int tbx
         sh[i * 2 + 1] = hi;
     }
     __syncthreads();
-    const int ty = threadIdx.x / kScTX, tx = threadIdx.x % kScTX;
+    const int ty = threadIdx.x / TX, tx = threadIdx.x % TX;
     const int dy = dy0 + ty, dx = dx0 + tx;
     int pass = 0;
-    if (dy < gy && dx < gx) {
+    if (ty < kScTY && dy < gy && dx < gx) {
         uint64_t lo = 0, hi = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            lo += sh[((ty + k) * kScTX + tx) * 2];
-            hi += sh[((ty + k) * kScTX + tx) * 2 + 1];
+            lo += sh[((ty + k) * TX + tx) * 2];
+            hi += sh[((ty + k) * TX + tx) * 2 + 1];
         }
         int64_t s = 0;
 #pragma unroll
@@ -3162,7 +3169,7 @@ __global__ __launch_bounds__(kBlock) void kt_pool_score_cells_levels(const Lvl* 
     const int l = (b >= end.x) + (b >= end.y) + (b >= end.z);
     const int base = l == 0 ? 0 : l == 1 ? end.x : l == 2 ? end.y : end.z;
     const Lvl& a = tab[l];
-    const int lb = b - base, nbx = (a.gx + kScTX - 1) / kScTX;
+    const int tw = sc_tx(a.L), lb = b - base, nbx = (a.gx + tw - 1) / tw;
     const int tbx = lb % nbx, tby = lb / nbx;
     if (l == 0) act_full_part(a, lb * kBlock + threadIdx.x, end.x * kBlock);
     switch (a.L) {

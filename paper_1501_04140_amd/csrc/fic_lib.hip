@@ -593,7 +593,7 @@ void launch_score(const Lvl* dt, const std::vector<Lvl>& h, const int64_t* T, hi
     const bool cells = max_over(h, [](const Lvl& a) { return a.total; }) >= kScoreCellsMin &&
                        std::all_of(h.begin(), h.end(), [](const Lvl& a) { return a.L == L; });
     if (cells) {
-        const int bx = max_over(h, [](const Lvl& a) { return cdiv(a.gx, kScTX); });
+        const int bx = max_over(h, [](const Lvl& a) { return cdiv(a.gx, sc_tx(L)); });
         const int by = max_over(h, [](const Lvl& a) { return cdiv(a.gy, kScTY); });
         kt_pool_score_cells<L, TAB><<<dim3(bx, by, h.size()), kBlock, 0, st>>>(h[0], dt, T, fill_act ? 1 : 0);
         return;
@@ -877,7 +877,7 @@ int launch_quadtree_one(const std::vector<Lvl>& t, const int64_t* T, bool filter
     if (all_cells) {
         int end[4];
         for (int l = 0; l < 4; ++l)
-            end[l] = (l ? end[l - 1] : 0) + (l < nl ? cdiv(t[l].gx, kScTX) * cdiv(t[l].gy, kScTY) : 0);
+            end[l] = (l ? end[l - 1] : 0) + (l < nl ? cdiv(t[l].gx, sc_tx(t[l].L)) * cdiv(t[l].gy, kScTY) : 0);
         kt_pool_score_cells_levels<<<end[nl - 1], kBlock, 0, st>>>(fork.dlv, make_int4(end[0], end[1], end[2], end[3]),
                                                                    T);
     } else if (!fill) {
